@@ -1,0 +1,349 @@
+"""Block smoothers, P0 coarse space, hybrid V-cycle and outer Krylov methods.
+
+Oracle (test infrastructure only; see the package docstring).
+
+Each routine takes the paper's steps in the paper's order:
+  * block-Jacobi: alg block_jacobi (Sec. 2.2.1) with W = omega^-1 D;
+  * the block systems D_T du_T = d_T (eqn block_system) are solved either
+    exactly (dense LU) or inexactly with a Krylov method stopped when the
+    2-norm of the block residual has dropped by the factor eps (Sec. 2.2.1),
+    preconditioned by the diagonal of D_T (Sec. 3.2);
+  * intergrid operators: P0 injection, P|_T = (1, ..., 1)^T, R = P^T
+    (Sec. 2.2.2);
+  * coarse matrix A_hat = P^T A P (eqn galerkin_product) and its direct
+    evaluation a_h(psi_hat_j, psi_hat_i) on P0 indicator functions
+    (App. A.1, eqn p0_galerkin1);
+  * hybrid V-cycle: alg hybrid_multigrid;
+  * outer CG / flexible CG / flexible GMRES with right preconditioning,
+    stopped on ||r_k||_2 <= rtol ||r_0||_2 (Sec. 4.2, Sec. 4.3).
+Where the paper leaves the step order open (inner PCG, GMRES details) the
+textbook algorithms are written out: Hestenes-Stiefel PCG, and Saad's
+restarted GMRES with modified Gram-Schmidt and Givens rotations.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from . import dg as _dg
+
+
+# ---------------------------------------------------------------------------
+# inner block solves
+# ---------------------------------------------------------------------------
+def block_solve_exact(D: np.ndarray, d: np.ndarray):
+    """du = D^-1 d by dense LU.  Returns (du, 0)."""
+    return sla.lu_solve(sla.lu_factor(D), d), 0
+
+
+def block_pcg(D: np.ndarray, d: np.ndarray, eps: float, max_inner: int):
+    """Diagonally preconditioned CG on D x = d from x = 0.
+
+    Stops when ||d - D x||_2 <= eps ||d||_2 (the recursive residual) or
+    after max_inner applications of D.  Returns (x, iterations).
+    """
+    x = np.zeros_like(d)
+    r = d.copy()
+    dnorm = np.linalg.norm(d)
+    if dnorm == 0.0:
+        return x, 0
+    diag = np.diag(D).copy()
+    z = r / diag
+    p = z.copy()
+    rho = r @ z
+    it = 0
+    while it < max_inner:
+        q = D @ p
+        it += 1
+        alpha = rho / (p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        if np.linalg.norm(r) <= eps * dnorm:
+            break
+        z = r / diag
+        rho_new = r @ z
+        beta = rho_new / rho
+        p = z + beta * p
+        rho = rho_new
+    return x, it
+
+
+def block_gmres(D: np.ndarray, d: np.ndarray, eps: float, max_inner: int, restart: int):
+    """Right-preconditioned restarted GMRES on D x = d from x = 0, M = diag(D).
+
+    Modified Gram-Schmidt Arnoldi, Givens rotations; stops when the
+    Arnoldi residual estimate |g_{j+1}| <= eps ||d||_2 or after max_inner
+    applications of D.  Returns (x, iterations).
+    """
+    n = d.size
+    x = np.zeros_like(d)
+    dnorm = np.linalg.norm(d)
+    if dnorm == 0.0:
+        return x, 0
+    minv = 1.0 / np.diag(D)
+    target = eps * dnorm
+    it = 0
+    r = d.copy()
+    beta = dnorm
+    while True:
+        m = restart
+        V = np.zeros((m + 1, n))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        V[0] = r / beta
+        g[0] = beta
+        done = False
+        k = 0
+        for j in range(m):
+            w = D @ (minv * V[j])
+            it += 1
+            for i in range(j + 1):
+                H[i, j] = w @ V[i]
+                w = w - H[i, j] * V[i]
+            hnext = np.linalg.norm(w)
+            H[j + 1, j] = hnext
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            rr = np.hypot(H[j, j], H[j + 1, j])
+            cs[j] = H[j, j] / rr
+            sn[j] = H[j + 1, j] / rr
+            H[j, j] = rr
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            k = j + 1
+            if abs(g[j + 1]) <= target or it >= max_inner:
+                done = True
+                break
+            V[j + 1] = w / hnext
+        y = sla.solve_triangular(H[:k, :k], g[:k], lower=False)
+        x = x + minv * (V[:k].T @ y)
+        if done or it >= max_inner:
+            return x, it
+        r = d - D @ x
+        beta = np.linalg.norm(r)
+        if beta <= target:
+            return x, it
+
+
+# ---------------------------------------------------------------------------
+# block-Jacobi smoother (alg block_jacobi)
+# ---------------------------------------------------------------------------
+def block_jacobi(A, Dblocks, f, u0, omega=1.0, nsweeps=1, inner="exact", eps=1e-2,
+                 max_inner=None, restart=30, stats=None):
+    """n_sweeps block-Jacobi steps u <- u + omega D^-1_eps (f - A u)."""
+    ncell, nb, _ = Dblocks.shape
+    if max_inner is None:
+        max_inner = nb
+    u = np.array(u0, dtype=np.float64, copy=True)
+    for _ in range(nsweeps):
+        d = (f - A @ u).reshape(ncell, nb)
+        du = np.zeros_like(d)
+        for T in range(ncell):
+            if inner == "exact":
+                du[T], it = block_solve_exact(Dblocks[T], d[T])
+            elif inner == "cg":
+                du[T], it = block_pcg(Dblocks[T], d[T], eps, max_inner)
+            elif inner == "gmres":
+                du[T], it = block_gmres(Dblocks[T], d[T], eps, max_inner, min(restart, nb))
+            else:
+                raise ValueError(inner)
+            if stats is not None:
+                stats.append(it)
+        u = u + omega * du.ravel()
+    return u
+
+
+# ---------------------------------------------------------------------------
+# P0 subspace (Sec. 2.2.2, 2.2.3, App. A.1)
+# ---------------------------------------------------------------------------
+def p0_prolongation(prob: _dg.Problem) -> sp.csr_matrix:
+    """P with P|_T = (1, ..., 1)^T: (ndof, ncell)."""
+    return sp.kron(sp.identity(prob.ncell, format="csr"), np.ones((prob.nloc, 1)), format="csr")
+
+
+def p0_galerkin(A, prob: _dg.Problem) -> np.ndarray:
+    """A_hat = P^T A P (eqn galerkin_product), dense (ncell, ncell)."""
+    P = p0_prolongation(prob)
+    return np.asarray((P.T @ (A.tocsr() @ P)).todense())
+
+
+def p0_direct(prob: _dg.Problem) -> np.ndarray:
+    """A_hat_{T,T'} = a_h(1_T', 1_T) evaluated directly on P0 indicators.
+
+    Gradients of P0 functions vanish, so only c |T| on the diagonal, the
+    upwind terms and the penalty terms remain (eqn p0_galerkin1); the
+    face integrals use the same face quadrature as A.
+    """
+    tab = _dg.Tables(prob)
+    h = prob.h
+    nc = prob.ncell
+    Ah = np.zeros((nc, nc))
+    vol = np.prod(h)
+    for c in range(nc):
+        Ah[c, c] += prob.creact(c) * vol
+        for bf, k, side in _dg.boundary_faces(prob, c):
+            if prob.bc[bf] != "D":
+                continue
+            WF = _dg.face_weights(prob, tab, k)
+            _, _, xi = _dg.face_tab(prob, tab, k, side)
+            nu_k = 1.0 if side == 1 else -1.0
+            gam = _dg.penalty_boundary(prob, k, prob.Kdiag(c)[k])
+            val = gam * WF.sum()
+            if prob.has_b:
+                bnu = nu_k * prob.bfield(prob.origin(c) + xi * h)[:, k]
+                val += np.sum(WF * bnu * (bnu >= 0.0))
+            Ah[c, c] += val
+    for c in range(nc):
+        ijk = prob.cell_ijk(c)
+        for k in range(3):
+            if ijk[k] + 1 >= prob.cells[k]:
+                continue
+            nb = list(ijk)
+            nb[k] += 1
+            cu = prob.cell_id(*nb)
+            WF = _dg.face_weights(prob, tab, k)
+            _, _, xi = _dg.face_tab(prob, tab, k, 1)
+            dm, dp = prob.Kdiag(c)[k], prob.Kdiag(cu)[k]
+            gam = _dg.penalty_interior(prob, k, dm, dp)
+            if prob.has_b:
+                bnu = prob.bfield(prob.origin(c) + xi * h)[:, k]
+            else:
+                bnu = np.zeros(WF.shape)
+            chim = (bnu >= 0.0).astype(np.float64)
+            # (s, t) in {-, +} with sign [[1_s]] = +1 / -1
+            for s, cs_, ss in (("-", c, 1.0), ("+", cu, -1.0)):
+                for t, ct, st in (("-", c, 1.0), ("+", cu, -1.0)):
+                    chit = chim if t == "-" else 1.0 - chim
+                    Ah[cs_, ct] += ss * np.sum(WF * bnu * chit) + gam * ss * st * WF.sum()
+    return Ah
+
+
+# ---------------------------------------------------------------------------
+# hybrid V-cycle (alg hybrid_multigrid)
+# ---------------------------------------------------------------------------
+def vcycle(A, Dblocks, prob: _dg.Problem, r, coarse_solve, n_pre=1, n_post=1, omega=1.0,
+           inner="exact", eps=1e-2, max_inner=None, restart=30, stats=None):
+    """z ~= A^-1 r: presmooth from zero, residual, restrict, coarse solve,
+    prolongate-add, postsmooth."""
+    P = p0_prolongation(prob)
+    kw = dict(omega=omega, inner=inner, eps=eps, max_inner=max_inner, restart=restart, stats=stats)
+    z = block_jacobi(A, Dblocks, r, np.zeros_like(r), nsweeps=n_pre, **kw)
+    res = r - A @ z
+    rh = P.T @ res
+    zh = coarse_solve(rh)
+    z = z + P @ zh
+    z = block_jacobi(A, Dblocks, r, z, nsweeps=n_post, **kw)
+    return z
+
+
+def exact_coarse(Ahat: np.ndarray):
+    lu = sla.lu_factor(Ahat)
+    return lambda rh: sla.lu_solve(lu, rh)
+
+
+# ---------------------------------------------------------------------------
+# outer Krylov methods
+# ---------------------------------------------------------------------------
+def cg(A, f, x0=None, precond=None, rtol=1e-8, maxit=1000, flexible=False):
+    """Preconditioned CG (flexible: Polak-Ribiere beta).
+
+    Returns (x, iterations, history of ||r_k|| / ||r_0||)."""
+    x = np.zeros_like(f) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    M = (lambda r: r.copy()) if precond is None else precond
+    r = f - A @ x
+    r0 = np.linalg.norm(r)
+    hist = [1.0]
+    if r0 == 0.0:
+        return x, 0, hist
+    z = M(r)
+    p = z.copy()
+    rho = r @ z
+    it = 0
+    while it < maxit:
+        q = A @ p
+        alpha = rho / (p @ q)
+        x = x + alpha * p
+        r_old = r
+        r = r - alpha * q
+        it += 1
+        hist.append(np.linalg.norm(r) / r0)
+        if hist[-1] <= rtol:
+            break
+        z = M(r)
+        if flexible:
+            rho_new = r @ z
+            beta = (z @ (r - r_old)) / rho
+        else:
+            rho_new = r @ z
+            beta = rho_new / rho
+        p = z + beta * p
+        rho = rho_new
+    return x, it, hist
+
+
+def fgmres(A, f, x0=None, precond=None, rtol=1e-8, maxit=1000, restart=30):
+    """Flexible GMRES(restart), right preconditioning, MGS, Givens.
+
+    Returns (x, iterations, history of the estimated ||r_k|| / ||r_0||)."""
+    x = np.zeros_like(f) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    M = (lambda r: r.copy()) if precond is None else precond
+    r = f - A @ x
+    r0 = np.linalg.norm(r)
+    hist = [1.0]
+    if r0 == 0.0:
+        return x, 0, hist
+    it = 0
+    beta = r0
+    while it < maxit:
+        m = restart
+        V = np.zeros((m + 1, f.size))
+        Z = np.zeros((m, f.size))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        V[0] = r / beta
+        g[0] = beta
+        k = 0
+        done = False
+        for j in range(m):
+            Z[j] = M(V[j])
+            w = A @ Z[j]
+            for i in range(j + 1):
+                H[i, j] = w @ V[i]
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            rr = np.hypot(H[j, j], H[j + 1, j])
+            cs[j] = H[j, j] / rr
+            sn[j] = H[j + 1, j] / rr
+            hnext = H[j + 1, j]
+            H[j, j] = rr
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            k = j + 1
+            hist.append(abs(g[j + 1]) / r0)
+            if hist[-1] <= rtol or it >= maxit:
+                done = True
+                break
+            V[j + 1] = w / hnext
+        y = sla.solve_triangular(H[:k, :k], g[:k], lower=False)
+        x = x + Z[:k].T @ y
+        if done:
+            break
+        r = f - A @ x
+        beta = np.linalg.norm(r)
+        if beta / r0 <= rtol:
+            break
+    return x, it, hist

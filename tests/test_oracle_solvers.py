@@ -1,0 +1,215 @@
+"""Pins of the oracle's smoothers, coarse space, V-cycle and outer solvers,
+and of the memory model (CPU only).
+
+  * inner PCG / GMRES with a tiny eps reproduce the dense block solve
+    (brute force), PCG on a diagonal block needs exactly one iteration,
+    restarted GMRES still converges;
+  * one exact block-Jacobi sweep on a one-cell mesh solves A u = f (A = D),
+    and the exact solution is a fixed point of the sweep (alg block_jacobi);
+  * the hybrid V-cycle (alg hybrid_multigrid) with exact block solves,
+    n_pre = n_post and an exact coarse solve is a symmetric positive
+    definite operator for b = 0;
+  * outer CG / flexible CG / flexible GMRES converge to the sparse direct
+    solution within the tolerance;
+  * the memory model reproduces every printed entry of the paper's four
+    memory tables (tests/golden/*.csv, Sec. 4.4).
+"""
+import csv
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import dg, memory_model as mm, solvers
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def read_golden(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return list(csv.DictReader(line for line in fh if not line.startswith("#")))
+
+
+def small(p=2, with_b=False, seed=0, cells=(3, 3, 2), **kw):
+    rng = np.random.default_rng(seed)
+    nc = int(np.prod(cells))
+    extra = {}
+    if with_b:
+        extra = dict(b0=(0.6, -0.4, 0.3), B=((0.0, 1.0, 0.0), (-1.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
+    extra.update(kw)
+    return dg.Problem(cells=cells, p=p, K=np.exp(rng.normal(size=(nc, 3))), **extra)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_block_pcg_tight_equals_dense(p):
+    pr = small(p)
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    rng = np.random.default_rng(1)
+    for T in range(pr.ncell):
+        d = rng.normal(size=pr.nloc)
+        x, it = solvers.block_pcg(Db[T], d, 1e-14, 10 * pr.nloc)
+        xe, _ = solvers.block_solve_exact(Db[T], d)
+        assert np.linalg.norm(x - xe) <= 1e-11 * np.linalg.norm(xe)
+        assert 1 <= it <= 10 * pr.nloc
+
+
+def test_block_pcg_diagonal_one_iteration():
+    D = np.diag(np.arange(1.0, 9.0))
+    d = np.linspace(-1, 2, 8)
+    x, it = solvers.block_pcg(D, d, 1e-12, 8)
+    assert it == 1
+    np.testing.assert_allclose(x, d / np.diag(D), rtol=1e-15)
+    x0, it0 = solvers.block_pcg(D, np.zeros(8), 1e-2, 8)
+    assert it0 == 0 and not x0.any()
+
+
+@pytest.mark.parametrize("restart", [4, 30])
+def test_block_gmres_tight_equals_dense(restart):
+    pr = small(2, with_b=True)
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    assert np.abs(Db[0] - Db[0].T).max() > 1e-3  # really nonsymmetric
+    rng = np.random.default_rng(2)
+    for T in range(pr.ncell):
+        d = rng.normal(size=pr.nloc)
+        x, it = solvers.block_gmres(Db[T], d, 1e-13, 20 * pr.nloc, restart)
+        xe, _ = solvers.block_solve_exact(Db[T], d)
+        assert np.linalg.norm(x - xe) <= 1e-10 * np.linalg.norm(xe)
+
+
+def test_block_gmres_loose_tolerance_is_met():
+    pr = small(3, with_b=True)
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    rng = np.random.default_rng(3)
+    for T in range(pr.ncell):
+        d = rng.normal(size=pr.nloc)
+        x, it = solvers.block_gmres(Db[T], d, 1e-2, pr.nloc, 30)
+        assert np.linalg.norm(d - Db[T] @ x) <= 1e-2 * np.linalg.norm(d) * (1 + 1e-10)
+
+
+def test_block_jacobi_single_cell_exact():
+    pr = small(2, cells=(1, 1, 1))
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    f = np.random.default_rng(4).normal(size=pr.ndof)
+    u = solvers.block_jacobi(A, Db, f, np.zeros(pr.ndof), omega=1.0, nsweeps=1, inner="exact")
+    np.testing.assert_allclose(A @ u, f, rtol=0, atol=1e-12 * np.abs(f).max())
+
+
+def test_block_jacobi_fixed_point_and_damping():
+    pr = small(2)
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    rng = np.random.default_rng(5)
+    ue = rng.normal(size=pr.ndof)
+    f = A @ ue
+    u = solvers.block_jacobi(A, Db, f, ue, omega=0.7, nsweeps=2, inner="exact")
+    np.testing.assert_allclose(u, ue, rtol=1e-12, atol=1e-12)
+    # one damped sweep from zero: u = omega D^-1 f, cell by cell
+    u1 = solvers.block_jacobi(A, Db, f, np.zeros(pr.ndof), omega=0.7, nsweeps=1, inner="exact")
+    F = f.reshape(pr.ncell, -1)
+    expect = np.concatenate([0.7 * np.linalg.solve(Db[T], F[T]) for T in range(pr.ncell)])
+    np.testing.assert_allclose(u1, expect, rtol=1e-12, atol=1e-13)
+
+
+def test_vcycle_symmetric_positive_definite():
+    pr = small(2, cells=(3, 2, 2))
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    Ah = solvers.p0_direct(pr)
+    cs = solvers.exact_coarse(Ah)
+    rng = np.random.default_rng(6)
+    r1, r2 = rng.normal(size=(2, pr.ndof))
+    kw = dict(n_pre=1, n_post=1, omega=0.8, inner="exact")
+    z1 = solvers.vcycle(A, Db, pr, r1, cs, **kw)
+    z2 = solvers.vcycle(A, Db, pr, r2, cs, **kw)
+    assert r2 @ z1 == pytest.approx(r1 @ z2, rel=1e-11)
+    assert r1 @ z1 > 0 and r2 @ z2 > 0
+    # linearity
+    z12 = solvers.vcycle(A, Db, pr, r1 + 2 * r2, cs, **kw)
+    np.testing.assert_allclose(z12, z1 + 2 * z2, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("flexible", [False, True])
+def test_outer_cg_with_vcycle(flexible):
+    pr = small(2, cells=(4, 3, 3))
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    cs = solvers.exact_coarse(solvers.p0_direct(pr))
+    f = np.random.default_rng(7).normal(size=pr.ndof)
+    ue = spla.spsolve(A.tocsc(), f)
+    it_stats = []
+
+    def M(r):
+        return solvers.vcycle(A, Db, pr, r, cs, inner="cg", eps=1e-2, stats=it_stats)
+
+    x, it, hist = solvers.cg(A, f, precond=M, rtol=1e-10, maxit=200, flexible=flexible)
+    assert hist[-1] <= 1e-10
+    assert np.linalg.norm(f - A @ x) <= 1e-10 * np.linalg.norm(f) * (1 + 1e-6)
+    assert np.linalg.norm(x - ue) <= 1e-7 * np.linalg.norm(ue)
+    assert it < 60
+    assert max(it_stats) <= pr.nloc
+
+
+def test_outer_fgmres_with_vcycle_convection():
+    pr = small(2, with_b=True, cells=(4, 3, 3))
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    cs = solvers.exact_coarse(solvers.p0_direct(pr))
+    f = np.random.default_rng(8).normal(size=pr.ndof)
+    ue = spla.spsolve(A.tocsc(), f)
+
+    def M(r):
+        return solvers.vcycle(A, Db, pr, r, cs, inner="gmres", eps=1e-2)
+
+    for restart in (5, 30):
+        x, it, hist = solvers.fgmres(A, f, precond=M, rtol=1e-10, maxit=300, restart=restart)
+        assert np.linalg.norm(f - A @ x) <= 1.01e-10 * np.linalg.norm(f)
+        assert np.linalg.norm(x - ue) <= 1e-7 * np.linalg.norm(ue)
+
+
+def test_unpreconditioned_cg_matches_dense():
+    pr = small(1, cells=(2, 2, 2))
+    A = dg.assemble(pr)
+    f = np.random.default_rng(9).normal(size=pr.ndof)
+    x, it, hist = solvers.cg(A, f, rtol=1e-12, maxit=2000)
+    np.testing.assert_allclose(x, np.linalg.solve(A.toarray(), f), rtol=1e-8, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# memory model vs the paper's printed tables
+# ---------------------------------------------------------------------------
+def _grids():
+    return {int(r["p"]): (int(r["nx"]) * int(r["ny"]) * int(r["nz"]), r) for r in read_golden("problem_sizes.csv")}
+
+
+def test_problem_size_table():
+    for p, (nc, r) in _grids().items():
+        assert round(mm.matrix_doubles(p, nc) * 8 / 2**30, 1) == float(r["matrix_gib"])
+        assert round(mm.vector_doubles(p, nc) / 1e6, 1) == float(r["dofs_1e6"])
+        assert mm.matrix_doubles(p, nc) // mm.vector_doubles(p, nc) == int(r["ratio"])
+        assert (p + 1) ** 3 == int(r["dofs_per_cell"])
+
+
+@pytest.mark.parametrize(
+    "fname,fun,unit",
+    [
+        ("memory_diffusion.csv", mm.diffusion_doubles, 1e9),
+        ("memory_convection_restart100.csv", lambda p, nc: mm.convection_doubles(p, nc, 100, 100), 2**30),
+        ("memory_convection_restart15_12.csv", lambda p, nc: mm.convection_doubles(p, nc, 15, 12), 2**30),
+    ],
+)
+def test_memory_tables(fname, fun, unit):
+    grids = _grids()
+    for r in read_golden(fname):
+        p = int(r["p"])
+        t = fun(p, grids[p][0])
+        mx, pmf, mf = (t[k] * 8 / unit for k in ("MX", "PMF", "MF"))
+        assert round(mx, 1) == float(r["mx_gb"])
+        assert round(pmf, 1) == float(r["pmf_gb"])
+        assert round(mx / pmf, 1) == float(r["pmf_ratio"])
+        assert round(mf, 3) == float(r["mf_gb"])
+        assert round(mx / mf, 1) == float(r["mf_ratio"])
