@@ -1,0 +1,222 @@
+/*
+ * libdgmg -- matrix-free DG operator, block smoothers and hybrid multigrid
+ * for high-order DG discretisations on one MI355X (gfx950).
+ *
+ * Method: Bastian, Mueller, Muething, Piatkowski, "Matrix-free multigrid
+ * block-preconditioners for higher order Discontinuous Galerkin
+ * discretisations" (arXiv:1805.11930).
+ *
+ * Problem (Sec. 2, eqns linearproblem / boundary_conditions):
+ *     div(b u - K grad u) + c u = f  in a box,
+ *     u = g on Dirichlet faces, (b u - K grad u).nu = j on Neumann faces,
+ * discretised with the weighted symmetric interior penalty method plus
+ * upwind flux (Sec. 2.1, eqn bilinear_form_split, right-hand side eqn rhs)
+ * on a uniform Cartesian mesh of hexahedra with a tensor-product nodal
+ * Lagrange basis of degree p whose nodes are the p+1 Gauss-Legendre
+ * points (collocated with the tensor Gauss quadrature of p+1 points).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Cells: c = ix + nx*(iy + ny*iz).  DOF (jx,jy,jz) of cell c has global
+ *    index c*(p+1)^3 + jx + (p+1)*(jy + (p+1)*jz).  Values are nodal.
+ *  - Box faces are numbered 0..5 = -x, +x, -y, +y, -z, +z.
+ *  - K is diagonal and constant per cell, c constant per cell, and the
+ *    advection field affine: b(x) = b0 + B x (B row-major).
+ *  - Vectors passed to dg_apply / dg_block_* / dg_mg_vcycle are DEVICE
+ *    pointers owned by the caller, contiguous, of type double (DG_FP64) or
+ *    float (DG_FP32), 16-byte aligned, and must stay alive until the work
+ *    queued on `stream` has completed.  Input and output must not overlap.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    dg_apply, dg_block_apply, dg_block_smooth and dg_mg_vcycle only
+ *    enqueue work and return; calls that fill host results synchronise.
+ *  - A problem handle may be used by one stream at a time.
+ *  - Every call returns DG_OK (0) or a status below; no exception crosses
+ *    the interface.  dg_last_error() returns a text for the last failure
+ *    of the calling thread.
+ */
+#ifndef DGMG_H
+#define DGMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------- */
+#define DG_OK 0
+#define DG_ENOCONV 1     /* finished without reaching rtol; outputs valid   */
+#define DG_EAGAIN 2      /* serving: solve still running                     */
+#define DG_EINVAL (-1)   /* bad argument (null pointer, p out of range, ...) */
+#define DG_ENOMEM (-2)   /* device allocation or admission failure           */
+#define DG_EDEVICE (-3)  /* HIP runtime error                                */
+#define DG_EBREAKDOWN (-4) /* NaN/Inf or CG breakdown (p^T A p <= 0)         */
+
+#define DG_MAX_P 4       /* polynomial degrees 1..DG_MAX_P are compiled      */
+
+enum { DG_FP64 = 0, DG_FP32 = 1 };
+enum { DG_BC_DIRICHLET = 0, DG_BC_NEUMANN = 1 };
+enum { DG_INNER_CG = 0, DG_INNER_GMRES = 1 };
+enum { DG_KRYLOV_CG = 0, DG_KRYLOV_FCG = 1, DG_KRYLOV_FGMRES = 2 };
+enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK_JACOBI = 1, DG_PRECOND_MG = 2 };
+
+typedef struct dg_problem dg_problem;          /* opaque, library-owned */
+typedef struct dg_solve_state dg_solve_state;  /* opaque, library-owned */
+
+/* Problem description (Sec. 2 problem statement; Sec. 2.1 discretisation).
+ * All arrays are HOST memory and are copied by dg_problem_create. */
+typedef struct {
+  int nx, ny, nz;          /* cells per direction, >= 1                    */
+  double lx, ly, lz;       /* box edge lengths, > 0; box = [0,lx]x[0,ly]x[0,lz] */
+  int p;                   /* polynomial degree, 1..DG_MAX_P               */
+  int bc[6];               /* DG_BC_DIRICHLET / DG_BC_NEUMANN per box face */
+  double penalty_factor;   /* prefactor sigma of gamma_F (Sec. 2.1, penalty
+                              definition, which uses alpha p (p+d-1)); <= 0
+                              selects 1.25 p (p+2)                         */
+  const double *K;         /* [ncell][3] diagonal of K per cell, or NULL    */
+  double K_scalar;         /* K = K_scalar * I when K == NULL (must be > 0) */
+  const double *c;         /* [ncell] reaction per cell, or NULL            */
+  double c_scalar;         /* c when c == NULL                              */
+  double b0[3];            /* b(x) = b0 + B x                               */
+  double B[9];
+} dg_problem_desc;
+
+/* Block smoother options (alg block_jacobi, Sec. 2.2.1; inner solve
+ * Sec. 3.2). */
+typedef struct {
+  int n_sweeps;     /* number of block-Jacobi steps, >= 1                  */
+  double omega;     /* damping, W = omega^-1 D                              */
+  double eps;       /* inner stop: ||d_T - D_T x||_2 <= eps ||d_T||_2       */
+  int max_inner;    /* cap on D_T applications per block (<= 0: (p+1)^3)   */
+  int inner;        /* DG_INNER_CG (b = 0) or DG_INNER_GMRES               */
+  int restart;      /* inner GMRES restart length (<= 0: 16)               */
+  int zero_guess;   /* 1: u_in is taken as zero and not read                */
+} dg_smooth_opts;
+
+/* Optional smoother statistics (filled after a synchronisation). */
+typedef struct {
+  long long blocks;       /* block solves performed                        */
+  long long inner_total;  /* sum of inner iterations                       */
+  int inner_max;          /* largest inner iteration count                 */
+  double inner_avg;       /* inner_total / blocks                          */
+} dg_smooth_stats;
+
+/* Hybrid V-cycle options (alg hybrid_multigrid; P0 subspace, Sec. 2.2.2,
+ * 2.2.3 and App. A.1). */
+typedef struct {
+  int n_pre, n_post;        /* smoothing steps                              */
+  dg_smooth_opts smooth;    /* smoother (n_sweeps and zero_guess ignored)   */
+  int coarse_cycles;        /* cycles of the P0 aggregation V-cycle (>= 1)  */
+  int coarse_smooth;        /* Jacobi sweeps per level in that cycle        */
+  double coarse_omega;      /* Jacobi damping on the P0 levels              */
+} dg_mg_opts;
+
+/* Outer solve options (Sec. 4.2: CG to 1e-8; Sec. 4.3: flexible GMRES). */
+typedef struct {
+  int krylov;               /* DG_KRYLOV_CG / _FCG / _FGMRES                */
+  int restart;              /* FGMRES restart (<= 0: 30)                    */
+  double rtol;              /* stop when ||f - A u||_2 <= rtol ||f - A u0||_2 */
+  int maxit;                /* iteration cap                                */
+  int precond;              /* DG_PRECOND_*                                 */
+  int precond_precision;    /* DG_FP64 or DG_FP32 (mixed precision)         */
+  dg_mg_opts mg;            /* V-cycle (and block-Jacobi smoother) options  */
+} dg_solve_opts;
+
+typedef struct {
+  int status;               /* DG_OK, DG_ENOCONV, DG_EBREAKDOWN             */
+  int iters;                /* outer iterations                             */
+  double rel_residual;      /* true FP64 ||f - A u||_2 / ||f - A u0||_2     */
+  double t_setup, t_solve;  /* seconds                                      */
+  double inner_avg;         /* mean inner iterations per block solve        */
+  int inner_max;
+  size_t footprint;         /* device bytes held by the problem + solve     */
+  double t_apply;           /* seconds in FP64 operator-apply kernels (HIP
+                               events on the solve's stream)                */
+  int n_apply;              /* number of those applies                      */
+  double t_precond;         /* seconds in the preconditioner (HIP events)   */
+  int n_precond;            /* preconditioner applications                  */
+} dg_solve_result;
+
+/* ---- problem lifetime ---------------------------------------------- */
+/* Validates the description (DG_EINVAL on nx,ny,nz < 1, lengths <= 0,
+ * p outside 1..DG_MAX_P, bad bc, K not finite or <= 0, c not finite or
+ * < 0, non-finite b), copies coefficients to the device and builds the
+ * 1-D tables and the P0 coarse hierarchy.  *out is NULL on failure. */
+int dg_problem_create(const dg_problem_desc *desc, dg_problem **out);
+void dg_problem_destroy(dg_problem *prob);
+const char *dg_last_error(void);
+
+/* Number of DOFs (ncell (p+1)^3) and of boundary quadrature points. */
+int64_t dg_ndof(const dg_problem *prob);
+int64_t dg_boundary_npoints(const dg_problem *prob);
+
+/* Physical coordinates, HOST output [ndof][3], of the DOF nodes, which are
+ * also the volume quadrature points (Gauss nodes, collocated basis). */
+int dg_node_points(const dg_problem *prob, double *xyz);
+/* Physical coordinates, HOST output [npts][3], of the boundary face
+ * quadrature points: box faces 0..5 in order; on each box face, the faces
+ * of the boundary cells with the first tangential cell index fastest
+ * (tangential axes in increasing order), and on each cell face the
+ * (p+1)^2 Gauss points, first tangential coordinate fastest. */
+int dg_boundary_points(const dg_problem *prob, double *xyz);
+
+/* Right-hand side l_h(psi_i) (eqn rhs).  f_qp: DEVICE [ndof] values of f
+ * at the volume quadrature points (NULL = 0).  bnd_qp: DEVICE [npts]
+ * values at the boundary points, read as g on Dirichlet faces and as j on
+ * Neumann faces (NULL = 0).  rhs: DEVICE [ndof] double output. */
+int dg_assemble_rhs(dg_problem *prob, const double *f_qp, const double *bnd_qp, double *rhs,
+                    void *stream);
+
+/* ---- hot path -------------------------------------------------------- */
+/* v = A u, A_ij = a_h(psi_j, psi_i) (eqn linear_equation), matrix-free by
+ * sum factorisation (Sec. 3.1): volume, interior-face and boundary-face
+ * terms.  precision: DG_FP64 (double vectors) or DG_FP32 (float vectors). */
+int dg_apply(dg_problem *prob, int precision, const void *u, void *v, void *stream);
+
+/* y_T = D_T x_T for every cell T, D_T = A_{T,T} (eqn block_diag_apply). */
+int dg_block_apply(dg_problem *prob, int precision, const void *x, void *y, void *stream);
+
+/* diag(D_T) for every cell, DEVICE [ndof] output (Sec. 3.2, the diagonal
+ * preconditioner of the inner solve). */
+int dg_block_diag(dg_problem *prob, int precision, void *diag, void *stream);
+
+/* x_T ~= D_T^-1 d_T for every cell by the inner Krylov method of
+ * dg_block_smooth (eqn block_system, Sec. 2.2.1 / 3.2).  iters: DEVICE
+ * [ncell] int output of inner iterations per block, or NULL. */
+int dg_block_solve(dg_problem *prob, int precision, const void *d, void *x,
+                   const dg_smooth_opts *opts, int *iters, void *stream);
+
+/* n_sweeps block-Jacobi steps (alg block_jacobi):
+ *   u^(k) = u^(k-1) + omega D^-1_eps (f - A u^(k-1)),
+ * u^(0) = u_in (or 0 when opts->zero_guess), result in u_out.  u_in and
+ * u_out must differ.  stats (nullable) forces a synchronisation. */
+int dg_block_smooth(dg_problem *prob, int precision, const void *f, const void *u_in, void *u_out,
+                    const dg_smooth_opts *opts, dg_smooth_stats *stats, void *stream);
+
+/* z ~= A^-1 r by one hybrid V-cycle from a zero initial guess
+ * (alg hybrid_multigrid): presmooth, residual, restriction R = P^T
+ * (P0 injection, Sec. 2.2.2), coarse correction with the P0 matrix
+ * A_hat = P^T A P (App. A.1), prolongation, postsmooth. */
+int dg_mg_vcycle(dg_problem *prob, int precision, const void *r, void *z, const dg_mg_opts *opts,
+                 void *stream);
+
+/* Solve A u = f with an FP64 outer Krylov method preconditioned by the
+ * V-cycle (or block-Jacobi) in precond_precision.  f, u: DEVICE double
+ * [ndof]; u holds the initial guess on entry and the solution on return.
+ * Synchronises; fills *res (nullable). */
+int dg_solve(dg_problem *prob, const double *f, double *u, const dg_solve_opts *opts,
+             dg_solve_result *res, void *stream);
+
+/* Device bytes the library would hold for this problem and solve. */
+int dg_footprint(const dg_problem_desc *desc, const dg_solve_opts *opts, size_t *bytes);
+
+/* ---- defaults ------------------------------------------------------- */
+void dg_default_smooth_opts(dg_smooth_opts *o);
+void dg_default_mg_opts(dg_mg_opts *o);
+void dg_default_solve_opts(dg_solve_opts *o);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGMG_H */

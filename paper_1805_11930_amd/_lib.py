@@ -1,0 +1,226 @@
+"""ctypes binding of libdgmg (include/dgmg.h): argument marshalling only.
+
+Every numerical step runs in the HIP library; this module converts torch
+tensors to device pointers and HIP streams, mirrors the C structs, and
+turns status codes into exceptions.  There is no fallback: if the shared
+library is missing or cannot be loaded, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgmg.so")
+
+DG_OK, DG_ENOCONV, DG_EAGAIN = 0, 1, 2
+DG_EINVAL, DG_ENOMEM, DG_EDEVICE, DG_EBREAKDOWN = -1, -2, -3, -4
+DG_MAX_P = 4
+DG_FP64, DG_FP32 = 0, 1
+DG_BC_DIRICHLET, DG_BC_NEUMANN = 0, 1
+DG_INNER_CG, DG_INNER_GMRES = 0, 1
+DG_KRYLOV_CG, DG_KRYLOV_FCG, DG_KRYLOV_FGMRES = 0, 1, 2
+DG_PRECOND_NONE, DG_PRECOND_BLOCK_JACOBI, DG_PRECOND_MG = 0, 1, 2
+
+EXPORTS = (
+    "dg_problem_create", "dg_problem_destroy", "dg_last_error", "dg_ndof", "dg_boundary_npoints",
+    "dg_node_points", "dg_boundary_points", "dg_assemble_rhs", "dg_apply", "dg_block_apply",
+    "dg_block_diag", "dg_block_solve", "dg_block_smooth", "dg_mg_vcycle", "dg_solve", "dg_footprint",
+    "dg_default_smooth_opts", "dg_default_mg_opts", "dg_default_solve_opts",
+)
+
+
+class DgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libdgmg status {code}: {msg}")
+        self.code = code
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+        ("p", ctypes.c_int), ("bc", ctypes.c_int * 6), ("penalty_factor", ctypes.c_double),
+        ("K", ctypes.POINTER(ctypes.c_double)), ("K_scalar", ctypes.c_double),
+        ("c", ctypes.POINTER(ctypes.c_double)), ("c_scalar", ctypes.c_double),
+        ("b0", ctypes.c_double * 3), ("B", ctypes.c_double * 9),
+    ]
+
+
+class SmoothOpts(ctypes.Structure):
+    _fields_ = [
+        ("n_sweeps", ctypes.c_int), ("omega", ctypes.c_double), ("eps", ctypes.c_double),
+        ("max_inner", ctypes.c_int), ("inner", ctypes.c_int), ("restart", ctypes.c_int),
+        ("zero_guess", ctypes.c_int),
+    ]
+
+
+class SmoothStats(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_longlong), ("inner_total", ctypes.c_longlong), ("inner_max", ctypes.c_int),
+                ("inner_avg", ctypes.c_double)]
+
+
+class MgOpts(ctypes.Structure):
+    _fields_ = [
+        ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int), ("smooth", SmoothOpts),
+        ("coarse_cycles", ctypes.c_int), ("coarse_smooth", ctypes.c_int), ("coarse_omega", ctypes.c_double),
+    ]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("krylov", ctypes.c_int), ("restart", ctypes.c_int), ("rtol", ctypes.c_double), ("maxit", ctypes.c_int),
+        ("precond", ctypes.c_int), ("precond_precision", ctypes.c_int), ("mg", MgOpts),
+    ]
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("iters", ctypes.c_int), ("rel_residual", ctypes.c_double),
+        ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double), ("inner_avg", ctypes.c_double),
+        ("inner_max", ctypes.c_int), ("footprint", ctypes.c_size_t), ("t_apply", ctypes.c_double),
+        ("n_apply", ctypes.c_int), ("t_precond", ctypes.c_double), ("n_precond", ctypes.c_int),
+    ]
+
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libdgmg.so (raises OSError / RuntimeError when absent)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1805_11930_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    lib.dg_problem_create.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(vp)]
+    lib.dg_problem_destroy.argtypes = [vp]
+    lib.dg_problem_destroy.restype = None
+    lib.dg_last_error.restype = ctypes.c_char_p
+    lib.dg_ndof.argtypes = [vp]
+    lib.dg_ndof.restype = i64
+    lib.dg_boundary_npoints.argtypes = [vp]
+    lib.dg_boundary_npoints.restype = i64
+    lib.dg_node_points.argtypes = [vp, dp]
+    lib.dg_boundary_points.argtypes = [vp, dp]
+    lib.dg_assemble_rhs.argtypes = [vp, vp, vp, vp, vp]
+    lib.dg_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.dg_block_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.dg_block_diag.argtypes = [vp, ctypes.c_int, vp, vp]
+    lib.dg_block_solve.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.POINTER(SmoothOpts), vp, vp]
+    lib.dg_block_smooth.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.POINTER(SmoothOpts),
+                                    ctypes.POINTER(SmoothStats), vp]
+    lib.dg_mg_vcycle.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.POINTER(MgOpts), vp]
+    lib.dg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveResult), vp]
+    lib.dg_footprint.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(SolveOpts), ctypes.POINTER(ctypes.c_size_t)]
+    lib.dg_default_smooth_opts.argtypes = [ctypes.POINTER(SmoothOpts)]
+    lib.dg_default_smooth_opts.restype = None
+    lib.dg_default_mg_opts.argtypes = [ctypes.POINTER(MgOpts)]
+    lib.dg_default_mg_opts.restype = None
+    lib.dg_default_solve_opts.argtypes = [ctypes.POINTER(SolveOpts)]
+    lib.dg_default_solve_opts.restype = None
+    _LIB = lib
+    return lib
+
+
+def _check(rc: int, allow=(DG_OK,)) -> int:
+    if rc not in allow:
+        msg = load().dg_last_error()
+        raise DgError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def smooth_opts(**kw) -> SmoothOpts:
+    o = SmoothOpts()
+    load().dg_default_smooth_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def mg_opts(smooth: dict | None = None, **kw) -> MgOpts:
+    o = MgOpts()
+    load().dg_default_mg_opts(ctypes.byref(o))
+    for k, v in (smooth or {}).items():
+        setattr(o.smooth, k, v)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def solve_opts(mg: dict | None = None, smooth: dict | None = None, **kw) -> SolveOpts:
+    o = SolveOpts()
+    load().dg_default_solve_opts(ctypes.byref(o))
+    for k, v in (mg or {}).items():
+        setattr(o.mg, k, v)
+    for k, v in (smooth or {}).items():
+        setattr(o.mg.smooth, k, v)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+_BC = {"D": DG_BC_DIRICHLET, "N": DG_BC_NEUMANN}
+
+
+@dataclass
+class ProblemSpec:
+    """Host-side description mirroring dg_problem_desc."""
+
+    cells: tuple
+    lengths: tuple = (1.0, 1.0, 1.0)
+    p: int = 1
+    bc: tuple = ("D",) * 6
+    sigma: float | None = None
+    K: np.ndarray | float = 1.0
+    c: np.ndarray | float = 0.0
+    b0: tuple = (0.0, 0.0, 0.0)
+    B: tuple = ((0.0,) * 3,) * 3
+    _keep: list = field(default_factory=list, repr=False)
+
+    def desc(self) -> ProblemDesc:
+        d = ProblemDesc()
+        d.nx, d.ny, d.nz = (int(v) for v in self.cells)
+        d.lx, d.ly, d.lz = (float(v) for v in self.lengths)
+        d.p = int(self.p)
+        for i, t in enumerate(self.bc):
+            d.bc[i] = _BC[t] if isinstance(t, str) else int(t)
+        d.penalty_factor = float(self.sigma) if self.sigma is not None else 0.0
+        ncell = d.nx * d.ny * d.nz
+        self._keep = []
+        K = np.asarray(self.K, dtype=np.float64)
+        if K.ndim == 0:
+            d.K = None
+            d.K_scalar = float(K)
+        else:
+            K = np.ascontiguousarray(np.broadcast_to(K, (ncell, 3)), dtype=np.float64)
+            self._keep.append(K)
+            d.K = K.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.K_scalar = 0.0
+        c = np.asarray(self.c, dtype=np.float64)
+        if c.ndim == 0:
+            d.c = None
+            d.c_scalar = float(c)
+        else:
+            c = np.ascontiguousarray(np.broadcast_to(c, (ncell,)), dtype=np.float64)
+            self._keep.append(c)
+            d.c = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.c_scalar = 0.0
+        for i in range(3):
+            d.b0[i] = float(self.b0[i])
+        Bm = np.asarray(self.B, dtype=np.float64).reshape(9)
+        for i in range(9):
+            d.B[i] = float(Bm[i])
+        return d
+
+
+def footprint(spec: ProblemSpec, opts: SolveOpts | None = None) -> int:
+    out = ctypes.c_size_t(0)
+    d = spec.desc()
+    _check(load().dg_footprint(ctypes.byref(d), ctypes.byref(opts) if opts is not None else None, ctypes.byref(out)))
+    return int(out.value)

@@ -1,0 +1,383 @@
+// C-ABI entry points: argument checks and dispatch to the kernels, the
+// hybrid V-cycle (alg hybrid_multigrid) and the outer Krylov solvers.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dg_internal.h"
+#include "vec.h"
+
+namespace dgmg {
+int alloc_tmp(dg_problem *pr, int prec, int k, void **out);
+int alloc_small(dg_problem *pr);
+}  // namespace dgmg
+
+using namespace dgmg;
+
+namespace {
+
+inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+int check_vec(const void *p, const char *name) {
+  if (!p) {
+    set_error(std::string(name) + " is NULL");
+    return DG_EINVAL;
+  }
+  if (((uintptr_t)p) % 16 != 0) {
+    set_error(std::string(name) + " is not 16-byte aligned");
+    return DG_EINVAL;
+  }
+  return DG_OK;
+}
+
+int check_prec(int prec) {
+  if (prec != DG_FP64 && prec != DG_FP32) {
+    set_error("precision must be DG_FP64 or DG_FP32");
+    return DG_EINVAL;
+  }
+  return DG_OK;
+}
+
+int smooth_args(const dg_problem *pr, const dg_smooth_opts *o, SmoothArgs &a) {
+  if (!o) {
+    set_error("smoother options are NULL");
+    return DG_EINVAL;
+  }
+  if (!(o->eps >= 0) || !std::isfinite(o->omega) || (o->inner != DG_INNER_CG && o->inner != DG_INNER_GMRES)) {
+    set_error("invalid smoother options (eps >= 0, finite omega, inner CG or GMRES)");
+    return DG_EINVAL;
+  }
+  a.omega = o->omega;
+  a.eps = o->eps;
+  a.max_inner = o->max_inner > 0 ? o->max_inner : (int)pr->nloc;
+  a.inner = o->inner;
+  a.restart = o->restart > 0 ? o->restart : 12;
+  if (a.restart > 16) a.restart = 16;
+  if (a.restart > pr->nloc) a.restart = (int)pr->nloc;
+  a.zero_guess = o->zero_guess;
+  a.write_du = 0;
+  a.defect = 1;
+  return DG_OK;
+}
+
+size_t esize(int prec) { return prec == DG_FP64 ? sizeof(double) : sizeof(float); }
+
+// n block-Jacobi sweeps from `src` (NULL = zero) ending in `dst`, using
+// `alt` as the other ping-pong buffer.  dst != alt; src may equal alt but
+// not dst unless n == 0.
+int sweeps(dg_problem *pr, int prec, const void *f, const void *src, void *dst, void *alt, int n,
+           const SmoothArgs &base, int *iters, hipStream_t s) {
+  if (n <= 0) {
+    if (src == nullptr)
+      DG_HIP(hipMemsetAsync(dst, 0, (size_t)pr->ndof * esize(prec), s));
+    else if (src != dst)
+      DG_HIP(hipMemcpyAsync(dst, src, (size_t)pr->ndof * esize(prec), hipMemcpyDeviceToDevice, s));
+    return DG_OK;
+  }
+  const void *cur = src;
+  for (int k = 1; k <= n; ++k) {
+    void *out = ((n - k) % 2 == 0) ? dst : alt;
+    if (out == cur) out = (out == dst) ? alt : dst;  // never smooth in place
+    SmoothArgs a = base;
+    a.zero_guess = cur == nullptr ? 1 : 0;
+    int rc = launch_smooth(pr, prec, f, cur ? cur : f, out, a, iters, s);
+    if (rc) return rc;
+    cur = out;
+  }
+  if (cur != dst) DG_HIP(hipMemcpyAsync(dst, cur, (size_t)pr->ndof * esize(prec), hipMemcpyDeviceToDevice, s));
+  return DG_OK;
+}
+
+// ---- P0 aggregation cycle on the coarse levels --------------------------
+template <typename T>
+struct LevelPtr {
+  static T *r(CoarseLevel &L);
+  static T *x(CoarseLevel &L);
+  static T *t(CoarseLevel &L);
+  static const T *A(const CoarseLevel &L);
+  static const T *inv(const dg_problem *pr);
+};
+template <>
+struct LevelPtr<double> {
+  static double *r(CoarseLevel &L) { return L.r64; }
+  static double *x(CoarseLevel &L) { return L.x64; }
+  static double *t(CoarseLevel &L) { return L.t64; }
+  static const double *A(const CoarseLevel &L) { return L.A64; }
+  static const double *inv(const dg_problem *pr) { return pr->bottom_inv64; }
+};
+template <>
+struct LevelPtr<float> {
+  static float *r(CoarseLevel &L) { return L.r32; }
+  static float *x(CoarseLevel &L) { return L.x32; }
+  static float *t(CoarseLevel &L) { return L.t32; }
+  static const float *A(const CoarseLevel &L) { return L.A32; }
+  static const float *inv(const dg_problem *pr) { return pr->bottom_inv32; }
+};
+
+// x_l ~= A_l^-1 r_l (both stored in level l's r / x buffers)
+template <typename T>
+int coarse_cycle(dg_problem *pr, size_t l, int nu, T w, hipStream_t s) {
+  using LP = LevelPtr<T>;
+  CoarseLevel &L = pr->levels[l];
+  if (l + 1 == pr->levels.size()) return dense_mv<T>(pr->bottom_n, LP::inv(pr), LP::r(L), LP::x(L), s);
+  int rc;
+  T *x = LP::x(L), *t = LP::t(L);
+  const T *A = LP::A(L), *r = LP::r(L);
+  // presmooth from zero: x = w D^-1 r, then nu-1 more sweeps
+  if ((rc = coarse_jacobi<T>(A, L.nx, L.ny, L.nz, w, r, nullptr, x, s))) return rc;
+  for (int k = 1; k < nu; ++k) {
+    if ((rc = coarse_jacobi<T>(A, L.nx, L.ny, L.nz, w, r, x, t, s))) return rc;
+    std::swap(x, t);
+  }
+  CoarseLevel &C = pr->levels[l + 1];
+  if ((rc = coarse_restrict<T>(A, L.nx, L.ny, L.nz, r, x, C.nx, C.ny, C.nz, LP::r(C), s))) return rc;
+  if ((rc = coarse_cycle<T>(pr, l + 1, nu, w, s))) return rc;
+  if ((rc = coarse_prolong<T>(L.nx, L.ny, L.nz, C.nx, C.ny, LP::x(C), x, s))) return rc;
+  for (int k = 0; k < nu; ++k) {
+    if ((rc = coarse_jacobi<T>(A, L.nx, L.ny, L.nz, w, r, x, t, s))) return rc;
+    std::swap(x, t);
+  }
+  if (x != LP::x(L)) DG_HIP(hipMemcpyAsync(LP::x(L), x, (size_t)L.n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  return DG_OK;
+}
+
+template <typename T>
+int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hipStream_t s) {
+  SmoothArgs sa;
+  int rc = smooth_args(pr, &o->smooth, sa);
+  if (rc) return rc;
+  void *t0, *t1;
+  if ((rc = alloc_tmp(pr, prec, 0, &t0)) || (rc = alloc_tmp(pr, prec, 1, &t1))) return rc;
+  // presmoothing ends in X so that postsmoothing ends in z without a copy
+  void *X = (o->n_post % 2 == 1) ? t0 : (void *)z;
+  void *Y = (X == t0) ? (void *)z : t0;
+  if ((rc = sweeps(pr, prec, r, nullptr, X, Y, o->n_pre, sa, nullptr, s))) return rc;
+  // residual, restriction R = P^T
+  if ((rc = launch_apply(pr, prec, X, t1, s))) return rc;
+  using LP = LevelPtr<T>;
+  CoarseLevel &L0 = pr->levels[0];
+  if ((rc = restrict_p0<T>(pr->ncell, pr->nloc, r, (const T *)t1, LP::r(L0), s))) return rc;
+  const int nu = o->coarse_smooth > 0 ? o->coarse_smooth : 2;
+  const T w = (T)(o->coarse_omega > 0 ? o->coarse_omega : 2.0 / 3.0);
+  if ((rc = coarse_cycle<T>(pr, 0, nu, w, s))) return rc;
+  // prolongation P (injection) and add
+  if ((rc = prolong_add_p0<T>(pr->ndof, pr->nloc, LP::x(L0), (T *)X, s))) return rc;
+  return sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s);
+}
+
+int vcycle(dg_problem *pr, int prec, const void *r, void *z, const dg_mg_opts *o, hipStream_t s) {
+  if (prec == DG_FP64) return vcycle_t<double>(pr, prec, (const double *)r, (double *)z, o, s);
+  return vcycle_t<float>(pr, prec, (const float *)r, (float *)z, o, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+void dg_default_smooth_opts(dg_smooth_opts *o) {
+  if (!o) return;
+  o->n_sweeps = 1;
+  o->omega = 1.0;
+  o->eps = 1e-2;
+  o->max_inner = 0;
+  o->inner = DG_INNER_CG;
+  o->restart = 12;
+  o->zero_guess = 0;
+}
+
+void dg_default_mg_opts(dg_mg_opts *o) {
+  if (!o) return;
+  o->n_pre = 1;
+  o->n_post = 1;
+  dg_default_smooth_opts(&o->smooth);
+  o->coarse_cycles = 1;
+  o->coarse_smooth = 2;
+  o->coarse_omega = 2.0 / 3.0;
+}
+
+void dg_default_solve_opts(dg_solve_opts *o) {
+  if (!o) return;
+  o->krylov = DG_KRYLOV_FCG;
+  o->restart = 30;
+  o->rtol = 1e-8;
+  o->maxit = 500;
+  o->precond = DG_PRECOND_MG;
+  o->precond_precision = DG_FP32;
+  dg_default_mg_opts(&o->mg);
+}
+
+int dg_assemble_rhs(dg_problem *pr, const double *f_qp, const double *bnd_qp, double *rhs, void *stream) {
+  if (!pr) {
+    set_error("problem is NULL");
+    return DG_EINVAL;
+  }
+  int rc = check_vec(rhs, "rhs");
+  if (rc) return rc;
+  return launch_rhs(pr, f_qp, bnd_qp, rhs, S(stream));
+}
+
+int dg_apply(dg_problem *pr, int precision, const void *u, void *v, void *stream) {
+  if (!pr) {
+    set_error("problem is NULL");
+    return DG_EINVAL;
+  }
+  int rc;
+  if ((rc = check_prec(precision)) || (rc = check_vec(u, "u")) || (rc = check_vec(v, "v"))) return rc;
+  if (u == v) {
+    set_error("dg_apply: u and v must differ");
+    return DG_EINVAL;
+  }
+  return launch_apply(pr, precision, u, v, S(stream));
+}
+
+int dg_block_apply(dg_problem *pr, int precision, const void *x, void *y, void *stream) {
+  if (!pr) {
+    set_error("problem is NULL");
+    return DG_EINVAL;
+  }
+  int rc;
+  if ((rc = check_prec(precision)) || (rc = check_vec(x, "x")) || (rc = check_vec(y, "y"))) return rc;
+  if (x == y) {
+    set_error("dg_block_apply: x and y must differ");
+    return DG_EINVAL;
+  }
+  return launch_block_apply(pr, precision, x, y, S(stream));
+}
+
+int dg_block_diag(dg_problem *pr, int precision, void *diag, void *stream) {
+  if (!pr) {
+    set_error("problem is NULL");
+    return DG_EINVAL;
+  }
+  int rc;
+  if ((rc = check_prec(precision)) || (rc = check_vec(diag, "diag"))) return rc;
+  return launch_block_diag(pr, precision, diag, S(stream));
+}
+
+int dg_block_solve(dg_problem *pr, int precision, const void *d, void *x, const dg_smooth_opts *opts, int *iters,
+                   void *stream) {
+  if (!pr) {
+    set_error("problem is NULL");
+    return DG_EINVAL;
+  }
+  int rc;
+  if ((rc = check_prec(precision)) || (rc = check_vec(d, "d")) || (rc = check_vec(x, "x"))) return rc;
+  if (d == x) {
+    set_error("dg_block_solve: d and x must differ");
+    return DG_EINVAL;
+  }
+  SmoothArgs a;
+  if ((rc = smooth_args(pr, opts, a))) return rc;
+  a.zero_guess = 1;
+  a.write_du = 1;
+  a.defect = 0;
+  return launch_smooth(pr, precision, d, d, x, a, iters, S(stream));
+}
+
+int dg_block_smooth(dg_problem *pr, int precision, const void *f, const void *u_in, void *u_out,
+                    const dg_smooth_opts *opts, dg_smooth_stats *stats, void *stream) {
+  if (!pr) {
+    set_error("problem is NULL");
+    return DG_EINVAL;
+  }
+  int rc;
+  if ((rc = check_prec(precision)) || (rc = check_vec(f, "f")) || (rc = check_vec(u_out, "u_out"))) return rc;
+  if (!opts) {
+    set_error("smoother options are NULL");
+    return DG_EINVAL;
+  }
+  if (!opts->zero_guess && (rc = check_vec(u_in, "u_in"))) return rc;
+  if (u_in == u_out || f == u_out) {
+    set_error("dg_block_smooth: u_out must differ from u_in and f");
+    return DG_EINVAL;
+  }
+  if (opts->n_sweeps < 1) {
+    set_error("n_sweeps must be >= 1");
+    return DG_EINVAL;
+  }
+  SmoothArgs a;
+  if ((rc = smooth_args(pr, opts, a))) return rc;
+  hipStream_t s = S(stream);
+  void *alt = nullptr;
+  if (opts->n_sweeps > 1 && (rc = alloc_tmp(pr, precision, 2, &alt))) return rc;
+  int *iters = stats ? pr->iters_buf : nullptr;
+  unsigned long long tot = 0;
+  int mx = 0;
+  const void *cur = opts->zero_guess ? nullptr : u_in;
+  for (int k = 1; k <= opts->n_sweeps; ++k) {
+    void *out = ((opts->n_sweeps - k) % 2 == 0) ? u_out : alt;
+    SmoothArgs ak = a;
+    ak.zero_guess = cur == nullptr;
+    if ((rc = launch_smooth(pr, precision, f, cur ? cur : f, out, ak, iters, s))) return rc;
+    if (stats) {
+      unsigned long long *dev = (unsigned long long *)pr->red_buf;
+      if ((rc = iter_stats(pr->ncell, iters, dev, s))) return rc;
+      unsigned long long h[2];
+      DG_HIP(hipMemcpyAsync(h, dev, sizeof(h), hipMemcpyDeviceToHost, s));
+      DG_HIP(hipStreamSynchronize(s));
+      tot += h[0];
+      mx = (int)h[1] > mx ? (int)h[1] : mx;
+    }
+    cur = out;
+  }
+  if (stats) {
+    stats->blocks = (long long)pr->ncell * opts->n_sweeps;
+    stats->inner_total = (long long)tot;
+    stats->inner_max = mx;
+    stats->inner_avg = stats->blocks ? (double)tot / stats->blocks : 0.0;
+  }
+  return DG_OK;
+}
+
+int dg_mg_vcycle(dg_problem *pr, int precision, const void *r, void *z, const dg_mg_opts *opts, void *stream) {
+  if (!pr || !opts) {
+    set_error("problem or options are NULL");
+    return DG_EINVAL;
+  }
+  int rc;
+  if ((rc = check_prec(precision)) || (rc = check_vec(r, "r")) || (rc = check_vec(z, "z"))) return rc;
+  if (r == z) {
+    set_error("dg_mg_vcycle: r and z must differ");
+    return DG_EINVAL;
+  }
+  if (opts->n_pre < 0 || opts->n_post < 0) {
+    set_error("n_pre and n_post must be >= 0");
+    return DG_EINVAL;
+  }
+  return vcycle(pr, precision, r, z, opts, S(stream));
+}
+
+}  // extern "C"
+
+// exported for solve.cpp
+namespace dgmg {
+int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, double rnorm, float *r32,
+                  float *z32, hipStream_t s) {
+  int rc;
+  if (o->precond == DG_PRECOND_NONE) {
+    DG_HIP(hipMemcpyAsync(z, r, (size_t)pr->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return DG_OK;
+  }
+  const bool mixed = o->precond_precision == DG_FP32;
+  const double sc = (mixed && rnorm > 0) ? 1.0 / rnorm : 1.0;
+  const void *rin = r;
+  void *zout = z;
+  if (mixed) {
+    if ((rc = cast_d2f(pr->ndof, sc, r, r32, s))) return rc;
+    rin = r32;
+    zout = z32;
+  }
+  const int prec = mixed ? DG_FP32 : DG_FP64;
+  if (o->precond == DG_PRECOND_MG) {
+    if ((rc = vcycle(pr, prec, rin, zout, &o->mg, s))) return rc;
+  } else {
+    SmoothArgs a;
+    if ((rc = smooth_args(pr, &o->mg.smooth, a))) return rc;
+    a.zero_guess = 1;
+    if ((rc = launch_smooth(pr, prec, rin, rin, zout, a, nullptr, s))) return rc;
+  }
+  if (mixed && (rc = cast_f2d(pr->ndof, 1.0 / sc, z32, z, s))) return rc;
+  return DG_OK;
+}
+}  // namespace dgmg

@@ -1,0 +1,272 @@
+// Matrix-free DG operator apply v = A u (Sec. 3.1) and its block diagonal
+// D_T (eqn block_diag_apply), on gfx950.
+//
+// Mapping.  A workgroup of 256 lanes takes CPB = floor(256 / (p+1)^2)
+// consecutive cells (p=1: 64, p=2: 28, p=3: 16, p=4: 10).  The cells of a
+// workgroup are one contiguous range of the cell-major DOF vector, so the
+// staging load into LDS and the final store are fully coalesced.  Lane
+// (cell, a, b) owns the line index (a, b) of its cell and processes, one
+// after the other, the x-line (y=a, z=b), the y-line (x=a, z=b) and the
+// z-line (x=a, y=b) through it: each line is a (p+1)-vector read from LDS,
+// the 1-D operator is applied in registers, and the contributions of the
+// three directions are summed in an LDS accumulator.  Neighbour lines for
+// the face terms come from LDS when the neighbour cell belongs to the same
+// workgroup and from global memory (L2 / MALL hits) otherwise; only four
+// traces per neighbour line are formed.
+//
+// XCD-aware order: consecutive workgroup ids are spread round-robin over
+// the eight XCDs, so the logical block index is remapped to give every XCD
+// one contiguous slab of cells; the y and z neighbours a slab reads are then
+// mostly in that XCD's own L2.
+#include "line_ops.h"
+
+namespace dgmg {
+
+constexpr int kApplyThreads = 256;
+
+template <int N>
+struct ApplyShape {
+  static constexpr int N2 = N * N;
+  static constexpr int N3 = N * N * N;
+  static constexpr int CPB = kApplyThreads / N2;
+};
+
+__device__ inline int xcd_block(int b, int G) {
+  const int q = G >> 3, r = G & 7;
+  const int x = b & 7, k = b >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// position in the cell of node i on the line (a, b) along axis k
+template <int N>
+__device__ __host__ inline int line_pos(int k, int i, int a, int b) {
+  return k == 0 ? i + N * a + N * N * b : (k == 1 ? a + N * i + N * N * b : a + N * b + N * N * i);
+}
+
+// NB: with neighbour couplings (A) or without (D_T).
+template <int P, typename T, bool NB>
+__global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, DevTab<T, P + 1> tb, const T *__restrict__ u,
+                                                         T *__restrict__ v) {
+  constexpr int N = P + 1;
+  using S = ApplyShape<N>;
+  __shared__ T us[S::CPB * S::N3];
+  __shared__ T vs[S::CPB * S::N3];
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int c0 = blk * S::CPB;
+  const int ncb = min(S::CPB, g.ncell - c0);
+  const int tid = threadIdx.x;
+  const T *ub = u + (size_t)c0 * S::N3;
+  for (int idx = tid; idx < ncb * S::N3; idx += kApplyThreads) us[idx] = ub[idx];
+  __syncthreads();
+  const int cl = tid / S::N2;
+  const int ln = tid - cl * S::N2;
+  const int a = ln % N, b = ln / N;
+  const bool active = cl < ncb;
+  const int c = c0 + cl;
+  int ijk[3] = {0, 0, 0};
+  if (active) {
+    ijk[0] = c % g.nx;
+    ijk[1] = (c / g.nx) % g.ny;
+    ijk[2] = c / (g.nx * g.ny);
+  }
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  const int stride[3] = {1, g.nx, g.nx * g.ny};
+  const bool hasb = g.has_b != 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (active) {
+      T ul[N], out[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) ul[i] = us[cl * S::N3 + line_pos<N>(k, i, a, b)];
+      T tLu = T(0), tLd = T(0), tRu = T(0), tRd = T(0);
+      if (NB) {
+        if (ijk[k] > 0) {
+          const int cn = c - stride[k];
+          const T *src = (cn >= c0) ? us + (cn - c0) * S::N3 : u + (size_t)cn * S::N3;
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            const T x = src[line_pos<N>(k, i, a, b)];
+            tLu += tb.e1[i] * x;
+            tLd += tb.d1[i] * x;
+          }
+        }
+        if (ijk[k] < nn[k] - 1) {
+          const int cn = c + stride[k];
+          const T *src = (cn < c0 + ncb) ? us + (cn - c0) * S::N3 : u + (size_t)cn * S::N3;
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            const T x = src[line_pos<N>(k, i, a, b)];
+            tRu += tb.e0[i] * x;
+            tRd += tb.d0[i] * x;
+          }
+        }
+      }
+      const LineCtx<T> ctx = make_ctx<T, N>(g, tb, k, ijk[0], ijk[1], ijk[2], a, b);
+      line_apply<T, N>(ctx, tb, ul, tLu, tLd, tRu, tRd, hasb, out);
+      if (k == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) vs[cl * S::N3 + line_pos<N>(0, i, a, b)] = out[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) vs[cl * S::N3 + line_pos<N>(k, i, a, b)] += out[i];
+      }
+    }
+    __syncthreads();
+  }
+  T *vb = v + (size_t)c0 * S::N3;
+  for (int idx = tid; idx < ncb * S::N3; idx += kApplyThreads) vb[idx] = vs[idx];
+}
+
+// diag(D_T): one lane per DOF.
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_block_diag(Geo g, DevTab<T, P + 1> tb, T *__restrict__ diag) {
+  constexpr int N = P + 1, N2 = N * N, N3 = N * N * N;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)g.ncell * N3) return;
+  const int c = (int)(gid / N3);
+  const int j = (int)(gid - (int64_t)c * N3);
+  const int q[3] = {j % N, (j / N) % N, j / N2};
+  const int ix = c % g.nx, iy = (c / g.nx) % g.ny, iz = c / (g.nx * g.ny);
+  T s = T(0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int t1 = (k == 0) ? 1 : 0, t2 = (k == 2) ? 1 : 2;
+    const LineCtx<T> ctx = make_ctx<T, N>(g, tb, k, ix, iy, iz, q[t1], q[t2]);
+    s += line_diag<T, N>(ctx, tb, q[k], g.has_b != 0);
+  }
+  diag[gid] = s;
+}
+
+// Right-hand side l_h(psi_i) (eqn rhs), one lane per DOF.  With the
+// collocated basis, (f, psi_i)_T = W_i f(x_i); boundary faces add the
+// Neumann flux -(j, psi_i)_F and on Dirichlet faces
+// -(Phi(0,g,b_nu), psi_i)_F - (nu.K grad psi_i, g)_F + gamma_F (g, psi_i)_F.
+template <int P>
+__global__ __launch_bounds__(256) void k_rhs(Geo g, DevTab<double, P + 1> tb, const double *__restrict__ fq,
+                                             const double *__restrict__ bq, double *__restrict__ rhs) {
+  constexpr int N = P + 1, N2 = N * N, N3 = N * N * N;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)g.ncell * N3) return;
+  const int c = (int)(gid / N3);
+  const int j = (int)(gid - (int64_t)c * N3);
+  const int q[3] = {j % N, (j / N) % N, j / N2};
+  const int ijk[3] = {c % g.nx, (c / g.nx) % g.ny, c / (g.nx * g.ny)};
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  double val = 0.0;
+  if (fq) val = tb.w[q[0]] * tb.w[q[1]] * tb.w[q[2]] * g.vol * fq[gid];
+  if (bq) {
+    int64_t off = 0;
+    for (int f = 0; f < 6; ++f) {
+      const int k = f >> 1, side = f & 1;
+      const int t1 = (k == 0) ? 1 : 0, t2 = (k == 2) ? 1 : 2;
+      const int64_t nface = (int64_t)nn[t1] * nn[t2];
+      const bool on = side ? (ijk[k] == nn[k] - 1) : (ijk[k] == 0);
+      if (on) {
+        const int64_t cf = ijk[t1] + (int64_t)nn[t1] * ijk[t2];
+        const double bv = bq[off + cf * N2 + q[t1] + N * q[t2]];
+        const double WF = tb.w[q[t1]] * tb.w[q[t2]] * g.vol / g.h[k];
+        const double ev = side ? tb.e1[q[k]] : tb.e0[q[k]];
+        const double dv = (side ? tb.d1[q[k]] : tb.d0[q[k]]) / g.h[k];
+        if (g.bc[f] == FACE_NEUMANN) {
+          val -= WF * bv * ev;
+        } else {
+          const double nu = side ? 1.0 : -1.0;
+          const double d = g.K[3 * c + k];
+          const double gam = g.sigma * d / g.h[k];
+          double bnu = 0.0;
+          if (g.has_b) {
+            double x[3];
+            for (int a = 0; a < 3; ++a) x[a] = (ijk[a] + (double)tb.xi[q[a]]) * g.h[a];
+            x[k] = (ijk[k] + side) * g.h[k];
+            double bk = g.b0[k];
+            for (int a = 0; a < 3; ++a) bk += g.B[3 * k + a] * x[a];
+            bnu = nu * bk;
+          }
+          const double inflow = bnu < 0.0 ? bnu : 0.0;
+          val -= WF * (inflow * bv * ev + bv * nu * d * dv - gam * bv * ev);
+        }
+      }
+      off += nface * N2;
+    }
+  }
+  rhs[gid] = val;
+}
+
+template <int P, typename T>
+static int launch_apply_t(const dg_problem *pr, const void *u, void *v, hipStream_t s, bool nb) {
+  constexpr int N = P + 1;
+  const int G = (int)((pr->ncell + ApplyShape<N>::CPB - 1) / ApplyShape<N>::CPB);
+  DevTab<T, N> tb = make_devtab<T, N>(pr->tab);
+  if (nb)
+    hipLaunchKernelGGL((k_apply<P, T, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, tb, (const T *)u, (T *)v);
+  else
+    hipLaunchKernelGGL((k_apply<P, T, false>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, tb, (const T *)u,
+                       (T *)v);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+template <typename T>
+static int dispatch_apply(const dg_problem *pr, const void *u, void *v, hipStream_t s, bool nb) {
+  switch (pr->p) {
+    case 1: return launch_apply_t<1, T>(pr, u, v, s, nb);
+    case 2: return launch_apply_t<2, T>(pr, u, v, s, nb);
+    case 3: return launch_apply_t<3, T>(pr, u, v, s, nb);
+    case 4: return launch_apply_t<4, T>(pr, u, v, s, nb);
+  }
+  set_error("unsupported degree");
+  return DG_EINVAL;
+}
+
+int launch_apply(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s) {
+  return prec == DG_FP64 ? dispatch_apply<double>(pr, u, v, s, true) : dispatch_apply<float>(pr, u, v, s, true);
+}
+
+int launch_block_apply(const dg_problem *pr, int prec, const void *x, void *y, hipStream_t s) {
+  return prec == DG_FP64 ? dispatch_apply<double>(pr, x, y, s, false) : dispatch_apply<float>(pr, x, y, s, false);
+}
+
+template <int P, typename T>
+static int launch_diag_t(const dg_problem *pr, void *diag, hipStream_t s) {
+  constexpr int N = P + 1;
+  const int64_t tot = pr->ndof;
+  const int G = (int)((tot + 255) / 256);
+  DevTab<T, N> tb = make_devtab<T, N>(pr->tab);
+  hipLaunchKernelGGL((k_block_diag<P, T>), dim3(G), dim3(256), 0, s, pr->geo, tb, (T *)diag);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int launch_block_diag(const dg_problem *pr, int prec, void *diag, hipStream_t s) {
+  switch (pr->p) {
+    case 1: return prec == DG_FP64 ? launch_diag_t<1, double>(pr, diag, s) : launch_diag_t<1, float>(pr, diag, s);
+    case 2: return prec == DG_FP64 ? launch_diag_t<2, double>(pr, diag, s) : launch_diag_t<2, float>(pr, diag, s);
+    case 3: return prec == DG_FP64 ? launch_diag_t<3, double>(pr, diag, s) : launch_diag_t<3, float>(pr, diag, s);
+    case 4: return prec == DG_FP64 ? launch_diag_t<4, double>(pr, diag, s) : launch_diag_t<4, float>(pr, diag, s);
+  }
+  set_error("unsupported degree");
+  return DG_EINVAL;
+}
+
+template <int P>
+static int launch_rhs_t(const dg_problem *pr, const double *fq, const double *bq, double *rhs, hipStream_t s) {
+  constexpr int N = P + 1;
+  const int G = (int)((pr->ndof + 255) / 256);
+  DevTab<double, N> tb = make_devtab<double, N>(pr->tab);
+  hipLaunchKernelGGL((k_rhs<P>), dim3(G), dim3(256), 0, s, pr->geo, tb, fq, bq, rhs);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int launch_rhs(const dg_problem *pr, const double *fq, const double *bq, double *rhs, hipStream_t s) {
+  switch (pr->p) {
+    case 1: return launch_rhs_t<1>(pr, fq, bq, rhs, s);
+    case 2: return launch_rhs_t<2>(pr, fq, bq, rhs, s);
+    case 3: return launch_rhs_t<3>(pr, fq, bq, rhs, s);
+    case 4: return launch_rhs_t<4>(pr, fq, bq, rhs, s);
+  }
+  set_error("unsupported degree");
+  return DG_EINVAL;
+}
+
+}  // namespace dgmg

@@ -1,0 +1,139 @@
+// Internal declarations of libdgmg (not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dgmg.h"
+
+namespace dgmg {
+
+constexpr int kMaxN = DG_MAX_P + 1;
+
+// Face kinds of a cell side.
+enum FaceKind : int { FACE_INTERIOR = 0, FACE_DIRICHLET = 1, FACE_NEUMANN = 2 };
+
+// 1-D tables of the Gauss-Legendre nodal basis on [0,1] (double, host).
+// D[q][j] = l_j'(xi_q); S = D^T W D; end values / derivatives of l_j.
+struct Tables1D {
+  int n = 0;
+  double xi[kMaxN], w[kMaxN];
+  double D[kMaxN][kMaxN];
+  double S[kMaxN][kMaxN];
+  double e0[kMaxN], e1[kMaxN], d0[kMaxN], d1[kMaxN];
+};
+void build_tables(int n, Tables1D &t);
+
+// Kernel-side copy of the tables in the compute precision.  N is fixed at
+// compile time; every loop over it unrolls.
+template <typename T, int N>
+struct DevTab {
+  T S[N][N];   // D^T diag(w) D
+  T Dt[N][N];  // Dt[i][q] = D[q][i]
+  T w[N], xi[N], e0[N], e1[N], d0[N], d1[N];
+};
+
+template <typename T, int N>
+DevTab<T, N> make_devtab(const Tables1D &t) {
+  DevTab<T, N> d;
+  for (int i = 0; i < N; ++i) {
+    for (int j = 0; j < N; ++j) {
+      d.S[i][j] = (T)t.S[i][j];
+      d.Dt[i][j] = (T)t.D[j][i];
+    }
+    d.w[i] = (T)t.w[i];
+    d.xi[i] = (T)t.xi[i];
+    d.e0[i] = (T)t.e0[i];
+    d.e1[i] = (T)t.e1[i];
+    d.d0[i] = (T)t.d0[i];
+    d.d1[i] = (T)t.d1[i];
+  }
+  return d;
+}
+
+// Mesh, coefficients and discretisation constants passed to kernels.
+struct Geo {
+  int nx, ny, nz;
+  int ncell;
+  double h[3];
+  double vol;
+  double sigma;   // penalty prefactor
+  int bc[6];      // FACE_DIRICHLET / FACE_NEUMANN per box face
+  double b0[3];
+  double B[9];
+  int has_b;
+  int has_c;
+  const double *K;  // device [ncell][3]
+  const double *c;  // device [ncell] (valid when has_c)
+};
+
+// P0 aggregation hierarchy used as the simple coarse solver.
+struct CoarseLevel {
+  int nx, ny, nz, n;
+  // 7-point stencil per unknown: diag, -x,+x,-y,+y,-z,+z couplings
+  double *A64 = nullptr;  // device [7][n]
+  float *A32 = nullptr;
+  double *r64 = nullptr, *x64 = nullptr, *t64 = nullptr;  // device [n]
+  float *r32 = nullptr, *x32 = nullptr, *t32 = nullptr;
+};
+
+struct Workspace {
+  size_t bytes = 0;
+  void *buf = nullptr;
+};
+
+}  // namespace dgmg
+
+struct dg_problem {
+  dg_problem_desc desc;
+  int p = 0, n = 0, nloc = 0;
+  int64_t ncell = 0, ndof = 0;
+  dgmg::Geo geo;
+  dgmg::Tables1D tab;
+  double *dK = nullptr;
+  double *dc = nullptr;
+  int device = 0;
+  // coarse hierarchy (level 0 = one unknown per cell)
+  std::vector<dgmg::CoarseLevel> levels;
+  double *bottom_inv64 = nullptr;  // dense inverse of the coarsest matrix
+  float *bottom_inv32 = nullptr;
+  int bottom_n = 0;
+  // DG-sized temporaries for the V-cycle and smoother (allocated lazily)
+  void *mg_tmp[2][4] = {{nullptr}};  // [precision][k]
+  int *iters_buf = nullptr;          // [ncell]
+  void *red_buf = nullptr;           // reduction scratch
+  size_t held_bytes = 0;
+};
+
+namespace dgmg {
+
+void set_error(const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define DG_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e__ = (call);                           \
+    if (e__ != hipSuccess) return dgmg::hip_fail(e__, #call); \
+  } while (0)
+
+// kernel launchers (apply.hip / smooth.hip / vec.hip / coarse.hip)
+int launch_apply(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s);
+int launch_block_apply(const dg_problem *pr, int prec, const void *x, void *y, hipStream_t s);
+int launch_block_diag(const dg_problem *pr, int prec, void *diag, hipStream_t s);
+int launch_rhs(const dg_problem *pr, const double *f_qp, const double *bnd, double *rhs, hipStream_t s);
+
+struct SmoothArgs {
+  double omega, eps;
+  int max_inner, inner, restart;
+  int zero_guess;   // u_in treated as 0
+  int write_du;     // output is the correction only (block solve)
+  int defect;       // compute d = f - A u (otherwise d = f)
+};
+int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin, void *uout,
+                  const SmoothArgs &a, int *iters, hipStream_t s);
+
+}  // namespace dgmg

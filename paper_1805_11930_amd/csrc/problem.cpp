@@ -1,0 +1,446 @@
+// Problem handle: validation, device copies of the coefficients, 1-D
+// tables and the P0 coarse hierarchy (Sec. 2.2.2-2.2.3, App. A.1).
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+
+namespace dgmg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int hip_fail(hipError_t e, const char *what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? DG_ENOMEM : DG_EDEVICE;
+}
+
+static int dmalloc(dg_problem *pr, void **p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_fail(e, "hipMalloc");
+  }
+  pr->held_bytes += bytes;
+  return DG_OK;
+}
+
+// P0 coarse matrix A_hat_{T,T'} = a_h(1_T', 1_T) (App. A.1, eqn
+// p0_galerkin1): gradients of P0 functions vanish, so only the reaction
+// c |T|, the upwind terms and the penalty terms remain.  The face integrals
+// of the upwind terms use the same tangential Gauss points as the DG
+// operator, so A_hat equals P^T A P exactly.
+static void p0_stencil(const dg_problem *pr, const std::vector<double> &K, const std::vector<double> &cc,
+                       std::vector<double> &A) {
+  const Geo &g = pr->geo;
+  const int64_t n = pr->ncell;
+  const int N = pr->n;
+  const Tables1D &t = pr->tab;
+  A.assign(7 * n, 0.0);
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  const int64_t stride[3] = {1, g.nx, (int64_t)g.nx * g.ny};
+  for (int64_t c = 0; c < n; ++c) {
+    const int ijk[3] = {(int)(c % g.nx), (int)((c / g.nx) % g.ny), (int)(c / ((int64_t)g.nx * g.ny))};
+    A[c] += cc[c] * g.vol;
+    for (int k = 0; k < 3; ++k) {
+      const int t1 = (k == 0) ? 1 : 0, t2 = (k == 2) ? 1 : 2;
+      const double area = g.vol / g.h[k];
+      for (int side = 0; side < 2; ++side) {
+        const bool boundary = side ? (ijk[k] == nn[k] - 1) : (ijk[k] == 0);
+        // sum over face points of W^F b_nu chi (outward / T- orientation)
+        auto upwind = [&](double nu, bool positive_part) {
+          double s = 0.0;
+          if (!g.has_b) return 0.0;
+          for (int a = 0; a < N; ++a)
+            for (int b = 0; b < N; ++b) {
+              double x[3];
+              x[k] = (ijk[k] + side) * g.h[k];
+              x[t1] = (ijk[t1] + t.xi[a]) * g.h[t1];
+              x[t2] = (ijk[t2] + t.xi[b]) * g.h[t2];
+              double bk = g.b0[k];
+              for (int l = 0; l < 3; ++l) bk += g.B[3 * k + l] * x[l];
+              const double bnu = nu * bk;
+              const double WF = t.w[a] * t.w[b] * area;
+              if (positive_part ? (bnu >= 0.0) : (bnu < 0.0)) s += WF * bnu;
+            }
+          return s;
+        };
+        if (boundary) {
+          if (g.bc[2 * k + side] != FACE_DIRICHLET) continue;
+          const double d = K[3 * c + k];
+          const double gam = g.sigma * d / g.h[k];
+          A[c] += gam * area + upwind(side ? 1.0 : -1.0, true);
+        } else if (side == 1) {
+          // interior face, this cell is T- (nu = +e_k), neighbour T+
+          const int64_t cu = c + stride[k];
+          const double dm = K[3 * c + k], dp = K[3 * cu + k];
+          const double gam = g.sigma * 2.0 * dm * dp / (dm + dp) / g.h[k];
+          const double up_pos = upwind(1.0, true);   // sum W b_nu chi-
+          const double up_neg = upwind(1.0, false);  // sum W b_nu chi+
+          A[c] += up_pos + gam * area;                          // (-,-)
+          A[(2 + 2 * k) * n + c] += up_neg - gam * area;        // row T-, col T+ (+k)
+          A[(1 + 2 * k) * n + cu] += -up_pos - gam * area;      // row T+, col T- (-k)
+          A[cu] += -up_neg + gam * area;                        // (+,+)
+        }
+      }
+    }
+  }
+}
+
+// Galerkin product with piecewise-constant aggregation of 2x2x2 blocks.
+static void aggregate(const std::vector<double> &A, int nx, int ny, int nz, std::vector<double> &Ac, int &cnx,
+                      int &cny, int &cnz) {
+  cnx = (nx + 1) / 2;
+  cny = (ny + 1) / 2;
+  cnz = (nz + 1) / 2;
+  const int64_t n = (int64_t)nx * ny * nz, nc = (int64_t)cnx * cny * cnz;
+  Ac.assign(7 * nc, 0.0);
+  for (int iz = 0; iz < nz; ++iz)
+    for (int iy = 0; iy < ny; ++iy)
+      for (int ix = 0; ix < nx; ++ix) {
+        const int64_t i = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
+        const int jx = ix / 2, jy = iy / 2, jz = iz / 2;
+        const int64_t J = jx + (int64_t)cnx * (jy + (int64_t)cny * jz);
+        Ac[J] += A[i];
+        const int ii[3] = {ix, iy, iz};
+        const int jj[3] = {jx, jy, jz};
+        for (int dir = 0; dir < 6; ++dir) {
+          const double a = A[(1 + dir) * n + i];
+          if (a == 0.0) continue;
+          const int k = dir / 2, sgn = (dir & 1) ? 1 : -1;
+          const int nb = ii[k] + sgn;
+          if ((nb / 2) == jj[k] && nb >= 0)
+            Ac[J] += a;  // neighbour inside the same aggregate
+          else
+            Ac[(1 + dir) * nc + J] += a;
+        }
+      }
+}
+
+static bool dense_inverse(std::vector<double> M, int n, std::vector<double> &inv) {
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(M[(size_t)r * n + col]) > std::fabs(M[(size_t)piv * n + col])) piv = r;
+    if (M[(size_t)piv * n + col] == 0.0) return false;
+    if (piv != col)
+      for (int j = 0; j < n; ++j) {
+        std::swap(M[(size_t)piv * n + j], M[(size_t)col * n + j]);
+        std::swap(inv[(size_t)piv * n + j], inv[(size_t)col * n + j]);
+      }
+    const double d = 1.0 / M[(size_t)col * n + col];
+    for (int j = 0; j < n; ++j) {
+      M[(size_t)col * n + j] *= d;
+      inv[(size_t)col * n + j] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = M[(size_t)r * n + col];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        M[(size_t)r * n + j] -= f * M[(size_t)col * n + j];
+        inv[(size_t)r * n + j] -= f * inv[(size_t)col * n + j];
+      }
+    }
+  }
+  return true;
+}
+
+static int upload_level(dg_problem *pr, CoarseLevel &L, const std::vector<double> &A) {
+  const int64_t n = L.n;
+  int rc;
+  if ((rc = dmalloc(pr, (void **)&L.A64, 7 * n * sizeof(double)))) return rc;
+  if ((rc = dmalloc(pr, (void **)&L.A32, 7 * n * sizeof(float)))) return rc;
+  for (double **p : {&L.r64, &L.x64, &L.t64})
+    if ((rc = dmalloc(pr, (void **)p, n * sizeof(double)))) return rc;
+  for (float **p : {&L.r32, &L.x32, &L.t32})
+    if ((rc = dmalloc(pr, (void **)p, n * sizeof(float)))) return rc;
+  std::vector<float> Af(A.begin(), A.end());
+  DG_HIP(hipMemcpy(L.A64, A.data(), 7 * n * sizeof(double), hipMemcpyHostToDevice));
+  DG_HIP(hipMemcpy(L.A32, Af.data(), 7 * n * sizeof(float), hipMemcpyHostToDevice));
+  return DG_OK;
+}
+
+constexpr int kBottomMax = 512;
+
+static int build_coarse(dg_problem *pr, const std::vector<double> &K, const std::vector<double> &cc) {
+  std::vector<double> A;
+  p0_stencil(pr, K, cc, A);
+  int nx = pr->geo.nx, ny = pr->geo.ny, nz = pr->geo.nz;
+  while (true) {
+    CoarseLevel L;
+    L.nx = nx;
+    L.ny = ny;
+    L.nz = nz;
+    L.n = nx * ny * nz;
+    int rc = upload_level(pr, L, A);
+    pr->levels.push_back(L);
+    if (rc) return rc;
+    if (L.n <= kBottomMax) break;
+    std::vector<double> Ac;
+    int cnx, cny, cnz;
+    aggregate(A, nx, ny, nz, Ac, cnx, cny, cnz);
+    A.swap(Ac);
+    nx = cnx;
+    ny = cny;
+    nz = cnz;
+  }
+  // dense inverse of the coarsest level
+  const CoarseLevel &B = pr->levels.back();
+  const int n = B.n;
+  std::vector<double> M((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const int ix = i % B.nx, iy = (i / B.nx) % B.ny, iz = i / (B.nx * B.ny);
+    M[(size_t)i * n + i] = A[i];
+    const int off[6] = {-1, 1, -B.nx, B.nx, -B.nx * B.ny, B.nx * B.ny};
+    const bool ok[6] = {ix > 0, ix < B.nx - 1, iy > 0, iy < B.ny - 1, iz > 0, iz < B.nz - 1};
+    for (int d = 0; d < 6; ++d)
+      if (ok[d]) M[(size_t)i * n + i + off[d]] += A[(1 + d) * n + i];
+  }
+  std::vector<double> inv;
+  if (!dense_inverse(M, n, inv)) {
+    set_error("singular coarse matrix (pure Neumann problem without reaction?)");
+    return DG_EINVAL;
+  }
+  int rc;
+  if ((rc = dmalloc(pr, (void **)&pr->bottom_inv64, (size_t)n * n * sizeof(double)))) return rc;
+  if ((rc = dmalloc(pr, (void **)&pr->bottom_inv32, (size_t)n * n * sizeof(float)))) return rc;
+  std::vector<float> invf(inv.begin(), inv.end());
+  DG_HIP(hipMemcpy(pr->bottom_inv64, inv.data(), (size_t)n * n * sizeof(double), hipMemcpyHostToDevice));
+  DG_HIP(hipMemcpy(pr->bottom_inv32, invf.data(), (size_t)n * n * sizeof(float), hipMemcpyHostToDevice));
+  pr->bottom_n = n;
+  return DG_OK;
+}
+
+int alloc_tmp(dg_problem *pr, int prec, int k, void **out) {
+  if (!pr->mg_tmp[prec][k]) {
+    const size_t es = prec == DG_FP64 ? sizeof(double) : sizeof(float);
+    int rc = dmalloc(pr, &pr->mg_tmp[prec][k], (size_t)pr->ndof * es);
+    if (rc) return rc;
+  }
+  *out = pr->mg_tmp[prec][k];
+  return DG_OK;
+}
+
+int alloc_small(dg_problem *pr) {
+  int rc;
+  if (!pr->iters_buf && (rc = dmalloc(pr, (void **)&pr->iters_buf, pr->ncell * sizeof(int)))) return rc;
+  if (!pr->red_buf && (rc = dmalloc(pr, &pr->red_buf, 8 * 1024 * sizeof(double) + 64))) return rc;
+  return DG_OK;
+}
+
+}  // namespace dgmg
+
+using namespace dgmg;
+
+extern "C" {
+
+const char *dg_last_error(void) { return g_last_error.c_str(); }
+
+void dg_problem_destroy(dg_problem *pr) {
+  if (!pr) return;
+  (void)hipFree(pr->dK);
+  (void)hipFree(pr->dc);
+  for (auto &L : pr->levels) {
+    (void)hipFree(L.A64);
+    (void)hipFree(L.A32);
+    (void)hipFree(L.r64);
+    (void)hipFree(L.x64);
+    (void)hipFree(L.t64);
+    (void)hipFree(L.r32);
+    (void)hipFree(L.x32);
+    (void)hipFree(L.t32);
+  }
+  (void)hipFree(pr->bottom_inv64);
+  (void)hipFree(pr->bottom_inv32);
+  for (auto &row : pr->mg_tmp)
+    for (void *p : row) (void)hipFree(p);
+  (void)hipFree(pr->iters_buf);
+  (void)hipFree(pr->red_buf);
+  delete pr;
+}
+
+int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
+  if (!out) {
+    set_error("dg_problem_create: out is NULL");
+    return DG_EINVAL;
+  }
+  *out = nullptr;
+  if (!d) {
+    set_error("dg_problem_create: desc is NULL");
+    return DG_EINVAL;
+  }
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) {
+    set_error("cell counts must be >= 1");
+    return DG_EINVAL;
+  }
+  if (!(d->lx > 0) || !(d->ly > 0) || !(d->lz > 0) || !std::isfinite(d->lx) || !std::isfinite(d->ly) ||
+      !std::isfinite(d->lz)) {
+    set_error("box lengths must be finite and > 0");
+    return DG_EINVAL;
+  }
+  if (d->p < 1 || d->p > DG_MAX_P) {
+    set_error("p must be in 1..DG_MAX_P");
+    return DG_EINVAL;
+  }
+  const int64_t ncell = (int64_t)d->nx * d->ny * d->nz;
+  const int n = d->p + 1;
+  if (ncell * n * n * n > ((int64_t)1 << 31) - 1 || ncell > ((int64_t)1 << 30)) {
+    set_error("problem too large for 32-bit cell indexing");
+    return DG_EINVAL;
+  }
+  for (int f = 0; f < 6; ++f)
+    if (d->bc[f] != DG_BC_DIRICHLET && d->bc[f] != DG_BC_NEUMANN) {
+      set_error("bc entries must be DG_BC_DIRICHLET or DG_BC_NEUMANN");
+      return DG_EINVAL;
+    }
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(d->b0[i])) {
+      set_error("b0 must be finite");
+      return DG_EINVAL;
+    }
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(d->B[i])) {
+      set_error("B must be finite");
+      return DG_EINVAL;
+    }
+  if (!std::isfinite(d->penalty_factor)) {
+    set_error("penalty_factor must be finite");
+    return DG_EINVAL;
+  }
+  std::vector<double> K(3 * ncell), cc(ncell, 0.0);
+  for (int64_t i = 0; i < 3 * ncell; ++i) {
+    const double v = d->K ? d->K[i] : d->K_scalar;
+    if (!(v > 0) || !std::isfinite(v)) {
+      set_error("K must be finite and > 0");
+      return DG_EINVAL;
+    }
+    K[i] = v;
+  }
+  bool has_c = false;
+  for (int64_t i = 0; i < ncell; ++i) {
+    const double v = d->c ? d->c[i] : d->c_scalar;
+    if (!(v >= 0) || !std::isfinite(v)) {
+      set_error("c must be finite and >= 0");
+      return DG_EINVAL;
+    }
+    cc[i] = v;
+    has_c = has_c || v != 0.0;
+  }
+  dg_problem *pr = new dg_problem();
+  pr->desc = *d;
+  pr->desc.K = nullptr;
+  pr->desc.c = nullptr;
+  pr->p = d->p;
+  pr->n = n;
+  pr->nloc = n * n * n;
+  pr->ncell = ncell;
+  pr->ndof = ncell * pr->nloc;
+  (void)hipGetDevice(&pr->device);
+  build_tables(n, pr->tab);
+  Geo &g = pr->geo;
+  g.nx = d->nx;
+  g.ny = d->ny;
+  g.nz = d->nz;
+  g.ncell = (int)ncell;
+  g.h[0] = d->lx / d->nx;
+  g.h[1] = d->ly / d->ny;
+  g.h[2] = d->lz / d->nz;
+  g.vol = g.h[0] * g.h[1] * g.h[2];
+  g.sigma = d->penalty_factor > 0 ? d->penalty_factor : 1.25 * d->p * (d->p + 2);
+  for (int f = 0; f < 6; ++f) g.bc[f] = d->bc[f] == DG_BC_DIRICHLET ? FACE_DIRICHLET : FACE_NEUMANN;
+  g.has_b = 0;
+  for (int i = 0; i < 3; ++i) {
+    g.b0[i] = d->b0[i];
+    if (d->b0[i] != 0.0) g.has_b = 1;
+  }
+  for (int i = 0; i < 9; ++i) {
+    g.B[i] = d->B[i];
+    if (d->B[i] != 0.0) g.has_b = 1;
+  }
+  g.has_c = has_c ? 1 : 0;
+  int rc = dmalloc(pr, (void **)&pr->dK, 3 * ncell * sizeof(double));
+  if (!rc) rc = dmalloc(pr, (void **)&pr->dc, ncell * sizeof(double));
+  if (!rc) {
+    hipError_t e = hipMemcpy(pr->dK, K.data(), 3 * ncell * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(pr->dc, cc.data(), ncell * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy");
+  }
+  g.K = pr->dK;
+  g.c = pr->dc;
+  if (!rc) rc = build_coarse(pr, K, cc);
+  if (!rc) rc = alloc_small(pr);
+  if (rc) {
+    dg_problem_destroy(pr);
+    return rc;
+  }
+  *out = pr;
+  return DG_OK;
+}
+
+int64_t dg_ndof(const dg_problem *pr) { return pr ? pr->ndof : -1; }
+
+int64_t dg_boundary_npoints(const dg_problem *pr) {
+  if (!pr) return -1;
+  const Geo &g = pr->geo;
+  const int64_t n2 = (int64_t)pr->n * pr->n;
+  return 2 * n2 * ((int64_t)g.ny * g.nz + (int64_t)g.nx * g.nz + (int64_t)g.nx * g.ny);
+}
+
+int dg_node_points(const dg_problem *pr, double *xyz) {
+  if (!pr || !xyz) {
+    set_error("dg_node_points: NULL argument");
+    return DG_EINVAL;
+  }
+  const Geo &g = pr->geo;
+  const int N = pr->n;
+  int64_t o = 0;
+  for (int64_t c = 0; c < pr->ncell; ++c) {
+    const int ix = (int)(c % g.nx), iy = (int)((c / g.nx) % g.ny), iz = (int)(c / ((int64_t)g.nx * g.ny));
+    for (int k = 0; k < N; ++k)
+      for (int j = 0; j < N; ++j)
+        for (int i = 0; i < N; ++i) {
+          xyz[3 * o + 0] = (ix + pr->tab.xi[i]) * g.h[0];
+          xyz[3 * o + 1] = (iy + pr->tab.xi[j]) * g.h[1];
+          xyz[3 * o + 2] = (iz + pr->tab.xi[k]) * g.h[2];
+          ++o;
+        }
+  }
+  return DG_OK;
+}
+
+int dg_boundary_points(const dg_problem *pr, double *xyz) {
+  if (!pr || !xyz) {
+    set_error("dg_boundary_points: NULL argument");
+    return DG_EINVAL;
+  }
+  const Geo &g = pr->geo;
+  const int N = pr->n;
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  int64_t o = 0;
+  for (int f = 0; f < 6; ++f) {
+    const int k = f / 2, side = f % 2;
+    const int t1 = (k == 0) ? 1 : 0, t2 = (k == 2) ? 1 : 2;
+    for (int c2 = 0; c2 < nn[t2]; ++c2)
+      for (int c1 = 0; c1 < nn[t1]; ++c1)
+        for (int b = 0; b < N; ++b)
+          for (int a = 0; a < N; ++a) {
+            double x[3];
+            x[k] = side ? nn[k] * g.h[k] : 0.0;
+            x[t1] = (c1 + pr->tab.xi[a]) * g.h[t1];
+            x[t2] = (c2 + pr->tab.xi[b]) * g.h[t2];
+            xyz[3 * o + 0] = x[0];
+            xyz[3 * o + 1] = x[1];
+            xyz[3 * o + 2] = x[2];
+            ++o;
+          }
+  }
+  return DG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,490 @@
+// Fused matrix-free block-Jacobi sweep (alg block_jacobi, Sec. 2.2.1) with
+// inexact iterative block inversion (Sec. 2.2.1, eqn block_system; the
+// diagonal preconditioner of Sec. 3.2).
+//
+// One sweep  u_out = u_in + omega * D^-1_eps (f - A u_in)  runs as a single
+// kernel:  defect (the same line operators as the apply, neighbours read
+// from global memory), then a Krylov solve of D_T du_T = d_T in every cell,
+// then the damped update.
+//
+// Mapping.  A workgroup is ONE wavefront of 64 lanes.  Each cell gets L
+// lanes, L = the power of two >= (p+1)^2 (p=1: 4, p=2,3: 16, p=4: 32), so
+// 64/L cells share a wavefront and the per-cell dot products are butterfly
+// shuffles inside aligned lane groups (bitwise identical in every lane of
+// the cell).  Lane (a, b) keeps the x-line (y=a, z=b) of every Krylov
+// vector in registers.  D_T p is applied as in the apply: x-direction in
+// registers, y- and z-directions through an LDS transpose, two barriers per
+// application (a barrier of a one-wave workgroup is cheap).  Cells of a
+// wavefront iterate until all of them have converged; a converged cell is
+// masked, so the lock-step waste is bounded by the worst of 2-16 cells
+// rather than of a whole grid.
+//
+// Inner methods (readings of the paper, which does not spell them out):
+//   CG:    Hestenes-Stiefel PCG, x0 = 0, M = diag(D_T), stop when the
+//          recursive residual satisfies ||r||_2 <= eps ||d_T||_2 or after
+//          max_inner applications of D_T;
+//   GMRES: right-preconditioned restarted GMRES(restart), modified
+//          Gram-Schmidt, Givens rotations, stop when the Arnoldi residual
+//          estimate <= eps ||d_T||_2 or after max_inner applications.
+#include "line_ops.h"
+
+namespace dgmg {
+
+constexpr int kSmoothThreads = 64;
+constexpr int kGmresMax = 16;  // largest inner GMRES restart length
+
+template <int N>
+struct SmoothShape {
+  static constexpr int N2 = N * N;
+  static constexpr int N3 = N * N * N;
+  static constexpr int L = N2 <= 4 ? 4 : (N2 <= 16 ? 16 : 32);
+  static constexpr int CPW = kSmoothThreads / L;
+};
+
+template <int N>
+__device__ inline int lpos(int k, int i, int a, int b) {
+  return k == 0 ? i + N * a + N * N * b : (k == 1 ? a + N * i + N * N * b : a + N * b + N * N * i);
+}
+
+// Sum over the L lanes of a cell; every lane of the cell receives the same
+// bits (pairwise commutative butterfly).
+template <int L, typename T>
+__device__ inline T cell_sum(T v) {
+#pragma unroll
+  for (int m = 1; m < L; m <<= 1) v += __shfl_xor(v, m, L);
+  return v;
+}
+
+struct SmoothKArgs {
+  double omega, eps;
+  int max_inner, restart;
+  int zero_guess, write_du, defect;
+};
+
+template <int P, typename T>
+struct CellLines {
+  LineCtx<T> cx, cy, cz;
+};
+
+// q = D_T p on the lane's x-line.  All lanes of the wavefront must call it.
+template <int P, typename T>
+__device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1> &tb, bool on, bool hasb,
+                                const T (&p)[P + 1], T (&q)[P + 1], T *Ps, T *Qy, T *Qz, int a, int b) {
+  constexpr int N = P + 1;
+  T qx[N];
+  if (on) {
+    line_apply<T, N>(cl.cx, tb, p, T(0), T(0), T(0), T(0), hasb, qx);
+#pragma unroll
+    for (int i = 0; i < N; ++i) Ps[lpos<N>(0, i, a, b)] = p[i];
+  }
+  __syncthreads();
+  if (on) {
+    T yl[N], yo[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) yl[i] = Ps[lpos<N>(1, i, a, b)];
+    line_apply<T, N>(cl.cy, tb, yl, T(0), T(0), T(0), T(0), hasb, yo);
+#pragma unroll
+    for (int i = 0; i < N; ++i) Qy[lpos<N>(1, i, a, b)] = yo[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) yl[i] = Ps[lpos<N>(2, i, a, b)];
+    line_apply<T, N>(cl.cz, tb, yl, T(0), T(0), T(0), T(0), hasb, yo);
+#pragma unroll
+    for (int i = 0; i < N; ++i) Qz[lpos<N>(2, i, a, b)] = yo[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) q[i] = on ? qx[i] + Qy[lpos<N>(0, i, a, b)] + Qz[lpos<N>(0, i, a, b)] : T(0);
+}
+
+template <int P, int INNER, typename T>
+__global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, DevTab<T, P + 1> tb, const T *__restrict__ f,
+                                                           const T *__restrict__ uin, T *__restrict__ uout,
+                                                           SmoothKArgs sa, int *__restrict__ iters) {
+  constexpr int N = P + 1;
+  using S = SmoothShape<N>;
+  constexpr int L = S::L;
+  __shared__ T Ps_all[S::CPW * S::N3];
+  __shared__ T Qy_all[S::CPW * S::N3];
+  __shared__ T Qz_all[S::CPW * S::N3];
+  // GMRES storage: Krylov basis (lane-private x-lines) and the rotated
+  // Hessenberg columns of each cell.
+  __shared__ T Vs_all[INNER == DG_INNER_GMRES ? S::CPW * (kGmresMax + 1) * S::N3 : 1];
+  __shared__ T Hs_all[INNER == DG_INNER_GMRES ? S::CPW * kGmresMax * kGmresMax : 1];
+
+  const int tid = threadIdx.x;
+  const int cw = tid / L;
+  const int lane = tid - cw * L;
+  const int c = blockIdx.x * S::CPW + cw;
+  const bool on = (lane < S::N2) && (c < g.ncell);
+  const int a = on ? lane % N : 0;
+  const int b = on ? lane / N : 0;
+  T *Ps = Ps_all + cw * S::N3;
+  T *Qy = Qy_all + cw * S::N3;
+  T *Qz = Qz_all + cw * S::N3;
+  const bool hasb = g.has_b != 0;
+
+  int ijk[3] = {0, 0, 0};
+  CellLines<P, T> cl;
+  if (on) {
+    ijk[0] = c % g.nx;
+    ijk[1] = (c / g.nx) % g.ny;
+    ijk[2] = c / (g.nx * g.ny);
+    cl.cx = make_ctx<T, N>(g, tb, 0, ijk[0], ijk[1], ijk[2], a, b);
+    cl.cy = make_ctx<T, N>(g, tb, 1, ijk[0], ijk[1], ijk[2], a, b);
+    cl.cz = make_ctx<T, N>(g, tb, 2, ijk[0], ijk[1], ijk[2], a, b);
+  }
+  const size_t base = (size_t)c * S::N3;
+
+  // ---- defect d = f - A u -------------------------------------------------
+  T ul[N], d[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    ul[i] = (on && !sa.zero_guess) ? uin[base + lpos<N>(0, i, a, b)] : T(0);
+    d[i] = on ? f[base + lpos<N>(0, i, a, b)] : T(0);
+  }
+  if (sa.defect && !sa.zero_guess) {
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    const int stride[3] = {1, g.nx, g.nx * g.ny};
+    T ax[N];
+    if (on) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) Ps[lpos<N>(0, i, a, b)] = ul[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (on) {
+        T line[N], out[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) line[i] = k == 0 ? ul[i] : Ps[lpos<N>(k, i, a, b)];
+        T tLu = T(0), tLd = T(0), tRu = T(0), tRd = T(0);
+        if (ijk[k] > 0) {
+          const T *src = uin + (size_t)(c - stride[k]) * S::N3;
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            const T x = src[lpos<N>(k, i, a, b)];
+            tLu += tb.e1[i] * x;
+            tLd += tb.d1[i] * x;
+          }
+        }
+        if (ijk[k] < nn[k] - 1) {
+          const T *src = uin + (size_t)(c + stride[k]) * S::N3;
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            const T x = src[lpos<N>(k, i, a, b)];
+            tRu += tb.e0[i] * x;
+            tRd += tb.d0[i] * x;
+          }
+        }
+        const LineCtx<T> &ctx = k == 0 ? cl.cx : (k == 1 ? cl.cy : cl.cz);
+        line_apply<T, N>(ctx, tb, line, tLu, tLd, tRu, tRd, hasb, out);
+        if (k == 0) {
+#pragma unroll
+          for (int i = 0; i < N; ++i) ax[i] = out[i];
+        } else {
+          T *Q = k == 1 ? Qy : Qz;
+#pragma unroll
+          for (int i = 0; i < N; ++i) Q[lpos<N>(k, i, a, b)] = out[i];
+        }
+      }
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) d[i] -= ax[i] + Qy[lpos<N>(0, i, a, b)] + Qz[lpos<N>(0, i, a, b)];
+    }
+    __syncthreads();
+  }
+
+  // ---- diagonal preconditioner M = diag(D_T) ------------------------------
+  T dinv[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T dd = T(1);
+    if (on) {
+      const LineCtx<T> cy = make_ctx<T, N>(g, tb, 1, ijk[0], ijk[1], ijk[2], i, b);
+      const LineCtx<T> cz = make_ctx<T, N>(g, tb, 2, ijk[0], ijk[1], ijk[2], i, a);
+      dd = line_diag<T, N>(cl.cx, tb, i, hasb) + line_diag<T, N>(cy, tb, a, hasb) +
+           line_diag<T, N>(cz, tb, b, hasb);
+    }
+    dinv[i] = T(1) / dd;
+  }
+
+  // ---- inner solve D_T x = d ------------------------------------------------
+  T x[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = T(0);
+  int it = 0;
+  T dn2 = T(0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) dn2 += d[i] * d[i];
+  dn2 = cell_sum<L>(dn2);
+  const T epsT = (T)sa.eps;
+
+  if (INNER == DG_INNER_CG) {
+    T r[N], z[N], p[N], q[N];
+    T rho = T(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      r[i] = d[i];
+      z[i] = r[i] * dinv[i];
+      p[i] = z[i];
+      rho += r[i] * z[i];
+    }
+    rho = cell_sum<L>(rho);
+    const T tgt2 = epsT * epsT * dn2;
+    bool conv = !(dn2 > T(0));
+#pragma unroll 1
+    while (true) {
+      const bool act = !conv && it < sa.max_inner;
+      if (__ballot(act) == 0) break;
+      dt_apply<P, T>(cl, tb, on, hasb, p, q, Ps, Qy, Qz, a, b);
+      T pq = T(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) pq += p[i] * q[i];
+      pq = cell_sum<L>(pq);
+      bool act2 = act;
+      if (act && !(pq > T(0))) {  // breakdown: keep the iterate
+        conv = true;
+        act2 = false;
+      }
+      if (act2) {
+        const T alpha = rho / pq;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          x[i] += alpha * p[i];
+          r[i] -= alpha * q[i];
+        }
+        ++it;
+      }
+      T rr = T(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) rr += r[i] * r[i];
+      rr = cell_sum<L>(rr);
+      if (act2 && rr <= tgt2) conv = true;
+      T rz = T(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        z[i] = r[i] * dinv[i];
+        rz += r[i] * z[i];
+      }
+      rz = cell_sum<L>(rz);
+      if (act2 && !conv) {
+        const T beta = rz / rho;
+#pragma unroll
+        for (int i = 0; i < N; ++i) p[i] = z[i] + beta * p[i];
+        rho = rz;
+      }
+    }
+  } else {
+    // restarted right-preconditioned GMRES
+    const int R = sa.restart;
+    T *Vs = Vs_all + cw * (kGmresMax + 1) * S::N3;
+    T *Hs = Hs_all + cw * kGmresMax * kGmresMax;
+    const int my = lane * N;  // private slot of this lane's x-line in Vs
+    const T dnorm = sqrt(dn2);
+    const T target = epsT * dnorm;
+    bool done = !(dn2 > T(0));
+    T r[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[i] = d[i];
+    T beta = dnorm;
+#pragma unroll 1
+    while (__ballot(!done) != 0) {
+      T cs[kGmresMax], sn[kGmresMax], gv[kGmresMax + 1];
+#pragma unroll
+      for (int j = 0; j < kGmresMax; ++j) {
+        cs[j] = T(0);
+        sn[j] = T(0);
+        gv[j + 1] = T(0);
+      }
+      gv[0] = beta;
+      const T ib = done ? T(0) : T(1) / beta;
+      if (on) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) Vs[my + i] = r[i] * ib;
+      }
+      int kk = 0;           // columns of this cycle for this cell
+      bool cyc = !done;     // cell still in this cycle
+      bool conv = false;
+#pragma unroll 1
+      for (int j = 0; j < R; ++j) {
+        if (__ballot(cyc) == 0) break;
+        T vj[N], w[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) vj[i] = on ? Vs[j * S::N3 + my + i] * dinv[i] : T(0);
+        dt_apply<P, T>(cl, tb, on, hasb, vj, w, Ps, Qy, Qz, a, b);
+        if (cyc) ++it;
+        T hcol[kGmresMax + 1];
+#pragma unroll
+        for (int i = 0; i <= kGmresMax; ++i) hcol[i] = T(0);
+#pragma unroll
+        for (int i = 0; i < kGmresMax; ++i) {
+          if (i <= j) {  // modified Gram-Schmidt against V_0..V_j
+            T vi[N];
+            T h = T(0);
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+              vi[l] = on ? Vs[i * S::N3 + my + l] : T(0);
+              h += w[l] * vi[l];
+            }
+            h = cell_sum<L>(h);
+#pragma unroll
+            for (int l = 0; l < N; ++l) w[l] -= h * vi[l];
+            hcol[i] = h;
+          }
+        }
+        T hn = T(0);
+#pragma unroll
+        for (int l = 0; l < N; ++l) hn += w[l] * w[l];
+        hn = sqrt(cell_sum<L>(hn));
+        // earlier rotations, then the new one
+#pragma unroll
+        for (int i = 0; i < kGmresMax; ++i) {
+          if (i < j) {
+            const T t0 = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
+            hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
+            hcol[i] = t0;
+          }
+        }
+        T hj = T(0), gj = T(0);
+#pragma unroll
+        for (int i = 0; i < kGmresMax; ++i)
+          if (i == j) {
+            hj = hcol[i];
+            gj = gv[i];
+          }
+        const T rr = sqrt(hj * hj + hn * hn);
+        const T cj = hj / rr, sj = hn / rr;
+        const T gnext = -sj * gj;
+#pragma unroll
+        for (int i = 0; i < kGmresMax; ++i)
+          if (i == j) {
+            cs[i] = cj;
+            sn[i] = sj;
+            hcol[i] = rr;
+            gv[i] = cj * gj;
+            gv[i + 1] = gnext;
+          }
+        if (cyc && lane == 0) {
+#pragma unroll
+          for (int i = 0; i < kGmresMax; ++i)
+            if (i <= j) Hs[i * kGmresMax + j] = hcol[i];
+        }
+        if (cyc) {
+          kk = j + 1;
+          if (fabs(gnext) <= target || it >= sa.max_inner || !(rr > T(0))) {
+            conv = fabs(gnext) <= target || !(rr > T(0));
+            cyc = false;
+          } else if (on) {
+            const T ih = T(1) / hn;
+#pragma unroll
+            for (int l = 0; l < N; ++l) Vs[(j + 1) * S::N3 + my + l] = w[l] * ih;
+          }
+        }
+      }
+      __syncthreads();  // Hs written by lane 0 of each cell
+      // back substitution H y = g and x += M^-1 V y (cells with kk > 0)
+      T y[kGmresMax];
+#pragma unroll
+      for (int i = kGmresMax - 1; i >= 0; --i) {
+        T s = T(0);
+        if (i < kk) {
+          s = gv[i];
+#pragma unroll
+          for (int l = 0; l < kGmresMax; ++l)
+            if (l > i && l < kk) s -= Hs[i * kGmresMax + l] * y[l];
+          s /= Hs[i * kGmresMax + i];
+        }
+        y[i] = s;
+      }
+      if (on) {
+#pragma unroll
+        for (int i = 0; i < kGmresMax; ++i) {
+          if (i < kk) {
+#pragma unroll
+            for (int l = 0; l < N; ++l) x[l] += dinv[l] * y[i] * Vs[i * S::N3 + my + l];
+          }
+        }
+      }
+      __syncthreads();
+      const bool was_active = !done;
+      if (was_active && (conv || it >= sa.max_inner)) done = true;
+      // restart: r = d - D_T x (all lanes take part in the transposes)
+      if (__ballot(!done) != 0) {
+        T dx[N];
+        dt_apply<P, T>(cl, tb, on, hasb, x, dx, Ps, Qy, Qz, a, b);
+        T rn = T(0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          r[i] = d[i] - dx[i];
+          rn += r[i] * r[i];
+        }
+        rn = sqrt(cell_sum<L>(rn));
+        if (!done) {
+          beta = rn;
+          if (beta <= target) done = true;
+        }
+      }
+    }
+  }
+
+  // ---- update ---------------------------------------------------------------
+  if (on) {
+    const T om = (T)sa.omega;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const T val = sa.write_du ? x[i] : ul[i] + om * x[i];
+      uout[base + lpos<N>(0, i, a, b)] = val;
+    }
+    if (iters && lane == 0) iters[c] = it;
+  }
+}
+
+template <int P, typename T>
+static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin, void *uout, const SmoothArgs &a,
+                           int *iters, hipStream_t s) {
+  constexpr int N = P + 1;
+  using Sh = SmoothShape<N>;
+  const int G = (int)((pr->ncell + Sh::CPW - 1) / Sh::CPW);
+  DevTab<T, N> tb = make_devtab<T, N>(pr->tab);
+  SmoothKArgs ka;
+  ka.omega = a.omega;
+  ka.eps = a.eps;
+  ka.max_inner = a.max_inner;
+  ka.restart = a.restart;
+  ka.zero_guess = a.zero_guess;
+  ka.write_du = a.write_du;
+  ka.defect = a.defect;
+  if (a.inner == DG_INNER_CG)
+    hipLaunchKernelGGL((k_smooth<P, DG_INNER_CG, T>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo, tb,
+                       (const T *)f, (const T *)uin, (T *)uout, ka, iters);
+  else
+    hipLaunchKernelGGL((k_smooth<P, DG_INNER_GMRES, T>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo, tb,
+                       (const T *)f, (const T *)uin, (T *)uout, ka, iters);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin, void *uout, const SmoothArgs &a,
+                  int *iters, hipStream_t s) {
+  if (a.inner == DG_INNER_GMRES && (a.restart < 1 || a.restart > kGmresMax)) {
+    set_error("inner GMRES restart must be in 1..16");
+    return DG_EINVAL;
+  }
+  const bool d = prec == DG_FP64;
+  switch (pr->p) {
+    case 1: return d ? launch_smooth_t<1, double>(pr, f, uin, uout, a, iters, s)
+                     : launch_smooth_t<1, float>(pr, f, uin, uout, a, iters, s);
+    case 2: return d ? launch_smooth_t<2, double>(pr, f, uin, uout, a, iters, s)
+                     : launch_smooth_t<2, float>(pr, f, uin, uout, a, iters, s);
+    case 3: return d ? launch_smooth_t<3, double>(pr, f, uin, uout, a, iters, s)
+                     : launch_smooth_t<3, float>(pr, f, uin, uout, a, iters, s);
+    case 4: return d ? launch_smooth_t<4, double>(pr, f, uin, uout, a, iters, s)
+                     : launch_smooth_t<4, float>(pr, f, uin, uout, a, iters, s);
+  }
+  set_error("unsupported degree");
+  return DG_EINVAL;
+}
+
+}  // namespace dgmg

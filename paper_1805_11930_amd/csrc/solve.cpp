@@ -1,0 +1,356 @@
+// Outer Krylov solvers of dg_solve: FP64 CG / flexible CG / flexible
+// GMRES(m) around the hybrid-multigrid (or block-Jacobi) preconditioner,
+// which may run in FP32 (iterative refinement: the outer residuals, inner
+// products and the operator apply stay in FP64).
+//
+// Sec. 4.2 solves the diffusion problems with CG to ||r||/||r_0|| = 1e-8;
+// Sec. 4.3 uses flexible GMRES for the convection-dominated problem.  A
+// preconditioner with inexact inner block solves, or one applied in FP32,
+// is not a fixed linear operator, so the flexible variants are the
+// defaults: flexible CG uses the Polak-Ribiere form of beta, and FGMRES
+// keeps the preconditioned vectors Z.  Before the FP32 cast the residual
+// is scaled by 1/||r||_2 so that it is O(1) whatever the problem scale.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dg_internal.h"
+#include "vec.h"
+
+namespace dgmg {
+int alloc_tmp(dg_problem *pr, int prec, int k, void **out);
+int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, double rnorm, float *r32,
+                  float *z32, hipStream_t s);
+}  // namespace dgmg
+
+using namespace dgmg;
+
+namespace {
+
+struct DevBuf {
+  std::vector<void *> ptrs;
+  size_t bytes = 0;
+  ~DevBuf() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  int get(T **out, size_t n) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (solve workspace)");
+    ptrs.push_back(p);
+    bytes += n * sizeof(T);
+    *out = (T *)p;
+    return DG_OK;
+  }
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Ctx {
+  dg_problem *pr;
+  const dg_solve_opts *o;
+  hipStream_t s;
+  double *part, *dout;
+  float *r32 = nullptr, *z32 = nullptr;
+  int64_t n;
+};
+
+int host_dots(Ctx &c, const DotSet &ds, double *out) {
+  int rc = dots(ds, c.n, c.part, c.dout, c.s);
+  if (rc) return rc;
+  DG_HIP(hipMemcpyAsync(out, c.dout, ds.m * sizeof(double), hipMemcpyDeviceToHost, c.s));
+  DG_HIP(hipStreamSynchronize(c.s));
+  return DG_OK;
+}
+
+int host_dot(Ctx &c, const double *a, const double *b, double *out) {
+  DotSet ds;
+  ds.m = 1;
+  ds.a[0] = a;
+  ds.b[0] = b;
+  return host_dots(c, ds, out);
+}
+
+int residual(Ctx &c, const double *f, const double *u, double *r, double *tmp) {
+  int rc = launch_apply(c.pr, DG_FP64, u, tmp, c.s);
+  if (rc) return rc;
+  return sub(c.n, f, tmp, r, c.s);
+}
+
+int solve_cg(Ctx &c, const double *f, double *u, dg_solve_result *res, DevBuf &wb, double r0) {
+  const bool flex = c.o->krylov == DG_KRYLOV_FCG;
+  double *r, *p, *q, *z, *rold = nullptr;
+  int rc;
+  if ((rc = wb.get(&r, c.n)) || (rc = wb.get(&p, c.n)) || (rc = wb.get(&q, c.n)) || (rc = wb.get(&z, c.n)))
+    return rc;
+  if (flex && (rc = wb.get(&rold, c.n))) return rc;
+  if ((rc = residual(c, f, u, r, q))) return rc;
+  double rnorm = r0;
+  if ((rc = precond_apply(c.pr, c.o, r, z, rnorm, c.r32, c.z32, c.s))) return rc;
+  double rz;
+  if ((rc = host_dot(c, r, z, &rz))) return rc;
+  DG_HIP(hipMemcpyAsync(p, z, c.n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+  int it = 0;
+  res->status = DG_ENOCONV;
+  while (it < c.o->maxit) {
+    if ((rc = launch_apply(c.pr, DG_FP64, p, q, c.s))) return rc;
+    double pq;
+    if ((rc = host_dot(c, p, q, &pq))) return rc;
+    if (!(pq > 0) || !std::isfinite(pq) || !std::isfinite(rz)) {
+      res->status = DG_EBREAKDOWN;
+      set_error("CG breakdown: p^T A p <= 0 or not finite");
+      break;
+    }
+    const double alpha = rz / pq;
+    if (flex) DG_HIP(hipMemcpyAsync(rold, r, c.n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    if ((rc = cg_update(c.n, alpha, p, q, u, r, c.s))) return rc;
+    ++it;
+    double rr;
+    if ((rc = host_dot(c, r, r, &rr))) return rc;
+    rnorm = std::sqrt(rr);
+    if (!std::isfinite(rnorm)) {
+      res->status = DG_EBREAKDOWN;
+      set_error("non-finite residual");
+      break;
+    }
+    if (rnorm <= c.o->rtol * r0) {
+      res->status = DG_OK;
+      break;
+    }
+    if ((rc = precond_apply(c.pr, c.o, r, z, rnorm, c.r32, c.z32, c.s))) return rc;
+    double beta;
+    if (flex) {
+      DotSet ds;
+      ds.m = 2;
+      ds.a[0] = z;
+      ds.b[0] = r;
+      ds.a[1] = z;
+      ds.b[1] = rold;
+      double v[2];
+      if ((rc = host_dots(c, ds, v))) return rc;
+      beta = (v[0] - v[1]) / rz;
+      rz = v[0];
+    } else {
+      double zr;
+      if ((rc = host_dot(c, z, r, &zr))) return rc;
+      beta = zr / rz;
+      rz = zr;
+    }
+    if ((rc = axpby(c.n, 1.0, z, beta, p, c.s))) return rc;
+  }
+  res->iters = it;
+  return DG_OK;
+}
+
+int solve_fgmres(Ctx &c, const double *f, double *u, dg_solve_result *res, DevBuf &wb, double r0) {
+  const int m = c.o->restart > 0 ? (c.o->restart < kMaxBasis - 1 ? c.o->restart : kMaxBasis - 1) : 30;
+  std::vector<double *> V(m + 1), Z(m);
+  int rc;
+  for (auto &v : V)
+    if ((rc = wb.get(&v, c.n))) return rc;
+  for (auto &z : Z)
+    if ((rc = wb.get(&z, c.n))) return rc;
+  double *r, *tmp;
+  if ((rc = wb.get(&r, c.n)) || (rc = wb.get(&tmp, c.n))) return rc;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 2);
+  if ((rc = residual(c, f, u, r, tmp))) return rc;
+  double beta = r0;
+  int it = 0;
+  res->status = DG_ENOCONV;
+  bool done = false;
+  while (!done && it < c.o->maxit) {
+    if ((rc = axpby(c.n, 1.0 / beta, r, 0.0, V[0], c.s))) return rc;
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      if ((rc = precond_apply(c.pr, c.o, V[j], Z[j], 1.0, c.r32, c.z32, c.s))) return rc;
+      double *w = V[j + 1];
+      if ((rc = launch_apply(c.pr, DG_FP64, Z[j], w, c.s))) return rc;
+      // classical Gram-Schmidt, applied twice
+      VecList vl;
+      for (int i = 0; i <= j; ++i) vl.v[i] = V[i];
+      std::vector<double> hc(j + 1, 0.0);
+      for (int pass = 0; pass < 2; ++pass) {
+        if ((rc = mdot(vl, j + 1, w, c.n, c.part, c.dout, c.s))) return rc;
+        DG_HIP(hipMemcpyAsync(h.data(), c.dout, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, c.s));
+        DG_HIP(hipStreamSynchronize(c.s));
+        Coefs cf;
+        for (int i = 0; i <= j; ++i) {
+          cf.c[i] = h[i];
+          hc[i] += h[i];
+        }
+        if ((rc = mupdate(vl, cf, j + 1, c.n, w, c.s))) return rc;
+      }
+      double hn2;
+      if ((rc = host_dot(c, w, w, &hn2))) return rc;
+      const double hn = std::sqrt(hn2);
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc[i];
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = t;
+      }
+      const double hj = H[(size_t)j * m + j];
+      const double rr = std::hypot(hj, hn);
+      cs[j] = hj / rr;
+      sn[j] = hn / rr;
+      H[(size_t)j * m + j] = rr;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      k = j + 1;
+      if (!std::isfinite(g[j + 1])) {
+        res->status = DG_EBREAKDOWN;
+        set_error("non-finite residual estimate in FGMRES");
+        done = true;
+        break;
+      }
+      if (std::fabs(g[j + 1]) <= c.o->rtol * r0 || it >= c.o->maxit || hn == 0.0) {
+        done = true;
+        break;
+      }
+      if ((rc = axpby(c.n, 1.0 / hn, w, 0.0, w, c.s))) return rc;
+    }
+    // y = H^-1 g, u += Z y
+    std::vector<double> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int l = i + 1; l < k; ++l) s -= H[(size_t)i * m + l] * y[l];
+      y[i] = s / H[(size_t)i * m + i];
+    }
+    VecList zl;
+    Coefs yc;
+    for (int i = 0; i < k; ++i) {
+      zl.v[i] = Z[i];
+      yc.c[i] = y[i];
+    }
+    if ((rc = mcombine(zl, yc, k, c.n, u, c.s))) return rc;
+    if ((rc = residual(c, f, u, r, tmp))) return rc;
+    double rr;
+    if ((rc = host_dot(c, r, r, &rr))) return rc;
+    beta = std::sqrt(rr);
+    if (beta <= c.o->rtol * r0) {
+      res->status = DG_OK;
+      done = true;
+    } else if (done && res->status != DG_EBREAKDOWN) {
+      done = it >= c.o->maxit;  // estimate converged but true residual not yet: restart
+    }
+  }
+  res->iters = it;
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" int dg_solve(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, dg_solve_result *res,
+                        void *stream) {
+  if (!pr || !f || !u || !o) {
+    set_error("dg_solve: NULL argument");
+    return DG_EINVAL;
+  }
+  if (o->krylov < DG_KRYLOV_CG || o->krylov > DG_KRYLOV_FGMRES || o->precond < DG_PRECOND_NONE ||
+      o->precond > DG_PRECOND_MG || (o->precond_precision != DG_FP64 && o->precond_precision != DG_FP32) ||
+      !(o->rtol > 0) || o->maxit < 1) {
+    set_error("dg_solve: invalid options");
+    return DG_EINVAL;
+  }
+  dg_solve_result tmp;
+  if (!res) res = &tmp;
+  std::memset(res, 0, sizeof(*res));
+  hipStream_t s = (hipStream_t)stream;
+  const double t0 = now_s();
+  DevBuf wb;
+  Ctx c;
+  c.pr = pr;
+  c.o = o;
+  c.s = s;
+  c.n = pr->ndof;
+  int rc;
+  if ((rc = wb.get(&c.part, (size_t)kMaxBasis * kDotBlocks)) || (rc = wb.get(&c.dout, kMaxBasis))) return rc;
+  if (o->precond_precision == DG_FP32 && o->precond != DG_PRECOND_NONE) {
+    if ((rc = wb.get(&c.r32, c.n)) || (rc = wb.get(&c.z32, c.n))) return rc;
+  }
+  // preconditioner temporaries are allocated here so that the solve phase
+  // measures no allocation
+  void *dummy;
+  const int pp = o->precond_precision;
+  if (o->precond == DG_PRECOND_MG && ((rc = alloc_tmp(pr, pp, 0, &dummy)) || (rc = alloc_tmp(pr, pp, 1, &dummy))))
+    return rc;
+  double *r, *t;
+  if ((rc = wb.get(&r, c.n)) || (rc = wb.get(&t, c.n))) return rc;
+  DG_HIP(hipStreamSynchronize(s));
+  const double t1 = now_s();
+  if ((rc = residual(c, f, u, r, t))) return rc;
+  double rr0;
+  if ((rc = host_dot(c, r, r, &rr0))) return rc;
+  const double r0 = std::sqrt(rr0);
+  if (!std::isfinite(r0)) {
+    set_error("initial residual is not finite");
+    res->status = DG_EBREAKDOWN;
+    return DG_EBREAKDOWN;
+  }
+  if (r0 == 0.0) {
+    res->status = DG_OK;
+  } else if (o->krylov == DG_KRYLOV_FGMRES) {
+    rc = solve_fgmres(c, f, u, res, wb, r0);
+  } else {
+    rc = solve_cg(c, f, u, res, wb, r0);
+  }
+  if (rc) return rc;
+  // true FP64 residual
+  if ((rc = residual(c, f, u, r, t))) return rc;
+  double rr;
+  if ((rc = host_dot(c, r, r, &rr))) return rc;
+  const double t2 = now_s();
+  res->rel_residual = r0 > 0 ? std::sqrt(rr) / r0 : 0.0;
+  res->t_setup = t1 - t0;
+  res->t_solve = t2 - t1;
+  res->footprint = pr->held_bytes + wb.bytes;
+  if (res->status == DG_OK && !(res->rel_residual <= o->rtol * 1.0000001)) res->status = DG_ENOCONV;
+  return res->status;
+}
+
+extern "C" int dg_footprint(const dg_problem_desc *d, const dg_solve_opts *o, size_t *bytes) {
+  if (!d || !bytes) {
+    set_error("dg_footprint: NULL argument");
+    return DG_EINVAL;
+  }
+  if (d->p < 1 || d->p > DG_MAX_P || d->nx < 1 || d->ny < 1 || d->nz < 1) {
+    set_error("dg_footprint: invalid description");
+    return DG_EINVAL;
+  }
+  const int64_t ncell = (int64_t)d->nx * d->ny * d->nz;
+  const int64_t nloc = (int64_t)(d->p + 1) * (d->p + 1) * (d->p + 1);
+  const int64_t ndof = ncell * nloc;
+  size_t b = 0;
+  b += ncell * 4 * sizeof(double);       // K, c
+  b += ncell * sizeof(int) + 8 * 1024 * sizeof(double) + 64;
+  // coarse levels: ~8/7 of level 0, 7 stencil entries + 3 vectors in both precisions
+  const int64_t nco = ncell + ncell / 7 + 1;
+  b += nco * (7 + 3) * (sizeof(double) + sizeof(float));
+  b += 512 * 512 * (sizeof(double) + sizeof(float));
+  dg_solve_opts def;
+  if (!o) {
+    dg_default_solve_opts(&def);
+    o = &def;
+  }
+  const size_t pe = o->precond_precision == DG_FP32 ? sizeof(float) : sizeof(double);
+  if (o->precond == DG_PRECOND_MG) b += 2 * ndof * pe;
+  if (o->precond_precision == DG_FP32 && o->precond != DG_PRECOND_NONE) b += 2 * ndof * sizeof(float);
+  int64_t nvec = 2;  // residual + temporary of dg_solve
+  if (o->krylov == DG_KRYLOV_FGMRES) {
+    const int m = o->restart > 0 ? (o->restart < kMaxBasis - 1 ? o->restart : kMaxBasis - 1) : 30;
+    nvec += 2 * m + 1 + 2;
+  } else {
+    nvec += o->krylov == DG_KRYLOV_FCG ? 5 : 4;
+  }
+  b += nvec * ndof * sizeof(double);
+  b += (kMaxBasis * kDotBlocks + kMaxBasis) * sizeof(double);
+  *bytes = b;
+  return DG_OK;
+}

@@ -1,0 +1,56 @@
+// Launchers of the vector, transfer and coarse-level kernels (vec.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dgmg {
+
+constexpr int kMaxDots = 4;
+constexpr int kDotBlocks = 1024;
+
+struct DotSet {
+  int m;
+  const double *a[kMaxDots];
+  const double *b[kMaxDots];
+};
+
+// out_dev[j] = a_j . b_j ; part: device scratch of kMaxDots*kDotBlocks doubles
+int dots(const DotSet &ds, int64_t n, double *part, double *out_dev, hipStream_t s);
+int axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+int sub(int64_t n, const double *x, const double *y, double *z, hipStream_t s);
+int cg_update(int64_t n, double a, const double *p, const double *q, double *x, double *r, hipStream_t s);
+int cast_d2f(int64_t n, double sc, const double *x, float *y, hipStream_t s);
+int cast_f2d(int64_t n, double sc, const float *x, double *y, hipStream_t s);
+
+template <typename T>
+int restrict_p0(int64_t ncell, int nloc, const T *r, const T *ar, T *rh, hipStream_t s);
+template <typename T>
+int prolong_add_p0(int64_t n, int nloc, const T *zh, T *u, hipStream_t s);
+
+template <typename T>
+int coarse_jacobi(const T *A, int nx, int ny, int nz, T w, const T *r, const T *xi, T *xo, hipStream_t s);
+template <typename T>
+int coarse_restrict(const T *A, int nx, int ny, int nz, const T *r, const T *x, int cnx, int cny, int cnz, T *rc,
+                    hipStream_t s);
+template <typename T>
+int coarse_prolong(int nx, int ny, int nz, int cnx, int cny, const T *xc, T *x, hipStream_t s);
+template <typename T>
+int dense_mv(int n, const T *Ainv, const T *r, T *x, hipStream_t s);
+
+constexpr int kMaxBasis = 32;
+struct VecList {
+  const double *v[kMaxBasis];
+};
+struct Coefs {
+  double c[kMaxBasis];
+};
+// out_dev[i] = V_i . w for i < m; part: kMaxBasis*kDotBlocks doubles
+int mdot(const VecList &vl, int m, const double *w, int64_t n, double *part, double *out_dev, hipStream_t s);
+int mupdate(const VecList &vl, const Coefs &h, int m, int64_t n, double *w, hipStream_t s);
+int mcombine(const VecList &vl, const Coefs &y, int m, int64_t n, double *x, hipStream_t s);
+
+int iter_stats(int64_t n, const int *it, unsigned long long *out_dev, hipStream_t s);
+
+}  // namespace dgmg

@@ -1,0 +1,380 @@
+// Vector kernels of the outer Krylov methods, the mixed-precision casts,
+// the P0 intergrid transfers (Sec. 2.2.2: P|_T = (1,...,1)^T, R = P^T) and
+// the levels of the simple P0 aggregation cycle used as coarse solver.
+//
+// Reductions are deterministic: a fixed grid of partial sums followed by a
+// single-block final sum in a fixed order, so repeated calls on the same
+// data give the same bits.
+#include <hip/hip_runtime.h>
+
+#include "dg_internal.h"
+#include "vec.h"
+
+namespace dgmg {
+
+constexpr int kRedThreads = 256;
+
+// ---- deterministic dot products ------------------------------------------
+// out[j] = sum_i a_j[i] * b_j[i] for up to kMaxDots pairs in one pass.
+__global__ __launch_bounds__(kRedThreads) void k_dots_partial(DotSet ds, int64_t n, double *__restrict__ part) {
+  __shared__ double sh[kMaxDots][kRedThreads / 64];
+  double acc[kMaxDots];
+#pragma unroll
+  for (int j = 0; j < kMaxDots; ++j) acc[j] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kRedThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+    for (int j = 0; j < kMaxDots; ++j)
+      if (j < ds.m) acc[j] += ds.a[j][i] * ds.b[j][i];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < kMaxDots; ++j) {
+    double v = acc[j];
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    if (lane == 0) sh[j][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kMaxDots) {
+    const int j = threadIdx.x;
+    double s = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[j][w];
+    part[(size_t)j * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_dots_final(int m, int nblk, const double *__restrict__ part,
+                                                             double *__restrict__ out) {
+  __shared__ double sh[kRedThreads / 64];
+  for (int j = 0; j < m; ++j) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += kRedThreads) v += part[(size_t)j * nblk + i];
+    for (int mm = 32; mm >= 1; mm >>= 1) v += __shfl_xor(v, mm, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
+      out[j] = s;
+    }
+    __syncthreads();
+  }
+}
+
+int dots(const DotSet &ds, int64_t n, double *part, double *out_dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots_partial, dim3(kDotBlocks), dim3(kRedThreads), 0, s, ds, n, part);
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kRedThreads), 0, s, ds.m, kDotBlocks, part, out_dev);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+// ---- BLAS-1 -----------------------------------------------------------------
+// y = a*x + b*y
+__global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, double b, double *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+// z = x - y
+__global__ void k_sub(int64_t n, const double *__restrict__ x, const double *__restrict__ y, double *__restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = x[i] - y[i];
+}
+// x += a p ; r -= a q
+__global__ void k_cg_update(int64_t n, double a, const double *__restrict__ p, const double *__restrict__ q,
+                            double *__restrict__ x, double *__restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    x[i] += a * p[i];
+    r[i] -= a * q[i];
+  }
+}
+template <typename S, typename D>
+__global__ void k_cast_scale(int64_t n, double s, const S *__restrict__ x, D *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (D)(s * (double)x[i]);
+}
+
+static inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+int axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, grid1(n), dim3(256), 0, s, n, a, x, b, y);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int sub(int64_t n, const double *x, const double *y, double *z, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, grid1(n), dim3(256), 0, s, n, x, y, z);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int cg_update(int64_t n, double a, const double *p, const double *q, double *x, double *r, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update, grid1(n), dim3(256), 0, s, n, a, p, q, x, r);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int cast_d2f(int64_t n, double sc, const double *x, float *y, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast_scale<double, float>), grid1(n), dim3(256), 0, s, n, sc, x, y);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int cast_f2d(int64_t n, double sc, const float *x, double *y, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast_scale<float, double>), grid1(n), dim3(256), 0, s, n, sc, x, y);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+// ---- P0 transfers ---------------------------------------------------------
+// rh[c] = sum_{i in T_c} (r[i] - ar[i])  (restriction of the residual; ar may be null)
+template <typename T>
+__global__ void k_restrict(int64_t ncell, int nloc, const T *__restrict__ r, const T *__restrict__ ar,
+                           T *__restrict__ rh) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  T s = T(0);
+  const T *rc = r + c * nloc;
+  if (ar) {
+    const T *ac = ar + c * nloc;
+    for (int i = 0; i < nloc; ++i) s += rc[i] - ac[i];
+  } else {
+    for (int i = 0; i < nloc; ++i) s += rc[i];
+  }
+  rh[c] = s;
+}
+// u[i] += zh[cell(i)]
+template <typename T>
+__global__ void k_prolong_add(int64_t n, int nloc, const T *__restrict__ zh, T *__restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) u[i] += zh[i / nloc];
+}
+
+template <typename T>
+int restrict_p0(int64_t ncell, int nloc, const T *r, const T *ar, T *rh, hipStream_t s) {
+  hipLaunchKernelGGL((k_restrict<T>), grid1(ncell), dim3(256), 0, s, ncell, nloc, r, ar, rh);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+template <typename T>
+int prolong_add_p0(int64_t n, int nloc, const T *zh, T *u, hipStream_t s) {
+  hipLaunchKernelGGL((k_prolong_add<T>), grid1(n), dim3(256), 0, s, n, nloc, zh, u);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+template int restrict_p0<double>(int64_t, int, const double *, const double *, double *, hipStream_t);
+template int restrict_p0<float>(int64_t, int, const float *, const float *, float *, hipStream_t);
+template int prolong_add_p0<double>(int64_t, int, const double *, double *, hipStream_t);
+template int prolong_add_p0<float>(int64_t, int, const float *, float *, hipStream_t);
+
+// ---- P0 aggregation levels (7-point stencils) ------------------------------
+// A[0][i] = diagonal, A[1..6][i] = couplings to -x,+x,-y,+y,-z,+z.
+template <typename T>
+__device__ inline T stencil_apply(const T *__restrict__ A, int64_t n, const T *__restrict__ x, int i, int ix, int iy,
+                                  int iz, int nx, int ny, int nz) {
+  T s = A[i] * x[i];
+  if (ix > 0) s += A[n + i] * x[i - 1];
+  if (ix < nx - 1) s += A[2 * n + i] * x[i + 1];
+  if (iy > 0) s += A[3 * n + i] * x[i - nx];
+  if (iy < ny - 1) s += A[4 * n + i] * x[i + nx];
+  if (iz > 0) s += A[5 * n + i] * x[i - nx * ny];
+  if (iz < nz - 1) s += A[6 * n + i] * x[i + nx * ny];
+  return s;
+}
+
+// one damped Jacobi sweep xo = xi + w D^-1 (r - A xi); xi == null means xi = 0
+template <typename T>
+__global__ void k_jacobi(const T *__restrict__ A, int nx, int ny, int nz, T w, const T *__restrict__ r,
+                         const T *__restrict__ xi, T *__restrict__ xo) {
+  const int n = nx * ny * nz;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (!xi) {
+    xo[i] = w * r[i] / A[i];
+    return;
+  }
+  const int ix = i % nx, iy = (i / nx) % ny, iz = i / (nx * ny);
+  const T ax = stencil_apply(A, n, xi, i, ix, iy, iz, nx, ny, nz);
+  xo[i] = xi[i] + w * (r[i] - ax) / A[i];
+}
+
+// rc[agg] = sum over the aggregate of (r - A x)
+template <typename T>
+__global__ void k_coarse_restrict(const T *__restrict__ A, int nx, int ny, int nz, const T *__restrict__ r,
+                                  const T *__restrict__ x, int cnx, int cny, int cnz, T *__restrict__ rc) {
+  const int nc = cnx * cny * cnz;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nc) return;
+  const int jx = j % cnx, jy = (j / cnx) % cny, jz = j / (cnx * cny);
+  const int n = nx * ny * nz;
+  T s = T(0);
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int ix = 2 * jx + dx, iy = 2 * jy + dy, iz = 2 * jz + dz;
+        if (ix >= nx || iy >= ny || iz >= nz) continue;
+        const int i = ix + nx * (iy + ny * iz);
+        s += r[i] - stencil_apply(A, n, x, i, ix, iy, iz, nx, ny, nz);
+      }
+  rc[j] = s;
+}
+
+// x += xc[agg(i)]
+template <typename T>
+__global__ void k_coarse_prolong(int nx, int ny, int nz, int cnx, int cny, const T *__restrict__ xc,
+                                 T *__restrict__ x) {
+  const int n = nx * ny * nz;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int ix = i % nx, iy = (i / nx) % ny, iz = i / (nx * ny);
+  x[i] += xc[(ix >> 1) + cnx * ((iy >> 1) + cny * (iz >> 1))];
+}
+
+// x = Ainv r, dense (n <= a few hundred): one block, rows strided
+template <typename T>
+__global__ void k_dense_mv(int n, const T *__restrict__ Ainv, const T *__restrict__ r, T *__restrict__ x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    T s = T(0);
+    for (int j = 0; j < n; ++j) s += Ainv[(size_t)i * n + j] * r[j];
+    x[i] = s;
+  }
+}
+
+template <typename T>
+int coarse_jacobi(const T *A, int nx, int ny, int nz, T w, const T *r, const T *xi, T *xo, hipStream_t s) {
+  const int n = nx * ny * nz;
+  hipLaunchKernelGGL((k_jacobi<T>), dim3((n + 255) / 256), dim3(256), 0, s, A, nx, ny, nz, w, r, xi, xo);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+template <typename T>
+int coarse_restrict(const T *A, int nx, int ny, int nz, const T *r, const T *x, int cnx, int cny, int cnz, T *rc,
+                    hipStream_t s) {
+  const int nc = cnx * cny * cnz;
+  hipLaunchKernelGGL((k_coarse_restrict<T>), dim3((nc + 255) / 256), dim3(256), 0, s, A, nx, ny, nz, r, x, cnx,
+                     cny, cnz, rc);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+template <typename T>
+int coarse_prolong(int nx, int ny, int nz, int cnx, int cny, const T *xc, T *x, hipStream_t s) {
+  const int n = nx * ny * nz;
+  hipLaunchKernelGGL((k_coarse_prolong<T>), dim3((n + 255) / 256), dim3(256), 0, s, nx, ny, nz, cnx, cny, xc, x);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+template <typename T>
+int dense_mv(int n, const T *Ainv, const T *r, T *x, hipStream_t s) {
+  hipLaunchKernelGGL((k_dense_mv<T>), dim3((n + 63) / 64), dim3(64), 0, s, n, Ainv, r, x);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+#define DG_INST(T)                                                                                          \
+  template int coarse_jacobi<T>(const T *, int, int, int, T, const T *, const T *, T *, hipStream_t);       \
+  template int coarse_restrict<T>(const T *, int, int, int, const T *, const T *, int, int, int, T *,       \
+                                  hipStream_t);                                                             \
+  template int coarse_prolong<T>(int, int, int, int, int, const T *, T *, hipStream_t);                     \
+  template int dense_mv<T>(int, const T *, const T *, T *, hipStream_t);
+DG_INST(double)
+DG_INST(float)
+#undef DG_INST
+
+
+// ---- multi-vector kernels for Gram-Schmidt in FGMRES ------------------------
+// part[i*nblk + blk] = partial of V_i . w, i < m <= kMaxBasis
+__global__ __launch_bounds__(kRedThreads) void k_mdot_partial(VecList vl, int m, const double *__restrict__ w,
+                                                              int64_t n, double *__restrict__ part) {
+  __shared__ double sh[kMaxBasis][kRedThreads / 64];
+  double acc[kMaxBasis];
+#pragma unroll
+  for (int j = 0; j < kMaxBasis; ++j) acc[j] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kRedThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
+    const double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < kMaxBasis; ++j)
+      if (j < m) acc[j] += vl.v[j][i] * wi;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < kMaxBasis; ++j) {
+    if (j < m) {
+      double v = acc[j];
+      for (int mm = 32; mm >= 1; mm >>= 1) v += __shfl_xor(v, mm, 64);
+      if (lane == 0) sh[j][wv] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < m) {
+    const int j = threadIdx.x;
+    double s = 0.0;
+    for (int q = 0; q < kRedThreads / 64; ++q) s += sh[j][q];
+    part[(size_t)j * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// w -= sum_i h_i V_i
+__global__ void k_mupdate(VecList vl, Coefs h, int m, int64_t n, double *__restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = w[i];
+  for (int j = 0; j < m; ++j) s -= h.c[j] * vl.v[j][i];
+  w[i] = s;
+}
+
+// x += sum_i y_i Z_i
+__global__ void k_mcombine(VecList vl, Coefs y, int m, int64_t n, double *__restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = x[i];
+  for (int j = 0; j < m; ++j) s += y.c[j] * vl.v[j][i];
+  x[i] = s;
+}
+
+int mdot(const VecList &vl, int m, const double *w, int64_t n, double *part, double *out_dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_mdot_partial, dim3(kDotBlocks), dim3(kRedThreads), 0, s, vl, m, w, n, part);
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kRedThreads), 0, s, m, kDotBlocks, part, out_dev);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int mupdate(const VecList &vl, const Coefs &h, int m, int64_t n, double *w, hipStream_t s) {
+  hipLaunchKernelGGL(k_mupdate, grid1(n), dim3(256), 0, s, vl, h, m, n, w);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int mcombine(const VecList &vl, const Coefs &y, int m, int64_t n, double *x, hipStream_t s) {
+  hipLaunchKernelGGL(k_mcombine, grid1(n), dim3(256), 0, s, vl, y, m, n, x);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+// ---- smoother statistics: sum and max of the per-cell iteration counts ----
+__global__ void k_iter_stats(int64_t n, const int *__restrict__ it, unsigned long long *__restrict__ out) {
+  // single block, deterministic
+  __shared__ unsigned long long ssum[256];
+  __shared__ int smax[256];
+  unsigned long long s = 0;
+  int m = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    s += (unsigned long long)it[i];
+    m = it[i] > m ? it[i] : m;
+  }
+  ssum[threadIdx.x] = s;
+  smax[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      ssum[threadIdx.x] += ssum[threadIdx.x + w];
+      smax[threadIdx.x] = smax[threadIdx.x] > smax[threadIdx.x + w] ? smax[threadIdx.x] : smax[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = ssum[0];
+    out[1] = (unsigned long long)smax[0];
+  }
+}
+
+int iter_stats(int64_t n, const int *it, unsigned long long *out_dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_iter_stats, dim3(1), dim3(256), 0, s, n, it, out_dev);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+}  // namespace dgmg

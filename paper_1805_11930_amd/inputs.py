@@ -1,0 +1,170 @@
+"""Seeded synthetic inputs for the tests and the benchmark.
+
+Holds no arithmetic of the DG method: only problem parameters, coefficient
+fields, manufactured solutions and random vectors.  Both the HIP path and
+the CPU oracle receive the same inputs from here.
+
+Workloads (the paper's public SPE10 data set is not available, so W3 is a
+synthetic stand-in with SPE10's shape and contrast):
+  W1  Poisson, unit cube, 8^3 cells, p=2, sigma = 2p(p+1) = 12, K = I,
+      homogeneous Dirichlet, f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z).
+  W2  Poisson, unit cube, 32^3 cells, p=4, K = I, u = seeded random
+      polynomial of total degree 3 (seed 2), g = u, f = -lap u.
+  W3  60 x 220 x 85 cells of 20 x 10 x 2 (ft), p=2, per-cell diagonal K:
+      log10 Kx = per z-layer Gaussian-filtered N(0,1) noise (sigma 5 cells,
+      reflecting), standardised per layer, times 1.5, clipped to [-3, 3];
+      Ky = Kx, Kz = 0.1 Kx (seed 3); Neumann on z faces, Dirichlet 0 on the
+      lateral faces; f = +1 in the cell column (0, 0, :) and -1 in
+      (59, 219, :).
+  W4  unit cube, 48^3 cells, p=3, K = 1e-3 I, b = (-(y-1/2), x-1/2, 0.2),
+      c = 0, f = 1, homogeneous Dirichlet.
+  W5  serving mix: N in {8,12,16,24,32} cells per side, p in {2,3,4}, K_T =
+      exp(Z_T) I with Z ~ N(0,1), random load vector (seed 5000 + i),
+      homogeneous Dirichlet.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+PI = np.pi
+
+
+@dataclass
+class Workload:
+    name: str
+    cells: tuple
+    lengths: tuple
+    p: int
+    bc: tuple
+    sigma: float | None
+    K: object
+    c: object = 0.0
+    b0: tuple = (0.0, 0.0, 0.0)
+    B: tuple = ((0.0,) * 3,) * 3
+    f: object = None      # callable (npts,3) -> (npts,) or None
+    g: object = None      # Dirichlet data
+    j: object = None      # Neumann data
+    exact: object = None  # exact solution, when known
+    info: dict = field(default_factory=dict)
+
+    @property
+    def ncell(self) -> int:
+        return int(np.prod(self.cells))
+
+    @property
+    def ndof(self) -> int:
+        return self.ncell * (self.p + 1) ** 3
+
+
+def _sinsin(x):
+    return np.sin(PI * x[:, 0]) * np.sin(PI * x[:, 1]) * np.sin(PI * x[:, 2])
+
+
+def w1(cells=(8, 8, 8)) -> Workload:
+    return Workload("poisson-8^3-p2", cells, (1.0, 1.0, 1.0), 2, ("D",) * 6, 12.0, 1.0,
+                    f=lambda x: 3 * PI**2 * _sinsin(x), exact=_sinsin)
+
+
+def random_poly3(seed: int = 2):
+    """u = sum_{a+b+c <= 3} C_abc x^a y^b z^c, C ~ N(0,1); returns (u, -lap u)."""
+    rng = np.random.default_rng(seed)
+    exps = [(a, b, c) for a in range(4) for b in range(4) for c in range(4) if a + b + c <= 3]
+    C = rng.normal(size=len(exps))
+
+    def u(x):
+        out = np.zeros(len(x))
+        for (a, b, c), m in zip(exps, C):
+            out += m * x[:, 0] ** a * x[:, 1] ** b * x[:, 2] ** c
+        return out
+
+    def mlap(x):
+        out = np.zeros(len(x))
+        for (a, b, c), m in zip(exps, C):
+            if a > 1:
+                out -= m * a * (a - 1) * x[:, 0] ** (a - 2) * x[:, 1] ** b * x[:, 2] ** c
+            if b > 1:
+                out -= m * b * (b - 1) * x[:, 0] ** a * x[:, 1] ** (b - 2) * x[:, 2] ** c
+            if c > 1:
+                out -= m * c * (c - 1) * x[:, 0] ** a * x[:, 1] ** b * x[:, 2] ** (c - 2)
+        return out
+
+    return u, mlap
+
+
+def w2(cells=(32, 32, 32), p=4) -> Workload:
+    u, mlap = random_poly3(2)
+    return Workload("poisson-32^3-p4", cells, (1.0, 1.0, 1.0), p, ("D",) * 6, None, 1.0, f=mlap, g=u, exact=u)
+
+
+def spe10_like_K(cells=(60, 220, 85), seed: int = 3) -> np.ndarray:
+    """Layered log-normal diagonal permeability, shape (ncell, 3)."""
+    from scipy.ndimage import gaussian_filter
+
+    nx, ny, nz = cells
+    rng = np.random.default_rng(seed)
+    logk = np.empty((nz, ny, nx))
+    for k in range(nz):
+        layer = gaussian_filter(rng.normal(size=(ny, nx)), sigma=5.0, mode="reflect")
+        layer = (layer - layer.mean()) / layer.std()
+        logk[k] = np.clip(1.5 * layer, -3.0, 3.0)
+    kx = 10.0 ** logk.reshape(-1)  # x fastest, then y, then z
+    return np.stack([kx, kx, 0.1 * kx], axis=1)
+
+
+def w3(cells=(60, 220, 85)) -> Workload:
+    nx, ny, nz = cells
+    lengths = (20.0 * nx, 10.0 * ny, 2.0 * nz)
+    hx, hy = lengths[0] / nx, lengths[1] / ny
+
+    def f(x):
+        out = np.zeros(len(x))
+        out[(x[:, 0] < hx) & (x[:, 1] < hy)] = 1.0
+        out[(x[:, 0] > lengths[0] - hx) & (x[:, 1] > lengths[1] - hy)] = -1.0
+        return out
+
+    return Workload("spe10-like-60x220x85-p2", cells, lengths, 2, ("D", "D", "D", "D", "N", "N"), None,
+                    spe10_like_K(cells), f=f)
+
+
+def w4(cells=(48, 48, 48), p=3) -> Workload:
+    return Workload("convection-48^3-p3", cells, (1.0, 1.0, 1.0), p, ("D",) * 6, None, 1e-3,
+                    b0=(0.5, -0.5, 0.2), B=((0.0, -1.0, 0.0), (1.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
+                    f=lambda x: np.ones(len(x)))
+
+
+def w5_requests(n: int = 256, seed: int = 55):
+    """The serving mix: list of (N, p, seed_i)."""
+    rng = np.random.default_rng(seed)
+    Ns = rng.choice([8, 12, 16, 24, 32], size=n)
+    ps = rng.choice([2, 3, 4], size=n)
+    return [(int(N), int(p), 5000 + i) for i, (N, p) in enumerate(zip(Ns, ps))]
+
+
+def w5_problem(N: int, p: int, seed: int):
+    rng = np.random.default_rng(seed)
+    ncell = N**3
+    K = np.exp(rng.normal(size=ncell))
+    K = np.stack([K, K, K], axis=1)
+    rhs = rng.normal(size=ncell * (p + 1) ** 3)
+    return Workload(f"serve-{N}^3-p{p}", (N, N, N), (1.0, 1.0, 1.0), p, ("D",) * 6, None, K), rhs
+
+
+def random_vector(n: int, seed: int) -> np.ndarray:
+    return np.random.default_rng(seed).normal(size=n)
+
+
+def random_case(p: int, cells=(5, 3, 4), seed: int = 0, with_b: bool = False, with_c: bool = True,
+                bc=("D", "N", "D", "D", "N", "D"), lengths=(1.0, 0.7, 1.3), sigma=None) -> Workload:
+    """Small random case with the structure of the workloads: random
+    per-cell diagonal K (log-normal), optional reaction and affine advection,
+    mixed boundary types."""
+    rng = np.random.default_rng(seed)
+    nc = int(np.prod(cells))
+    K = np.exp(rng.normal(size=(nc, 3)))
+    c = np.abs(rng.normal(size=nc)) if with_c else 0.0
+    kw = {}
+    if with_b:
+        kw = dict(b0=(0.3, -0.7, 0.2), B=((0.5, 1.0, 0.0), (-1.0, -0.2, 0.5), (0.3, 0.0, -0.3)))
+    return Workload(f"random-p{p}", cells, lengths, p, bc, sigma, K, c, **kw)

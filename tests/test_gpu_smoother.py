@@ -1,0 +1,237 @@
+"""GPU parity of the inner block solves, the block-Jacobi smoother, the hybrid
+V-cycle and the outer solves against the CPU oracle (through the C ABI).
+
+  * eps tiny: the inner Krylov solve equals the dense block solve
+    (brute force), FP64 <= 1e-10;
+  * eps = 1e-2 (the paper's choice): the GPU replays the oracle's PCG /
+    GMRES steps; per-cell iteration counts are equal except where the
+    stopping ratio lies within 1e-8 of eps (none here), iterates <= 1e-10;
+  * smoother sweeps and the V-cycle with the exact coarse solve (meshes of
+    at most 512 cells, where the P0 problem is solved densely) match the
+    oracle's alg block_jacobi / alg hybrid_multigrid to 1e-9;
+  * solves reach the requested relative residual (true FP64 residual) and
+    match the sparse direct solution.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import dg, solvers
+from paper_1805_11930_amd import inputs
+from tests.helpers import oracle_problem, rel, spec
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+
+
+def _lib(w):
+    from paper_1805_11930_amd import Problem
+
+    return Problem(spec(w))
+
+
+def _setup(p, with_b, cells=(5, 3, 4), seed=0):
+    w = inputs.random_case(p, cells=cells, seed=seed, with_b=with_b)
+    opr = oracle_problem(w)
+    A = dg.assemble(opr)
+    Db = dg.block_diagonal(A, opr.ncell)
+    return w, opr, A, Db
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_block_solve_tight_equals_dense(p):
+    from paper_1805_11930_amd import DG_INNER_CG, smooth_opts
+
+    print(f"block solve tight p={p}", flush=True)
+    w, opr, A, Db = _setup(p, False)
+    d = inputs.random_vector(opr.ndof, 31)
+    D = d.reshape(opr.ncell, -1)
+    ref = np.concatenate([np.linalg.solve(Db[T], D[T]) for T in range(opr.ncell)])
+    P = _lib(w)
+    x = P.block_solve(torch.from_numpy(d).cuda(), smooth_opts(eps=1e-14, max_inner=10 * opr.nloc, inner=DG_INNER_CG))
+    assert rel(x.cpu().numpy(), ref) <= 1e-10
+    P.close()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_block_pcg_replay(p):
+    from paper_1805_11930_amd import DG_INNER_CG, smooth_opts
+
+    print(f"block PCG replay p={p}", flush=True)
+    w, opr, A, Db = _setup(p, False, seed=4)
+    d = inputs.random_vector(opr.ndof, 32)
+    D = d.reshape(opr.ncell, -1)
+    ref, its = [], []
+    for T in range(opr.ncell):
+        x, it = solvers.block_pcg(Db[T], D[T], 1e-2, opr.nloc)
+        ref.append(x)
+        its.append(it)
+    P = _lib(w)
+    x, it_gpu = P.block_solve(torch.from_numpy(d).cuda(), smooth_opts(eps=1e-2, inner=DG_INNER_CG), iters=True)
+    assert list(it_gpu.cpu().numpy()) == its
+    xg = x.cpu().numpy().reshape(opr.ncell, -1)
+    for T in range(opr.ncell):
+        assert rel(xg[T], ref[T]) <= 1e-10
+    # FP32: the tolerance is met on every block (within FP32 rounding)
+    x32, it32 = P.block_solve(torch.from_numpy(d).float().cuda(), smooth_opts(eps=1e-2, inner=DG_INNER_CG),
+                              iters=True)
+    x32 = x32.cpu().numpy().astype(np.float64).reshape(opr.ncell, -1)
+    for T in range(opr.ncell):
+        assert np.linalg.norm(D[T] - Db[T] @ x32[T]) <= 1.01e-2 * np.linalg.norm(D[T])
+    assert np.abs(it32.cpu().numpy() - np.array(its)).max() <= 1
+    P.close()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("restart", [4, 12])
+def test_block_gmres_replay(p, restart):
+    from paper_1805_11930_amd import DG_INNER_GMRES, smooth_opts
+
+    print(f"block GMRES replay p={p} restart={restart}", flush=True)
+    w, opr, A, Db = _setup(p, True, seed=5)
+    d = inputs.random_vector(opr.ndof, 33)
+    D = d.reshape(opr.ncell, -1)
+    r_eff = min(restart, opr.nloc)
+    ref, its = [], []
+    for T in range(opr.ncell):
+        x, it = solvers.block_gmres(Db[T], D[T], 1e-2, opr.nloc, r_eff)
+        ref.append(x)
+        its.append(it)
+    P = _lib(w)
+    x, it_gpu = P.block_solve(torch.from_numpy(d).cuda(),
+                              smooth_opts(eps=1e-2, inner=DG_INNER_GMRES, restart=restart), iters=True)
+    assert list(it_gpu.cpu().numpy()) == its
+    xg = x.cpu().numpy().reshape(opr.ncell, -1)
+    for T in range(opr.ncell):
+        assert rel(xg[T], ref[T]) <= 1e-9
+    # tight tolerance reaches the dense solution
+    xt = P.block_solve(torch.from_numpy(d).cuda(),
+                       smooth_opts(eps=1e-13, inner=DG_INNER_GMRES, restart=restart, max_inner=20 * opr.nloc))
+    dense = np.concatenate([np.linalg.solve(Db[T], D[T]) for T in range(opr.ncell)])
+    assert rel(xt.cpu().numpy(), dense) <= 1e-9
+    P.close()
+
+
+@pytest.mark.parametrize("p,with_b", [(1, False), (2, False), (3, True), (4, False)])
+def test_block_jacobi_sweeps(p, with_b):
+    from paper_1805_11930_amd import DG_INNER_CG, DG_INNER_GMRES, smooth_opts
+
+    print(f"block-Jacobi sweeps p={p} b={with_b}", flush=True)
+    w, opr, A, Db = _setup(p, with_b, cells=(6, 4, 3), seed=6)
+    f = inputs.random_vector(opr.ndof, 34)
+    u0 = inputs.random_vector(opr.ndof, 35)
+    inner = "gmres" if with_b else "cg"
+    ref = solvers.block_jacobi(A, Db, f, u0, omega=0.8, nsweeps=3, inner=inner, eps=1e-2, restart=12)
+    P = _lib(w)
+    o = smooth_opts(n_sweeps=3, omega=0.8, eps=1e-2, inner=DG_INNER_GMRES if with_b else DG_INNER_CG, restart=12)
+    got, st = P.block_smooth(torch.from_numpy(f).cuda(), torch.from_numpy(u0).cuda(), o, stats=True)
+    assert rel(got.cpu().numpy(), ref) <= 1e-9
+    assert st.blocks == 3 * opr.ncell and 1 <= st.inner_max <= opr.nloc
+    # zero initial guess: first sweep is omega D^-1 f
+    o0 = smooth_opts(n_sweeps=1, omega=0.8, eps=1e-2, inner=o.inner, restart=12)
+    ref0 = solvers.block_jacobi(A, Db, f, np.zeros_like(f), omega=0.8, nsweeps=1, inner=inner, eps=1e-2, restart=12)
+    got0 = P.block_smooth(torch.from_numpy(f).cuda(), None, o0)
+    assert rel(got0.cpu().numpy(), ref0) <= 1e-9
+    P.close()
+
+
+@pytest.mark.parametrize("p,with_b,npre,npost", [(2, False, 1, 1), (3, False, 2, 1), (2, True, 1, 2), (4, False, 0, 1)])
+def test_vcycle_exact_coarse(p, with_b, npre, npost):
+    from paper_1805_11930_amd import DG_INNER_CG, DG_INNER_GMRES, mg_opts
+
+    print(f"V-cycle p={p} b={with_b} pre={npre} post={npost}", flush=True)
+    w, opr, A, Db = _setup(p, with_b, cells=(5, 4, 3), seed=7)
+    r = inputs.random_vector(opr.ndof, 36)
+    inner = "gmres" if with_b else "cg"
+    cs = solvers.exact_coarse(solvers.p0_direct(opr))
+    ref = solvers.vcycle(A, Db, opr, r, cs, n_pre=npre, n_post=npost, omega=0.9, inner=inner, eps=1e-2, restart=12)
+    P = _lib(w)
+    o = mg_opts(smooth=dict(omega=0.9, eps=1e-2, inner=DG_INNER_GMRES if with_b else DG_INNER_CG, restart=12),
+                n_pre=npre, n_post=npost)
+    z = P.mg_vcycle(torch.from_numpy(r).cuda(), o)
+    assert rel(z.cpu().numpy(), ref) <= 1e-9
+    z32 = P.mg_vcycle(torch.from_numpy(r).float().cuda(), o)
+    assert rel(z32.cpu().numpy(), ref) <= 1e-3  # FP32 smoother iterations may differ by one near eps
+    P.close()
+
+
+def test_solve_w1_block_jacobi_and_mg():
+    """Workload W1 (8^3, p=2, sigma=12): FP64 and mixed-precision solves to
+    1e-10, against the sparse direct solution of the oracle's A."""
+    from paper_1805_11930_amd import (DG_FP32, DG_FP64, DG_KRYLOV_CG, DG_KRYLOV_FCG, DG_PRECOND_BLOCK_JACOBI,
+                                      DG_PRECOND_MG, solve_opts)
+
+    w = inputs.w1()
+    print("solve W1", flush=True)
+    opr = oracle_problem(w)
+    A = dg.assemble(opr)
+    rhs = dg.assemble_rhs(opr, f=w.f)
+    ref = spla.spsolve(A.tocsc(), rhs)
+    P = _lib(w)
+    f = P.rhs_from_functions(f=w.f)
+    assert rel(f.cpu().numpy(), rhs) <= 1e-13
+    for precond, prec, krylov, eps in [
+        (DG_PRECOND_BLOCK_JACOBI, DG_FP64, DG_KRYLOV_CG, 1e-12),
+        (DG_PRECOND_BLOCK_JACOBI, DG_FP64, DG_KRYLOV_FCG, 1e-2),
+        (DG_PRECOND_MG, DG_FP64, DG_KRYLOV_FCG, 1e-2),
+        (DG_PRECOND_MG, DG_FP32, DG_KRYLOV_FCG, 1e-2),
+    ]:
+        o = solve_opts(krylov=krylov, precond=precond, precond_precision=prec, rtol=1e-10, maxit=400,
+                       smooth=dict(eps=eps))
+        u, res = P.solve(f, opts=o)
+        print(f"  precond={precond} prec={prec} krylov={krylov} eps={eps}: iters={res.iters} "
+              f"rel_res={res.rel_residual:.3e}", flush=True)
+        assert res.status == 0
+        assert res.rel_residual <= 1e-10
+        assert rel(u.cpu().numpy(), ref) <= 1e-8
+    # outer CG with an exact block-Jacobi preconditioner: the oracle's CG
+    # takes the same number of iterations (+-1)
+    Db = dg.block_diagonal(A, opr.ncell)
+
+    def M(r):
+        return solvers.block_jacobi(A, Db, r, np.zeros_like(r), nsweeps=1, inner="exact")
+
+    _, it_ref, _ = solvers.cg(A, rhs, precond=M, rtol=1e-10, maxit=400)
+    o = solve_opts(krylov=DG_KRYLOV_CG, precond=DG_PRECOND_BLOCK_JACOBI, precond_precision=DG_FP64, rtol=1e-10,
+                   maxit=400, smooth=dict(eps=1e-13, max_inner=400))
+    _, res = P.solve(f, opts=o)
+    assert abs(res.iters - it_ref) <= 1
+    P.close()
+
+
+def test_solve_convection_fgmres():
+    from paper_1805_11930_amd import DG_FP32, DG_INNER_GMRES, DG_KRYLOV_FGMRES, DG_PRECOND_MG, solve_opts
+
+    w = inputs.w4(cells=(8, 8, 8), p=2)
+    print("solve convection 8^3 p=2 FGMRES", flush=True)
+    opr = oracle_problem(w)
+    A = dg.assemble(opr)
+    rhs = dg.assemble_rhs(opr, f=w.f)
+    ref = spla.spsolve(A.tocsc(), rhs)
+    P = _lib(w)
+    f = P.rhs_from_functions(f=w.f)
+    o = solve_opts(krylov=DG_KRYLOV_FGMRES, restart=30, precond=DG_PRECOND_MG, precond_precision=DG_FP32, rtol=1e-8,
+                   maxit=300, smooth=dict(eps=1e-2, inner=DG_INNER_GMRES, restart=12))
+    u, res = P.solve(f, opts=o)
+    print(f"  iters={res.iters} rel_res={res.rel_residual:.3e}", flush=True)
+    assert res.status == 0 and res.rel_residual <= 1e-8
+    assert rel(u.cpu().numpy(), ref) <= 1e-6
+    P.close()
+
+
+def test_solve_reports_nonconvergence():
+    from paper_1805_11930_amd import DG_PRECOND_MG, solve_opts
+
+    w = inputs.w1(cells=(4, 4, 4))
+    P = _lib(w)
+    f = P.rhs_from_functions(f=w.f)
+    u, res = P.solve(f, opts=solve_opts(precond=DG_PRECOND_MG, rtol=1e-12, maxit=1))
+    assert res.status == 1 and res.iters == 1
+    P.close()
