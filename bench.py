@@ -1,0 +1,264 @@
+"""Benchmark of the DG hot path on one MI355X.
+
+A step is one pass of the whole hot path over the workload: one FP64
+flexible-CG solve to a relative residual of 1e-8, preconditioned by one
+FP32 hybrid-multigrid V-cycle per iteration (block-Jacobi smoother with
+inner PCG at eps = 1e-2, P0 coarse correction), i.e. operator applies,
+fused smoother sweeps, transfers, coarse cycle and outer vector work.
+
+value  = DG operator-apply throughput (GDOF/s) of the FP64 applies that
+         run inside the timed solves, each bracketed by HIP events on the
+         solve's stream (dg_solve_result.t_apply / n_apply).
+ms_per_step = mean wall time of one solve (time-to-solve, mixed).
+Also reported: FP64-preconditioned time-to-solve, FP32 apply throughput,
+smoother and V-cycle timings, the roofline of the apply kernel, and the
+CPU oracle (explicitly assembled BSR matrix, scipy matvec) on a bounded
+sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload w2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DG apply GDOF/s + time-to-solve @1e-8 rel residual, FP64 vs mixed; p99 latency"
+HBM_PEAK_GBS = 8000.0
+APPLY_SOURCES = ["paper_1805_11930_amd/csrc/apply.hip", "paper_1805_11930_amd/csrc/line_ops.h"]
+COUNTERS = os.path.join(ROOT, "profiles", "apply_fp64_poisson32_p4_counters.json")
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def apply_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in APPLY_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_dof(p: int, elem: int) -> float:
+    """Algorithmic HBM bytes per DOF of one apply: read u, write v, and the
+    per-cell diagonal K (3 values, stored in FP64)."""
+    n3 = (p + 1) ** 3
+    return 2 * elem + 24.0 / n3
+
+
+def make_workload(name: str):
+    from paper_1805_11930_amd import inputs
+
+    return {"w1": inputs.w1, "w2": inputs.w2, "w3": inputs.w3, "w4": inputs.w4}[name]()
+
+
+def cpu_baseline(w, seconds: float = 12.0) -> dict:
+    """Oracle apply (explicit BSR matrix, scipy matvec) on a bounded sample
+    of the workload: the same p, coefficients and boundary types on an
+    8x8x8-cell sub-box."""
+    import numpy as np
+
+    from oracle import dg
+
+    sub = (8, 8, 8)
+    nc = 512
+    K = w.K if np.ndim(w.K) == 0 else np.asarray(w.K)[:nc]
+    lengths = tuple(L * s / N for L, s, N in zip(w.lengths, sub, w.cells))
+    pr = dg.Problem(cells=sub, lengths=lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=K, c=w.c, b0=w.b0, B=w.B)
+    t0 = time.perf_counter()
+    A = dg.assemble(pr)
+    t_asm = time.perf_counter() - t0
+    u = np.random.default_rng(1).normal(size=pr.ndof)
+    v = A @ u
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        v = A @ u
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {
+        "value": pr.ndof * reps / el / 1e9,
+        "unit": "GDOF/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"apply v=Au with the oracle's assembled BSR matrix (scipy matvec, single thread), "
+                  f"p={w.p}, 8x8x8 cells = {pr.ndof} DOF, {reps} applies in {el:.1f} s "
+                  f"(assembly {t_asm:.1f} s not timed)",
+    }
+
+
+def event_time(fn, reps: int) -> float:
+    """Mean seconds per call of fn() on torch's current stream (HIP events)."""
+    import torch
+
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) * 1e-3 / reps
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w3", "w4"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--apply-only", type=int, default=0,
+                    help="profiling aid: run this many FP64 applies and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the hot path runs on one MI355X, see the sharding notes).", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    from paper_1805_11930_amd import (DG_FP32, DG_FP64, DG_INNER_CG, DG_INNER_GMRES, DG_KRYLOV_FCG,
+                                      DG_KRYLOV_FGMRES, DG_PRECOND_MG, Problem, ProblemSpec, mg_opts, smooth_opts,
+                                      solve_opts)
+
+    torch.cuda.set_device(0)
+    w = make_workload(args.workload)
+    log(f"[bench] workload {w.name}: cells={w.cells} p={w.p} ndof={w.ndof}")
+    P = Problem(ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c,
+                            b0=w.b0, B=w.B))
+    u_rand = torch.from_numpy(np.random.default_rng(3).normal(size=P.ndof)).cuda()
+    if args.apply_only:
+        v = torch.empty_like(u_rand)
+        for _ in range(args.apply_only):
+            P.apply(u_rand, v)
+        torch.cuda.synchronize()
+        log(f"[bench] ran {args.apply_only} FP64 applies")
+        return 0
+    f = P.rhs_from_functions(f=w.f, g=w.g, j=w.j)
+    conv = bool(w.b0 != (0.0, 0.0, 0.0) or np.any(np.asarray(w.B) != 0))
+    inner = DG_INNER_GMRES if conv else DG_INNER_CG
+    krylov = DG_KRYLOV_FGMRES if conv else DG_KRYLOV_FCG
+
+    def opts(prec):
+        return solve_opts(krylov=krylov, restart=30, precond=DG_PRECOND_MG, precond_precision=prec, rtol=1e-8,
+                          maxit=1000, smooth=dict(eps=1e-2, inner=inner, restart=12))
+
+    o_mixed, o_fp64 = opts(DG_FP32), opts(DG_FP64)
+    u = torch.zeros_like(f)
+
+    def step(o):
+        u.zero_()
+        _, res = P.solve(f, u, o)
+        return res
+
+    for i in range(args.warmup):
+        res = step(o_mixed)
+        log(f"[bench] warmup {i}: iters={res.iters} rel_res={res.rel_residual:.2e} t={res.t_solve:.3f}s")
+    torch.cuda.synchronize()
+    t_apply = 0.0
+    n_apply = 0
+    iters = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res = step(o_mixed)
+        t_apply += res.t_apply
+        n_apply += res.n_apply
+        iters.append(res.iters)
+        if res.status != 0:
+            log(f"[bench] step {i} did not converge: status={res.status} rel_res={res.rel_residual:.2e}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"[bench] timed {args.steps} mixed solves: {ms_per_step:.1f} ms/step, iters={iters}")
+    apply_s = t_apply / max(n_apply, 1)
+    gdofs = P.ndof / apply_s / 1e9
+    bpd = bytes_per_dof(w.p, 8)
+    achieved = bpd * P.ndof / apply_s / 1e9
+    # ---- other rows of the hot path (outside the timed region) ----------
+    res64 = step(o_fp64)
+    log(f"[bench] FP64-preconditioned solve: iters={res64.iters} t={res64.t_solve:.3f}s")
+    res_m = step(o_mixed)
+    u32 = u_rand.float()
+    v32 = torch.empty_like(u32)
+    v64 = torch.empty_like(u_rand)
+    t_a64 = event_time(lambda: P.apply(u_rand, v64), 20)
+    t_a32 = event_time(lambda: P.apply(u32, v32), 20)
+    f32 = f.float() / f.norm()
+    sm = smooth_opts(eps=1e-2, inner=inner, restart=12)
+    out32 = torch.empty_like(f32)
+    t_sm = event_time(lambda: P.block_smooth(f32, u32, sm, out=out32), 5)
+    _, st = P.block_smooth(f32, u32, sm, out=out32, stats=True)
+    mo = mg_opts(smooth=dict(eps=1e-2, inner=inner, restart=12))
+    t_vc = event_time(lambda: P.mg_vcycle(f32, mo, out=out32), 5)
+    traffic = None
+    if os.path.exists(COUNTERS):
+        with open(COUNTERS) as fh:
+            cnt = json.load(fh)
+        if cnt.get("source_hash") == apply_source_hash() and cnt.get("workload") == w.name:
+            traffic = cnt.get("hbm_bytes_per_launch")
+    line = {
+        "metric": METRIC,
+        "value": round(gdofs, 3),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "cells": list(w.cells),
+            "p": w.p,
+            "ndof": P.ndof,
+            "step": "one FP64 flexible Krylov solve to 1e-8 preconditioned by an FP32 hybrid-multigrid V-cycle",
+            "value_from": "mean duration of the FP64 operator-apply kernel inside the timed solves (HIP events)",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_apply<P=4,double>",
+            "bytes_per_dof": round(bpd, 3),
+        },
+        "time_to_solve_s": {"mixed": round(ms_per_step / 1e3, 4), "fp64": round(res64.t_solve, 4)},
+        "iterations": {"mixed": iters, "fp64": res64.iters},
+        "rel_residual": {"mixed": res_m.rel_residual, "fp64": res64.rel_residual},
+        "rows": {
+            "apply_fp64_gdofs": round(P.ndof / t_a64 / 1e9, 2),
+            "apply_fp32_gdofs": round(P.ndof / t_a32 / 1e9, 2),
+            "smoother_sweep_fp32_ms": round(t_sm * 1e3, 3),
+            "smoother_inner_avg": round(st.inner_avg, 3),
+            "smoother_inner_max": st.inner_max,
+            "vcycle_fp32_ms": round(t_vc * 1e3, 3),
+            "precond_ms_per_iter_mixed": round(res_m.t_precond * 1e3 / max(res_m.n_precond, 1), 3),
+            "apply_launches_timed": n_apply,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline ...")
+        line["cpu_baseline"] = cpu_baseline(w)
+    P.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

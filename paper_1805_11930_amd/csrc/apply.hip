@@ -50,14 +50,15 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, DevTab<T, P + 1>
   constexpr int N = P + 1;
   using S = ApplyShape<N>;
   __shared__ T us[S::CPB * S::N3];
-  __shared__ T vs[S::CPB * S::N3];
+  __shared__ T qy[S::CPB * S::N3];
+  __shared__ T qz[S::CPB * S::N3];
+  __shared__ AxisCoef<T> fcs[S::CPB][3];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int c0 = blk * S::CPB;
   const int ncb = min(S::CPB, g.ncell - c0);
   const int tid = threadIdx.x;
   const T *ub = u + (size_t)c0 * S::N3;
   for (int idx = tid; idx < ncb * S::N3; idx += kApplyThreads) us[idx] = ub[idx];
-  __syncthreads();
   const int cl = tid / S::N2;
   const int ln = tid - cl * S::N2;
   const int a = ln % N, b = ln / N;
@@ -69,9 +70,15 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, DevTab<T, P + 1>
     ijk[1] = (c / g.nx) % g.ny;
     ijk[2] = c / (g.nx * g.ny);
   }
+  // face coefficients: one lane per cell and axis
+  if (active && ln < 3) fcs[cl][ln] = make_axis_coef<T>(g, c, ln, ijk);
+  __syncthreads();
   const int nn[3] = {g.nx, g.ny, g.nz};
   const int stride[3] = {1, g.nx, g.nx * g.ny};
   const bool hasb = g.has_b != 0;
+  const T vol = (T)g.vol;
+  const T stan = tb.w[a] * tb.w[b];
+  T qx[N];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     if (active) {
@@ -101,20 +108,29 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, DevTab<T, P + 1>
           }
         }
       }
-      const LineCtx<T> ctx = make_ctx<T, N>(g, tb, k, ijk[0], ijk[1], ijk[2], a, b);
-      line_apply<T, N>(ctx, tb, ul, tLu, tLd, tRu, tRd, hasb, out);
+      LineConv<T> lc = {T(0), T(0), T(0), T(0)};
+      if (hasb) lc = make_line_conv<T, N>(g, tb, k, ijk, a, b);
+      const T cre = (k == 0 && g.has_c) ? (T)g.c[c] : T(0);
+      line_apply<T, N>(tb, fcs[cl][k], stan, vol, cre, hasb, lc, ul, tLu, tLd, tRu, tRd, out);
       if (k == 0) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) vs[cl * S::N3 + line_pos<N>(0, i, a, b)] = out[i];
+        for (int i = 0; i < N; ++i) qx[i] = out[i];
       } else {
+        T *Q = k == 1 ? qy : qz;
 #pragma unroll
-        for (int i = 0; i < N; ++i) vs[cl * S::N3 + line_pos<N>(k, i, a, b)] += out[i];
+        for (int i = 0; i < N; ++i) Q[cl * S::N3 + line_pos<N>(k, i, a, b)] = out[i];
       }
     }
-    __syncthreads();
   }
-  T *vb = v + (size_t)c0 * S::N3;
-  for (int idx = tid; idx < ncb * S::N3; idx += kApplyThreads) vb[idx] = vs[idx];
+  __syncthreads();
+  if (active) {
+    T *vb = v + (size_t)c * S::N3 + N * a + S::N2 * b;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int p = cl * S::N3 + line_pos<N>(0, i, a, b);
+      vb[i] = qx[i] + qy[p] + qz[p];
+    }
+  }
 }
 
 // diag(D_T): one lane per DOF.
@@ -126,13 +142,17 @@ __global__ __launch_bounds__(256) void k_block_diag(Geo g, DevTab<T, P + 1> tb, 
   const int c = (int)(gid / N3);
   const int j = (int)(gid - (int64_t)c * N3);
   const int q[3] = {j % N, (j / N) % N, j / N2};
-  const int ix = c % g.nx, iy = (c / g.nx) % g.ny, iz = c / (g.nx * g.ny);
+  const int ijk[3] = {c % g.nx, (c / g.nx) % g.ny, c / (g.nx * g.ny)};
+  const bool hasb = g.has_b != 0;
   T s = T(0);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int t1 = (k == 0) ? 1 : 0, t2 = (k == 2) ? 1 : 2;
-    const LineCtx<T> ctx = make_ctx<T, N>(g, tb, k, ix, iy, iz, q[t1], q[t2]);
-    s += line_diag<T, N>(ctx, tb, q[k], g.has_b != 0);
+    const AxisCoef<T> f = make_axis_coef<T>(g, c, k, ijk);
+    LineConv<T> lc = {T(0), T(0), T(0), T(0)};
+    if (hasb) lc = make_line_conv<T, N>(g, tb, k, ijk, q[t1], q[t2]);
+    const T cre = (k == 0 && g.has_c) ? (T)g.c[c] : T(0);
+    s += line_diag<T, N>(tb, f, tb.w[q[t1]] * tb.w[q[t2]], (T)g.vol, cre, hasb, lc, q[k]);
   }
   diag[gid] = s;
 }

@@ -21,40 +21,102 @@
 // Face terms (interior face, normal nu = +e_k from T- to T+):
 //   Phi(u-,u+,b_nu)[[v]] - {K du/dnu}_omega [[v]] - {K dv/dnu}_omega [[u]]
 //   + gamma_F [[u]][[v]],
-// omega- = d+/(d- + d+), omega+ = d-/(d- + d+), d = K_kk,
-// gamma_F = sigma <d-,d+> |F| / min|T| with <a,b> = 2ab/(a+b) and
-// |F|/|T| = 1/h_k on a uniform mesh; Dirichlet faces take omega = 1 and
-// gamma_F = sigma d |F|/|T|; Neumann faces contribute nothing to A.
+// omega- = d+/(d- + d+), omega+ = d-/(d- + d+), d = K_kk, so both weighted
+// fluxes carry the same coefficient kappa = d- d+ / (d- + d+); gamma_F =
+// sigma <d-,d+> |F| / min|T| = 2 sigma kappa / h_k on a uniform mesh.
+// A Dirichlet face (omega = 1, gamma_F = sigma d / h_k) is the same
+// expression with kappa = d and a neighbour whose traces are zero; a
+// Neumann face contributes nothing to A.
 #pragma once
 
 #include "dg_internal.h"
 
 namespace dgmg {
 
+// Face coefficients of one cell along one axis.
 template <typename T>
-struct LineCtx {
-  T stan;     // product of the tangential Gauss weights of the line
-  T hk;       // cell size along the line
-  T vol;      // cell volume
-  T delta;    // K_kk of the cell
-  T dL, dR;   // K_kk of the neighbours (interior faces only)
-  T sigma;    // penalty prefactor
-  T cre;      // reaction coefficient added on this line (0 except one axis)
-  T beta;     // b_k on the line, without its x_k part
-  T Bkk;      // d b_k / d x_k
-  T xk0;      // cell origin along the line
-  int left, right;  // FaceKind of the faces at xi_k = 0 and xi_k = 1
+struct AxisCoef {
+  T d;        // K_kk of the cell
+  T kL, gL;   // kappa and gamma_F of the face at xi_k = 0
+  T kR, gR;   // ... and at xi_k = 1
+  T ih;       // 1 / h_k
+  int fl;     // bit 0: face at xi_k = 0 has terms; bit 1: face at xi_k = 1;
+              // bit 2 / bit 3: that face is interior (a neighbour exists)
 };
 
-// v = (1-D operator along the line) u.  Neighbour traces enter through
-// four numbers: tLu = e1.uL, tLd = d1.uL (left neighbour, its face at
-// xi_k = 1) and tRu = e0.uR, tRd = d0.uR (right neighbour).  For the block
-// diagonal D_T these are zero while the face stays interior.
+// Advection along one line: b_k(x) = beta + Bkk * x_k on the line.
+template <typename T>
+struct LineConv {
+  T beta, Bkk, xk0, hk;
+};
+
+template <typename T>
+__host__ __device__ inline AxisCoef<T> make_axis_coef(const Geo &g, int cell, int k, const int (&ijk)[3]) {
+  AxisCoef<T> f;
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  const int stride[3] = {1, g.nx, g.nx * g.ny};
+  const double d = g.K[3 * cell + k];
+  const double ih = 1.0 / g.h[k];
+  double kL = 0.0, gL = 0.0, kR = 0.0, gR = 0.0;
+  int fl = 0;
+  if (ijk[k] > 0) {
+    const double dn = g.K[3 * (cell - stride[k]) + k];
+    kL = d * dn / (d + dn);
+    gL = 2.0 * g.sigma * kL * ih;
+    fl |= 1 | 4;
+  } else if (g.bc[2 * k] == FACE_DIRICHLET) {
+    kL = d;
+    gL = g.sigma * d * ih;
+    fl |= 1;
+  }
+  if (ijk[k] < nn[k] - 1) {
+    const double dn = g.K[3 * (cell + stride[k]) + k];
+    kR = d * dn / (d + dn);
+    gR = 2.0 * g.sigma * kR * ih;
+    fl |= 2 | 8;
+  } else if (g.bc[2 * k + 1] == FACE_DIRICHLET) {
+    kR = d;
+    gR = g.sigma * d * ih;
+    fl |= 2;
+  }
+  f.d = (T)d;
+  f.kL = (T)kL;
+  f.gL = (T)gL;
+  f.kR = (T)kR;
+  f.gR = (T)gR;
+  f.ih = (T)ih;
+  f.fl = fl;
+  return f;
+}
+
+// Advection data of the line along axis k through cell ijk with tangential
+// node indices (ta, tb_) on the two other axes (in increasing axis order).
 template <typename T, int N>
-__host__ __device__ inline void line_apply(const LineCtx<T> &c, const DevTab<T, N> &tb, const T (&u)[N], T tLu,
-                                           T tLd, T tRu, T tRd, bool hasb, T (&v)[N]) {
-  const T ih = T(1) / c.hk;
-  const T alpha = c.stan * c.vol * c.delta * ih * ih;
+__host__ __device__ inline LineConv<T> make_line_conv(const Geo &g, const DevTab<T, N> &tb, int k, const int (&ijk)[3],
+                                                      int ta, int tb_) {
+  const int t1 = (k == 0) ? 1 : 0;
+  const int t2 = (k == 2) ? 1 : 2;
+  const double x1 = (ijk[t1] + (double)tb.xi[ta]) * g.h[t1];
+  const double x2 = (ijk[t2] + (double)tb.xi[tb_]) * g.h[t2];
+  LineConv<T> lc;
+  lc.beta = (T)(g.b0[k] + g.B[3 * k + t1] * x1 + g.B[3 * k + t2] * x2);
+  lc.Bkk = (T)g.B[3 * k + k];
+  lc.xk0 = (T)(ijk[k] * g.h[k]);
+  lc.hk = (T)g.h[k];
+  return lc;
+}
+
+// v = (1-D operator along the line) u, scaled by the tangential weight
+// product stan.  Neighbour traces: tLu = e1.uL, tLd = d1.uL (left neighbour
+// at its face xi_k = 1), tRu = e0.uR, tRd = d0.uR (right neighbour).  For
+// the block diagonal D_T, and on Dirichlet faces, they are zero.  cre is
+// the reaction coefficient (added on one axis only).
+template <typename T, int N>
+__host__ __device__ inline void line_apply(const DevTab<T, N> &tb, const AxisCoef<T> &f, T stan, T vol, T cre,
+                                           bool hasb, const LineConv<T> &lc, const T (&u)[N], T tLu, T tLd, T tRu,
+                                           T tRd, T (&v)[N]) {
+  const T ih = f.ih;
+  const T alpha = stan * vol * f.d * ih * ih;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     T acc = T(0);
@@ -62,16 +124,16 @@ __host__ __device__ inline void line_apply(const LineCtx<T> &c, const DevTab<T, 
     for (int l = 0; l < N; ++l) acc += tb.S[i][l] * u[l];
     v[i] = alpha * acc;
   }
-  if (c.cre != T(0)) {
-    const T rc = c.cre * c.vol * c.stan;
+  if (cre != T(0)) {
+    const T rc = cre * vol * stan;
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] += rc * tb.w[i] * u[i];
   }
   if (hasb) {
-    const T coef = -c.stan * c.vol * ih;
+    const T coef = -stan * vol * ih;
     T bu[N];
 #pragma unroll
-    for (int q = 0; q < N; ++q) bu[q] = tb.w[q] * (c.beta + c.Bkk * (c.xk0 + tb.xi[q] * c.hk)) * u[q];
+    for (int q = 0; q < N; ++q) bu[q] = tb.w[q] * (lc.beta + lc.Bkk * (lc.xk0 + tb.xi[q] * lc.hk)) * u[q];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       T acc = T(0);
@@ -80,161 +142,75 @@ __host__ __device__ inline void line_apply(const LineCtx<T> &c, const DevTab<T, 
       v[i] += coef * acc;
     }
   }
-  const T WF = c.stan * c.vol * ih;
-  if (c.right != FACE_NEUMANN) {
+  const T WF = stan * vol * ih;
+  if (f.fl & 2) {
     T uM = T(0), gM = T(0);
 #pragma unroll
     for (int l = 0; l < N; ++l) {
       uM += tb.e1[l] * u[l];
       gM += tb.d1[l] * u[l];
     }
-    gM *= ih;
-    const T bnu = hasb ? c.beta + c.Bkk * (c.xk0 + c.hk) : T(0);
-    T s, t;
-    if (c.right == FACE_INTERIOR) {
-      const T uP = tRu, gP = tRd * ih;
-      const T den = T(1) / (c.delta + c.dR);
-      const T wM = c.dR * den, wP = c.delta * den;
-      const T gam = c.sigma * T(2) * c.delta * c.dR * den * ih;
-      const T flux = bnu >= T(0) ? bnu * uM : bnu * uP;
-      const T jump = uM - uP;
-      s = flux - (wM * c.delta * gM + wP * c.dR * gP) + gam * jump;
-      t = -wM * c.delta * jump * ih;
-    } else {
-      const T gam = c.sigma * c.delta * ih;
-      const T flux = bnu >= T(0) ? bnu * uM : T(0);
-      s = flux - c.delta * gM + gam * uM;
-      t = -c.delta * uM * ih;
+    const T jump = uM - tRu;
+    T s = -f.kR * (gM + tRd) * ih + f.gR * jump;
+    if (hasb) {
+      const T bnu = lc.beta + lc.Bkk * (lc.xk0 + lc.hk);
+      s += bnu >= T(0) ? bnu * uM : bnu * tRu;
     }
     s *= WF;
-    t *= WF;
+    const T t = -WF * f.kR * jump * ih;
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] += s * tb.e1[i] + t * tb.d1[i];
   }
-  if (c.left != FACE_NEUMANN) {
+  if (f.fl & 1) {
     T uP = T(0), gP = T(0);
 #pragma unroll
     for (int l = 0; l < N; ++l) {
       uP += tb.e0[l] * u[l];
       gP += tb.d0[l] * u[l];
     }
-    gP *= ih;
-    const T bk = hasb ? c.beta + c.Bkk * c.xk0 : T(0);
-    T s, t;
-    if (c.left == FACE_INTERIOR) {
-      const T uM = tLu, gM = tLd * ih;
-      const T den = T(1) / (c.dL + c.delta);
-      const T wM = c.delta * den, wP = c.dL * den;
-      const T gam = c.sigma * T(2) * c.dL * c.delta * den * ih;
-      const T flux = bk >= T(0) ? bk * uM : bk * uP;
-      const T jump = uM - uP;
-      s = -(flux - (wM * c.dL * gM + wP * c.delta * gP) + gam * jump);
-      t = -wP * c.delta * jump * ih;
-    } else {
-      const T bnu = -bk;  // outward normal -e_k
-      const T gam = c.sigma * c.delta * ih;
-      const T flux = bnu >= T(0) ? bnu * uP : T(0);
-      s = flux + c.delta * gP + gam * uP;
-      t = c.delta * uP * ih;
+    const T jump = tLu - uP;
+    T s = -f.kL * (tLd + gP) * ih + f.gL * jump;
+    if (hasb) {
+      const T bk = lc.beta + lc.Bkk * lc.xk0;
+      s += bk >= T(0) ? bk * tLu : bk * uP;
     }
-    s *= WF;
-    t *= WF;
+    s *= -WF;
+    const T t = -WF * f.kL * jump * ih;
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] += s * tb.e0[i] + t * tb.d0[i];
   }
 }
 
 // Diagonal entry i of the line operator without neighbour couplings
-// (the same expressions as line_apply with u = unit vector e_i).
+// (line_apply with u = unit vector e_i and zero neighbour traces).
 template <typename T, int N>
-__host__ __device__ inline T line_diag(const LineCtx<T> &c, const DevTab<T, N> &tb, int i, bool hasb) {
-  const T ih = T(1) / c.hk;
-  T d = c.stan * c.vol * c.delta * ih * ih * tb.S[i][i];
-  d += c.cre * c.vol * c.stan * tb.w[i];
-  if (hasb) d += -c.stan * c.vol * ih * tb.Dt[i][i] * tb.w[i] * (c.beta + c.Bkk * (c.xk0 + tb.xi[i] * c.hk));
-  const T WF = c.stan * c.vol * ih;
-  if (c.right != FACE_NEUMANN) {
-    const T uM = tb.e1[i], gM = tb.d1[i] * ih;
-    const T bnu = hasb ? c.beta + c.Bkk * (c.xk0 + c.hk) : T(0);
-    const T flux = bnu >= T(0) ? bnu * uM : T(0);
-    T s, t;
-    if (c.right == FACE_INTERIOR) {
-      const T den = T(1) / (c.delta + c.dR);
-      const T wM = c.dR * den;
-      const T gam = c.sigma * T(2) * c.delta * c.dR * den * ih;
-      s = flux - wM * c.delta * gM + gam * uM;
-      t = -wM * c.delta * uM * ih;
-    } else {
-      const T gam = c.sigma * c.delta * ih;
-      s = flux - c.delta * gM + gam * uM;
-      t = -c.delta * uM * ih;
+__host__ __device__ inline T line_diag(const DevTab<T, N> &tb, const AxisCoef<T> &f, T stan, T vol, T cre, bool hasb,
+                                       const LineConv<T> &lc, int i) {
+  const T ih = f.ih;
+  T d = stan * vol * f.d * ih * ih * tb.S[i][i] + cre * vol * stan * tb.w[i];
+  if (hasb) d += -stan * vol * ih * tb.Dt[i][i] * tb.w[i] * (lc.beta + lc.Bkk * (lc.xk0 + tb.xi[i] * lc.hk));
+  const T WF = stan * vol * ih;
+  if (f.fl & 2) {
+    const T uM = tb.e1[i], gM = tb.d1[i];
+    T s = -f.kR * gM * ih + f.gR * uM;
+    if (hasb) {
+      const T bnu = lc.beta + lc.Bkk * (lc.xk0 + lc.hk);
+      s += bnu >= T(0) ? bnu * uM : T(0);
     }
+    const T t = -f.kR * uM * ih;
     d += WF * (s * tb.e1[i] + t * tb.d1[i]);
   }
-  if (c.left != FACE_NEUMANN) {
-    const T uP = tb.e0[i], gP = tb.d0[i] * ih;
-    const T bk = hasb ? c.beta + c.Bkk * c.xk0 : T(0);
-    T s, t;
-    if (c.left == FACE_INTERIOR) {
-      const T den = T(1) / (c.dL + c.delta);
-      const T wP = c.dL * den;
-      const T gam = c.sigma * T(2) * c.dL * c.delta * den * ih;
-      const T flux = bk >= T(0) ? T(0) : bk * uP;
-      const T jump = -uP;
-      s = -(flux - wP * c.delta * gP + gam * jump);
-      t = -wP * c.delta * jump * ih;
-    } else {
-      const T bnu = -bk;
-      const T gam = c.sigma * c.delta * ih;
-      const T flux = bnu >= T(0) ? bnu * uP : T(0);
-      s = flux + c.delta * gP + gam * uP;
-      t = c.delta * uP * ih;
+  if (f.fl & 1) {
+    const T uP = tb.e0[i], gP = tb.d0[i];
+    T s = -f.kL * gP * ih - f.gL * uP;
+    if (hasb) {
+      const T bk = lc.beta + lc.Bkk * lc.xk0;
+      s += bk >= T(0) ? T(0) : bk * uP;
     }
-    d += WF * (s * tb.e0[i] + t * tb.d0[i]);
+    const T t = f.kL * uP * ih;
+    d += -WF * s * tb.e0[i] + WF * t * tb.d0[i];
   }
   return d;
-}
-
-// Build the context of the line along axis k through cell (ix,iy,iz) with
-// tangential node indices (ta, tb_) on the two other axes (in increasing
-// axis order).  K is read from the device array g.K.
-template <typename T, int N>
-__host__ __device__ inline LineCtx<T> make_ctx(const Geo &g, const DevTab<T, N> &tb, int k, int ix, int iy, int iz,
-                                               int ta, int tb_) {
-  LineCtx<T> c;
-  const int ijk[3] = {ix, iy, iz};
-  const int nn[3] = {g.nx, g.ny, g.nz};
-  const int cell = ix + g.nx * (iy + g.ny * iz);
-  const int stride[3] = {1, g.nx, g.nx * g.ny};
-  c.stan = tb.w[ta] * tb.w[tb_];
-  c.hk = (T)g.h[k];
-  c.vol = (T)g.vol;
-  c.delta = (T)g.K[3 * cell + k];
-  c.sigma = (T)g.sigma;
-  c.cre = (k == 0 && g.has_c) ? (T)g.c[cell] : T(0);
-  if (ijk[k] > 0) {
-    c.left = FACE_INTERIOR;
-    c.dL = (T)g.K[3 * (cell - stride[k]) + k];
-  } else {
-    c.left = g.bc[2 * k];
-    c.dL = T(0);
-  }
-  if (ijk[k] < nn[k] - 1) {
-    c.right = FACE_INTERIOR;
-    c.dR = (T)g.K[3 * (cell + stride[k]) + k];
-  } else {
-    c.right = g.bc[2 * k + 1];
-    c.dR = T(0);
-  }
-  // tangential axes t1 < t2 and their physical coordinates
-  const int t1 = (k == 0) ? 1 : 0;
-  const int t2 = (k == 2) ? 1 : 2;
-  const double x1 = (ijk[t1] + (double)tb.xi[ta]) * g.h[t1];
-  const double x2 = (ijk[t2] + (double)tb.xi[tb_]) * g.h[t2];
-  c.beta = (T)(g.b0[k] + g.B[3 * k + t1] * x1 + g.B[3 * k + t2] * x2);
-  c.Bkk = (T)g.B[3 * k + k];
-  c.xk0 = (T)(ijk[k] * g.h[k]);
-  return c;
 }
 
 }  // namespace dgmg

@@ -61,9 +61,14 @@ struct SmoothKArgs {
   int zero_guess, write_du, defect;
 };
 
+// Per-lane data of the three lines (x: y=a,z=b; y: x=a,z=b; z: x=a,y=b)
+// through the lane's line index; all three share the tangential weight
+// product w_a w_b.
 template <int P, typename T>
 struct CellLines {
-  LineCtx<T> cx, cy, cz;
+  AxisCoef<T> f[3];
+  LineConv<T> lc[3];
+  T stan, vol, cre;
 };
 
 // q = D_T p on the lane's x-line.  All lanes of the wavefront must call it.
@@ -73,7 +78,7 @@ __device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1
   constexpr int N = P + 1;
   T qx[N];
   if (on) {
-    line_apply<T, N>(cl.cx, tb, p, T(0), T(0), T(0), T(0), hasb, qx);
+    line_apply<T, N>(tb, cl.f[0], cl.stan, cl.vol, cl.cre, hasb, cl.lc[0], p, T(0), T(0), T(0), T(0), qx);
 #pragma unroll
     for (int i = 0; i < N; ++i) Ps[lpos<N>(0, i, a, b)] = p[i];
   }
@@ -82,12 +87,12 @@ __device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1
     T yl[N], yo[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) yl[i] = Ps[lpos<N>(1, i, a, b)];
-    line_apply<T, N>(cl.cy, tb, yl, T(0), T(0), T(0), T(0), hasb, yo);
+    line_apply<T, N>(tb, cl.f[1], cl.stan, cl.vol, T(0), hasb, cl.lc[1], yl, T(0), T(0), T(0), T(0), yo);
 #pragma unroll
     for (int i = 0; i < N; ++i) Qy[lpos<N>(1, i, a, b)] = yo[i];
 #pragma unroll
     for (int i = 0; i < N; ++i) yl[i] = Ps[lpos<N>(2, i, a, b)];
-    line_apply<T, N>(cl.cz, tb, yl, T(0), T(0), T(0), T(0), hasb, yo);
+    line_apply<T, N>(tb, cl.f[2], cl.stan, cl.vol, T(0), hasb, cl.lc[2], yl, T(0), T(0), T(0), T(0), yo);
 #pragma unroll
     for (int i = 0; i < N; ++i) Qz[lpos<N>(2, i, a, b)] = yo[i];
   }
@@ -125,13 +130,19 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, DevTab<T, P + 
 
   int ijk[3] = {0, 0, 0};
   CellLines<P, T> cl;
+  cl.stan = tb.w[a] * tb.w[b];
+  cl.vol = (T)g.vol;
+  cl.cre = T(0);
   if (on) {
     ijk[0] = c % g.nx;
     ijk[1] = (c / g.nx) % g.ny;
     ijk[2] = c / (g.nx * g.ny);
-    cl.cx = make_ctx<T, N>(g, tb, 0, ijk[0], ijk[1], ijk[2], a, b);
-    cl.cy = make_ctx<T, N>(g, tb, 1, ijk[0], ijk[1], ijk[2], a, b);
-    cl.cz = make_ctx<T, N>(g, tb, 2, ijk[0], ijk[1], ijk[2], a, b);
+    cl.cre = g.has_c ? (T)g.c[c] : T(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      cl.f[k] = make_axis_coef<T>(g, c, k, ijk);
+      cl.lc[k] = hasb ? make_line_conv<T, N>(g, tb, k, ijk, a, b) : LineConv<T>{T(0), T(0), T(0), T(0)};
+    }
   }
   const size_t base = (size_t)c * S::N3;
 
@@ -176,8 +187,8 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, DevTab<T, P + 
             tRd += tb.d0[i] * x;
           }
         }
-        const LineCtx<T> &ctx = k == 0 ? cl.cx : (k == 1 ? cl.cy : cl.cz);
-        line_apply<T, N>(ctx, tb, line, tLu, tLd, tRu, tRd, hasb, out);
+        line_apply<T, N>(tb, cl.f[k], cl.stan, cl.vol, k == 0 ? cl.cre : T(0), hasb, cl.lc[k], line, tLu, tLd, tRu,
+                         tRd, out);
         if (k == 0) {
 #pragma unroll
           for (int i = 0; i < N; ++i) ax[i] = out[i];
@@ -202,10 +213,14 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, DevTab<T, P + 
   for (int i = 0; i < N; ++i) {
     T dd = T(1);
     if (on) {
-      const LineCtx<T> cy = make_ctx<T, N>(g, tb, 1, ijk[0], ijk[1], ijk[2], i, b);
-      const LineCtx<T> cz = make_ctx<T, N>(g, tb, 2, ijk[0], ijk[1], ijk[2], i, a);
-      dd = line_diag<T, N>(cl.cx, tb, i, hasb) + line_diag<T, N>(cy, tb, a, hasb) +
-           line_diag<T, N>(cz, tb, b, hasb);
+      // DOF (i, a, b) lies on the x-line (a, b), the y-line (x=i, z=b) and
+      // the z-line (x=i, y=a)
+      const LineConv<T> zero = {T(0), T(0), T(0), T(0)};
+      const LineConv<T> ly = hasb ? make_line_conv<T, N>(g, tb, 1, ijk, i, b) : zero;
+      const LineConv<T> lz = hasb ? make_line_conv<T, N>(g, tb, 2, ijk, i, a) : zero;
+      dd = line_diag<T, N>(tb, cl.f[0], cl.stan, cl.vol, cl.cre, hasb, cl.lc[0], i) +
+           line_diag<T, N>(tb, cl.f[1], tb.w[i] * tb.w[b], cl.vol, T(0), hasb, ly, a) +
+           line_diag<T, N>(tb, cl.f[2], tb.w[i] * tb.w[a], cl.vol, T(0), hasb, lz, b);
     }
     dinv[i] = T(1) / dd;
   }

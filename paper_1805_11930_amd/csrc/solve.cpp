@@ -57,7 +57,37 @@ struct Ctx {
   double *part, *dout;
   float *r32 = nullptr, *z32 = nullptr;
   int64_t n;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double t_apply = 0.0, t_precond = 0.0;
+  int n_apply = 0, n_precond = 0;
 };
+
+// FP64 operator apply bracketed by HIP events on the solve's stream.
+int timed_apply(Ctx &c, const double *u, double *v) {
+  DG_HIP(hipEventRecord(c.ev0, c.s));
+  int rc = launch_apply(c.pr, DG_FP64, u, v, c.s);
+  if (rc) return rc;
+  DG_HIP(hipEventRecord(c.ev1, c.s));
+  DG_HIP(hipEventSynchronize(c.ev1));
+  float ms = 0.f;
+  DG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+  c.t_apply += 1e-3 * ms;
+  ++c.n_apply;
+  return DG_OK;
+}
+
+int timed_precond(Ctx &c, const double *r, double *z, double rnorm) {
+  DG_HIP(hipEventRecord(c.ev0, c.s));
+  int rc = precond_apply(c.pr, c.o, r, z, rnorm, c.r32, c.z32, c.s);
+  if (rc) return rc;
+  DG_HIP(hipEventRecord(c.ev1, c.s));
+  DG_HIP(hipEventSynchronize(c.ev1));
+  float ms = 0.f;
+  DG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+  c.t_precond += 1e-3 * ms;
+  ++c.n_precond;
+  return DG_OK;
+}
 
 int host_dots(Ctx &c, const DotSet &ds, double *out) {
   int rc = dots(ds, c.n, c.part, c.dout, c.s);
@@ -76,7 +106,7 @@ int host_dot(Ctx &c, const double *a, const double *b, double *out) {
 }
 
 int residual(Ctx &c, const double *f, const double *u, double *r, double *tmp) {
-  int rc = launch_apply(c.pr, DG_FP64, u, tmp, c.s);
+  int rc = timed_apply(c, u, tmp);
   if (rc) return rc;
   return sub(c.n, f, tmp, r, c.s);
 }
@@ -90,14 +120,14 @@ int solve_cg(Ctx &c, const double *f, double *u, dg_solve_result *res, DevBuf &w
   if (flex && (rc = wb.get(&rold, c.n))) return rc;
   if ((rc = residual(c, f, u, r, q))) return rc;
   double rnorm = r0;
-  if ((rc = precond_apply(c.pr, c.o, r, z, rnorm, c.r32, c.z32, c.s))) return rc;
+  if ((rc = timed_precond(c, r, z, rnorm))) return rc;
   double rz;
   if ((rc = host_dot(c, r, z, &rz))) return rc;
   DG_HIP(hipMemcpyAsync(p, z, c.n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
   int it = 0;
   res->status = DG_ENOCONV;
   while (it < c.o->maxit) {
-    if ((rc = launch_apply(c.pr, DG_FP64, p, q, c.s))) return rc;
+    if ((rc = timed_apply(c, p, q))) return rc;
     double pq;
     if ((rc = host_dot(c, p, q, &pq))) return rc;
     if (!(pq > 0) || !std::isfinite(pq) || !std::isfinite(rz)) {
@@ -121,7 +151,7 @@ int solve_cg(Ctx &c, const double *f, double *u, dg_solve_result *res, DevBuf &w
       res->status = DG_OK;
       break;
     }
-    if ((rc = precond_apply(c.pr, c.o, r, z, rnorm, c.r32, c.z32, c.s))) return rc;
+    if ((rc = timed_precond(c, r, z, rnorm))) return rc;
     double beta;
     if (flex) {
       DotSet ds;
@@ -168,9 +198,9 @@ int solve_fgmres(Ctx &c, const double *f, double *u, dg_solve_result *res, DevBu
     g[0] = beta;
     int k = 0;
     for (int j = 0; j < m; ++j) {
-      if ((rc = precond_apply(c.pr, c.o, V[j], Z[j], 1.0, c.r32, c.z32, c.s))) return rc;
+      if ((rc = timed_precond(c, V[j], Z[j], 1.0))) return rc;
       double *w = V[j + 1];
-      if ((rc = launch_apply(c.pr, DG_FP64, Z[j], w, c.s))) return rc;
+      if ((rc = timed_apply(c, Z[j], w))) return rc;
       // classical Gram-Schmidt, applied twice
       VecList vl;
       for (int i = 0; i <= j; ++i) vl.v[i] = V[i];
@@ -271,6 +301,17 @@ extern "C" int dg_solve(dg_problem *pr, const double *f, double *u, const dg_sol
   c.s = s;
   c.n = pr->ndof;
   int rc;
+  struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } evs;
+  DG_HIP(hipEventCreate(&evs.a));
+  DG_HIP(hipEventCreate(&evs.b));
+  c.ev0 = evs.a;
+  c.ev1 = evs.b;
   if ((rc = wb.get(&c.part, (size_t)kMaxBasis * kDotBlocks)) || (rc = wb.get(&c.dout, kMaxBasis))) return rc;
   if (o->precond_precision == DG_FP32 && o->precond != DG_PRECOND_NONE) {
     if ((rc = wb.get(&c.r32, c.n)) || (rc = wb.get(&c.z32, c.n))) return rc;
@@ -311,6 +352,10 @@ extern "C" int dg_solve(dg_problem *pr, const double *f, double *u, const dg_sol
   res->t_setup = t1 - t0;
   res->t_solve = t2 - t1;
   res->footprint = pr->held_bytes + wb.bytes;
+  res->t_apply = c.t_apply;
+  res->n_apply = c.n_apply;
+  res->t_precond = c.t_precond;
+  res->n_precond = c.n_precond;
   if (res->status == DG_OK && !(res->rel_residual <= o->rtol * 1.0000001)) res->status = DG_ENOCONV;
   return res->status;
 }
