@@ -208,6 +208,30 @@ int dg_mg_vcycle(dg_problem *prob, int precision, const void *r, void *z, const 
 int dg_solve(dg_problem *prob, const double *f, double *u, const dg_solve_opts *opts,
              dg_solve_result *res, void *stream);
 
+/* ---- resident solves and continuous batching ---------------------- */
+/* Start an outer CG / flexible-CG solve of A u = f (options as dg_solve;
+ * FGMRES is not available here) that stays resident on the device: the
+ * state owns its workspace and a HIP stream of default priority, computes
+ * the initial residual and first preconditioned residual, and returns.
+ * f and u (DEVICE double [ndof], caller-owned) must stay valid until the
+ * state is destroyed; u holds the initial guess and receives the solution.
+ * One state per problem handle at a time (a problem's V-cycle temporaries
+ * are shared by its solves).  DG_ENOMEM when the workspace does not fit. */
+int dg_solve_start(dg_problem *prob, const double *f, double *u, const dg_solve_opts *opts,
+                   dg_solve_state **out);
+/* Advance every unfinished state in active[0..n_active) by one outer
+ * iteration.  The iteration runs in three phases (apply, update, precondition);
+ * each phase is enqueued for all states on their own streams and then
+ * waited for once, so requests of different sizes and degrees overlap on
+ * the device and share the host round trips.  A request's arithmetic is
+ * the same alone and in any batch.  Returns after all states' work for the
+ * step is complete; `stream` is not used (reserved). */
+int dg_batch_step(dg_solve_state **active, int n_active, void *stream);
+/* DG_EAGAIN while the solve runs; DG_OK once finished, with *res (nullable)
+ * filled (its status is DG_OK, DG_ENOCONV or DG_EBREAKDOWN). */
+int dg_solve_poll(dg_solve_state *state, dg_solve_result *res);
+void dg_solve_state_destroy(dg_solve_state *state);
+
 /* Device bytes the library would hold for this problem and solve. */
 int dg_footprint(const dg_problem_desc *desc, const dg_solve_opts *opts, size_t *bytes);
 

@@ -29,7 +29,8 @@ EXPORTS = (
     "dg_problem_create", "dg_problem_destroy", "dg_last_error", "dg_ndof", "dg_boundary_npoints",
     "dg_node_points", "dg_boundary_points", "dg_assemble_rhs", "dg_apply", "dg_block_apply",
     "dg_block_diag", "dg_block_solve", "dg_block_smooth", "dg_mg_vcycle", "dg_solve", "dg_footprint",
-    "dg_default_smooth_opts", "dg_default_mg_opts", "dg_default_solve_opts",
+    "dg_default_smooth_opts", "dg_default_mg_opts", "dg_default_solve_opts", "dg_solve_start", "dg_batch_step",
+    "dg_solve_poll", "dg_solve_state_destroy",
 )
 
 
@@ -124,6 +125,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_default_mg_opts.restype = None
     lib.dg_default_solve_opts.argtypes = [ctypes.POINTER(SolveOpts)]
     lib.dg_default_solve_opts.restype = None
+    lib.dg_solve_start.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(vp)]
+    lib.dg_batch_step.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+    lib.dg_solve_poll.argtypes = [vp, ctypes.POINTER(SolveResult)]
+    lib.dg_solve_state_destroy.argtypes = [vp]
+    lib.dg_solve_state_destroy.restype = None
     _LIB = lib
     return lib
 

@@ -21,7 +21,7 @@ OUT = os.path.join(HERE, "libdgmg.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("DGMG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["tables.cpp", "problem.cpp", "api.cpp", "solve.cpp", "apply.hip", "smooth.hip", "vec.hip"]
+SOURCES = ["tables.cpp", "problem.cpp", "api.cpp", "solve.cpp", "batch.cpp", "apply.hip", "smooth.hip", "vec.hip"]
 
 COMMON = [
     "-O3",

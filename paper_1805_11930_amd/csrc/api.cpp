@@ -67,7 +67,7 @@ size_t esize(int prec) { return prec == DG_FP64 ? sizeof(double) : sizeof(float)
 // `alt` as the other ping-pong buffer.  dst != alt; src may equal alt but
 // not dst unless n == 0.
 int sweeps(dg_problem *pr, int prec, const void *f, const void *src, void *dst, void *alt, int n,
-           const SmoothArgs &base, int *iters, hipStream_t s) {
+           const SmoothArgs &base, int *iters, hipStream_t s, const void *zh = nullptr) {
   if (n <= 0) {
     if (src == nullptr)
       DG_HIP(hipMemsetAsync(dst, 0, (size_t)pr->ndof * esize(prec), s));
@@ -81,6 +81,7 @@ int sweeps(dg_problem *pr, int prec, const void *f, const void *src, void *dst, 
     if (out == cur) out = (out == dst) ? alt : dst;  // never smooth in place
     SmoothArgs a = base;
     a.zero_guess = cur == nullptr ? 1 : 0;
+    a.zh = (k == 1 && cur != nullptr) ? zh : nullptr;  // P0 correction enters the first sweep
     int rc = launch_smooth(pr, prec, f, cur ? cur : f, out, a, iters, s);
     if (rc) return rc;
     cur = out;
@@ -115,12 +116,17 @@ struct LevelPtr<float> {
   static const float *inv(const dg_problem *pr) { return pr->bottom_inv32; }
 };
 
-// x_l ~= A_l^-1 r_l (both stored in level l's r / x buffers)
+// x_l ~= A_l^-1 r_l: one V-cycle of the P0 aggregation hierarchy from a
+// zero guess; r_l is level l's r buffer, the result is left in one of
+// level l's x / t buffers and returned in *result.
 template <typename T>
-int coarse_cycle(dg_problem *pr, size_t l, int nu, T w, hipStream_t s) {
+int coarse_cycle(dg_problem *pr, size_t l, int nu, T w, hipStream_t s, T **result) {
   using LP = LevelPtr<T>;
   CoarseLevel &L = pr->levels[l];
-  if (l + 1 == pr->levels.size()) return dense_mv<T>(pr->bottom_n, LP::inv(pr), LP::r(L), LP::x(L), s);
+  if (l + 1 == pr->levels.size()) {
+    *result = LP::x(L);
+    return dense_mv<T>(pr->bottom_n, LP::inv(pr), LP::r(L), LP::x(L), s);
+  }
   int rc;
   T *x = LP::x(L), *t = LP::t(L);
   const T *A = LP::A(L), *r = LP::r(L);
@@ -132,13 +138,14 @@ int coarse_cycle(dg_problem *pr, size_t l, int nu, T w, hipStream_t s) {
   }
   CoarseLevel &C = pr->levels[l + 1];
   if ((rc = coarse_restrict<T>(A, L.nx, L.ny, L.nz, r, x, C.nx, C.ny, C.nz, LP::r(C), s))) return rc;
-  if ((rc = coarse_cycle<T>(pr, l + 1, nu, w, s))) return rc;
-  if ((rc = coarse_prolong<T>(L.nx, L.ny, L.nz, C.nx, C.ny, LP::x(C), x, s))) return rc;
+  T *xc = nullptr;
+  if ((rc = coarse_cycle<T>(pr, l + 1, nu, w, s, &xc))) return rc;
+  if ((rc = coarse_prolong<T>(L.nx, L.ny, L.nz, C.nx, C.ny, xc, x, s))) return rc;
   for (int k = 0; k < nu; ++k) {
     if ((rc = coarse_jacobi<T>(A, L.nx, L.ny, L.nz, w, r, x, t, s))) return rc;
     std::swap(x, t);
   }
-  if (x != LP::x(L)) DG_HIP(hipMemcpyAsync(LP::x(L), x, (size_t)L.n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  *result = x;
   return DG_OK;
 }
 
@@ -147,23 +154,23 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
   SmoothArgs sa;
   int rc = smooth_args(pr, &o->smooth, sa);
   if (rc) return rc;
-  void *t0, *t1;
-  if ((rc = alloc_tmp(pr, prec, 0, &t0)) || (rc = alloc_tmp(pr, prec, 1, &t1))) return rc;
+  void *t0;
+  if ((rc = alloc_tmp(pr, prec, 0, &t0))) return rc;
   // presmoothing ends in X so that postsmoothing ends in z without a copy
   void *X = (o->n_post % 2 == 1) ? t0 : (void *)z;
   void *Y = (X == t0) ? (void *)z : t0;
   if ((rc = sweeps(pr, prec, r, nullptr, X, Y, o->n_pre, sa, nullptr, s))) return rc;
-  // residual, restriction R = P^T
-  if ((rc = launch_apply(pr, prec, X, t1, s))) return rc;
+  // residual and restriction R = P^T in one pass
   using LP = LevelPtr<T>;
   CoarseLevel &L0 = pr->levels[0];
-  if ((rc = restrict_p0<T>(pr->ncell, pr->nloc, r, (const T *)t1, LP::r(L0), s))) return rc;
+  if ((rc = launch_residual_restrict(pr, prec, X, r, LP::r(L0), s))) return rc;
   const int nu = o->coarse_smooth > 0 ? o->coarse_smooth : 2;
   const T w = (T)(o->coarse_omega > 0 ? o->coarse_omega : 2.0 / 3.0);
-  if ((rc = coarse_cycle<T>(pr, 0, nu, w, s))) return rc;
-  // prolongation P (injection) and add
-  if ((rc = prolong_add_p0<T>(pr->ndof, pr->nloc, LP::x(L0), (T *)X, s))) return rc;
-  return sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s);
+  T *xh = nullptr;
+  if ((rc = coarse_cycle<T>(pr, 0, nu, w, s, &xh))) return rc;
+  if (o->n_post == 0) return prolong_add_p0<T>(pr->ndof, pr->nloc, xh, (T *)X, s);  // X == z here
+  // prolongation P (injection) fused into the first postsmoothing sweep
+  return sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s, xh);
 }
 
 int vcycle(dg_problem *pr, int prec, const void *r, void *z, const dg_mg_opts *o, hipStream_t s) {
@@ -178,7 +185,7 @@ extern "C" {
 void dg_default_smooth_opts(dg_smooth_opts *o) {
   if (!o) return;
   o->n_sweeps = 1;
-  o->omega = 1.0;
+  o->omega = 0.7;
   o->eps = 1e-2;
   o->max_inner = 0;
   o->inner = DG_INNER_CG;
@@ -192,7 +199,7 @@ void dg_default_mg_opts(dg_mg_opts *o) {
   o->n_post = 1;
   dg_default_smooth_opts(&o->smooth);
   o->coarse_cycles = 1;
-  o->coarse_smooth = 2;
+  o->coarse_smooth = 4;
   o->coarse_omega = 2.0 / 3.0;
 }
 

@@ -44,9 +44,13 @@ __device__ __host__ inline int line_pos(int k, int i, int a, int b) {
 }
 
 // NB: with neighbour couplings (A) or without (D_T).
-template <int P, typename T, bool NB>
+// RES: instead of writing v = A u, write rh[c] = sum over the DOFs of cell c
+// of (r - A u): the residual followed by the P0 restriction R = P^T
+// (Sec. 2.2.2), fused so that A u never goes to memory.
+template <int P, typename T, bool NB, bool RES = false>
 __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, DevTab<T, P + 1> tb, const T *__restrict__ u,
-                                                         T *__restrict__ v) {
+                                                         T *__restrict__ v, const T *__restrict__ r = nullptr,
+                                                         T *__restrict__ rh = nullptr) {
   constexpr int N = P + 1;
   using S = ApplyShape<N>;
   __shared__ T us[S::CPB * S::N3];
@@ -123,12 +127,32 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, DevTab<T, P + 1>
     }
   }
   __syncthreads();
-  if (active) {
-    T *vb = v + (size_t)c * S::N3 + N * a + S::N2 * b;
+  if (!RES) {
+    if (active) {
+      T *vb = v + (size_t)c * S::N3 + N * a + S::N2 * b;
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const int p = cl * S::N3 + line_pos<N>(0, i, a, b);
-      vb[i] = qx[i] + qy[p] + qz[p];
+      for (int i = 0; i < N; ++i) {
+        const int p = cl * S::N3 + line_pos<N>(0, i, a, b);
+        vb[i] = qx[i] + qy[p] + qz[p];
+      }
+    }
+  } else {
+    __shared__ T part[S::CPB * S::N2];
+    if (active) {
+      const T *rb = r + (size_t)c * S::N3 + N * a + S::N2 * b;
+      T sum = T(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int p = cl * S::N3 + line_pos<N>(0, i, a, b);
+        sum += rb[i] - (qx[i] + qy[p] + qz[p]);
+      }
+      part[cl * S::N2 + ln] = sum;
+    }
+    __syncthreads();
+    if (active && ln == 0) {
+      T sum = T(0);
+      for (int l = 0; l < S::N2; ++l) sum += part[cl * S::N2 + l];
+      rh[c] = sum;
     }
   }
 }
@@ -233,6 +257,29 @@ static int dispatch_apply(const dg_problem *pr, const void *u, void *v, hipStrea
     case 2: return launch_apply_t<2, T>(pr, u, v, s, nb);
     case 3: return launch_apply_t<3, T>(pr, u, v, s, nb);
     case 4: return launch_apply_t<4, T>(pr, u, v, s, nb);
+  }
+  set_error("unsupported degree");
+  return DG_EINVAL;
+}
+
+template <int P, typename T>
+static int launch_res_t(const dg_problem *pr, const void *u, const void *r, void *rh, hipStream_t s) {
+  constexpr int N = P + 1;
+  const int G = (int)((pr->ncell + ApplyShape<N>::CPB - 1) / ApplyShape<N>::CPB);
+  DevTab<T, N> tb = make_devtab<T, N>(pr->tab);
+  hipLaunchKernelGGL((k_apply<P, T, true, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, tb, (const T *)u,
+                     (T *)nullptr, (const T *)r, (T *)rh);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, const void *r, void *rh, hipStream_t s) {
+  const bool d = prec == DG_FP64;
+  switch (pr->p) {
+    case 1: return d ? launch_res_t<1, double>(pr, u, r, rh, s) : launch_res_t<1, float>(pr, u, r, rh, s);
+    case 2: return d ? launch_res_t<2, double>(pr, u, r, rh, s) : launch_res_t<2, float>(pr, u, r, rh, s);
+    case 3: return d ? launch_res_t<3, double>(pr, u, r, rh, s) : launch_res_t<3, float>(pr, u, r, rh, s);
+    case 4: return d ? launch_res_t<4, double>(pr, u, r, rh, s) : launch_res_t<4, float>(pr, u, r, rh, s);
   }
   set_error("unsupported degree");
   return DG_EINVAL;

@@ -81,11 +81,6 @@ struct CoarseLevel {
   float *r32 = nullptr, *x32 = nullptr, *t32 = nullptr;
 };
 
-struct Workspace {
-  size_t bytes = 0;
-  void *buf = nullptr;
-};
-
 }  // namespace dgmg
 
 struct dg_problem {
@@ -123,6 +118,8 @@ int hip_fail(hipError_t e, const char *what);
 // kernel launchers (apply.hip / smooth.hip / vec.hip / coarse.hip)
 int launch_apply(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s);
 int launch_block_apply(const dg_problem *pr, int prec, const void *x, void *y, hipStream_t s);
+// rh[c] = sum_{i in cell c} (r - A u)_i
+int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, const void *r, void *rh, hipStream_t s);
 int launch_block_diag(const dg_problem *pr, int prec, void *diag, hipStream_t s);
 int launch_rhs(const dg_problem *pr, const double *f_qp, const double *bnd, double *rhs, hipStream_t s);
 
@@ -132,6 +129,7 @@ struct SmoothArgs {
   int zero_guess;   // u_in treated as 0
   int write_du;     // output is the correction only (block solve)
   int defect;       // compute d = f - A u (otherwise d = f)
+  const void *zh = nullptr;  // optional P0 correction: u_in + P zh is smoothed
 };
 int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin, void *uout,
                   const SmoothArgs &a, int *iters, hipStream_t s);

@@ -104,7 +104,8 @@ __device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1
 template <int P, int INNER, typename T>
 __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, DevTab<T, P + 1> tb, const T *__restrict__ f,
                                                            const T *__restrict__ uin, T *__restrict__ uout,
-                                                           SmoothKArgs sa, int *__restrict__ iters) {
+                                                           SmoothKArgs sa, int *__restrict__ iters,
+                                                           const T *__restrict__ zh) {
   constexpr int N = P + 1;
   using S = SmoothShape<N>;
   constexpr int L = S::L;
@@ -148,9 +149,12 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, DevTab<T, P + 
 
   // ---- defect d = f - A u -------------------------------------------------
   T ul[N], d[N];
+  // the smoothed iterate is u_in + P zh when a P0 correction is given
+  // (prolongation fused into the sweep; P|_T = (1,...,1)^T)
+  const T zc = (on && zh) ? zh[c] : T(0);
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    ul[i] = (on && !sa.zero_guess) ? uin[base + lpos<N>(0, i, a, b)] : T(0);
+    ul[i] = (on && !sa.zero_guess) ? uin[base + lpos<N>(0, i, a, b)] + zc : T(0);
     d[i] = on ? f[base + lpos<N>(0, i, a, b)] : T(0);
   }
   if (sa.defect && !sa.zero_guess) {
@@ -170,19 +174,23 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, DevTab<T, P + 
         for (int i = 0; i < N; ++i) line[i] = k == 0 ? ul[i] : Ps[lpos<N>(k, i, a, b)];
         T tLu = T(0), tLd = T(0), tRu = T(0), tRd = T(0);
         if (ijk[k] > 0) {
-          const T *src = uin + (size_t)(c - stride[k]) * S::N3;
+          const int cn = c - stride[k];
+          const T *src = uin + (size_t)cn * S::N3;
+          const T zn = zh ? zh[cn] : T(0);
 #pragma unroll
           for (int i = 0; i < N; ++i) {
-            const T x = src[lpos<N>(k, i, a, b)];
+            const T x = src[lpos<N>(k, i, a, b)] + zn;
             tLu += tb.e1[i] * x;
             tLd += tb.d1[i] * x;
           }
         }
         if (ijk[k] < nn[k] - 1) {
-          const T *src = uin + (size_t)(c + stride[k]) * S::N3;
+          const int cn = c + stride[k];
+          const T *src = uin + (size_t)cn * S::N3;
+          const T zn = zh ? zh[cn] : T(0);
 #pragma unroll
           for (int i = 0; i < N; ++i) {
-            const T x = src[lpos<N>(k, i, a, b)];
+            const T x = src[lpos<N>(k, i, a, b)] + zn;
             tRu += tb.e0[i] * x;
             tRd += tb.d0[i] * x;
           }
@@ -473,16 +481,20 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
   ka.defect = a.defect;
   if (a.inner == DG_INNER_CG)
     hipLaunchKernelGGL((k_smooth<P, DG_INNER_CG, T>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo, tb,
-                       (const T *)f, (const T *)uin, (T *)uout, ka, iters);
+                       (const T *)f, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh);
   else
     hipLaunchKernelGGL((k_smooth<P, DG_INNER_GMRES, T>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo, tb,
-                       (const T *)f, (const T *)uin, (T *)uout, ka, iters);
+                       (const T *)f, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
 
 int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin, void *uout, const SmoothArgs &a,
                   int *iters, hipStream_t s) {
+  if (a.zh && (a.zero_guess || !a.defect)) {
+    set_error("a P0 correction needs a smoothed input");
+    return DG_EINVAL;
+  }
   if (a.inner == DG_INNER_GMRES && (a.restart < 1 || a.restart > kGmresMax)) {
     set_error("inner GMRES restart must be in 1..16");
     return DG_EINVAL;

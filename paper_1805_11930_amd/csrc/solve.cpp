@@ -18,37 +18,26 @@
 #include "dg_internal.h"
 #include "vec.h"
 
-namespace dgmg {
-int alloc_tmp(dg_problem *pr, int prec, int k, void **out);
-int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, double rnorm, float *r32,
-                  float *z32, hipStream_t s);
-}  // namespace dgmg
+#include "solve_common.h"
 
 using namespace dgmg;
 
-namespace {
+namespace dgmg {
+int solve_cg_batched(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, dg_solve_result *res,
+                     hipStream_t s);
 
-struct DevBuf {
-  std::vector<void *> ptrs;
-  size_t bytes = 0;
-  ~DevBuf() {
-    for (void *p : ptrs) (void)hipFree(p);
+int validate_solve_opts(const dg_solve_opts *o) {
+  if (o->krylov < DG_KRYLOV_CG || o->krylov > DG_KRYLOV_FGMRES || o->precond < DG_PRECOND_NONE ||
+      o->precond > DG_PRECOND_MG || (o->precond_precision != DG_FP64 && o->precond_precision != DG_FP32) ||
+      !(o->rtol > 0) || o->maxit < 1) {
+    set_error("invalid solve options");
+    return DG_EINVAL;
   }
-  template <typename T>
-  int get(T **out, size_t n) {
-    void *p = nullptr;
-    hipError_t e = hipMalloc(&p, n * sizeof(T));
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc (solve workspace)");
-    ptrs.push_back(p);
-    bytes += n * sizeof(T);
-    *out = (T *)p;
-    return DG_OK;
-  }
-};
-
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  return DG_OK;
 }
+}  // namespace dgmg
+
+namespace {
 
 struct Ctx {
   dg_problem *pr;
@@ -109,71 +98,6 @@ int residual(Ctx &c, const double *f, const double *u, double *r, double *tmp) {
   int rc = timed_apply(c, u, tmp);
   if (rc) return rc;
   return sub(c.n, f, tmp, r, c.s);
-}
-
-int solve_cg(Ctx &c, const double *f, double *u, dg_solve_result *res, DevBuf &wb, double r0) {
-  const bool flex = c.o->krylov == DG_KRYLOV_FCG;
-  double *r, *p, *q, *z, *rold = nullptr;
-  int rc;
-  if ((rc = wb.get(&r, c.n)) || (rc = wb.get(&p, c.n)) || (rc = wb.get(&q, c.n)) || (rc = wb.get(&z, c.n)))
-    return rc;
-  if (flex && (rc = wb.get(&rold, c.n))) return rc;
-  if ((rc = residual(c, f, u, r, q))) return rc;
-  double rnorm = r0;
-  if ((rc = timed_precond(c, r, z, rnorm))) return rc;
-  double rz;
-  if ((rc = host_dot(c, r, z, &rz))) return rc;
-  DG_HIP(hipMemcpyAsync(p, z, c.n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
-  int it = 0;
-  res->status = DG_ENOCONV;
-  while (it < c.o->maxit) {
-    if ((rc = timed_apply(c, p, q))) return rc;
-    double pq;
-    if ((rc = host_dot(c, p, q, &pq))) return rc;
-    if (!(pq > 0) || !std::isfinite(pq) || !std::isfinite(rz)) {
-      res->status = DG_EBREAKDOWN;
-      set_error("CG breakdown: p^T A p <= 0 or not finite");
-      break;
-    }
-    const double alpha = rz / pq;
-    if (flex) DG_HIP(hipMemcpyAsync(rold, r, c.n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
-    if ((rc = cg_update(c.n, alpha, p, q, u, r, c.s))) return rc;
-    ++it;
-    double rr;
-    if ((rc = host_dot(c, r, r, &rr))) return rc;
-    rnorm = std::sqrt(rr);
-    if (!std::isfinite(rnorm)) {
-      res->status = DG_EBREAKDOWN;
-      set_error("non-finite residual");
-      break;
-    }
-    if (rnorm <= c.o->rtol * r0) {
-      res->status = DG_OK;
-      break;
-    }
-    if ((rc = timed_precond(c, r, z, rnorm))) return rc;
-    double beta;
-    if (flex) {
-      DotSet ds;
-      ds.m = 2;
-      ds.a[0] = z;
-      ds.b[0] = r;
-      ds.a[1] = z;
-      ds.b[1] = rold;
-      double v[2];
-      if ((rc = host_dots(c, ds, v))) return rc;
-      beta = (v[0] - v[1]) / rz;
-      rz = v[0];
-    } else {
-      double zr;
-      if ((rc = host_dot(c, z, r, &zr))) return rc;
-      beta = zr / rz;
-      rz = zr;
-    }
-    if ((rc = axpby(c.n, 1.0, z, beta, p, c.s))) return rc;
-  }
-  res->iters = it;
-  return DG_OK;
 }
 
 int solve_fgmres(Ctx &c, const double *f, double *u, dg_solve_result *res, DevBuf &wb, double r0) {
@@ -283,16 +207,13 @@ extern "C" int dg_solve(dg_problem *pr, const double *f, double *u, const dg_sol
     set_error("dg_solve: NULL argument");
     return DG_EINVAL;
   }
-  if (o->krylov < DG_KRYLOV_CG || o->krylov > DG_KRYLOV_FGMRES || o->precond < DG_PRECOND_NONE ||
-      o->precond > DG_PRECOND_MG || (o->precond_precision != DG_FP64 && o->precond_precision != DG_FP32) ||
-      !(o->rtol > 0) || o->maxit < 1) {
-    set_error("dg_solve: invalid options");
-    return DG_EINVAL;
-  }
+  int rc = validate_solve_opts(o);
+  if (rc) return rc;
   dg_solve_result tmp;
   if (!res) res = &tmp;
   std::memset(res, 0, sizeof(*res));
   hipStream_t s = (hipStream_t)stream;
+  if (o->krylov != DG_KRYLOV_FGMRES) return solve_cg_batched(pr, f, u, o, res, s);
   const double t0 = now_s();
   DevBuf wb;
   Ctx c;
@@ -300,7 +221,6 @@ extern "C" int dg_solve(dg_problem *pr, const double *f, double *u, const dg_sol
   c.o = o;
   c.s = s;
   c.n = pr->ndof;
-  int rc;
   struct Events {
     hipEvent_t a = nullptr, b = nullptr;
     ~Events() {
@@ -319,9 +239,7 @@ extern "C" int dg_solve(dg_problem *pr, const double *f, double *u, const dg_sol
   // preconditioner temporaries are allocated here so that the solve phase
   // measures no allocation
   void *dummy;
-  const int pp = o->precond_precision;
-  if (o->precond == DG_PRECOND_MG && ((rc = alloc_tmp(pr, pp, 0, &dummy)) || (rc = alloc_tmp(pr, pp, 1, &dummy))))
-    return rc;
+  if (o->precond == DG_PRECOND_MG && (rc = alloc_tmp(pr, o->precond_precision, 0, &dummy))) return rc;
   double *r, *t;
   if ((rc = wb.get(&r, c.n)) || (rc = wb.get(&t, c.n))) return rc;
   DG_HIP(hipStreamSynchronize(s));
@@ -337,12 +255,9 @@ extern "C" int dg_solve(dg_problem *pr, const double *f, double *u, const dg_sol
   }
   if (r0 == 0.0) {
     res->status = DG_OK;
-  } else if (o->krylov == DG_KRYLOV_FGMRES) {
-    rc = solve_fgmres(c, f, u, res, wb, r0);
-  } else {
-    rc = solve_cg(c, f, u, res, wb, r0);
+  } else if ((rc = solve_fgmres(c, f, u, res, wb, r0))) {
+    return rc;
   }
-  if (rc) return rc;
   // true FP64 residual
   if ((rc = residual(c, f, u, r, t))) return rc;
   double rr;

@@ -1,0 +1,43 @@
+// Helpers shared by the outer solvers (solve.cpp, batch.cpp).
+#pragma once
+
+#include <chrono>
+#include <vector>
+
+#include "dg_internal.h"
+
+namespace dgmg {
+
+int alloc_tmp(dg_problem *pr, int prec, int k, void **out);
+int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, double rnorm, float *r32,
+                  float *z32, hipStream_t s);
+
+// Device allocations owned by one solve; freed together.
+struct DevBuf {
+  std::vector<void *> ptrs;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  int get(T **out, size_t n) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (solve workspace)");
+    ptrs.push_back(p);
+    bytes += n * sizeof(T);
+    *out = (T *)p;
+    return DG_OK;
+  }
+};
+
+inline double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int validate_solve_opts(const dg_solve_opts *o);
+
+}  // namespace dgmg

@@ -20,7 +20,8 @@ struct DotSet {
 int dots(const DotSet &ds, int64_t n, double *part, double *out_dev, hipStream_t s);
 int axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
 int sub(int64_t n, const double *x, const double *y, double *z, hipStream_t s);
-int cg_update(int64_t n, double a, const double *p, const double *q, double *x, double *r, hipStream_t s);
+int cg_update(int64_t n, double a, const double *p, const double *q, double *x, const double *r_in, double *r_out,
+              hipStream_t s);
 int cast_d2f(int64_t n, double sc, const double *x, float *y, hipStream_t s);
 int cast_f2d(int64_t n, double sc, const float *x, double *y, hipStream_t s);
 

@@ -79,13 +79,13 @@ __global__ void k_sub(int64_t n, const double *__restrict__ x, const double *__r
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) z[i] = x[i] - y[i];
 }
-// x += a p ; r -= a q
+// x += a p ; r_out = r_in - a q   (r_out may be r_in)
 __global__ void k_cg_update(int64_t n, double a, const double *__restrict__ p, const double *__restrict__ q,
-                            double *__restrict__ x, double *__restrict__ r) {
+                            double *__restrict__ x, const double *r_in, double *r_out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     x[i] += a * p[i];
-    r[i] -= a * q[i];
+    r_out[i] = r_in[i] - a * q[i];
   }
 }
 template <typename S, typename D>
@@ -106,8 +106,9 @@ int sub(int64_t n, const double *x, const double *y, double *z, hipStream_t s) {
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
-int cg_update(int64_t n, double a, const double *p, const double *q, double *x, double *r, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update, grid1(n), dim3(256), 0, s, n, a, p, q, x, r);
+int cg_update(int64_t n, double a, const double *p, const double *q, double *x, const double *r_in, double *r_out,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update, grid1(n), dim3(256), 0, s, n, a, p, q, x, r_in, r_out);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
@@ -226,14 +227,18 @@ __global__ void k_coarse_prolong(int nx, int ny, int nz, int cnx, int cny, const
   x[i] += xc[(ix >> 1) + cnx * ((iy >> 1) + cny * (iz >> 1))];
 }
 
-// x = Ainv r, dense (n <= a few hundred): one block, rows strided
+// x = Ainv r, dense (n <= 512): one wavefront per row, coalesced row reads
 template <typename T>
-__global__ void k_dense_mv(int n, const T *__restrict__ Ainv, const T *__restrict__ r, T *__restrict__ x) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    T s = T(0);
-    for (int j = 0; j < n; ++j) s += Ainv[(size_t)i * n + j] * r[j];
-    x[i] = s;
-  }
+__global__ __launch_bounds__(256) void k_dense_mv(int n, const T *__restrict__ Ainv, const T *__restrict__ r,
+                                                  T *__restrict__ x) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;  // uniform per wavefront
+  T s = T(0);
+  for (int j = lane; j < n; j += 64) s += Ainv[(size_t)row * n + j] * r[j];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+  if (lane == 0) x[row] = s;
 }
 
 template <typename T>
@@ -261,7 +266,7 @@ int coarse_prolong(int nx, int ny, int nz, int cnx, int cny, const T *xc, T *x, 
 }
 template <typename T>
 int dense_mv(int n, const T *Ainv, const T *r, T *x, hipStream_t s) {
-  hipLaunchKernelGGL((k_dense_mv<T>), dim3((n + 63) / 64), dim3(64), 0, s, n, Ainv, r, x);
+  hipLaunchKernelGGL((k_dense_mv<T>), dim3((n + 3) / 4), dim3(256), 0, s, n, Ainv, r, x);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

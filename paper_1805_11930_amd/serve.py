@@ -1,0 +1,163 @@
+"""Continuous-batching solve server over the libdgmg resident-solve calls.
+
+Requests (a problem description and a right-hand side) arrive over time.
+The loop admits waiting requests, first come first served, as long as the
+device bytes they need (dg_footprint plus their f and u vectors) fit in
+the HBM budget and a slot is free; it then advances every active solve by
+one outer iteration with one dg_batch_step call (their kernels overlap on
+the device, each on its own stream), retires finished solves (freeing
+their memory) and admits again.  A request whose footprint exceeds the
+whole budget is rejected (DG_ENOMEM).  All numerical work runs in the HIP
+library; this module only schedules.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .problem import Problem
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float            # seconds after the start of the run
+    spec: L.ProblemSpec
+    rhs: np.ndarray           # DG load vector (FP64)
+    # filled by the server
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    status: int = L.DG_EAGAIN
+    iters: int = 0
+    rel_residual: float = float("nan")
+    solution: np.ndarray | None = field(default=None, repr=False)
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class _Active:
+    def __init__(self, req: Request, prob: Problem, f: torch.Tensor, u: torch.Tensor, state: ctypes.c_void_p,
+                 nbytes: int):
+        self.req, self.prob, self.f, self.u, self.state, self.nbytes = req, prob, f, u, state, nbytes
+
+
+class SolveServer:
+    def __init__(self, opts: L.SolveOpts, hbm_budget: int | None = None, max_active: int = 32,
+                 keep_solutions: bool = False):
+        self.lib = L.load()
+        self.opts = opts
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget = int(0.8 * free)
+        self.budget = int(hbm_budget)
+        self.max_active = max_active
+        self.keep = keep_solutions
+
+    def footprint(self, req: Request) -> int:
+        ndof = int(np.prod(req.spec.cells)) * (req.spec.p + 1) ** 3
+        return L.footprint(req.spec, self.opts) + 2 * 8 * ndof
+
+    def _admit(self, req: Request, now: float) -> _Active:
+        prob = Problem(req.spec)
+        f = torch.from_numpy(np.ascontiguousarray(req.rhs, dtype=np.float64)).cuda()
+        u = torch.zeros_like(f)
+        torch.cuda.synchronize()
+        st = ctypes.c_void_p()
+        L._check(self.lib.dg_solve_start(prob.h, f.data_ptr(), u.data_ptr(), ctypes.byref(self.opts), ctypes.byref(st)))
+        req.admitted = now
+        return _Active(req, prob, f, u, st, self.footprint(req))
+
+    def _retire(self, a: _Active, now: float):
+        res = L.SolveResult()
+        L._check(self.lib.dg_solve_poll(a.state, ctypes.byref(res)))
+        a.req.finished = now
+        a.req.status = res.status
+        a.req.iters = res.iters
+        a.req.rel_residual = res.rel_residual
+        if self.keep:
+            a.req.solution = a.u.cpu().numpy()
+        self.lib.dg_solve_state_destroy(a.state)
+        a.prob.close()
+
+    def run(self, requests: list[Request], log=None) -> dict:
+        pending = sorted(requests, key=lambda r: r.arrival)
+        queue: list[Request] = []
+        active: list[_Active] = []
+        used = 0
+        steps = 0
+        peak_active = 0
+        t0 = time.perf_counter()
+        while pending or queue or active:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.pop(0))
+            # admission by HBM footprint, first come first served
+            while queue and len(active) < self.max_active:
+                req = queue[0]
+                need = self.footprint(req)
+                if need > self.budget:
+                    queue.pop(0)
+                    req.status = L.DG_ENOMEM
+                    req.finished = now
+                    continue
+                if used + need > self.budget:
+                    break
+                queue.pop(0)
+                active.append(self._admit(req, time.perf_counter() - t0))
+                used += need
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
+                continue
+            peak_active = max(peak_active, len(active))
+            arr = (ctypes.c_void_p * len(active))(*[a.state.value for a in active])
+            L._check(self.lib.dg_batch_step(arr, len(active), None))
+            steps += 1
+            now = time.perf_counter() - t0
+            still = []
+            for a in active:
+                if self.lib.dg_solve_poll(a.state, None) == L.DG_EAGAIN:
+                    still.append(a)
+                else:
+                    self._retire(a, now)
+                    used -= a.nbytes
+            active = still
+        makespan = time.perf_counter() - t0
+        done = [r for r in requests if r.status in (L.DG_OK, L.DG_ENOCONV)]
+        lat = np.array([r.latency for r in done])
+        return {
+            "requests": len(requests),
+            "completed": len(done),
+            "converged": sum(r.status == L.DG_OK for r in requests),
+            "rejected": sum(r.status == L.DG_ENOMEM for r in requests),
+            "makespan_s": makespan,
+            "solves_per_s": len(done) / makespan if makespan > 0 else 0.0,
+            "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
+            "batch_steps": steps,
+            "peak_active": peak_active,
+        }
+
+
+def make_requests(mix, rate: float | None, seed: int = 55) -> list[Request]:
+    """Requests for a list of (N, p, seed) from inputs.w5_requests; arrivals
+    form a Poisson process of the given rate (None: all at time 0)."""
+    from . import inputs
+
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i, (N, p, s) in enumerate(mix):
+        if rate:
+            t += rng.exponential(1.0 / rate)
+        w, rhs = inputs.w5_problem(N, p, s)
+        spec = L.ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c)
+        out.append(Request(i, t if rate else 0.0, spec, rhs))
+    return out

@@ -1,0 +1,126 @@
+"""Resident solves and continuous batching (through the C ABI).
+
+  * a resident solve stepped alone equals dg_solve bit for bit;
+  * each request's solution is bit-identical alone and inside a mixed
+    batch of different sizes and degrees, and every request reaches the
+    requested relative residual (checked against the oracle's matrix for
+    the smallest request);
+  * admission honours the HBM budget: a request larger than the budget is
+    rejected, the rest queue and complete;
+  * FGMRES cannot be resident (DG_EINVAL).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import dg
+from paper_1805_11930_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+
+
+MIX = [(4, 2, 7001), (6, 3, 7002), (5, 4, 7003), (8, 2, 7004), (4, 3, 7005), (6, 2, 7006)]
+
+
+def _opts(prec):
+    from paper_1805_11930_amd import DG_KRYLOV_FCG, DG_PRECOND_MG, solve_opts
+
+    return solve_opts(krylov=DG_KRYLOV_FCG, precond=DG_PRECOND_MG, precond_precision=prec, rtol=1e-8, maxit=400)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_resident_equals_dg_solve(prec):
+    from paper_1805_11930_amd import _lib as L
+    from paper_1805_11930_amd.problem import Problem
+
+    print(f"resident vs dg_solve prec={prec}", flush=True)
+    w, rhs = inputs.w5_problem(6, 3, 7100)
+    spec = L.ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, K=w.K)
+    P = Problem(spec)
+    f = torch.from_numpy(rhs).cuda()
+    u1, res1 = P.solve(f, opts=_opts(prec))
+    lib = L.load()
+    u2 = torch.zeros_like(f)
+    st = ctypes.c_void_p()
+    L._check(lib.dg_solve_start(P.h, f.data_ptr(), u2.data_ptr(), ctypes.byref(_opts(prec)), ctypes.byref(st)))
+    arr = (ctypes.c_void_p * 1)(st.value)
+    steps = 0
+    while lib.dg_solve_poll(st, None) == L.DG_EAGAIN:
+        L._check(lib.dg_batch_step(arr, 1, None))
+        steps += 1
+        assert steps < 500
+    res2 = L.SolveResult()
+    L._check(lib.dg_solve_poll(st, ctypes.byref(res2)))
+    lib.dg_solve_state_destroy(st)
+    assert res1.status == 0 and res2.status == 0
+    assert res1.iters == res2.iters == steps
+    assert torch.equal(u1, u2)
+    P.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_alone_vs_mixed_batch(prec):
+    from paper_1805_11930_amd.serve import SolveServer, make_requests
+
+    print(f"alone vs mixed prec={prec}", flush=True)
+    alone = []
+    for req in make_requests(MIX, None):
+        srv = SolveServer(_opts(prec), keep_solutions=True)
+        st = srv.run([req])
+        assert st["converged"] == 1
+        alone.append(req)
+    mixed = make_requests(MIX, None)
+    srv = SolveServer(_opts(prec), keep_solutions=True, max_active=8)
+    st = srv.run(mixed)
+    assert st["converged"] == len(MIX) and st["peak_active"] == len(MIX)
+    for a, m in zip(alone, mixed):
+        assert a.iters == m.iters
+        assert np.array_equal(a.solution, m.solution), a.rid
+        assert m.rel_residual <= 1e-8
+    # the smallest request against the oracle's matrix
+    w, rhs = inputs.w5_problem(*MIX[0])
+    opr = dg.Problem(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, K=w.K)
+    A = dg.assemble(opr)
+    r = rhs - A @ mixed[0].solution
+    assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(rhs)
+
+
+def test_admission_budget_and_rejection():
+    from paper_1805_11930_amd import _lib as L
+    from paper_1805_11930_amd.serve import SolveServer, make_requests
+
+    print("admission under a small HBM budget", flush=True)
+    reqs = make_requests([(4, 2, 7201), (4, 2, 7202), (4, 2, 7203), (8, 4, 7204)], rate=None)
+    srv = SolveServer(_opts(1), keep_solutions=False)
+    small = srv.footprint(reqs[0])
+    big = srv.footprint(reqs[3])
+    assert big > 2 * small
+    srv.budget = 2 * small + 1  # two small requests fit at a time, the big one never
+    st = srv.run(reqs)
+    assert st["rejected"] == 1 and reqs[3].status == L.DG_ENOMEM
+    assert st["converged"] == 3
+    assert st["peak_active"] == 2
+
+
+def test_fgmres_not_resident():
+    from paper_1805_11930_amd import DG_KRYLOV_FGMRES, _lib as L, solve_opts
+    from paper_1805_11930_amd.problem import Problem
+
+    w, rhs = inputs.w5_problem(4, 2, 7300)
+    P = Problem(L.ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, K=w.K))
+    f = torch.from_numpy(rhs).cuda()
+    u = torch.zeros_like(f)
+    st = ctypes.c_void_p()
+    rc = L.load().dg_solve_start(P.h, f.data_ptr(), u.data_ptr(), ctypes.byref(solve_opts(krylov=DG_KRYLOV_FGMRES)),
+                                 ctypes.byref(st))
+    assert rc == L.DG_EINVAL and not st.value
+    P.close()
