@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "DG apply GDOF/s + time-to-solve @1e-8 rel residual, FP64 vs mixed; p99 latency"
 HBM_PEAK_GBS = 8000.0
 APPLY_SOURCES = ["paper_1805_11930_amd/csrc/apply.hip", "paper_1805_11930_amd/csrc/line_ops.h"]
-COUNTERS = os.path.join(ROOT, "profiles", "apply_fp64_poisson32_p4_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "apply_fp64_poisson32_p4_counters.md")
 
 
 def log(msg: str) -> None:
@@ -97,6 +97,31 @@ def cpu_baseline(w, seconds: float = 12.0) -> dict:
     }
 
 
+def serving_leg(n_requests: int) -> dict:
+    """Serving mix W5: closed-loop FP64 throughput sets the arrival rate
+    (0.7 x solves/s); the same Poisson arrival trace (seed 55) is then
+    served with the FP64 and with the mixed-precision preconditioner."""
+    from paper_1805_11930_amd import DG_FP32, DG_FP64, DG_KRYLOV_FCG, DG_PRECOND_MG, inputs, solve_opts
+    from paper_1805_11930_amd.serve import SolveServer, make_requests
+
+    mix = inputs.w5_requests(n_requests)
+
+    def opts(prec):
+        return solve_opts(krylov=DG_KRYLOV_FCG, precond=DG_PRECOND_MG, precond_precision=prec, rtol=1e-8, maxit=500)
+
+    closed = SolveServer(opts(DG_FP64)).run(make_requests(mix, None))
+    rate = 0.7 * closed["solves_per_s"]
+    log(f"[bench] serving closed-loop FP64: {closed['solves_per_s']:.1f} solves/s -> arrival rate {rate:.1f}/s")
+    out = {"requests": n_requests, "arrival_rate_per_s": round(rate, 2),
+           "closed_loop_fp64_solves_per_s": round(closed["solves_per_s"], 2)}
+    for name, prec in (("fp64", DG_FP64), ("mixed", DG_FP32)):
+        st = SolveServer(opts(prec)).run(make_requests(mix, rate))
+        log(f"[bench] serving {name}: p50 {st['p50_latency_s'] * 1e3:.1f} ms, p99 {st['p99_latency_s'] * 1e3:.1f} ms, "
+            f"{st['solves_per_s']:.1f} solves/s, converged {st['converged']}/{st['requests']}")
+        out[name] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in st.items()}
+    return out
+
+
 def event_time(fn, reps: int) -> float:
     """Mean seconds per call of fn() on torch's current stream (HIP events)."""
     import torch
@@ -118,8 +143,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w3", "w4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=256, help="serving leg size (0 = skip)")
     ap.add_argument("--apply-only", type=int, default=0,
                     help="profiling aid: run this many FP64 applies and exit")
+    ap.add_argument("--copy-only", type=int, default=0,
+                    help="counter calibration: run this many 256 MiB device-to-device copies and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -133,6 +161,14 @@ def main() -> int:
                                       solve_opts)
 
     torch.cuda.set_device(0)
+    if args.copy_only:
+        src = torch.ones(64 * 2**20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.copy_only):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] ran {args.copy_only} copies of {src.numel() * 4} bytes")
+        return 0
     w = make_workload(args.workload)
     log(f"[bench] workload {w.name}: cells={w.cells} p={w.p} ndof={w.ndof}")
     P = Problem(ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c,
@@ -204,7 +240,10 @@ def main() -> int:
     traffic = None
     if os.path.exists(COUNTERS):
         with open(COUNTERS) as fh:
-            cnt = json.load(fh)
+            cnt = {}
+            for ln in fh:
+                if ln.startswith("counters-json:"):
+                    cnt = json.loads(ln.split(":", 1)[1])
         if cnt.get("source_hash") == apply_source_hash() and cnt.get("workload") == w.name:
             traffic = cnt.get("hbm_bytes_per_launch")
     line = {
@@ -252,6 +291,8 @@ def main() -> int:
             "apply_launches_timed": n_apply,
         },
     }
+    if args.serve_requests > 0:
+        line["serving"] = serving_leg(args.serve_requests)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
         line["cpu_baseline"] = cpu_baseline(w)

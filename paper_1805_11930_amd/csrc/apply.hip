@@ -18,6 +18,8 @@
 // the eight XCDs, so the logical block index is remapped to give every XCD
 // one contiguous slab of cells; the y and z neighbours a slab reads are then
 // mostly in that XCD's own L2.
+#include <type_traits>
+
 #include "line_ops.h"
 
 namespace dgmg {
@@ -43,26 +45,63 @@ __device__ __host__ inline int line_pos(int k, int i, int a, int b) {
   return k == 0 ? i + N * a + N * N * b : (k == 1 ? a + N * i + N * N * b : a + N * b + N * N * i);
 }
 
+// Stage ncb cells (contiguous in memory) into LDS with 16-byte loads.
+template <typename T>
+__device__ inline void stage_cells(const T *__restrict__ src, T *dst, int count, int tid) {
+  constexpr int V = 16 / sizeof(T);
+  if ((((uintptr_t)src) & 15) == 0) {
+    using VT = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    const int nv = count / V;
+    const VT *sv = reinterpret_cast<const VT *>(src);
+    VT *dv = reinterpret_cast<VT *>(dst);
+    for (int i = tid; i < nv; i += kApplyThreads) dv[i] = sv[i];
+    for (int i = nv * V + tid; i < count; i += kApplyThreads) dst[i] = src[i];
+  } else {
+    for (int i = tid; i < count; i += kApplyThreads) dst[i] = src[i];
+  }
+}
+
+// Two traces of the same line in a neighbour cell: w0 . line and w1 . line,
+// the line read from LDS when the neighbour is staged, else from global.
+template <typename T, int N>
+__device__ inline void neighbour_traces(bool in_lds, const T *lds_cell, const T *__restrict__ glob_cell, int k, int a,
+                                        int b, const T (&w0)[N], const T (&w1)[N], T &t0, T &t1) {
+  T x[N];
+  if (in_lds) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = lds_cell[line_pos<N>(k, i, a, b)];
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = glob_cell[line_pos<N>(k, i, a, b)];
+  }
+  t0 = T(0);
+  t1 = T(0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    t0 += w0[i] * x[i];
+    t1 += w1[i] * x[i];
+  }
+}
+
 // NB: with neighbour couplings (A) or without (D_T).
 // RES: instead of writing v = A u, write rh[c] = sum over the DOFs of cell c
 // of (r - A u): the residual followed by the P0 restriction R = P^T
 // (Sec. 2.2.2), fused so that A u never goes to memory.
 template <int P, typename T, bool NB, bool RES = false>
-__global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, DevTab<T, P + 1> tb, const T *__restrict__ u,
-                                                         T *__restrict__ v, const T *__restrict__ r = nullptr,
+__global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restrict__ u, T *__restrict__ v,
+                                                         const T *__restrict__ r = nullptr,
                                                          T *__restrict__ rh = nullptr) {
   constexpr int N = P + 1;
   using S = ApplyShape<N>;
+  constexpr DevTab<T, N> tb = make_ctab<T, N>();
   __shared__ T us[S::CPB * S::N3];
-  __shared__ T qy[S::CPB * S::N3];
-  __shared__ T qz[S::CPB * S::N3];
+  __shared__ T qs[S::CPB * S::N3];  // y, then y + z contributions
   __shared__ AxisCoef<T> fcs[S::CPB][3];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int c0 = blk * S::CPB;
   const int ncb = min(S::CPB, g.ncell - c0);
   const int tid = threadIdx.x;
-  const T *ub = u + (size_t)c0 * S::N3;
-  for (int idx = tid; idx < ncb * S::N3; idx += kApplyThreads) us[idx] = ub[idx];
+  stage_cells<T>(u + (size_t)c0 * S::N3, us, ncb * S::N3, tid);
   const int cl = tid / S::N2;
   const int ln = tid - cl * S::N2;
   const int a = ln % N, b = ln / N;
@@ -82,7 +121,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, DevTab<T, P + 1>
   const bool hasb = g.has_b != 0;
   const T vol = (T)g.vol;
   const T stan = tb.w[a] * tb.w[b];
-  T qx[N];
+  T qx[N], qz[N];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     if (active) {
@@ -93,48 +132,42 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, DevTab<T, P + 1>
       if (NB) {
         if (ijk[k] > 0) {
           const int cn = c - stride[k];
-          const T *src = (cn >= c0) ? us + (cn - c0) * S::N3 : u + (size_t)cn * S::N3;
-#pragma unroll
-          for (int i = 0; i < N; ++i) {
-            const T x = src[line_pos<N>(k, i, a, b)];
-            tLu += tb.e1[i] * x;
-            tLd += tb.d1[i] * x;
-          }
+          const bool lds = cn >= c0;
+          neighbour_traces<T, N>(lds, us + (lds ? cn - c0 : 0) * S::N3, u + (size_t)cn * S::N3, k, a, b, tb.e1,
+                                 tb.d1, tLu, tLd);
         }
         if (ijk[k] < nn[k] - 1) {
           const int cn = c + stride[k];
-          const T *src = (cn < c0 + ncb) ? us + (cn - c0) * S::N3 : u + (size_t)cn * S::N3;
-#pragma unroll
-          for (int i = 0; i < N; ++i) {
-            const T x = src[line_pos<N>(k, i, a, b)];
-            tRu += tb.e0[i] * x;
-            tRd += tb.d0[i] * x;
-          }
+          const bool lds = cn < c0 + ncb;
+          neighbour_traces<T, N>(lds, us + (lds ? cn - c0 : 0) * S::N3, u + (size_t)cn * S::N3, k, a, b, tb.e0,
+                                 tb.d0, tRu, tRd);
         }
       }
       LineConv<T> lc = {T(0), T(0), T(0), T(0)};
       if (hasb) lc = make_line_conv<T, N>(g, tb, k, ijk, a, b);
       const T cre = (k == 0 && g.has_c) ? (T)g.c[c] : T(0);
       line_apply<T, N>(tb, fcs[cl][k], stan, vol, cre, hasb, lc, ul, tLu, tLd, tRu, tRd, out);
-      if (k == 0) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) qx[i] = out[i];
-      } else {
-        T *Q = k == 1 ? qy : qz;
-#pragma unroll
-        for (int i = 0; i < N; ++i) Q[cl * S::N3 + line_pos<N>(k, i, a, b)] = out[i];
+      for (int i = 0; i < N; ++i) {
+        if (k == 0) qx[i] = out[i];
+        if (k == 1) qs[cl * S::N3 + line_pos<N>(1, i, a, b)] = out[i];
+        if (k == 2) qz[i] = out[i];
       }
     }
+  }
+  __syncthreads();
+  // z contributions: each DOF lies on exactly one z-line, so no two lanes
+  // update the same entry
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) qs[cl * S::N3 + line_pos<N>(2, i, a, b)] += qz[i];
   }
   __syncthreads();
   if (!RES) {
     if (active) {
       T *vb = v + (size_t)c * S::N3 + N * a + S::N2 * b;
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const int p = cl * S::N3 + line_pos<N>(0, i, a, b);
-        vb[i] = qx[i] + qy[p] + qz[p];
-      }
+      for (int i = 0; i < N; ++i) vb[i] = qx[i] + qs[cl * S::N3 + line_pos<N>(0, i, a, b)];
     }
   } else {
     __shared__ T part[S::CPB * S::N2];
@@ -142,10 +175,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, DevTab<T, P + 1>
       const T *rb = r + (size_t)c * S::N3 + N * a + S::N2 * b;
       T sum = T(0);
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const int p = cl * S::N3 + line_pos<N>(0, i, a, b);
-        sum += rb[i] - (qx[i] + qy[p] + qz[p]);
-      }
+      for (int i = 0; i < N; ++i) sum += rb[i] - (qx[i] + qs[cl * S::N3 + line_pos<N>(0, i, a, b)]);
       part[cl * S::N2 + ln] = sum;
     }
     __syncthreads();
@@ -159,8 +189,9 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, DevTab<T, P + 1>
 
 // diag(D_T): one lane per DOF.
 template <int P, typename T>
-__global__ __launch_bounds__(256) void k_block_diag(Geo g, DevTab<T, P + 1> tb, T *__restrict__ diag) {
+__global__ __launch_bounds__(256) void k_block_diag(Geo g, T *__restrict__ diag) {
   constexpr int N = P + 1, N2 = N * N, N3 = N * N * N;
+  constexpr DevTab<T, N> tb = make_ctab<T, N>();
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)g.ncell * N3) return;
   const int c = (int)(gid / N3);
@@ -186,9 +217,10 @@ __global__ __launch_bounds__(256) void k_block_diag(Geo g, DevTab<T, P + 1> tb, 
 // Neumann flux -(j, psi_i)_F and on Dirichlet faces
 // -(Phi(0,g,b_nu), psi_i)_F - (nu.K grad psi_i, g)_F + gamma_F (g, psi_i)_F.
 template <int P>
-__global__ __launch_bounds__(256) void k_rhs(Geo g, DevTab<double, P + 1> tb, const double *__restrict__ fq,
-                                             const double *__restrict__ bq, double *__restrict__ rhs) {
+__global__ __launch_bounds__(256) void k_rhs(Geo g, const double *__restrict__ fq, const double *__restrict__ bq,
+                                             double *__restrict__ rhs) {
   constexpr int N = P + 1, N2 = N * N, N3 = N * N * N;
+  constexpr DevTab<double, N> tb = make_ctab<double, N>();
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)g.ncell * N3) return;
   const int c = (int)(gid / N3);
@@ -240,12 +272,12 @@ template <int P, typename T>
 static int launch_apply_t(const dg_problem *pr, const void *u, void *v, hipStream_t s, bool nb) {
   constexpr int N = P + 1;
   const int G = (int)((pr->ncell + ApplyShape<N>::CPB - 1) / ApplyShape<N>::CPB);
-  DevTab<T, N> tb = make_devtab<T, N>(pr->tab);
   if (nb)
-    hipLaunchKernelGGL((k_apply<P, T, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, tb, (const T *)u, (T *)v);
+    hipLaunchKernelGGL((k_apply<P, T, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u, (T *)v,
+                       (const T *)nullptr, (T *)nullptr);
   else
-    hipLaunchKernelGGL((k_apply<P, T, false>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, tb, (const T *)u,
-                       (T *)v);
+    hipLaunchKernelGGL((k_apply<P, T, false>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u, (T *)v,
+                       (const T *)nullptr, (T *)nullptr);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
@@ -266,8 +298,7 @@ template <int P, typename T>
 static int launch_res_t(const dg_problem *pr, const void *u, const void *r, void *rh, hipStream_t s) {
   constexpr int N = P + 1;
   const int G = (int)((pr->ncell + ApplyShape<N>::CPB - 1) / ApplyShape<N>::CPB);
-  DevTab<T, N> tb = make_devtab<T, N>(pr->tab);
-  hipLaunchKernelGGL((k_apply<P, T, true, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, tb, (const T *)u,
+  hipLaunchKernelGGL((k_apply<P, T, true, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u,
                      (T *)nullptr, (const T *)r, (T *)rh);
   DG_HIP(hipGetLastError());
   return DG_OK;
@@ -298,8 +329,7 @@ static int launch_diag_t(const dg_problem *pr, void *diag, hipStream_t s) {
   constexpr int N = P + 1;
   const int64_t tot = pr->ndof;
   const int G = (int)((tot + 255) / 256);
-  DevTab<T, N> tb = make_devtab<T, N>(pr->tab);
-  hipLaunchKernelGGL((k_block_diag<P, T>), dim3(G), dim3(256), 0, s, pr->geo, tb, (T *)diag);
+  hipLaunchKernelGGL((k_block_diag<P, T>), dim3(G), dim3(256), 0, s, pr->geo, (T *)diag);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
@@ -319,8 +349,7 @@ template <int P>
 static int launch_rhs_t(const dg_problem *pr, const double *fq, const double *bq, double *rhs, hipStream_t s) {
   constexpr int N = P + 1;
   const int G = (int)((pr->ndof + 255) / 256);
-  DevTab<double, N> tb = make_devtab<double, N>(pr->tab);
-  hipLaunchKernelGGL((k_rhs<P>), dim3(G), dim3(256), 0, s, pr->geo, tb, fq, bq, rhs);
+  hipLaunchKernelGGL((k_rhs<P>), dim3(G), dim3(256), 0, s, pr->geo, fq, bq, rhs);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

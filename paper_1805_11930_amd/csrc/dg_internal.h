@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/dgmg.h"
+#include "ctables.h"
 
 namespace dgmg {
 
@@ -28,17 +29,19 @@ struct Tables1D {
 };
 void build_tables(int n, Tables1D &t);
 
-// Kernel-side copy of the tables in the compute precision.  N is fixed at
-// compile time; every loop over it unrolls.
+// Kernel-side copy of the tables in the compute precision, built at compile
+// time from the constexpr tables (ctables.h); inside kernels every entry is
+// a literal.  N is fixed at compile time; every loop over it unrolls.
 template <typename T, int N>
 struct DevTab {
-  T S[N][N];   // D^T diag(w) D
-  T Dt[N][N];  // Dt[i][q] = D[q][i]
-  T w[N], xi[N], e0[N], e1[N], d0[N], d1[N];
+  T S[N][N] = {};   // D^T diag(w) D
+  T Dt[N][N] = {};  // Dt[i][q] = D[q][i]
+  T w[N] = {}, xi[N] = {}, e0[N] = {}, e1[N] = {}, d0[N] = {}, d1[N] = {};
 };
 
 template <typename T, int N>
-DevTab<T, N> make_devtab(const Tables1D &t) {
+constexpr DevTab<T, N> make_ctab() {
+  constexpr ct::Tab<N> t = ct::make_tab<N>();
   DevTab<T, N> d;
   for (int i = 0; i < N; ++i) {
     for (int j = 0; j < N; ++j) {

@@ -166,7 +166,7 @@ static int upload_level(dg_problem *pr, CoarseLevel &L, const std::vector<double
   return DG_OK;
 }
 
-constexpr int kBottomMax = 512;
+constexpr int kBottomMax = 128;
 
 static int build_coarse(dg_problem *pr, const std::vector<double> &K, const std::vector<double> &cc) {
   std::vector<double> A;

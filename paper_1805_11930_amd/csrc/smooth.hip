@@ -102,13 +102,14 @@ __device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1
 }
 
 template <int P, int INNER, typename T>
-__global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, DevTab<T, P + 1> tb, const T *__restrict__ f,
+__global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__restrict__ f,
                                                            const T *__restrict__ uin, T *__restrict__ uout,
                                                            SmoothKArgs sa, int *__restrict__ iters,
                                                            const T *__restrict__ zh) {
   constexpr int N = P + 1;
   using S = SmoothShape<N>;
   constexpr int L = S::L;
+  constexpr DevTab<T, N> tb = make_ctab<T, N>();
   __shared__ T Ps_all[S::CPW * S::N3];
   __shared__ T Qy_all[S::CPW * S::N3];
   __shared__ T Qz_all[S::CPW * S::N3];
@@ -470,7 +471,6 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
   constexpr int N = P + 1;
   using Sh = SmoothShape<N>;
   const int G = (int)((pr->ncell + Sh::CPW - 1) / Sh::CPW);
-  DevTab<T, N> tb = make_devtab<T, N>(pr->tab);
   SmoothKArgs ka;
   ka.omega = a.omega;
   ka.eps = a.eps;
@@ -480,10 +480,10 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
   ka.write_du = a.write_du;
   ka.defect = a.defect;
   if (a.inner == DG_INNER_CG)
-    hipLaunchKernelGGL((k_smooth<P, DG_INNER_CG, T>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo, tb,
+    hipLaunchKernelGGL((k_smooth<P, DG_INNER_CG, T>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo,
                        (const T *)f, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh);
   else
-    hipLaunchKernelGGL((k_smooth<P, DG_INNER_GMRES, T>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo, tb,
+    hipLaunchKernelGGL((k_smooth<P, DG_INNER_GMRES, T>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo,
                        (const T *)f, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh);
   DG_HIP(hipGetLastError());
   return DG_OK;
