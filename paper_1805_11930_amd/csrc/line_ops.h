@@ -213,4 +213,23 @@ __host__ __device__ inline T line_diag(const DevTab<T, N> &tb, const AxisCoef<T>
   return d;
 }
 
+// Entry (i, l) of the 1-D block operator along one axis for b = 0, without
+// the tangential weight factor: the line part of D_T is stan * M u with
+//   M = vol [ d/h^2 S + (1/h) (face at xi=1) + (1/h) (face at xi=0) ]
+//       (+ c vol diag(w) on the axis that carries the reaction),
+// i.e. line_apply with zero neighbour traces written as a matrix.  D_T is
+// then the Kronecker sum  Mx (x) Wy (x) Wz + Wx (x) My (x) Wz + Wx (x) Wy (x) Mz
+// with W = diag(w).
+template <typename T, int N>
+__host__ __device__ inline T line_matrix_entry(const DevTab<T, N> &tb, const AxisCoef<T> &f, T vol, T cre, int i,
+                                               int l) {
+  const T ih = f.ih;
+  T m = f.d * ih * ih * tb.S[i][l];
+  if (f.fl & 2) m += ih * (tb.e1[i] * (f.gR * tb.e1[l] - f.kR * ih * tb.d1[l]) - f.kR * ih * tb.d1[i] * tb.e1[l]);
+  if (f.fl & 1) m += ih * (tb.e0[i] * (f.gL * tb.e0[l] + f.kL * ih * tb.d0[l]) + f.kL * ih * tb.d0[i] * tb.e0[l]);
+  m *= vol;
+  if (i == l) m += cre * vol * tb.w[i];
+  return m;
+}
+
 }  // namespace dgmg

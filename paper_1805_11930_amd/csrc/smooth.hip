@@ -71,14 +71,32 @@ struct CellLines {
   T stan, vol, cre;
 };
 
+// stan * (M u) with the cell's per-axis matrix M held in LDS (b = 0)
+template <typename T, int N>
+__device__ inline void mat_line(const T *M, T stan, const T (&u)[N], T (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) acc += M[i * N + l] * u[l];
+    v[i] = stan * acc;
+  }
+}
+
 // q = D_T p on the lane's x-line.  All lanes of the wavefront must call it.
+// Ms: the cell's three axis matrices (b = 0), or nullptr (generic path).
 template <int P, typename T>
 __device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1> &tb, bool on, bool hasb,
-                                const T (&p)[P + 1], T (&q)[P + 1], T *Ps, T *Qy, T *Qz, int a, int b) {
+                                const T *Ms, const T (&p)[P + 1], T (&q)[P + 1], T *Ps, T *Qy, T *Qz, int a,
+                                int b) {
   constexpr int N = P + 1;
+  constexpr int N2 = N * N;
   T qx[N];
   if (on) {
-    line_apply<T, N>(tb, cl.f[0], cl.stan, cl.vol, cl.cre, hasb, cl.lc[0], p, T(0), T(0), T(0), T(0), qx);
+    if (Ms)
+      mat_line<T, N>(Ms, cl.stan, p, qx);
+    else
+      line_apply<T, N>(tb, cl.f[0], cl.stan, cl.vol, cl.cre, hasb, cl.lc[0], p, T(0), T(0), T(0), T(0), qx);
 #pragma unroll
     for (int i = 0; i < N; ++i) Ps[lpos<N>(0, i, a, b)] = p[i];
   }
@@ -87,12 +105,18 @@ __device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1
     T yl[N], yo[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) yl[i] = Ps[lpos<N>(1, i, a, b)];
-    line_apply<T, N>(tb, cl.f[1], cl.stan, cl.vol, T(0), hasb, cl.lc[1], yl, T(0), T(0), T(0), T(0), yo);
+    if (Ms)
+      mat_line<T, N>(Ms + N2, cl.stan, yl, yo);
+    else
+      line_apply<T, N>(tb, cl.f[1], cl.stan, cl.vol, T(0), hasb, cl.lc[1], yl, T(0), T(0), T(0), T(0), yo);
 #pragma unroll
     for (int i = 0; i < N; ++i) Qy[lpos<N>(1, i, a, b)] = yo[i];
 #pragma unroll
     for (int i = 0; i < N; ++i) yl[i] = Ps[lpos<N>(2, i, a, b)];
-    line_apply<T, N>(tb, cl.f[2], cl.stan, cl.vol, T(0), hasb, cl.lc[2], yl, T(0), T(0), T(0), T(0), yo);
+    if (Ms)
+      mat_line<T, N>(Ms + 2 * N2, cl.stan, yl, yo);
+    else
+      line_apply<T, N>(tb, cl.f[2], cl.stan, cl.vol, T(0), hasb, cl.lc[2], yl, T(0), T(0), T(0), T(0), yo);
 #pragma unroll
     for (int i = 0; i < N; ++i) Qz[lpos<N>(2, i, a, b)] = yo[i];
   }
@@ -101,7 +125,9 @@ __device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1
   for (int i = 0; i < N; ++i) q[i] = on ? qx[i] + Qy[lpos<N>(0, i, a, b)] + Qz[lpos<N>(0, i, a, b)] : T(0);
 }
 
-template <int P, int INNER, typename T>
+// HASB: advection present (compile-time, so the b = 0 kernels carry no
+// advection code and keep only the per-cell matrices live in the loop).
+template <int P, int INNER, typename T, bool HASB>
 __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__restrict__ f,
                                                            const T *__restrict__ uin, T *__restrict__ uout,
                                                            SmoothKArgs sa, int *__restrict__ iters,
@@ -113,6 +139,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   __shared__ T Ps_all[S::CPW * S::N3];
   __shared__ T Qy_all[S::CPW * S::N3];
   __shared__ T Qz_all[S::CPW * S::N3];
+  __shared__ T Ms_all[S::CPW * 3 * S::N2];  // per-cell axis matrices (b = 0)
   // GMRES storage: Krylov basis (lane-private x-lines) and the rotated
   // Hessenberg columns of each cell.
   __shared__ T Vs_all[INNER == DG_INNER_GMRES ? S::CPW * (kGmresMax + 1) * S::N3 : 1];
@@ -128,7 +155,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   T *Ps = Ps_all + cw * S::N3;
   T *Qy = Qy_all + cw * S::N3;
   T *Qz = Qz_all + cw * S::N3;
-  const bool hasb = g.has_b != 0;
+  constexpr bool hasb = HASB;
 
   int ijk[3] = {0, 0, 0};
   CellLines<P, T> cl;
@@ -147,6 +174,15 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
     }
   }
   const size_t base = (size_t)c * S::N3;
+  // for b = 0 each axis of D_T is one n x n matrix per cell: lane (a, b)
+  // builds entry (a, b) of the three matrices once
+  T *Ms = HASB ? nullptr : Ms_all + cw * 3 * S::N2;
+  if (Ms && on) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      Ms[k * S::N2 + a * N + b] = line_matrix_entry<T, N>(tb, cl.f[k], cl.vol, k == 0 ? cl.cre : T(0), a, b);
+  }
+  __syncthreads();
 
   // ---- defect d = f - A u -------------------------------------------------
   T ul[N], d[N];
@@ -221,7 +257,11 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     T dd = T(1);
-    if (on) {
+    if (on && Ms) {
+      // DOF (i, a, b): x-line (a, b), y-line (x=i, z=b), z-line (x=i, y=a)
+      dd = tb.w[a] * tb.w[b] * Ms[i * N + i] + tb.w[i] * tb.w[b] * Ms[S::N2 + a * N + a] +
+           tb.w[i] * tb.w[a] * Ms[2 * S::N2 + b * N + b];
+    } else if (on) {
       // DOF (i, a, b) lies on the x-line (a, b), the y-line (x=i, z=b) and
       // the z-line (x=i, y=a)
       const LineConv<T> zero = {T(0), T(0), T(0), T(0)};
@@ -262,7 +302,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
     while (true) {
       const bool act = !conv && it < sa.max_inner;
       if (__ballot(act) == 0) break;
-      dt_apply<P, T>(cl, tb, on, hasb, p, q, Ps, Qy, Qz, a, b);
+      dt_apply<P, T>(cl, tb, on, hasb, Ms, p, q, Ps, Qy, Qz, a, b);
       T pq = T(0);
 #pragma unroll
       for (int i = 0; i < N; ++i) pq += p[i] * q[i];
@@ -337,7 +377,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
         T vj[N], w[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) vj[i] = on ? Vs[j * S::N3 + my + i] * dinv[i] : T(0);
-        dt_apply<P, T>(cl, tb, on, hasb, vj, w, Ps, Qy, Qz, a, b);
+        dt_apply<P, T>(cl, tb, on, hasb, Ms, vj, w, Ps, Qy, Qz, a, b);
         if (cyc) ++it;
         T hcol[kGmresMax + 1];
 #pragma unroll
@@ -437,7 +477,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
       // restart: r = d - D_T x (all lanes take part in the transposes)
       if (__ballot(!done) != 0) {
         T dx[N];
-        dt_apply<P, T>(cl, tb, on, hasb, x, dx, Ps, Qy, Qz, a, b);
+        dt_apply<P, T>(cl, tb, on, hasb, Ms, x, dx, Ps, Qy, Qz, a, b);
         T rn = T(0);
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -479,12 +519,22 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
   ka.zero_guess = a.zero_guess;
   ka.write_du = a.write_du;
   ka.defect = a.defect;
-  if (a.inner == DG_INNER_CG)
-    hipLaunchKernelGGL((k_smooth<P, DG_INNER_CG, T>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo,
-                       (const T *)f, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh);
-  else
-    hipLaunchKernelGGL((k_smooth<P, DG_INNER_GMRES, T>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo,
-                       (const T *)f, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh);
+  const bool hb = pr->geo.has_b != 0;
+#define DG_SMOOTH_LAUNCH(INNER, HB)                                                                          \
+  hipLaunchKernelGGL((k_smooth<P, INNER, T, HB>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo, (const T *)f, \
+                     (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh)
+  if (a.inner == DG_INNER_CG) {
+    if (hb)
+      DG_SMOOTH_LAUNCH(DG_INNER_CG, true);
+    else
+      DG_SMOOTH_LAUNCH(DG_INNER_CG, false);
+  } else {
+    if (hb)
+      DG_SMOOTH_LAUNCH(DG_INNER_GMRES, true);
+    else
+      DG_SMOOTH_LAUNCH(DG_INNER_GMRES, false);
+  }
+#undef DG_SMOOTH_LAUNCH
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
