@@ -225,13 +225,115 @@ def p0_direct(prob: _dg.Problem) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# conforming Q1 subspace (Sec. 2.2.2, 2.2.3, App. A.2)
+# ---------------------------------------------------------------------------
+def q1_vertex_id(prob: _dg.Problem, vx, vy, vz) -> int:
+    nx, ny, _ = prob.cells
+    return vx + (nx + 1) * (vy + (ny + 1) * vz)
+
+
+def q1_nvert(prob: _dg.Problem) -> int:
+    nx, ny, nz = prob.cells
+    return (nx + 1) * (ny + 1) * (nz + 1)
+
+
+def q1_prolongation(prob: _dg.Problem) -> sp.csr_matrix:
+    """P with (P|_T)_ij = psi_hat_j(zeta_i): the trilinear vertex functions
+    evaluated at the DG nodes (the nodal interpolation of Sec. 2.2.2)."""
+    tab = _dg.Tables(prob)
+    xi = tab.nodes
+    n = prob.n
+    rows, cols, vals = [], [], []
+    for c in range(prob.ncell):
+        ix, iy, iz = prob.cell_ijk(c)
+        for kz in range(n):
+            for ky in range(n):
+                for kx in range(n):
+                    row = c * prob.nloc + kx + n * (ky + n * kz)
+                    for dz in (0, 1):
+                        for dy in (0, 1):
+                            for dx in (0, 1):
+                                wgt = ((xi[kx] if dx else 1 - xi[kx]) * (xi[ky] if dy else 1 - xi[ky])
+                                       * (xi[kz] if dz else 1 - xi[kz]))
+                                rows.append(row)
+                                cols.append(q1_vertex_id(prob, ix + dx, iy + dy, iz + dz))
+                                vals.append(wgt)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(prob.ndof, q1_nvert(prob)))
+
+
+def q1_galerkin(A, prob: _dg.Problem) -> np.ndarray:
+    """A_hat = P^T A P for the Q1 subspace, dense (nvert, nvert)."""
+    P = q1_prolongation(prob)
+    return np.asarray((P.T @ (A.tocsr() @ P)).todense())
+
+
+def q1_direct(prob: _dg.Problem) -> np.ndarray:
+    """A_hat_ij = a_h(psi_hat_j, psi_hat_i) evaluated directly on the
+    trilinear vertex functions (App. A.2): continuous functions have no
+    jumps, so only the volume terms and the Dirichlet-face terms of a_h
+    remain; same quadrature as A."""
+    tab = _dg.Tables(prob)
+    h = prob.h
+    xq, wq = tab.xq, tab.wq
+    # 1-D linear hats and derivatives at the quadrature points
+    L1 = np.stack([1 - xq, xq], axis=1)  # (m, 2)
+    D1 = np.stack([-np.ones_like(xq), np.ones_like(xq)], axis=1)
+    Phi = _dg.tensor_tab(L1, L1, L1)  # (Q, 8), corner index dx + 2dy + 4dz
+    G = [_dg.tensor_tab(D1 / h[0], L1, L1), _dg.tensor_tab(L1, D1 / h[1], L1), _dg.tensor_tab(L1, L1, D1 / h[2])]
+    W = _dg.tensor_weights(wq, wq, wq) * np.prod(h)
+    xi_vol = _dg.tensor_points(xq, xq, xq)
+    nv = q1_nvert(prob)
+    Ah = np.zeros((nv, nv))
+    ends = [np.array([[1.0, 0.0]]), np.array([[0.0, 1.0]])]
+    dends = [np.array([[-1.0, 1.0]]), np.array([[-1.0, 1.0]])]
+    for c in range(prob.ncell):
+        ix, iy, iz = prob.cell_ijk(c)
+        verts = [q1_vertex_id(prob, ix + (q & 1), iy + ((q >> 1) & 1), iz + (q >> 2)) for q in range(8)]
+        K = prob.Kdiag(c)
+        E = np.zeros((8, 8))
+        for k in range(3):
+            E += K[k] * (G[k].T * W) @ G[k]
+        if prob.has_b:
+            bq = prob.bfield(prob.origin(c) + xi_vol * h)
+            for k in range(3):
+                E -= (G[k].T * (W * bq[:, k])) @ Phi
+        E += prob.creact(c) * (Phi.T * W) @ Phi
+        for bf, k, side in _dg.boundary_faces(prob, c):
+            if prob.bc[bf] != "D":
+                continue
+            vals = [L1, L1, L1]
+            ders = [L1, L1, L1]
+            vals[k] = ends[side]
+            ders[k] = dends[side] / h[k]
+            Tr = _dg.tensor_tab(*vals)
+            Dk = _dg.tensor_tab(*ders)
+            pts = [xq, xq, xq]
+            pts[k] = np.array([float(side)])
+            xi = _dg.tensor_points(*pts)
+            WF = _dg.face_weights(prob, tab, k)
+            nu_k = 1.0 if side == 1 else -1.0
+            d = K[k]
+            gam = _dg.penalty_boundary(prob, k, d)
+            Dn = nu_k * Dk
+            E += -d * (Tr.T * WF) @ Dn - d * (Dn.T * WF) @ Tr + gam * (Tr.T * WF) @ Tr
+            if prob.has_b:
+                bnu = nu_k * prob.bfield(prob.origin(c) + xi * h)[:, k]
+                E += (Tr.T * (WF * bnu * (bnu >= 0.0))) @ Tr
+        for a_, va in enumerate(verts):
+            for b_, vb in enumerate(verts):
+                Ah[va, vb] += E[a_, b_]
+    return Ah
+
+
+# ---------------------------------------------------------------------------
 # hybrid V-cycle (alg hybrid_multigrid)
 # ---------------------------------------------------------------------------
 def vcycle(A, Dblocks, prob: _dg.Problem, r, coarse_solve, n_pre=1, n_post=1, omega=1.0,
-           inner="exact", eps=1e-2, max_inner=None, restart=30, stats=None):
+           inner="exact", eps=1e-2, max_inner=None, restart=30, stats=None, P=None):
     """z ~= A^-1 r: presmooth from zero, residual, restrict, coarse solve,
-    prolongate-add, postsmooth."""
-    P = p0_prolongation(prob)
+    prolongate-add, postsmooth.  P: prolongation (default: P0)."""
+    if P is None:
+        P = p0_prolongation(prob)
     kw = dict(omega=omega, inner=inner, eps=eps, max_inner=max_inner, restart=restart, stats=stats)
     z = block_jacobi(A, Dblocks, r, np.zeros_like(r), nsweeps=n_pre, **kw)
     res = r - A @ z

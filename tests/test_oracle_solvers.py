@@ -213,3 +213,55 @@ def test_memory_tables(fname, fun, unit):
         assert round(mx / pmf, 1) == float(r["pmf_ratio"])
         assert round(mf, 3) == float(r["mf_gb"])
         assert round(mx / mf, 1) == float(r["mf_ratio"])
+
+
+# ---------------------------------------------------------------------------
+# Q1 subspace (App. A.2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("with_b", [False, True])
+def test_q1_galerkin_equals_direct(with_b):
+    """P^T A P on the conforming Q1 subspace equals the direct evaluation of
+    a_h on the trilinear functions: volume terms plus Dirichlet-face terms
+    only, the interior jump terms vanishing (App. A.2)."""
+    kw = {}
+    if with_b:
+        kw = dict(b0=(0.3, -0.7, 0.2), B=((0.5, 1.0, 0.0), (-1.0, -0.2, 0.5), (0.3, 0.0, -0.3)))
+    pr = small(2, cells=(3, 2, 2), seed=9, bc=("D", "N", "D", "D", "N", "D"), c=0.7, **kw)
+    A = dg.assemble(pr)
+    G = solvers.q1_galerkin(A, pr)
+    D = solvers.q1_direct(pr)
+    assert np.abs(G - D).max() <= 1e-12 * np.abs(G).max()
+
+
+def test_q1_prolongation_reproduces_trilinear():
+    """P applied to the vertex values of a global trilinear function gives
+    its nodal interpolant (Q1 is a subspace of V_h^p)."""
+    pr = small(3, cells=(3, 2, 4))
+    nx, ny, nz = pr.cells
+    h = pr.h
+    coef = np.random.default_rng(3).normal(size=8)
+
+    def f(x):
+        X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+        return (coef[0] + coef[1] * X + coef[2] * Y + coef[3] * Z + coef[4] * X * Y + coef[5] * Y * Z
+                + coef[6] * X * Z + coef[7] * X * Y * Z)
+
+    V = np.array([[vx * h[0], vy * h[1], vz * h[2]] for vz in range(nz + 1) for vy in range(ny + 1)
+                  for vx in range(nx + 1)])
+    P = solvers.q1_prolongation(pr)
+    np.testing.assert_allclose(P @ f(V), dg.interpolate(pr, f), rtol=1e-13, atol=1e-13)
+
+
+def test_vcycle_q1_symmetric():
+    pr = small(2, cells=(3, 2, 2))
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    P = solvers.q1_prolongation(pr)
+    cs = solvers.exact_coarse(solvers.q1_direct(pr))
+    rng = np.random.default_rng(6)
+    r1, r2 = rng.normal(size=(2, pr.ndof))
+    kw = dict(n_pre=1, n_post=1, omega=0.7, inner="exact", P=P)
+    z1 = solvers.vcycle(A, Db, pr, r1, cs, **kw)
+    z2 = solvers.vcycle(A, Db, pr, r2, cs, **kw)
+    assert r2 @ z1 == pytest.approx(r1 @ z2, rel=1e-11)
+    assert r1 @ z1 > 0
