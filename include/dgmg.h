@@ -60,6 +60,7 @@ enum { DG_BC_DIRICHLET = 0, DG_BC_NEUMANN = 1 };
 enum { DG_INNER_CG = 0, DG_INNER_GMRES = 1 };
 enum { DG_KRYLOV_CG = 0, DG_KRYLOV_FCG = 1, DG_KRYLOV_FGMRES = 2 };
 enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK_JACOBI = 1, DG_PRECOND_MG = 2 };
+enum { DG_COARSE_P0 = 0, DG_COARSE_Q1 = 1, DG_COARSE_AUTO = 2 };
 
 typedef struct dg_problem dg_problem;          /* opaque, library-owned */
 typedef struct dg_solve_state dg_solve_state;  /* opaque, library-owned */
@@ -102,14 +103,29 @@ typedef struct {
   double inner_avg;       /* inner_total / blocks                          */
 } dg_smooth_stats;
 
-/* Hybrid V-cycle options (alg hybrid_multigrid; P0 subspace, Sec. 2.2.2,
- * 2.2.3 and App. A.1). */
+/* Hybrid V-cycle options (alg hybrid_multigrid; coarse subspaces of
+ * Sec. 2.2.2-2.2.3).  coarse_space:
+ *   DG_COARSE_P0  piecewise constants, one unknown per cell, A_hat = P^T A P
+ *                 by the direct formula of App. A.1; coarse solver: a
+ *                 structured 2x2x2 aggregation V-cycle (7-point stencils);
+ *   DG_COARSE_Q1  continuous trilinears, one unknown per mesh vertex,
+ *                 A_hat = a_h on the vertex functions (App. A.2), equal to
+ *                 P^T A P; coarse solver: a vertex-grid V-cycle with
+ *                 trilinear Galerkin coarsening (27-point stencils), built
+ *                 on first use;
+ *   DG_COARSE_AUTO (default) Q1 when b = 0, P0 otherwise (the Q1 matrix
+ *                 has no upwinding inside the domain, so it is a poor
+ *                 coarse model of convection-dominated problems).
+ * Both coarse solvers use damped Jacobi and a dense inverse of the
+ * coarsest level (<= 128 unknowns), with a fixed number of cycles, so the
+ * V-cycle is a fixed linear operator. */
 typedef struct {
-  int n_pre, n_post;        /* smoothing steps                              */
+  int n_pre, n_post;        /* smoothing steps, 0..64                       */
   dg_smooth_opts smooth;    /* smoother (n_sweeps and zero_guess ignored)   */
-  int coarse_cycles;        /* cycles of the P0 aggregation V-cycle (>= 1)  */
-  int coarse_smooth;        /* Jacobi sweeps per level in that cycle        */
-  double coarse_omega;      /* Jacobi damping on the P0 levels              */
+  int coarse_space;         /* DG_COARSE_P0, DG_COARSE_Q1 or DG_COARSE_AUTO */
+  int coarse_cycles;        /* V-cycles of the coarse solver (0 or 1: one)  */
+  int coarse_smooth;        /* Jacobi sweeps per level (0: 2), 0..64        */
+  double coarse_omega;      /* Jacobi damping on the coarse levels (<= 0: 2/3) */
 } dg_mg_opts;
 
 /* Outer solve options (Sec. 4.2: CG to 1e-8; Sec. 4.3: flexible GMRES). */
@@ -196,8 +212,9 @@ int dg_block_smooth(dg_problem *prob, int precision, const void *f, const void *
 
 /* z ~= A^-1 r by one hybrid V-cycle from a zero initial guess
  * (alg hybrid_multigrid): presmooth, residual, restriction R = P^T
- * (P0 injection, Sec. 2.2.2), coarse correction with the P0 matrix
- * A_hat = P^T A P (App. A.1), prolongation, postsmooth. */
+ * (Sec. 2.2.2), coarse correction with A_hat = P^T A P in the P0 or Q1
+ * subspace (App. A.1 / A.2; the Q1 hierarchy is built on the first call
+ * that asks for it, a synchronous host setup), prolongation, postsmooth. */
 int dg_mg_vcycle(dg_problem *prob, int precision, const void *r, void *z, const dg_mg_opts *opts,
                  void *stream);
 
@@ -207,6 +224,16 @@ int dg_mg_vcycle(dg_problem *prob, int precision, const void *r, void *z, const 
  * Synchronises; fills *res (nullable). */
 int dg_solve(dg_problem *prob, const double *f, double *u, const dg_solve_opts *opts,
              dg_solve_result *res, void *stream);
+
+/* Coarse-hierarchy introspection (tests, diagnostics).  Level `level` of
+ * the DG_COARSE_P0 or DG_COARSE_Q1 hierarchy (built if needed; level 0 is
+ * the coarse space itself, A_hat = P^T A P): dims (HOST int[5]) receives
+ * (vx, vy, vz, ns, nlevels), the grid of unknowns (x fastest), the stencil
+ * width (7: diag, -x, +x, -y, +y, -z, +z; 27: o = (dx+1) + 3 (dy+1) +
+ * 9 (dz+1) for the coupling to the unknown at offset (dx, dy, dz)) and the
+ * number of levels.  When out is not NULL it receives the FP64 stencil,
+ * HOST [ns][vx*vy*vz].  Synchronous.  DG_EINVAL for a level out of range. */
+int dg_coarse_stencil(dg_problem *prob, int coarse_space, int level, int *dims, double *out);
 
 /* ---- resident solves and continuous batching ---------------------- */
 /* Start an outer CG / flexible-CG solve of A u = f (options as dg_solve;

@@ -24,13 +24,14 @@ DG_BC_DIRICHLET, DG_BC_NEUMANN = 0, 1
 DG_INNER_CG, DG_INNER_GMRES = 0, 1
 DG_KRYLOV_CG, DG_KRYLOV_FCG, DG_KRYLOV_FGMRES = 0, 1, 2
 DG_PRECOND_NONE, DG_PRECOND_BLOCK_JACOBI, DG_PRECOND_MG = 0, 1, 2
+DG_COARSE_P0, DG_COARSE_Q1, DG_COARSE_AUTO = 0, 1, 2
 
 EXPORTS = (
     "dg_problem_create", "dg_problem_destroy", "dg_last_error", "dg_ndof", "dg_boundary_npoints",
     "dg_node_points", "dg_boundary_points", "dg_assemble_rhs", "dg_apply", "dg_block_apply",
     "dg_block_diag", "dg_block_solve", "dg_block_smooth", "dg_mg_vcycle", "dg_solve", "dg_footprint",
-    "dg_default_smooth_opts", "dg_default_mg_opts", "dg_default_solve_opts", "dg_solve_start", "dg_batch_step",
-    "dg_solve_poll", "dg_solve_state_destroy",
+    "dg_coarse_stencil", "dg_default_smooth_opts", "dg_default_mg_opts", "dg_default_solve_opts",
+    "dg_solve_start", "dg_batch_step", "dg_solve_poll", "dg_solve_state_destroy",
 )
 
 
@@ -67,7 +68,7 @@ class SmoothStats(ctypes.Structure):
 class MgOpts(ctypes.Structure):
     _fields_ = [
         ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int), ("smooth", SmoothOpts),
-        ("coarse_cycles", ctypes.c_int), ("coarse_smooth", ctypes.c_int), ("coarse_omega", ctypes.c_double),
+        ("coarse_space", ctypes.c_int), ("coarse_cycles", ctypes.c_int), ("coarse_smooth", ctypes.c_int), ("coarse_omega", ctypes.c_double),
     ]
 
 
@@ -119,6 +120,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_mg_vcycle.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.POINTER(MgOpts), vp]
     lib.dg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveResult), vp]
     lib.dg_footprint.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(SolveOpts), ctypes.POINTER(ctypes.c_size_t)]
+    lib.dg_coarse_stencil.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), vp]
     lib.dg_default_smooth_opts.argtypes = [ctypes.POINTER(SmoothOpts)]
     lib.dg_default_smooth_opts.restype = None
     lib.dg_default_mg_opts.argtypes = [ctypes.POINTER(MgOpts)]

@@ -21,7 +21,10 @@ OUT = os.path.join(HERE, "libdgmg.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("DGMG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["tables.cpp", "problem.cpp", "api.cpp", "solve.cpp", "batch.cpp", "apply.hip", "smooth.hip", "vec.hip"]
+SOURCES = [
+    "tables.cpp", "problem.cpp", "q1.cpp", "api.cpp", "solve.cpp", "batch.cpp",
+    "apply.hip", "smooth.hip", "vec.hip", "coarse.hip",
+]
 
 COMMON = [
     "-O3",

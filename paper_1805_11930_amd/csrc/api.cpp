@@ -6,11 +6,29 @@
 #include <vector>
 
 #include "dg_internal.h"
+#include "solve_common.h"
 #include "vec.h"
 
 namespace dgmg {
 int alloc_tmp(dg_problem *pr, int prec, int k, void **out);
 int alloc_small(dg_problem *pr);
+int ensure_hierarchy(dg_problem *pr, int kind);
+
+int validate_mg_opts(const dg_mg_opts *o) {
+  if (o->n_pre < 0 || o->n_post < 0 || o->n_pre > 64 || o->n_post > 64) {
+    set_error("n_pre and n_post must be in 0..64");
+    return DG_EINVAL;
+  }
+  if (o->coarse_space != DG_COARSE_P0 && o->coarse_space != DG_COARSE_Q1 && o->coarse_space != DG_COARSE_AUTO) {
+    set_error("coarse_space must be DG_COARSE_P0, DG_COARSE_Q1 or DG_COARSE_AUTO");
+    return DG_EINVAL;
+  }
+  if (o->coarse_cycles < 0 || o->coarse_cycles > 64 || o->coarse_smooth < 0 || o->coarse_smooth > 64) {
+    set_error("coarse_cycles and coarse_smooth must be in 0..64");
+    return DG_EINVAL;
+  }
+  return DG_OK;
+}
 }  // namespace dgmg
 
 using namespace dgmg;
@@ -90,62 +108,107 @@ int sweeps(dg_problem *pr, int prec, const void *f, const void *src, void *dst, 
   return DG_OK;
 }
 
-// ---- P0 aggregation cycle on the coarse levels --------------------------
+// ---- coarse cycles (P0 aggregation or Q1 vertex-grid hierarchy) ---------
 template <typename T>
-struct LevelPtr {
-  static T *r(CoarseLevel &L);
-  static T *x(CoarseLevel &L);
-  static T *t(CoarseLevel &L);
-  static const T *A(const CoarseLevel &L);
-  static const T *inv(const dg_problem *pr);
-};
+struct LevelPtr;
 template <>
 struct LevelPtr<double> {
   static double *r(CoarseLevel &L) { return L.r64; }
   static double *x(CoarseLevel &L) { return L.x64; }
   static double *t(CoarseLevel &L) { return L.t64; }
+  static double *acc(CoarseLevel &L) { return L.acc64; }
+  static double *rs(CoarseLevel &L) { return L.rs64; }
   static const double *A(const CoarseLevel &L) { return L.A64; }
-  static const double *inv(const dg_problem *pr) { return pr->bottom_inv64; }
+  static const double *dinv(const CoarseLevel &L) { return L.dinv64; }
+  static const double *inv(const Hierarchy &H) { return H.inv64; }
 };
 template <>
 struct LevelPtr<float> {
   static float *r(CoarseLevel &L) { return L.r32; }
   static float *x(CoarseLevel &L) { return L.x32; }
   static float *t(CoarseLevel &L) { return L.t32; }
+  static float *acc(CoarseLevel &L) { return L.acc32; }
+  static float *rs(CoarseLevel &L) { return L.rs32; }
   static const float *A(const CoarseLevel &L) { return L.A32; }
-  static const float *inv(const dg_problem *pr) { return pr->bottom_inv32; }
+  static const float *dinv(const CoarseLevel &L) { return L.dinv32; }
+  static const float *inv(const Hierarchy &H) { return H.inv32; }
 };
 
-// x_l ~= A_l^-1 r_l: one V-cycle of the P0 aggregation hierarchy from a
-// zero guess; r_l is level l's r buffer, the result is left in one of
-// level l's x / t buffers and returned in *result.
 template <typename T>
-int coarse_cycle(dg_problem *pr, size_t l, int nu, T w, hipStream_t s, T **result) {
+int level_jacobi(const CoarseLevel &L, T w, const T *r, const T *xi, T *xo, hipStream_t s) {
+  const T *A = LevelPtr<T>::A(L);
+  return L.ns == 27 ? jacobi27<T>(A, LevelPtr<T>::dinv(L), L.nx, L.ny, L.nz, w, r, xi, xo, s)
+                    : coarse_jacobi<T>(A, L.nx, L.ny, L.nz, w, r, xi, xo, s);
+}
+
+// x_l ~= A_l^-1 r_l: one V-cycle of the hierarchy from a zero guess; r_l is
+// level l's r buffer, the result is left in one of level l's x / t buffers
+// and returned in *result.
+template <typename T>
+int coarse_cycle(Hierarchy &H, size_t l, int nu, T w, hipStream_t s, T **result) {
   using LP = LevelPtr<T>;
-  CoarseLevel &L = pr->levels[l];
-  if (l + 1 == pr->levels.size()) {
+  CoarseLevel &L = H.levels[l];
+  if (l + 1 == H.levels.size()) {
     *result = LP::x(L);
-    return dense_mv<T>(pr->bottom_n, LP::inv(pr), LP::r(L), LP::x(L), s);
+    return dense_mv<T>(H.bottom_n, LP::inv(H), LP::r(L), LP::x(L), s);
   }
   int rc;
   T *x = LP::x(L), *t = LP::t(L);
   const T *A = LP::A(L), *r = LP::r(L);
   // presmooth from zero: x = w D^-1 r, then nu-1 more sweeps
-  if ((rc = coarse_jacobi<T>(A, L.nx, L.ny, L.nz, w, r, nullptr, x, s))) return rc;
+  if ((rc = level_jacobi<T>(L, w, r, nullptr, x, s))) return rc;
   for (int k = 1; k < nu; ++k) {
-    if ((rc = coarse_jacobi<T>(A, L.nx, L.ny, L.nz, w, r, x, t, s))) return rc;
+    if ((rc = level_jacobi<T>(L, w, r, x, t, s))) return rc;
     std::swap(x, t);
   }
-  CoarseLevel &C = pr->levels[l + 1];
-  if ((rc = coarse_restrict<T>(A, L.nx, L.ny, L.nz, r, x, C.nx, C.ny, C.nz, LP::r(C), s))) return rc;
+  CoarseLevel &C = H.levels[l + 1];
+  if (L.ns == 27) {
+    if ((rc = residual27<T>(A, L.nx, L.ny, L.nz, r, x, t, s))) return rc;
+    if ((rc = restrict27<T>(L.nx, L.ny, L.nz, t, C.nx, C.ny, C.nz, LP::r(C), s))) return rc;
+  } else if ((rc = coarse_restrict<T>(A, L.nx, L.ny, L.nz, r, x, C.nx, C.ny, C.nz, LP::r(C), s))) {
+    return rc;
+  }
   T *xc = nullptr;
-  if ((rc = coarse_cycle<T>(pr, l + 1, nu, w, s, &xc))) return rc;
-  if ((rc = coarse_prolong<T>(L.nx, L.ny, L.nz, C.nx, C.ny, xc, x, s))) return rc;
+  if ((rc = coarse_cycle<T>(H, l + 1, nu, w, s, &xc))) return rc;
+  if (L.ns == 27)
+    rc = prolong27<T>(L.nx, L.ny, L.nz, C.nx, C.ny, C.nz, xc, x, s);
+  else
+    rc = coarse_prolong<T>(L.nx, L.ny, L.nz, C.nx, C.ny, xc, x, s);
+  if (rc) return rc;
   for (int k = 0; k < nu; ++k) {
-    if ((rc = coarse_jacobi<T>(A, L.nx, L.ny, L.nz, w, r, x, t, s))) return rc;
+    if ((rc = level_jacobi<T>(L, w, r, x, t, s))) return rc;
     std::swap(x, t);
   }
   *result = x;
+  return DG_OK;
+}
+
+// x_0 ~= A_0^-1 r_0 on level 0 of H by `cycles` V-cycles (a fixed number,
+// so the result is a linear function of r_0): x += V(r_0 - A_0 x).
+template <typename T>
+int coarse_solve(Hierarchy &H, int cycles, int nu, T w, hipStream_t s, T **result) {
+  using LP = LevelPtr<T>;
+  CoarseLevel &L = H.levels[0];
+  if (cycles <= 1 || H.levels.size() == 1) return coarse_cycle<T>(H, 0, nu, w, s, result);
+  const int64_t n = L.n;
+  T *acc = LP::acc(L), *rs = LP::rs(L);
+  int rc;
+  DG_HIP(hipMemcpyAsync(rs, LP::r(L), n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  T *x = nullptr;
+  if ((rc = coarse_cycle<T>(H, 0, nu, w, s, &x))) return rc;
+  DG_HIP(hipMemcpyAsync(acc, x, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  for (int c = 1; c < cycles; ++c) {
+    if (L.ns == 27)
+      rc = residual27<T>(LP::A(L), L.nx, L.ny, L.nz, rs, acc, LP::r(L), s);
+    else
+      rc = residual7<T>(LP::A(L), L.nx, L.ny, L.nz, rs, acc, LP::r(L), s);
+    if (rc) return rc;
+    if ((rc = coarse_cycle<T>(H, 0, nu, w, s, &x))) return rc;
+    if ((rc = add_to<T>(n, x, acc, s))) return rc;
+  }
+  // restore r_0 for callers that read it again
+  DG_HIP(hipMemcpyAsync(LP::r(L), rs, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  *result = acc;
   return DG_OK;
 }
 
@@ -154,20 +217,35 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
   SmoothArgs sa;
   int rc = smooth_args(pr, &o->smooth, sa);
   if (rc) return rc;
+  const int kind = coarse_kind(o->coarse_space, pr->geo.has_b != 0);
+  if ((rc = ensure_hierarchy(pr, kind))) return rc;
+  Hierarchy &H = kind == COARSE_Q1 ? pr->q1h : pr->p0h;
   void *t0;
   if ((rc = alloc_tmp(pr, prec, 0, &t0))) return rc;
   // presmoothing ends in X so that postsmoothing ends in z without a copy
   void *X = (o->n_post % 2 == 1) ? t0 : (void *)z;
   void *Y = (X == t0) ? (void *)z : t0;
   if ((rc = sweeps(pr, prec, r, nullptr, X, Y, o->n_pre, sa, nullptr, s))) return rc;
-  // residual and restriction R = P^T in one pass
+  // residual and restriction R = P^T
   using LP = LevelPtr<T>;
-  CoarseLevel &L0 = pr->levels[0];
-  if ((rc = launch_residual_restrict(pr, prec, X, r, LP::r(L0), s))) return rc;
+  CoarseLevel &L0 = H.levels[0];
+  if (kind == COARSE_Q1) {
+    T *cs = (T *)pr->corner_buf[prec];
+    if ((rc = launch_residual_restrict(pr, prec, X, r, cs, s, COARSE_Q1))) return rc;
+    if ((rc = q1_gather<T>(pr->geo.nx, pr->geo.ny, pr->geo.nz, cs, LP::r(L0), s))) return rc;
+  } else if ((rc = launch_residual_restrict(pr, prec, X, r, LP::r(L0), s, COARSE_P0))) {
+    return rc;
+  }
   const int nu = o->coarse_smooth > 0 ? o->coarse_smooth : 2;
   const T w = (T)(o->coarse_omega > 0 ? o->coarse_omega : 2.0 / 3.0);
   T *xh = nullptr;
-  if ((rc = coarse_cycle<T>(pr, 0, nu, w, s, &xh))) return rc;
+  if ((rc = coarse_solve<T>(H, o->coarse_cycles, nu, w, s, &xh))) return rc;
+  if (kind == COARSE_Q1) {
+    // prolongation P (nodal interpolation of the trilinear correction)
+    if ((rc = q1_prolong_add<T>(pr->p, pr->geo.nx, pr->geo.ny, pr->geo.nz, xh, (T *)X, s))) return rc;
+    if (o->n_post == 0) return DG_OK;  // X == z here
+    return sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s);
+  }
   if (o->n_post == 0) return prolong_add_p0<T>(pr->ndof, pr->nloc, xh, (T *)X, s);  // X == z here
   // prolongation P (injection) fused into the first postsmoothing sweep
   return sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s, xh);
@@ -198,6 +276,7 @@ void dg_default_mg_opts(dg_mg_opts *o) {
   o->n_pre = 1;
   o->n_post = 1;
   dg_default_smooth_opts(&o->smooth);
+  o->coarse_space = DG_COARSE_AUTO;
   o->coarse_cycles = 1;
   o->coarse_smooth = 4;
   o->coarse_omega = 2.0 / 3.0;
@@ -348,11 +427,35 @@ int dg_mg_vcycle(dg_problem *pr, int precision, const void *r, void *z, const dg
     set_error("dg_mg_vcycle: r and z must differ");
     return DG_EINVAL;
   }
-  if (opts->n_pre < 0 || opts->n_post < 0) {
-    set_error("n_pre and n_post must be >= 0");
+  if ((rc = validate_mg_opts(opts))) return rc;
+  return vcycle(pr, precision, r, z, opts, S(stream));
+}
+
+int dg_coarse_stencil(dg_problem *pr, int coarse_space, int level, int *dims, double *out) {
+  if (!pr || !dims) {
+    set_error("dg_coarse_stencil: problem or dims is NULL");
     return DG_EINVAL;
   }
-  return vcycle(pr, precision, r, z, opts, S(stream));
+  if (coarse_space != DG_COARSE_P0 && coarse_space != DG_COARSE_Q1) {
+    set_error("coarse_space must be DG_COARSE_P0 or DG_COARSE_Q1");
+    return DG_EINVAL;
+  }
+  const int kind = coarse_space == DG_COARSE_Q1 ? COARSE_Q1 : COARSE_P0;
+  int rc = ensure_hierarchy(pr, kind);
+  if (rc) return rc;
+  const Hierarchy &H = kind == COARSE_Q1 ? pr->q1h : pr->p0h;
+  if (level < 0 || level >= (int)H.levels.size()) {
+    set_error("dg_coarse_stencil: level out of range");
+    return DG_EINVAL;
+  }
+  const CoarseLevel &L = H.levels[level];
+  dims[0] = L.nx;
+  dims[1] = L.ny;
+  dims[2] = L.nz;
+  dims[3] = L.ns;
+  dims[4] = (int)H.levels.size();
+  if (out) DG_HIP(hipMemcpy(out, L.A64, (size_t)L.ns * L.n * sizeof(double), hipMemcpyDeviceToHost));
+  return DG_OK;
 }
 
 }  // extern "C"

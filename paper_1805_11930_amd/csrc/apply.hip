@@ -84,10 +84,16 @@ __device__ inline void neighbour_traces(bool in_lds, const T *lds_cell, const T 
 }
 
 // NB: with neighbour couplings (A) or without (D_T).
-// RES: instead of writing v = A u, write rh[c] = sum over the DOFs of cell c
-// of (r - A u): the residual followed by the P0 restriction R = P^T
-// (Sec. 2.2.2), fused so that A u never goes to memory.
-template <int P, typename T, bool NB, bool RES = false>
+// RES = 0: write v = A u.
+// RES = 1: write rh[c] = sum over the DOFs of cell c of (r - A u): the
+//   residual followed by the P0 restriction R = P^T (Sec. 2.2.2), fused so
+//   that A u never goes to memory.
+// RES = 2: write rh[8c + q] = sum_i phi_q(x_i) (r - A u)_i for the eight
+//   trilinear corner functions phi_q of cell c, q = qx + 2 qy + 4 qz: the
+//   per-cell half of the Q1 restriction R = P^T (Sec. 2.2.2, the nodal
+//   interpolation of the vertex functions); the vertex gather follows in a
+//   separate kernel.
+template <int P, typename T, bool NB, int RES = 0>
 __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restrict__ u, T *__restrict__ v,
                                                          const T *__restrict__ r = nullptr,
                                                          T *__restrict__ rh = nullptr) {
@@ -163,11 +169,41 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
     for (int i = 0; i < N; ++i) qs[cl * S::N3 + line_pos<N>(2, i, a, b)] += qz[i];
   }
   __syncthreads();
-  if (!RES) {
+  if constexpr (RES == 0) {
     if (active) {
       T *vb = v + (size_t)c * S::N3 + N * a + S::N2 * b;
 #pragma unroll
       for (int i = 0; i < N; ++i) vb[i] = qx[i] + qs[cl * S::N3 + line_pos<N>(0, i, a, b)];
+    }
+  } else if constexpr (RES == 2) {
+    // lane (a, b) holds the x-line (y = xi_a, z = xi_b) of the residual;
+    // its share of corner q is (sum_i L_qx(xi_i) r_i) L_qy(xi_a) L_qz(xi_b)
+    // with L_0 = 1 - xi, L_1 = xi.  The eight shares of the cell's lanes are
+    // summed in LDS.
+    __shared__ T part[S::CPB * 8 * S::N2];
+    if (active) {
+      const T *rb = r + (size_t)c * S::N3 + N * a + S::N2 * b;
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const T ri = rb[i] - (qx[i] + qs[cl * S::N3 + line_pos<N>(0, i, a, b)]);
+        s0 += (T(1) - tb.xi[i]) * ri;
+        s1 += tb.xi[i] * ri;
+      }
+      const T ly[2] = {T(1) - tb.xi[a], tb.xi[a]};
+      const T lz[2] = {T(1) - tb.xi[b], tb.xi[b]};
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        part[(cl * 8 + q) * S::N2 + ln] = ((q & 1) ? s1 : s0) * ly[(q >> 1) & 1] * lz[q >> 2];
+    }
+    __syncthreads();
+    // a cell has N2 lanes (4 for p = 1): each reduces corners ln, ln + N2, ...
+    if (active) {
+      for (int q = ln; q < 8; q += S::N2) {
+        T sum = T(0);
+        for (int l = 0; l < S::N2; ++l) sum += part[(cl * 8 + q) * S::N2 + l];
+        rh[8 * (size_t)c + q] = sum;
+      }
     }
   } else {
     __shared__ T part[S::CPB * S::N2];
@@ -295,22 +331,27 @@ static int dispatch_apply(const dg_problem *pr, const void *u, void *v, hipStrea
 }
 
 template <int P, typename T>
-static int launch_res_t(const dg_problem *pr, const void *u, const void *r, void *rh, hipStream_t s) {
+static int launch_res_t(const dg_problem *pr, const void *u, const void *r, void *rh, hipStream_t s, int kind) {
   constexpr int N = P + 1;
   const int G = (int)((pr->ncell + ApplyShape<N>::CPB - 1) / ApplyShape<N>::CPB);
-  hipLaunchKernelGGL((k_apply<P, T, true, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u,
-                     (T *)nullptr, (const T *)r, (T *)rh);
+  if (kind == COARSE_Q1)
+    hipLaunchKernelGGL((k_apply<P, T, true, 2>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u,
+                       (T *)nullptr, (const T *)r, (T *)rh);
+  else
+    hipLaunchKernelGGL((k_apply<P, T, true, 1>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u,
+                       (T *)nullptr, (const T *)r, (T *)rh);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
 
-int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, const void *r, void *rh, hipStream_t s) {
+int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, const void *r, void *rh, hipStream_t s,
+                             int kind) {
   const bool d = prec == DG_FP64;
   switch (pr->p) {
-    case 1: return d ? launch_res_t<1, double>(pr, u, r, rh, s) : launch_res_t<1, float>(pr, u, r, rh, s);
-    case 2: return d ? launch_res_t<2, double>(pr, u, r, rh, s) : launch_res_t<2, float>(pr, u, r, rh, s);
-    case 3: return d ? launch_res_t<3, double>(pr, u, r, rh, s) : launch_res_t<3, float>(pr, u, r, rh, s);
-    case 4: return d ? launch_res_t<4, double>(pr, u, r, rh, s) : launch_res_t<4, float>(pr, u, r, rh, s);
+    case 1: return d ? launch_res_t<1, double>(pr, u, r, rh, s, kind) : launch_res_t<1, float>(pr, u, r, rh, s, kind);
+    case 2: return d ? launch_res_t<2, double>(pr, u, r, rh, s, kind) : launch_res_t<2, float>(pr, u, r, rh, s, kind);
+    case 3: return d ? launch_res_t<3, double>(pr, u, r, rh, s, kind) : launch_res_t<3, float>(pr, u, r, rh, s, kind);
+    case 4: return d ? launch_res_t<4, double>(pr, u, r, rh, s, kind) : launch_res_t<4, float>(pr, u, r, rh, s, kind);
   }
   set_error("unsupported degree");
   return DG_EINVAL;

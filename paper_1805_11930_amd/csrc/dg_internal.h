@@ -74,14 +74,48 @@ struct Geo {
   const double *c;  // device [ncell] (valid when has_c)
 };
 
-// P0 aggregation hierarchy used as the simple coarse solver.
+// One level of a coarse hierarchy on a structured grid of vx * vy * vz
+// unknowns: P0 (one unknown per cell, 7-point stencil, piecewise-constant
+// 2x2x2 aggregation between levels) or Q1 (one unknown per mesh vertex,
+// 27-point stencil, trilinear interpolation between levels).
 struct CoarseLevel {
   int nx, ny, nz, n;
-  // 7-point stencil per unknown: diag, -x,+x,-y,+y,-z,+z couplings
-  double *A64 = nullptr;  // device [7][n]
+  int ns = 7;             // stencil entries per unknown (7 or 27)
+  double *A64 = nullptr;  // device [ns][n]
   float *A32 = nullptr;
+  // 27-point levels: inverse of the smoothing diagonal, 2 / sum_o |A[o][i]|
+  // (half the l1 row norm; equal to the diagonal on the isotropic Q1
+  // stencil, and it keeps damped Jacobi convergent on anisotropic cells)
+  double *dinv64 = nullptr;
+  float *dinv32 = nullptr;
   double *r64 = nullptr, *x64 = nullptr, *t64 = nullptr;  // device [n]
   float *r32 = nullptr, *x32 = nullptr, *t32 = nullptr;
+  // level 0 only: accumulated solution and saved right-hand side of
+  // repeated coarse cycles
+  double *acc64 = nullptr, *rs64 = nullptr;
+  float *acc32 = nullptr, *rs32 = nullptr;
+};
+
+// 7-point stencil order: diag, -x, +x, -y, +y, -z, +z.
+// 27-point stencil order: o = (dx+1) + 3 (dy+1) + 9 (dz+1), diag at 13.
+constexpr int kDiag27 = 13;
+
+enum CoarseKind : int { COARSE_P0 = 0, COARSE_Q1 = 1 };
+
+// DG_COARSE_* option -> hierarchy (AUTO: Q1 without advection, else P0)
+inline int coarse_kind(int option, bool has_b) {
+  if (option == DG_COARSE_Q1) return COARSE_Q1;
+  if (option == DG_COARSE_AUTO) return has_b ? COARSE_P0 : COARSE_Q1;
+  return COARSE_P0;
+}
+
+struct Hierarchy {
+  int kind = COARSE_P0;
+  int built = 0;  // 0: not yet, 1: ready, < 0: failed with that status
+  std::vector<CoarseLevel> levels;
+  double *inv64 = nullptr;  // dense inverse of the coarsest matrix
+  float *inv32 = nullptr;
+  int bottom_n = 0;
 };
 
 }  // namespace dgmg
@@ -95,11 +129,11 @@ struct dg_problem {
   double *dK = nullptr;
   double *dc = nullptr;
   int device = 0;
-  // coarse hierarchy (level 0 = one unknown per cell)
-  std::vector<dgmg::CoarseLevel> levels;
-  double *bottom_inv64 = nullptr;  // dense inverse of the coarsest matrix
-  float *bottom_inv32 = nullptr;
-  int bottom_n = 0;
+  // host copies of the coefficients (for building coarse spaces)
+  std::vector<double> hK, hc;
+  // coarse hierarchies: P0 (built with the problem) and Q1 (on first use)
+  dgmg::Hierarchy p0h, q1h;
+  void *corner_buf[2] = {nullptr, nullptr};  // [ncell][8] Q1 corner sums per precision
   // DG-sized temporaries for the V-cycle and smoother (allocated lazily)
   void *mg_tmp[2][4] = {{nullptr}};  // [precision][k]
   int *iters_buf = nullptr;          // [ncell]
@@ -121,8 +155,10 @@ int hip_fail(hipError_t e, const char *what);
 // kernel launchers (apply.hip / smooth.hip / vec.hip / coarse.hip)
 int launch_apply(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s);
 int launch_block_apply(const dg_problem *pr, int prec, const void *x, void *y, hipStream_t s);
-// rh[c] = sum_{i in cell c} (r - A u)_i
-int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, const void *r, void *rh, hipStream_t s);
+// rh[c] = sum_{i in cell c} (r - A u)_i                  (P0 restriction)
+// rh[8 c + q] = sum_{i in cell c} phi_q(xi_i) (r - A u)_i  (Q1 corner sums)
+int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, const void *r, void *rh, hipStream_t s,
+                             int kind = COARSE_P0);
 int launch_block_diag(const dg_problem *pr, int prec, void *diag, hipStream_t s);
 int launch_rhs(const dg_problem *pr, const double *f_qp, const double *bnd, double *rhs, hipStream_t s);
 

@@ -18,7 +18,7 @@ int hip_fail(hipError_t e, const char *what) {
   return e == hipErrorOutOfMemory ? DG_ENOMEM : DG_EDEVICE;
 }
 
-static int dmalloc(dg_problem *pr, void **p, size_t bytes) {
+int dmalloc(dg_problem *pr, void **p, size_t bytes) {
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -120,7 +120,9 @@ static void aggregate(const std::vector<double> &A, int nx, int ny, int nz, std:
       }
 }
 
-static bool dense_inverse(std::vector<double> M, int n, std::vector<double> &inv) {
+constexpr int kBottomMax = 128;
+
+bool dense_inverse(std::vector<double> M, int n, std::vector<double> &inv) {
   inv.assign((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
   for (int col = 0; col < n; ++col) {
@@ -151,26 +153,87 @@ static bool dense_inverse(std::vector<double> M, int n, std::vector<double> &inv
   return true;
 }
 
-static int upload_level(dg_problem *pr, CoarseLevel &L, const std::vector<double> &A) {
-  const int64_t n = L.n;
+// Device copy of one level's stencil (both precisions) and its work vectors.
+int upload_level(dg_problem *pr, CoarseLevel &L, const std::vector<double> &A, bool first) {
+  const int64_t n = L.n, ns = L.ns;
   int rc;
-  if ((rc = dmalloc(pr, (void **)&L.A64, 7 * n * sizeof(double)))) return rc;
-  if ((rc = dmalloc(pr, (void **)&L.A32, 7 * n * sizeof(float)))) return rc;
+  if ((rc = dmalloc(pr, (void **)&L.A64, ns * n * sizeof(double)))) return rc;
+  if ((rc = dmalloc(pr, (void **)&L.A32, ns * n * sizeof(float)))) return rc;
   for (double **p : {&L.r64, &L.x64, &L.t64})
     if ((rc = dmalloc(pr, (void **)p, n * sizeof(double)))) return rc;
   for (float **p : {&L.r32, &L.x32, &L.t32})
     if ((rc = dmalloc(pr, (void **)p, n * sizeof(float)))) return rc;
+  if (first) {
+    for (double **p : {&L.acc64, &L.rs64})
+      if ((rc = dmalloc(pr, (void **)p, n * sizeof(double)))) return rc;
+    for (float **p : {&L.acc32, &L.rs32})
+      if ((rc = dmalloc(pr, (void **)p, n * sizeof(float)))) return rc;
+  }
   std::vector<float> Af(A.begin(), A.end());
-  DG_HIP(hipMemcpy(L.A64, A.data(), 7 * n * sizeof(double), hipMemcpyHostToDevice));
-  DG_HIP(hipMemcpy(L.A32, Af.data(), 7 * n * sizeof(float), hipMemcpyHostToDevice));
+  DG_HIP(hipMemcpy(L.A64, A.data(), ns * n * sizeof(double), hipMemcpyHostToDevice));
+  DG_HIP(hipMemcpy(L.A32, Af.data(), ns * n * sizeof(float), hipMemcpyHostToDevice));
+  if (ns == 27) {
+    std::vector<double> d(n);
+    for (int64_t i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int o = 0; o < 27; ++o) s += std::fabs(A[(size_t)o * n + i]);
+      if (!(s > 0.0)) {
+        set_error("coarse level has an empty row");
+        return DG_EINVAL;
+      }
+      d[i] = 2.0 / s;
+    }
+    std::vector<float> df(d.begin(), d.end());
+    if ((rc = dmalloc(pr, (void **)&L.dinv64, n * sizeof(double)))) return rc;
+    if ((rc = dmalloc(pr, (void **)&L.dinv32, n * sizeof(float)))) return rc;
+    DG_HIP(hipMemcpy(L.dinv64, d.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    DG_HIP(hipMemcpy(L.dinv32, df.data(), n * sizeof(float), hipMemcpyHostToDevice));
+  }
   return DG_OK;
 }
 
-constexpr int kBottomMax = 128;
+// Dense inverse of the coarsest level (stencil A with L.ns entries) on the
+// device in both precisions.
+int upload_bottom(dg_problem *pr, Hierarchy &H, const std::vector<double> &A) {
+  const CoarseLevel &B = H.levels.back();
+  const int n = B.n;
+  std::vector<double> M((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const int ix = i % B.nx, iy = (i / B.nx) % B.ny, iz = i / (B.nx * B.ny);
+    if (B.ns == 7) {
+      M[(size_t)i * n + i] = A[i];
+      const int off[6] = {-1, 1, -B.nx, B.nx, -B.nx * B.ny, B.nx * B.ny};
+      const bool ok[6] = {ix > 0, ix < B.nx - 1, iy > 0, iy < B.ny - 1, iz > 0, iz < B.nz - 1};
+      for (int d = 0; d < 6; ++d)
+        if (ok[d]) M[(size_t)i * n + i + off[d]] += A[(1 + d) * n + i];
+    } else {
+      for (int o = 0; o < 27; ++o) {
+        const int jx = ix + o % 3 - 1, jy = iy + (o / 3) % 3 - 1, jz = iz + o / 9 - 1;
+        if (jx < 0 || jy < 0 || jz < 0 || jx >= B.nx || jy >= B.ny || jz >= B.nz) continue;
+        M[(size_t)i * n + jx + B.nx * (jy + B.ny * jz)] += A[(size_t)o * n + i];
+      }
+    }
+  }
+  std::vector<double> inv;
+  if (!dense_inverse(M, n, inv)) {
+    set_error("singular coarse matrix (pure Neumann problem without reaction?)");
+    return DG_EINVAL;
+  }
+  int rc;
+  if ((rc = dmalloc(pr, (void **)&H.inv64, (size_t)n * n * sizeof(double)))) return rc;
+  if ((rc = dmalloc(pr, (void **)&H.inv32, (size_t)n * n * sizeof(float)))) return rc;
+  std::vector<float> invf(inv.begin(), inv.end());
+  DG_HIP(hipMemcpy(H.inv64, inv.data(), (size_t)n * n * sizeof(double), hipMemcpyHostToDevice));
+  DG_HIP(hipMemcpy(H.inv32, invf.data(), (size_t)n * n * sizeof(float), hipMemcpyHostToDevice));
+  H.bottom_n = n;
+  return DG_OK;
+}
 
-static int build_coarse(dg_problem *pr, const std::vector<double> &K, const std::vector<double> &cc) {
+static int build_p0(dg_problem *pr) {
+  Hierarchy &H = pr->p0h;
+  H.kind = COARSE_P0;
   std::vector<double> A;
-  p0_stencil(pr, K, cc, A);
+  p0_stencil(pr, pr->hK, pr->hc, A);
   int nx = pr->geo.nx, ny = pr->geo.ny, nz = pr->geo.nz;
   while (true) {
     CoarseLevel L;
@@ -178,8 +241,9 @@ static int build_coarse(dg_problem *pr, const std::vector<double> &K, const std:
     L.ny = ny;
     L.nz = nz;
     L.n = nx * ny * nz;
-    int rc = upload_level(pr, L, A);
-    pr->levels.push_back(L);
+    L.ns = 7;
+    int rc = upload_level(pr, L, A, H.levels.empty());
+    H.levels.push_back(L);
     if (rc) return rc;
     if (L.n <= kBottomMax) break;
     std::vector<double> Ac;
@@ -190,31 +254,21 @@ static int build_coarse(dg_problem *pr, const std::vector<double> &K, const std:
     ny = cny;
     nz = cnz;
   }
-  // dense inverse of the coarsest level
-  const CoarseLevel &B = pr->levels.back();
-  const int n = B.n;
-  std::vector<double> M((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) {
-    const int ix = i % B.nx, iy = (i / B.nx) % B.ny, iz = i / (B.nx * B.ny);
-    M[(size_t)i * n + i] = A[i];
-    const int off[6] = {-1, 1, -B.nx, B.nx, -B.nx * B.ny, B.nx * B.ny};
-    const bool ok[6] = {ix > 0, ix < B.nx - 1, iy > 0, iy < B.ny - 1, iz > 0, iz < B.nz - 1};
-    for (int d = 0; d < 6; ++d)
-      if (ok[d]) M[(size_t)i * n + i + off[d]] += A[(1 + d) * n + i];
+  return upload_bottom(pr, H, A);
+}
+
+int build_q1(dg_problem *pr, int bottom_max);
+
+int ensure_hierarchy(dg_problem *pr, int kind) {
+  Hierarchy &H = kind == COARSE_Q1 ? pr->q1h : pr->p0h;
+  if (H.built == 1) return DG_OK;
+  if (H.built < 0) {
+    set_error("the coarse space could not be built for this problem");
+    return H.built;
   }
-  std::vector<double> inv;
-  if (!dense_inverse(M, n, inv)) {
-    set_error("singular coarse matrix (pure Neumann problem without reaction?)");
-    return DG_EINVAL;
-  }
-  int rc;
-  if ((rc = dmalloc(pr, (void **)&pr->bottom_inv64, (size_t)n * n * sizeof(double)))) return rc;
-  if ((rc = dmalloc(pr, (void **)&pr->bottom_inv32, (size_t)n * n * sizeof(float)))) return rc;
-  std::vector<float> invf(inv.begin(), inv.end());
-  DG_HIP(hipMemcpy(pr->bottom_inv64, inv.data(), (size_t)n * n * sizeof(double), hipMemcpyHostToDevice));
-  DG_HIP(hipMemcpy(pr->bottom_inv32, invf.data(), (size_t)n * n * sizeof(float), hipMemcpyHostToDevice));
-  pr->bottom_n = n;
-  return DG_OK;
+  const int rc = kind == COARSE_Q1 ? build_q1(pr, kBottomMax) : build_p0(pr);
+  H.built = rc == DG_OK ? 1 : (rc < 0 ? rc : DG_EINVAL);
+  return rc;
 }
 
 int alloc_tmp(dg_problem *pr, int prec, int k, void **out) {
@@ -246,18 +300,15 @@ void dg_problem_destroy(dg_problem *pr) {
   if (!pr) return;
   (void)hipFree(pr->dK);
   (void)hipFree(pr->dc);
-  for (auto &L : pr->levels) {
-    (void)hipFree(L.A64);
-    (void)hipFree(L.A32);
-    (void)hipFree(L.r64);
-    (void)hipFree(L.x64);
-    (void)hipFree(L.t64);
-    (void)hipFree(L.r32);
-    (void)hipFree(L.x32);
-    (void)hipFree(L.t32);
+  for (Hierarchy *H : {&pr->p0h, &pr->q1h}) {
+    for (auto &L : H->levels) {
+      for (double *p : {L.A64, L.dinv64, L.r64, L.x64, L.t64, L.acc64, L.rs64}) (void)hipFree(p);
+      for (float *p : {L.A32, L.dinv32, L.r32, L.x32, L.t32, L.acc32, L.rs32}) (void)hipFree(p);
+    }
+    (void)hipFree(H->inv64);
+    (void)hipFree(H->inv32);
   }
-  (void)hipFree(pr->bottom_inv64);
-  (void)hipFree(pr->bottom_inv32);
+  for (void *p : pr->corner_buf) (void)hipFree(p);
   for (auto &row : pr->mg_tmp)
     for (void *p : row) (void)hipFree(p);
   (void)hipFree(pr->iters_buf);
@@ -373,7 +424,9 @@ int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
   }
   g.K = pr->dK;
   g.c = pr->dc;
-  if (!rc) rc = build_coarse(pr, K, cc);
+  pr->hK.swap(K);
+  pr->hc.swap(cc);
+  if (!rc) rc = ensure_hierarchy(pr, COARSE_P0);
   if (!rc) rc = alloc_small(pr);
   if (rc) {
     dg_problem_destroy(pr);

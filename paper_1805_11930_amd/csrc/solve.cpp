@@ -33,6 +33,7 @@ int validate_solve_opts(const dg_solve_opts *o) {
     set_error("invalid solve options");
     return DG_EINVAL;
   }
+  if (o->precond == DG_PRECOND_MG) return validate_mg_opts(&o->mg);
   return DG_OK;
 }
 }  // namespace dgmg
@@ -290,14 +291,25 @@ extern "C" int dg_footprint(const dg_problem_desc *d, const dg_solve_opts *o, si
   size_t b = 0;
   b += ncell * 4 * sizeof(double);       // K, c
   b += ncell * sizeof(int) + 8 * 1024 * sizeof(double) + 64;
-  // coarse levels: ~8/7 of level 0, 7 stencil entries + 3 vectors in both precisions
-  const int64_t nco = ncell + ncell / 7 + 1;
-  b += nco * (7 + 3) * (sizeof(double) + sizeof(float));
-  b += 512 * 512 * (sizeof(double) + sizeof(float));
   dg_solve_opts def;
   if (!o) {
     dg_default_solve_opts(&def);
     o = &def;
+  }
+  const size_t both = sizeof(double) + sizeof(float);
+  // P0 hierarchy (always built): levels ~8/7 of level 0, 7 stencil entries
+  // + 3 vectors per unknown, 2 more vectors on level 0, dense bottom
+  const int64_t nco = ncell + ncell / 7 + 1;
+  b += (nco * (7 + 3) + 2 * ncell) * both;
+  b += 128 * 128 * both;
+  bool has_b = false;
+  for (int i = 0; i < 3; ++i) has_b = has_b || d->b0[i] != 0.0;
+  for (int i = 0; i < 9; ++i) has_b = has_b || d->B[i] != 0.0;
+  if (o->precond == DG_PRECOND_MG && coarse_kind(o->mg.coarse_space, has_b) == COARSE_Q1) {
+    // Q1 hierarchy: vertex levels (27-point stencils), corner sums
+    const int64_t nv = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
+    b += ((nv + nv / 7 + 1) * (27 + 3) + 2 * nv) * both;
+    b += 8 * ncell * both + 128 * 128 * both;
   }
   const size_t pe = o->precond_precision == DG_FP32 ? sizeof(float) : sizeof(double);
   if (o->precond == DG_PRECOND_MG) b += 2 * ndof * pe;

@@ -39,5 +39,6 @@ inline double now_s() {
 }
 
 int validate_solve_opts(const dg_solve_opts *o);
+int validate_mg_opts(const dg_mg_opts *o);
 
 }  // namespace dgmg

@@ -40,6 +40,24 @@ int coarse_prolong(int nx, int ny, int nz, int cnx, int cny, const T *xc, T *x, 
 template <typename T>
 int dense_mv(int n, const T *Ainv, const T *r, T *x, hipStream_t s);
 
+// Q1 vertex-grid levels and transfers (coarse.hip)
+template <typename T>
+int jacobi27(const T *A, const T *dinv, int vx, int vy, int vz, T w, const T *r, const T *xi, T *xo, hipStream_t s);
+template <typename T>
+int residual27(const T *A, int vx, int vy, int vz, const T *r, const T *x, T *out, hipStream_t s);
+template <typename T>
+int restrict27(int vx, int vy, int vz, const T *t, int cx, int cy, int cz, T *rc, hipStream_t s);
+template <typename T>
+int prolong27(int vx, int vy, int vz, int cx, int cy, int cz, const T *xc, T *x, hipStream_t s);
+template <typename T>
+int q1_gather(int nx, int ny, int nz, const T *cs, T *rv, hipStream_t s);
+template <typename T>
+int q1_prolong_add(int p, int nx, int ny, int nz, const T *xv, T *u, hipStream_t s);
+template <typename T>
+int residual7(const T *A, int nx, int ny, int nz, const T *r, const T *x, T *out, hipStream_t s);
+template <typename T>
+int add_to(int64_t n, const T *x, T *y, hipStream_t s);
+
 constexpr int kMaxBasis = 32;
 struct VecList {
   const double *v[kMaxBasis];

@@ -48,6 +48,7 @@ class Workload:
     j: object = None      # Neumann data
     exact: object = None  # exact solution, when known
     info: dict = field(default_factory=dict)
+    coarse: str = "auto"  # coarse space of the V-cycle: "auto" (Q1 if b = 0, else P0), "q1" or "p0"
 
     @property
     def ncell(self) -> int:
@@ -125,7 +126,7 @@ def w3(cells=(60, 220, 85)) -> Workload:
         return out
 
     return Workload("spe10-like-60x220x85-p2", cells, lengths, 2, ("D", "D", "D", "D", "N", "N"), None,
-                    spe10_like_K(cells), f=f)
+                    spe10_like_K(cells), f=f, coarse="p0")
 
 
 def w4(cells=(48, 48, 48), p=3) -> Workload:

@@ -161,6 +161,16 @@ class Problem:
             _stream()))
         return (out, st) if stats else out
 
+    def coarse_stencil(self, coarse_space: int, level: int = 0):
+        """(dims (vx, vy, vz), stencil [ns, vx*vy*vz] float64 numpy, nlevels)
+        of one level of the P0 or Q1 coarse hierarchy."""
+        dims = (ctypes.c_int * 5)()
+        L._check(self.lib.dg_coarse_stencil(self.h, coarse_space, level, dims, None))
+        vx, vy, vz, ns, nlev = list(dims)
+        out = np.empty((ns, vx * vy * vz), dtype=np.float64)
+        L._check(self.lib.dg_coarse_stencil(self.h, coarse_space, level, dims, out.ctypes.data))
+        return (vx, vy, vz), out, nlev
+
     def mg_vcycle(self, r: torch.Tensor, opts: L.MgOpts | None = None, out: torch.Tensor | None = None):
         opts = opts or L.mg_opts()
         if out is None:

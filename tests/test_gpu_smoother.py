@@ -144,7 +144,7 @@ def test_block_jacobi_sweeps(p, with_b):
 
 @pytest.mark.parametrize("p,with_b,npre,npost", [(2, False, 1, 1), (3, False, 2, 1), (2, True, 1, 2), (4, False, 0, 1)])
 def test_vcycle_exact_coarse(p, with_b, npre, npost):
-    from paper_1805_11930_amd import DG_INNER_CG, DG_INNER_GMRES, mg_opts
+    from paper_1805_11930_amd import DG_COARSE_P0, DG_INNER_CG, DG_INNER_GMRES, mg_opts
 
     print(f"V-cycle p={p} b={with_b} pre={npre} post={npost}", flush=True)
     w, opr, A, Db = _setup(p, with_b, cells=(5, 4, 3), seed=7)
@@ -154,7 +154,7 @@ def test_vcycle_exact_coarse(p, with_b, npre, npost):
     ref = solvers.vcycle(A, Db, opr, r, cs, n_pre=npre, n_post=npost, omega=0.9, inner=inner, eps=1e-2, restart=12)
     P = _lib(w)
     o = mg_opts(smooth=dict(omega=0.9, eps=1e-2, inner=DG_INNER_GMRES if with_b else DG_INNER_CG, restart=12),
-                n_pre=npre, n_post=npost)
+                n_pre=npre, n_post=npost, coarse_space=DG_COARSE_P0)
     z = P.mg_vcycle(torch.from_numpy(r).cuda(), o)
     assert rel(z.cpu().numpy(), ref) <= 1e-9
     z32 = P.mg_vcycle(torch.from_numpy(r).float().cuda(), o)
