@@ -9,10 +9,11 @@
 // after the other, the x-line (y=a, z=b), the y-line (x=a, z=b) and the
 // z-line (x=a, y=b) through it: each line is a (p+1)-vector read from LDS,
 // the 1-D operator is applied in registers, and the contributions of the
-// three directions are summed in an LDS accumulator.  Neighbour lines for
-// the face terms come from LDS when the neighbour cell belongs to the same
-// workgroup and from global memory (L2 / MALL hits) otherwise; only four
-// traces per neighbour line are formed.
+// three directions are summed in an LDS accumulator.  The workgroup also
+// stages one cell on either side of its range, so every x-neighbour line is
+// in LDS; the y- and z-neighbour lines are read from global memory (L2 /
+// MALL hits) at the start, together with the staging loads, and reduced to
+// their four face traces at once.
 //
 // XCD-aware order: consecutive workgroup ids are spread round-robin over
 // the eight XCDs, so the logical block index is remapped to give every XCD
@@ -45,41 +46,134 @@ __device__ __host__ inline int line_pos(int k, int i, int a, int b) {
   return k == 0 ? i + N * a + N * N * b : (k == 1 ? a + N * i + N * N * b : a + N * b + N * N * i);
 }
 
-// Stage ncb cells (contiguous in memory) into LDS with 16-byte loads.
-template <typename T>
-__device__ inline void stage_cells(const T *__restrict__ src, T *dst, int count, int tid) {
-  constexpr int V = 16 / sizeof(T);
-  if ((((uintptr_t)src) & 15) == 0) {
-    using VT = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
-    const int nv = count / V;
-    const VT *sv = reinterpret_cast<const VT *>(src);
-    VT *dv = reinterpret_cast<VT *>(dst);
-    for (int i = tid; i < nv; i += kApplyThreads) dv[i] = sv[i];
-    for (int i = nv * V + tid; i < count; i += kApplyThreads) dst[i] = src[i];
-  } else {
-    for (int i = tid; i < count; i += kApplyThreads) dst[i] = src[i];
+// Shared prologue of both apply kernels: every global load of a workgroup
+// is issued before the first one is waited for (the 16-byte loads of its
+// cells plus one cell on either side, the y / z neighbour lines of each
+// lane, the coefficient data), so that each workgroup pays one memory
+// round trip.
+template <int N, typename T, bool NB>
+struct Stage {
+  using S = ApplyShape<N>;
+  static constexpr int N2 = S::N2, N3 = S::N3, CPB = S::CPB;
+  static constexpr int H = NB ? 1 : 0;  // x-halo cells on each side
+  static constexpr int V = 16 / sizeof(T);
+  static constexpr int STAGE = (CPB + 2 * H) * N3 + 2 * V;
+  static constexpr int NVEC = (STAGE / V + kApplyThreads - 1) / kApplyThreads;
+  static constexpr int LDS = NVEC * kApplyThreads * V;
+  using VT = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+};
+
+// Load the staged range [c0 - H, c0 + CPB + H) into registers, from an
+// element offset rounded down to a 16-byte boundary (elements outside
+// [0, ndof) read as zero).  Returns the LDS offset of cell c0 - H.
+template <int N, typename T, bool NB>
+__device__ inline int stage_load(const Geo &g, const T *__restrict__ u, int c0, int tid,
+                                 typename Stage<N, T, NB>::VT (&pre)[Stage<N, T, NB>::NVEC]) {
+  using St = Stage<N, T, NB>;
+  using VT = typename St::VT;
+  constexpr int V = St::V, N3 = St::N3;
+  const int64_t ndof = (int64_t)g.ncell * N3;
+  const int64_t e_first = (int64_t)(c0 - St::H) * N3;
+  const int64_t eb = e_first >= 0 ? (e_first / V) * V : -(((-e_first) + V - 1) / V) * V;
+#pragma unroll
+  for (int j = 0; j < St::NVEC; ++j) {
+    const int64_t e = eb + (int64_t)(j * kApplyThreads + tid) * V;
+    if (e >= 0 && e + V <= ndof) {
+      pre[j] = *reinterpret_cast<const VT *>(u + e);
+    } else {
+      T t[V];
+#pragma unroll
+      for (int q = 0; q < V; ++q) t[q] = (e + q >= 0 && e + q < ndof) ? u[e + q] : T(0);
+      pre[j] = *reinterpret_cast<const VT *>(t);
+    }
+  }
+  return (int)(e_first - eb);
+}
+
+// The y and z neighbour lines of line index (a, b) of cell c (the cell
+// itself where there is no neighbour; those traces are discarded).
+template <int N, typename T>
+__device__ inline void neighbour_lines(const Geo &g, const T *__restrict__ u, int c, const int (&ijk)[3], int a,
+                                       int b, T (&yl)[N], T (&yr)[N], T (&zl)[N], T (&zr)[N]) {
+  constexpr int N3 = N * N * N;
+  const int sy = g.nx, sz = g.nx * g.ny;
+  const T *pyl = u + (size_t)(ijk[1] > 0 ? c - sy : c) * N3;
+  const T *pyr = u + (size_t)(ijk[1] < g.ny - 1 ? c + sy : c) * N3;
+  const T *pzl = u + (size_t)(ijk[2] > 0 ? c - sz : c) * N3;
+  const T *pzr = u + (size_t)(ijk[2] < g.nz - 1 ? c + sz : c) * N3;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    yl[i] = pyl[line_pos<N>(1, i, a, b)];
+    yr[i] = pyr[line_pos<N>(1, i, a, b)];
+    zl[i] = pzl[line_pos<N>(2, i, a, b)];
+    zr[i] = pzr[line_pos<N>(2, i, a, b)];
   }
 }
 
-// Two traces of the same line in a neighbour cell: w0 . line and w1 . line,
-// the line read from LDS when the neighbour is staged, else from global.
-template <typename T, int N>
-__device__ inline void neighbour_traces(bool in_lds, const T *lds_cell, const T *__restrict__ glob_cell, int k, int a,
-                                        int b, const T (&w0)[N], const T (&w1)[N], T &t0, T &t1) {
-  T x[N];
-  if (in_lds) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) x[i] = lds_cell[line_pos<N>(k, i, a, b)];
-  } else {
-#pragma unroll
-    for (int i = 0; i < N; ++i) x[i] = glob_cell[line_pos<N>(k, i, a, b)];
-  }
-  t0 = T(0);
-  t1 = T(0);
+// Value / derivative traces at the shared faces: (e1 . left, d1 . left,
+// e0 . right, d0 . right).
+template <int N, typename T>
+__device__ inline void face_traces(const DevTab<T, N> &tb, const T (&lo)[N], const T (&hi)[N], T (&t)[4]) {
+  t[0] = t[1] = t[2] = t[3] = T(0);
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    t0 += w0[i] * x[i];
-    t1 += w1[i] * x[i];
+    t[0] += tb.e1[i] * lo[i];
+    t[1] += tb.d1[i] * lo[i];
+    t[2] += tb.e0[i] * hi[i];
+    t[3] += tb.d0[i] * hi[i];
+  }
+}
+
+// Residual epilogue (RES = 1: P0 sums, RES = 2: Q1 corner sums) of the
+// x-line (y = xi_a, z = xi_b) of cell c held by lane (cl, ln): qx = (A u)
+// at its N DOFs.  Every lane of the workgroup must call this.
+template <int N, typename T, int RES>
+__device__ inline void residual_epilogue(const DevTab<T, N> &tb, bool active, int c, int cl, int ln, int a, int b,
+                                         const T (&qx)[N], const T *__restrict__ r, T *__restrict__ rh) {
+  constexpr int N2 = N * N, N3 = N * N * N, CPB = ApplyShape<N>::CPB;
+  if constexpr (RES == 2) {
+    // lane (a, b)'s share of corner q is (sum_i L_qx(xi_i) r_i)
+    // L_qy(xi_a) L_qz(xi_b) with L_0 = 1 - xi, L_1 = xi; the shares of the
+    // cell's lanes are summed in LDS
+    __shared__ T part[CPB * 8 * N2];
+    if (active) {
+      const T *rb = r + (size_t)c * N3 + N * a + N2 * b;
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const T ri = rb[i] - qx[i];
+        s0 += (T(1) - tb.xi[i]) * ri;
+        s1 += tb.xi[i] * ri;
+      }
+      const T ly[2] = {T(1) - tb.xi[a], tb.xi[a]};
+      const T lz[2] = {T(1) - tb.xi[b], tb.xi[b]};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) part[(cl * 8 + q) * N2 + ln] = ((q & 1) ? s1 : s0) * ly[(q >> 1) & 1] * lz[q >> 2];
+    }
+    __syncthreads();
+    // a cell has N2 lanes (4 for p = 1): each reduces corners ln, ln + N2, ...
+    if (active) {
+      for (int q = ln; q < 8; q += N2) {
+        T sum = T(0);
+        for (int l = 0; l < N2; ++l) sum += part[(cl * 8 + q) * N2 + l];
+        rh[8 * (size_t)c + q] = sum;
+      }
+    }
+  } else {
+    __shared__ T part[CPB * N2];
+    if (active) {
+      const T *rb = r + (size_t)c * N3 + N * a + N2 * b;
+      T sum = T(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) sum += rb[i] - qx[i];
+      part[cl * N2 + ln] = sum;
+    }
+    __syncthreads();
+    if (active && ln == 0) {
+      T sum = T(0);
+      for (int l = 0; l < N2; ++l) sum += part[cl * N2 + l];
+      rh[c] = sum;
+    }
   }
 }
 
@@ -93,70 +187,108 @@ __device__ inline void neighbour_traces(bool in_lds, const T *lds_cell, const T 
 //   per-cell half of the Q1 restriction R = P^T (Sec. 2.2.2, the nodal
 //   interpolation of the vertex functions); the vertex gather follows in a
 //   separate kernel.
+//
+// Generic kernel (any affine b): lane (cell, a, b) applies the 1-D line
+// operator along x, y and z to its three lines through (a, b); the
+// contributions meet in LDS.
 template <int P, typename T, bool NB, int RES = 0>
 __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restrict__ u, T *__restrict__ v,
                                                          const T *__restrict__ r = nullptr,
                                                          T *__restrict__ rh = nullptr) {
   constexpr int N = P + 1;
-  using S = ApplyShape<N>;
+  using St = Stage<N, T, NB>;
+  constexpr int N2 = St::N2, N3 = St::N3, CPB = St::CPB, H = St::H;
+  using VT = typename St::VT;
   constexpr DevTab<T, N> tb = make_ctab<T, N>();
-  __shared__ T us[S::CPB * S::N3];
-  __shared__ T qs[S::CPB * S::N3];  // y, then y + z contributions
-  __shared__ AxisCoef<T> fcs[S::CPB][3];
+  __shared__ __align__(16) T us[St::LDS];
+  __shared__ T qs[CPB * N3];  // y, then y + z contributions
+  __shared__ AxisCoef<T> fcs[CPB][3];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int c0 = blk * S::CPB;
-  const int ncb = min(S::CPB, g.ncell - c0);
+  const int c0 = blk * CPB;
+  const int ncb = min(CPB, g.ncell - c0);
   const int tid = threadIdx.x;
-  stage_cells<T>(u + (size_t)c0 * S::N3, us, ncb * S::N3, tid);
-  const int cl = tid / S::N2;
-  const int ln = tid - cl * S::N2;
+  const int cl = tid / N2;
+  const int ln = tid - cl * N2;
   const int a = ln % N, b = ln / N;
   const bool active = cl < ncb;
   const int c = c0 + cl;
   int ijk[3] = {0, 0, 0};
-  if (active) {
-    ijk[0] = c % g.nx;
-    ijk[1] = (c / g.nx) % g.ny;
-    ijk[2] = c / (g.nx * g.ny);
-  }
-  // face coefficients: one lane per cell and axis
-  if (active && ln < 3) fcs[cl][ln] = make_axis_coef<T>(g, c, ln, ijk);
-  __syncthreads();
+  if (active) cell_coords(g, c, ijk);
   const int nn[3] = {g.nx, g.ny, g.nz};
   const int stride[3] = {1, g.nx, g.nx * g.ny};
+
+  VT pre[St::NVEC];
+  const int shift = stage_load<N, T, NB>(g, u, c0, tid, pre);
+  T yl[N], yr[N], zl[N], zr[N];
+  if (NB && active) neighbour_lines<N, T>(g, u, c, ijk, a, b, yl, yr, zl, zr);
+  // face coefficients: lane ln < 3 of each cell handles axis ln (neighbour
+  // indices clamped to the cell itself, so that no load waits for another)
+  double kd = 0.0, km = 0.0, kp = 0.0;
+  const bool coef_lane = active && ln < 3;
+  if (coef_lane) {
+    const int k = ln;
+    const int ik = k == 0 ? ijk[0] : (k == 1 ? ijk[1] : ijk[2]);
+    const int nk = k == 0 ? nn[0] : (k == 1 ? nn[1] : nn[2]);
+    const int sk = k == 0 ? 1 : (k == 1 ? stride[1] : stride[2]);
+    kd = g.K[3 * (size_t)c + k];
+    km = g.K[3 * (size_t)(ik > 0 ? c - sk : c) + k];
+    kp = g.K[3 * (size_t)(ik < nk - 1 ? c + sk : c) + k];
+  }
+  const T cre = (active && g.has_c) ? (T)g.c[c] : T(0);
+  const T stan = tb.w[a] * tb.w[b];
+
+  T tr[2][4] = {{T(0), T(0), T(0), T(0)}, {T(0), T(0), T(0), T(0)}};
+  if (NB) {
+    face_traces<N, T>(tb, yl, yr, tr[0]);
+    face_traces<N, T>(tb, zl, zr, tr[1]);
+  }
+#pragma unroll
+  for (int j = 0; j < St::NVEC; ++j) reinterpret_cast<VT *>(us)[j * kApplyThreads + tid] = pre[j];
+  if (coef_lane) {
+    // compile-time axis in each branch: the per-axis mesh data stay scalar
+    if (ln == 0)
+      fcs[cl][0] = axis_coef_from<T>(g, 0, ijk, kd, km, kp);
+    else if (ln == 1)
+      fcs[cl][1] = axis_coef_from<T>(g, 1, ijk, kd, km, kp);
+    else
+      fcs[cl][2] = axis_coef_from<T>(g, 2, ijk, kd, km, kp);
+  }
+  __syncthreads();
+
   const bool hasb = g.has_b != 0;
   const T vol = (T)g.vol;
-  const T stan = tb.w[a] * tb.w[b];
+  const T *own = us + shift + (cl + H) * N3;
   T qx[N], qz[N];
+  if (active) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (active) {
+    for (int k = 0; k < 3; ++k) {
       T ul[N], out[N];
 #pragma unroll
-      for (int i = 0; i < N; ++i) ul[i] = us[cl * S::N3 + line_pos<N>(k, i, a, b)];
-      T tLu = T(0), tLd = T(0), tRu = T(0), tRd = T(0);
+      for (int i = 0; i < N; ++i) ul[i] = own[line_pos<N>(k, i, a, b)];
+      T t[4] = {T(0), T(0), T(0), T(0)};
       if (NB) {
-        if (ijk[k] > 0) {
-          const int cn = c - stride[k];
-          const bool lds = cn >= c0;
-          neighbour_traces<T, N>(lds, us + (lds ? cn - c0 : 0) * S::N3, u + (size_t)cn * S::N3, k, a, b, tb.e1,
-                                 tb.d1, tLu, tLd);
+        if (k == 0) {
+          T lo[N], hi[N];
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            lo[i] = own[line_pos<N>(0, i, a, b) - N3];
+            hi[i] = own[line_pos<N>(0, i, a, b) + N3];
+          }
+          face_traces<N, T>(tb, lo, hi, t);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) t[q] = tr[k - 1][q];
         }
-        if (ijk[k] < nn[k] - 1) {
-          const int cn = c + stride[k];
-          const bool lds = cn < c0 + ncb;
-          neighbour_traces<T, N>(lds, us + (lds ? cn - c0 : 0) * S::N3, u + (size_t)cn * S::N3, k, a, b, tb.e0,
-                                 tb.d0, tRu, tRd);
-        }
+        if (ijk[k] == 0) t[0] = t[1] = T(0);
+        if (ijk[k] == nn[k] - 1) t[2] = t[3] = T(0);
       }
       LineConv<T> lc = {T(0), T(0), T(0), T(0)};
       if (hasb) lc = make_line_conv<T, N>(g, tb, k, ijk, a, b);
-      const T cre = (k == 0 && g.has_c) ? (T)g.c[c] : T(0);
-      line_apply<T, N>(tb, fcs[cl][k], stan, vol, cre, hasb, lc, ul, tLu, tLd, tRu, tRd, out);
+      line_apply<T, N>(tb, fcs[cl][k], stan, vol, k == 0 ? cre : T(0), hasb, lc, ul, t[0], t[1], t[2], t[3], out);
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         if (k == 0) qx[i] = out[i];
-        if (k == 1) qs[cl * S::N3 + line_pos<N>(1, i, a, b)] = out[i];
+        if (k == 1) qs[cl * N3 + line_pos<N>(1, i, a, b)] = out[i];
         if (k == 2) qz[i] = out[i];
       }
     }
@@ -166,60 +298,21 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
   // update the same entry
   if (active) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) qs[cl * S::N3 + line_pos<N>(2, i, a, b)] += qz[i];
+    for (int i = 0; i < N; ++i) qs[cl * N3 + line_pos<N>(2, i, a, b)] += qz[i];
   }
   __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) qx[i] += qs[cl * N3 + line_pos<N>(0, i, a, b)];
+  }
   if constexpr (RES == 0) {
     if (active) {
-      T *vb = v + (size_t)c * S::N3 + N * a + S::N2 * b;
+      T *vb = v + (size_t)c * N3 + N * a + N2 * b;
 #pragma unroll
-      for (int i = 0; i < N; ++i) vb[i] = qx[i] + qs[cl * S::N3 + line_pos<N>(0, i, a, b)];
-    }
-  } else if constexpr (RES == 2) {
-    // lane (a, b) holds the x-line (y = xi_a, z = xi_b) of the residual;
-    // its share of corner q is (sum_i L_qx(xi_i) r_i) L_qy(xi_a) L_qz(xi_b)
-    // with L_0 = 1 - xi, L_1 = xi.  The eight shares of the cell's lanes are
-    // summed in LDS.
-    __shared__ T part[S::CPB * 8 * S::N2];
-    if (active) {
-      const T *rb = r + (size_t)c * S::N3 + N * a + S::N2 * b;
-      T s0 = T(0), s1 = T(0);
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const T ri = rb[i] - (qx[i] + qs[cl * S::N3 + line_pos<N>(0, i, a, b)]);
-        s0 += (T(1) - tb.xi[i]) * ri;
-        s1 += tb.xi[i] * ri;
-      }
-      const T ly[2] = {T(1) - tb.xi[a], tb.xi[a]};
-      const T lz[2] = {T(1) - tb.xi[b], tb.xi[b]};
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        part[(cl * 8 + q) * S::N2 + ln] = ((q & 1) ? s1 : s0) * ly[(q >> 1) & 1] * lz[q >> 2];
-    }
-    __syncthreads();
-    // a cell has N2 lanes (4 for p = 1): each reduces corners ln, ln + N2, ...
-    if (active) {
-      for (int q = ln; q < 8; q += S::N2) {
-        T sum = T(0);
-        for (int l = 0; l < S::N2; ++l) sum += part[(cl * 8 + q) * S::N2 + l];
-        rh[8 * (size_t)c + q] = sum;
-      }
+      for (int i = 0; i < N; ++i) vb[i] = qx[i];
     }
   } else {
-    __shared__ T part[S::CPB * S::N2];
-    if (active) {
-      const T *rb = r + (size_t)c * S::N3 + N * a + S::N2 * b;
-      T sum = T(0);
-#pragma unroll
-      for (int i = 0; i < N; ++i) sum += rb[i] - (qx[i] + qs[cl * S::N3 + line_pos<N>(0, i, a, b)]);
-      part[cl * S::N2 + ln] = sum;
-    }
-    __syncthreads();
-    if (active && ln == 0) {
-      T sum = T(0);
-      for (int l = 0; l < S::N2; ++l) sum += part[cl * S::N2 + l];
-      rh[c] = sum;
-    }
+    residual_epilogue<N, T, RES>(tb, active, c, cl, ln, a, b, qx, r, rh);
   }
 }
 

@@ -58,11 +58,31 @@ constexpr DevTab<T, N> make_ctab() {
   return d;
 }
 
+// Exact division of 0 <= n < 2^31 by a fixed divisor d >= 1 with one
+// multiply and one shift (Granlund and Montgomery, "Division by invariant
+// integers using multiplication", 1994): m = ceil(2^s / d) with
+// s = 31 + ceil(log2 d) fits in 32 bits and q = (n m) >> s.
+struct FastDiv {
+  uint32_t m = 1;
+  int s = 0;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  f.s = 31 + l;
+  f.m = (uint32_t)(((1ull << f.s) + d - 1) / d);
+  return f;
+}
+__host__ __device__ inline int fdiv(int n, FastDiv f) { return (int)(((uint64_t)(uint32_t)n * f.m) >> f.s); }
+
 // Mesh, coefficients and discretisation constants passed to kernels.
 struct Geo {
   int nx, ny, nz;
   int ncell;
+  FastDiv fx, fxy;  // division by nx and by nx * ny
   double h[3];
+  double ih[3];     // 1 / h
   double vol;
   double sigma;   // penalty prefactor
   int bc[6];      // FACE_DIRICHLET / FACE_NEUMANN per box face

@@ -50,18 +50,18 @@ struct LineConv {
   T beta, Bkk, xk0, hk;
 };
 
+// Face coefficients from K_kk of the cell (d) and of its neighbours below
+// and above along k (dm, dp; not read where there is no neighbour).
 template <typename T>
-__host__ __device__ inline AxisCoef<T> make_axis_coef(const Geo &g, int cell, int k, const int (&ijk)[3]) {
+__host__ __device__ inline AxisCoef<T> axis_coef_from(const Geo &g, int k, const int (&ijk)[3], double d, double dm,
+                                                      double dp) {
   AxisCoef<T> f;
   const int nn[3] = {g.nx, g.ny, g.nz};
-  const int stride[3] = {1, g.nx, g.nx * g.ny};
-  const double d = g.K[3 * cell + k];
-  const double ih = 1.0 / g.h[k];
+  const double ih = g.ih[k];
   double kL = 0.0, gL = 0.0, kR = 0.0, gR = 0.0;
   int fl = 0;
   if (ijk[k] > 0) {
-    const double dn = g.K[3 * (cell - stride[k]) + k];
-    kL = d * dn / (d + dn);
+    kL = d * dm / (d + dm);
     gL = 2.0 * g.sigma * kL * ih;
     fl |= 1 | 4;
   } else if (g.bc[2 * k] == FACE_DIRICHLET) {
@@ -70,8 +70,7 @@ __host__ __device__ inline AxisCoef<T> make_axis_coef(const Geo &g, int cell, in
     fl |= 1;
   }
   if (ijk[k] < nn[k] - 1) {
-    const double dn = g.K[3 * (cell + stride[k]) + k];
-    kR = d * dn / (d + dn);
+    kR = d * dp / (d + dp);
     gR = 2.0 * g.sigma * kR * ih;
     fl |= 2 | 8;
   } else if (g.bc[2 * k + 1] == FACE_DIRICHLET) {
@@ -87,6 +86,26 @@ __host__ __device__ inline AxisCoef<T> make_axis_coef(const Geo &g, int cell, in
   f.ih = (T)ih;
   f.fl = fl;
   return f;
+}
+
+template <typename T>
+__host__ __device__ inline AxisCoef<T> make_axis_coef(const Geo &g, int cell, int k, const int (&ijk)[3]) {
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  const int stride[3] = {1, g.nx, g.nx * g.ny};
+  const double d = g.K[3 * cell + k];
+  const double dm = ijk[k] > 0 ? g.K[3 * (cell - stride[k]) + k] : d;
+  const double dp = ijk[k] < nn[k] - 1 ? g.K[3 * (cell + stride[k]) + k] : d;
+  return axis_coef_from<T>(g, k, ijk, d, dm, dp);
+}
+
+// Cell coordinates (ix, iy, iz) of cell c.
+__host__ __device__ inline void cell_coords(const Geo &g, int c, int (&ijk)[3]) {
+  const int iz = fdiv(c, g.fxy);
+  const int rem = c - iz * (g.nx * g.ny);
+  const int iy = fdiv(rem, g.fx);
+  ijk[0] = rem - iy * g.nx;
+  ijk[1] = iy;
+  ijk[2] = iz;
 }
 
 // Advection data of the line along axis k through cell ijk with tangential

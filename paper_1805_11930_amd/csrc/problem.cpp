@@ -403,6 +403,9 @@ int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
   g.h[1] = d->ly / d->ny;
   g.h[2] = d->lz / d->nz;
   g.vol = g.h[0] * g.h[1] * g.h[2];
+  for (int k = 0; k < 3; ++k) g.ih[k] = 1.0 / g.h[k];
+  g.fx = make_fastdiv((uint32_t)d->nx);
+  g.fxy = make_fastdiv((uint32_t)(d->nx * d->ny));
   g.sigma = d->penalty_factor > 0 ? d->penalty_factor : 1.25 * d->p * (d->p + 2);
   for (int f = 0; f < 6; ++f) g.bc[f] = d->bc[f] == DG_BC_DIRICHLET ? FACE_DIRICHLET : FACE_NEUMANN;
   g.has_b = 0;
