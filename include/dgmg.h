@@ -126,6 +126,9 @@ typedef struct {
   int coarse_cycles;        /* V-cycles of the coarse solver (0 or 1: one)  */
   int coarse_smooth;        /* Jacobi sweeps per level (0: 2), 0..64        */
   double coarse_omega;      /* Jacobi damping on the coarse levels (<= 0: 2/3) */
+  int graph;                /* 1: replay the coarse solve from a HIP graph
+                               (captured on first use per option set, kernel
+                               nodes only); 0: launch its kernels directly */
 } dg_mg_opts;
 
 /* Outer solve options (Sec. 4.2: CG to 1e-8; Sec. 4.3: flexible GMRES). */

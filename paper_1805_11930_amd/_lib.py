@@ -68,7 +68,8 @@ class SmoothStats(ctypes.Structure):
 class MgOpts(ctypes.Structure):
     _fields_ = [
         ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int), ("smooth", SmoothOpts),
-        ("coarse_space", ctypes.c_int), ("coarse_cycles", ctypes.c_int), ("coarse_smooth", ctypes.c_int), ("coarse_omega", ctypes.c_double),
+        ("coarse_space", ctypes.c_int), ("coarse_cycles", ctypes.c_int), ("coarse_smooth", ctypes.c_int),
+        ("coarse_omega", ctypes.c_double), ("graph", ctypes.c_int),
     ]
 
 

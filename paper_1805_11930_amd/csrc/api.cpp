@@ -143,9 +143,11 @@ int level_jacobi(const CoarseLevel &L, T w, const T *r, const T *xi, T *xo, hipS
 
 // x_l ~= A_l^-1 r_l: one V-cycle of the hierarchy from a zero guess; r_l is
 // level l's r buffer, the result is left in one of level l's x / t buffers
-// and returned in *result.
+// and returned in *result.  x_init: level l's x buffer already holds the
+// first damped Jacobi sweep from zero, w D^-1 r_l (fused into the kernel
+// that produced r_l).
 template <typename T>
-int coarse_cycle(Hierarchy &H, size_t l, int nu, T w, hipStream_t s, T **result) {
+int coarse_cycle(Hierarchy &H, size_t l, int nu, T w, hipStream_t s, T **result, bool x_init) {
   using LP = LevelPtr<T>;
   CoarseLevel &L = H.levels[l];
   if (l + 1 == H.levels.size()) {
@@ -156,20 +158,23 @@ int coarse_cycle(Hierarchy &H, size_t l, int nu, T w, hipStream_t s, T **result)
   T *x = LP::x(L), *t = LP::t(L);
   const T *A = LP::A(L), *r = LP::r(L);
   // presmooth from zero: x = w D^-1 r, then nu-1 more sweeps
-  if ((rc = level_jacobi<T>(L, w, r, nullptr, x, s))) return rc;
+  if (!x_init && (rc = level_jacobi<T>(L, w, r, nullptr, x, s))) return rc;
   for (int k = 1; k < nu; ++k) {
     if ((rc = level_jacobi<T>(L, w, r, x, t, s))) return rc;
     std::swap(x, t);
   }
   CoarseLevel &C = H.levels[l + 1];
+  const bool fuse = L.ns == 27 && l + 2 < H.levels.size();  // the coarser level smooths
   if (L.ns == 27) {
     if ((rc = residual27<T>(A, L.nx, L.ny, L.nz, r, x, t, s))) return rc;
-    if ((rc = restrict27<T>(L.nx, L.ny, L.nz, t, C.nx, C.ny, C.nz, LP::r(C), s))) return rc;
+    if ((rc = restrict27<T>(L.nx, L.ny, L.nz, t, C.nx, C.ny, C.nz, LP::r(C), LP::dinv(C), w,
+                            fuse ? LP::x(C) : nullptr, s)))
+      return rc;
   } else if ((rc = coarse_restrict<T>(A, L.nx, L.ny, L.nz, r, x, C.nx, C.ny, C.nz, LP::r(C), s))) {
     return rc;
   }
   T *xc = nullptr;
-  if ((rc = coarse_cycle<T>(H, l + 1, nu, w, s, &xc))) return rc;
+  if ((rc = coarse_cycle<T>(H, l + 1, nu, w, s, &xc, fuse))) return rc;
   if (L.ns == 27)
     rc = prolong27<T>(L.nx, L.ny, L.nz, C.nx, C.ny, C.nz, xc, x, s);
   else
@@ -185,30 +190,78 @@ int coarse_cycle(Hierarchy &H, size_t l, int nu, T w, hipStream_t s, T **result)
 
 // x_0 ~= A_0^-1 r_0 on level 0 of H by `cycles` V-cycles (a fixed number,
 // so the result is a linear function of r_0): x += V(r_0 - A_0 x).
+// x_init as for coarse_cycle (first cycle only).  Kernels only: the
+// sequence can be captured into a HIP graph.
 template <typename T>
-int coarse_solve(Hierarchy &H, int cycles, int nu, T w, hipStream_t s, T **result) {
+int coarse_solve(Hierarchy &H, int cycles, int nu, T w, hipStream_t s, T **result, bool x_init) {
   using LP = LevelPtr<T>;
   CoarseLevel &L = H.levels[0];
-  if (cycles <= 1 || H.levels.size() == 1) return coarse_cycle<T>(H, 0, nu, w, s, result);
+  if (cycles <= 1 || H.levels.size() == 1) return coarse_cycle<T>(H, 0, nu, w, s, result, x_init);
   const int64_t n = L.n;
   T *acc = LP::acc(L), *rs = LP::rs(L);
   int rc;
-  DG_HIP(hipMemcpyAsync(rs, LP::r(L), n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  if ((rc = copy_vec<T>(n, LP::r(L), rs, s))) return rc;
   T *x = nullptr;
-  if ((rc = coarse_cycle<T>(H, 0, nu, w, s, &x))) return rc;
-  DG_HIP(hipMemcpyAsync(acc, x, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  if ((rc = coarse_cycle<T>(H, 0, nu, w, s, &x, x_init))) return rc;
+  if ((rc = copy_vec<T>(n, x, acc, s))) return rc;
   for (int c = 1; c < cycles; ++c) {
     if (L.ns == 27)
       rc = residual27<T>(LP::A(L), L.nx, L.ny, L.nz, rs, acc, LP::r(L), s);
     else
       rc = residual7<T>(LP::A(L), L.nx, L.ny, L.nz, rs, acc, LP::r(L), s);
     if (rc) return rc;
-    if ((rc = coarse_cycle<T>(H, 0, nu, w, s, &x))) return rc;
+    if ((rc = coarse_cycle<T>(H, 0, nu, w, s, &x, false))) return rc;
     if ((rc = add_to<T>(n, x, acc, s))) return rc;
   }
   // restore r_0 for callers that read it again
-  DG_HIP(hipMemcpyAsync(LP::r(L), rs, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  if ((rc = copy_vec<T>(n, rs, LP::r(L), s))) return rc;
   *result = acc;
+  return DG_OK;
+}
+
+// The coarse solve replayed from a HIP graph: captured once per hierarchy,
+// precision and cycle parameters on a private stream of default priority,
+// then launched on the caller's stream.  The graph holds kernel nodes only.
+template <typename T>
+int coarse_solve_graph(dg_problem *pr, Hierarchy &H, int prec, int cycles, int nu, T w, hipStream_t s, T **result,
+                       bool x_init) {
+  CoarseGraph *hit = nullptr;
+  for (auto &cg : pr->graphs)
+    if (cg.kind == H.kind && cg.prec == prec && cg.cycles == cycles && cg.nu == nu && cg.w == (double)w &&
+        cg.x_init == x_init) {
+      hit = &cg;
+      break;
+    }
+  if (!hit) {
+    if (!pr->capture_stream) DG_HIP(hipStreamCreateWithFlags(&pr->capture_stream, hipStreamNonBlocking));
+    DG_HIP(hipStreamBeginCapture(pr->capture_stream, hipStreamCaptureModeThreadLocal));
+    T *res = nullptr;
+    int rc = coarse_solve<T>(H, cycles, nu, w, pr->capture_stream, &res, x_init);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(pr->capture_stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) return hip_fail(e2, "hipGraphInstantiate");
+    CoarseGraph cg;
+    cg.kind = H.kind;
+    cg.prec = prec;
+    cg.cycles = cycles;
+    cg.nu = nu;
+    cg.w = (double)w;
+    cg.x_init = x_init;
+    cg.exec = exec;
+    cg.result = res;
+    pr->graphs.push_back(cg);
+    hit = &pr->graphs.back();
+  }
+  DG_HIP(hipGraphLaunch(hit->exec, s));
+  *result = (T *)hit->result;
   return DG_OK;
 }
 
@@ -229,17 +282,26 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
   // residual and restriction R = P^T
   using LP = LevelPtr<T>;
   CoarseLevel &L0 = H.levels[0];
+  const int nu = o->coarse_smooth > 0 ? o->coarse_smooth : 2;
+  const T w = (T)(o->coarse_omega > 0 ? o->coarse_omega : 2.0 / 3.0);
+  bool x_init = false;
   if (kind == COARSE_Q1) {
     T *cs = (T *)pr->corner_buf[prec];
     if ((rc = launch_residual_restrict(pr, prec, X, r, cs, s, COARSE_Q1))) return rc;
-    if ((rc = q1_gather<T>(pr->geo.nx, pr->geo.ny, pr->geo.nz, cs, LP::r(L0), s))) return rc;
+    x_init = H.levels.size() > 1;  // level 0 smooths: fuse its first sweep into the gather
+    if ((rc = q1_gather<T>(pr->geo.nx, pr->geo.ny, pr->geo.nz, cs, LP::r(L0), LP::dinv(L0), w,
+                           x_init ? LP::x(L0) : nullptr, s)))
+      return rc;
   } else if ((rc = launch_residual_restrict(pr, prec, X, r, LP::r(L0), s, COARSE_P0))) {
     return rc;
   }
-  const int nu = o->coarse_smooth > 0 ? o->coarse_smooth : 2;
-  const T w = (T)(o->coarse_omega > 0 ? o->coarse_omega : 2.0 / 3.0);
+  const int cycles = o->coarse_cycles > 1 ? o->coarse_cycles : 1;
   T *xh = nullptr;
-  if ((rc = coarse_solve<T>(H, o->coarse_cycles, nu, w, s, &xh))) return rc;
+  if (o->graph)
+    rc = coarse_solve_graph<T>(pr, H, prec, cycles, nu, w, s, &xh, x_init);
+  else
+    rc = coarse_solve<T>(H, cycles, nu, w, s, &xh, x_init);
+  if (rc) return rc;
   if (kind == COARSE_Q1) {
     // prolongation P (nodal interpolation of the trilinear correction)
     if ((rc = q1_prolong_add<T>(pr->p, pr->geo.nx, pr->geo.ny, pr->geo.nz, xh, (T *)X, s))) return rc;
@@ -280,6 +342,7 @@ void dg_default_mg_opts(dg_mg_opts *o) {
   o->coarse_cycles = 1;
   o->coarse_smooth = 4;
   o->coarse_omega = 2.0 / 3.0;
+  o->graph = 1;
 }
 
 void dg_default_solve_opts(dg_solve_opts *o) {

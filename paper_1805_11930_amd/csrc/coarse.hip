@@ -33,24 +33,27 @@ __device__ inline W1 interp1(int i, int vf, int vc) {
   return {i >> 1, true};
 }
 
+// (A x)_i for the 27-point stencil.  Couplings to unknowns outside the grid
+// are exact zeros in every level's stencil (the level-0 matrix only couples
+// vertices of a common cell, and Galerkin products keep that), so the
+// neighbour index is clamped into the grid instead of branching: all 54
+// loads are independent and issue at once.
 template <typename T>
 __device__ inline T stencil27(const T *__restrict__ A, int64_t n, const T *__restrict__ x, int64_t i, int ix, int iy,
                               int iz, int vx, int vy, int vz) {
+  const int ox[3] = {ix > 0 ? -1 : 0, 0, ix < vx - 1 ? 1 : 0};
+  const int64_t oy[3] = {iy > 0 ? -(int64_t)vx : 0, 0, iy < vy - 1 ? (int64_t)vx : 0};
+  const int64_t oz[3] = {iz > 0 ? -(int64_t)vx * vy : 0, 0, iz < vz - 1 ? (int64_t)vx * vy : 0};
   T s = T(0);
 #pragma unroll
-  for (int dz = -1; dz <= 1; ++dz) {
-    if (iz + dz < 0 || iz + dz >= vz) continue;
+  for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      if (iy + dy < 0 || iy + dy >= vy) continue;
+    for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        if (ix + dx < 0 || ix + dx >= vx) continue;
-        const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
-        s += A[o * n + i] * x[i + dx + (int64_t)vx * (dy + (int64_t)vy * dz)];
+      for (int dx = 0; dx < 3; ++dx) {
+        const int o = dx + 3 * dy + 9 * dz;
+        s += A[o * n + i] * x[i + ox[dx] + oy[dy] + oz[dz]];
       }
-    }
-  }
   return s;
 }
 
@@ -84,9 +87,11 @@ __global__ void k_residual27(const T *__restrict__ A, int vx, int vy, int vz, co
 
 // rc = P^T t: coarse J gathers the fine vertices within one fine step of
 // its own fine position, with their interpolation weights towards J.
+// When xz is not null, also xz = w dinv rc: the first damped Jacobi sweep
+// from zero on the coarse level.
 template <typename T>
 __global__ void k_restrict27(int vx, int vy, int vz, const T *__restrict__ t, int cx, int cy, int cz,
-                             T *__restrict__ rc) {
+                             T *__restrict__ rc, const T *__restrict__ dinv, T w, T *__restrict__ xz) {
   const int64_t nc = (int64_t)cx * cy * cz;
   const int64_t J = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (J >= nc) return;
@@ -121,6 +126,7 @@ __global__ void k_restrict27(int vx, int vy, int vz, const T *__restrict__ t, in
       for (int a = 0; a < cnt[0]; ++a)
         s += fw[0][a] * fw[1][b] * fw[2][c] * t[fi[0][a] + (int64_t)vx * (fi[1][b] + (int64_t)vy * fi[2][c])];
   rc[J] = s;
+  if (xz) xz[J] = w * dinv[J] * s;
 }
 
 // x += P xc (trilinear interpolation from the coarser vertex level)
@@ -157,7 +163,8 @@ __global__ void k_prolong27(int vx, int vy, int vz, int cx, int cy, int cz, cons
 // Q1 prolongation, second half (the first half, the per-cell corner sums,
 // is fused into the residual kernel).
 template <typename T>
-__global__ void k_q1_gather(int nx, int ny, int nz, const T *__restrict__ cs, T *__restrict__ rv) {
+__global__ void k_q1_gather(int nx, int ny, int nz, const T *__restrict__ cs, T *__restrict__ rv,
+                            const T *__restrict__ dinv, T w, T *__restrict__ xz) {
   const int vx = nx + 1, vy = ny + 1;
   const int64_t n = (int64_t)vx * vy * (nz + 1);
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -183,6 +190,7 @@ __global__ void k_q1_gather(int nx, int ny, int nz, const T *__restrict__ cs, T 
     }
   }
   rv[v] = s;
+  if (xz) xz[v] = w * dinv[v] * s;
 }
 
 // u += P x_hat: every DG node receives the trilinear interpolant of the
@@ -237,6 +245,12 @@ __global__ void k_add(int64_t n, const T *__restrict__ x, T *__restrict__ y) {
   if (i < n) y[i] += x[i];
 }
 
+template <typename T>
+__global__ void k_copy(int64_t n, const T *__restrict__ x, T *__restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+
 }  // namespace
 
 template <typename T>
@@ -253,9 +267,10 @@ int residual27(const T *A, int vx, int vy, int vz, const T *r, const T *x, T *ou
   return DG_OK;
 }
 template <typename T>
-int restrict27(int vx, int vy, int vz, const T *t, int cx, int cy, int cz, T *rc, hipStream_t s) {
+int restrict27(int vx, int vy, int vz, const T *t, int cx, int cy, int cz, T *rc, const T *dinv, T w, T *xz,
+               hipStream_t s) {
   hipLaunchKernelGGL((k_restrict27<T>), grid_for((int64_t)cx * cy * cz), dim3(256), 0, s, vx, vy, vz, t, cx, cy, cz,
-                     rc);
+                     rc, dinv, w, xz);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
@@ -267,9 +282,9 @@ int prolong27(int vx, int vy, int vz, int cx, int cy, int cz, const T *xc, T *x,
   return DG_OK;
 }
 template <typename T>
-int q1_gather(int nx, int ny, int nz, const T *cs, T *rv, hipStream_t s) {
+int q1_gather(int nx, int ny, int nz, const T *cs, T *rv, const T *dinv, T w, T *xz, hipStream_t s) {
   hipLaunchKernelGGL((k_q1_gather<T>), grid_for((int64_t)(nx + 1) * (ny + 1) * (nz + 1)), dim3(256), 0, s, nx, ny,
-                     nz, cs, rv);
+                     nz, cs, rv, dinv, w, xz);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
@@ -299,16 +314,23 @@ int add_to(int64_t n, const T *x, T *y, hipStream_t s) {
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
+template <typename T>
+int copy_vec(int64_t n, const T *x, T *y, hipStream_t s) {
+  hipLaunchKernelGGL((k_copy<T>), grid_for(n), dim3(256), 0, s, n, x, y);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
 
 #define DG_INST(T)                                                                                        \
   template int jacobi27<T>(const T *, const T *, int, int, int, T, const T *, const T *, T *, hipStream_t); \
   template int residual27<T>(const T *, int, int, int, const T *, const T *, T *, hipStream_t);           \
-  template int restrict27<T>(int, int, int, const T *, int, int, int, T *, hipStream_t);                  \
+  template int restrict27<T>(int, int, int, const T *, int, int, int, T *, const T *, T, T *, hipStream_t); \
   template int prolong27<T>(int, int, int, int, int, int, const T *, T *, hipStream_t);                   \
-  template int q1_gather<T>(int, int, int, const T *, T *, hipStream_t);                                  \
+  template int q1_gather<T>(int, int, int, const T *, T *, const T *, T, T *, hipStream_t);                \
   template int q1_prolong_add<T>(int, int, int, int, const T *, T *, hipStream_t);                        \
   template int residual7<T>(const T *, int, int, int, const T *, const T *, T *, hipStream_t);            \
-  template int add_to<T>(int64_t, const T *, T *, hipStream_t);
+  template int add_to<T>(int64_t, const T *, T *, hipStream_t);                                           \
+  template int copy_vec<T>(int64_t, const T *, T *, hipStream_t);
 DG_INST(double)
 DG_INST(float)
 #undef DG_INST

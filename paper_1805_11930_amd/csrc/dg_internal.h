@@ -129,6 +129,15 @@ inline int coarse_kind(int option, bool has_b) {
   return COARSE_P0;
 }
 
+// A captured coarse solve (see coarse_solve_graph).
+struct CoarseGraph {
+  int kind, prec, cycles, nu;
+  double w;
+  bool x_init;
+  hipGraphExec_t exec;
+  void *result;  // device buffer that holds the coarse solution after a launch
+};
+
 struct Hierarchy {
   int kind = COARSE_P0;
   int built = 0;  // 0: not yet, 1: ready, < 0: failed with that status
@@ -154,6 +163,8 @@ struct dg_problem {
   // coarse hierarchies: P0 (built with the problem) and Q1 (on first use)
   dgmg::Hierarchy p0h, q1h;
   void *corner_buf[2] = {nullptr, nullptr};  // [ncell][8] Q1 corner sums per precision
+  std::vector<dgmg::CoarseGraph> graphs;      // captured coarse solves
+  hipStream_t capture_stream = nullptr;       // private stream used only for capturing
   // DG-sized temporaries for the V-cycle and smoother (allocated lazily)
   void *mg_tmp[2][4] = {{nullptr}};  // [precision][k]
   int *iters_buf = nullptr;          // [ncell]

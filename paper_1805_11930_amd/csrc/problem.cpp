@@ -309,6 +309,8 @@ void dg_problem_destroy(dg_problem *pr) {
     (void)hipFree(H->inv32);
   }
   for (void *p : pr->corner_buf) (void)hipFree(p);
+  for (auto &cg : pr->graphs) (void)hipGraphExecDestroy(cg.exec);
+  if (pr->capture_stream) (void)hipStreamDestroy(pr->capture_stream);
   for (auto &row : pr->mg_tmp)
     for (void *p : row) (void)hipFree(p);
   (void)hipFree(pr->iters_buf);

@@ -46,17 +46,20 @@ int jacobi27(const T *A, const T *dinv, int vx, int vy, int vz, T w, const T *r,
 template <typename T>
 int residual27(const T *A, int vx, int vy, int vz, const T *r, const T *x, T *out, hipStream_t s);
 template <typename T>
-int restrict27(int vx, int vy, int vz, const T *t, int cx, int cy, int cz, T *rc, hipStream_t s);
+int restrict27(int vx, int vy, int vz, const T *t, int cx, int cy, int cz, T *rc, const T *dinv, T w, T *xz,
+               hipStream_t s);
 template <typename T>
 int prolong27(int vx, int vy, int vz, int cx, int cy, int cz, const T *xc, T *x, hipStream_t s);
 template <typename T>
-int q1_gather(int nx, int ny, int nz, const T *cs, T *rv, hipStream_t s);
+int q1_gather(int nx, int ny, int nz, const T *cs, T *rv, const T *dinv, T w, T *xz, hipStream_t s);
 template <typename T>
 int q1_prolong_add(int p, int nx, int ny, int nz, const T *xv, T *u, hipStream_t s);
 template <typename T>
 int residual7(const T *A, int nx, int ny, int nz, const T *r, const T *x, T *out, hipStream_t s);
 template <typename T>
 int add_to(int64_t n, const T *x, T *y, hipStream_t s);
+template <typename T>
+int copy_vec(int64_t n, const T *x, T *y, hipStream_t s);
 
 constexpr int kMaxBasis = 32;
 struct VecList {

@@ -126,7 +126,7 @@ def w3(cells=(60, 220, 85)) -> Workload:
         return out
 
     return Workload("spe10-like-60x220x85-p2", cells, lengths, 2, ("D", "D", "D", "D", "N", "N"), None,
-                    spe10_like_K(cells), f=f, coarse="p0")
+                    spe10_like_K(cells), f=f)
 
 
 def w4(cells=(48, 48, 48), p=3) -> Workload:

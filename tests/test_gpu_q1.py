@@ -208,3 +208,31 @@ def test_q1_rejects_bad_options():
     with pytest.raises(DgError):
         P.coarse_stencil(1, 99)
     P.close()
+
+
+@pytest.mark.parametrize("space", ["p0", "q1"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("cycles", [1, 3])
+def test_coarse_graph_replays_equal_eager(space, prec, cycles):
+    """The coarse solve replayed from its captured HIP graph gives the same
+    bits as the eager launches, on every replay, with other eager work and
+    synchronisations in between (the graph holds kernel nodes only)."""
+    from paper_1805_11930_amd import DG_COARSE_P0, DG_COARSE_Q1, mg_opts
+
+    w = inputs.random_case(2, cells=(9, 7, 6), seed=21)
+    P = _lib(w)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    cs = DG_COARSE_Q1 if space == "q1" else DG_COARSE_P0
+    assert P.coarse_stencil(cs, 0)[2] >= 2  # a real multilevel coarse cycle
+    base = dict(coarse_space=cs, coarse_cycles=cycles)
+    rs = [torch.from_numpy(inputs.random_vector(P.ndof, 50 + k)).to(dt).cuda() for k in range(3)]
+    eager = [P.mg_vcycle(r, mg_opts(graph=0, **base)).clone() for r in rs]
+    junk = torch.empty_like(rs[0])
+    for rep in range(3):
+        for k, r in enumerate(rs):
+            z = P.mg_vcycle(r, mg_opts(graph=1, **base))
+            torch.cuda.synchronize()
+            assert torch.equal(z, eager[k]), (rep, k)
+            P.apply(rs[(k + 1) % 3], junk)  # eager work between replays
+            P.mg_vcycle(rs[(k + 2) % 3], mg_opts(graph=0, **base), out=junk)
+    P.close()
