@@ -57,7 +57,7 @@ extern "C" {
 
 enum { DG_FP64 = 0, DG_FP32 = 1 };
 enum { DG_BC_DIRICHLET = 0, DG_BC_NEUMANN = 1 };
-enum { DG_INNER_CG = 0, DG_INNER_GMRES = 1 };
+enum { DG_INNER_CG = 0, DG_INNER_GMRES = 1, DG_INNER_FDM = 2 };
 enum { DG_KRYLOV_CG = 0, DG_KRYLOV_FCG = 1, DG_KRYLOV_FGMRES = 2 };
 enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK_JACOBI = 1, DG_PRECOND_MG = 2 };
 enum { DG_COARSE_P0 = 0, DG_COARSE_Q1 = 1, DG_COARSE_AUTO = 2 };
@@ -90,7 +90,11 @@ typedef struct {
   double omega;     /* damping, W = omega^-1 D                              */
   double eps;       /* inner stop: ||d_T - D_T x||_2 <= eps ||d_T||_2       */
   int max_inner;    /* cap on D_T applications per block (<= 0: (p+1)^3)   */
-  int inner;        /* DG_INNER_CG (b = 0) or DG_INNER_GMRES               */
+  int inner;        /* DG_INNER_CG (b = 0) or DG_INNER_GMRES, the paper's
+                       iterative block solves; DG_INNER_FDM (b = 0 only):
+                       exact block solve with stored per-cell factors (fast
+                       diagonalisation of the Kronecker-sum block, built on
+                       first use; eps, max_inner, restart are ignored)     */
   int restart;      /* inner GMRES restart length (<= 0: 16)               */
   int zero_guess;   /* 1: u_in is taken as zero and not read                */
 } dg_smooth_opts;

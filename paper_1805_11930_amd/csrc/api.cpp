@@ -57,14 +57,20 @@ int check_prec(int prec) {
   return DG_OK;
 }
 
-int smooth_args(const dg_problem *pr, const dg_smooth_opts *o, SmoothArgs &a) {
+int smooth_args(dg_problem *pr, const dg_smooth_opts *o, SmoothArgs &a) {
   if (!o) {
     set_error("smoother options are NULL");
     return DG_EINVAL;
   }
-  if (!(o->eps >= 0) || !std::isfinite(o->omega) || (o->inner != DG_INNER_CG && o->inner != DG_INNER_GMRES)) {
-    set_error("invalid smoother options (eps >= 0, finite omega, inner CG or GMRES)");
+  if (!(o->eps >= 0) || !std::isfinite(o->omega) ||
+      (o->inner != DG_INNER_CG && o->inner != DG_INNER_GMRES && o->inner != DG_INNER_FDM)) {
+    set_error("invalid smoother options (eps >= 0, finite omega, inner CG, GMRES or FDM)");
     return DG_EINVAL;
+  }
+  if (o->inner == DG_INNER_FDM) {
+    int rc = ensure_fdm(pr, DG_FP64);
+    if (!rc) rc = ensure_fdm(pr, DG_FP32);
+    if (rc) return rc;
   }
   a.omega = o->omega;
   a.eps = o->eps;

@@ -163,6 +163,7 @@ struct dg_problem {
   // coarse hierarchies: P0 (built with the problem) and Q1 (on first use)
   dgmg::Hierarchy p0h, q1h;
   void *corner_buf[2] = {nullptr, nullptr};  // [ncell][8] Q1 corner sums per precision
+  void *fdm[2] = {nullptr, nullptr};          // fast-diagonalisation factors per precision
   std::vector<dgmg::CoarseGraph> graphs;      // captured coarse solves
   hipStream_t capture_stream = nullptr;       // private stream used only for capturing
   // DG-sized temporaries for the V-cycle and smoother (allocated lazily)
@@ -203,5 +204,7 @@ struct SmoothArgs {
 };
 int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin, void *uout,
                   const SmoothArgs &a, int *iters, hipStream_t s);
+// fast-diagonalisation factors of the cell blocks (b = 0), built on first use
+int ensure_fdm(dg_problem *pr, int prec);
 
 }  // namespace dgmg

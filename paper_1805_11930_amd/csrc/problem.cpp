@@ -309,6 +309,7 @@ void dg_problem_destroy(dg_problem *pr) {
     (void)hipFree(H->inv32);
   }
   for (void *p : pr->corner_buf) (void)hipFree(p);
+  for (void *p : pr->fdm) (void)hipFree(p);
   for (auto &cg : pr->graphs) (void)hipGraphExecDestroy(cg.exec);
   if (pr->capture_stream) (void)hipStreamDestroy(pr->capture_stream);
   for (auto &row : pr->mg_tmp)

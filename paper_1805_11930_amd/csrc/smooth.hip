@@ -26,6 +26,9 @@
 //   GMRES: right-preconditioned restarted GMRES(restart), modified
 //          Gram-Schmidt, Givens rotations, stop when the Arnoldi residual
 //          estimate <= eps ||d_T||_2 or after max_inner applications.
+// and, for b = 0, the exact solve with stored factors (fdm.hip):
+//   FDM:   x = (Tz (x) Ty (x) Tx) diag(1/(lx+ly+lz)) (Tz (x) Ty (x) Tx)^T d,
+//          the six contractions through the same LDS transposes.
 #include "line_ops.h"
 
 namespace dgmg {
@@ -127,11 +130,24 @@ __device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1
 
 // HASB: advection present (compile-time, so the b = 0 kernels carry no
 // advection code and keep only the per-cell matrices live in the loop).
+// Contraction of the lane's line with a matrix stored row-major in LDS:
+// v_i = sum_l M[i][l] u_l (TR = false) or sum_l M[l][i] u_l (TR = true).
+template <typename T, int N, bool TR>
+__device__ inline void contract(const T *M, const T (&u)[N], T (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) acc += (TR ? M[l * N + i] : M[i * N + l]) * u[l];
+    v[i] = acc;
+  }
+}
+
 template <int P, int INNER, typename T, bool HASB>
 __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__restrict__ f,
                                                            const T *__restrict__ uin, T *__restrict__ uout,
                                                            SmoothKArgs sa, int *__restrict__ iters,
-                                                           const T *__restrict__ zh) {
+                                                           const T *__restrict__ zh, const T *__restrict__ fdm) {
   constexpr int N = P + 1;
   using S = SmoothShape<N>;
   constexpr int L = S::L;
@@ -139,7 +155,8 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   __shared__ T Ps_all[S::CPW * S::N3];
   __shared__ T Qy_all[S::CPW * S::N3];
   __shared__ T Qz_all[S::CPW * S::N3];
-  __shared__ T Ms_all[S::CPW * 3 * S::N2];  // per-cell axis matrices (b = 0)
+  __shared__ T Ms_all[S::CPW * 3 * S::N2];  // per-cell axis matrices (b = 0), or the FDM factors T_k
+  __shared__ T Lm_all[INNER == DG_INNER_FDM ? S::CPW * 3 * N : 1];  // FDM eigenvalues
   // GMRES storage: Krylov basis (lane-private x-lines) and the rotated
   // Hessenberg columns of each cell.
   __shared__ T Vs_all[INNER == DG_INNER_GMRES ? S::CPW * (kGmresMax + 1) * S::N3 : 1];
@@ -177,7 +194,22 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   // for b = 0 each axis of D_T is one n x n matrix per cell: lane (a, b)
   // builds entry (a, b) of the three matrices once
   T *Ms = HASB ? nullptr : Ms_all + cw * 3 * S::N2;
-  if (Ms && on) {
+  T *Lm = Lm_all + (INNER == DG_INNER_FDM ? cw * 3 * N : 0);
+  if (INNER == DG_INNER_FDM) {
+    // the cell's stored factors [3][N*N + N] -> T_k into Ms, lambda_k into Lm
+    constexpr int NF = S::N2 + N;
+    if (c < g.ncell) {
+      const T *src = fdm + (size_t)c * 3 * NF;
+      for (int e = lane; e < 3 * NF; e += L) {
+        const int k = e / NF, j = e - k * NF;
+        const T val = src[e];
+        if (j < S::N2)
+          Ms_all[cw * 3 * S::N2 + k * S::N2 + j] = val;
+        else
+          Lm[k * N + (j - S::N2)] = val;
+      }
+    }
+  } else if (Ms && on) {
 #pragma unroll
     for (int k = 0; k < 3; ++k)
       Ms[k * S::N2 + a * N + b] = line_matrix_entry<T, N>(tb, cl.f[k], cl.vol, k == 0 ? cl.cre : T(0), a, b);
@@ -257,7 +289,9 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     T dd = T(1);
-    if (on && Ms) {
+    if (INNER == DG_INNER_FDM) {
+      // not used
+    } else if (on && Ms) {
       // DOF (i, a, b): x-line (a, b), y-line (x=i, z=b), z-line (x=i, y=a)
       dd = tb.w[a] * tb.w[b] * Ms[i * N + i] + tb.w[i] * tb.w[b] * Ms[S::N2 + a * N + a] +
            tb.w[i] * tb.w[a] * Ms[2 * S::N2 + b * N + b];
@@ -285,7 +319,53 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   dn2 = cell_sum<L>(dn2);
   const T epsT = (T)sa.eps;
 
-  if (INNER == DG_INNER_CG) {
+  if (INNER == DG_INNER_FDM) {
+    // x = (Tz Ty Tx) Lambda^-1 (Tz Ty Tx)^T d by six 1-D contractions; the
+    // eigen-index of axis k replaces the node index after its forward step
+    const T *Tx = Ms_all + cw * 3 * S::N2, *Ty = Tx + S::N2, *Tz = Tx + 2 * S::N2;
+    T u1[N], u2[N];
+    if (on) {
+      contract<T, N, true>(Tx, d, u1);
+#pragma unroll
+      for (int i = 0; i < N; ++i) Ps[lpos<N>(0, i, a, b)] = u1[i];
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) u1[i] = Ps[lpos<N>(1, i, a, b)];
+      contract<T, N, true>(Ty, u1, u2);
+#pragma unroll
+      for (int i = 0; i < N; ++i) Qy[lpos<N>(1, i, a, b)] = u2[i];
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) u1[i] = Qy[lpos<N>(2, i, a, b)];
+      contract<T, N, true>(Tz, u1, u2);
+      // z-line (x = a, y = b): eigen-indices (a, b, i)
+      const T lxy = Lm[a] + Lm[N + b];
+#pragma unroll
+      for (int i = 0; i < N; ++i) u2[i] /= lxy + Lm[2 * N + i];
+      contract<T, N, false>(Tz, u2, u1);
+#pragma unroll
+      for (int i = 0; i < N; ++i) Qz[lpos<N>(2, i, a, b)] = u1[i];
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) u1[i] = Qz[lpos<N>(1, i, a, b)];
+      contract<T, N, false>(Ty, u1, u2);
+#pragma unroll
+      for (int i = 0; i < N; ++i) Ps[lpos<N>(1, i, a, b)] = u2[i];
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) u1[i] = Ps[lpos<N>(0, i, a, b)];
+      contract<T, N, false>(Tx, u1, x);
+    }
+    it = dn2 > T(0) ? 1 : 0;
+  } else if (INNER == DG_INNER_CG) {
     T r[N], z[N], p[N], q[N];
     T rho = T(0);
 #pragma unroll
@@ -522,8 +602,15 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
   const bool hb = pr->geo.has_b != 0;
 #define DG_SMOOTH_LAUNCH(INNER, HB)                                                                          \
   hipLaunchKernelGGL((k_smooth<P, INNER, T, HB>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo, (const T *)f, \
-                     (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh)
-  if (a.inner == DG_INNER_CG) {
+                     (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh, (const T *)fdm)
+  const void *fdm = pr->fdm[sizeof(T) == 8 ? DG_FP64 : DG_FP32];
+  if (a.inner == DG_INNER_FDM) {
+    if (hb || !fdm) {
+      set_error("the fast-diagonalisation block solve needs b = 0 and its factors");
+      return DG_EINVAL;
+    }
+    DG_SMOOTH_LAUNCH(DG_INNER_FDM, false);
+  } else if (a.inner == DG_INNER_CG) {
     if (hb)
       DG_SMOOTH_LAUNCH(DG_INNER_CG, true);
     else
