@@ -159,9 +159,9 @@ def main() -> int:
     import numpy as np
     import torch
 
-    from paper_1805_11930_amd import (DG_COARSE_P0, DG_COARSE_Q1, DG_FP32, DG_FP64, DG_INNER_CG, DG_INNER_GMRES,
-                                      DG_KRYLOV_FCG, DG_KRYLOV_FGMRES, DG_PRECOND_MG, Problem, ProblemSpec, mg_opts,
-                                      smooth_opts, solve_opts)
+    from paper_1805_11930_amd import (DG_COARSE_P0, DG_COARSE_Q1, DG_FP32, DG_FP64, DG_INNER_CG, DG_INNER_FDM,
+                                      DG_INNER_GMRES, DG_KRYLOV_FCG, DG_KRYLOV_FGMRES, DG_PRECOND_MG, Problem,
+                                      ProblemSpec, mg_opts, smooth_opts, solve_opts)
 
     torch.cuda.set_device(0)
     if args.copy_only:
@@ -245,6 +245,32 @@ def main() -> int:
     _, st = P.block_smooth(f32, u32, sm, out=out32, stats=True)
     mo = mg_opts(smooth=dict(eps=1e-2, inner=inner, restart=12), coarse_space=coarse)
     t_vc = event_time(lambda: P.mg_vcycle(f32, mo, out=out32), 5)
+    # stored-factor exact block solve (b = 0 only): same V-cycle and solves
+    fdm = None
+    if not conv:
+        def opts_fdm(prec):
+            return solve_opts(krylov=krylov, restart=30, precond=DG_PRECOND_MG, precond_precision=prec, rtol=1e-8,
+                              maxit=1000, smooth=dict(inner=DG_INNER_FDM), mg=dict(coarse_space=coarse))
+        smf = smooth_opts(inner=DG_INNER_FDM)
+        P.block_smooth(f32, u32, smf, out=out32)
+        t_smf = event_time(lambda: P.block_smooth(f32, u32, smf, out=out32), 5)
+        fdm_res = {}
+        for name, prec in (("mixed", DG_FP32), ("fp64", DG_FP64)):
+            step(opts_fdm(prec))
+            best = None
+            for _ in range(3):
+                r_ = step(opts_fdm(prec))
+                best = r_ if best is None or r_.t_solve < best.t_solve else best
+            fdm_res[name] = best
+        fdm = {
+            "inner": "exact block solve by fast diagonalisation (stored per-cell factors)",
+            "smoother_sweep_fp32_ms": round(t_smf * 1e3, 3),
+            "time_to_solve_s": {k: round(v.t_solve, 4) for k, v in fdm_res.items()},
+            "iterations": {k: v.iters for k, v in fdm_res.items()},
+            "rel_residual": {k: v.rel_residual for k, v in fdm_res.items()},
+        }
+        log(f"[bench] FDM smoother: sweep {t_smf * 1e3:.3f} ms, mixed solve {fdm_res['mixed'].t_solve * 1e3:.1f} ms "
+            f"({fdm_res['mixed'].iters} it), FP64 {fdm_res['fp64'].t_solve * 1e3:.1f} ms")
     traffic = None
     if os.path.exists(COUNTERS):
         with open(COUNTERS) as fh:
@@ -299,6 +325,7 @@ def main() -> int:
             "precond_ms_per_iter_mixed": round(res_m.t_precond * 1e3 / max(res_m.n_precond, 1), 3),
             "apply_launches_timed": n_apply,
         },
+        "fdm_smoother": fdm,
     }
     if args.serve_requests > 0:
         line["serving"] = serving_leg(args.serve_requests)

@@ -270,6 +270,11 @@ void dg_solve_state_destroy(dg_solve_state *state);
 int dg_footprint(const dg_problem_desc *desc, const dg_solve_opts *opts, size_t *bytes);
 
 /* ---- defaults ------------------------------------------------------- */
+/* smoother: n_sweeps 1, omega 0.8, eps 1e-2 (the paper's choice),
+ *   max_inner (p+1)^3, inner CG, restart 12;
+ * V-cycle: n_pre = n_post = 1, coarse_space AUTO, coarse_cycles 1,
+ *   coarse_smooth 4, coarse_omega 2/3, graph 1;
+ * solve: FCG, restart 30, rtol 1e-8, maxit 500, MG preconditioner in FP32. */
 void dg_default_smooth_opts(dg_smooth_opts *o);
 void dg_default_mg_opts(dg_mg_opts *o);
 void dg_default_solve_opts(dg_solve_opts *o);

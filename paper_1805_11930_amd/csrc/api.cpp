@@ -331,7 +331,7 @@ extern "C" {
 void dg_default_smooth_opts(dg_smooth_opts *o) {
   if (!o) return;
   o->n_sweeps = 1;
-  o->omega = 0.7;
+  o->omega = 0.8;
   o->eps = 1e-2;
   o->max_inner = 0;
   o->inner = DG_INNER_CG;
