@@ -13,6 +13,7 @@
 // axis (the nodal interpolation of a coarser trilinear function), and the
 // coarse matrix is the Galerkin product P^T A P (built on the host).
 #include "dg_internal.h"
+#include "q1_element.h"
 #include "vec.h"
 
 namespace dgmg {
@@ -251,7 +252,142 @@ __global__ void k_copy(int64_t n, const T *__restrict__ x, T *__restrict__ y) {
   if (i < n) y[i] = x[i];
 }
 
+// ---- setup of the Q1 hierarchy on the device ----------------------------
+// Level 0: vertex v gathers, from each of its (up to eight) cells, the row
+// of that cell's trilinear element matrix for the corner at v.
+template <int P>
+__global__ __launch_bounds__(128) void k_q1_assemble(Geo g, double *__restrict__ A) {
+  constexpr int N = P + 1;
+  constexpr DevTab<double, N> tb = make_ctab<double, N>();
+  const int vx = g.nx + 1, vy = g.ny + 1;
+  const int64_t n = (int64_t)vx * vy * (g.nz + 1);
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int ix = (int)(v % vx), iy = (int)((v / vx) % vy), iz = (int)(v / ((int64_t)vx * vy));
+  double acc[27];
+  for (int o = 0; o < 27; ++o) acc[o] = 0.0;
+  for (int sz = 0; sz < 2; ++sz) {
+    const int cz = iz - 1 + sz;
+    if (cz < 0 || cz >= g.nz) continue;
+    for (int sy = 0; sy < 2; ++sy) {
+      const int cy = iy - 1 + sy;
+      if (cy < 0 || cy >= g.ny) continue;
+      for (int sx = 0; sx < 2; ++sx) {
+        const int cx = ix - 1 + sx;
+        if (cx < 0 || cx >= g.nx) continue;
+        const int c = cx + g.nx * (cy + g.ny * cz);
+        const int ijk[3] = {cx, cy, cz};
+        const int da[3] = {1 - sx, 1 - sy, 1 - sz};  // corner of the cell at v
+        double row[8];
+        q1_element_row<N>(g, tb, c, ijk, da[0] + 2 * da[1] + 4 * da[2], row);
+        for (int b = 0; b < 8; ++b) {
+          const int o = ((b & 1) - da[0] + 1) + 3 * (((b >> 1) & 1) - da[1] + 1) + 9 * ((b >> 2) - da[2] + 1);
+          acc[o] += row[b];
+        }
+      }
+    }
+  }
+  for (int o = 0; o < 27; ++o) A[o * n + v] = acc[o];
+}
+
+// Ac = P^T A P: coarse vertex I gathers the fine vertices i with P_iI != 0,
+// their 27 couplings A_ij, and the interpolation weights of j towards the
+// coarse vertices J around I.
+__global__ __launch_bounds__(128) void k_galerkin27(const double *__restrict__ A, int vx, int vy, int vz,
+                                                    double *__restrict__ Ac, int cx, int cy, int cz) {
+  const int64_t n = (int64_t)vx * vy * vz, nc = (int64_t)cx * cy * cz;
+  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int II[3] = {(int)(I % cx), (int)((I / cx) % cy), (int)(I / ((int64_t)cx * cy))};
+  const int vf[3] = {vx, vy, vz}, vc[3] = {cx, cy, cz};
+  double acc[27];
+  for (int o = 0; o < 27; ++o) acc[o] = 0.0;
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int iz = min(2 * II[2], vz - 1) + dz;
+    if (iz < 0 || iz >= vz) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int iy = min(2 * II[1], vy - 1) + dy;
+      if (iy < 0 || iy >= vy) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ix = min(2 * II[0], vx - 1) + dx;
+        if (ix < 0 || ix >= vx) continue;
+        const int ii[3] = {ix, iy, iz};
+        // weight of fine i towards coarse I
+        double wi = 1.0;
+        for (int k = 0; k < 3; ++k) {
+          const W1 q = interp1(ii[k], vf[k], vc[k]);
+          double wk = 0.0;
+          if (q.j0 == II[k]) wk = q.two ? 0.5 : 1.0;
+          else if (q.two && q.j0 + 1 == II[k]) wk = 0.5;
+          wi *= wk;
+        }
+        if (wi == 0.0) continue;
+        const int64_t i = ix + (int64_t)vx * (iy + (int64_t)vy * iz);
+        for (int o = 0; o < 27; ++o) {
+          const int jj[3] = {ix + o % 3 - 1, iy + (o / 3) % 3 - 1, iz + o / 9 - 1};
+          if (jj[0] < 0 || jj[1] < 0 || jj[2] < 0 || jj[0] >= vx || jj[1] >= vy || jj[2] >= vz) continue;
+          const double a = A[o * n + i];
+          if (a == 0.0) continue;
+          W1 q[3];
+          for (int k = 0; k < 3; ++k) q[k] = interp1(jj[k], vf[k], vc[k]);
+          for (int t2 = 0; t2 < (q[2].two ? 2 : 1); ++t2)
+            for (int t1 = 0; t1 < (q[1].two ? 2 : 1); ++t1)
+              for (int t0 = 0; t0 < (q[0].two ? 2 : 1); ++t0) {
+                const int J[3] = {q[0].j0 + t0, q[1].j0 + t1, q[2].j0 + t2};
+                const double wj = (q[0].two ? 0.5 : 1.0) * (q[1].two ? 0.5 : 1.0) * (q[2].two ? 0.5 : 1.0);
+                const int oc = (J[0] - II[0] + 1) + 3 * (J[1] - II[1] + 1) + 9 * (J[2] - II[2] + 1);
+                if (oc >= 0 && oc < 27) acc[oc] += wi * a * wj;  // always true: |J - I| <= 1 per axis
+              }
+        }
+      }
+    }
+  }
+  for (int o = 0; o < 27; ++o) Ac[o * nc + I] = acc[o];
+}
+
+// FP32 copy of a level's stencil and the l1 smoothing diagonal 2 / sum |A|.
+__global__ __launch_bounds__(256) void k_level_finish(const double *__restrict__ A, int64_t n, float *__restrict__ A32,
+                                                      double *__restrict__ d64, float *__restrict__ d32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int o = 0; o < 27; ++o) {
+    const double a = A[o * n + i];
+    A32[o * n + i] = (float)a;
+    s += fabs(a);
+  }
+  const double d = s > 0.0 ? 2.0 / s : 0.0;
+  d64[i] = d;
+  d32[i] = (float)d;
+}
+
 }  // namespace
+
+int q1_assemble(const dg_problem *pr, double *A, hipStream_t s) {
+  const int64_t n = (int64_t)(pr->geo.nx + 1) * (pr->geo.ny + 1) * (pr->geo.nz + 1);
+  const dim3 g((unsigned)((n + 127) / 128)), b(128);
+  switch (pr->p) {
+    case 1: hipLaunchKernelGGL((k_q1_assemble<1>), g, b, 0, s, pr->geo, A); break;
+    case 2: hipLaunchKernelGGL((k_q1_assemble<2>), g, b, 0, s, pr->geo, A); break;
+    case 3: hipLaunchKernelGGL((k_q1_assemble<3>), g, b, 0, s, pr->geo, A); break;
+    case 4: hipLaunchKernelGGL((k_q1_assemble<4>), g, b, 0, s, pr->geo, A); break;
+    default: set_error("unsupported degree"); return DG_EINVAL;
+  }
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int galerkin27(const double *A, int vx, int vy, int vz, double *Ac, int cx, int cy, int cz, hipStream_t s) {
+  const int64_t nc = (int64_t)cx * cy * cz;
+  hipLaunchKernelGGL(k_galerkin27, dim3((unsigned)((nc + 127) / 128)), dim3(128), 0, s, A, vx, vy, vz, Ac, cx, cy,
+                     cz);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int level_finish(const double *A, int64_t n, float *A32, double *d64, float *d32, hipStream_t s) {
+  hipLaunchKernelGGL(k_level_finish, grid_for(n), dim3(256), 0, s, A, n, A32, d64, d32);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
 
 template <typename T>
 int jacobi27(const T *A, const T *dinv, int vx, int vy, int vz, T w, const T *r, const T *xi, T *xo, hipStream_t s) {

@@ -153,8 +153,9 @@ bool dense_inverse(std::vector<double> M, int n, std::vector<double> &inv) {
   return true;
 }
 
-// Device copy of one level's stencil (both precisions) and its work vectors.
-int upload_level(dg_problem *pr, CoarseLevel &L, const std::vector<double> &A, bool first) {
+// Device buffers of one level: stencil (both precisions), work vectors
+// and, for 27-point levels, the smoothing diagonal.
+int alloc_level(dg_problem *pr, CoarseLevel &L, bool first) {
   const int64_t n = L.n, ns = L.ns;
   int rc;
   if ((rc = dmalloc(pr, (void **)&L.A64, ns * n * sizeof(double)))) return rc;
@@ -169,26 +170,21 @@ int upload_level(dg_problem *pr, CoarseLevel &L, const std::vector<double> &A, b
     for (float **p : {&L.acc32, &L.rs32})
       if ((rc = dmalloc(pr, (void **)p, n * sizeof(float)))) return rc;
   }
+  if (ns == 27) {
+    if ((rc = dmalloc(pr, (void **)&L.dinv64, n * sizeof(double)))) return rc;
+    if ((rc = dmalloc(pr, (void **)&L.dinv32, n * sizeof(float)))) return rc;
+  }
+  return DG_OK;
+}
+
+// Host stencil A (P0 levels) to a freshly allocated level.
+int upload_level(dg_problem *pr, CoarseLevel &L, const std::vector<double> &A, bool first) {
+  const int64_t n = L.n, ns = L.ns;
+  int rc;
+  if ((rc = alloc_level(pr, L, first))) return rc;
   std::vector<float> Af(A.begin(), A.end());
   DG_HIP(hipMemcpy(L.A64, A.data(), ns * n * sizeof(double), hipMemcpyHostToDevice));
   DG_HIP(hipMemcpy(L.A32, Af.data(), ns * n * sizeof(float), hipMemcpyHostToDevice));
-  if (ns == 27) {
-    std::vector<double> d(n);
-    for (int64_t i = 0; i < n; ++i) {
-      double s = 0.0;
-      for (int o = 0; o < 27; ++o) s += std::fabs(A[(size_t)o * n + i]);
-      if (!(s > 0.0)) {
-        set_error("coarse level has an empty row");
-        return DG_EINVAL;
-      }
-      d[i] = 2.0 / s;
-    }
-    std::vector<float> df(d.begin(), d.end());
-    if ((rc = dmalloc(pr, (void **)&L.dinv64, n * sizeof(double)))) return rc;
-    if ((rc = dmalloc(pr, (void **)&L.dinv32, n * sizeof(float)))) return rc;
-    DG_HIP(hipMemcpy(L.dinv64, d.data(), n * sizeof(double), hipMemcpyHostToDevice));
-    DG_HIP(hipMemcpy(L.dinv32, df.data(), n * sizeof(float), hipMemcpyHostToDevice));
-  }
   return DG_OK;
 }
 

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+struct dg_problem;
+
 namespace dgmg {
 
 constexpr int kMaxDots = 4;
@@ -41,6 +43,9 @@ template <typename T>
 int dense_mv(int n, const T *Ainv, const T *r, T *x, hipStream_t s);
 
 // Q1 vertex-grid levels and transfers (coarse.hip)
+int q1_assemble(const dg_problem *pr, double *A, hipStream_t s);
+int galerkin27(const double *A, int vx, int vy, int vz, double *Ac, int cx, int cy, int cz, hipStream_t s);
+int level_finish(const double *A, int64_t n, float *A32, double *d64, float *d32, hipStream_t s);
 template <typename T>
 int jacobi27(const T *A, const T *dinv, int vx, int vy, int vz, T w, const T *r, const T *xi, T *xo, hipStream_t s);
 template <typename T>

@@ -68,7 +68,9 @@ class SolveServer:
         prob = Problem(req.spec)
         f = torch.from_numpy(np.ascontiguousarray(req.rhs, dtype=np.float64)).cuda()
         u = torch.zeros_like(f)
-        torch.cuda.synchronize()
+        # f and u are ready once torch's stream has run; the solve runs on
+        # its own stream, so only that stream is waited for (not the device)
+        torch.cuda.current_stream().synchronize()
         st = ctypes.c_void_p()
         L._check(self.lib.dg_solve_start(prob.h, f.data_ptr(), u.data_ptr(), ctypes.byref(self.opts), ctypes.byref(st)))
         req.admitted = now
