@@ -4,6 +4,11 @@ Oracle (test infrastructure only; see the package docstring).
 
 Each routine takes the paper's steps in the paper's order:
   * block-Jacobi: alg block_jacobi (Sec. 2.2.1) with W = omega^-1 D;
+  * block-SOR: alg block_SOR in a given cell order, in place (Sec. 2.2.1):
+    the local defect leaves out the cell's own block and the new value is
+    (1 - omega) u + omega du; the backward sweep reverses the order and
+    block-SSOR is a forward then a backward sweep; the red-black (two
+    colour) cell order is the one whose colours can be swept in parallel;
   * the block systems D_T du_T = d_T (eqn block_system) are solved either
     exactly (dense LU) or inexactly with a Krylov method stopped when the
     2-norm of the block residual has dropped by the factor eps (Sec. 2.2.1),
@@ -156,6 +161,79 @@ def block_jacobi(A, Dblocks, f, u0, omega=1.0, nsweeps=1, inner="exact", eps=1e-
             if stats is not None:
                 stats.append(it)
         u = u + omega * du.ravel()
+    return u
+
+
+def _inner_solve(D, d, inner, eps, max_inner, restart):
+    if inner == "exact":
+        return block_solve_exact(D, d)
+    if inner == "cg":
+        return block_pcg(D, d, eps, max_inner)
+    if inner == "gmres":
+        return block_gmres(D, d, eps, max_inner, min(restart, d.size))
+    raise ValueError(inner)
+
+
+# ---------------------------------------------------------------------------
+# block-SOR / block-SSOR smoothers (alg block_SOR, Sec. 2.2.1)
+# ---------------------------------------------------------------------------
+def lexicographic_order(prob: _dg.Problem) -> np.ndarray:
+    """Cells in index order (x fastest)."""
+    return np.arange(prob.ncell)
+
+
+def multicolour_order(prob: _dg.Problem) -> np.ndarray:
+    """Red-black ordering of the cells: every cell with ix + iy + iz even
+    (in index order), then every odd one.  Face neighbours differ by one in
+    exactly one index, so no two cells of one colour share a face."""
+    ijk = np.array([prob.cell_ijk(c) for c in range(prob.ncell)]).reshape(-1, 3)
+    colour = ijk.sum(axis=1) % 2
+    cells = np.arange(prob.ncell)
+    return np.concatenate([cells[colour == 0], cells[colour == 1]])
+
+
+def block_sor(A, Dblocks, f, u0, order, omega=1.0, nsweeps=1, inner="exact", eps=1e-2,
+              max_inner=None, restart=30, stats=None):
+    """n_sweeps forward block-SOR steps over the cells in ``order``.
+
+    Alg block_SOR: cell T_rho, taken in the given order, forms its local
+    defect from f_rho minus the couplings to every other cell (the cells
+    visited before it already carry step-k values, the others step k-1
+    values, so updating u in place is exactly the algorithm), solves
+    D_rho du = d_rho (exactly or to the relative tolerance eps) and sets
+    u_rho = (1 - omega) u_rho + omega du.  The backward sweep is the same
+    with the order reversed.
+    """
+    ncell, nb, _ = Dblocks.shape
+    if max_inner is None:
+        max_inner = nb
+    Ab = sp.bsr_matrix(A, blocksize=(nb, nb))
+    Ab.sort_indices()
+    u = np.array(u0, dtype=np.float64, copy=True).reshape(ncell, nb)
+    fb = np.asarray(f, dtype=np.float64).reshape(ncell, nb)
+    for _ in range(nsweeps):
+        for rho in order:
+            d = fb[rho].copy()
+            for k in range(Ab.indptr[rho], Ab.indptr[rho + 1]):
+                sigma = Ab.indices[k]
+                if sigma != rho:
+                    d -= Ab.data[k] @ u[sigma]
+            du, it = _inner_solve(Dblocks[rho], d, inner, eps, max_inner, restart)
+            if stats is not None:
+                stats.append(it)
+            u[rho] = (1.0 - omega) * u[rho] + omega * du
+    return u.ravel()
+
+
+def block_ssor(A, Dblocks, f, u0, order, omega=1.0, nsweeps=1, **kw):
+    """n_sweeps block-SSOR steps: each is a forward block-SOR sweep over
+    ``order`` followed by a backward sweep over the reversed order
+    (Sec. 2.2.1)."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    rev = np.asarray(order)[::-1]
+    for _ in range(nsweeps):
+        u = block_sor(A, Dblocks, f, u, order, omega=omega, nsweeps=1, **kw)
+        u = block_sor(A, Dblocks, f, u, rev, omega=omega, nsweeps=1, **kw)
     return u
 
 
@@ -329,18 +407,37 @@ def q1_direct(prob: _dg.Problem) -> np.ndarray:
 # hybrid V-cycle (alg hybrid_multigrid)
 # ---------------------------------------------------------------------------
 def vcycle(A, Dblocks, prob: _dg.Problem, r, coarse_solve, n_pre=1, n_post=1, omega=1.0,
-           inner="exact", eps=1e-2, max_inner=None, restart=30, stats=None, P=None):
+           inner="exact", eps=1e-2, max_inner=None, restart=30, stats=None, P=None,
+           smoother="jacobi", order=None):
     """z ~= A^-1 r: presmooth from zero, residual, restrict, coarse solve,
-    prolongate-add, postsmooth.  P: prolongation (default: P0)."""
+    prolongate-add, postsmooth.  P: prolongation (default: P0).
+
+    smoother: 'jacobi', 'ssor', or 'sor' (forward sweeps before the coarse
+    correction, backward sweeps after it, so that the cycle is symmetric
+    for a symmetric A); order: the cell order of the SOR sweeps (default
+    red-black)."""
     if P is None:
         P = p0_prolongation(prob)
+    if order is None:
+        order = multicolour_order(prob)
+    order = np.asarray(order)
     kw = dict(omega=omega, inner=inner, eps=eps, max_inner=max_inner, restart=restart, stats=stats)
-    z = block_jacobi(A, Dblocks, r, np.zeros_like(r), nsweeps=n_pre, **kw)
+
+    def smooth(u, n, post):
+        if smoother == "jacobi":
+            return block_jacobi(A, Dblocks, r, u, nsweeps=n, **kw)
+        if smoother == "ssor":
+            return block_ssor(A, Dblocks, r, u, order, nsweeps=n, **kw)
+        if smoother == "sor":
+            return block_sor(A, Dblocks, r, u, order[::-1] if post else order, nsweeps=n, **kw)
+        raise ValueError(smoother)
+
+    z = smooth(np.zeros_like(r), n_pre, False)
     res = r - A @ z
     rh = P.T @ res
     zh = coarse_solve(rh)
     z = z + P @ zh
-    z = block_jacobi(A, Dblocks, r, z, nsweeps=n_post, **kw)
+    z = smooth(z, n_post, True)
     return z
 
 

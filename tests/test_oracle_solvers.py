@@ -11,6 +11,14 @@ and of the memory model (CPU only).
     definite operator for b = 0;
   * outer CG / flexible CG / flexible GMRES converge to the sparse direct
     solution within the tolerance;
+  * block-SOR / block-SSOR sweeps (alg block_SOR) equal the matrix
+    splitting iterations u + W^-1 (f - A u) with the paper's W for SOR and
+    SSOR, computed globally from dense D, L, U for the same cell order;
+    red-black results do not depend on the order inside a colour; with
+    (almost) no diffusion and cells ordered along b one SOR sweep solves the
+    upwind system (Sec. 4.3), a red-black one does not; SSOR from zero and
+    the SOR/SSOR V-cycles are symmetric for b = 0; tight inner solves
+    reproduce the exact sweeps;
   * the memory model reproduces every printed entry of the paper's four
     memory tables (tests/golden/*.csv, Sec. 4.4).
 """
@@ -265,3 +273,133 @@ def test_vcycle_q1_symmetric():
     z2 = solvers.vcycle(A, Db, pr, r2, cs, **kw)
     assert r2 @ z1 == pytest.approx(r1 @ z2, rel=1e-11)
     assert r1 @ z1 > 0
+
+
+# ---------------------------------------------------------------------------
+# block-SOR / block-SSOR (alg block_SOR, Sec. 2.2.1)
+# ---------------------------------------------------------------------------
+def _splitting(A, pr, order):
+    """Dense D, L, U of A for the cell order: L holds the blocks A_{rho,sigma}
+    with sigma visited before rho, U those visited after."""
+    Ad = A.toarray()
+    nb = pr.nloc
+    pos = np.empty(pr.ncell, dtype=int)
+    pos[np.asarray(order)] = np.arange(pr.ncell)
+    cell = np.arange(pr.ndof) // nb
+    before = pos[cell][None, :] < pos[cell][:, None]
+    same = cell[None, :] == cell[:, None]
+    return Ad * same, Ad * before, Ad * ~(before | same)
+
+
+@pytest.mark.parametrize("with_b", [False, True])
+@pytest.mark.parametrize("omega", [1.0, 1.3])
+@pytest.mark.parametrize("ordering", ["lex", "rb"])
+def test_block_sor_is_the_splitting_iteration(with_b, omega, ordering):
+    # one sweep is u + W^-1 (f - A u) with W = omega^-1 D + L (Sec. 2.2.1)
+    pr = small(2, with_b=with_b, cells=(3, 2, 2))
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    order = solvers.lexicographic_order(pr) if ordering == "lex" else solvers.multicolour_order(pr)
+    rng = np.random.default_rng(11)
+    f, u0 = rng.normal(size=(2, pr.ndof))
+    D, L, _ = _splitting(A, pr, order)
+    W = D / omega + L
+    expect = u0 + np.linalg.solve(W, f - A @ u0)
+    got = solvers.block_sor(A, Db, f, u0, order, omega=omega, nsweeps=1)
+    np.testing.assert_allclose(got, expect, rtol=0, atol=1e-11 * np.abs(expect).max())
+
+
+@pytest.mark.parametrize("with_b", [False, True])
+def test_block_ssor_is_the_splitting_iteration(with_b):
+    # W = (omega (2 - omega))^-1 (D + omega L) D^-1 (D + omega U) (Sec. 2.2.1)
+    omega = 1.2
+    pr = small(1, with_b=with_b, cells=(3, 3, 2))
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    order = solvers.multicolour_order(pr)
+    rng = np.random.default_rng(12)
+    f, u0 = rng.normal(size=(2, pr.ndof))
+    D, L, U = _splitting(A, pr, order)
+    W = (D + omega * L) @ np.linalg.solve(D, D + omega * U) / (omega * (2.0 - omega))
+    expect = u0 + np.linalg.solve(W, f - A @ u0)
+    got = solvers.block_ssor(A, Db, f, u0, order, omega=omega, nsweeps=1)
+    np.testing.assert_allclose(got, expect, rtol=0, atol=1e-11 * np.abs(expect).max())
+
+
+def test_multicolour_order_is_independent_within_a_colour():
+    pr = small(2, with_b=True, cells=(4, 3, 3))
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    order = solvers.multicolour_order(pr)
+    ijk = np.array([pr.cell_ijk(c) for c in order])
+    colour = ijk.sum(axis=1) % 2
+    assert np.all(colour[:-1] <= colour[1:])  # one colour after the other
+    # no two cells of one colour share a face
+    for c in range(pr.ncell):
+        for d in range(pr.ncell):
+            if np.abs(np.subtract(pr.cell_ijk(c), pr.cell_ijk(d))).sum() == 1:
+                assert sum(pr.cell_ijk(c)) % 2 != sum(pr.cell_ijk(d)) % 2
+    rng = np.random.default_rng(13)
+    f, u0 = rng.normal(size=(2, pr.ndof))
+    shuffled = np.concatenate([rng.permutation(order[colour == 0]), rng.permutation(order[colour == 1])])
+    a = solvers.block_ssor(A, Db, f, u0, order, omega=1.1)
+    b = solvers.block_ssor(A, Db, f, u0, shuffled, omega=1.1)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * np.abs(a).max())
+
+
+def test_block_sor_pure_advection_downwind_one_sweep_is_exact():
+    # Pe -> infinity: with the cells ordered along b, one sweep with
+    # omega = 1 solves the upwind system exactly (Sec. 4.3); K = 1e-13
+    # leaves couplings against the flow of relative size ~1e-13
+    pr = dg.Problem(cells=(3, 3, 2), p=2, K=1e-13, b0=(1.0, 0.5, 0.3))
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    rng = np.random.default_rng(14)
+    f, u0 = rng.normal(size=(2, pr.ndof))
+    ue = spla.spsolve(A.tocsc(), f)
+    u = solvers.block_sor(A, Db, f, u0, solvers.lexicographic_order(pr), omega=1.0)
+    np.testing.assert_allclose(u, ue, rtol=0, atol=1e-9 * np.abs(ue).max())
+    # red-black is not a downwind order: one sweep is not exact
+    u_rb = solvers.block_sor(A, Db, f, u0, solvers.multicolour_order(pr), omega=1.0)
+    assert np.abs(u_rb - ue).max() > 1e-3 * np.abs(ue).max()
+
+
+def test_block_ssor_from_zero_is_symmetric_positive_definite():
+    pr = small(2, cells=(3, 2, 2))
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    order = solvers.multicolour_order(pr)
+    rng = np.random.default_rng(15)
+    r1, r2 = rng.normal(size=(2, pr.ndof))
+    z = lambda r: solvers.block_ssor(A, Db, r, np.zeros(pr.ndof), order, omega=1.3)
+    z1, z2 = z(r1), z(r2)
+    assert r2 @ z1 == pytest.approx(r1 @ z2, rel=1e-11)
+    assert r1 @ z1 > 0 and r2 @ z2 > 0
+
+
+@pytest.mark.parametrize("smoother", ["sor", "ssor"])
+def test_vcycle_sor_smoothers_symmetric(smoother):
+    pr = small(2, cells=(3, 2, 2))
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    cs = solvers.exact_coarse(solvers.p0_direct(pr))
+    rng = np.random.default_rng(16)
+    r1, r2 = rng.normal(size=(2, pr.ndof))
+    kw = dict(n_pre=1, n_post=1, omega=1.0, inner="exact", smoother=smoother)
+    z1 = solvers.vcycle(A, Db, pr, r1, cs, **kw)
+    z2 = solvers.vcycle(A, Db, pr, r2, cs, **kw)
+    assert r2 @ z1 == pytest.approx(r1 @ z2, rel=1e-11)
+    assert r1 @ z1 > 0
+
+
+@pytest.mark.parametrize("inner,with_b", [("cg", False), ("gmres", True)])
+def test_block_sor_tight_inner_equals_exact(inner, with_b):
+    pr = small(2, with_b=with_b, cells=(3, 2, 2))
+    A = dg.assemble(pr)
+    Db = dg.block_diagonal(A, pr.ncell)
+    order = solvers.multicolour_order(pr)
+    rng = np.random.default_rng(17)
+    f, u0 = rng.normal(size=(2, pr.ndof))
+    a = solvers.block_ssor(A, Db, f, u0, order, omega=0.9, inner="exact")
+    b = solvers.block_ssor(A, Db, f, u0, order, omega=0.9, inner=inner, eps=1e-14, max_inner=200, restart=27)
+    np.testing.assert_allclose(b, a, rtol=0, atol=1e-10 * np.abs(a).max())
