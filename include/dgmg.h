@@ -59,7 +59,15 @@ enum { DG_FP64 = 0, DG_FP32 = 1 };
 enum { DG_BC_DIRICHLET = 0, DG_BC_NEUMANN = 1 };
 enum { DG_INNER_CG = 0, DG_INNER_GMRES = 1, DG_INNER_FDM = 2 };
 enum { DG_KRYLOV_CG = 0, DG_KRYLOV_FCG = 1, DG_KRYLOV_FGMRES = 2 };
-enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK_JACOBI = 1, DG_PRECOND_MG = 2 };
+enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK = 1, DG_PRECOND_MG = 2 };
+#define DG_PRECOND_BLOCK_JACOBI DG_PRECOND_BLOCK
+/* Sweep of the block smoother (Sec. 2.2.1): block-Jacobi (alg
+ * block_jacobi), forward or backward block-SOR (alg block_SOR) and
+ * block-SSOR (a forward then a backward sweep).  The SOR sweeps visit the
+ * cells in red-black order (ix + iy + iz even, then odd; backward: odd,
+ * then even): cells of one colour share no face, so each colour is swept
+ * in parallel, in place. */
+enum { DG_SWEEP_JACOBI = 0, DG_SWEEP_SOR = 1, DG_SWEEP_SSOR = 2, DG_SWEEP_SOR_BACKWARD = 3 };
 enum { DG_COARSE_P0 = 0, DG_COARSE_Q1 = 1, DG_COARSE_AUTO = 2 };
 
 typedef struct dg_problem dg_problem;          /* opaque, library-owned */
@@ -83,11 +91,13 @@ typedef struct {
   double B[9];
 } dg_problem_desc;
 
-/* Block smoother options (alg block_jacobi, Sec. 2.2.1; inner solve
- * Sec. 3.2). */
+/* Block smoother options (alg block_jacobi, alg block_SOR, Sec. 2.2.1;
+ * inner solve Sec. 3.2). */
 typedef struct {
-  int n_sweeps;     /* number of block-Jacobi steps, >= 1                  */
-  double omega;     /* damping, W = omega^-1 D                              */
+  int n_sweeps;     /* number of smoothing steps (an SSOR step is a forward
+                       and a backward sweep), >= 1                          */
+  double omega;     /* damping / relaxation: W = omega^-1 D (Jacobi),
+                       omega^-1 D + L (SOR)                                 */
   double eps;       /* inner stop: ||d_T - D_T x||_2 <= eps ||d_T||_2       */
   int max_inner;    /* cap on D_T applications per block (<= 0: (p+1)^3)   */
   int inner;        /* DG_INNER_CG (b = 0) or DG_INNER_GMRES, the paper's
@@ -97,6 +107,7 @@ typedef struct {
                        first use; eps, max_inner, restart are ignored)     */
   int restart;      /* inner GMRES restart length (<= 0: 16)               */
   int zero_guess;   /* 1: u_in is taken as zero and not read                */
+  int sweep;        /* DG_SWEEP_* (default DG_SWEEP_JACOBI)                 */
 } dg_smooth_opts;
 
 /* Optional smoother statistics (filled after a synchronisation). */
@@ -125,7 +136,11 @@ typedef struct {
  * V-cycle is a fixed linear operator. */
 typedef struct {
   int n_pre, n_post;        /* smoothing steps, 0..64                       */
-  dg_smooth_opts smooth;    /* smoother (n_sweeps and zero_guess ignored)   */
+  dg_smooth_opts smooth;    /* smoother (n_sweeps and zero_guess ignored);
+                               with DG_SWEEP_SOR the presmoothing sweeps go
+                               forward and the postsmoothing ones backward
+                               (DG_SWEEP_SOR_BACKWARD: the reverse), so the
+                               cycle is symmetric for a symmetric A        */
   int coarse_space;         /* DG_COARSE_P0, DG_COARSE_Q1 or DG_COARSE_AUTO */
   int coarse_cycles;        /* V-cycles of the coarse solver (0 or 1: one)  */
   int coarse_smooth;        /* Jacobi sweeps per level (0: 2), 0..64        */
@@ -143,7 +158,9 @@ typedef struct {
   int maxit;                /* iteration cap                                */
   int precond;              /* DG_PRECOND_*                                 */
   int precond_precision;    /* DG_FP64 or DG_FP32 (mixed precision)         */
-  dg_mg_opts mg;            /* V-cycle (and block-Jacobi smoother) options  */
+  dg_mg_opts mg;            /* V-cycle options; DG_PRECOND_BLOCK applies
+                               mg.smooth.n_sweeps smoother steps (kind
+                               mg.smooth.sweep) from a zero guess           */
 } dg_solve_opts;
 
 typedef struct {
@@ -210,10 +227,15 @@ int dg_block_diag(dg_problem *prob, int precision, void *diag, void *stream);
 int dg_block_solve(dg_problem *prob, int precision, const void *d, void *x,
                    const dg_smooth_opts *opts, int *iters, void *stream);
 
-/* n_sweeps block-Jacobi steps (alg block_jacobi):
- *   u^(k) = u^(k-1) + omega D^-1_eps (f - A u^(k-1)),
- * u^(0) = u_in (or 0 when opts->zero_guess), result in u_out.  u_in and
- * u_out must differ.  stats (nullable) forces a synchronisation. */
+/* n_sweeps smoothing steps from u^(0) = u_in (or 0 when opts->zero_guess),
+ * result in u_out; stats (nullable) forces a synchronisation.
+ *   DG_SWEEP_JACOBI (alg block_jacobi):
+ *     u^(k) = u^(k-1) + omega D^-1_eps (f - A u^(k-1));  u_in != u_out.
+ *   DG_SWEEP_SOR / _SOR_BACKWARD / _SSOR (alg block_SOR): per cell T, in
+ *     red-black order, d_T = f_T - sum over the face neighbours S of
+ *     A_{T,S} u_S (current values), D_T x = d_T solved to eps, then
+ *     u_T = (1 - omega) u_T + omega x, in place in u_out (u_in may equal
+ *     u_out; otherwise u_in is copied first). */
 int dg_block_smooth(dg_problem *prob, int precision, const void *f, const void *u_in, void *u_out,
                     const dg_smooth_opts *opts, dg_smooth_stats *stats, void *stream);
 

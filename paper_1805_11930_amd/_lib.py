@@ -23,7 +23,9 @@ DG_FP64, DG_FP32 = 0, 1
 DG_BC_DIRICHLET, DG_BC_NEUMANN = 0, 1
 DG_INNER_CG, DG_INNER_GMRES, DG_INNER_FDM = 0, 1, 2
 DG_KRYLOV_CG, DG_KRYLOV_FCG, DG_KRYLOV_FGMRES = 0, 1, 2
-DG_PRECOND_NONE, DG_PRECOND_BLOCK_JACOBI, DG_PRECOND_MG = 0, 1, 2
+DG_PRECOND_NONE, DG_PRECOND_BLOCK, DG_PRECOND_MG = 0, 1, 2
+DG_PRECOND_BLOCK_JACOBI = DG_PRECOND_BLOCK
+DG_SWEEP_JACOBI, DG_SWEEP_SOR, DG_SWEEP_SSOR, DG_SWEEP_SOR_BACKWARD = 0, 1, 2, 3
 DG_COARSE_P0, DG_COARSE_Q1, DG_COARSE_AUTO = 0, 1, 2
 
 EXPORTS = (
@@ -56,7 +58,7 @@ class SmoothOpts(ctypes.Structure):
     _fields_ = [
         ("n_sweeps", ctypes.c_int), ("omega", ctypes.c_double), ("eps", ctypes.c_double),
         ("max_inner", ctypes.c_int), ("inner", ctypes.c_int), ("restart", ctypes.c_int),
-        ("zero_guess", ctypes.c_int),
+        ("zero_guess", ctypes.c_int), ("sweep", ctypes.c_int),
     ]
 
 

@@ -63,8 +63,9 @@ int smooth_args(dg_problem *pr, const dg_smooth_opts *o, SmoothArgs &a) {
     return DG_EINVAL;
   }
   if (!(o->eps >= 0) || !std::isfinite(o->omega) ||
-      (o->inner != DG_INNER_CG && o->inner != DG_INNER_GMRES && o->inner != DG_INNER_FDM)) {
-    set_error("invalid smoother options (eps >= 0, finite omega, inner CG, GMRES or FDM)");
+      (o->inner != DG_INNER_CG && o->inner != DG_INNER_GMRES && o->inner != DG_INNER_FDM) ||
+      o->sweep < DG_SWEEP_JACOBI || o->sweep > DG_SWEEP_SOR_BACKWARD) {
+    set_error("invalid smoother options (eps >= 0, finite omega, inner CG, GMRES or FDM, sweep DG_SWEEP_*)");
     return DG_EINVAL;
   }
   if (o->inner == DG_INNER_FDM) {
@@ -82,6 +83,7 @@ int smooth_args(dg_problem *pr, const dg_smooth_opts *o, SmoothArgs &a) {
   a.zero_guess = o->zero_guess;
   a.write_du = 0;
   a.defect = 1;
+  a.sweep = o->sweep;
   return DG_OK;
 }
 
@@ -111,6 +113,57 @@ int sweeps(dg_problem *pr, int prec, const void *f, const void *src, void *dst, 
     cur = out;
   }
   if (cur != dst) DG_HIP(hipMemcpyAsync(dst, cur, (size_t)pr->ndof * esize(prec), hipMemcpyDeviceToDevice, s));
+  return DG_OK;
+}
+
+// One block-SOR sweep (alg block_SOR) over the red-black order, in place on
+// u: colour 0 then colour 1 (backward: 1 then 0).  zero: u is taken as 0
+// (the first colour skips the defect and clears the other colour).
+int sor_pass(dg_problem *pr, int prec, const void *f, void *u, bool backward, bool zero, const SmoothArgs &base,
+             int *iters, hipStream_t s) {
+  for (int h = 0; h < 2; ++h) {
+    SmoothArgs a = base;
+    a.colour = backward ? 1 - h : h;
+    a.sor = 1;
+    a.zh = nullptr;
+    a.zero_guess = (zero && h == 0) ? 1 : 0;
+    int rc = launch_smooth(pr, prec, f, u, u, a, iters, s);
+    if (rc) return rc;
+  }
+  return DG_OK;
+}
+
+// Direction of the k-th of the n_dir single-direction sweeps of n steps of
+// the given SOR kind (SSOR: forward, backward, forward, ...).
+bool sor_backward(int sweep, int k) {
+  if (sweep == DG_SWEEP_SSOR) return k % 2 == 1;
+  return sweep == DG_SWEEP_SOR_BACKWARD;
+}
+int sor_dirs(int sweep, int n) { return sweep == DG_SWEEP_SSOR ? 2 * n : n; }
+
+// n block-SOR/SSOR steps in place on dst, starting from src (NULL = zero;
+// src != dst is copied first) plus the optional P0 correction P zh.
+int sor_sweeps(dg_problem *pr, int prec, const void *f, const void *src, void *dst, int n, int sweep,
+               const SmoothArgs &base, hipStream_t s, const void *zh = nullptr) {
+  const bool zero = src == nullptr;
+  int rc;
+  if (!zero && src != dst) DG_HIP(hipMemcpyAsync(dst, src, (size_t)pr->ndof * esize(prec), hipMemcpyDeviceToDevice, s));
+  if (zh) {
+    if (zero) {
+      set_error("internal: a P0 correction needs a smoothed input");
+      return DG_EINVAL;
+    }
+    rc = prec == DG_FP64 ? prolong_add_p0<double>(pr->ndof, pr->nloc, (const double *)zh, (double *)dst, s)
+                         : prolong_add_p0<float>(pr->ndof, pr->nloc, (const float *)zh, (float *)dst, s);
+    if (rc) return rc;
+  }
+  if (n <= 0) {
+    if (zero) DG_HIP(hipMemsetAsync(dst, 0, (size_t)pr->ndof * esize(prec), s));
+    return DG_OK;
+  }
+  const int nd = sor_dirs(sweep, n);
+  for (int k = 0; k < nd; ++k)
+    if ((rc = sor_pass(pr, prec, f, dst, sor_backward(sweep, k), zero && k == 0, base, nullptr, s))) return rc;
   return DG_OK;
 }
 
@@ -282,9 +335,17 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
   void *t0;
   if ((rc = alloc_tmp(pr, prec, 0, &t0))) return rc;
   // presmoothing ends in X so that postsmoothing ends in z without a copy
-  void *X = (o->n_post % 2 == 1) ? t0 : (void *)z;
+  // (the SOR sweeps work in place: X = z)
+  const int sw = sa.sweep;
+  const bool sor = sw != DG_SWEEP_JACOBI;
+  const int sw_post = sw == DG_SWEEP_SOR ? DG_SWEEP_SOR_BACKWARD : (sw == DG_SWEEP_SOR_BACKWARD ? DG_SWEEP_SOR : sw);
+  void *X = (!sor && o->n_post % 2 == 1) ? t0 : (void *)z;
   void *Y = (X == t0) ? (void *)z : t0;
-  if ((rc = sweeps(pr, prec, r, nullptr, X, Y, o->n_pre, sa, nullptr, s))) return rc;
+  if (sor)
+    rc = sor_sweeps(pr, prec, r, nullptr, X, o->n_pre, sw, sa, s);
+  else
+    rc = sweeps(pr, prec, r, nullptr, X, Y, o->n_pre, sa, nullptr, s);
+  if (rc) return rc;
   // residual and restriction R = P^T
   using LP = LevelPtr<T>;
   CoarseLevel &L0 = H.levels[0];
@@ -312,8 +373,10 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
     // prolongation P (nodal interpolation of the trilinear correction)
     if ((rc = q1_prolong_add<T>(pr->p, pr->geo.nx, pr->geo.ny, pr->geo.nz, xh, (T *)X, s))) return rc;
     if (o->n_post == 0) return DG_OK;  // X == z here
+    if (sor) return sor_sweeps(pr, prec, r, z, z, o->n_post, sw_post, sa, s);
     return sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s);
   }
+  if (sor) return sor_sweeps(pr, prec, r, z, z, o->n_post, sw_post, sa, s, xh);
   if (o->n_post == 0) return prolong_add_p0<T>(pr->ndof, pr->nloc, xh, (T *)X, s);  // X == z here
   // prolongation P (injection) fused into the first postsmoothing sweep
   return sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s, xh);
@@ -337,6 +400,7 @@ void dg_default_smooth_opts(dg_smooth_opts *o) {
   o->inner = DG_INNER_CG;
   o->restart = 12;
   o->zero_guess = 0;
+  o->sweep = DG_SWEEP_JACOBI;
 }
 
 void dg_default_mg_opts(dg_mg_opts *o) {
@@ -443,10 +507,6 @@ int dg_block_smooth(dg_problem *pr, int precision, const void *f, const void *u_
     return DG_EINVAL;
   }
   if (!opts->zero_guess && (rc = check_vec(u_in, "u_in"))) return rc;
-  if (u_in == u_out || f == u_out) {
-    set_error("dg_block_smooth: u_out must differ from u_in and f");
-    return DG_EINVAL;
-  }
   if (opts->n_sweeps < 1) {
     set_error("n_sweeps must be >= 1");
     return DG_EINVAL;
@@ -454,6 +514,42 @@ int dg_block_smooth(dg_problem *pr, int precision, const void *f, const void *u_
   SmoothArgs a;
   if ((rc = smooth_args(pr, opts, a))) return rc;
   hipStream_t s = S(stream);
+  if (a.sweep != DG_SWEEP_JACOBI) {
+    if (f == u_out) {
+      set_error("dg_block_smooth: u_out must differ from f");
+      return DG_EINVAL;
+    }
+    const bool zero = opts->zero_guess != 0;
+    if (!zero && u_in != u_out)
+      DG_HIP(hipMemcpyAsync(u_out, u_in, (size_t)pr->ndof * esize(precision), hipMemcpyDeviceToDevice, s));
+    int *iters = stats ? pr->iters_buf : nullptr;
+    unsigned long long tot = 0;
+    int mx = 0;
+    const int nd = sor_dirs(a.sweep, opts->n_sweeps);
+    for (int k = 0; k < nd; ++k) {
+      if ((rc = sor_pass(pr, precision, f, u_out, sor_backward(a.sweep, k), zero && k == 0, a, iters, s))) return rc;
+      if (stats) {
+        unsigned long long *dev = (unsigned long long *)pr->red_buf;
+        if ((rc = iter_stats(pr->ncell, iters, dev, s))) return rc;
+        unsigned long long h[2];
+        DG_HIP(hipMemcpyAsync(h, dev, sizeof(h), hipMemcpyDeviceToHost, s));
+        DG_HIP(hipStreamSynchronize(s));
+        tot += h[0];
+        mx = (int)h[1] > mx ? (int)h[1] : mx;
+      }
+    }
+    if (stats) {
+      stats->blocks = (long long)pr->ncell * nd;
+      stats->inner_total = (long long)tot;
+      stats->inner_max = mx;
+      stats->inner_avg = stats->blocks ? (double)tot / stats->blocks : 0.0;
+    }
+    return DG_OK;
+  }
+  if (u_in == u_out || f == u_out) {
+    set_error("dg_block_smooth: u_out must differ from u_in and f");
+    return DG_EINVAL;
+  }
   void *alt = nullptr;
   if (opts->n_sweeps > 1 && (rc = alloc_tmp(pr, precision, 2, &alt))) return rc;
   int *iters = stats ? pr->iters_buf : nullptr;
@@ -551,10 +647,21 @@ int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, doubl
   if (o->precond == DG_PRECOND_MG) {
     if ((rc = vcycle(pr, prec, rin, zout, &o->mg, s))) return rc;
   } else {
+    // block smoother steps from zero: mg.smooth.n_sweeps of mg.smooth.sweep
     SmoothArgs a;
     if ((rc = smooth_args(pr, &o->mg.smooth, a))) return rc;
-    a.zero_guess = 1;
-    if ((rc = launch_smooth(pr, prec, rin, rin, zout, a, nullptr, s))) return rc;
+    const int n = o->mg.smooth.n_sweeps > 1 ? o->mg.smooth.n_sweeps : 1;
+    if (a.sweep != DG_SWEEP_JACOBI) {
+      rc = sor_sweeps(pr, prec, rin, nullptr, zout, n, a.sweep, a, s);
+    } else if (n == 1) {
+      a.zero_guess = 1;
+      rc = launch_smooth(pr, prec, rin, rin, zout, a, nullptr, s);
+    } else {
+      void *alt;
+      if ((rc = alloc_tmp(pr, prec, 2, &alt))) return rc;
+      rc = sweeps(pr, prec, rin, nullptr, zout, alt, n, a, nullptr, s);
+    }
+    if (rc) return rc;
   }
   if (mixed && (rc = cast_f2d(pr->ndof, 1.0 / sc, z32, z, s))) return rc;
   return DG_OK;

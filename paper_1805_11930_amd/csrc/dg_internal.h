@@ -201,6 +201,9 @@ struct SmoothArgs {
   int write_du;     // output is the correction only (block solve)
   int defect;       // compute d = f - A u (otherwise d = f)
   const void *zh = nullptr;  // optional P0 correction: u_in + P zh is smoothed
+  int colour = -1;  // >= 0: one red-black colour, in place (uin == uout)
+  int sor = 0;      // block-SOR update form (alg block_SOR)
+  int sweep = 0;    // DG_SWEEP_* of the options (host-side dispatch)
 };
 int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin, void *uout,
                   const SmoothArgs &a, int *iters, hipStream_t s);

@@ -62,6 +62,13 @@ struct SmoothKArgs {
   double omega, eps;
   int max_inner, restart;
   int zero_guess, write_du, defect;
+  // colour >= 0: only the cells with (ix + iy + iz) % 2 == colour, slot j
+  // of the grid -> half-row j / hx (hx = ceil(nx / 2)), cell
+  // ix = 2 (j % hx) + ((iy + iz + colour) & 1); rows = ny * nz.
+  int colour, hx, rows;
+  // block-SOR form (alg block_SOR): the defect leaves out the cell's own
+  // block and the new value is (1 - omega) u + omega x
+  int sor;
 };
 
 // Per-lane data of the three lines (x: y=a,z=b; y: x=a,z=b; z: x=a,y=b)
@@ -144,8 +151,11 @@ __device__ inline void contract(const T *M, const T (&u)[N], T (&v)[N]) {
 }
 
 template <int P, int INNER, typename T, bool HASB>
-__global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__restrict__ f,
-                                                           const T *__restrict__ uin, T *__restrict__ uout,
+//
+// uin and uout may be the same vector for a colour sweep: the cells written
+// are exactly the cells of that colour, each by its own lanes after they
+// read it, and the neighbours read all have the other colour.
+__global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__restrict__ f, const T *uin, T *uout,
                                                            SmoothKArgs sa, int *__restrict__ iters,
                                                            const T *__restrict__ zh, const T *__restrict__ fdm) {
   constexpr int N = P + 1;
@@ -165,8 +175,28 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   const int tid = threadIdx.x;
   const int cw = tid / L;
   const int lane = tid - cw * L;
-  const int c = blockIdx.x * S::CPW + cw;
-  const bool on = (lane < S::N2) && (c < g.ncell);
+  const int slot = blockIdx.x * S::CPW + cw;
+  int c = slot;
+  bool valid = slot < g.ncell;
+  if (sa.colour >= 0) {
+    const int r = slot / sa.hx;
+    const int t = slot - r * sa.hx;
+    const int iy = r % g.ny, iz = r / g.ny;
+    const int s0 = (iy + iz + sa.colour) & 1;
+    const int ix = 2 * t + s0;
+    valid = r < sa.rows && ix < g.nx;
+    c = valid ? ix + g.nx * r : 0;
+    // from a zero guess the slot also clears its x-partner cell
+    // 2t + 1 - s0 of the other colour (the pairs (2t, 2t+1) cover the row),
+    // so that the other colour's sweep starts from zero
+    const int px = 2 * t + 1 - s0;
+    if (sa.zero_guess && r < sa.rows && px < g.nx && lane < S::N2) {
+      T *dst = uout + ((size_t)px + (size_t)g.nx * r) * S::N3;
+#pragma unroll
+      for (int i = 0; i < N; ++i) dst[lpos<N>(0, i, lane % N, lane / N)] = T(0);
+    }
+  }
+  const bool on = (lane < S::N2) && valid;
   const int a = on ? lane % N : 0;
   const int b = on ? lane / N : 0;
   T *Ps = Ps_all + cw * S::N3;
@@ -198,7 +228,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   if (INNER == DG_INNER_FDM) {
     // the cell's stored factors [3][N*N + N] -> T_k into Ms, lambda_k into Lm
     constexpr int NF = S::N2 + N;
-    if (c < g.ncell) {
+    if (valid) {
       const T *src = fdm + (size_t)c * 3 * NF;
       for (int e = lane; e < 3 * NF; e += L) {
         const int k = e / NF, j = e - k * NF;
@@ -229,10 +259,12 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   if (sa.defect && !sa.zero_guess) {
     const int nn[3] = {g.nx, g.ny, g.nz};
     const int stride[3] = {1, g.nx, g.nx * g.ny};
-    T ax[N];
+    T ax[N], own[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) own[i] = sa.sor ? T(0) : ul[i];
     if (on) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) Ps[lpos<N>(0, i, a, b)] = ul[i];
+      for (int i = 0; i < N; ++i) Ps[lpos<N>(0, i, a, b)] = own[i];
     }
     __syncthreads();
 #pragma unroll
@@ -240,7 +272,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
       if (on) {
         T line[N], out[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) line[i] = k == 0 ? ul[i] : Ps[lpos<N>(k, i, a, b)];
+        for (int i = 0; i < N; ++i) line[i] = k == 0 ? own[i] : Ps[lpos<N>(k, i, a, b)];
         T tLu = T(0), tLd = T(0), tRu = T(0), tRd = T(0);
         if (ijk[k] > 0) {
           const int cn = c - stride[k];
@@ -576,9 +608,10 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   // ---- update ---------------------------------------------------------------
   if (on) {
     const T om = (T)sa.omega;
+    const T keep = sa.sor ? T(1) - om : T(1);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const T val = sa.write_du ? x[i] : ul[i] + om * x[i];
+      const T val = sa.write_du ? x[i] : keep * ul[i] + om * x[i];
       uout[base + lpos<N>(0, i, a, b)] = val;
     }
     if (iters && lane == 0) iters[c] = it;
@@ -590,8 +623,13 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
                            int *iters, hipStream_t s) {
   constexpr int N = P + 1;
   using Sh = SmoothShape<N>;
-  const int G = (int)((pr->ncell + Sh::CPW - 1) / Sh::CPW);
   SmoothKArgs ka;
+  ka.colour = a.colour;
+  ka.hx = (pr->geo.nx + 1) / 2;
+  ka.rows = pr->geo.ny * pr->geo.nz;
+  ka.sor = a.sor;
+  const int64_t slots = a.colour >= 0 ? (int64_t)ka.hx * ka.rows : pr->ncell;
+  const int G = (int)((slots + Sh::CPW - 1) / Sh::CPW);
   ka.omega = a.omega;
   ka.eps = a.eps;
   ka.max_inner = a.max_inner;
@@ -630,6 +668,11 @@ int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin
                   int *iters, hipStream_t s) {
   if (a.zh && (a.zero_guess || !a.defect)) {
     set_error("a P0 correction needs a smoothed input");
+    return DG_EINVAL;
+  }
+  if ((a.colour >= 0) != (uin == uout) || (a.colour >= 0 && (a.zh || a.write_du || !a.defect)) ||
+      a.colour > 1) {
+    set_error("internal: a colour sweep runs in place, without a P0 correction");
     return DG_EINVAL;
   }
   if (a.inner == DG_INNER_GMRES && (a.restart < 1 || a.restart > kGmresMax)) {

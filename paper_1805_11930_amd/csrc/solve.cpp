@@ -34,6 +34,11 @@ int validate_solve_opts(const dg_solve_opts *o) {
     return DG_EINVAL;
   }
   if (o->precond == DG_PRECOND_MG) return validate_mg_opts(&o->mg);
+  if (o->precond == DG_PRECOND_BLOCK && (o->mg.smooth.n_sweeps > 64 || o->mg.smooth.sweep < DG_SWEEP_JACOBI ||
+                                         o->mg.smooth.sweep > DG_SWEEP_SOR_BACKWARD)) {
+    set_error("block preconditioner: n_sweeps <= 64 and sweep DG_SWEEP_*");
+    return DG_EINVAL;
+  }
   return DG_OK;
 }
 }  // namespace dgmg
@@ -313,6 +318,10 @@ extern "C" int dg_footprint(const dg_problem_desc *d, const dg_solve_opts *o, si
   }
   const size_t pe = o->precond_precision == DG_FP32 ? sizeof(float) : sizeof(double);
   if (o->precond == DG_PRECOND_MG) b += 2 * ndof * pe;
+  if (o->precond == DG_PRECOND_BLOCK && o->mg.smooth.sweep == DG_SWEEP_JACOBI && o->mg.smooth.n_sweeps > 1)
+    b += ndof * pe;
+  if (o->precond != DG_PRECOND_NONE && o->mg.smooth.inner == DG_INNER_FDM)
+    b += ncell * 3 * (int64_t)(d->p + 1) * (d->p + 2) * both;  // stored factors T_k, lambda_k
   if (o->precond_precision == DG_FP32 && o->precond != DG_PRECOND_NONE) b += 2 * ndof * sizeof(float);
   int64_t nvec = 2;  // residual + temporary of dg_solve
   if (o->krylov == DG_KRYLOV_FGMRES) {

@@ -149,7 +149,8 @@ class Problem:
     def block_smooth(self, f: torch.Tensor, u_in: torch.Tensor | None, opts: L.SmoothOpts | None = None,
                      out: torch.Tensor | None = None, stats: bool = False):
         opts = opts or L.smooth_opts()
-        if u_in is None:
+        if u_in is None and not opts.zero_guess:
+            opts = L.SmoothOpts.from_buffer_copy(opts)  # leave the caller's options unchanged
             opts.zero_guess = 1
         if out is None:
             out = torch.empty_like(f)
