@@ -12,7 +12,9 @@ Each routine takes the paper's steps in the paper's order:
   * the block systems D_T du_T = d_T (eqn block_system) are solved either
     exactly (dense LU) or inexactly with a Krylov method stopped when the
     2-norm of the block residual has dropped by the factor eps (Sec. 2.2.1),
-    preconditioned by the diagonal of D_T (Sec. 3.2);
+    preconditioned by the diagonal of D_T or, for strongly convective
+    blocks, by its tridiagonal part solved with the Thomas algorithm
+    (Sec. 3.2, Sec. 4.3);
   * intergrid operators: P0 injection, P|_T = (1, ..., 1)^T, R = P^T
     (Sec. 2.2.2);
   * coarse matrix A_hat = P^T A P (eqn galerkin_product) and its direct
@@ -74,8 +76,42 @@ def block_pcg(D: np.ndarray, d: np.ndarray, eps: float, max_inner: int):
     return x, it
 
 
-def block_gmres(D: np.ndarray, d: np.ndarray, eps: float, max_inner: int, restart: int):
-    """Right-preconditioned restarted GMRES on D x = d from x = 0, M = diag(D).
+def thomas(sub: np.ndarray, diag: np.ndarray, sup: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Solve the tridiagonal system  sub_i x_{i-1} + diag_i x_i + sup_i x_{i+1}
+    = v_i  by the Thomas algorithm (Gaussian elimination without pivoting:
+    a forward sweep that removes the sub-diagonal, then back substitution)."""
+    n = v.size
+    cp = np.zeros(n)
+    y = np.zeros(n)
+    for i in range(n):
+        m = diag[i] - (sub[i] * cp[i - 1] if i > 0 else 0.0)
+        cp[i] = sup[i] / m if i < n - 1 else 0.0
+        y[i] = (v[i] - (sub[i] * y[i - 1] if i > 0 else 0.0)) / m
+    x = np.zeros(n)
+    for i in range(n - 1, -1, -1):
+        x[i] = y[i] - (cp[i] * x[i + 1] if i < n - 1 else 0.0)
+    return x
+
+
+def block_preconditioner(D: np.ndarray, kind: str):
+    """v -> M^-1 v for the inner Krylov method (Sec. 3.2): 'diag' divides by
+    the diagonal of D_T; 'tridiag' solves with the tridiagonal part of D_T
+    (cell DOFs in their x-fastest order) by the Thomas algorithm."""
+    if kind == "diag":
+        minv = 1.0 / np.diag(D)
+        return lambda v: minv * v
+    if kind == "tridiag":
+        n = D.shape[0]
+        diag = np.diag(D).copy()
+        sub = np.concatenate([[0.0], np.diag(D, -1)])
+        sup = np.concatenate([np.diag(D, 1), [0.0]])
+        return lambda v: thomas(sub, diag, sup, v)
+    raise ValueError(kind)
+
+
+def block_gmres(D: np.ndarray, d: np.ndarray, eps: float, max_inner: int, restart: int, precond: str = "diag"):
+    """Right-preconditioned restarted GMRES on D x = d from x = 0 with
+    M = diag(D) or the tridiagonal part of D (block_preconditioner).
 
     Modified Gram-Schmidt Arnoldi, Givens rotations; stops when the
     Arnoldi residual estimate |g_{j+1}| <= eps ||d||_2 or after max_inner
@@ -86,7 +122,7 @@ def block_gmres(D: np.ndarray, d: np.ndarray, eps: float, max_inner: int, restar
     dnorm = np.linalg.norm(d)
     if dnorm == 0.0:
         return x, 0
-    minv = 1.0 / np.diag(D)
+    minv = block_preconditioner(D, precond)
     target = eps * dnorm
     it = 0
     r = d.copy()
@@ -103,7 +139,7 @@ def block_gmres(D: np.ndarray, d: np.ndarray, eps: float, max_inner: int, restar
         done = False
         k = 0
         for j in range(m):
-            w = D @ (minv * V[j])
+            w = D @ minv(V[j])
             it += 1
             for i in range(j + 1):
                 H[i, j] = w @ V[i]
@@ -127,7 +163,7 @@ def block_gmres(D: np.ndarray, d: np.ndarray, eps: float, max_inner: int, restar
                 break
             V[j + 1] = w / hnext
         y = sla.solve_triangular(H[:k, :k], g[:k], lower=False)
-        x = x + minv * (V[:k].T @ y)
+        x = x + minv(V[:k].T @ y)
         if done or it >= max_inner:
             return x, it
         r = d - D @ x
@@ -140,7 +176,7 @@ def block_gmres(D: np.ndarray, d: np.ndarray, eps: float, max_inner: int, restar
 # block-Jacobi smoother (alg block_jacobi)
 # ---------------------------------------------------------------------------
 def block_jacobi(A, Dblocks, f, u0, omega=1.0, nsweeps=1, inner="exact", eps=1e-2,
-                 max_inner=None, restart=30, stats=None):
+                 max_inner=None, restart=30, stats=None, precond="diag"):
     """n_sweeps block-Jacobi steps u <- u + omega D^-1_eps (f - A u)."""
     ncell, nb, _ = Dblocks.shape
     if max_inner is None:
@@ -155,7 +191,7 @@ def block_jacobi(A, Dblocks, f, u0, omega=1.0, nsweeps=1, inner="exact", eps=1e-
             elif inner == "cg":
                 du[T], it = block_pcg(Dblocks[T], d[T], eps, max_inner)
             elif inner == "gmres":
-                du[T], it = block_gmres(Dblocks[T], d[T], eps, max_inner, min(restart, nb))
+                du[T], it = block_gmres(Dblocks[T], d[T], eps, max_inner, min(restart, nb), precond)
             else:
                 raise ValueError(inner)
             if stats is not None:
@@ -164,13 +200,13 @@ def block_jacobi(A, Dblocks, f, u0, omega=1.0, nsweeps=1, inner="exact", eps=1e-
     return u
 
 
-def _inner_solve(D, d, inner, eps, max_inner, restart):
+def _inner_solve(D, d, inner, eps, max_inner, restart, precond="diag"):
     if inner == "exact":
         return block_solve_exact(D, d)
     if inner == "cg":
         return block_pcg(D, d, eps, max_inner)
     if inner == "gmres":
-        return block_gmres(D, d, eps, max_inner, min(restart, d.size))
+        return block_gmres(D, d, eps, max_inner, min(restart, d.size), precond)
     raise ValueError(inner)
 
 
@@ -193,7 +229,7 @@ def multicolour_order(prob: _dg.Problem) -> np.ndarray:
 
 
 def block_sor(A, Dblocks, f, u0, order, omega=1.0, nsweeps=1, inner="exact", eps=1e-2,
-              max_inner=None, restart=30, stats=None):
+              max_inner=None, restart=30, stats=None, precond="diag"):
     """n_sweeps forward block-SOR steps over the cells in ``order``.
 
     Alg block_SOR: cell T_rho, taken in the given order, forms its local
@@ -218,7 +254,7 @@ def block_sor(A, Dblocks, f, u0, order, omega=1.0, nsweeps=1, inner="exact", eps
                 sigma = Ab.indices[k]
                 if sigma != rho:
                     d -= Ab.data[k] @ u[sigma]
-            du, it = _inner_solve(Dblocks[rho], d, inner, eps, max_inner, restart)
+            du, it = _inner_solve(Dblocks[rho], d, inner, eps, max_inner, restart, precond)
             if stats is not None:
                 stats.append(it)
             u[rho] = (1.0 - omega) * u[rho] + omega * du
@@ -408,7 +444,7 @@ def q1_direct(prob: _dg.Problem) -> np.ndarray:
 # ---------------------------------------------------------------------------
 def vcycle(A, Dblocks, prob: _dg.Problem, r, coarse_solve, n_pre=1, n_post=1, omega=1.0,
            inner="exact", eps=1e-2, max_inner=None, restart=30, stats=None, P=None,
-           smoother="jacobi", order=None):
+           smoother="jacobi", order=None, precond="diag"):
     """z ~= A^-1 r: presmooth from zero, residual, restrict, coarse solve,
     prolongate-add, postsmooth.  P: prolongation (default: P0).
 
@@ -421,7 +457,8 @@ def vcycle(A, Dblocks, prob: _dg.Problem, r, coarse_solve, n_pre=1, n_post=1, om
     if order is None:
         order = multicolour_order(prob)
     order = np.asarray(order)
-    kw = dict(omega=omega, inner=inner, eps=eps, max_inner=max_inner, restart=restart, stats=stats)
+    kw = dict(omega=omega, inner=inner, eps=eps, max_inner=max_inner, restart=restart, stats=stats,
+              precond=precond)
 
     def smooth(u, n, post):
         if smoother == "jacobi":

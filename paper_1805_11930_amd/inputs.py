@@ -18,6 +18,9 @@ synthetic stand-in with SPE10's shape and contrast):
       (59, 219, :).
   W4  unit cube, 48^3 cells, p=3, K = 1e-3 I, b = (-(y-1/2), x-1/2, 0.2),
       c = 0, f = 1, homogeneous Dirichlet.
+  Pe2000  the paper's convection-dominated problem (Sec. 4.3): [0,1]^2 x
+      [0,2], b = (1,0,0) or (1, 0.5, 0.3), kappa = max b_i h / 2000,
+      u = X(1-X) Y(1-Y) Z(1-Z), homogeneous Dirichlet.
   W5  serving mix: N in {8,12,16,24,32} cells per side, p in {2,3,4}, K_T =
       exp(Z_T) I with Z ~ N(0,1), random load vector (seed 5000 + i),
       homogeneous Dirichlet.
@@ -133,6 +136,39 @@ def w4(cells=(48, 48, 48), p=3) -> Workload:
     return Workload("convection-48^3-p3", cells, (1.0, 1.0, 1.0), p, ("D",) * 6, None, 1e-3,
                     b0=(0.5, -0.5, 0.2), B=((0.0, -1.0, 0.0), (1.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
                     f=lambda x: np.ones(len(x)))
+
+
+def pe2000(b=(1.0, 0.0, 0.0), p=3, cells=None) -> Workload:
+    """Convection-dominated problem of the paper's Sec. 4.3:
+    -kappa lap u + div(b u) = f on [0,1] x [0,1] x [0,2], b constant, grid
+    Peclet number max_i b_i h / kappa = 2000, exact solution
+    u = X(1-X) Y(1-Y) Z(1-Z) with X = x/Lx, ..., zero on the boundary
+    (homogeneous Dirichlet).  Default grids: the paper's isotropic grids
+    per degree (p=2: 56x56x112, p=3: 32x32x64, p=4: 20x20x40)."""
+    if cells is None:
+        cells = {1: (128, 128, 256), 2: (56, 56, 112), 3: (32, 32, 64), 4: (20, 20, 40)}[p]
+    lengths = (1.0, 1.0, 2.0)
+    h = lengths[0] / cells[0]
+    kappa = max(b) * h / 2000.0
+    bx, by, bz = b
+
+    def parts(x):
+        X, Y, Z = x[:, 0] / lengths[0], x[:, 1] / lengths[1], x[:, 2] / lengths[2]
+        return X * (1 - X), Y * (1 - Y), Z * (1 - Z), (1 - 2 * X) / lengths[0], (1 - 2 * Y) / lengths[1], \
+            (1 - 2 * Z) / lengths[2]
+
+    def u(x):
+        qx, qy, qz, _, _, _ = parts(x)
+        return qx * qy * qz
+
+    def f(x):
+        qx, qy, qz, dx, dy, dz = parts(x)
+        lap = -2 * (qy * qz / lengths[0] ** 2 + qx * qz / lengths[1] ** 2 + qx * qy / lengths[2] ** 2)
+        return -kappa * lap + bx * dx * qy * qz + by * qx * dy * qz + bz * qx * qy * dz
+
+    name = "convection-pe2000-b%s-%dx%dx%d-p%d" % ("x" if b[1] == 0 and b[2] == 0 else "xyz", *cells, p)
+    return Workload(name, tuple(cells), lengths, p, ("D",) * 6, None, kappa, b0=tuple(b), f=f, exact=u,
+                    info={"kappa": kappa, "peclet": 2000.0})
 
 
 def w5_requests(n: int = 256, seed: int = 55):
