@@ -68,6 +68,7 @@ enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK = 1, DG_PRECOND_MG = 2 };
  * then even): cells of one colour share no face, so each colour is swept
  * in parallel, in place. */
 enum { DG_SWEEP_JACOBI = 0, DG_SWEEP_SOR = 1, DG_SWEEP_SSOR = 2, DG_SWEEP_SOR_BACKWARD = 3 };
+enum { DG_IPREC_DIAG = 0, DG_IPREC_TRIDIAG = 1 };
 enum { DG_COARSE_P0 = 0, DG_COARSE_Q1 = 1, DG_COARSE_AUTO = 2 };
 
 typedef struct dg_problem dg_problem;          /* opaque, library-owned */
@@ -105,9 +106,15 @@ typedef struct {
                        exact block solve with stored per-cell factors (fast
                        diagonalisation of the Kronecker-sum block, built on
                        first use; eps, max_inner, restart are ignored)     */
-  int restart;      /* inner GMRES restart length (<= 0: 16)               */
+  int restart;      /* inner GMRES restart length, 1..16 (<= 0: 12)        */
   int zero_guess;   /* 1: u_in is taken as zero and not read                */
   int sweep;        /* DG_SWEEP_* (default DG_SWEEP_JACOBI)                 */
+  int inner_precond; /* preconditioner of the inner Krylov method (Sec. 3.2):
+                       DG_IPREC_DIAG (default), the diagonal of D_T, or
+                       DG_IPREC_TRIDIAG (inner GMRES only): the tridiagonal
+                       part of D_T in the x-fastest DOF order, solved by the
+                       Thomas algorithm -- for strongly convective blocks,
+                       Sec. 4.3                                              */
 } dg_smooth_opts;
 
 /* Optional smoother statistics (filled after a synchronisation). */

@@ -26,6 +26,7 @@ DG_KRYLOV_CG, DG_KRYLOV_FCG, DG_KRYLOV_FGMRES = 0, 1, 2
 DG_PRECOND_NONE, DG_PRECOND_BLOCK, DG_PRECOND_MG = 0, 1, 2
 DG_PRECOND_BLOCK_JACOBI = DG_PRECOND_BLOCK
 DG_SWEEP_JACOBI, DG_SWEEP_SOR, DG_SWEEP_SSOR, DG_SWEEP_SOR_BACKWARD = 0, 1, 2, 3
+DG_IPREC_DIAG, DG_IPREC_TRIDIAG = 0, 1
 DG_COARSE_P0, DG_COARSE_Q1, DG_COARSE_AUTO = 0, 1, 2
 
 EXPORTS = (
@@ -58,7 +59,7 @@ class SmoothOpts(ctypes.Structure):
     _fields_ = [
         ("n_sweeps", ctypes.c_int), ("omega", ctypes.c_double), ("eps", ctypes.c_double),
         ("max_inner", ctypes.c_int), ("inner", ctypes.c_int), ("restart", ctypes.c_int),
-        ("zero_guess", ctypes.c_int), ("sweep", ctypes.c_int),
+        ("zero_guess", ctypes.c_int), ("sweep", ctypes.c_int), ("inner_precond", ctypes.c_int),
     ]
 
 

@@ -64,8 +64,12 @@ int smooth_args(dg_problem *pr, const dg_smooth_opts *o, SmoothArgs &a) {
   }
   if (!(o->eps >= 0) || !std::isfinite(o->omega) ||
       (o->inner != DG_INNER_CG && o->inner != DG_INNER_GMRES && o->inner != DG_INNER_FDM) ||
-      o->sweep < DG_SWEEP_JACOBI || o->sweep > DG_SWEEP_SOR_BACKWARD) {
-    set_error("invalid smoother options (eps >= 0, finite omega, inner CG, GMRES or FDM, sweep DG_SWEEP_*)");
+      o->sweep < DG_SWEEP_JACOBI || o->sweep > DG_SWEEP_SOR_BACKWARD ||
+      (o->inner_precond != DG_IPREC_DIAG && o->inner_precond != DG_IPREC_TRIDIAG) ||
+      (o->inner_precond == DG_IPREC_TRIDIAG && o->inner != DG_INNER_GMRES)) {
+    set_error(
+        "invalid smoother options (eps >= 0, finite omega, inner CG, GMRES or FDM, sweep DG_SWEEP_*, "
+        "inner_precond DG_IPREC_DIAG, or DG_IPREC_TRIDIAG with inner GMRES)");
     return DG_EINVAL;
   }
   if (o->inner == DG_INNER_FDM) {
@@ -84,6 +88,7 @@ int smooth_args(dg_problem *pr, const dg_smooth_opts *o, SmoothArgs &a) {
   a.write_du = 0;
   a.defect = 1;
   a.sweep = o->sweep;
+  a.tridiag = o->inner_precond == DG_IPREC_TRIDIAG;
   return DG_OK;
 }
 
@@ -401,6 +406,7 @@ void dg_default_smooth_opts(dg_smooth_opts *o) {
   o->restart = 12;
   o->zero_guess = 0;
   o->sweep = DG_SWEEP_JACOBI;
+  o->inner_precond = DG_IPREC_DIAG;
 }
 
 void dg_default_mg_opts(dg_mg_opts *o) {

@@ -204,6 +204,7 @@ struct SmoothArgs {
   int colour = -1;  // >= 0: one red-black colour, in place (uin == uout)
   int sor = 0;      // block-SOR update form (alg block_SOR)
   int sweep = 0;    // DG_SWEEP_* of the options (host-side dispatch)
+  int tridiag = 0;  // inner preconditioner: tridiagonal part of D_T (Thomas)
 };
 int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin, void *uout,
                   const SmoothArgs &a, int *iters, hipStream_t s);

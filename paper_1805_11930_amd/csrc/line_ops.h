@@ -232,6 +232,37 @@ __host__ __device__ inline T line_diag(const DevTab<T, N> &tb, const AxisCoef<T>
   return d;
 }
 
+// Entry (i, l) of the line operator without neighbour couplings: component
+// i of line_apply applied to the unit vector e_l with zero neighbour traces.
+template <typename T, int N>
+__host__ __device__ inline T line_entry(const DevTab<T, N> &tb, const AxisCoef<T> &f, T stan, T vol, T cre, bool hasb,
+                                        const LineConv<T> &lc, int i, int l) {
+  const T ih = f.ih;
+  T m = stan * vol * f.d * ih * ih * tb.S[i][l];
+  if (i == l) m += cre * vol * stan * tb.w[i];
+  if (hasb) m += -stan * vol * ih * tb.Dt[i][l] * tb.w[l] * (lc.beta + lc.Bkk * (lc.xk0 + tb.xi[l] * lc.hk));
+  const T WF = stan * vol * ih;
+  if (f.fl & 2) {
+    const T uM = tb.e1[l], gM = tb.d1[l];
+    T s = -f.kR * gM * ih + f.gR * uM;
+    if (hasb) {
+      const T bnu = lc.beta + lc.Bkk * (lc.xk0 + lc.hk);
+      s += bnu >= T(0) ? bnu * uM : T(0);
+    }
+    m += WF * (s * tb.e1[i] - f.kR * uM * ih * tb.d1[i]);
+  }
+  if (f.fl & 1) {
+    const T uP = tb.e0[l], gP = tb.d0[l];
+    T s = -f.kL * gP * ih - f.gL * uP;
+    if (hasb) {
+      const T bk = lc.beta + lc.Bkk * lc.xk0;
+      s += bk >= T(0) ? T(0) : bk * uP;
+    }
+    m += -WF * s * tb.e0[i] + WF * f.kL * uP * ih * tb.d0[i];
+  }
+  return m;
+}
+
 // Entry (i, l) of the 1-D block operator along one axis for b = 0, without
 // the tangential weight factor: the line part of D_T is stan * M u with
 //   M = vol [ d/h^2 S + (1/h) (face at xi=1) + (1/h) (face at xi=0) ]

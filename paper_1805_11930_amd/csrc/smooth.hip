@@ -150,11 +150,33 @@ __device__ inline void contract(const T *M, const T (&u)[N], T (&v)[N]) {
   }
 }
 
-template <int P, int INNER, typename T, bool HASB>
-//
+// Inner preconditioner M^-1 v on the lane's x-line: the diagonal of D_T
+// (TRI = false: dinv = 1 / diag), or the tridiagonal part of D_T solved by
+// the Thomas algorithm (TRI = true: dinv = 1 / pivot, tc = eliminated
+// super-diagonal, tl = sub-diagonal).  With the x-fastest DOF order the
+// tridiagonal part of D_T has no entries between two x-lines, so it is one
+// tridiagonal system per x-line, held in the registers of its lane.
+template <typename T, int N, bool TRI>
+__device__ inline void prec_apply(const T (&dinv)[N], const T (&tc)[N], const T (&tl)[N], const T (&v)[N],
+                                  T (&out)[N]) {
+  if constexpr (!TRI) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = v[i] * dinv[i];
+  } else {
+    T y[N];
+    y[0] = v[0] * dinv[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i) y[i] = (v[i] - tl[i] * y[i - 1]) * dinv[i];
+    out[N - 1] = y[N - 1];
+#pragma unroll
+    for (int i = N - 2; i >= 0; --i) out[i] = y[i] - tc[i] * out[i + 1];
+  }
+}
+
 // uin and uout may be the same vector for a colour sweep: the cells written
 // are exactly the cells of that colour, each by its own lanes after they
 // read it, and the neighbours read all have the other colour.
+template <int P, int INNER, typename T, bool HASB, bool TRI>
 __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__restrict__ f, const T *uin, T *uout,
                                                            SmoothKArgs sa, int *__restrict__ iters,
                                                            const T *__restrict__ zh, const T *__restrict__ fdm) {
@@ -316,8 +338,8 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
     __syncthreads();
   }
 
-  // ---- diagonal preconditioner M = diag(D_T) ------------------------------
-  T dinv[N];
+  // ---- inner preconditioner: M = diag(D_T) or its tridiagonal part ---------
+  T dinv[N], tc[N], tl[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     T dd = T(1);
@@ -337,7 +359,28 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
            line_diag<T, N>(tb, cl.f[1], tb.w[i] * tb.w[b], cl.vol, T(0), hasb, ly, a) +
            line_diag<T, N>(tb, cl.f[2], tb.w[i] * tb.w[a], cl.vol, T(0), hasb, lz, b);
     }
-    dinv[i] = T(1) / dd;
+    dinv[i] = TRI ? dd : T(1) / dd;  // TRI: the diagonal, factored below
+  }
+  if constexpr (TRI) {
+    // Thomas factorisation of the x-line's tridiagonal: pivots
+    // m_i = diag_i - sub_i c_(i-1), c_i = sup_i / m_i
+    T cprev = T(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const T sub = (on && i > 0) ? line_entry<T, N>(tb, cl.f[0], cl.stan, cl.vol, cl.cre, hasb, cl.lc[0], i, i - 1)
+                                  : T(0);
+      const T sup = (on && i < N - 1)
+                        ? line_entry<T, N>(tb, cl.f[0], cl.stan, cl.vol, cl.cre, hasb, cl.lc[0], i, i + 1)
+                        : T(0);
+      const T m = dinv[i] - sub * cprev;
+      dinv[i] = T(1) / m;
+      tc[i] = sup * dinv[i];
+      tl[i] = sub;
+      cprev = tc[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) tc[i] = tl[i] = T(0);
   }
 
   // ---- inner solve D_T x = d ------------------------------------------------
@@ -487,8 +530,15 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
       for (int j = 0; j < R; ++j) {
         if (__ballot(cyc) == 0) break;
         T vj[N], w[N];
+        if constexpr (TRI) {
+          T vv[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) vj[i] = on ? Vs[j * S::N3 + my + i] * dinv[i] : T(0);
+          for (int i = 0; i < N; ++i) vv[i] = on ? Vs[j * S::N3 + my + i] : T(0);
+          prec_apply<T, N, TRI>(dinv, tc, tl, vv, vj);
+        } else {
+#pragma unroll
+          for (int i = 0; i < N; ++i) vj[i] = on ? Vs[j * S::N3 + my + i] * dinv[i] : T(0);
+        }
         dt_apply<P, T>(cl, tb, on, hasb, Ms, vj, w, Ps, Qy, Qz, a, b);
         if (cyc) ++it;
         T hcol[kGmresMax + 1];
@@ -575,11 +625,28 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
         y[i] = s;
       }
       if (on) {
+        if constexpr (TRI) {
+          // x += M^-1 (V y)
+          T vy[N], mv[N];
 #pragma unroll
-        for (int i = 0; i < kGmresMax; ++i) {
-          if (i < kk) {
+          for (int l = 0; l < N; ++l) vy[l] = T(0);
 #pragma unroll
-            for (int l = 0; l < N; ++l) x[l] += dinv[l] * y[i] * Vs[i * S::N3 + my + l];
+          for (int i = 0; i < kGmresMax; ++i) {
+            if (i < kk) {
+#pragma unroll
+              for (int l = 0; l < N; ++l) vy[l] += y[i] * Vs[i * S::N3 + my + l];
+            }
+          }
+          prec_apply<T, N, TRI>(dinv, tc, tl, vy, mv);
+#pragma unroll
+          for (int l = 0; l < N; ++l) x[l] += mv[l];
+        } else {
+#pragma unroll
+          for (int i = 0; i < kGmresMax; ++i) {
+            if (i < kk) {
+#pragma unroll
+              for (int l = 0; l < N; ++l) x[l] += dinv[l] * y[i] * Vs[i * S::N3 + my + l];
+            }
           }
         }
       }
@@ -638,26 +705,35 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
   ka.write_du = a.write_du;
   ka.defect = a.defect;
   const bool hb = pr->geo.has_b != 0;
-#define DG_SMOOTH_LAUNCH(INNER, HB)                                                                          \
-  hipLaunchKernelGGL((k_smooth<P, INNER, T, HB>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo, (const T *)f, \
-                     (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh, (const T *)fdm)
+#define DG_SMOOTH_LAUNCH(INNER, HB, TRI)                                                                        \
+  hipLaunchKernelGGL((k_smooth<P, INNER, T, HB, TRI>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo,            \
+                     (const T *)f, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh, (const T *)fdm)
   const void *fdm = pr->fdm[sizeof(T) == 8 ? DG_FP64 : DG_FP32];
   if (a.inner == DG_INNER_FDM) {
     if (hb || !fdm) {
       set_error("the fast-diagonalisation block solve needs b = 0 and its factors");
       return DG_EINVAL;
     }
-    DG_SMOOTH_LAUNCH(DG_INNER_FDM, false);
+    DG_SMOOTH_LAUNCH(DG_INNER_FDM, false, false);
   } else if (a.inner == DG_INNER_CG) {
+    if (a.tridiag) {
+      set_error("the tridiagonal inner preconditioner needs inner GMRES");
+      return DG_EINVAL;
+    }
     if (hb)
-      DG_SMOOTH_LAUNCH(DG_INNER_CG, true);
+      DG_SMOOTH_LAUNCH(DG_INNER_CG, true, false);
     else
-      DG_SMOOTH_LAUNCH(DG_INNER_CG, false);
+      DG_SMOOTH_LAUNCH(DG_INNER_CG, false, false);
+  } else if (a.tridiag) {
+    if (hb)
+      DG_SMOOTH_LAUNCH(DG_INNER_GMRES, true, true);
+    else
+      DG_SMOOTH_LAUNCH(DG_INNER_GMRES, false, true);
   } else {
     if (hb)
-      DG_SMOOTH_LAUNCH(DG_INNER_GMRES, true);
+      DG_SMOOTH_LAUNCH(DG_INNER_GMRES, true, false);
     else
-      DG_SMOOTH_LAUNCH(DG_INNER_GMRES, false);
+      DG_SMOOTH_LAUNCH(DG_INNER_GMRES, false, false);
   }
 #undef DG_SMOOTH_LAUNCH
   DG_HIP(hipGetLastError());
