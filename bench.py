@@ -122,6 +122,46 @@ def serving_leg(n_requests: int) -> dict:
     return out
 
 
+def pe2000_leg(p: int = 3) -> dict:
+    """Convection-dominated problem of Sec. 4.3 on the paper's isotropic grid
+    for degree p: FGMRES(30) to 1e-8 preconditioned by two red-black
+    block-SSOR steps whose block solves are GMRES to eps = 1e-2 with the
+    tridiagonal (Thomas) preconditioner, FP32 and FP64 preconditioner.
+    Reported as time per unknown, the paper's unit for this test."""
+    import torch
+
+    from paper_1805_11930_amd import (DG_FP32, DG_FP64, DG_INNER_GMRES, DG_IPREC_TRIDIAG, DG_KRYLOV_FGMRES,
+                                      DG_PRECOND_BLOCK, DG_SWEEP_SSOR, Problem, ProblemSpec, inputs, solve_opts)
+
+    out = {"preconditioner": "2 x red-black block-SSOR, inner GMRES(12) eps=1e-2 with the Thomas preconditioner",
+           "krylov": "FGMRES(30), rtol 1e-8"}
+    for tag, b in (("b100", (1.0, 0.0, 0.0)), ("b1_05_03", (1.0, 0.5, 0.3))):
+        w = inputs.pe2000(b=b, p=p)
+        P = Problem(ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c,
+                                b0=w.b0, B=w.B))
+        f = P.rhs_from_functions(f=w.f)
+        u = torch.zeros_like(f)
+        row = {"workload": w.name, "ndof": P.ndof}
+        for name, prec in (("mixed", DG_FP32), ("fp64", DG_FP64)):
+            o = solve_opts(krylov=DG_KRYLOV_FGMRES, restart=30, precond=DG_PRECOND_BLOCK, precond_precision=prec,
+                           rtol=1e-8, maxit=300,
+                           smooth=dict(n_sweeps=2, sweep=DG_SWEEP_SSOR, omega=1.0, eps=1e-2, inner=DG_INNER_GMRES,
+                                       restart=12, inner_precond=DG_IPREC_TRIDIAG))
+            best = None
+            for _ in range(3):
+                u.zero_()
+                _, r = P.solve(f, u, o)
+                best = r if best is None or r.t_solve < best.t_solve else best
+            row[name] = {"time_to_solve_s": round(best.t_solve, 4), "iterations": best.iters,
+                         "rel_residual": best.rel_residual,
+                         "us_per_dof": round(best.t_solve / P.ndof * 1e6, 5)}
+            log(f"[bench] Pe=2000 {tag} {name}: {best.t_solve * 1e3:.1f} ms, {best.iters} it, "
+                f"rel_res {best.rel_residual:.2e}")
+        out[tag] = row
+        P.close()
+    return out
+
+
 def event_time(fn, reps: int) -> float:
     """Mean seconds per call of fn() on torch's current stream (HIP events)."""
     import torch
@@ -147,6 +187,7 @@ def main() -> int:
                          "for the convection box and the layered SPE10-like field)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256, help="serving leg size (0 = skip)")
+    ap.add_argument("--pe2000", type=int, default=1, help="run the Pe=2000 convection leg (0 = skip)")
     ap.add_argument("--apply-only", type=int, default=0,
                     help="profiling aid: run this many FP64 applies and exit")
     ap.add_argument("--copy-only", type=int, default=0,
@@ -327,6 +368,8 @@ def main() -> int:
         },
         "fdm_smoother": fdm,
     }
+    if args.pe2000:
+        line["convection_pe2000"] = pe2000_leg()
     if args.serve_requests > 0:
         line["serving"] = serving_leg(args.serve_requests)
     if not args.no_cpu_baseline:
