@@ -26,8 +26,13 @@ documented separately):
     jx + n*(jy + n*jz), n = p + 1;
   * box faces are numbered 0..5 = -x, +x, -y, +y, -z, +z; each has a
     boundary type 'D' (Dirichlet) or 'N' (Neumann);
-  * K is diagonal and constant per cell, c is constant per cell, and the
-    advection field is affine, b(x) = b0 + B x.
+  * K is diagonal, either constant per cell or a field K(x) given as a
+    callable and evaluated at the quadrature points; c likewise; the
+    advection field is affine, b(x) = b0 + B x.  With a K field the face
+    quantities delta = nu^T K nu, the weights omega and the penalty gamma_F
+    are taken pointwise at each face quadrature point, each side's delta
+    from its own evaluation of the field (the same value for a continuous
+    field, so omega = 1/2 there).
 Readings of the paper where it is silent:
   * interior face normal nu points from T- (lower cell index along the
     axis) into T+; ``flip=True`` reverses every interior face (the form is
@@ -66,6 +71,8 @@ class Problem:
     c: np.ndarray | float = 0.0  # (ncell,) or a scalar
     nq: int | None = None  # quadrature points per direction (default p + 1)
     flip: bool = False  # orientation of interior faces (test of invariance)
+    Kfield: object = None  # callable x (npts, 3) -> diagonal of K (npts, 3); overrides K
+    cfield: object = None  # callable x (npts, 3) -> c (npts,); overrides c
     _Kc: np.ndarray = field(init=False, repr=False, default=None)
     _cc: np.ndarray = field(init=False, repr=False, default=None)
 
@@ -123,6 +130,18 @@ class Problem:
     def creact(self, c) -> float:
         return float(self._cc[c])
 
+    def K_at(self, c, x) -> np.ndarray:
+        """Diagonal of K of cell c at physical points x (npts, 3) -> (npts, 3)."""
+        if self.Kfield is not None:
+            return np.asarray(self.Kfield(x), dtype=np.float64).reshape(len(x), 3)
+        return np.broadcast_to(self._Kc[c], (len(x), 3))
+
+    def c_at(self, c, x) -> np.ndarray:
+        """c of cell c at physical points x -> (npts,)."""
+        if self.cfield is not None:
+            return np.asarray(self.cfield(x), dtype=np.float64).reshape(len(x))
+        return np.full(len(x), float(self._cc[c]))
+
     def bfield(self, x: np.ndarray) -> np.ndarray:
         """b at points x[..., 3] -> [..., 3]."""
         return np.asarray(self.b0, dtype=np.float64) + x @ np.asarray(self.B, dtype=np.float64).T
@@ -130,6 +149,21 @@ class Problem:
     @property
     def has_b(self) -> bool:
         return bool(np.any(np.asarray(self.b0) != 0) or np.any(np.asarray(self.B) != 0))
+
+
+def cell_centre_problem(prob: Problem) -> Problem:
+    """The same problem with K and c frozen at the cell centres (constant per
+    cell): the operator the preconditioner works with when K and c are
+    fields (Sec. 4.2: K and c only at cell centres in the preconditioner)."""
+    from dataclasses import replace
+
+    if prob.Kfield is None and prob.cfield is None:
+        return prob
+    centres = np.array([prob.origin(c) + 0.5 * prob.h for c in range(prob.ncell)])
+    K = prob.Kfield(centres) if prob.Kfield is not None else prob._Kc
+    cc = prob.cfield(centres) if prob.cfield is not None else prob._cc
+    return replace(prob, K=np.asarray(K, dtype=np.float64).reshape(prob.ncell, 3),
+                   c=np.asarray(cc, dtype=np.float64).reshape(prob.ncell), Kfield=None, cfield=None)
 
 
 # ---------------------------------------------------------------------------
@@ -213,34 +247,35 @@ def face_weights(prob: Problem, tab: Tables, k: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 def volume_matrix(prob: Problem, tab: Tables, c: int, Phi, G) -> np.ndarray:
     """(A^v_{T,T})_{ij} = a^v(psi_j, psi_i) on cell T = c:
-    sum_q W_q [ (K grad phi_j - b phi_j) . grad phi_i + c phi_j phi_i ]."""
+    sum_q W_q [ (K(x_q) grad phi_j - b phi_j) . grad phi_i + c(x_q) phi_j phi_i ]."""
     h = prob.h
     W = tensor_weights(tab.wq, tab.wq, tab.wq) * np.prod(h)
-    K = prob.Kdiag(c)
+    xq = prob.origin(c) + tensor_points(tab.xq, tab.xq, tab.xq) * h
+    Kq = prob.K_at(c, xq)
     V = np.zeros((Phi.shape[1], Phi.shape[1]))
     for k in AXES:
-        V += K[k] * (G[k].T * W) @ G[k]
+        V += (G[k].T * (W * Kq[:, k])) @ G[k]
     if prob.has_b:
-        xq = prob.origin(c) + tensor_points(tab.xq, tab.xq, tab.xq) * h
         bq = prob.bfield(xq)
         for k in AXES:
             V -= (G[k].T * (W * bq[:, k])) @ Phi
-    cr = prob.creact(c)
-    if cr != 0.0:
-        V += cr * (Phi.T * W) @ Phi
+    cq = prob.c_at(c, xq)
+    if np.any(cq != 0.0):
+        V += (Phi.T * (W * cq)) @ Phi
     return V
 
 
-def penalty_interior(prob: Problem, k: int, dm: float, dp: float) -> float:
+def penalty_interior(prob: Problem, k: int, dm, dp):
     """gamma_F = sigma_p <delta-, delta+> |F| / min(|T-|, |T+|) (uniform mesh:
-    |F| / |T| = 1 / h_k), <a, b> = 2ab / (a + b)."""
+    |F| / |T| = 1 / h_k), <a, b> = 2ab / (a + b); delta scalars or arrays
+    over the face points."""
     h = prob.h
     area = np.prod([h[a] for a in AXES if a != k])
     vol = np.prod(h)
     return prob.sigma_p * (2.0 * dm * dp / (dm + dp)) * area / vol
 
 
-def penalty_boundary(prob: Problem, k: int, d: float) -> float:
+def penalty_boundary(prob: Problem, k: int, d):
     """gamma_F = sigma_p delta |F| / |T| on a Dirichlet face."""
     h = prob.h
     area = np.prod([h[a] for a in AXES if a != k])
@@ -270,7 +305,7 @@ def interior_face_blocks(prob: Problem, tab: Tables, k: int, cl: int, cu: int):
         Tr = {"-": Tr_u, "+": Tr_l}
         Dk = {"-": Dk_u, "+": Dk_l}
         nu_k = -1.0
-    delta = {s: prob.Kdiag(cells[s])[k] for s in "-+"}  # nu^T K nu
+    delta = {s: prob.K_at(cells[s], x)[:, k] for s in "-+"}  # nu^T K nu at the face points
     omega = {"-": delta["+"] / (delta["-"] + delta["+"]), "+": delta["-"] / (delta["-"] + delta["+"])}
     gam = penalty_interior(prob, k, delta["-"], delta["+"])
     sgn = {"-": 1.0, "+": -1.0}  # [[v]] = v- - v+
@@ -285,9 +320,9 @@ def interior_face_blocks(prob: Problem, tab: Tables, k: int, cl: int, cu: int):
     for s in "-+":  # test side
         for t in "-+":  # trial side
             F = sgn[s] * (Tr[s].T * (WF * bnu * chi[t])) @ Tr[t]
-            F -= sgn[s] * omega[t] * delta[t] * (Tr[s].T * WF) @ Dn[t]
-            F -= sgn[t] * omega[s] * delta[s] * (Dn[s].T * WF) @ Tr[t]
-            F += gam * sgn[s] * sgn[t] * (Tr[s].T * WF) @ Tr[t]
+            F -= sgn[s] * (Tr[s].T * (WF * omega[t] * delta[t])) @ Dn[t]
+            F -= sgn[t] * (Dn[s].T * (WF * omega[s] * delta[s])) @ Tr[t]
+            F += sgn[s] * sgn[t] * (Tr[s].T * (WF * gam)) @ Tr[t]
             blocks[(cells[s], cells[t])] = F
     return blocks
 
@@ -299,10 +334,10 @@ def dirichlet_face_matrix(prob: Problem, tab: Tables, c: int, k: int, side: int)
     Tr, Dk, xi = face_tab(prob, tab, k, side)
     WF = face_weights(prob, tab, k)
     nu_k = 1.0 if side == 1 else -1.0
-    d = prob.Kdiag(c)[k]
+    d = prob.K_at(c, prob.origin(c) + xi * h)[:, k]
     gam = penalty_boundary(prob, k, d)
     Dn = nu_k * Dk
-    Bm = -d * (Tr.T * WF) @ Dn - d * (Dn.T * WF) @ Tr + gam * (Tr.T * WF) @ Tr
+    Bm = -(Tr.T * (WF * d)) @ Dn - (Dn.T * (WF * d)) @ Tr + (Tr.T * (WF * gam)) @ Tr
     if prob.has_b:
         bnu = nu_k * prob.bfield(prob.origin(c) + xi * h)[:, k]
         chi = (bnu >= 0.0).astype(np.float64)
@@ -407,13 +442,13 @@ def assemble_rhs(prob: Problem, f=None, g=None, j=None) -> np.ndarray:
             if g is None:
                 continue
             gv = g(x)
-            d = prob.Kdiag(c)[k]
+            d = prob.K_at(c, x)[:, k]
             gam = penalty_boundary(prob, k, d)
             bnu = nu_k * prob.bfield(x)[:, k] if prob.has_b else np.zeros(WF.shape)
             inflow = (bnu < 0.0).astype(np.float64)  # Phi(0, g, b_nu) = b_nu g when b_nu < 0
             rhs[c] -= Tr.T @ (WF * inflow * bnu * gv)
-            rhs[c] -= d * (nu_k * Dk).T @ (WF * gv)
-            rhs[c] += gam * Tr.T @ (WF * gv)
+            rhs[c] -= (nu_k * Dk).T @ (WF * d * gv)
+            rhs[c] += Tr.T @ (WF * gam * gv)
     return rhs.ravel()
 
 

@@ -294,6 +294,8 @@ def p0_direct(prob: _dg.Problem) -> np.ndarray:
     upwind terms and the penalty terms remain (eqn p0_galerkin1); the
     face integrals use the same face quadrature as A.
     """
+    if prob.Kfield is not None or prob.cfield is not None:
+        raise ValueError("coarse matrices are built from the cell-centre problem (dg.cell_centre_problem)")
     tab = _dg.Tables(prob)
     h = prob.h
     nc = prob.ncell
@@ -386,6 +388,8 @@ def q1_direct(prob: _dg.Problem) -> np.ndarray:
     trilinear vertex functions (App. A.2): continuous functions have no
     jumps, so only the volume terms and the Dirichlet-face terms of a_h
     remain; same quadrature as A."""
+    if prob.Kfield is not None or prob.cfield is not None:
+        raise ValueError("coarse matrices are built from the cell-centre problem (dg.cell_centre_problem)")
     tab = _dg.Tables(prob)
     h = prob.h
     xq, wq = tab.xq, tab.wq

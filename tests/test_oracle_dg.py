@@ -18,7 +18,13 @@ the weights omega^+-, the penalty gamma_F and the upwind flux Phi):
   * convergence O(h^(p+1)) in L2 for a smooth manufactured solution
     (observed rate in [p + 0.7, p + 1.3] on the finest pair of meshes);
   * the P0 Galerkin product P^T A P equals the direct evaluation of a_h on
-    P0 indicators (App. A.1).
+    P0 indicators (App. A.1);
+  * coefficient fields (Sec. 4.2): a constant field gives the cell-constant
+    matrix and right-hand side; with K(x) = diag(P_1(x), P_2(y), P_3(z)),
+    P_k quadratic, every integrand is exact, so Q_p solutions are
+    reproduced (this fails if K is frozen anywhere); symmetric positive
+    definite; L2 rates p+1 for a smooth solution; the cell-centre problem
+    of the preconditioner holds the field's centre values.
 """
 import numpy as np
 import pytest
@@ -265,3 +271,110 @@ def test_l2_convergence(p, Ns):
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert rates[-1] >= p + 0.7, (errs, rates)
     assert rates[-1] <= p + 1.3, (errs, rates)
+
+
+# ---------------------------------------------------------------------------
+# coefficient fields K(x), c(x) at the quadrature points (Sec. 4.2)
+# ---------------------------------------------------------------------------
+def _axis_field(q0, q1, q2):
+    """K(x) = diag(P_1(x), P_2(y), P_3(z)), P_k(s) = q0_k + q1_k s + q2_k s^2,
+    and its derivative dP_k/dx_k."""
+    q0, q1, q2 = (np.asarray(v, dtype=np.float64) for v in (q0, q1, q2))
+    return (lambda x: q0 + q1 * x + q2 * x ** 2), (lambda x: q1 + 2.0 * q2 * x)
+
+
+FIELD = ((1.0, 0.5, 2.0), (0.3, -0.2, 0.1), (3.0, 1.0, 0.5))
+
+
+def test_constant_field_equals_cell_constant_coefficients():
+    K0 = np.array([1.3, 0.7, 2.0])
+    bc = ("D", "N", "D", "D", "N", "D")
+    a = dg.Problem(cells=(3, 2, 2), lengths=(1.0, 0.7, 1.3), p=2, K=np.tile(K0, (12, 1)), c=0.4, bc=bc,
+                   b0=(0.2, -0.1, 0.3))
+    b = dg.Problem(cells=(3, 2, 2), lengths=(1.0, 0.7, 1.3), p=2, bc=bc, b0=(0.2, -0.1, 0.3),
+                   Kfield=lambda x: np.tile(K0, (len(x), 1)), cfield=lambda x: np.full(len(x), 0.4))
+    Aa, Ab = dg.assemble(a).toarray(), dg.assemble(b).toarray()
+    assert np.abs(Aa - Ab).max() <= 1e-14 * np.abs(Aa).max()
+    g = lambda x: np.sin(x[:, 0]) + x[:, 1] * x[:, 2]
+    ra, rb = dg.assemble_rhs(a, f=g, g=g, j=g), dg.assemble_rhs(b, f=g, g=g, j=g)
+    assert np.abs(ra - rb).max() <= 1e-14 * np.abs(ra).max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_field_polynomial_reproduction(p):
+    # every integrand is a polynomial of degree <= 2p per direction for a
+    # quadratic P_k(x_k) and u in Q_p, so the p+1-point Gauss rule is exact
+    # and the consistent form reproduces u
+    rng = np.random.default_rng(40 + p)
+    K, dK = _axis_field(*FIELD)
+    c0 = 0.4
+    bc = ("D", "N", "D", "D", "N", "D")
+    pr = dg.Problem(cells=(3, 2, 2), lengths=(1.0, 0.7, 1.3), p=p, bc=bc, Kfield=K,
+                    cfield=lambda x: np.full(len(x), c0))
+    u, grad, hd = _poly_case(p, rng)
+
+    def f(x):  # -div(K grad u) + c u, K_kk depending on x_k only
+        return -np.sum(dK(x) * grad(x) + K(x) * hd(x), axis=1) + c0 * u(x)
+
+    def j(x):  # -K grad u . nu on the Neumann faces +x and -z
+        flux = -K(x) * grad(x)
+        out = np.full(len(x), np.nan)
+        on_px = np.isclose(x[:, 0], 1.0)
+        on_mz = np.isclose(x[:, 2], 0.0)
+        out[on_px] = flux[on_px, 0]
+        out[on_mz] = -flux[on_mz, 2]
+        assert not np.isnan(out).any()
+        return out
+
+    A = dg.assemble(pr)
+    rhs = dg.assemble_rhs(pr, f=f, g=u, j=j)
+    uI = dg.interpolate(pr, u)
+    assert np.abs(rhs - A @ uI).max() <= 1e-12 * np.abs(rhs).max()
+
+
+def test_field_operator_symmetric_positive_definite():
+    K, _ = _axis_field(*FIELD)
+    pr = dg.Problem(cells=(3, 2, 2), p=2, Kfield=K, cfield=lambda x: 1e-8 * np.sum(x ** 2, axis=1))
+    A = dg.assemble(pr).toarray()
+    assert np.abs(A - A.T).max() <= 1e-13 * np.abs(A).max()
+    assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
+
+
+@pytest.mark.parametrize("p,Ns", [(1, (4, 8)), (2, (2, 4))])
+def test_field_l2_convergence(p, Ns):
+    pi = np.pi
+    K, dK = _axis_field(*FIELD)
+
+    def uex(x):
+        return np.sin(pi * x[:, 0]) * np.sin(pi * x[:, 1]) * np.sin(pi * x[:, 2])
+
+    def grad(x):
+        s = np.sin(pi * x)
+        cs = np.cos(pi * x)
+        return pi * np.stack([cs[:, 0] * s[:, 1] * s[:, 2], s[:, 0] * cs[:, 1] * s[:, 2],
+                              s[:, 0] * s[:, 1] * cs[:, 2]], axis=1)
+
+    def f(x):
+        return -np.sum(dK(x) * grad(x), axis=1) + pi ** 2 * np.sum(K(x), axis=1) * uex(x)
+
+    errs = []
+    for N in Ns:
+        pr = dg.Problem(cells=(N, N, N), p=p, Kfield=K)
+        u = spla.spsolve(dg.assemble(pr).tocsc(), dg.assemble_rhs(pr, f=f))
+        errs.append(dg.l2_error(pr, u, uex))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert p + 0.6 <= rates[-1] <= p + 1.4, (errs, rates)
+
+
+def test_cell_centre_problem():
+    K, _ = _axis_field(*FIELD)
+    pr = dg.Problem(cells=(3, 2, 2), lengths=(1.0, 0.7, 1.3), p=1, Kfield=K,
+                    cfield=lambda x: 2.0 + np.sum(x ** 2, axis=1))
+    pc = dg.cell_centre_problem(pr)
+    for c in (0, 5, 11):
+        xc = pr.origin(c) + 0.5 * pr.h
+        assert np.allclose(pc.Kdiag(c), K(xc[None, :])[0], rtol=1e-15)
+        assert pc.creact(c) == pytest.approx(2.0 + xc @ xc, rel=1e-15)
+    with pytest.raises(ValueError):
+        solvers.p0_direct(pr)
+    assert solvers.p0_direct(pc).shape == (12, 12)
