@@ -28,6 +28,7 @@ DG_PRECOND_BLOCK_JACOBI = DG_PRECOND_BLOCK
 DG_SWEEP_JACOBI, DG_SWEEP_SOR, DG_SWEEP_SSOR, DG_SWEEP_SOR_BACKWARD = 0, 1, 2, 3
 DG_IPREC_DIAG, DG_IPREC_TRIDIAG = 0, 1
 DG_COARSE_P0, DG_COARSE_Q1, DG_COARSE_AUTO = 0, 1, 2
+DG_FIELD_NONE, DG_FIELD_AXIS_QUADRATIC = 0, 1
 
 EXPORTS = (
     "dg_problem_create", "dg_problem_destroy", "dg_last_error", "dg_ndof", "dg_boundary_npoints",
@@ -52,6 +53,7 @@ class ProblemDesc(ctypes.Structure):
         ("K", ctypes.POINTER(ctypes.c_double)), ("K_scalar", ctypes.c_double),
         ("c", ctypes.POINTER(ctypes.c_double)), ("c_scalar", ctypes.c_double),
         ("b0", ctypes.c_double * 3), ("B", ctypes.c_double * 9),
+        ("field", ctypes.c_int), ("kq", ctypes.c_double * 9), ("cq", ctypes.c_double * 2),
     ]
 
 
@@ -193,6 +195,11 @@ class ProblemSpec:
     c: np.ndarray | float = 0.0
     b0: tuple = (0.0, 0.0, 0.0)
     B: tuple = ((0.0,) * 3,) * 3
+    # coefficient field (DG_FIELD_AXIS_QUADRATIC): kq = (q0[3], q1[3], q2[3]),
+    # K_kk(x) = q0_k + q1_k x_k + q2_k x_k^2; cq = (c0, c2), c(x) = c0 + c2 |x|^2;
+    # K and c are then ignored
+    kfield: tuple | None = None
+    cfield: tuple = (0.0, 0.0)
     _keep: list = field(default_factory=list, repr=False)
 
     def desc(self) -> ProblemDesc:
@@ -228,6 +235,13 @@ class ProblemSpec:
         Bm = np.asarray(self.B, dtype=np.float64).reshape(9)
         for i in range(9):
             d.B[i] = float(Bm[i])
+        d.field = DG_FIELD_NONE
+        if self.kfield is not None:
+            d.field = DG_FIELD_AXIS_QUADRATIC
+            kq = np.asarray(self.kfield, dtype=np.float64).reshape(9)
+            for i in range(9):
+                d.kq[i] = float(kq[i])
+            d.cq[0], d.cq[1] = (float(v) for v in self.cfield)
         return d
 
 

@@ -191,7 +191,12 @@ __device__ inline void residual_epilogue(const DevTab<T, N> &tb, bool active, in
 // Generic kernel (any affine b): lane (cell, a, b) applies the 1-D line
 // operator along x, y and z to its three lines through (a, b); the
 // contributions meet in LDS.
-template <int P, typename T, bool NB, int RES = 0>
+//
+// FLD: the outer operator of a problem with a coefficient field: K_kk and
+// c are evaluated at the nodes (= quadrature points) of each line instead
+// of taken per cell (the preconditioner's kernels use the cell-centre
+// values).
+template <int P, typename T, bool NB, int RES = 0, bool FLD = false>
 __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restrict__ u, T *__restrict__ v,
                                                          const T *__restrict__ r = nullptr,
                                                          T *__restrict__ rh = nullptr) {
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
   // indices clamped to the cell itself, so that no load waits for another)
   double kd = 0.0, km = 0.0, kp = 0.0;
   const bool coef_lane = active && ln < 3;
-  if (coef_lane) {
+  if (coef_lane && !FLD) {
     const int k = ln;
     const int ik = k == 0 ? ijk[0] : (k == 1 ? ijk[1] : ijk[2]);
     const int nk = k == 0 ? nn[0] : (k == 1 ? nn[1] : nn[2]);
@@ -234,7 +239,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
     km = g.K[3 * (size_t)(ik > 0 ? c - sk : c) + k];
     kp = g.K[3 * (size_t)(ik < nk - 1 ? c + sk : c) + k];
   }
-  const T cre = (active && g.has_c) ? (T)g.c[c] : T(0);
+  const T cre = (active && g.has_c && !FLD) ? (T)g.c[c] : T(0);
   const T stan = tb.w[a] * tb.w[b];
 
   T tr[2][4] = {{T(0), T(0), T(0), T(0)}, {T(0), T(0), T(0), T(0)}};
@@ -246,12 +251,21 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
   for (int j = 0; j < St::NVEC; ++j) reinterpret_cast<VT *>(us)[j * kApplyThreads + tid] = pre[j];
   if (coef_lane) {
     // compile-time axis in each branch: the per-axis mesh data stay scalar
-    if (ln == 0)
-      fcs[cl][0] = axis_coef_from<T>(g, 0, ijk, kd, km, kp);
-    else if (ln == 1)
-      fcs[cl][1] = axis_coef_from<T>(g, 1, ijk, kd, km, kp);
-    else
-      fcs[cl][2] = axis_coef_from<T>(g, 2, ijk, kd, km, kp);
+    if constexpr (FLD) {
+      if (ln == 0)
+        fcs[cl][0] = axis_coef_field<T>(g, 0, ijk);
+      else if (ln == 1)
+        fcs[cl][1] = axis_coef_field<T>(g, 1, ijk);
+      else
+        fcs[cl][2] = axis_coef_field<T>(g, 2, ijk);
+    } else {
+      if (ln == 0)
+        fcs[cl][0] = axis_coef_from<T>(g, 0, ijk, kd, km, kp);
+      else if (ln == 1)
+        fcs[cl][1] = axis_coef_from<T>(g, 1, ijk, kd, km, kp);
+      else
+        fcs[cl][2] = axis_coef_from<T>(g, 2, ijk, kd, km, kp);
+    }
   }
   __syncthreads();
 
@@ -285,6 +299,19 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
       LineConv<T> lc = {T(0), T(0), T(0), T(0)};
       if (hasb) lc = make_line_conv<T, N>(g, tb, k, ijk, a, b);
       line_apply<T, N>(tb, fcs[cl][k], stan, vol, k == 0 ? cre : T(0), hasb, lc, ul, t[0], t[1], t[2], t[3], out);
+      if constexpr (FLD) {
+        // K_kk at the line's nodes; c at the nodes of the x-line
+        T pk[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) pk[q] = (T)field_K(g, k, (ijk[k] + (double)tb.xi[q]) * g.h[k]);
+        line_volume_field<T, N>(tb, stan, vol, (T)g.ih[k], pk, ul, out);
+        if (k == 0 && g.has_c) {
+          const double y = (ijk[1] + (double)tb.xi[a]) * g.h[1], z = (ijk[2] + (double)tb.xi[b]) * g.h[2];
+#pragma unroll
+          for (int i = 0; i < N; ++i)
+            out[i] += (T)field_c(g, (ijk[0] + (double)tb.xi[i]) * g.h[0], y, z) * vol * stan * tb.w[i] * ul[i];
+        }
+      }
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         if (k == 0) qx[i] = out[i];
@@ -376,7 +403,7 @@ __global__ __launch_bounds__(256) void k_rhs(Geo g, const double *__restrict__ f
           val -= WF * bv * ev;
         } else {
           const double nu = side ? 1.0 : -1.0;
-          const double d = g.K[3 * c + k];
+          const double d = g.field ? field_K(g, k, (ijk[k] + side) * g.h[k]) : g.K[3 * c + k];
           const double gam = g.sigma * d / g.h[k];
           double bnu = 0.0;
           if (g.has_b) {
@@ -401,7 +428,10 @@ template <int P, typename T>
 static int launch_apply_t(const dg_problem *pr, const void *u, void *v, hipStream_t s, bool nb) {
   constexpr int N = P + 1;
   const int G = (int)((pr->ncell + ApplyShape<N>::CPB - 1) / ApplyShape<N>::CPB);
-  if (nb)
+  if (nb && pr->geo.field)
+    hipLaunchKernelGGL((k_apply<P, T, true, 0, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u,
+                       (T *)v, (const T *)nullptr, (T *)nullptr);
+  else if (nb)
     hipLaunchKernelGGL((k_apply<P, T, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u, (T *)v,
                        (const T *)nullptr, (T *)nullptr);
   else

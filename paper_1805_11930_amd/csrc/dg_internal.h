@@ -92,7 +92,21 @@ struct Geo {
   int has_c;
   const double *K;  // device [ncell][3]
   const double *c;  // device [ncell] (valid when has_c)
+  // coefficient field of the outer operator (DG_FIELD_AXIS_QUADRATIC):
+  // K_kk(x) = kq[k] + kq[3+k] x_k + kq[6+k] x_k^2, c(x) = cq[0] + cq[1] |x|^2;
+  // K and c above then hold the values at the cell centres
+  int field;
+  double kq[9];
+  double cq[2];
 };
+
+// P_k(s) of the axis-quadratic coefficient field
+__host__ __device__ inline double field_K(const Geo &g, int k, double s) {
+  return g.kq[k] + s * (g.kq[3 + k] + s * g.kq[6 + k]);
+}
+__host__ __device__ inline double field_c(const Geo &g, double x, double y, double z) {
+  return g.cq[0] + g.cq[1] * (x * x + y * y + z * z);
+}
 
 // One level of a coarse hierarchy on a structured grid of vx * vy * vz
 // unknowns: P0 (one unknown per cell, 7-point stencil, piecewise-constant

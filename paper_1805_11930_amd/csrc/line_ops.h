@@ -50,32 +50,34 @@ struct LineConv {
   T beta, Bkk, xk0, hk;
 };
 
-// Face coefficients from K_kk of the cell (d) and of its neighbours below
-// and above along k (dm, dp; not read where there is no neighbour).
+// Face coefficients along axis k from delta = K_kk on both sides of the
+// lower face (own side dLo, neighbour dLn) and of the upper face (dRo,
+// dRn); the neighbour values are not read where there is no neighbour.
+// d is the cell's K_kk for the volume term.
 template <typename T>
-__host__ __device__ inline AxisCoef<T> axis_coef_from(const Geo &g, int k, const int (&ijk)[3], double d, double dm,
-                                                      double dp) {
+__host__ __device__ inline AxisCoef<T> axis_coef_faces(const Geo &g, int k, const int (&ijk)[3], double d,
+                                                       double dLo, double dLn, double dRo, double dRn) {
   AxisCoef<T> f;
   const int nn[3] = {g.nx, g.ny, g.nz};
   const double ih = g.ih[k];
   double kL = 0.0, gL = 0.0, kR = 0.0, gR = 0.0;
   int fl = 0;
   if (ijk[k] > 0) {
-    kL = d * dm / (d + dm);
+    kL = dLo * dLn / (dLo + dLn);
     gL = 2.0 * g.sigma * kL * ih;
     fl |= 1 | 4;
   } else if (g.bc[2 * k] == FACE_DIRICHLET) {
-    kL = d;
-    gL = g.sigma * d * ih;
+    kL = dLo;
+    gL = g.sigma * dLo * ih;
     fl |= 1;
   }
   if (ijk[k] < nn[k] - 1) {
-    kR = d * dp / (d + dp);
+    kR = dRo * dRn / (dRo + dRn);
     gR = 2.0 * g.sigma * kR * ih;
     fl |= 2 | 8;
   } else if (g.bc[2 * k + 1] == FACE_DIRICHLET) {
-    kR = d;
-    gR = g.sigma * d * ih;
+    kR = dRo;
+    gR = g.sigma * dRo * ih;
     fl |= 2;
   }
   f.d = (T)d;
@@ -86,6 +88,50 @@ __host__ __device__ inline AxisCoef<T> axis_coef_from(const Geo &g, int k, const
   f.ih = (T)ih;
   f.fl = fl;
   return f;
+}
+
+// Face coefficients from K_kk of the cell (d) and of its neighbours below
+// and above along k (dm, dp; not read where there is no neighbour).
+template <typename T>
+__host__ __device__ inline AxisCoef<T> axis_coef_from(const Geo &g, int k, const int (&ijk)[3], double d, double dm,
+                                                      double dp) {
+  return axis_coef_faces<T>(g, k, ijk, d, d, dm, d, dp);
+}
+
+// Face coefficients of the coefficient field along axis k: K_kk = P_k(x_k)
+// is constant on a face normal to e_k and the same from both sides; the
+// volume part (d = 0 here) is added by line_volume_field.
+template <typename T>
+__host__ __device__ inline AxisCoef<T> axis_coef_field(const Geo &g, int k, const int (&ijk)[3]) {
+  const double pl = field_K(g, k, ijk[k] * g.h[k]);
+  const double pr = field_K(g, k, (ijk[k] + 1) * g.h[k]);
+  return axis_coef_faces<T>(g, k, ijk, 0.0, pl, pl, pr, pr);
+}
+
+// Volume diffusion along one line with K_kk varying along it (sum
+// factorisation in three steps: derivative at the quadrature points,
+// scaling by w_q K_kk(x_q), transposed derivative):
+//   v_i += stan vol / h^2 sum_q D[q][i] w_q pk[q] sum_l D[q][l] u_l,
+// pk[q] = K_kk at the q-th node of the line.
+template <typename T, int N>
+__host__ __device__ inline void line_volume_field(const DevTab<T, N> &tb, T stan, T vol, T ih, const T (&pk)[N],
+                                                  const T (&u)[N], T (&v)[N]) {
+  T gq[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    T acc = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) acc += tb.Dt[l][q] * u[l];
+    gq[q] = acc * tb.w[q] * pk[q];
+  }
+  const T alpha = stan * vol * ih * ih;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int q = 0; q < N; ++q) acc += tb.Dt[i][q] * gq[q];
+    v[i] += alpha * acc;
+  }
 }
 
 template <typename T>

@@ -363,24 +363,71 @@ int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
     set_error("penalty_factor must be finite");
     return DG_EINVAL;
   }
-  std::vector<double> K(3 * ncell), cc(ncell, 0.0);
-  for (int64_t i = 0; i < 3 * ncell; ++i) {
-    const double v = d->K ? d->K[i] : d->K_scalar;
-    if (!(v > 0) || !std::isfinite(v)) {
-      set_error("K must be finite and > 0");
-      return DG_EINVAL;
-    }
-    K[i] = v;
+  if (d->field != DG_FIELD_NONE && d->field != DG_FIELD_AXIS_QUADRATIC) {
+    set_error("field must be DG_FIELD_NONE or DG_FIELD_AXIS_QUADRATIC");
+    return DG_EINVAL;
   }
-  bool has_c = false;
-  for (int64_t i = 0; i < ncell; ++i) {
-    const double v = d->c ? d->c[i] : d->c_scalar;
-    if (!(v >= 0) || !std::isfinite(v)) {
-      set_error("c must be finite and >= 0");
+  const double len[3] = {d->lx, d->ly, d->lz};
+  const int cnt[3] = {d->nx, d->ny, d->nz};
+  if (d->field == DG_FIELD_AXIS_QUADRATIC) {
+    for (int i = 0; i < 9; ++i)
+      if (!std::isfinite(d->kq[i])) {
+        set_error("field coefficients kq must be finite");
+        return DG_EINVAL;
+      }
+    for (int k = 0; k < 3; ++k) {
+      // minimum of P_k on [0, L_k]: at an end or at the vertex
+      const double a0 = d->kq[k], a1 = d->kq[3 + k], a2 = d->kq[6 + k];
+      auto P = [&](double t) { return a0 + t * (a1 + t * a2); };
+      double mn = std::min(P(0.0), P(len[k]));
+      if (a2 != 0.0) {
+        const double t = -a1 / (2.0 * a2);
+        if (t > 0.0 && t < len[k]) mn = std::min(mn, P(t));
+      }
+      if (!(mn > 0.0)) {
+        set_error("field: P_k must be > 0 on [0, L_k]");
+        return DG_EINVAL;
+      }
+    }
+    const double r2 = len[0] * len[0] + len[1] * len[1] + len[2] * len[2];
+    if (!std::isfinite(d->cq[0]) || !std::isfinite(d->cq[1]) || !(d->cq[0] >= 0.0) ||
+        !(d->cq[0] + d->cq[1] * r2 >= 0.0)) {
+      set_error("field: c(x) = cq[0] + cq[1] |x|^2 must be finite and >= 0 on the box");
       return DG_EINVAL;
     }
-    cc[i] = v;
-    has_c = has_c || v != 0.0;
+  }
+  std::vector<double> K(3 * ncell), cc(ncell, 0.0);
+  bool has_c = false;
+  if (d->field == DG_FIELD_AXIS_QUADRATIC) {
+    // cell-centre values for the preconditioner
+    for (int64_t c = 0; c < ncell; ++c) {
+      const int64_t ijk[3] = {c % d->nx, (c / d->nx) % d->ny, c / ((int64_t)d->nx * d->ny)};
+      double xc[3];
+      for (int k = 0; k < 3; ++k) {
+        xc[k] = (ijk[k] + 0.5) * (len[k] / cnt[k]);
+        K[3 * c + k] = d->kq[k] + xc[k] * (d->kq[3 + k] + xc[k] * d->kq[6 + k]);
+      }
+      cc[c] = d->cq[0] + d->cq[1] * (xc[0] * xc[0] + xc[1] * xc[1] + xc[2] * xc[2]);
+    }
+    has_c = d->cq[0] != 0.0 || d->cq[1] != 0.0;
+  } else {
+    for (int64_t i = 0; i < 3 * ncell; ++i) {
+      const double v = d->K ? d->K[i] : d->K_scalar;
+      if (!(v > 0) || !std::isfinite(v)) {
+        set_error("K must be finite and > 0");
+        return DG_EINVAL;
+      }
+      K[i] = v;
+    }
+    for (int64_t i = 0; i < ncell; ++i) {
+      const double v = d->c ? d->c[i] : d->c_scalar;
+      if (!(v >= 0) || !std::isfinite(v)) {
+        set_error("c must be finite and >= 0");
+        return DG_EINVAL;
+      }
+      cc[i] = v;
+      has_c = has_c || v != 0.0;
+    }
   }
   dg_problem *pr = new dg_problem();
   pr->desc = *d;
@@ -417,6 +464,9 @@ int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
     if (d->B[i] != 0.0) g.has_b = 1;
   }
   g.has_c = has_c ? 1 : 0;
+  g.field = d->field;
+  for (int i = 0; i < 9; ++i) g.kq[i] = d->field ? d->kq[i] : 0.0;
+  for (int i = 0; i < 2; ++i) g.cq[i] = d->field ? d->cq[i] : 0.0;
   int rc = dmalloc(pr, (void **)&pr->dK, 3 * ncell * sizeof(double));
   if (!rc) rc = dmalloc(pr, (void **)&pr->dc, ncell * sizeof(double));
   if (!rc) {

@@ -21,6 +21,9 @@ synthetic stand-in with SPE10's shape and contrast):
   Pe2000  the paper's convection-dominated problem (Sec. 4.3): [0,1]^2 x
       [0,2], b = (1,0,0) or (1, 0.5, 0.3), kappa = max b_i h / 2000,
       u = X(1-X) Y(1-Y) Z(1-Z), homogeneous Dirichlet.
+  Inhom  second diffusion test (Sec. 4.2): [0,1]^2 x [0,2], axis-aligned
+      K(x) = diag(P_1(x), P_2(y), P_3(z)), P_k = p0_k + p2_k s^2,
+      c = 1e-8 |x|^2, Gaussian f, g (Dirichlet) and j (Neumann on x = 1).
   W5  serving mix: N in {8,12,16,24,32} cells per side, p in {2,3,4}, K_T =
       exp(Z_T) I with Z ~ N(0,1), random load vector (seed 5000 + i),
       homogeneous Dirichlet.
@@ -52,6 +55,10 @@ class Workload:
     exact: object = None  # exact solution, when known
     info: dict = field(default_factory=dict)
     coarse: str = "auto"  # coarse space of the V-cycle: "auto" (Q1 if b = 0, else P0), "q1" or "p0"
+    # axis-quadratic coefficient field: kfield = (q0, q1, q2) (3 each),
+    # K_kk(x) = q0_k + q1_k x_k + q2_k x_k^2; cfield = (c0, c2), c = c0 + c2 |x|^2
+    kfield: tuple | None = None
+    cfield: tuple = (0.0, 0.0)
 
     @property
     def ncell(self) -> int:
@@ -169,6 +176,34 @@ def pe2000(b=(1.0, 0.0, 0.0), p=3, cells=None) -> Workload:
     name = "convection-pe2000-b%s-%dx%dx%d-p%d" % ("x" if b[1] == 0 and b[2] == 0 else "xyz", *cells, p)
     return Workload(name, tuple(cells), lengths, p, ("D",) * 6, None, kappa, b0=tuple(b), f=f, exact=u,
                     info={"kappa": kappa, "peclet": 2000.0})
+
+
+def field_functions(kfield, cfield=(0.0, 0.0)):
+    """Callables K(x) -> (npts, 3) diagonal and c(x) -> (npts,) of an
+    axis-quadratic coefficient field."""
+    q0, q1, q2 = (np.asarray(v, dtype=np.float64) for v in kfield)
+    c0, c2 = (float(v) for v in cfield)
+    return (lambda x: q0 + q1 * x + q2 * x ** 2), (lambda x: c0 + c2 * np.sum(x ** 2, axis=1))
+
+
+def gaussian(x0, s: float = 0.1):
+    x0 = np.asarray(x0, dtype=np.float64)
+    return lambda x: np.exp(-np.sum((x - x0) ** 2, axis=1) / (2.0 * s * s))
+
+
+def inhomogeneous(p=4, cells=None, kfield=((1.0, 0.5, 2.0), (0.0, 0.0, 0.0), (3.0, 1.0, 0.5))) -> Workload:
+    """Second diffusion test of Sec. 4.2: -div(K(x) grad u) + c(x) u = f on
+    [0,1] x [0,1] x [0,2] with K(x) = sum_k P_k(x_k) n_k n_k^T, n_k = e_k,
+    P_k(s) = p0_k + p2_k s^2 (the paper leaves p0, p2 open; here
+    p0 = (1, 0.5, 2), p2 = (3, 1, 0.5)), c(x) = 1e-8 |x|^2; Neumann on the
+    face x = 1 with j a Gaussian at (1, 0.5, 0.5), Dirichlet elsewhere with
+    g a Gaussian at (0, 0.5, 0.5), f a Gaussian at (0.75, 0.5, 0.3), all of
+    width 0.1.  Default grid: the paper's isotropic grid for degree p."""
+    if cells is None:
+        cells = {1: (128, 128, 256), 2: (56, 56, 112), 3: (32, 32, 64), 4: (20, 20, 40)}[p]
+    return Workload("inhomogeneous-%dx%dx%d-p%d" % (*cells, p), tuple(cells), (1.0, 1.0, 2.0), p,
+                    ("D", "N", "D", "D", "D", "D"), None, 1.0, f=gaussian((0.75, 0.5, 0.3)),
+                    g=gaussian((0.0, 0.5, 0.5)), j=gaussian((1.0, 0.5, 0.5)), kfield=kfield, cfield=(0.0, 1e-8))
 
 
 def w5_requests(n: int = 256, seed: int = 55):

@@ -8,6 +8,11 @@ from oracle import dg
 
 
 def oracle_problem(w, **kw) -> dg.Problem:
+    if getattr(w, "kfield", None) is not None:
+        from paper_1805_11930_amd import inputs
+
+        Kf, cf = inputs.field_functions(w.kfield, w.cfield)
+        kw = dict(kw, Kfield=Kf, cfield=cf)
     return dg.Problem(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c, b0=w.b0, B=w.B,
                       **kw)
 
@@ -15,7 +20,8 @@ def oracle_problem(w, **kw) -> dg.Problem:
 def spec(w):
     from paper_1805_11930_amd import ProblemSpec
 
-    return ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c, b0=w.b0, B=w.B)
+    return ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c, b0=w.b0, B=w.B,
+                       kfield=getattr(w, "kfield", None), cfield=getattr(w, "cfield", (0.0, 0.0)))
 
 
 def rel(a, b) -> float:
