@@ -162,6 +162,44 @@ def pe2000_leg(p: int = 3) -> dict:
     return out
 
 
+def diffusion_leg(p: int = 3) -> dict:
+    """The two diffusion tests of Sec. 4.2 on the paper's isotropic grid for
+    degree p ([0,1]^2 x [0,2]): Poisson and the inhomogeneous problem with
+    K(x), c(x) at the quadrature points of the outer operator and their
+    cell-centre values in the FP32 / FP64 V-cycle; FCG to 1e-8, inner PCG
+    eps = 1e-2.  Time per unknown, the paper's unit for these tests."""
+    import torch
+
+    from paper_1805_11930_amd import (DG_FP32, DG_FP64, DG_KRYLOV_FCG, DG_PRECOND_MG, Problem, ProblemSpec, inputs,
+                                      solve_opts)
+
+    out = {"krylov": "flexible CG, rtol 1e-8", "preconditioner": "V-cycle, block-Jacobi, inner PCG eps=1e-2, Q1"}
+    for tag, w in (("poisson", inputs.poisson_gauss(p)), ("inhomogeneous", inputs.inhomogeneous(p))):
+        P = Problem(ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c,
+                                b0=w.b0, B=w.B, kfield=w.kfield, cfield=w.cfield))
+        f = P.rhs_from_functions(f=w.f, g=w.g, j=w.j)
+        u = torch.zeros_like(f)
+        v = torch.empty_like(f)
+        t_a = event_time(lambda: P.apply(f, v), 20)
+        row = {"workload": w.name, "ndof": P.ndof, "apply_fp64_gdofs": round(P.ndof / t_a / 1e9, 2)}
+        for name, prec in (("mixed", DG_FP32), ("fp64", DG_FP64)):
+            o = solve_opts(krylov=DG_KRYLOV_FCG, precond=DG_PRECOND_MG, precond_precision=prec, rtol=1e-8,
+                           maxit=500)
+            best = None
+            for _ in range(3):
+                u.zero_()
+                _, r = P.solve(f, u, o)
+                best = r if best is None or r.t_solve < best.t_solve else best
+            row[name] = {"time_to_solve_s": round(best.t_solve, 4), "iterations": best.iters,
+                         "rel_residual": best.rel_residual,
+                         "us_per_dof": round(best.t_solve / P.ndof * 1e6, 5)}
+            log(f"[bench] {tag} p={p} {name}: {best.t_solve * 1e3:.1f} ms, {best.iters} it, "
+                f"rel_res {best.rel_residual:.2e}")
+        out[tag] = row
+        P.close()
+    return out
+
+
 def event_time(fn, reps: int) -> float:
     """Mean seconds per call of fn() on torch's current stream (HIP events)."""
     import torch
@@ -188,6 +226,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256, help="serving leg size (0 = skip)")
     ap.add_argument("--pe2000", type=int, default=1, help="run the Pe=2000 convection leg (0 = skip)")
+    ap.add_argument("--diffusion", type=int, default=1,
+                    help="run the Poisson / inhomogeneous diffusion leg on the paper's p=3 grid (0 = skip)")
     ap.add_argument("--apply-only", type=int, default=0,
                     help="profiling aid: run this many FP64 applies and exit")
     ap.add_argument("--copy-only", type=int, default=0,
@@ -368,6 +408,8 @@ def main() -> int:
         },
         "fdm_smoother": fdm,
     }
+    if args.diffusion:
+        line["diffusion_sec42"] = diffusion_leg()
     if args.pe2000:
         line["convection_pe2000"] = pe2000_leg()
     if args.serve_requests > 0:

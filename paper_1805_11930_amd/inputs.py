@@ -206,6 +206,16 @@ def inhomogeneous(p=4, cells=None, kfield=((1.0, 0.5, 2.0), (0.0, 0.0, 0.0), (3.
                     g=gaussian((0.0, 0.5, 0.5)), j=gaussian((1.0, 0.5, 0.5)), kfield=kfield, cfield=(0.0, 1e-8))
 
 
+def poisson_gauss(p=3, cells=None) -> Workload:
+    """First diffusion test of Sec. 4.2: -lap u = f on [0,1] x [0,1] x [0,2],
+    homogeneous Dirichlet, f a Gaussian of width 0.1 at (0.75, 0.5, 0.3);
+    default grid: the paper's isotropic grid for degree p."""
+    if cells is None:
+        cells = {1: (128, 128, 256), 2: (56, 56, 112), 3: (32, 32, 64), 4: (20, 20, 40)}[p]
+    return Workload("poisson-gauss-%dx%dx%d-p%d" % (*cells, p), tuple(cells), (1.0, 1.0, 2.0), p, ("D",) * 6, None,
+                    1.0, f=gaussian((0.75, 0.5, 0.3)))
+
+
 def w5_requests(n: int = 256, seed: int = 55):
     """The serving mix: list of (N, p, seed_i)."""
     rng = np.random.default_rng(seed)
