@@ -133,7 +133,8 @@ def pe2000_leg(p: int = 3) -> dict:
     from paper_1805_11930_amd import (DG_FP32, DG_FP64, DG_INNER_GMRES, DG_IPREC_TRIDIAG, DG_KRYLOV_FGMRES,
                                       DG_PRECOND_BLOCK, DG_SWEEP_SSOR, Problem, ProblemSpec, inputs, solve_opts)
 
-    out = {"preconditioner": "2 x red-black block-SSOR, inner GMRES(12) eps=1e-2 with the Thomas preconditioner",
+    out = {"preconditioner": "2 x block-SSOR in the 12-colour diagonal order, inner GMRES(12) eps=1e-2 with the "
+                             "Thomas preconditioner",
            "krylov": "FGMRES(30), rtol 1e-8"}
     for tag, b in (("b100", (1.0, 0.0, 0.0)), ("b1_05_03", (1.0, 0.5, 0.3))):
         w = inputs.pe2000(b=b, p=p)
@@ -146,7 +147,7 @@ def pe2000_leg(p: int = 3) -> dict:
             o = solve_opts(krylov=DG_KRYLOV_FGMRES, restart=30, precond=DG_PRECOND_BLOCK, precond_precision=prec,
                            rtol=1e-8, maxit=300,
                            smooth=dict(n_sweeps=2, sweep=DG_SWEEP_SSOR, omega=1.0, eps=1e-2, inner=DG_INNER_GMRES,
-                                       restart=12, inner_precond=DG_IPREC_TRIDIAG))
+                                       restart=12, inner_precond=DG_IPREC_TRIDIAG, colours=12))
             best = None
             for _ in range(3):
                 u.zero_()

@@ -64,9 +64,11 @@ enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK = 1, DG_PRECOND_MG = 2 };
 /* Sweep of the block smoother (Sec. 2.2.1): block-Jacobi (alg
  * block_jacobi), forward or backward block-SOR (alg block_SOR) and
  * block-SSOR (a forward then a backward sweep).  The SOR sweeps visit the
- * cells in red-black order (ix + iy + iz even, then odd; backward: odd,
- * then even): cells of one colour share no face, so each colour is swept
- * in parallel, in place. */
+ * cells colour by colour, colour = (ix + iy + iz) mod C (C = 2: red-black;
+ * backward: the colours in reverse): cells of one colour share no face, so
+ * each colour is swept in parallel, in place.  Larger C moves the order
+ * towards the diagonal wavefront order, which is downwind for b with
+ * positive components. */
 enum { DG_SWEEP_JACOBI = 0, DG_SWEEP_SOR = 1, DG_SWEEP_SSOR = 2, DG_SWEEP_SOR_BACKWARD = 3 };
 enum { DG_IPREC_DIAG = 0, DG_IPREC_TRIDIAG = 1 };
 enum { DG_COARSE_P0 = 0, DG_COARSE_Q1 = 1, DG_COARSE_AUTO = 2 };
@@ -134,6 +136,8 @@ typedef struct {
                        part of D_T in the x-fastest DOF order, solved by the
                        Thomas algorithm -- for strongly convective blocks,
                        Sec. 4.3                                              */
+  int colours;      /* SOR sweeps: number C of colours (ix + iy + iz) mod C
+                       of the cell order, 2..64 (<= 0: 2, red-black)        */
 } dg_smooth_opts;
 
 /* Optional smoother statistics (filled after a synchronisation). */
@@ -258,7 +262,7 @@ int dg_block_solve(dg_problem *prob, int precision, const void *d, void *x,
  *   DG_SWEEP_JACOBI (alg block_jacobi):
  *     u^(k) = u^(k-1) + omega D^-1_eps (f - A u^(k-1));  u_in != u_out.
  *   DG_SWEEP_SOR / _SOR_BACKWARD / _SSOR (alg block_SOR): per cell T, in
- *     red-black order, d_T = f_T - sum over the face neighbours S of
+ *     the colour order (opts->colours), d_T = f_T - sum over the face neighbours S of
  *     A_{T,S} u_S (current values), D_T x = d_T solved to eps, then
  *     u_T = (1 - omega) u_T + omega x, in place in u_out (u_in may equal
  *     u_out; otherwise u_in is copied first). */

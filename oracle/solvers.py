@@ -218,14 +218,17 @@ def lexicographic_order(prob: _dg.Problem) -> np.ndarray:
     return np.arange(prob.ncell)
 
 
-def multicolour_order(prob: _dg.Problem) -> np.ndarray:
-    """Red-black ordering of the cells: every cell with ix + iy + iz even
-    (in index order), then every odd one.  Face neighbours differ by one in
-    exactly one index, so no two cells of one colour share a face."""
+def multicolour_order(prob: _dg.Problem, colours: int = 2) -> np.ndarray:
+    """Cells ordered by colour (ix + iy + iz) mod C, C = colours >= 2, each
+    colour in index order; C = 2 is the red-black order.  Face neighbours
+    differ by one in exactly one index, so no two cells of one colour share
+    a face.  When C is at least the number of diagonal planes
+    ix + iy + iz = const, the colour is the plane index and the order is a
+    hyperplane (wavefront) order."""
     ijk = np.array([prob.cell_ijk(c) for c in range(prob.ncell)]).reshape(-1, 3)
-    colour = ijk.sum(axis=1) % 2
+    colour = ijk.sum(axis=1) % colours
     cells = np.arange(prob.ncell)
-    return np.concatenate([cells[colour == 0], cells[colour == 1]])
+    return np.concatenate([cells[colour == q] for q in range(colours)])
 
 
 def block_sor(A, Dblocks, f, u0, order, omega=1.0, nsweeps=1, inner="exact", eps=1e-2,

@@ -62,6 +62,7 @@ class SmoothOpts(ctypes.Structure):
         ("n_sweeps", ctypes.c_int), ("omega", ctypes.c_double), ("eps", ctypes.c_double),
         ("max_inner", ctypes.c_int), ("inner", ctypes.c_int), ("restart", ctypes.c_int),
         ("zero_guess", ctypes.c_int), ("sweep", ctypes.c_int), ("inner_precond", ctypes.c_int),
+        ("colours", ctypes.c_int),
     ]
 
 

@@ -66,10 +66,10 @@ int smooth_args(dg_problem *pr, const dg_smooth_opts *o, SmoothArgs &a) {
       (o->inner != DG_INNER_CG && o->inner != DG_INNER_GMRES && o->inner != DG_INNER_FDM) ||
       o->sweep < DG_SWEEP_JACOBI || o->sweep > DG_SWEEP_SOR_BACKWARD ||
       (o->inner_precond != DG_IPREC_DIAG && o->inner_precond != DG_IPREC_TRIDIAG) ||
-      (o->inner_precond == DG_IPREC_TRIDIAG && o->inner != DG_INNER_GMRES)) {
+      (o->inner_precond == DG_IPREC_TRIDIAG && o->inner != DG_INNER_GMRES) || o->colours > 64) {
     set_error(
         "invalid smoother options (eps >= 0, finite omega, inner CG, GMRES or FDM, sweep DG_SWEEP_*, "
-        "inner_precond DG_IPREC_DIAG, or DG_IPREC_TRIDIAG with inner GMRES)");
+        "inner_precond DG_IPREC_DIAG, or DG_IPREC_TRIDIAG with inner GMRES, colours <= 64)");
     return DG_EINVAL;
   }
   if (o->inner == DG_INNER_FDM) {
@@ -89,6 +89,7 @@ int smooth_args(dg_problem *pr, const dg_smooth_opts *o, SmoothArgs &a) {
   a.defect = 1;
   a.sweep = o->sweep;
   a.tridiag = o->inner_precond == DG_IPREC_TRIDIAG;
+  a.ncol = o->colours >= 2 ? o->colours : 2;
   return DG_OK;
 }
 
@@ -121,14 +122,15 @@ int sweeps(dg_problem *pr, int prec, const void *f, const void *src, void *dst, 
   return DG_OK;
 }
 
-// One block-SOR sweep (alg block_SOR) over the red-black order, in place on
-// u: colour 0 then colour 1 (backward: 1 then 0).  zero: u is taken as 0
-// (the first colour skips the defect and clears the other colour).
+// One block-SOR sweep (alg block_SOR) over the colour order, in place on
+// u: colours 0, 1, ..., C-1 (backward: C-1, ..., 0).  zero: u is taken as
+// 0 (the first colour skips the defect and clears the other colours).
 int sor_pass(dg_problem *pr, int prec, const void *f, void *u, bool backward, bool zero, const SmoothArgs &base,
              int *iters, hipStream_t s) {
-  for (int h = 0; h < 2; ++h) {
+  const int C = base.ncol;
+  for (int h = 0; h < C; ++h) {
     SmoothArgs a = base;
-    a.colour = backward ? 1 - h : h;
+    a.colour = backward ? C - 1 - h : h;
     a.sor = 1;
     a.zh = nullptr;
     a.zero_guess = (zero && h == 0) ? 1 : 0;
@@ -407,6 +409,7 @@ void dg_default_smooth_opts(dg_smooth_opts *o) {
   o->zero_guess = 0;
   o->sweep = DG_SWEEP_JACOBI;
   o->inner_precond = DG_IPREC_DIAG;
+  o->colours = 2;
 }
 
 void dg_default_mg_opts(dg_mg_opts *o) {

@@ -215,7 +215,8 @@ struct SmoothArgs {
   int write_du;     // output is the correction only (block solve)
   int defect;       // compute d = f - A u (otherwise d = f)
   const void *zh = nullptr;  // optional P0 correction: u_in + P zh is smoothed
-  int colour = -1;  // >= 0: one red-black colour, in place (uin == uout)
+  int colour = -1;  // >= 0: one colour (ix + iy + iz) mod ncol, in place (uin == uout)
+  int ncol = 2;     // number of colours of the SOR order
   int sor = 0;      // block-SOR update form (alg block_SOR)
   int sweep = 0;    // DG_SWEEP_* of the options (host-side dispatch)
   int tridiag = 0;  // inner preconditioner: tridiagonal part of D_T (Thomas)

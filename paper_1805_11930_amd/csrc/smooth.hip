@@ -62,10 +62,12 @@ struct SmoothKArgs {
   double omega, eps;
   int max_inner, restart;
   int zero_guess, write_du, defect;
-  // colour >= 0: only the cells with (ix + iy + iz) % 2 == colour, slot j
-  // of the grid -> half-row j / hx (hx = ceil(nx / 2)), cell
-  // ix = 2 (j % hx) + ((iy + iz + colour) & 1); rows = ny * nz.
-  int colour, hx, rows;
+  // colour >= 0: only the cells with (ix + iy + iz) mod ncol == colour;
+  // slot j of the grid -> row j / hx (hx = ceil(nx / ncol)) and block
+  // t = j % hx of ncol consecutive cells of that row, whose cell
+  // ix = ncol t + ((colour - iy - iz) mod ncol) has the colour;
+  // rows = ny * nz.
+  int colour, ncol, hx, rows;
   // block-SOR form (alg block_SOR): the defect leaves out the cell's own
   // block and the new value is (1 - omega) u + omega x
   int sor;
@@ -201,21 +203,25 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   int c = slot;
   bool valid = slot < g.ncell;
   if (sa.colour >= 0) {
+    const int C = sa.ncol;
     const int r = slot / sa.hx;
     const int t = slot - r * sa.hx;
     const int iy = r % g.ny, iz = r / g.ny;
-    const int s0 = (iy + iz + sa.colour) & 1;
-    const int ix = 2 * t + s0;
+    int s0 = (sa.colour - iy - iz) % C;
+    if (s0 < 0) s0 += C;
+    const int ix = C * t + s0;
     valid = r < sa.rows && ix < g.nx;
     c = valid ? ix + g.nx * r : 0;
-    // from a zero guess the slot also clears its x-partner cell
-    // 2t + 1 - s0 of the other colour (the pairs (2t, 2t+1) cover the row),
-    // so that the other colour's sweep starts from zero
-    const int px = 2 * t + 1 - s0;
-    if (sa.zero_guess && r < sa.rows && px < g.nx && lane < S::N2) {
-      T *dst = uout + ((size_t)px + (size_t)g.nx * r) * S::N3;
+    // from a zero guess the slot also clears the other cells of its block
+    // (the blocks cover the row), so that the later colours start from zero
+    if (sa.zero_guess && r < sa.rows && lane < S::N2) {
+      for (int s1 = 0; s1 < C; ++s1) {
+        const int px = C * t + s1;
+        if (s1 == s0 || px >= g.nx) continue;
+        T *dst = uout + ((size_t)px + (size_t)g.nx * r) * S::N3;
 #pragma unroll
-      for (int i = 0; i < N; ++i) dst[lpos<N>(0, i, lane % N, lane / N)] = T(0);
+        for (int i = 0; i < N; ++i) dst[lpos<N>(0, i, lane % N, lane / N)] = T(0);
+      }
     }
   }
   const bool on = (lane < S::N2) && valid;
@@ -692,7 +698,8 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
   using Sh = SmoothShape<N>;
   SmoothKArgs ka;
   ka.colour = a.colour;
-  ka.hx = (pr->geo.nx + 1) / 2;
+  ka.ncol = a.ncol;
+  ka.hx = (pr->geo.nx + a.ncol - 1) / a.ncol;
   ka.rows = pr->geo.ny * pr->geo.nz;
   ka.sor = a.sor;
   const int64_t slots = a.colour >= 0 ? (int64_t)ka.hx * ka.rows : pr->ncell;
@@ -747,7 +754,7 @@ int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin
     return DG_EINVAL;
   }
   if ((a.colour >= 0) != (uin == uout) || (a.colour >= 0 && (a.zh || a.write_du || !a.defect)) ||
-      a.colour > 1) {
+      a.ncol < 2 || a.colour >= a.ncol) {
     set_error("internal: a colour sweep runs in place, without a P0 correction");
     return DG_EINVAL;
   }

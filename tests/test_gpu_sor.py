@@ -1,12 +1,14 @@
 """GPU parity of the red-black block-SOR / block-SSOR smoother (alg
 block_SOR, Sec. 2.2.1) against the oracle, through the C ABI.
 
-  * forward, backward and symmetric sweeps from a given u and from zero,
-    p = 1-4, with and without advection, on grids with odd and even cell
+  * forward, backward and symmetric sweeps from a given u and from zero in
+    the red-black and in 3-, 4- and 5-colour diagonal orders, p = 1-4, with and without advection, on grids with odd and even cell
     counts per axis (the colour slots of a row and its partner cell), inner
     PCG / GMRES at the paper's eps = 1e-2 (the GPU replays the oracle's
     inner steps) and the exact stored-factor solve: FP64 <= 1e-9;
   * in place (u_in == u_out) equals out of place;
+  * with one colour per diagonal plane the order is downwind, and one SOR
+    sweep solves a pure-advection problem (red-black does not);
   * FP32 sweeps <= 1e-3 of the FP64 oracle;
   * the V-cycle with SOR / SSOR smoothing and the exact P0 coarse solve
     matches the oracle's cycle (forward pre-, backward postsmoothing);
@@ -47,8 +49,8 @@ def _setup(p, with_b, cells, seed=0):
     return w, opr, A, Db
 
 
-def _oracle_sweeps(A, Db, opr, f, u0, kind, n, **kw):
-    order = solvers.multicolour_order(opr)
+def _oracle_sweeps(A, Db, opr, f, u0, kind, n, colours=2, **kw):
+    order = solvers.multicolour_order(opr, colours)
     if kind == "ssor":
         return solvers.block_ssor(A, Db, f, u0, order, nsweeps=n, **kw)
     return solvers.block_sor(A, Db, f, u0, order[::-1] if kind == "back" else order, nsweeps=n, **kw)
@@ -57,26 +59,29 @@ def _oracle_sweeps(A, Db, opr, f, u0, kind, n, **kw):
 KINDS = {"sor": 1, "ssor": 2, "back": 3}
 
 
-@pytest.mark.parametrize("p,with_b,cells,kind", [
-    (1, False, (5, 4, 3), "sor"),
-    (2, False, (6, 3, 4), "ssor"),
-    (2, True, (5, 4, 3), "back"),
-    (3, True, (4, 5, 3), "ssor"),
-    (4, False, (3, 3, 5), "sor"),
-    (3, False, (1, 3, 4), "ssor"),
+@pytest.mark.parametrize("p,with_b,cells,kind,C", [
+    (1, False, (5, 4, 3), "sor", 2),
+    (2, False, (6, 3, 4), "ssor", 2),
+    (2, True, (5, 4, 3), "back", 2),
+    (3, True, (4, 5, 3), "ssor", 2),
+    (4, False, (3, 3, 5), "sor", 2),
+    (3, False, (1, 3, 4), "ssor", 2),
+    (2, True, (7, 4, 3), "ssor", 3),
+    (1, False, (5, 6, 2), "sor", 5),
+    (3, True, (9, 2, 3), "back", 4),
 ])
-def test_sor_sweeps_vs_oracle(p, with_b, cells, kind):
+def test_sor_sweeps_vs_oracle(p, with_b, cells, kind, C):
     from paper_1805_11930_amd import DG_INNER_CG, DG_INNER_GMRES, smooth_opts
 
-    print(f"block-SOR {kind} p={p} b={with_b} cells={cells}", flush=True)
+    print(f"block-SOR {kind} p={p} b={with_b} cells={cells} colours={C}", flush=True)
     w, opr, A, Db = _setup(p, with_b, cells, seed=21)
     f = inputs.random_vector(opr.ndof, 41)
     u0 = inputs.random_vector(opr.ndof, 42)
     inner = "gmres" if with_b else "cg"
-    kw = dict(omega=1.1, inner=inner, eps=1e-2, restart=12)
+    kw = dict(omega=1.1, inner=inner, eps=1e-2, restart=12, colours=C)
     P = _lib(w)
     o = smooth_opts(n_sweeps=2, omega=1.1, eps=1e-2, inner=DG_INNER_GMRES if with_b else DG_INNER_CG, restart=12,
-                    sweep=KINDS[kind])
+                    sweep=KINDS[kind], colours=C)
     ref = _oracle_sweeps(A, Db, opr, f, u0, kind, 2, **kw)
     got, st = P.block_smooth(torch.from_numpy(f).cuda(), torch.from_numpy(u0).cuda(), o, stats=True)
     assert rel(got.cpu().numpy(), ref) <= 1e-9
@@ -171,4 +176,30 @@ def test_sor_options_rejected():
         P.block_smooth(f, f, smooth_opts(sweep=7))
     with pytest.raises(DgError):
         P.block_smooth(f, None, smooth_opts(sweep=1), out=f)  # u_out == f
+    with pytest.raises(DgError):
+        P.block_smooth(f, None, smooth_opts(sweep=1, colours=65))
+    P.close()
+
+
+def test_wavefront_colours_solve_pure_advection_in_one_sweep():
+    # as many colours as diagonal planes (3 + 3 + 2 - 2 = 6): the colour
+    # order is the downwind wavefront order for b > 0, and one SOR sweep
+    # with (nearly) exact block solves solves the upwind system (Sec. 4.3)
+    from paper_1805_11930_amd import DG_INNER_GMRES, DG_SWEEP_SOR, smooth_opts
+
+    w = inputs.pe2000(b=(1.0, 0.5, 0.3), p=2, cells=(3, 3, 2))
+    w.K = 1e-13
+    opr = oracle_problem(w)
+    A = dg.assemble(opr)
+    f = inputs.random_vector(opr.ndof, 47)
+    u0 = inputs.random_vector(opr.ndof, 48)
+    ue = spla.spsolve(A.tocsc(), f)
+    P = _lib(w)
+    o = smooth_opts(n_sweeps=1, omega=1.0, eps=1e-14, inner=DG_INNER_GMRES, restart=16, max_inner=400,
+                    sweep=DG_SWEEP_SOR, colours=6)
+    got = P.block_smooth(torch.from_numpy(f).cuda(), torch.from_numpy(u0).cuda(), o).cpu().numpy()
+    assert rel(got, ue) <= 1e-9
+    o.colours = 2
+    rb = P.block_smooth(torch.from_numpy(f).cuda(), torch.from_numpy(u0).cuda(), o).cpu().numpy()
+    assert rel(rb, ue) > 1e-3
     P.close()

@@ -332,22 +332,24 @@ def test_block_ssor_is_the_splitting_iteration(with_b):
     np.testing.assert_allclose(got, expect, rtol=0, atol=1e-11 * np.abs(expect).max())
 
 
-def test_multicolour_order_is_independent_within_a_colour():
+@pytest.mark.parametrize("C", [2, 3, 5])
+def test_multicolour_order_is_independent_within_a_colour(C):
     pr = small(2, with_b=True, cells=(4, 3, 3))
     A = dg.assemble(pr)
     Db = dg.block_diagonal(A, pr.ncell)
-    order = solvers.multicolour_order(pr)
+    order = solvers.multicolour_order(pr, C)
     ijk = np.array([pr.cell_ijk(c) for c in order])
-    colour = ijk.sum(axis=1) % 2
+    colour = ijk.sum(axis=1) % C
     assert np.all(colour[:-1] <= colour[1:])  # one colour after the other
+    assert sorted(order) == list(range(pr.ncell))
     # no two cells of one colour share a face
     for c in range(pr.ncell):
         for d in range(pr.ncell):
             if np.abs(np.subtract(pr.cell_ijk(c), pr.cell_ijk(d))).sum() == 1:
-                assert sum(pr.cell_ijk(c)) % 2 != sum(pr.cell_ijk(d)) % 2
+                assert sum(pr.cell_ijk(c)) % C != sum(pr.cell_ijk(d)) % C
     rng = np.random.default_rng(13)
     f, u0 = rng.normal(size=(2, pr.ndof))
-    shuffled = np.concatenate([rng.permutation(order[colour == 0]), rng.permutation(order[colour == 1])])
+    shuffled = np.concatenate([rng.permutation(order[colour == q]) for q in range(C)])
     a = solvers.block_ssor(A, Db, f, u0, order, omega=1.1)
     b = solvers.block_ssor(A, Db, f, u0, shuffled, omega=1.1)
     np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * np.abs(a).max())
@@ -368,6 +370,11 @@ def test_block_sor_pure_advection_downwind_one_sweep_is_exact():
     # red-black is not a downwind order: one sweep is not exact
     u_rb = solvers.block_sor(A, Db, f, u0, solvers.multicolour_order(pr), omega=1.0)
     assert np.abs(u_rb - ue).max() > 1e-3 * np.abs(ue).max()
+    # as many colours as diagonal planes (3 + 3 + 2 - 2 = 6): the colour
+    # order is the wavefront order, downwind for b > 0, and one sweep is
+    # exact again
+    u_hp = solvers.block_sor(A, Db, f, u0, solvers.multicolour_order(pr, 6), omega=1.0)
+    np.testing.assert_allclose(u_hp, ue, rtol=0, atol=1e-9 * np.abs(ue).max())
 
 
 def test_block_ssor_from_zero_is_symmetric_positive_definite():
