@@ -124,8 +124,9 @@ def serving_leg(n_requests: int) -> dict:
 
 def pe2000_leg(p: int = 3) -> dict:
     """Convection-dominated problem of Sec. 4.3 on the paper's isotropic grid
-    for degree p: FGMRES(30) to 1e-8 preconditioned by two red-black
-    block-SSOR steps whose block solves are GMRES to eps = 1e-2 with the
+    for degree p: FGMRES(30) to 1e-8 preconditioned by two block-SSOR
+    steps in the 12-colour diagonal cell order (ix + iy + iz mod 12), whose
+    block solves are GMRES to eps = 1e-2 with the
     tridiagonal (Thomas) preconditioner, FP32 and FP64 preconditioner.
     Reported as time per unknown, the paper's unit for this test."""
     import torch
