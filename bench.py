@@ -232,6 +232,8 @@ def main() -> int:
                     help="run the Poisson / inhomogeneous diffusion leg on the paper's p=3 grid (0 = skip)")
     ap.add_argument("--apply-only", type=int, default=0,
                     help="profiling aid: run this many FP64 applies and exit")
+    ap.add_argument("--smooth-only", type=int, default=0,
+                    help="profiling aid: run this many FP32 block-Jacobi sweeps (inner PCG) and exit")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="counter calibration: run this many 256 MiB device-to-device copies and exit")
     args = ap.parse_args()
@@ -266,6 +268,16 @@ def main() -> int:
             P.apply(u_rand, v)
         torch.cuda.synchronize()
         log(f"[bench] ran {args.apply_only} FP64 applies")
+        return 0
+    if args.smooth_only:
+        f32 = (u_rand / u_rand.norm()).float()
+        u32 = torch.zeros_like(f32)
+        o32 = torch.empty_like(f32)
+        sm = smooth_opts(eps=1e-2, inner=DG_INNER_CG)
+        for _ in range(args.smooth_only):
+            P.block_smooth(f32, u32, sm, out=o32)
+        torch.cuda.synchronize()
+        log(f"[bench] ran {args.smooth_only} FP32 smoother sweeps")
         return 0
     f = P.rhs_from_functions(f=w.f, g=w.g, j=w.j)
     conv = bool(w.b0 != (0.0, 0.0, 0.0) or np.any(np.asarray(w.B) != 0))
