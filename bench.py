@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DG apply GDOF/s + time-to-solve @1e-8 rel residual, FP64 vs mixed; p99 latency"
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # published MI355X FP32 vector peak (packed FMA)
 APPLY_SOURCES = ["paper_1805_11930_amd/csrc/apply.hip", "paper_1805_11930_amd/csrc/line_ops.h"]
 COUNTERS = os.path.join(ROOT, "profiles", "apply_fp64_poisson32_p4_counters.md")
 
@@ -338,6 +339,13 @@ def main() -> int:
     out32 = torch.empty_like(f32)
     t_sm = event_time(lambda: P.block_smooth(f32, u32, sm, out=out32), 5)
     _, st = P.block_smooth(f32, u32, sm, out=out32, stats=True)
+    # algorithmic flops of the sweep: per cell the defect (three line
+    # operators of N^2 lines with N x N contractions and the face terms:
+    # 6 N^4 + 20 N^3) and per inner PCG iteration one D_T product (6 N^4)
+    # plus the dot products and updates (13 N^3)
+    nn = w.p + 1
+    sm_flops = P.ncell * (6 * nn**4 + 20 * nn**3) + st.inner_total * (6 * nn**4 + 13 * nn**3)
+    sm_tflops = sm_flops / t_sm / 1e12
     mo = mg_opts(smooth=dict(eps=1e-2, inner=inner, restart=12), coarse_space=coarse)
     t_vc = event_time(lambda: P.mg_vcycle(f32, mo, out=out32), 5)
     # stored-factor exact block solve (b = 0 only): same V-cycle and solves
@@ -414,6 +422,10 @@ def main() -> int:
             "apply_fp64_gdofs": round(P.ndof / t_a64 / 1e9, 2),
             "apply_fp32_gdofs": round(P.ndof / t_a32 / 1e9, 2),
             "smoother_sweep_fp32_ms": round(t_sm * 1e3, 3),
+            "smoother_roofline": {"bound": "alu", "kernel": f"k_smooth<P={w.p},PCG,float>",
+                                  "achieved": round(sm_tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": round(sm_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                                  "flops_per_launch": int(sm_flops)},
             "smoother_inner_avg": round(st.inner_avg, 3),
             "smoother_inner_max": st.inner_max,
             "vcycle_fp32_ms": round(t_vc * 1e3, 3),
