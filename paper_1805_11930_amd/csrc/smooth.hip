@@ -49,14 +49,44 @@ __device__ inline int lpos(int k, int i, int a, int b) {
   return k == 0 ? i + N * a + N * N * b : (k == 1 ? a + N * i + N * N * b : a + N * b + N * N * i);
 }
 
-// Sum over the L lanes of a cell; every lane of the cell receives the same
-// bits (pairwise commutative butterfly).
+// Lane permutation of a 32-bit register within rows of 16 lanes (DPP).
+template <int CTRL>
+__device__ inline float dpp_perm(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_perm(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the L lanes (L = 4, 16 or 32, aligned) of a cell; every lane of
+// the cell receives the same bits.  Each step adds the value of a partner
+// lane whose group is disjoint and of equal size: within quads (partner
+// lane xor 1, then xor 2), then the mirrored half-row (lane 7 - i of each
+// 8) and row (lane 15 - i of each 16) by DPP, then lane xor 16.  Both
+// partners of a step add the same two numbers, and addition commutes, so
+// the bits agree across the cell.
 template <int L, typename T>
 __device__ inline T cell_sum(T v) {
-#pragma unroll
-  for (int m = 1; m < L; m <<= 1) v += __shfl_xor(v, m, L);
+  static_assert(L == 4 || L == 16 || L == 32, "cell lane groups are 4, 16 or 32 lanes");
+  v += dpp_perm<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+  v += dpp_perm<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+  if constexpr (L >= 16) {
+    v += dpp_perm<0x141>(v);  // row_half_mirror
+    v += dpp_perm<0x140>(v);  // row_mirror
+  }
+  if constexpr (L == 32) v += __shfl_xor(v, 16, 32);
   return v;
 }
+
+// a / b for the scalars of the inner iteration: FP32 by the hardware
+// reciprocal (about 1 ulp; the FP32 inner solve stops at eps >= 1e-7),
+// FP64 correctly rounded
+__device__ inline float inner_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ inline double inner_div(double a, double b) { return a / b; }
 
 struct SmoothKArgs {
   double omega, eps;
@@ -474,7 +504,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
         act2 = false;
       }
       if (act2) {
-        const T alpha = rho / pq;
+        const T alpha = inner_div(rho, pq);
 #pragma unroll
         for (int i = 0; i < N; ++i) {
           x[i] += alpha * p[i];
@@ -495,7 +525,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
       }
       rz = cell_sum<L>(rz);
       if (act2 && !conv) {
-        const T beta = rz / rho;
+        const T beta = inner_div(rz, rho);
 #pragma unroll
         for (int i = 0; i < N; ++i) p[i] = z[i] + beta * p[i];
         rho = rz;
