@@ -62,6 +62,18 @@ __device__ inline double dpp_perm(double v) {
   return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// Value of lane i xor 16 within each group of 32 lanes (ds_swizzle in
+// bit mode: and-mask 0x1f, or-mask 0, xor-mask 0x10; no LDS memory access).
+__device__ inline float swz_xor16(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
+}
+__device__ inline double swz_xor16(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffff), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Sum over the L lanes (L = 4, 16 or 32, aligned) of a cell; every lane of
 // the cell receives the same bits.  Each step adds the value of a partner
 // lane whose group is disjoint and of equal size: within quads (partner
@@ -78,7 +90,7 @@ __device__ inline T cell_sum(T v) {
     v += dpp_perm<0x141>(v);  // row_half_mirror
     v += dpp_perm<0x140>(v);  // row_mirror
   }
-  if constexpr (L == 32) v += __shfl_xor(v, 16, 32);
+  if constexpr (L == 32) v += swz_xor16(v);
   return v;
 }
 
@@ -554,7 +566,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
         gv[j + 1] = T(0);
       }
       gv[0] = beta;
-      const T ib = done ? T(0) : T(1) / beta;
+      const T ib = done ? T(0) : inner_div(T(1), beta);
       if (on) {
 #pragma unroll
         for (int i = 0; i < N; ++i) Vs[my + i] = r[i] * ib;
@@ -617,7 +629,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
             gj = gv[i];
           }
         const T rr = sqrt(hj * hj + hn * hn);
-        const T cj = hj / rr, sj = hn / rr;
+        const T cj = inner_div(hj, rr), sj = inner_div(hn, rr);
         const T gnext = -sj * gj;
 #pragma unroll
         for (int i = 0; i < kGmresMax; ++i)
@@ -639,7 +651,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
             conv = fabs(gnext) <= target || !(rr > T(0));
             cyc = false;
           } else if (on) {
-            const T ih = T(1) / hn;
+            const T ih = inner_div(T(1), hn);
 #pragma unroll
             for (int l = 0; l < N; ++l) Vs[(j + 1) * S::N3 + my + l] = w[l] * ih;
           }
