@@ -26,13 +26,16 @@ documented separately):
     jx + n*(jy + n*jz), n = p + 1;
   * box faces are numbered 0..5 = -x, +x, -y, +y, -z, +z; each has a
     boundary type 'D' (Dirichlet) or 'N' (Neumann);
-  * K is diagonal, either constant per cell or a field K(x) given as a
-    callable and evaluated at the quadrature points; c likewise; the
-    advection field is affine, b(x) = b0 + B x.  With a K field the face
-    quantities delta = nu^T K nu, the weights omega and the penalty gamma_F
-    are taken pointwise at each face quadrature point, each side's delta
-    from its own evaluation of the field (the same value for a continuous
-    field, so omega = 1/2 there).
+  * K is diagonal and constant per cell, or a field K(x) given as a
+    callable and evaluated at the quadrature points, either diagonal
+    (returning (npts, 3)) or a full symmetric tensor (returning
+    (npts, 3, 3)); c likewise; the advection field is affine,
+    b(x) = b0 + B x.  With a K field the face quantities
+    delta = nu^T K nu, the weights omega and the penalty gamma_F are taken
+    pointwise at each face quadrature point, each side's delta from its
+    own evaluation of the field (the same value for a continuous field,
+    so omega = 1/2 there), and the normal fluxes nu . K grad use the full
+    gradient (normal and tangential derivatives) at the face points.
 Readings of the paper where it is silent:
   * interior face normal nu points from T- (lower cell index along the
     axis) into T+; ``flip=True`` reverses every interior face (the form is
@@ -131,10 +134,13 @@ class Problem:
         return float(self._cc[c])
 
     def K_at(self, c, x) -> np.ndarray:
-        """Diagonal of K of cell c at physical points x (npts, 3) -> (npts, 3)."""
+        """K of cell c at physical points x (npts, 3) -> (npts, 3, 3)."""
         if self.Kfield is not None:
-            return np.asarray(self.Kfield(x), dtype=np.float64).reshape(len(x), 3)
-        return np.broadcast_to(self._Kc[c], (len(x), 3))
+            K = np.asarray(self.Kfield(x), dtype=np.float64)
+            if K.ndim == 2:
+                K = K[:, :, None] * np.eye(3)[None, :, :]
+            return K.reshape(len(x), 3, 3)
+        return np.broadcast_to(np.diag(self._Kc[c]), (len(x), 3, 3))
 
     def c_at(self, c, x) -> np.ndarray:
         """c of cell c at physical points x -> (npts,)."""
@@ -160,7 +166,11 @@ def cell_centre_problem(prob: Problem) -> Problem:
     if prob.Kfield is None and prob.cfield is None:
         return prob
     centres = np.array([prob.origin(c) + 0.5 * prob.h for c in range(prob.ncell)])
-    K = prob.Kfield(centres) if prob.Kfield is not None else prob._Kc
+    if prob.Kfield is not None:
+        Kc = np.asarray(prob.Kfield(centres), dtype=np.float64)
+        K = Kc if Kc.ndim == 2 else np.diagonal(Kc, axis1=1, axis2=2)  # a full tensor keeps its diagonal
+    else:
+        K = prob._Kc
     cc = prob.cfield(centres) if prob.cfield is not None else prob._cc
     return replace(prob, K=np.asarray(K, dtype=np.float64).reshape(prob.ncell, 3),
                    c=np.asarray(cc, dtype=np.float64).reshape(prob.ncell), Kfield=None, cfield=None)
@@ -233,6 +243,30 @@ def face_tab(prob: Problem, tab: Tables, k: int, side: int):
     return Tr, Dk, xi
 
 
+def face_grad_tab(prob: Problem, tab: Tables, k: int, side: int):
+    """Physical gradients of all basis functions at the points of the face
+    xi_k = side: list over l of (Q, n^3) tables of d/dx_l phi_j."""
+    h = prob.h
+    out = []
+    for l in AXES:
+        f = [tab.L, tab.L, tab.L]
+        f[k] = tab.end_val[side][None, :]
+        if l == k:
+            f[k] = tab.end_der[side][None, :] / h[k]
+        else:
+            f[l] = tab.Dl / h[l]
+        out.append(tensor_tab(*f))
+    return out
+
+
+def face_flux_tab(prob: Problem, tab: Tables, c: int, k: int, side: int, x: np.ndarray, nu_k: float):
+    """(Q, n^3) table of nu . K(x) grad phi_j at the face points x of cell c
+    on its face xi_k = side, nu = nu_k e_k: nu_k sum_l K_kl(x) d_l phi_j."""
+    Gf = face_grad_tab(prob, tab, k, side)
+    Kx = prob.K_at(c, x)
+    return nu_k * sum(Kx[:, k, l][:, None] * Gf[l] for l in AXES)
+
+
 def face_weights(prob: Problem, tab: Tables, k: int) -> np.ndarray:
     """Physical face quadrature weights W^F_q = w_a w_b |F| for axis k."""
     h = prob.h
@@ -254,7 +288,9 @@ def volume_matrix(prob: Problem, tab: Tables, c: int, Phi, G) -> np.ndarray:
     Kq = prob.K_at(c, xq)
     V = np.zeros((Phi.shape[1], Phi.shape[1]))
     for k in AXES:
-        V += (G[k].T * (W * Kq[:, k])) @ G[k]
+        for l in AXES:
+            if np.any(Kq[:, k, l] != 0.0):
+                V += (G[k].T * (W * Kq[:, k, l])) @ G[l]
     if prob.has_b:
         bq = prob.bfield(xq)
         for k in AXES:
@@ -305,11 +341,12 @@ def interior_face_blocks(prob: Problem, tab: Tables, k: int, cl: int, cu: int):
         Tr = {"-": Tr_u, "+": Tr_l}
         Dk = {"-": Dk_u, "+": Dk_l}
         nu_k = -1.0
-    delta = {s: prob.K_at(cells[s], x)[:, k] for s in "-+"}  # nu^T K nu at the face points
+    delta = {s: prob.K_at(cells[s], x)[:, k, k] for s in "-+"}  # nu^T K nu at the face points
+    side_of = {"-": 1, "+": 0} if not prob.flip else {"-": 0, "+": 1}
+    flux = {s: face_flux_tab(prob, tab, cells[s], k, side_of[s], x, nu_k) for s in "-+"}  # nu . K grad phi
     omega = {"-": delta["+"] / (delta["-"] + delta["+"]), "+": delta["-"] / (delta["-"] + delta["+"])}
     gam = penalty_interior(prob, k, delta["-"], delta["+"])
     sgn = {"-": 1.0, "+": -1.0}  # [[v]] = v- - v+
-    Dn = {s: nu_k * Dk[s] for s in "-+"}  # d/dnu
     if prob.has_b:
         bnu = nu_k * prob.bfield(x)[:, k]
     else:
@@ -320,8 +357,8 @@ def interior_face_blocks(prob: Problem, tab: Tables, k: int, cl: int, cu: int):
     for s in "-+":  # test side
         for t in "-+":  # trial side
             F = sgn[s] * (Tr[s].T * (WF * bnu * chi[t])) @ Tr[t]
-            F -= sgn[s] * (Tr[s].T * (WF * omega[t] * delta[t])) @ Dn[t]
-            F -= sgn[t] * (Dn[s].T * (WF * omega[s] * delta[s])) @ Tr[t]
+            F -= sgn[s] * (Tr[s].T * (WF * omega[t])) @ flux[t]
+            F -= sgn[t] * (flux[s].T * (WF * omega[s])) @ Tr[t]
             F += sgn[s] * sgn[t] * (Tr[s].T * (WF * gam)) @ Tr[t]
             blocks[(cells[s], cells[t])] = F
     return blocks
@@ -334,10 +371,11 @@ def dirichlet_face_matrix(prob: Problem, tab: Tables, c: int, k: int, side: int)
     Tr, Dk, xi = face_tab(prob, tab, k, side)
     WF = face_weights(prob, tab, k)
     nu_k = 1.0 if side == 1 else -1.0
-    d = prob.K_at(c, prob.origin(c) + xi * h)[:, k]
+    x = prob.origin(c) + xi * h
+    d = prob.K_at(c, x)[:, k, k]
     gam = penalty_boundary(prob, k, d)
-    Dn = nu_k * Dk
-    Bm = -(Tr.T * (WF * d)) @ Dn - (Dn.T * (WF * d)) @ Tr + (Tr.T * (WF * gam)) @ Tr
+    flux = face_flux_tab(prob, tab, c, k, side, x, nu_k)
+    Bm = -(Tr.T * WF) @ flux - (flux.T * WF) @ Tr + (Tr.T * (WF * gam)) @ Tr
     if prob.has_b:
         bnu = nu_k * prob.bfield(prob.origin(c) + xi * h)[:, k]
         chi = (bnu >= 0.0).astype(np.float64)
@@ -442,12 +480,13 @@ def assemble_rhs(prob: Problem, f=None, g=None, j=None) -> np.ndarray:
             if g is None:
                 continue
             gv = g(x)
-            d = prob.K_at(c, x)[:, k]
+            d = prob.K_at(c, x)[:, k, k]
             gam = penalty_boundary(prob, k, d)
+            flux = face_flux_tab(prob, tab, c, k, side, x, nu_k)
             bnu = nu_k * prob.bfield(x)[:, k] if prob.has_b else np.zeros(WF.shape)
             inflow = (bnu < 0.0).astype(np.float64)  # Phi(0, g, b_nu) = b_nu g when b_nu < 0
             rhs[c] -= Tr.T @ (WF * inflow * bnu * gv)
-            rhs[c] -= (nu_k * Dk).T @ (WF * d * gv)
+            rhs[c] -= flux.T @ (WF * gv)
             rhs[c] += Tr.T @ (WF * gam * gv)
     return rhs.ravel()
 

@@ -24,7 +24,13 @@ the weights omega^+-, the penalty gamma_F and the upwind flux Phi):
     P_k quadratic, every integrand is exact, so Q_p solutions are
     reproduced (this fails if K is frozen anywhere); symmetric positive
     definite; L2 rates p+1 for a smooth solution; the cell-centre problem
-    of the preconditioner holds the field's centre values.
+    of the preconditioner holds the field's centre values;
+  * full-tensor fields K(x) = sum_m P_m(x_m) n_m n_m^T: with n = I they give
+    the diagonal field's matrix; with a rotated basis and linear P_m every
+    integrand (cross derivatives included) is exact, so Q_p solutions are
+    reproduced -- this fails if the cross-derivative volume terms or the
+    tangential derivatives in the face fluxes are dropped; SPD; L2 rate
+    p + 1 for a smooth solution with quadratic P_m.
 """
 import numpy as np
 import pytest
@@ -378,3 +384,129 @@ def test_cell_centre_problem():
     with pytest.raises(ValueError):
         solvers.p0_direct(pr)
     assert solvers.p0_direct(pc).shape == (12, 12)
+
+
+def _rotated_field(q0, q1, q2, n):
+    """K(x) = sum_m P_m(x_m) n_m n_m^T (rows of n orthonormal) as a full
+    tensor, and the divergence of K grad u for a polynomial u."""
+    q0, q1, q2 = (np.asarray(v, dtype=np.float64) for v in (q0, q1, q2))
+    n = np.asarray(n, dtype=np.float64)
+
+    def K(x):
+        P = q0 + q1 * x + q2 * x ** 2  # (npts, 3): P_m(x_m)
+        return np.einsum("qm,mk,ml->qkl", P, n, n)
+
+    def dK(x):  # d/dx_j K_kl = P_j'(x_j) n_jk n_jl
+        dP = q1 + 2.0 * q2 * x
+        return np.einsum("qj,jk,jl->qjkl", dP, n, n)
+
+    return K, dK
+
+
+def _rotation(a, b, c):
+    ca, sa, cb, sb, cc, sc = np.cos(a), np.sin(a), np.cos(b), np.sin(b), np.cos(c), np.sin(c)
+    Rz = np.array([[ca, -sa, 0], [sa, ca, 0], [0, 0, 1]])
+    Ry = np.array([[cb, 0, sb], [0, 1, 0], [-sb, 0, cb]])
+    Rx = np.array([[1, 0, 0], [0, cc, -sc], [0, sc, cc]])
+    return Rz @ Ry @ Rx
+
+
+def test_full_tensor_field_with_axis_directions_equals_diagonal_field():
+    Kd, _ = _axis_field(*FIELD)
+    Kf, _ = _rotated_field(*FIELD, np.eye(3))
+    bc = ("D", "N", "D", "D", "N", "D")
+    a = dg.Problem(cells=(3, 2, 2), lengths=(1.0, 0.7, 1.3), p=2, bc=bc, Kfield=Kd)
+    b = dg.Problem(cells=(3, 2, 2), lengths=(1.0, 0.7, 1.3), p=2, bc=bc, Kfield=Kf)
+    Aa, Ab = dg.assemble(a).toarray(), dg.assemble(b).toarray()
+    assert np.abs(Aa - Ab).max() <= 1e-14 * np.abs(Aa).max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_rotated_field_polynomial_reproduction(p):
+    # K_kl depends on one coordinate x_m, linearly here (q2 = 0); the
+    # integrands K_kl d_l u d_k v have degree <= 2p + 1 in every direction,
+    # so the p+1-point rule is exact and Q_p solutions are reproduced.  This
+    # pins the cross-derivative volume terms and the tangential derivatives
+    # in the face fluxes (dropping either breaks it).
+    rng = np.random.default_rng(50 + p)
+    n = _rotation(0.4, -0.7, 1.1)
+    K, dK = _rotated_field((1.0, 0.5, 2.0), (0.3, -0.2, 0.1), (0.0, 0.0, 0.0), n)
+    bc = ("D", "N", "D", "D", "N", "D")
+    pr = dg.Problem(cells=(3, 2, 2), lengths=(1.0, 0.7, 1.3), p=p, bc=bc, Kfield=K)
+    u, grad, hd = _poly_case(p, rng)
+
+    def hess(x):  # full Hessian of the polynomial by central differences of the exact gradient
+        e = 1e-6
+        Hm = np.zeros((len(x), 3, 3))
+        for j in range(3):
+            dx = np.zeros(3)
+            dx[j] = e
+            Hm[:, :, j] = (grad(x + dx) - grad(x - dx)) / (2 * e)
+        return Hm
+
+    def f(x):  # -div(K grad u) = -sum_kl (d_k K_kl d_l u + K_kl d_kl u)
+        g = grad(x)
+        div = np.einsum("qkkl,ql->q", dK(x), g) + np.einsum("qkl,qkl->q", K(x), hess(x))
+        return -div
+
+    def j(x):
+        flux = -np.einsum("qkl,ql->qk", K(x), grad(x))
+        out = np.full(len(x), np.nan)
+        on_px = np.isclose(x[:, 0], 1.0)
+        on_mz = np.isclose(x[:, 2], 0.0)
+        out[on_px] = flux[on_px, 0]
+        out[on_mz] = -flux[on_mz, 2]
+        assert not np.isnan(out).any()
+        return out
+
+    A = dg.assemble(pr)
+    rhs = dg.assemble_rhs(pr, f=f, g=u, j=j)
+    uI = dg.interpolate(pr, u)
+    # central differences of the exact gradient of a cubic are exact up to
+    # ~1e-10 relative rounding
+    assert np.abs(rhs - A @ uI).max() <= 1e-8 * np.abs(rhs).max()
+
+
+def test_rotated_field_spd_and_convergence():
+    n = _rotation(0.4, -0.7, 1.1)
+    K, dK = _rotated_field(*FIELD, n)
+    pr = dg.Problem(cells=(3, 2, 2), p=2, Kfield=K)
+    A = dg.assemble(pr).toarray()
+    assert np.abs(A - A.T).max() <= 1e-13 * np.abs(A).max()
+    assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
+    pi = np.pi
+
+    def uex(x):
+        return np.sin(pi * x[:, 0]) * np.sin(pi * x[:, 1]) * np.sin(pi * x[:, 2])
+
+    def grad(x):
+        s, cs = np.sin(pi * x), np.cos(pi * x)
+        return pi * np.stack([cs[:, 0] * s[:, 1] * s[:, 2], s[:, 0] * cs[:, 1] * s[:, 2],
+                              s[:, 0] * s[:, 1] * cs[:, 2]], axis=1)
+
+    def hess(x):
+        s, cs = np.sin(pi * x), np.cos(pi * x)
+        H = np.empty((len(x), 3, 3))
+        for a in range(3):
+            for b in range(3):
+                t = np.ones(len(x))
+                for m in range(3):
+                    if m == a and m == b:
+                        t = t * -s[:, m]
+                    elif m == a or m == b:
+                        t = t * cs[:, m]
+                    else:
+                        t = t * s[:, m]
+                H[:, a, b] = pi ** 2 * t
+        return H
+
+    def f(x):
+        return -(np.einsum("qkkl,ql->q", dK(x), grad(x)) + np.einsum("qkl,qkl->q", K(x), hess(x)))
+
+    errs = []
+    for N in (2, 4):
+        pr = dg.Problem(cells=(N, N, N), p=2, Kfield=K)
+        u = spla.spsolve(dg.assemble(pr).tocsc(), dg.assemble_rhs(pr, f=f))
+        errs.append(dg.l2_error(pr, u, uex))
+    rate = np.log2(errs[0] / errs[1])
+    assert 2.6 <= rate <= 3.4, (errs, rate)
