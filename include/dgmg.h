@@ -72,7 +72,7 @@ enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK = 1, DG_PRECOND_MG = 2 };
 enum { DG_SWEEP_JACOBI = 0, DG_SWEEP_SOR = 1, DG_SWEEP_SSOR = 2, DG_SWEEP_SOR_BACKWARD = 3 };
 enum { DG_IPREC_DIAG = 0, DG_IPREC_TRIDIAG = 1 };
 enum { DG_COARSE_P0 = 0, DG_COARSE_Q1 = 1, DG_COARSE_AUTO = 2 };
-enum { DG_FIELD_NONE = 0, DG_FIELD_AXIS_QUADRATIC = 1 };
+enum { DG_FIELD_NONE = 0, DG_FIELD_AXIS_QUADRATIC = 1, DG_FIELD_ROTATED_QUADRATIC = 2 };
 
 typedef struct dg_problem dg_problem;          /* opaque, library-owned */
 typedef struct dg_solve_state dg_solve_state;  /* opaque, library-owned */
@@ -93,24 +93,29 @@ typedef struct {
   double c_scalar;         /* c when c == NULL                              */
   double b0[3];            /* b(x) = b0 + B x                               */
   double B[9];
-  int field;               /* DG_FIELD_NONE (0, default): K and c as above;
-                              DG_FIELD_AXIS_QUADRATIC: coefficient fields
-                              evaluated at the quadrature points of the
-                              operator (Sec. 4.2, second diffusion test, with
-                              the orthonormal directions n_k = e_k):
-                                K(x) = diag(P_1(x), P_2(y), P_3(z)),
-                                P_k(s) = kq[k] + kq[3+k] s + kq[6+k] s^2,
-                                c(x) = cq[0] + cq[1] (x^2 + y^2 + z^2);
-                              P_k must be > 0 on [0, L_k] and c >= 0 on the
+  int field;               /* DG_FIELD_NONE (0, default): K and c as above.
+                              Otherwise coefficient fields evaluated at the
+                              quadrature points of the operator (Sec. 4.2,
+                              second diffusion test):
+                                K(x) = sum_m P_m(x_m) n_m n_m^T,
+                                P_m(s) = kq[m] + kq[3+m] s + kq[6+m] s^2,
+                                c(x) = cq[0] + cq[1] (x^2 + y^2 + z^2),
+                              with n_m = e_m (DG_FIELD_AXIS_QUADRATIC:
+                              K(x) = diag(P_1(x), P_2(y), P_3(z))) or n_m =
+                              row m of nrot, an orthonormal basis
+                              (DG_FIELD_ROTATED_QUADRATIC: a full tensor).
+                              P_m must be > 0 on [0, L_m] and c >= 0 on the
                               box.  K, K_scalar, c, c_scalar are then
                               ignored.  The preconditioner (dg_block_*,
                               dg_mg_vcycle and the preconditioner of
                               dg_solve) works with the field's values at the
-                              cell centres, as in the paper; dg_apply,
+                              cell centres, as in the paper (for a full
+                              tensor: its diagonal there); dg_apply,
                               dg_assemble_rhs and the outer Krylov method use
                               the field itself.                              */
   double kq[9];
   double cq[2];
+  double nrot[9];          /* DG_FIELD_ROTATED_QUADRATIC: rows n_1, n_2, n_3 */
 } dg_problem_desc;
 
 /* Block smoother options (alg block_jacobi, alg block_SOR, Sec. 2.2.1;

@@ -28,7 +28,7 @@ DG_PRECOND_BLOCK_JACOBI = DG_PRECOND_BLOCK
 DG_SWEEP_JACOBI, DG_SWEEP_SOR, DG_SWEEP_SSOR, DG_SWEEP_SOR_BACKWARD = 0, 1, 2, 3
 DG_IPREC_DIAG, DG_IPREC_TRIDIAG = 0, 1
 DG_COARSE_P0, DG_COARSE_Q1, DG_COARSE_AUTO = 0, 1, 2
-DG_FIELD_NONE, DG_FIELD_AXIS_QUADRATIC = 0, 1
+DG_FIELD_NONE, DG_FIELD_AXIS_QUADRATIC, DG_FIELD_ROTATED_QUADRATIC = 0, 1, 2
 
 EXPORTS = (
     "dg_problem_create", "dg_problem_destroy", "dg_last_error", "dg_ndof", "dg_boundary_npoints",
@@ -54,6 +54,7 @@ class ProblemDesc(ctypes.Structure):
         ("c", ctypes.POINTER(ctypes.c_double)), ("c_scalar", ctypes.c_double),
         ("b0", ctypes.c_double * 3), ("B", ctypes.c_double * 9),
         ("field", ctypes.c_int), ("kq", ctypes.c_double * 9), ("cq", ctypes.c_double * 2),
+        ("nrot", ctypes.c_double * 9),
     ]
 
 
@@ -201,6 +202,7 @@ class ProblemSpec:
     # K and c are then ignored
     kfield: tuple | None = None
     cfield: tuple = (0.0, 0.0)
+    nrot: tuple | None = None  # rows n_m of an orthonormal basis: K(x) = sum_m P_m(x_m) n_m n_m^T
     _keep: list = field(default_factory=list, repr=False)
 
     def desc(self) -> ProblemDesc:
@@ -238,11 +240,14 @@ class ProblemSpec:
             d.B[i] = float(Bm[i])
         d.field = DG_FIELD_NONE
         if self.kfield is not None:
-            d.field = DG_FIELD_AXIS_QUADRATIC
+            d.field = DG_FIELD_AXIS_QUADRATIC if self.nrot is None else DG_FIELD_ROTATED_QUADRATIC
             kq = np.asarray(self.kfield, dtype=np.float64).reshape(9)
             for i in range(9):
                 d.kq[i] = float(kq[i])
             d.cq[0], d.cq[1] = (float(v) for v in self.cfield)
+            nr = np.eye(3) if self.nrot is None else np.asarray(self.nrot, dtype=np.float64)
+            for i in range(9):
+                d.nrot[i] = float(nr.reshape(9)[i])
         return d
 
 

@@ -403,7 +403,35 @@ __global__ __launch_bounds__(256) void k_rhs(Geo g, const double *__restrict__ f
           val -= WF * bv * ev;
         } else {
           const double nu = side ? 1.0 : -1.0;
-          const double d = g.field ? field_K(g, k, (ijk[k] + side) * g.h[k]) : g.K[3 * c + k];
+          double d = g.field ? field_K(g, k, (ijk[k] + side) * g.h[k]) : g.K[3 * c + k];
+          if (g.field == DG_FIELD_ROTATED_QUADRATIC) {
+            // full tensor: K_kk here, and the tangential part of
+            // nu . K grad psi_i paired with g over the face points that
+            // share one tangential index with this DOF
+            double x[3];
+            x[k] = (ijk[k] + side) * g.h[k];
+            x[t1] = (ijk[t1] + (double)tb.xi[q[t1]]) * g.h[t1];
+            x[t2] = (ijk[t2] + (double)tb.xi[q[t2]]) * g.h[t2];
+            double Kx[3][3];
+            field_tensor(g, x, Kx);
+            d = Kx[k][k];
+            double tang = 0.0;
+            for (int jj = 0; jj < N; ++jj) {
+              // face point (jj, q[t2]): derivative along t1 of psi_i
+              x[t1] = (ijk[t1] + (double)tb.xi[jj]) * g.h[t1];
+              x[t2] = (ijk[t2] + (double)tb.xi[q[t2]]) * g.h[t2];
+              field_tensor(g, x, Kx);
+              const double g1 = bq[off + cf * N2 + jj + N * q[t2]];
+              tang += tb.w[jj] * tb.w[q[t2]] * g1 * Kx[k][t1] * g.ih[t1] * tb.Dt[q[t1]][jj];
+              // face point (q[t1], jj): derivative along t2
+              x[t1] = (ijk[t1] + (double)tb.xi[q[t1]]) * g.h[t1];
+              x[t2] = (ijk[t2] + (double)tb.xi[jj]) * g.h[t2];
+              field_tensor(g, x, Kx);
+              const double g2 = bq[off + cf * N2 + q[t1] + N * jj];
+              tang += tb.w[q[t1]] * tb.w[jj] * g2 * Kx[k][t2] * g.ih[t2] * tb.Dt[q[t2]][jj];
+            }
+            val -= g.vol / g.h[k] * nu * ev * tang;
+          }
           const double gam = g.sigma * d / g.h[k];
           double bnu = 0.0;
           if (g.has_b) {
@@ -428,6 +456,7 @@ template <int P, typename T>
 static int launch_apply_t(const dg_problem *pr, const void *u, void *v, hipStream_t s, bool nb) {
   constexpr int N = P + 1;
   const int G = (int)((pr->ncell + ApplyShape<N>::CPB - 1) / ApplyShape<N>::CPB);
+  if (nb && pr->geo.field == DG_FIELD_ROTATED_QUADRATIC) return launch_apply_tensor(pr, sizeof(T) == 8 ? DG_FP64 : DG_FP32, u, v, s);
   if (nb && pr->geo.field)
     hipLaunchKernelGGL((k_apply<P, T, true, 0, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u,
                        (T *)v, (const T *)nullptr, (T *)nullptr);

@@ -92,12 +92,14 @@ struct Geo {
   int has_c;
   const double *K;  // device [ncell][3]
   const double *c;  // device [ncell] (valid when has_c)
-  // coefficient field of the outer operator (DG_FIELD_AXIS_QUADRATIC):
-  // K_kk(x) = kq[k] + kq[3+k] x_k + kq[6+k] x_k^2, c(x) = cq[0] + cq[1] |x|^2;
-  // K and c above then hold the values at the cell centres
+  // coefficient field of the outer operator: K(x) = sum_m P_m(x_m) n_m n_m^T
+  // with P_m(s) = kq[m] + kq[3+m] s + kq[6+m] s^2 and n_m = row m of nrot
+  // (the identity for DG_FIELD_AXIS_QUADRATIC), c(x) = cq[0] + cq[1] |x|^2;
+  // K and c above then hold the (diagonal) values at the cell centres
   int field;
   double kq[9];
   double cq[2];
+  double nrot[9];
 };
 
 // P_k(s) of the axis-quadratic coefficient field
@@ -106,6 +108,18 @@ __host__ __device__ inline double field_K(const Geo &g, int k, double s) {
 }
 __host__ __device__ inline double field_c(const Geo &g, double x, double y, double z) {
   return g.cq[0] + g.cq[1] * (x * x + y * y + z * z);
+}
+// the full tensor K(x) of the rotated field (symmetric)
+__host__ __device__ inline void field_tensor(const Geo &g, const double (&x)[3], double (&K)[3][3]) {
+  double P[3];
+  for (int m = 0; m < 3; ++m) P[m] = field_K(g, m, x[m]);
+  for (int k = 0; k < 3; ++k)
+    for (int l = k; l < 3; ++l) {
+      double s = 0.0;
+      for (int m = 0; m < 3; ++m) s += P[m] * g.nrot[3 * m + k] * g.nrot[3 * m + l];
+      K[k][l] = s;
+      K[l][k] = s;
+    }
 }
 
 // One level of a coarse hierarchy on a structured grid of vx * vy * vz
@@ -201,6 +215,8 @@ int hip_fail(hipError_t e, const char *what);
 // kernel launchers (apply.hip / smooth.hip / vec.hip / coarse.hip)
 int launch_apply(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s);
 int launch_block_apply(const dg_problem *pr, int prec, const void *x, void *y, hipStream_t s);
+// outer operator of a full-tensor (rotated) coefficient field (apply_tensor.hip)
+int launch_apply_tensor(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s);
 // rh[c] = sum_{i in cell c} (r - A u)_i                  (P0 restriction)
 // rh[8 c + q] = sum_{i in cell c} phi_q(xi_i) (r - A u)_i  (Q1 corner sums)
 int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, const void *r, void *rh, hipStream_t s,

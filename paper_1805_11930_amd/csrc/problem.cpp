@@ -363,13 +363,26 @@ int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
     set_error("penalty_factor must be finite");
     return DG_EINVAL;
   }
-  if (d->field != DG_FIELD_NONE && d->field != DG_FIELD_AXIS_QUADRATIC) {
-    set_error("field must be DG_FIELD_NONE or DG_FIELD_AXIS_QUADRATIC");
+  if (d->field != DG_FIELD_NONE && d->field != DG_FIELD_AXIS_QUADRATIC && d->field != DG_FIELD_ROTATED_QUADRATIC) {
+    set_error("field must be DG_FIELD_NONE, DG_FIELD_AXIS_QUADRATIC or DG_FIELD_ROTATED_QUADRATIC");
     return DG_EINVAL;
+  }
+  double nrot[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  if (d->field == DG_FIELD_ROTATED_QUADRATIC) {
+    for (int i = 0; i < 9; ++i) nrot[i] = d->nrot[i];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double s = 0.0;
+        for (int i = 0; i < 3; ++i) s += nrot[3 * a + i] * nrot[3 * b + i];
+        if (!std::isfinite(s) || std::fabs(s - (a == b ? 1.0 : 0.0)) > 1e-12) {
+          set_error("field: the rows of nrot must be orthonormal");
+          return DG_EINVAL;
+        }
+      }
   }
   const double len[3] = {d->lx, d->ly, d->lz};
   const int cnt[3] = {d->nx, d->ny, d->nz};
-  if (d->field == DG_FIELD_AXIS_QUADRATIC) {
+  if (d->field != DG_FIELD_NONE) {
     for (int i = 0; i < 9; ++i)
       if (!std::isfinite(d->kq[i])) {
         set_error("field coefficients kq must be finite");
@@ -398,14 +411,19 @@ int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
   }
   std::vector<double> K(3 * ncell), cc(ncell, 0.0);
   bool has_c = false;
-  if (d->field == DG_FIELD_AXIS_QUADRATIC) {
-    // cell-centre values for the preconditioner
+  if (d->field != DG_FIELD_NONE) {
+    // cell-centre values for the preconditioner (the diagonal of K there)
     for (int64_t c = 0; c < ncell; ++c) {
       const int64_t ijk[3] = {c % d->nx, (c / d->nx) % d->ny, c / ((int64_t)d->nx * d->ny)};
-      double xc[3];
+      double xc[3], Pm[3];
       for (int k = 0; k < 3; ++k) {
         xc[k] = (ijk[k] + 0.5) * (len[k] / cnt[k]);
-        K[3 * c + k] = d->kq[k] + xc[k] * (d->kq[3 + k] + xc[k] * d->kq[6 + k]);
+        Pm[k] = d->kq[k] + xc[k] * (d->kq[3 + k] + xc[k] * d->kq[6 + k]);
+      }
+      for (int k = 0; k < 3; ++k) {
+        double s = 0.0;
+        for (int m = 0; m < 3; ++m) s += Pm[m] * nrot[3 * m + k] * nrot[3 * m + k];
+        K[3 * c + k] = s;
       }
       cc[c] = d->cq[0] + d->cq[1] * (xc[0] * xc[0] + xc[1] * xc[1] + xc[2] * xc[2]);
     }
@@ -467,6 +485,7 @@ int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
   g.field = d->field;
   for (int i = 0; i < 9; ++i) g.kq[i] = d->field ? d->kq[i] : 0.0;
   for (int i = 0; i < 2; ++i) g.cq[i] = d->field ? d->cq[i] : 0.0;
+  for (int i = 0; i < 9; ++i) g.nrot[i] = nrot[i];
   int rc = dmalloc(pr, (void **)&pr->dK, 3 * ncell * sizeof(double));
   if (!rc) rc = dmalloc(pr, (void **)&pr->dc, ncell * sizeof(double));
   if (!rc) {

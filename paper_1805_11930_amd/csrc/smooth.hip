@@ -95,9 +95,15 @@ __device__ inline T cell_sum(T v) {
 }
 
 // a / b for the scalars of the inner iteration: FP32 by the hardware
-// reciprocal (about 1 ulp; the FP32 inner solve stops at eps >= 1e-7),
-// FP64 correctly rounded
-__device__ inline float inner_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// reciprocal (about 1 ulp; the FP32 inner solve stops at eps >= 1e-7)
+// when b is a normal number, by IEEE division when b is zero or subnormal
+// (whose reciprocal overflows; blocks with tiny right-hand sides reach such
+// values), FP64 correctly rounded
+__device__ inline float inner_div(float a, float b) {
+  float r = a * __builtin_amdgcn_rcpf(b);
+  if (!(fabsf(b) >= 1.17549435e-38f)) r = a / b;
+  return r;
+}
 __device__ inline double inner_div(double a, double b) { return a / b; }
 
 struct SmoothKArgs {

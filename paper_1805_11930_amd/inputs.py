@@ -59,6 +59,7 @@ class Workload:
     # K_kk(x) = q0_k + q1_k x_k + q2_k x_k^2; cfield = (c0, c2), c = c0 + c2 |x|^2
     kfield: tuple | None = None
     cfield: tuple = (0.0, 0.0)
+    nrot: tuple | None = None  # orthonormal rows n_m: K(x) = sum_m P_m(x_m) n_m n_m^T (None: n_m = e_m)
 
     @property
     def ncell(self) -> int:
@@ -178,12 +179,26 @@ def pe2000(b=(1.0, 0.0, 0.0), p=3, cells=None) -> Workload:
                     info={"kappa": kappa, "peclet": 2000.0})
 
 
-def field_functions(kfield, cfield=(0.0, 0.0)):
-    """Callables K(x) -> (npts, 3) diagonal and c(x) -> (npts,) of an
-    axis-quadratic coefficient field."""
+def field_functions(kfield, cfield=(0.0, 0.0), nrot=None):
+    """Callables K(x) and c(x) -> (npts,) of a quadratic coefficient field:
+    K(x) -> (npts, 3) diagonal when nrot is None, else the full tensor
+    sum_m P_m(x_m) n_m n_m^T -> (npts, 3, 3)."""
     q0, q1, q2 = (np.asarray(v, dtype=np.float64) for v in kfield)
     c0, c2 = (float(v) for v in cfield)
-    return (lambda x: q0 + q1 * x + q2 * x ** 2), (lambda x: c0 + c2 * np.sum(x ** 2, axis=1))
+    cfun = lambda x: c0 + c2 * np.sum(x ** 2, axis=1)  # noqa: E731
+    if nrot is None:
+        return (lambda x: q0 + q1 * x + q2 * x ** 2), cfun
+    n = np.asarray(nrot, dtype=np.float64)
+    return (lambda x: np.einsum("qm,mk,ml->qkl", q0 + q1 * x + q2 * x ** 2, n, n)), cfun
+
+
+def rotation(a: float, b: float, c: float) -> np.ndarray:
+    """Orthonormal basis (rows) from three angles (z-y-x rotations)."""
+    ca, sa, cb, sb, cc, sc = np.cos(a), np.sin(a), np.cos(b), np.sin(b), np.cos(c), np.sin(c)
+    Rz = np.array([[ca, -sa, 0.0], [sa, ca, 0.0], [0.0, 0.0, 1.0]])
+    Ry = np.array([[cb, 0.0, sb], [0.0, 1.0, 0.0], [-sb, 0.0, cb]])
+    Rx = np.array([[1.0, 0.0, 0.0], [0.0, cc, -sc], [0.0, sc, cc]])
+    return (Rz @ Ry @ Rx).T
 
 
 def gaussian(x0, s: float = 0.1):
@@ -191,7 +206,8 @@ def gaussian(x0, s: float = 0.1):
     return lambda x: np.exp(-np.sum((x - x0) ** 2, axis=1) / (2.0 * s * s))
 
 
-def inhomogeneous(p=4, cells=None, kfield=((1.0, 0.5, 2.0), (0.0, 0.0, 0.0), (3.0, 1.0, 0.5))) -> Workload:
+def inhomogeneous(p=4, cells=None, kfield=((1.0, 0.5, 2.0), (0.0, 0.0, 0.0), (3.0, 1.0, 0.5)),
+                  nrot=None) -> Workload:
     """Second diffusion test of Sec. 4.2: -div(K(x) grad u) + c(x) u = f on
     [0,1] x [0,1] x [0,2] with K(x) = sum_k P_k(x_k) n_k n_k^T, n_k = e_k,
     P_k(s) = p0_k + p2_k s^2 (the paper leaves p0, p2 open; here
@@ -201,9 +217,11 @@ def inhomogeneous(p=4, cells=None, kfield=((1.0, 0.5, 2.0), (0.0, 0.0, 0.0), (3.
     width 0.1.  Default grid: the paper's isotropic grid for degree p."""
     if cells is None:
         cells = {1: (128, 128, 256), 2: (56, 56, 112), 3: (32, 32, 64), 4: (20, 20, 40)}[p]
-    return Workload("inhomogeneous-%dx%dx%d-p%d" % (*cells, p), tuple(cells), (1.0, 1.0, 2.0), p,
+    name = "inhomogeneous%s-%dx%dx%d-p%d" % ("-rotated" if nrot is not None else "", *cells, p)
+    return Workload(name, tuple(cells), (1.0, 1.0, 2.0), p,
                     ("D", "N", "D", "D", "D", "D"), None, 1.0, f=gaussian((0.75, 0.5, 0.3)),
-                    g=gaussian((0.0, 0.5, 0.5)), j=gaussian((1.0, 0.5, 0.5)), kfield=kfield, cfield=(0.0, 1e-8))
+                    g=gaussian((0.0, 0.5, 0.5)), j=gaussian((1.0, 0.5, 0.5)), kfield=kfield, cfield=(0.0, 1e-8),
+                    nrot=None if nrot is None else tuple(map(tuple, np.asarray(nrot, dtype=np.float64))))
 
 
 def poisson_gauss(p=3, cells=None) -> Workload:

@@ -11,7 +11,7 @@ def oracle_problem(w, **kw) -> dg.Problem:
     if getattr(w, "kfield", None) is not None:
         from paper_1805_11930_amd import inputs
 
-        Kf, cf = inputs.field_functions(w.kfield, w.cfield)
+        Kf, cf = inputs.field_functions(w.kfield, w.cfield, getattr(w, "nrot", None))
         kw = dict(kw, Kfield=Kf, cfield=cf)
     return dg.Problem(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c, b0=w.b0, B=w.B,
                       **kw)
@@ -21,7 +21,8 @@ def spec(w):
     from paper_1805_11930_amd import ProblemSpec
 
     return ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c, b0=w.b0, B=w.B,
-                       kfield=getattr(w, "kfield", None), cfield=getattr(w, "cfield", (0.0, 0.0)))
+                       kfield=getattr(w, "kfield", None), cfield=getattr(w, "cfield", (0.0, 0.0)),
+                       nrot=getattr(w, "nrot", None))
 
 
 def rel(a, b) -> float:

@@ -12,7 +12,10 @@ C ABI.
     V-cycle with the exact P0 coarse solve match the oracle's cell-centre
     problem;
   * the solve (FCG, FP32 and FP64 V-cycle) reaches 1e-8 and the sparse
-    direct solution of the field operator.
+    direct solution of the field operator;
+  * the same for a rotated basis n_m (a full K(x) tensor, the sum-factorised
+    tensor kernel): apply, right-hand side, sampled rows at full size, the
+    preconditioner's cell-centre diagonal, and the solve.
 """
 import numpy as np
 import pytest
@@ -130,5 +133,83 @@ def test_field_rejects_nonpositive_K():
     from paper_1805_11930_amd import DgError
 
     w = inputs.inhomogeneous(p=1, cells=(2, 2, 2), kfield=((1.0, 1.0, 1.0), (-3.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
+    with pytest.raises(DgError):
+        _lib(w)
+
+
+def _rotated_case(p, cells, with_b=False):
+    w = inputs.inhomogeneous(p=p, cells=cells, kfield=((1.0, 0.5, 2.0), (0.4, -0.2, 0.3), (3.0, 1.0, 0.5)),
+                             nrot=inputs.rotation(0.4, -0.7, 1.1))
+    w.cfield = (0.3, 0.7)
+    if with_b:
+        w.b0 = (0.6, -0.4, 0.3)
+        w.B = ((0.0, 1.0, 0.0), (-1.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+    return w
+
+
+@pytest.mark.parametrize("p,cells,with_b", [(1, (7, 5, 3), False), (2, (2, 9, 4), True), (3, (5, 3, 4), False),
+                                            (4, (3, 4, 5), True), (4, (6, 2, 3), False), (2, (1, 1, 1), False)])
+def test_rotated_field_apply_and_rhs(p, cells, with_b):
+    print(f"rotated field apply p={p} cells={cells} b={with_b}", flush=True)
+    w = _rotated_case(p, cells, with_b)
+    opr = oracle_problem(w)
+    A = dg.assemble(opr)
+    u = inputs.random_vector(opr.ndof, seed=64)
+    ref = A @ u
+    P = _lib(w)
+    ud = torch.from_numpy(u).cuda()
+    assert rel(P.apply(ud).cpu().numpy(), ref) <= 1e-12
+    assert rel(P.apply(ud.float()).cpu().numpy(), ref) <= 1e-5
+    rhs = dg.assemble_rhs(opr, f=w.f, g=w.g, j=w.j)
+    assert rel(P.rhs_from_functions(f=w.f, g=w.g, j=w.j).cpu().numpy(), rhs) <= 1e-12
+    # preconditioner: the diagonal of K at the cell centres
+    pc = dg.cell_centre_problem(opr)
+    Dc = dg.block_diagonal(dg.assemble(pc), pc.ncell)
+    U = u.reshape(opr.ncell, -1)
+    refb = np.concatenate([Dc[T] @ U[T] for T in range(opr.ncell)])
+    assert rel(P.block_apply(ud).cpu().numpy(), refb) <= 1e-12
+    P.close()
+
+
+def test_rotated_field_full_size_sampled_rows():
+    w = inputs.inhomogeneous(p=4, nrot=inputs.rotation(0.4, -0.7, 1.1))
+    print(f"rotated field sampled rows {w.name}", flush=True)
+    opr = oracle_problem(w)
+    u = inputs.random_vector(opr.ndof, seed=65)
+    nx, ny, nz = w.cells
+    samples = [0, nx - 1, opr.cell_id(nx // 2, ny // 2, nz // 2), opr.cell_id(nx - 1, ny - 1, nz - 1),
+               opr.cell_id(nx - 1, 3, 7), opr.cell_id(2, 0, nz - 1)]
+    ref = oracle_rows(opr, samples, u)
+    P = _lib(w)
+    v = P.apply(torch.from_numpy(u).cuda()).cpu().numpy().reshape(opr.ncell, -1)
+    for c in samples:
+        assert rel(v[c], ref[c]) <= 1e-12, c
+    P.close()
+
+
+def test_rotated_field_solve():
+    from paper_1805_11930_amd import DG_FP32, DG_FP64, DG_KRYLOV_FCG, DG_PRECOND_MG, solve_opts
+
+    w = inputs.inhomogeneous(p=2, cells=(8, 8, 16), nrot=inputs.rotation(0.4, -0.7, 1.1))
+    print(f"rotated field solve {w.name}", flush=True)
+    opr = oracle_problem(w)
+    A = dg.assemble(opr)
+    rhs = dg.assemble_rhs(opr, f=w.f, g=w.g, j=w.j)
+    ref = spla.spsolve(A.tocsc(), rhs)
+    P = _lib(w)
+    f = P.rhs_from_functions(f=w.f, g=w.g, j=w.j)
+    for prec in (DG_FP64, DG_FP32):
+        o = solve_opts(krylov=DG_KRYLOV_FCG, precond=DG_PRECOND_MG, precond_precision=prec, rtol=1e-8, maxit=300)
+        u, res = P.solve(f, opts=o)
+        print(f"  prec={prec} iters={res.iters} rel_res={res.rel_residual:.3e}", flush=True)
+        assert res.status == 0 and res.rel_residual <= 1e-8
+        assert rel(u.cpu().numpy(), ref) <= 1e-6
+    P.close()
+
+
+def test_rotated_field_rejects_non_orthonormal_basis():
+    from paper_1805_11930_amd import DgError
+
+    w = inputs.inhomogeneous(p=1, cells=(2, 2, 2), nrot=((1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 1.0, 0.0)))
     with pytest.raises(DgError):
         _lib(w)
