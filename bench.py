@@ -168,7 +168,8 @@ def pe2000_leg(p: int = 3) -> dict:
 def diffusion_leg(p: int = 3) -> dict:
     """The two diffusion tests of Sec. 4.2 on the paper's isotropic grid for
     degree p ([0,1]^2 x [0,2]): Poisson and the inhomogeneous problem with
-    K(x), c(x) at the quadrature points of the outer operator and their
+    K(x), c(x) at the quadrature points of the outer operator (axis-aligned
+    directions n_m = e_m, and a rotated basis: a full tensor) and their
     cell-centre values in the FP32 / FP64 V-cycle; FCG to 1e-8, inner PCG
     eps = 1e-2.  Time per unknown, the paper's unit for these tests."""
     import torch
@@ -177,9 +178,11 @@ def diffusion_leg(p: int = 3) -> dict:
                                       solve_opts)
 
     out = {"krylov": "flexible CG, rtol 1e-8", "preconditioner": "V-cycle, block-Jacobi, inner PCG eps=1e-2, Q1"}
-    for tag, w in (("poisson", inputs.poisson_gauss(p)), ("inhomogeneous", inputs.inhomogeneous(p))):
+    cases = (("poisson", inputs.poisson_gauss(p)), ("inhomogeneous", inputs.inhomogeneous(p)),
+             ("inhomogeneous_rotated", inputs.inhomogeneous(p, nrot=inputs.rotation(0.4, -0.7, 1.1))))
+    for tag, w in cases:
         P = Problem(ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c,
-                                b0=w.b0, B=w.B, kfield=w.kfield, cfield=w.cfield))
+                                b0=w.b0, B=w.B, kfield=w.kfield, cfield=w.cfield, nrot=w.nrot))
         f = P.rhs_from_functions(f=w.f, g=w.g, j=w.j)
         u = torch.zeros_like(f)
         v = torch.empty_like(f)
