@@ -310,13 +310,16 @@ int dg_coarse_stencil(dg_problem *prob, int coarse_space, int level, int *dims, 
  * are shared by its solves).  DG_ENOMEM when the workspace does not fit. */
 int dg_solve_start(dg_problem *prob, const double *f, double *u, const dg_solve_opts *opts,
                    dg_solve_state **out);
-/* Advance every unfinished state in active[0..n_active) by one outer
- * iteration.  The iteration runs in three phases (apply, update, precondition);
- * each phase is enqueued for all states on their own streams and then
- * waited for once, so requests of different sizes and degrees overlap on
- * the device and share the host round trips.  A request's arithmetic is
- * the same alone and in any batch.  Returns after all states' work for the
- * step is complete; `stream` is not used (reserved). */
+/* One step of every unfinished state in active[0..n_active): take the
+ * convergence decision of the outer iteration in flight (waiting only for
+ * that state's residual norm, while its preconditioner still runs) and
+ * enqueue the next iteration on the state's stream.  An iteration (apply,
+ * update, precondition) is enqueued as a whole with its scalars in device
+ * memory, so requests of different sizes and degrees overlap on the device
+ * and the device does not idle between iterations.  A solve of k
+ * iterations takes k + 1 steps (the last one only decides).  A request's
+ * arithmetic is the same alone and in any batch.  `stream` is not used
+ * (reserved). */
 int dg_batch_step(dg_solve_state **active, int n_active, void *stream);
 /* DG_EAGAIN while the solve runs; DG_OK once finished, with *res (nullable)
  * filled (its status is DG_OK, DG_ENOCONV or DG_EBREAKDOWN). */

@@ -636,8 +636,12 @@ int dg_coarse_stencil(dg_problem *pr, int coarse_space, int level, int *dims, do
 
 // exported for solve.cpp
 namespace dgmg {
-int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, double rnorm, float *r32,
-                  float *z32, hipStream_t s) {
+namespace {
+// z = M(r); with an FP32 preconditioner r is scaled by 1 / ||r||_2 before the
+// cast (host value rnorm, or rr = ||r||^2 in device memory when rr_dev is
+// given) and z scaled back after it.
+int precond_core(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, double rnorm,
+                 const double *rr_dev, float *r32, float *z32, hipStream_t s) {
   int rc;
   if (o->precond == DG_PRECOND_NONE) {
     DG_HIP(hipMemcpyAsync(z, r, (size_t)pr->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -648,7 +652,8 @@ int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, doubl
   const void *rin = r;
   void *zout = z;
   if (mixed) {
-    if ((rc = cast_d2f(pr->ndof, sc, r, r32, s))) return rc;
+    rc = rr_dev ? cast_d2f_dev(pr->ndof, rr_dev, r, r32, s) : cast_d2f(pr->ndof, sc, r, r32, s);
+    if (rc) return rc;
     rin = r32;
     zout = z32;
   }
@@ -672,7 +677,21 @@ int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, doubl
     }
     if (rc) return rc;
   }
-  if (mixed && (rc = cast_f2d(pr->ndof, 1.0 / sc, z32, z, s))) return rc;
+  if (mixed) {
+    rc = rr_dev ? cast_f2d_dev(pr->ndof, rr_dev, z32, z, s) : cast_f2d(pr->ndof, 1.0 / sc, z32, z, s);
+    if (rc) return rc;
+  }
   return DG_OK;
+}
+}  // namespace
+
+int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, double rnorm, float *r32,
+                  float *z32, hipStream_t s) {
+  return precond_core(pr, o, r, z, rnorm, nullptr, r32, z32, s);
+}
+
+int precond_apply_dev(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, const double *rr_dev,
+                      float *r32, float *z32, hipStream_t s) {
+  return precond_core(pr, o, r, z, 0.0, rr_dev, r32, z32, s);
 }
 }  // namespace dgmg

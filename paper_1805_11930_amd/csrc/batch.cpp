@@ -4,16 +4,21 @@
 // (Sec. 4.2: CG to a relative residual; flexible beta because the FP32 /
 // inexact V-cycle preconditioner is not a fixed linear operator) together
 // with its workspace and its own HIP stream (default priority).  One
-// iteration is split into three phases, each ending in a host scalar
-// decision:
-//   A: q = A p, (p, q)              -> alpha
-//   B: u += alpha p, r -= alpha q, (r, r)  -> convergence test
-//   C: z = M(r), (z, r), (z, r_old) -> beta, p = z + beta p
-// dg_batch_step runs phase A for every active state, waits once for all,
-// then B, then C, so a batch of requests pays three host round trips per
-// iteration in total and their kernels overlap on the device (one stream
-// per request).  Each request's arithmetic is exactly the same as alone:
-// nothing is shared between requests except the device.
+// iteration is enqueued as a whole, its scalars kept in device memory:
+//   q = A p, pq = (p, q); u += alpha p, r -= alpha q with alpha = rz / pq;
+//   rr = (r, r) -> copied to pinned host memory, event;
+//   z = M(r) (FP32: scaled by 1 / sqrt(rr) on the device);
+//   (z, r), (z, r_old); p = z + beta p, rz = (z, r).
+// The host then only waits for the event after rr: it takes the
+// convergence decision while the device runs the preconditioner, and the
+// next iteration is enqueued behind it, so the device does not idle between
+// iterations.  When the decision is "converged", the preconditioner and
+// beta update of that iteration still run but touch only z, p and the
+// scalars: u is the same as with a blocking test after every phase.
+// dg_batch_step takes the pending decision of every active state and
+// enqueues its next iteration; their kernels overlap on the device (one
+// stream per request).  Each request's arithmetic is exactly the same as
+// alone: nothing is shared between requests except the device.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -35,10 +40,16 @@ struct dg_solve_state {
   double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *rold = nullptr;
   float *r32 = nullptr, *z32 = nullptr;
   double *part = nullptr, *dout = nullptr;
-  double *hdots = nullptr;  // pinned host copy of the phase's inner products
-  hipEvent_t ea0 = nullptr, ea1 = nullptr, ep0 = nullptr, ep1 = nullptr;
+  // device scalars: [0] pq, [1] rr, [2] (z, r), [3] (z, r_old), [4..5] rz by
+  // iteration parity, [6] breakdown flag
+  double *dsc = nullptr;
+  double *hdots = nullptr;  // pinned host: [0] setup dots, [1..2] rr by parity, [3..4] flag by parity
+  hipEvent_t ea0[2] = {nullptr, nullptr}, ea1[2] = {nullptr, nullptr};
+  hipEvent_t ep0[2] = {nullptr, nullptr}, ep1[2] = {nullptr, nullptr}, err[2] = {nullptr, nullptr};
+  int pending = -1;       // parity of the enqueued iteration whose decision is open
+  int prec_unread = -1;   // parity of the last preconditioner not yet timed
   bool flex = true;
-  double r0 = 0, rnorm = 0, rz = 0, alpha = 0;
+  double r0 = 0, rnorm = 0;
   int it = 0;
   bool done = false, finalized = false;
   double t_start = 0, t_iter0 = 0;
@@ -47,8 +58,9 @@ struct dg_solve_state {
   dg_solve_result res;
 
   ~dg_solve_state() {
-    for (hipEvent_t e : {ea0, ea1, ep0, ep1})
-      if (e) (void)hipEventDestroy(e);
+    for (int k = 0; k < 2; ++k)
+      for (hipEvent_t e : {ea0[k], ea1[k], ep0[k], ep1[k], err[k]})
+        if (e) (void)hipEventDestroy(e);
     if (hdots) (void)hipHostFree(hdots);
     if (own_stream && s) (void)hipStreamDestroy(s);
   }
@@ -83,42 +95,69 @@ void finish(dg_solve_state *st, int status) {
   st->res.status = status;
 }
 
-// ---- phases ------------------------------------------------------------
-int enqueue_A(dg_solve_state *st) {
-  DG_HIP(hipEventRecord(st->ea0, st->s));
-  int rc = launch_apply(st->pr, DG_FP64, st->p, st->q, st->s);
-  if (rc) return rc;
-  DG_HIP(hipEventRecord(st->ea1, st->s));
-  return enqueue_dots(st, 1, st->p, st->q);
+// ---- one outer iteration ---------------------------------------------------
+int enqueue_iter(dg_solve_state *st) {
+  const int par = st->it & 1;
+  const int64_t n = st->pr->ndof;
+  double *rz_cur = st->dsc + 4 + par, *rz_next = st->dsc + 4 + (par ^ 1);
+  int rc;
+  // q = A p, pq
+  DG_HIP(hipEventRecord(st->ea0[par], st->s));
+  if ((rc = launch_apply(st->pr, DG_FP64, st->p, st->q, st->s))) return rc;
+  DG_HIP(hipEventRecord(st->ea1[par], st->s));
+  DotSet ds;
+  ds.m = 1;
+  ds.a[0] = st->p;
+  ds.b[0] = st->q;
+  if ((rc = dots(ds, n, st->part, st->dsc + 0, st->s))) return rc;
+  // u += alpha p, r -= alpha q (flexible: the new residual goes to the other buffer)
+  double *r_out = st->flex ? st->rold : st->r;
+  if ((rc = cg_update_dev(n, rz_cur, st->dsc + 0, st->p, st->q, st->u, st->r, r_out, st->dsc + 6, st->s))) return rc;
+  if (st->flex) std::swap(st->r, st->rold);
+  ds.a[0] = st->r;
+  ds.b[0] = st->r;
+  if ((rc = dots(ds, n, st->part, st->dsc + 1, st->s))) return rc;
+  DG_HIP(hipMemcpyAsync(st->hdots + 1 + par, st->dsc + 1, sizeof(double), hipMemcpyDeviceToHost, st->s));
+  DG_HIP(hipMemcpyAsync(st->hdots + 3 + par, st->dsc + 6, sizeof(double), hipMemcpyDeviceToHost, st->s));
+  DG_HIP(hipEventRecord(st->err[par], st->s));
+  // z = M(r), beta, p
+  DG_HIP(hipEventRecord(st->ep0[par], st->s));
+  if ((rc = precond_apply_dev(st->pr, &st->o, st->r, st->z, st->dsc + 1, st->r32, st->z32, st->s))) return rc;
+  DG_HIP(hipEventRecord(st->ep1[par], st->s));
+  ds.m = st->flex ? 2 : 1;
+  ds.a[0] = st->z;
+  ds.b[0] = st->r;
+  ds.a[1] = st->z;
+  ds.b[1] = st->rold;
+  if ((rc = dots(ds, n, st->part, st->dsc + 2, st->s))) return rc;
+  if ((rc = beta_update(n, st->dsc + 2, st->dsc + 3, rz_cur, rz_next, st->flex, st->z, st->p, st->s))) return rc;
+  st->pending = par;
+  return DG_OK;
 }
 
-void complete_A(dg_solve_state *st) {
-  st->t_apply += 1e-3 * elapsed_ms(st->ea0, st->ea1);
+void take_prec_time(dg_solve_state *st) {
+  if (st->prec_unread < 0) return;
+  st->t_precond += 1e-3 * elapsed_ms(st->ep0[st->prec_unread], st->ep1[st->prec_unread]);
+  ++st->n_precond;
+  st->prec_unread = -1;
+}
+
+// Waits for the residual norm of the pending iteration and decides.
+int check_iter(dg_solve_state *st) {
+  const int par = st->pending;
+  st->pending = -1;
+  DG_HIP(hipEventSynchronize(st->err[par]));
+  st->t_apply += 1e-3 * elapsed_ms(st->ea0[par], st->ea1[par]);
   ++st->n_apply;
-  const double pq = st->hdots[0];
-  if (!(pq > 0) || !std::isfinite(pq) || !std::isfinite(st->rz)) {
+  take_prec_time(st);  // the previous iteration's preconditioner has finished
+  st->prec_unread = par;
+  if (st->hdots[3 + par] != 0.0) {
     set_error("CG breakdown: p^T A p <= 0 or not finite");
     finish(st, DG_EBREAKDOWN);
-    return;
+    return DG_OK;
   }
-  st->alpha = st->rz / pq;
-}
-
-int enqueue_B(dg_solve_state *st) {
-  int rc;
-  if (st->flex) {
-    // the new residual goes to the other buffer; the previous one is kept
-    if ((rc = cg_update(st->pr->ndof, st->alpha, st->p, st->q, st->u, st->r, st->rold, st->s))) return rc;
-    std::swap(st->r, st->rold);
-  } else if ((rc = cg_update(st->pr->ndof, st->alpha, st->p, st->q, st->u, st->r, st->r, st->s))) {
-    return rc;
-  }
-  return enqueue_dots(st, 1, st->r, st->r);
-}
-
-void complete_B(dg_solve_state *st) {
   ++st->it;
-  st->rnorm = std::sqrt(st->hdots[0]);
+  st->rnorm = std::sqrt(st->hdots[1 + par]);
   if (!std::isfinite(st->rnorm)) {
     set_error("non-finite residual");
     finish(st, DG_EBREAKDOWN);
@@ -127,28 +166,7 @@ void complete_B(dg_solve_state *st) {
   } else if (st->it >= st->o.maxit) {
     finish(st, DG_ENOCONV);
   }
-}
-
-int enqueue_C(dg_solve_state *st) {
-  DG_HIP(hipEventRecord(st->ep0, st->s));
-  int rc = precond_apply(st->pr, &st->o, st->r, st->z, st->rnorm, st->r32, st->z32, st->s);
-  if (rc) return rc;
-  DG_HIP(hipEventRecord(st->ep1, st->s));
-  if (st->flex) return enqueue_dots(st, 2, st->z, st->r, st->z, st->rold);
-  return enqueue_dots(st, 1, st->z, st->r);
-}
-
-int complete_C(dg_solve_state *st) {
-  st->t_precond += 1e-3 * elapsed_ms(st->ep0, st->ep1);
-  ++st->n_precond;
-  double beta;
-  if (st->flex) {
-    beta = (st->hdots[0] - st->hdots[1]) / st->rz;
-  } else {
-    beta = st->hdots[0] / st->rz;
-  }
-  st->rz = st->hdots[0];
-  return axpby(st->pr->ndof, 1.0, st->z, beta, st->p, st->s);
+  return DG_OK;
 }
 
 // true FP64 residual of a finished state and its result record
@@ -158,6 +176,7 @@ int finalize(dg_solve_state *st) {
   if ((rc = sub(st->pr->ndof, st->f, st->q, st->z, st->s))) return rc;
   if ((rc = enqueue_dots(st, 1, st->z, st->z))) return rc;
   DG_HIP(hipStreamSynchronize(st->s));
+  take_prec_time(st);
   const double t_end = now_s();
   dg_solve_result &R = st->res;
   R.iters = st->it;
@@ -209,15 +228,16 @@ int start(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, hi
   } else {
     st->s = s;
   }
-  for (hipEvent_t *ev : {&st->ea0, &st->ea1, &st->ep0, &st->ep1}) {
-    e = hipEventCreate(ev);
-    if (e != hipSuccess) return fail(hip_fail(e, "hipEventCreate"));
-  }
-  e = hipHostMalloc((void **)&st->hdots, 4 * sizeof(double), hipHostMallocDefault);
+  for (int k = 0; k < 2; ++k)
+    for (hipEvent_t *ev : {&st->ea0[k], &st->ea1[k], &st->ep0[k], &st->ep1[k], &st->err[k]}) {
+      e = hipEventCreate(ev);
+      if (e != hipSuccess) return fail(hip_fail(e, "hipEventCreate"));
+    }
+  e = hipHostMalloc((void **)&st->hdots, 8 * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) return fail(hip_fail(e, "hipHostMalloc"));
   if ((rc = st->wb.get(&st->r, n)) || (rc = st->wb.get(&st->p, n)) || (rc = st->wb.get(&st->q, n)) ||
       (rc = st->wb.get(&st->z, n)) || (rc = st->wb.get(&st->part, (size_t)kMaxDots * kDotBlocks)) ||
-      (rc = st->wb.get(&st->dout, kMaxDots)))
+      (rc = st->wb.get(&st->dout, kMaxDots)) || (rc = st->wb.get(&st->dsc, 8)))
     return fail(rc);
   if (st->flex && (rc = st->wb.get(&st->rold, n))) return fail(rc);
   if (o->precond_precision == DG_FP32 && o->precond != DG_PRECOND_NONE) {
@@ -241,13 +261,17 @@ int start(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, hi
   if (st->r0 == 0.0) {
     finish(st, DG_OK);
   } else {
-    // z = M(r), rho = (r, z), p = z
+    // device scalars cleared (breakdown flag), z = M(r), rho = (r, z) into
+    // the device scalar of iteration 0, p = z
+    e = hipMemsetAsync(st->dsc, 0, 8 * sizeof(double), st->s);
+    if (e != hipSuccess) return fail(hip_fail(e, "hipMemsetAsync"));
+    DotSet ds;
+    ds.m = 1;
+    ds.a[0] = st->r;
+    ds.b[0] = st->z;
     if ((rc = precond_apply(pr, o, st->r, st->z, st->rnorm, st->r32, st->z32, st->s)) ||
-        (rc = enqueue_dots(st, 1, st->r, st->z)))
+        (rc = dots(ds, n, st->part, st->dsc + 4, st->s)))
       return fail(rc);
-    e = hipStreamSynchronize(st->s);
-    if (e != hipSuccess) return fail(hip_fail(e, "hipStreamSynchronize"));
-    st->rz = st->hdots[0];
     e = hipMemcpyAsync(st->p, st->z, n * sizeof(double), hipMemcpyDeviceToDevice, st->s);
     if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpyAsync"));
   }
@@ -255,40 +279,19 @@ int start(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, hi
   return DG_OK;
 }
 
-int wait_all(dg_solve_state **sts, const std::vector<int> &idx) {
-  for (int i : idx) DG_HIP(hipStreamSynchronize(sts[i]->s));
-  return DG_OK;
-}
 
+// One step of every active state: the pending decision (waiting for that
+// state's residual norm only), then the next iteration is enqueued.
 int batch_step(dg_solve_state **sts, int n) {
   int rc;
   std::vector<int> act;
   for (int i = 0; i < n; ++i)
     if (!sts[i]->done) act.push_back(i);
-  // phase A
-  for (int i : act)
-    if ((rc = enqueue_A(sts[i]))) return rc;
-  if ((rc = wait_all(sts, act))) return rc;
-  std::vector<int> act2;
   for (int i : act) {
-    complete_A(sts[i]);
-    if (!sts[i]->done) act2.push_back(i);
+    dg_solve_state *st = sts[i];
+    if (st->pending >= 0 && (rc = check_iter(st))) return rc;
+    if (!st->done && (rc = enqueue_iter(st))) return rc;
   }
-  // phase B
-  for (int i : act2)
-    if ((rc = enqueue_B(sts[i]))) return rc;
-  if ((rc = wait_all(sts, act2))) return rc;
-  std::vector<int> act3;
-  for (int i : act2) {
-    complete_B(sts[i]);
-    if (!sts[i]->done) act3.push_back(i);
-  }
-  // phase C
-  for (int i : act3)
-    if ((rc = enqueue_C(sts[i]))) return rc;
-  if ((rc = wait_all(sts, act3))) return rc;
-  for (int i : act3)
-    if ((rc = complete_C(sts[i]))) return rc;
   // results of the requests that finished in this step
   for (int i : act)
     if (sts[i]->done && !sts[i]->finalized && (rc = finalize(sts[i]))) return rc;

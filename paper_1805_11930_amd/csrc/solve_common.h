@@ -11,6 +11,9 @@ namespace dgmg {
 int alloc_tmp(dg_problem *pr, int prec, int k, void **out);
 int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, double rnorm, float *r32,
                   float *z32, hipStream_t s);
+// the same with rr = ||r||_2^2 read from device memory for the FP32 scaling
+int precond_apply_dev(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, const double *rr_dev,
+                      float *r32, float *z32, hipStream_t s);
 
 // Device allocations owned by one solve; freed together.
 struct DevBuf {

@@ -24,6 +24,13 @@ int axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t
 int sub(int64_t n, const double *x, const double *y, double *z, hipStream_t s);
 int cg_update(int64_t n, double a, const double *p, const double *q, double *x, const double *r_in, double *r_out,
               hipStream_t s);
+// outer-iteration kernels with device scalars (no host round trip)
+int cg_update_dev(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
+                  const double *r_in, double *r_out, double *flag, hipStream_t s);
+int beta_update(int64_t n, const double *zr, const double *zro, const double *rz_old, double *rz_new, bool flex,
+                const double *z, double *p, hipStream_t s);
+int cast_d2f_dev(int64_t n, const double *rr, const double *x, float *y, hipStream_t s);
+int cast_f2d_dev(int64_t n, const double *rr, const float *x, double *y, hipStream_t s);
 int cast_d2f(int64_t n, double sc, const double *x, float *y, hipStream_t s);
 int cast_f2d(int64_t n, double sc, const float *x, double *y, hipStream_t s);
 

@@ -94,6 +94,46 @@ __global__ void k_cast_scale(int64_t n, double s, const S *__restrict__ x, D *__
   if (i < n) y[i] = (D)(s * (double)x[i]);
 }
 
+// Outer-iteration kernels with their scalars in device memory, so that an
+// iteration is enqueued without waiting for the host.
+// x += a p ; r_out = r_in - a q with a = rz / pq; a breakdown (pq <= 0 or a
+// not finite) leaves x and r unchanged and sets *flag = 1.
+__global__ void k_cg_update_dev(int64_t n, const double *__restrict__ rz, const double *__restrict__ pq,
+                                const double *__restrict__ p, const double *__restrict__ q, double *__restrict__ x,
+                                const double *r_in, double *r_out, double *__restrict__ flag) {
+  const double d = *pq;
+  double a = *rz / d;
+  const bool bad = !(d > 0.0) || !isfinite(a);
+  if (bad) a = 0.0;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    x[i] += a * p[i];
+    r_out[i] = r_in[i] - a * q[i];
+  }
+  if (bad && i == 0) *flag = 1.0;
+}
+// p = z + beta p with beta = (zr - zro) / rz_old (flexible CG) or
+// zr / rz_old; thread 0 stores rz_new = zr (rz_new is not rz_old)
+__global__ void k_beta_update(int64_t n, const double *__restrict__ zr, const double *__restrict__ zro,
+                              const double *__restrict__ rz_old, double *__restrict__ rz_new, int flex,
+                              const double *__restrict__ z, double *__restrict__ p) {
+  const double b = flex ? (*zr - *zro) / *rz_old : *zr / *rz_old;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 1.0 * z[i] + b * p[i];
+  if (i == 0) *rz_new = *zr;
+}
+// y = s x with s = 1 / sqrt(rr) (INV = false) or 1 / (1 / sqrt(rr)) (the
+// inverse of the same rounded factor), rr read from device memory; s = 1
+// when rr is not positive
+template <typename S, typename D, bool INV>
+__global__ void k_cast_dscale(int64_t n, const double *__restrict__ rr, const S *__restrict__ x, D *__restrict__ y) {
+  const double r2 = *rr;
+  double s = r2 > 0.0 ? 1.0 / sqrt(r2) : 1.0;
+  if (INV) s = 1.0 / s;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (D)(s * (double)x[i]);
+}
+
 static inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 int axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
@@ -109,6 +149,28 @@ int sub(int64_t n, const double *x, const double *y, double *z, hipStream_t s) {
 int cg_update(int64_t n, double a, const double *p, const double *q, double *x, const double *r_in, double *r_out,
               hipStream_t s) {
   hipLaunchKernelGGL(k_cg_update, grid1(n), dim3(256), 0, s, n, a, p, q, x, r_in, r_out);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int cg_update_dev(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
+                  const double *r_in, double *r_out, double *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update_dev, grid1(n), dim3(256), 0, s, n, rz, pq, p, q, x, r_in, r_out, flag);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int beta_update(int64_t n, const double *zr, const double *zro, const double *rz_old, double *rz_new, bool flex,
+                const double *z, double *p, hipStream_t s) {
+  hipLaunchKernelGGL(k_beta_update, grid1(n), dim3(256), 0, s, n, zr, zro, rz_old, rz_new, flex ? 1 : 0, z, p);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int cast_d2f_dev(int64_t n, const double *rr, const double *x, float *y, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast_dscale<double, float, false>), grid1(n), dim3(256), 0, s, n, rr, x, y);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int cast_f2d_dev(int64_t n, const double *rr, const float *x, double *y, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast_dscale<float, double, true>), grid1(n), dim3(256), 0, s, n, rr, x, y);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

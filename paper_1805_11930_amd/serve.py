@@ -4,9 +4,10 @@ Requests (a problem description and a right-hand side) arrive over time.
 The loop admits waiting requests, first come first served, as long as the
 device bytes they need (dg_footprint plus their f and u vectors) fit in
 the HBM budget and a slot is free; it then advances every active solve by
-one outer iteration with one dg_batch_step call (their kernels overlap on
-the device, each on its own stream), retires finished solves (freeing
-their memory) and admits again.  A request whose footprint exceeds the
+one dg_batch_step call (the decision of its iteration in flight, then the
+next iteration enqueued; the kernels of all solves overlap on the device,
+each on its own stream), retires finished solves (freeing their memory)
+and admits again.  A request whose footprint exceeds the
 whole budget is rejected (DG_ENOMEM).  All numerical work runs in the HIP
 library; this module only schedules.
 """
