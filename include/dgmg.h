@@ -178,7 +178,9 @@ typedef struct {
                                cycle is symmetric for a symmetric A        */
   int coarse_space;         /* DG_COARSE_P0, DG_COARSE_Q1 or DG_COARSE_AUTO */
   int coarse_cycles;        /* V-cycles of the coarse solver (0 or 1: one)  */
-  int coarse_smooth;        /* Jacobi sweeps per level (0: 2), 0..64        */
+  int coarse_smooth;        /* Jacobi sweeps per level, 0..64; 0 (default):
+                               2, or 6 when some cell's K_kk / h_k^2 differ
+                               by more than a factor 4 between axes      */
   double coarse_omega;      /* Jacobi damping on the coarse levels (<= 0: 2/3) */
   int graph;                /* 1: replay the coarse solve from a HIP graph
                                (captured on first use per option set, kernel
@@ -333,7 +335,7 @@ int dg_footprint(const dg_problem_desc *desc, const dg_solve_opts *opts, size_t 
 /* smoother: n_sweeps 1, omega 0.8, eps 1e-2 (the paper's choice),
  *   max_inner (p+1)^3, inner CG, restart 12;
  * V-cycle: n_pre = n_post = 1, coarse_space AUTO, coarse_cycles 1,
- *   coarse_smooth 4, coarse_omega 2/3, graph 1;
+ *   coarse_smooth 0 (2 or 6 by anisotropy), coarse_omega 2/3, graph 1;
  * solve: FCG, restart 30, rtol 1e-8, maxit 500, MG preconditioner in FP32. */
 void dg_default_smooth_opts(dg_smooth_opts *o);
 void dg_default_mg_opts(dg_mg_opts *o);

@@ -356,7 +356,9 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
   // residual and restriction R = P^T
   using LP = LevelPtr<T>;
   CoarseLevel &L0 = H.levels[0];
-  const int nu = o->coarse_smooth > 0 ? o->coarse_smooth : 2;
+  // coarse Jacobi sweeps per level: as given, or 2 for nearly isotropic
+  // coefficients and 6 when K_kk / h_k^2 differ by more than 4 between axes
+  const int nu = o->coarse_smooth > 0 ? o->coarse_smooth : (pr->aniso > 4.0 ? 6 : 2);
   const T w = (T)(o->coarse_omega > 0 ? o->coarse_omega : 2.0 / 3.0);
   bool x_init = false;
   if (kind == COARSE_Q1) {
@@ -419,7 +421,7 @@ void dg_default_mg_opts(dg_mg_opts *o) {
   dg_default_smooth_opts(&o->smooth);
   o->coarse_space = DG_COARSE_AUTO;
   o->coarse_cycles = 1;
-  o->coarse_smooth = 4;
+  o->coarse_smooth = 0;
   o->coarse_omega = 2.0 / 3.0;
   o->graph = 1;
 }

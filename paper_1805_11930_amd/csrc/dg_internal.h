@@ -188,6 +188,9 @@ struct dg_problem {
   int device = 0;
   // host copies of the coefficients (for building coarse spaces)
   std::vector<double> hK, hc;
+  // largest ratio over cells of max_k / min_k of K_kk / h_k^2 (the
+  // anisotropy that point smoothers on the coarse levels have to overcome)
+  double aniso = 1.0;
   // coarse hierarchies: P0 (built with the problem) and Q1 (on first use)
   dgmg::Hierarchy p0h, q1h;
   void *corner_buf[2] = {nullptr, nullptr};  // [ncell][8] Q1 corner sums per precision

@@ -495,6 +495,15 @@ int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
   }
   g.K = pr->dK;
   g.c = pr->dc;
+  for (int64_t c = 0; c < ncell; ++c) {
+    double lo = 0.0, hi = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double a = K[3 * c + k] * g.ih[k] * g.ih[k];
+      lo = k == 0 ? a : std::min(lo, a);
+      hi = k == 0 ? a : std::max(hi, a);
+    }
+    pr->aniso = std::max(pr->aniso, hi / lo);
+  }
   pr->hK.swap(K);
   pr->hc.swap(cc);
   if (!rc) rc = ensure_hierarchy(pr, COARSE_P0);
