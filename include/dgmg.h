@@ -53,7 +53,7 @@ extern "C" {
 #define DG_EDEVICE (-3)  /* HIP runtime error                                */
 #define DG_EBREAKDOWN (-4) /* NaN/Inf or CG breakdown (p^T A p <= 0)         */
 
-#define DG_MAX_P 4       /* polynomial degrees 1..DG_MAX_P are compiled      */
+#define DG_MAX_P 5       /* polynomial degrees 1..DG_MAX_P are compiled      */
 
 enum { DG_FP64 = 0, DG_FP32 = 1 };
 enum { DG_BC_DIRICHLET = 0, DG_BC_NEUMANN = 1 };

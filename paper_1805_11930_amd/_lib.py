@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libdgmg.so")
 
 DG_OK, DG_ENOCONV, DG_EAGAIN = 0, 1, 2
 DG_EINVAL, DG_ENOMEM, DG_EDEVICE, DG_EBREAKDOWN = -1, -2, -3, -4
-DG_MAX_P = 4
+DG_MAX_P = 5
 DG_FP64, DG_FP32 = 0, 1
 DG_BC_DIRICHLET, DG_BC_NEUMANN = 0, 1
 DG_INNER_CG, DG_INNER_GMRES, DG_INNER_FDM = 0, 1, 2

@@ -477,6 +477,7 @@ static int dispatch_apply(const dg_problem *pr, const void *u, void *v, hipStrea
     case 2: return launch_apply_t<2, T>(pr, u, v, s, nb);
     case 3: return launch_apply_t<3, T>(pr, u, v, s, nb);
     case 4: return launch_apply_t<4, T>(pr, u, v, s, nb);
+    case 5: return launch_apply_t<5, T>(pr, u, v, s, nb);
   }
   set_error("unsupported degree");
   return DG_EINVAL;
@@ -504,6 +505,7 @@ int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, cons
     case 2: return d ? launch_res_t<2, double>(pr, u, r, rh, s, kind) : launch_res_t<2, float>(pr, u, r, rh, s, kind);
     case 3: return d ? launch_res_t<3, double>(pr, u, r, rh, s, kind) : launch_res_t<3, float>(pr, u, r, rh, s, kind);
     case 4: return d ? launch_res_t<4, double>(pr, u, r, rh, s, kind) : launch_res_t<4, float>(pr, u, r, rh, s, kind);
+    case 5: return d ? launch_res_t<5, double>(pr, u, r, rh, s, kind) : launch_res_t<5, float>(pr, u, r, rh, s, kind);
   }
   set_error("unsupported degree");
   return DG_EINVAL;
@@ -533,6 +535,7 @@ int launch_block_diag(const dg_problem *pr, int prec, void *diag, hipStream_t s)
     case 2: return prec == DG_FP64 ? launch_diag_t<2, double>(pr, diag, s) : launch_diag_t<2, float>(pr, diag, s);
     case 3: return prec == DG_FP64 ? launch_diag_t<3, double>(pr, diag, s) : launch_diag_t<3, float>(pr, diag, s);
     case 4: return prec == DG_FP64 ? launch_diag_t<4, double>(pr, diag, s) : launch_diag_t<4, float>(pr, diag, s);
+    case 5: return prec == DG_FP64 ? launch_diag_t<5, double>(pr, diag, s) : launch_diag_t<5, float>(pr, diag, s);
   }
   set_error("unsupported degree");
   return DG_EINVAL;
@@ -553,6 +556,7 @@ int launch_rhs(const dg_problem *pr, const double *fq, const double *bq, double 
     case 2: return launch_rhs_t<2>(pr, fq, bq, rhs, s);
     case 3: return launch_rhs_t<3>(pr, fq, bq, rhs, s);
     case 4: return launch_rhs_t<4>(pr, fq, bq, rhs, s);
+    case 5: return launch_rhs_t<5>(pr, fq, bq, rhs, s);
   }
   set_error("unsupported degree");
   return DG_EINVAL;

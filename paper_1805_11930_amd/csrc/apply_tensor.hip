@@ -354,6 +354,7 @@ int launch_apply_tensor(const dg_problem *pr, int prec, const void *u, void *v, 
     case 2: return d ? launch_t<2, double>(pr, u, v, s) : launch_t<2, float>(pr, u, v, s);
     case 3: return d ? launch_t<3, double>(pr, u, v, s) : launch_t<3, float>(pr, u, v, s);
     case 4: return d ? launch_t<4, double>(pr, u, v, s) : launch_t<4, float>(pr, u, v, s);
+    case 5: return d ? launch_t<5, double>(pr, u, v, s) : launch_t<5, float>(pr, u, v, s);
   }
   set_error("unsupported degree");
   return DG_EINVAL;

@@ -371,6 +371,7 @@ int q1_assemble(const dg_problem *pr, double *A, hipStream_t s) {
     case 2: hipLaunchKernelGGL((k_q1_assemble<2>), g, b, 0, s, pr->geo, A); break;
     case 3: hipLaunchKernelGGL((k_q1_assemble<3>), g, b, 0, s, pr->geo, A); break;
     case 4: hipLaunchKernelGGL((k_q1_assemble<4>), g, b, 0, s, pr->geo, A); break;
+    case 5: hipLaunchKernelGGL((k_q1_assemble<5>), g, b, 0, s, pr->geo, A); break;
     default: set_error("unsupported degree"); return DG_EINVAL;
   }
   DG_HIP(hipGetLastError());
@@ -433,6 +434,7 @@ int q1_prolong_add(int p, int nx, int ny, int nz, const T *xv, T *u, hipStream_t
     case 2: hipLaunchKernelGGL((k_q1_prolong_add<3, T>), g, dim3(256), 0, s, nx, ny, nz, xv, u); break;
     case 3: hipLaunchKernelGGL((k_q1_prolong_add<4, T>), g, dim3(256), 0, s, nx, ny, nz, xv, u); break;
     case 4: hipLaunchKernelGGL((k_q1_prolong_add<5, T>), g, dim3(256), 0, s, nx, ny, nz, xv, u); break;
+    case 5: hipLaunchKernelGGL((k_q1_prolong_add<6, T>), g, dim3(256), 0, s, nx, ny, nz, xv, u); break;
     default: set_error("q1_prolong_add: unsupported degree"); return DG_EINVAL;
   }
   DG_HIP(hipGetLastError());

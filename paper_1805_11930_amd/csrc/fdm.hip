@@ -148,6 +148,7 @@ int ensure_fdm(dg_problem *pr, int prec) {
       case 2: rc = launch_build<2>(pr, f64, 0); break;
       case 3: rc = launch_build<3>(pr, f64, 0); break;
       case 4: rc = launch_build<4>(pr, f64, 0); break;
+      case 5: rc = launch_build<5>(pr, f64, 0); break;
       default: set_error("unsupported degree"); return DG_EINVAL;
     }
     if (rc) return rc;

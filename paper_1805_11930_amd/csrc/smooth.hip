@@ -40,7 +40,7 @@ template <int N>
 struct SmoothShape {
   static constexpr int N2 = N * N;
   static constexpr int N3 = N * N * N;
-  static constexpr int L = N2 <= 4 ? 4 : (N2 <= 16 ? 16 : 32);
+  static constexpr int L = N2 <= 4 ? 4 : (N2 <= 16 ? 16 : (N2 <= 32 ? 32 : 64));
   static constexpr int CPW = kSmoothThreads / L;
 };
 
@@ -74,23 +74,25 @@ __device__ inline double swz_xor16(double v) {
   return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// Sum over the L lanes (L = 4, 16 or 32, aligned) of a cell; every lane of
-// the cell receives the same bits.  Each step adds the value of a partner
-// lane whose group is disjoint and of equal size: within quads (partner
-// lane xor 1, then xor 2), then the mirrored half-row (lane 7 - i of each
-// 8) and row (lane 15 - i of each 16) by DPP, then lane xor 16.  Both
+// Sum over the L lanes (L = 4, 16, 32 or 64, aligned) of a cell; every lane
+// of the cell receives the same bits.  Each step adds the value of a
+// partner lane whose group is disjoint and of equal size: within quads
+// (partner lane xor 1, then xor 2), then the mirrored half-row (lane 7 - i
+// of each 8) and row (lane 15 - i of each 16) by DPP, then lane xor 16 and
+// lane xor 32.  Both
 // partners of a step add the same two numbers, and addition commutes, so
 // the bits agree across the cell.
 template <int L, typename T>
 __device__ inline T cell_sum(T v) {
-  static_assert(L == 4 || L == 16 || L == 32, "cell lane groups are 4, 16 or 32 lanes");
+  static_assert(L == 4 || L == 16 || L == 32 || L == 64, "cell lane groups are 4, 16, 32 or 64 lanes");
   v += dpp_perm<0xB1>(v);  // quad_perm [1, 0, 3, 2]
   v += dpp_perm<0x4E>(v);  // quad_perm [2, 3, 0, 1]
   if constexpr (L >= 16) {
     v += dpp_perm<0x141>(v);  // row_half_mirror
     v += dpp_perm<0x140>(v);  // row_mirror
   }
-  if constexpr (L == 32) v += swz_xor16(v);
+  if constexpr (L >= 32) v += swz_xor16(v);
+  if constexpr (L == 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
@@ -820,6 +822,8 @@ int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin
                      : launch_smooth_t<3, float>(pr, f, uin, uout, a, iters, s);
     case 4: return d ? launch_smooth_t<4, double>(pr, f, uin, uout, a, iters, s)
                      : launch_smooth_t<4, float>(pr, f, uin, uout, a, iters, s);
+    case 5: return d ? launch_smooth_t<5, double>(pr, f, uin, uout, a, iters, s)
+                     : launch_smooth_t<5, float>(pr, f, uin, uout, a, iters, s);
   }
   set_error("unsupported degree");
   return DG_EINVAL;

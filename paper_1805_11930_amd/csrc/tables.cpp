@@ -28,6 +28,7 @@ void build_tables(int n, Tables1D &t) {
     case 3: copy_tab<3>(t); break;
     case 4: copy_tab<4>(t); break;
     case 5: copy_tab<5>(t); break;
+    case 6: copy_tab<6>(t); break;
     default: break;
   }
 }
