@@ -12,8 +12,10 @@
 // three directions are summed in an LDS accumulator.  The workgroup also
 // stages one cell on either side of its range, so every x-neighbour line is
 // in LDS; the y- and z-neighbour lines are read from global memory (L2 /
-// MALL hits) at the start, together with the staging loads, and reduced to
-// their four face traces at once.
+// MALL hits): the y lines at the start, together with the staging loads,
+// and reduced to their face traces at once; the z lines after the staging
+// barrier, so that their latency hides behind the x- and y-line work.  For
+// b = 0 the line operator runs in its even-odd form (line_apply_eo).
 //
 // XCD-aware order: consecutive workgroup ids are spread round-robin over
 // the eight XCDs, so the logical block index is remapped to give every XCD
@@ -105,6 +107,33 @@ __device__ inline void neighbour_lines(const Geo &g, const T *__restrict__ u, in
   for (int i = 0; i < N; ++i) {
     yl[i] = pyl[line_pos<N>(1, i, a, b)];
     yr[i] = pyr[line_pos<N>(1, i, a, b)];
+    zl[i] = pzl[line_pos<N>(2, i, a, b)];
+    zr[i] = pzr[line_pos<N>(2, i, a, b)];
+  }
+}
+
+template <int N, typename T>
+__device__ inline void neighbour_lines_y(const Geo &g, const T *__restrict__ u, int c, const int (&ijk)[3], int a,
+                                         int b, T (&yl)[N], T (&yr)[N]) {
+  constexpr int N3 = N * N * N;
+  const int sy = g.nx;
+  const T *pyl = u + (size_t)(ijk[1] > 0 ? c - sy : c) * N3;
+  const T *pyr = u + (size_t)(ijk[1] < g.ny - 1 ? c + sy : c) * N3;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    yl[i] = pyl[line_pos<N>(1, i, a, b)];
+    yr[i] = pyr[line_pos<N>(1, i, a, b)];
+  }
+}
+template <int N, typename T>
+__device__ inline void neighbour_lines_z(const Geo &g, const T *__restrict__ u, int c, const int (&ijk)[3], int a,
+                                         int b, T (&zl)[N], T (&zr)[N]) {
+  constexpr int N3 = N * N * N;
+  const int sz = g.nx * g.ny;
+  const T *pzl = u + (size_t)(ijk[2] > 0 ? c - sz : c) * N3;
+  const T *pzr = u + (size_t)(ijk[2] < g.nz - 1 ? c + sz : c) * N3;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
     zl[i] = pzl[line_pos<N>(2, i, a, b)];
     zr[i] = pzr[line_pos<N>(2, i, a, b)];
   }
@@ -225,7 +254,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
   VT pre[St::NVEC];
   const int shift = stage_load<N, T, NB>(g, u, c0, tid, pre);
   T yl[N], yr[N], zl[N], zr[N];
-  if (NB && active) neighbour_lines<N, T>(g, u, c, ijk, a, b, yl, yr, zl, zr);
+  if (NB && active) neighbour_lines_y<N, T>(g, u, c, ijk, a, b, yl, yr);
   // face coefficients: lane ln < 3 of each cell handles axis ln (neighbour
   // indices clamped to the cell itself, so that no load waits for another)
   double kd = 0.0, km = 0.0, kp = 0.0;
@@ -243,10 +272,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
   const T stan = tb.w[a] * tb.w[b];
 
   T tr[2][4] = {{T(0), T(0), T(0), T(0)}, {T(0), T(0), T(0), T(0)}};
-  if (NB) {
-    face_traces<N, T>(tb, yl, yr, tr[0]);
-    face_traces<N, T>(tb, zl, zr, tr[1]);
-  }
+  if (NB) face_traces<N, T>(tb, yl, yr, tr[0]);
 #pragma unroll
   for (int j = 0; j < St::NVEC; ++j) reinterpret_cast<VT *>(us)[j * kApplyThreads + tid] = pre[j];
   if (coef_lane) {
@@ -267,6 +293,8 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
         fcs[cl][2] = axis_coef_from<T>(g, 2, ijk, kd, km, kp);
     }
   }
+  // the z neighbour lines are loaded now, behind the x- and y-line work
+  if (NB && active) neighbour_lines_z<N, T>(g, u, c, ijk, a, b, zl, zr);
   __syncthreads();
 
   const bool hasb = g.has_b != 0;
@@ -289,16 +317,23 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
             hi[i] = own[line_pos<N>(0, i, a, b) + N3];
           }
           face_traces<N, T>(tb, lo, hi, t);
-        } else {
+        } else if (k == 1) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) t[q] = tr[k - 1][q];
+          for (int q = 0; q < 4; ++q) t[q] = tr[0][q];
+        } else {
+          face_traces<N, T>(tb, zl, zr, t);
         }
         if (ijk[k] == 0) t[0] = t[1] = T(0);
         if (ijk[k] == nn[k] - 1) t[2] = t[3] = T(0);
       }
       LineConv<T> lc = {T(0), T(0), T(0), T(0)};
       if (hasb) lc = make_line_conv<T, N>(g, tb, k, ijk, a, b);
-      line_apply<T, N>(tb, fcs[cl][k], stan, vol, k == 0 ? cre : T(0), hasb, lc, ul, t[0], t[1], t[2], t[3], out);
+      if (FLD || hasb)
+        line_apply<T, N>(tb, fcs[cl][k], stan, vol, k == 0 ? cre : T(0), hasb, lc, ul, t[0], t[1], t[2], t[3], out);
+      else if (k == 0 && g.has_c)
+        line_apply_eo<T, N, true>(fcs[cl][k], stan, vol, cre, ul, t[0], t[1], t[2], t[3], out);
+      else
+        line_apply_eo<T, N, false>(fcs[cl][k], stan, vol, T(0), ul, t[0], t[1], t[2], t[3], out);
       if constexpr (FLD) {
         // K_kk at the line's nodes; c at the nodes of the x-line
         T pk[N];

@@ -58,6 +58,49 @@ constexpr DevTab<T, N> make_ctab() {
   return d;
 }
 
+// Even-odd split of the 1-D tables.  The Gauss nodes are symmetric about
+// the cell centre, so S is centro-symmetric (S[i][l] = S[N-1-i][N-1-l]) and
+// e1[j] = e0[N-1-j], d1[j] = -d0[N-1-j].  With M = N / 2, the even part
+// ue[l] = u[l] + u[N-1-l] (l < M; ue[M] = u[M] for odd N) and the odd part
+// uo[l] = u[l] - u[N-1-l] of a line, (S u)[i] = ve[i] + vo[i] and
+// (S u)[N-1-i] = ve[i] - vo[i] with ve = Se ue, vo = So uo (and the middle
+// entry Sm . ue for odd N); the end values follow the same pattern.  Entries
+// carry the factor 1/2 of the back transform.
+template <typename T, int N>
+struct EoTab {
+  static constexpr int M = N / 2, O = N % 2, ME = M + O;
+  T Se[M][ME] = {}, So[M][M] = {}, Sm[ME] = {};
+  T ee[ME] = {}, eo[M] = {}, de[ME] = {}, dd[M] = {}, wh[ME] = {};
+};
+
+template <typename T, int N>
+constexpr EoTab<T, N> make_eotab() {
+  constexpr ct::Tab<N> t = ct::make_tab<N>();
+  using E = EoTab<T, N>;
+  constexpr int M = E::M;
+  E e;
+  for (int i = 0; i < M; ++i) {
+    for (int l = 0; l < M; ++l) {
+      e.Se[i][l] = (T)(0.5 * (t.S[i][l] + t.S[i][N - 1 - l]));
+      e.So[i][l] = (T)(0.5 * (t.S[i][l] - t.S[i][N - 1 - l]));
+    }
+    if (E::O) e.Se[i][M] = (T)t.S[i][M];
+    e.ee[i] = (T)(0.5 * (t.e0[i] + t.e0[N - 1 - i]));
+    e.eo[i] = (T)(0.5 * (t.e0[i] - t.e0[N - 1 - i]));
+    e.de[i] = (T)(0.5 * (t.d0[i] + t.d0[N - 1 - i]));
+    e.dd[i] = (T)(0.5 * (t.d0[i] - t.d0[N - 1 - i]));
+    e.wh[i] = (T)(0.5 * t.w[i]);
+  }
+  if (E::O) {
+    for (int l = 0; l < M; ++l) e.Sm[l] = (T)t.S[M][l];
+    e.Sm[M] = (T)t.S[M][M];
+    e.ee[M] = (T)t.e0[M];
+    e.de[M] = (T)t.d0[M];
+    e.wh[M] = (T)t.w[M];
+  }
+  return e;
+}
+
 // Exact division of 0 <= n < 2^31 by a fixed divisor d >= 1 with one
 // multiply and one shift (Granlund and Montgomery, "Division by invariant
 // integers using multiplication", 1994): m = ceil(2^s / d) with

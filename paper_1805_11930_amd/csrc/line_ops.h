@@ -246,6 +246,81 @@ __host__ __device__ inline void line_apply(const DevTab<T, N> &tb, const AxisCoe
   }
 }
 
+// line_apply for b = 0 in the even-odd form (EoTab): the same operator with
+// about half the multiply-adds and table values.  REACT: add the reaction
+// term cre (w_i u_i) (only the x line of a cell carries it).
+template <typename T, int N, bool REACT>
+__host__ __device__ inline void line_apply_eo(const AxisCoef<T> &f, T stan, T vol, T cre, const T (&u)[N], T tLu,
+                                              T tLd, T tRu, T tRd, T (&v)[N]) {
+  constexpr EoTab<T, N> et = make_eotab<T, N>();
+  constexpr int M = N / 2, O = N % 2, ME = M + O;
+  T ue[ME], uo[M];
+#pragma unroll
+  for (int l = 0; l < M; ++l) {
+    ue[l] = u[l] + u[N - 1 - l];
+    uo[l] = u[l] - u[N - 1 - l];
+  }
+  if constexpr (O) ue[M] = u[M];
+  // own traces: e0.u = Pe + Po, e1.u = Pe - Po, d0.u = Qe + Qo, d1.u = Qo - Qe
+  T Pe = T(0), Po = T(0), Qe = T(0), Qo = T(0);
+#pragma unroll
+  for (int l = 0; l < ME; ++l) {
+    Pe += et.ee[l] * ue[l];
+    Qe += et.de[l] * ue[l];
+  }
+#pragma unroll
+  for (int l = 0; l < M; ++l) {
+    Po += et.eo[l] * uo[l];
+    Qo += et.dd[l] * uo[l];
+  }
+  const T uP = Pe + Po, uM = Pe - Po, gP = Qe + Qo, gM = Qo - Qe;
+  const T ih = f.ih;
+  const T WF = stan * vol * ih;
+  const T alpha = WF * f.d * ih;
+  // face terms as v += s0 e0 + t0 d0 (face xi = 0) + s1 e1 + t1 d1 (xi = 1)
+  const T jR = uM - tRu;
+  const T sR = WF * (f.gR * jR - f.kR * (gM + tRd) * ih);
+  const T tR = -WF * f.kR * jR * ih;
+  const T jL = tLu - uP;
+  const T sL = -WF * (f.gL * jL - f.kL * (tLd + gP) * ih);
+  const T tL = -WF * f.kL * jL * ih;
+  const T s1 = (f.fl & 2) ? sR : T(0), t1 = (f.fl & 2) ? tR : T(0);
+  const T s0 = (f.fl & 1) ? sL : T(0), t0 = (f.fl & 1) ? tL : T(0);
+  const T se = s0 + s1, so = s0 - s1, te = t0 - t1, to = t0 + t1;
+  T ve[ME], vo[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T ae = T(0), ao = T(0);
+#pragma unroll
+    for (int l = 0; l < ME; ++l) ae += et.Se[i][l] * ue[l];
+#pragma unroll
+    for (int l = 0; l < M; ++l) ao += et.So[i][l] * uo[l];
+    ve[i] = alpha * ae + se * et.ee[i] + te * et.de[i];
+    vo[i] = alpha * ao + so * et.eo[i] + to * et.dd[i];
+  }
+  if constexpr (O) {
+    T am = T(0);
+#pragma unroll
+    for (int l = 0; l < ME; ++l) am += et.Sm[l] * ue[l];
+    ve[M] = alpha * am + se * et.ee[M] + te * et.de[M];
+  }
+  if constexpr (REACT) {
+    const T rc = cre * vol * stan;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      ve[i] += rc * et.wh[i] * ue[i];
+      vo[i] += rc * et.wh[i] * uo[i];
+    }
+    if constexpr (O) ve[M] += rc * et.wh[M] * ue[M];
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    v[i] = ve[i] + vo[i];
+    v[N - 1 - i] = ve[i] - vo[i];
+  }
+  if constexpr (O) v[M] = ve[M];
+}
+
 // Diagonal entry i of the line operator without neighbour couplings
 // (line_apply with u = unit vector e_i and zero neighbour traces).
 template <typename T, int N>

@@ -374,8 +374,13 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
             tRd += tb.d0[i] * x;
           }
         }
-        line_apply<T, N>(tb, cl.f[k], cl.stan, cl.vol, k == 0 ? cl.cre : T(0), hasb, cl.lc[k], line, tLu, tLd, tRu,
-                         tRd, out);
+        if constexpr (HASB)
+          line_apply<T, N>(tb, cl.f[k], cl.stan, cl.vol, k == 0 ? cl.cre : T(0), hasb, cl.lc[k], line, tLu, tLd, tRu,
+                           tRd, out);
+        else if (k == 0 && g.has_c)
+          line_apply_eo<T, N, true>(cl.f[k], cl.stan, cl.vol, cl.cre, line, tLu, tLd, tRu, tRd, out);
+        else
+          line_apply_eo<T, N, false>(cl.f[k], cl.stan, cl.vol, T(0), line, tLu, tLd, tRu, tRd, out);
         if (k == 0) {
 #pragma unroll
           for (int i = 0; i < N; ++i) ax[i] = out[i];
