@@ -34,6 +34,22 @@ __device__ inline W1 interp1(int i, int vf, int vc) {
   return {i >> 1, true};
 }
 
+// (ix, iy, iz) of index i on an nx-by-ny-by-* grid, x fastest; 32-bit
+// divisions below 2^31 (every realistic level), 64-bit above.
+__device__ inline void grid_coords(int64_t i, int nx, int ny, int &ix, int &iy, int &iz) {
+  if (i < 0x7fffffff) {
+    const unsigned u = (unsigned)i, a = (unsigned)nx, b = (unsigned)ny;
+    const unsigned q = u / a;
+    ix = (int)(u - q * a);
+    iy = (int)(q % b);
+    iz = (int)(q / b);
+  } else {
+    ix = (int)(i % nx);
+    iy = (int)((i / nx) % ny);
+    iz = (int)(i / ((int64_t)nx * ny));
+  }
+}
+
 // (A x)_i for the 27-point stencil.  Couplings to unknowns outside the grid
 // are exact zeros in every level's stencil (the level-0 matrix only couples
 // vertices of a common cell, and Galerkin products keep that), so the
@@ -71,7 +87,8 @@ __global__ void k_jacobi27(const T *__restrict__ A, const T *__restrict__ dinv, 
     xo[i] = wd * r[i];
     return;
   }
-  const int ix = (int)(i % vx), iy = (int)((i / vx) % vy), iz = (int)(i / ((int64_t)vx * vy));
+  int ix, iy, iz;
+  grid_coords(i, vx, vy, ix, iy, iz);
   xo[i] = xi[i] + wd * (r[i] - stencil27(A, n, xi, i, ix, iy, iz, vx, vy, vz));
 }
 
@@ -82,7 +99,8 @@ __global__ void k_residual27(const T *__restrict__ A, int vx, int vy, int vz, co
   const int64_t n = (int64_t)vx * vy * vz;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int ix = (int)(i % vx), iy = (int)((i / vx) % vy), iz = (int)(i / ((int64_t)vx * vy));
+  int ix, iy, iz;
+  grid_coords(i, vx, vy, ix, iy, iz);
   out[i] = r[i] - stencil27(A, n, x, i, ix, iy, iz, vx, vy, vz);
 }
 
@@ -96,7 +114,8 @@ __global__ void k_restrict27(int vx, int vy, int vz, const T *__restrict__ t, in
   const int64_t nc = (int64_t)cx * cy * cz;
   const int64_t J = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (J >= nc) return;
-  const int jj[3] = {(int)(J % cx), (int)((J / cx) % cy), (int)(J / ((int64_t)cx * cy))};
+  int jj[3];
+  grid_coords(J, cx, cy, jj[0], jj[1], jj[2]);
   const int vf[3] = {vx, vy, vz}, vcs[3] = {cx, cy, cz};
   // per axis: up to three fine indices and their weights towards jj
   int fi[3][3];
@@ -137,7 +156,8 @@ __global__ void k_prolong27(int vx, int vy, int vz, int cx, int cy, int cz, cons
   const int64_t n = (int64_t)vx * vy * vz;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int ii[3] = {(int)(i % vx), (int)((i / vx) % vy), (int)(i / ((int64_t)vx * vy))};
+  int ii[3];
+  grid_coords(i, vx, vy, ii[0], ii[1], ii[2]);
   const int vf[3] = {vx, vy, vz}, vcs[3] = {cx, cy, cz};
   int j[3][2];
   T w[3][2];
@@ -170,7 +190,8 @@ __global__ void k_q1_gather(int nx, int ny, int nz, const T *__restrict__ cs, T 
   const int64_t n = (int64_t)vx * vy * (nz + 1);
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const int ix = (int)(v % vx), iy = (int)((v / vx) % vy), iz = (int)(v / ((int64_t)vx * vy));
+  int ix, iy, iz;
+  grid_coords(v, vx, vy, ix, iy, iz);
   T s = T(0);
 #pragma unroll
   for (int sz = 0; sz < 2; ++sz) {
@@ -206,7 +227,8 @@ __global__ void k_q1_prolong_add(int nx, int ny, int nz, const T *__restrict__ x
   const int64_t c = g / N3;
   const int j = (int)(g - c * N3);
   const int kx = j % N, ky = (j / N) % N, kz = j / (N * N);
-  const int ix = (int)(c % nx), iy = (int)((c / nx) % ny), iz = (int)(c / ((int64_t)nx * ny));
+  int ix, iy, iz;
+  grid_coords(c, nx, ny, ix, iy, iz);
   const int vx = nx + 1, vy = ny + 1;
   const T x1 = tb.xi[kx], y1 = tb.xi[ky], z1 = tb.xi[kz];
   const T lx[2] = {T(1) - x1, x1}, ly[2] = {T(1) - y1, y1}, lz[2] = {T(1) - z1, z1};
@@ -229,7 +251,8 @@ __global__ void k_residual7(const T *__restrict__ A, int nx, int ny, int nz, con
   const int64_t n = (int64_t)nx * ny * nz;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((int64_t)nx * ny));
+  int ix, iy, iz;
+  grid_coords(i, nx, ny, ix, iy, iz);
   T s = A[i] * x[i];
   if (ix > 0) s += A[n + i] * x[i - 1];
   if (ix < nx - 1) s += A[2 * n + i] * x[i + 1];
@@ -263,7 +286,8 @@ __global__ __launch_bounds__(128) void k_q1_assemble(Geo g, double *__restrict__
   const int64_t n = (int64_t)vx * vy * (g.nz + 1);
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const int ix = (int)(v % vx), iy = (int)((v / vx) % vy), iz = (int)(v / ((int64_t)vx * vy));
+  int ix, iy, iz;
+  grid_coords(v, vx, vy, ix, iy, iz);
   double acc[27];
   for (int o = 0; o < 27; ++o) acc[o] = 0.0;
   for (int sz = 0; sz < 2; ++sz) {
@@ -298,7 +322,8 @@ __global__ __launch_bounds__(128) void k_galerkin27(const double *__restrict__ A
   const int64_t n = (int64_t)vx * vy * vz, nc = (int64_t)cx * cy * cz;
   const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
-  const int II[3] = {(int)(I % cx), (int)((I / cx) % cy), (int)(I / ((int64_t)cx * cy))};
+  int II[3];
+  grid_coords(I, cx, cy, II[0], II[1], II[2]);
   const int vf[3] = {vx, vy, vz}, vc[3] = {cx, cy, cz};
   double acc[27];
   for (int o = 0; o < 27; ++o) acc[o] = 0.0;
