@@ -276,7 +276,8 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
 #pragma unroll
   for (int j = 0; j < St::NVEC; ++j) reinterpret_cast<VT *>(us)[j * kApplyThreads + tid] = pre[j];
   if (coef_lane) {
-    // compile-time axis in each branch: the per-axis mesh data stay scalar
+    // field: a compile-time axis per branch; cell-constant coefficients: one
+    // path for the three axes (about a third of the instructions)
     if constexpr (FLD) {
       if (ln == 0)
         fcs[cl][0] = axis_coef_field<T>(g, 0, ijk);
@@ -285,12 +286,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
       else
         fcs[cl][2] = axis_coef_field<T>(g, 2, ijk);
     } else {
-      if (ln == 0)
-        fcs[cl][0] = axis_coef_from<T>(g, 0, ijk, kd, km, kp);
-      else if (ln == 1)
-        fcs[cl][1] = axis_coef_from<T>(g, 1, ijk, kd, km, kp);
-      else
-        fcs[cl][2] = axis_coef_from<T>(g, 2, ijk, kd, km, kp);
+      fcs[cl][ln] = axis_coef_lane<T>(g, ln, ijk, kd, km, kp);
     }
   }
   // the z neighbour lines are loaded now, behind the x- and y-line work

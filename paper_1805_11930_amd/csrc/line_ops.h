@@ -98,6 +98,34 @@ __host__ __device__ inline AxisCoef<T> axis_coef_from(const Geo &g, int k, const
   return axis_coef_faces<T>(g, k, ijk, d, d, dm, d, dp);
 }
 
+// axis_coef_from with the axis k a per-lane value: the per-axis mesh data
+// are selected instead of branched on, so lanes of different axes take one
+// path (same arithmetic, same results).
+template <typename T>
+__host__ __device__ inline AxisCoef<T> axis_coef_lane(const Geo &g, int k, const int (&ijk)[3], double d, double dm,
+                                                      double dp) {
+  const int ik = k == 0 ? ijk[0] : (k == 1 ? ijk[1] : ijk[2]);
+  const int nk = k == 0 ? g.nx : (k == 1 ? g.ny : g.nz);
+  const double ih = k == 0 ? g.ih[0] : (k == 1 ? g.ih[1] : g.ih[2]);
+  const bool dirL = (k == 0 ? g.bc[0] : (k == 1 ? g.bc[2] : g.bc[4])) == FACE_DIRICHLET;
+  const bool dirR = (k == 0 ? g.bc[1] : (k == 1 ? g.bc[3] : g.bc[5])) == FACE_DIRICHLET;
+  const bool inL = ik > 0, inR = ik < nk - 1;
+  const double hL = d * dm / (d + dm), hR = d * dp / (d + dp);
+  const double kL = inL ? hL : (dirL ? d : 0.0);
+  const double gL = inL ? 2.0 * g.sigma * hL * ih : (dirL ? g.sigma * d * ih : 0.0);
+  const double kR = inR ? hR : (dirR ? d : 0.0);
+  const double gR = inR ? 2.0 * g.sigma * hR * ih : (dirR ? g.sigma * d * ih : 0.0);
+  AxisCoef<T> f;
+  f.d = (T)d;
+  f.kL = (T)kL;
+  f.gL = (T)gL;
+  f.kR = (T)kR;
+  f.gR = (T)gR;
+  f.ih = (T)ih;
+  f.fl = (inL ? 5 : (dirL ? 1 : 0)) | (inR ? 10 : (dirR ? 2 : 0));
+  return f;
+}
+
 // Face coefficients of the coefficient field along axis k: K_kk = P_k(x_k)
 // is constant on a face normal to e_k and the same from both sides; the
 // volume part (d = 0 here) is added by line_volume_field.
