@@ -13,9 +13,9 @@
 // stages one cell on either side of its range, so every x-neighbour line is
 // in LDS; the y- and z-neighbour lines are read from global memory (L2 /
 // MALL hits): the y lines at the start, together with the staging loads,
-// and reduced to their face traces at once; the z lines after the staging
-// barrier, so that their latency hides behind the x- and y-line work.  For
-// b = 0 the line operator runs in its even-odd form (line_apply_eo).
+// and reduced to their face traces at once; the z lines after the x lines,
+// so that their latency hides behind the y-line work.  For b = 0 the line
+// operator runs in its even-odd form (line_apply_eo).
 //
 // XCD-aware order: consecutive workgroup ids are spread round-robin over
 // the eight XCDs, so the logical block index is remapped to give every XCD
@@ -34,6 +34,14 @@ struct ApplyShape {
   static constexpr int N2 = N * N;
   static constexpr int N3 = N * N * N;
   static constexpr int CPB = kApplyThreads / N2;
+  // waves per SIMD the register allocation is held to: five for FP64 at
+  // p = 2 and 4 (measured: p = 4 fits with a spill of three registers and
+  // runs 2 % faster than at four waves, p = 2 runs 5 % faster); otherwise
+  // what the allocation gives
+  template <typename T>
+  static constexpr int min_waves() {
+    return (sizeof(T) == 8 && (N == 3 || N == 5)) ? 5 : 1;
+  }
 };
 
 __device__ inline int xcd_block(int b, int G) {
@@ -226,7 +234,7 @@ __device__ inline void residual_epilogue(const DevTab<T, N> &tb, bool active, in
 // of taken per cell (the preconditioner's kernels use the cell-centre
 // values).
 template <int P, typename T, bool NB, int RES = 0, bool FLD = false>
-__global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restrict__ u, T *__restrict__ v,
+__global__ __launch_bounds__(kApplyThreads, ApplyShape<P + 1>::template min_waves<T>()) void k_apply(Geo g, const T *__restrict__ u, T *__restrict__ v,
                                                          const T *__restrict__ r = nullptr,
                                                          T *__restrict__ rh = nullptr) {
   constexpr int N = P + 1;
@@ -289,17 +297,21 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
       fcs[cl][ln] = axis_coef_lane<T>(g, ln, ijk, kd, km, kp);
     }
   }
-  // the z neighbour lines are loaded now, behind the x- and y-line work
-  if (NB && active) neighbour_lines_z<N, T>(g, u, c, ijk, a, b, zl, zr);
   __syncthreads();
 
   const bool hasb = g.has_b != 0;
   const T vol = (T)g.vol;
   const T *own = us + shift + (cl + H) * N3;
-  T qx[N], qz[N];
-  if (active) {
+  // The directions one after the other; their contributions meet in qs
+  // (a DOF lies on exactly one line per direction, so the writes of one
+  // direction do not collide), a barrier between directions.  Nothing but
+  // the current line is held in registers, which keeps p = 2 and 4 in FP64
+  // at five waves per SIMD.  The z neighbour lines are loaded after the x
+  // lines, behind the y-line work.
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 3; ++k) {
+    if (k == 1 && NB && active) neighbour_lines_z<N, T>(g, u, c, ijk, a, b, zl, zr);
+    if (active) {
       T ul[N], out[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) ul[i] = own[line_pos<N>(k, i, a, b)];
@@ -345,23 +357,19 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
       }
 #pragma unroll
       for (int i = 0; i < N; ++i) {
-        if (k == 0) qx[i] = out[i];
-        if (k == 1) qs[cl * N3 + line_pos<N>(1, i, a, b)] = out[i];
-        if (k == 2) qz[i] = out[i];
+        T *q = qs + cl * N3 + line_pos<N>(k, i, a, b);
+        if (k == 0)
+          *q = out[i];
+        else
+          *q += out[i];
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
-  // z contributions: each DOF lies on exactly one z-line, so no two lanes
-  // update the same entry
+  T qx[N];
   if (active) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) qs[cl * N3 + line_pos<N>(2, i, a, b)] += qz[i];
-  }
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) qx[i] += qs[cl * N3 + line_pos<N>(0, i, a, b)];
+    for (int i = 0; i < N; ++i) qx[i] = qs[cl * N3 + line_pos<N>(0, i, a, b)];
   }
   if constexpr (RES == 0) {
     if (active) {
