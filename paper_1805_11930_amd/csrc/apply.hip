@@ -34,14 +34,6 @@ struct ApplyShape {
   static constexpr int N2 = N * N;
   static constexpr int N3 = N * N * N;
   static constexpr int CPB = kApplyThreads / N2;
-  // waves per SIMD the register allocation is held to: five for FP64 at
-  // p = 2 and 4 (measured: p = 4 fits with a spill of three registers and
-  // runs 2 % faster than at four waves, p = 2 runs 5 % faster); otherwise
-  // what the allocation gives
-  template <typename T>
-  static constexpr int min_waves() {
-    return (sizeof(T) == 8 && (N == 3 || N == 5)) ? 5 : 1;
-  }
 };
 
 __device__ inline int xcd_block(int b, int G) {
@@ -229,12 +221,14 @@ __device__ inline void residual_epilogue(const DevTab<T, N> &tb, bool active, in
 // operator along x, y and z to its three lines through (a, b); the
 // contributions meet in LDS.
 //
+// HB = false: a build for b = 0 only (no advection code, fewer registers).
+//
 // FLD: the outer operator of a problem with a coefficient field: K_kk and
 // c are evaluated at the nodes (= quadrature points) of each line instead
 // of taken per cell (the preconditioner's kernels use the cell-centre
 // values).
-template <int P, typename T, bool NB, int RES = 0, bool FLD = false>
-__global__ __launch_bounds__(kApplyThreads, ApplyShape<P + 1>::template min_waves<T>()) void k_apply(Geo g, const T *__restrict__ u, T *__restrict__ v,
+template <int P, typename T, bool NB, int RES = 0, bool FLD = false, bool HB = true>
+__global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restrict__ u, T *__restrict__ v,
                                                          const T *__restrict__ r = nullptr,
                                                          T *__restrict__ rh = nullptr) {
   constexpr int N = P + 1;
@@ -299,15 +293,15 @@ __global__ __launch_bounds__(kApplyThreads, ApplyShape<P + 1>::template min_wave
   }
   __syncthreads();
 
-  const bool hasb = g.has_b != 0;
+  const bool hasb = HB && g.has_b != 0;
   const T vol = (T)g.vol;
   const T *own = us + shift + (cl + H) * N3;
   // The directions one after the other; their contributions meet in qs
   // (a DOF lies on exactly one line per direction, so the writes of one
   // direction do not collide), a barrier between directions.  Nothing but
-  // the current line is held in registers, which keeps p = 2 and 4 in FP64
-  // at five waves per SIMD.  The z neighbour lines are loaded after the x
-  // lines, behind the y-line work.
+  // the current line is held in registers: with HB = false the FP64 kernels
+  // run at five (p = 4, 5) to seven (p = 1) waves per SIMD.  The z neighbour
+  // lines are loaded after the x lines, behind the y-line work.
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     if (k == 1 && NB && active) neighbour_lines_z<N, T>(g, u, c, ijk, a, b, zl, zr);
@@ -499,9 +493,12 @@ static int launch_apply_t(const dg_problem *pr, const void *u, void *v, hipStrea
   if (nb && pr->geo.field)
     hipLaunchKernelGGL((k_apply<P, T, true, 0, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u,
                        (T *)v, (const T *)nullptr, (T *)nullptr);
-  else if (nb)
+  else if (nb && pr->geo.has_b)
     hipLaunchKernelGGL((k_apply<P, T, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u, (T *)v,
                        (const T *)nullptr, (T *)nullptr);
+  else if (nb)
+    hipLaunchKernelGGL((k_apply<P, T, true, 0, false, false>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo,
+                       (const T *)u, (T *)v, (const T *)nullptr, (T *)nullptr);
   else
     hipLaunchKernelGGL((k_apply<P, T, false>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u, (T *)v,
                        (const T *)nullptr, (T *)nullptr);
@@ -526,12 +523,19 @@ template <int P, typename T>
 static int launch_res_t(const dg_problem *pr, const void *u, const void *r, void *rh, hipStream_t s, int kind) {
   constexpr int N = P + 1;
   const int G = (int)((pr->ncell + ApplyShape<N>::CPB - 1) / ApplyShape<N>::CPB);
-  if (kind == COARSE_Q1)
+  const bool hb = pr->geo.has_b != 0;
+  if (kind == COARSE_Q1 && hb)
     hipLaunchKernelGGL((k_apply<P, T, true, 2>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u,
                        (T *)nullptr, (const T *)r, (T *)rh);
-  else
+  else if (kind == COARSE_Q1)
+    hipLaunchKernelGGL((k_apply<P, T, true, 2, false, false>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo,
+                       (const T *)u, (T *)nullptr, (const T *)r, (T *)rh);
+  else if (hb)
     hipLaunchKernelGGL((k_apply<P, T, true, 1>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u,
                        (T *)nullptr, (const T *)r, (T *)rh);
+  else
+    hipLaunchKernelGGL((k_apply<P, T, true, 1, false, false>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo,
+                       (const T *)u, (T *)nullptr, (const T *)r, (T *)rh);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
