@@ -179,8 +179,9 @@ typedef struct {
   int coarse_space;         /* DG_COARSE_P0, DG_COARSE_Q1 or DG_COARSE_AUTO */
   int coarse_cycles;        /* V-cycles of the coarse solver (0 or 1: one)  */
   int coarse_smooth;        /* Jacobi sweeps per level, 0..64; 0 (default):
-                               2, or 6 when some cell's K_kk / h_k^2 differ
-                               by more than a factor 4 between axes      */
+                               6 when some cell's K_kk / h_k^2 differ by
+                               more than a factor 4 between axes, else 4
+                               with advection (b != 0) and 2 without     */
   double coarse_omega;      /* Jacobi damping on the coarse levels (<= 0: 2/3) */
   int graph;                /* 1: replay the coarse solve from a HIP graph
                                (captured on first use per option set, kernel

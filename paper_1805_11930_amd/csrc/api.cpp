@@ -356,9 +356,10 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
   // residual and restriction R = P^T
   using LP = LevelPtr<T>;
   CoarseLevel &L0 = H.levels[0];
-  // coarse Jacobi sweeps per level: as given, or 2 for nearly isotropic
-  // coefficients and 6 when K_kk / h_k^2 differ by more than 4 between axes
-  const int nu = o->coarse_smooth > 0 ? o->coarse_smooth : (pr->aniso > 4.0 ? 6 : 2);
+  // coarse Jacobi sweeps per level: as given, or 6 when K_kk / h_k^2
+  // differ by more than 4 between axes, 4 with advection, else 2
+  const int nu =
+      o->coarse_smooth > 0 ? o->coarse_smooth : (pr->aniso > 4.0 ? 6 : (pr->geo.has_b ? 4 : 2));
   const T w = (T)(o->coarse_omega > 0 ? o->coarse_omega : 2.0 / 3.0);
   bool x_init = false;
   if (kind == COARSE_Q1) {
