@@ -110,13 +110,13 @@ int enqueue_iter(dg_solve_state *st) {
   ds.a[0] = st->p;
   ds.b[0] = st->q;
   if ((rc = dots(ds, n, st->part, st->dsc + 0, st->s))) return rc;
-  // u += alpha p, r -= alpha q (flexible: the new residual goes to the other buffer)
+  // u += alpha p, r -= alpha q (flexible: the new residual goes to the other
+  // buffer) and rr = (r, r) in the same pass
   double *r_out = st->flex ? st->rold : st->r;
-  if ((rc = cg_update_dev(n, rz_cur, st->dsc + 0, st->p, st->q, st->u, st->r, r_out, st->dsc + 6, st->s))) return rc;
+  if ((rc = cg_update_rr(n, rz_cur, st->dsc + 0, st->p, st->q, st->u, st->r, r_out, st->dsc + 6, st->part,
+                         st->dsc + 1, st->s)))
+    return rc;
   if (st->flex) std::swap(st->r, st->rold);
-  ds.a[0] = st->r;
-  ds.b[0] = st->r;
-  if ((rc = dots(ds, n, st->part, st->dsc + 1, st->s))) return rc;
   DG_HIP(hipMemcpyAsync(st->hdots + 1 + par, st->dsc + 1, sizeof(double), hipMemcpyDeviceToHost, st->s));
   DG_HIP(hipMemcpyAsync(st->hdots + 3 + par, st->dsc + 6, sizeof(double), hipMemcpyDeviceToHost, st->s));
   DG_HIP(hipEventRecord(st->err[par], st->s));

@@ -27,6 +27,10 @@ int cg_update(int64_t n, double a, const double *p, const double *q, double *x, 
 // outer-iteration kernels with device scalars (no host round trip)
 int cg_update_dev(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
                   const double *r_in, double *r_out, double *flag, hipStream_t s);
+// cg_update_dev and *rr = r_out . r_out (same sum as dots) in one pass over
+// the vectors; part: kDotBlocks doubles of scratch
+int cg_update_rr(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
+                 const double *r_in, double *r_out, double *flag, double *part, double *rr, hipStream_t s);
 int beta_update(int64_t n, const double *zr, const double *zro, const double *rz_old, double *rz_new, bool flex,
                 const double *z, double *p, hipStream_t s);
 int cast_d2f_dev(int64_t n, const double *rr, const double *x, float *y, hipStream_t s);

@@ -112,6 +112,39 @@ __global__ void k_cg_update_dev(int64_t n, const double *__restrict__ rz, const 
   }
   if (bad && i == 0) *flag = 1.0;
 }
+// k_cg_update_dev fused with the partial sums of r_out . r_out (grid-stride
+// over the fixed grid of k_dots_partial, same order; k_dots_final adds them)
+__global__ __launch_bounds__(kRedThreads) void k_cg_update_rr(int64_t n, const double *__restrict__ rz,
+                                                              const double *__restrict__ pq,
+                                                              const double *__restrict__ p,
+                                                              const double *__restrict__ q, double *__restrict__ x,
+                                                              const double *r_in, double *r_out,
+                                                              double *__restrict__ flag, double *__restrict__ part) {
+  __shared__ double sh[kRedThreads / 64];
+  const double d = *pq;
+  double a = *rz / d;
+  const bool bad = !(d > 0.0) || !isfinite(a);
+  if (bad) a = 0.0;
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kRedThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
+    x[i] += a * p[i];
+    const double ro = r_in[i] - a * q[i];
+    r_out[i] = ro;
+    acc += ro * ro;
+  }
+  if (bad && blockIdx.x == 0 && threadIdx.x == 0) *flag = 1.0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+  if (lane == 0) sh[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
+    part[blockIdx.x] = s;
+  }
+}
+
 // p = z + beta p with beta = (zr - zro) / rz_old (flexible CG) or
 // zr / rz_old; thread 0 stores rz_new = zr (rz_new is not rz_old)
 __global__ void k_beta_update(int64_t n, const double *__restrict__ zr, const double *__restrict__ zro,
@@ -149,6 +182,14 @@ int sub(int64_t n, const double *x, const double *y, double *z, hipStream_t s) {
 int cg_update(int64_t n, double a, const double *p, const double *q, double *x, const double *r_in, double *r_out,
               hipStream_t s) {
   hipLaunchKernelGGL(k_cg_update, grid1(n), dim3(256), 0, s, n, a, p, q, x, r_in, r_out);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int cg_update_rr(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
+                 const double *r_in, double *r_out, double *flag, double *part, double *rr, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update_rr, dim3(kDotBlocks), dim3(kRedThreads), 0, s, n, rz, pq, p, q, x, r_in, r_out, flag,
+                     part);
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kRedThreads), 0, s, 1, kDotBlocks, part, rr);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
