@@ -40,10 +40,10 @@ struct dg_solve_state {
   double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *rold = nullptr;
   float *r32 = nullptr, *z32 = nullptr;
   double *part = nullptr, *dout = nullptr;
-  // device scalars: [0] pq, [1] rr, [2] (z, r), [3] (z, r_old), [4..5] rz by
-  // iteration parity, [6] breakdown flag
+  // device scalars: [0] pq, [2] (z, r), [3] (z, r_old), [4..5] rz by
+  // iteration parity, [6] rr, [7] breakdown flag ([1] unused)
   double *dsc = nullptr;
-  double *hdots = nullptr;  // pinned host: [0] setup dots, [1..2] rr by parity, [3..4] flag by parity
+  double *hdots = nullptr;  // pinned host: [0] setup dots, [1 + 2 par] rr and [2 + 2 par] flag by parity
   hipEvent_t ea0[2] = {nullptr, nullptr}, ea1[2] = {nullptr, nullptr};
   hipEvent_t ep0[2] = {nullptr, nullptr}, ep1[2] = {nullptr, nullptr}, err[2] = {nullptr, nullptr};
   int pending = -1;       // parity of the enqueued iteration whose decision is open
@@ -113,16 +113,16 @@ int enqueue_iter(dg_solve_state *st) {
   // u += alpha p, r -= alpha q (flexible: the new residual goes to the other
   // buffer) and rr = (r, r) in the same pass
   double *r_out = st->flex ? st->rold : st->r;
-  if ((rc = cg_update_rr(n, rz_cur, st->dsc + 0, st->p, st->q, st->u, st->r, r_out, st->dsc + 6, st->part,
-                         st->dsc + 1, st->s)))
+  if ((rc = cg_update_rr(n, rz_cur, st->dsc + 0, st->p, st->q, st->u, st->r, r_out, st->dsc + 7, st->part,
+                         st->dsc + 6, st->s)))
     return rc;
   if (st->flex) std::swap(st->r, st->rold);
-  DG_HIP(hipMemcpyAsync(st->hdots + 1 + par, st->dsc + 1, sizeof(double), hipMemcpyDeviceToHost, st->s));
-  DG_HIP(hipMemcpyAsync(st->hdots + 3 + par, st->dsc + 6, sizeof(double), hipMemcpyDeviceToHost, st->s));
+  // rr and the breakdown flag are adjacent: one copy to the host
+  DG_HIP(hipMemcpyAsync(st->hdots + 1 + 2 * par, st->dsc + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, st->s));
   DG_HIP(hipEventRecord(st->err[par], st->s));
   // z = M(r), beta, p
   DG_HIP(hipEventRecord(st->ep0[par], st->s));
-  if ((rc = precond_apply_dev(st->pr, &st->o, st->r, st->z, st->dsc + 1, st->r32, st->z32, st->s))) return rc;
+  if ((rc = precond_apply_dev(st->pr, &st->o, st->r, st->z, st->dsc + 6, st->r32, st->z32, st->s))) return rc;
   DG_HIP(hipEventRecord(st->ep1[par], st->s));
   ds.m = st->flex ? 2 : 1;
   ds.a[0] = st->z;
@@ -151,13 +151,13 @@ int check_iter(dg_solve_state *st) {
   ++st->n_apply;
   take_prec_time(st);  // the previous iteration's preconditioner has finished
   st->prec_unread = par;
-  if (st->hdots[3 + par] != 0.0) {
+  if (st->hdots[2 + 2 * par] != 0.0) {
     set_error("CG breakdown: p^T A p <= 0 or not finite");
     finish(st, DG_EBREAKDOWN);
     return DG_OK;
   }
   ++st->it;
-  st->rnorm = std::sqrt(st->hdots[1 + par]);
+  st->rnorm = std::sqrt(st->hdots[1 + 2 * par]);
   if (!std::isfinite(st->rnorm)) {
     set_error("non-finite residual");
     finish(st, DG_EBREAKDOWN);

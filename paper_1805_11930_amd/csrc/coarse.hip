@@ -216,32 +216,46 @@ __global__ void k_q1_gather(int nx, int ny, int nz, const T *__restrict__ cs, T 
 }
 
 // u += P x_hat: every DG node receives the trilinear interpolant of the
-// vertex values of its cell, evaluated at the node (Sec. 2.2.2).
+// vertex values of its cell, evaluated at the node (Sec. 2.2.2).  One
+// thread per x-line of a cell: the eight vertex values are read once for
+// the line's N nodes.
 template <int N, typename T>
 __global__ void k_q1_prolong_add(int nx, int ny, int nz, const T *__restrict__ xv, T *__restrict__ u) {
-  constexpr int N3 = N * N * N;
+  constexpr int N2 = N * N, N3 = N * N * N;
   constexpr DevTab<T, N> tb = make_ctab<T, N>();
-  const int64_t ndof = (int64_t)nx * ny * nz * N3;
+  const int64_t nlines = (int64_t)nx * ny * nz * N2;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ndof) return;
-  const int64_t c = g / N3;
-  const int j = (int)(g - c * N3);
-  const int kx = j % N, ky = (j / N) % N, kz = j / (N * N);
+  if (g >= nlines) return;
+  const int64_t c = g / N2;
+  const int j = (int)(g - c * N2);
+  const int ky = j % N, kz = j / N;
   int ix, iy, iz;
   grid_coords(c, nx, ny, ix, iy, iz);
   const int vx = nx + 1, vy = ny + 1;
-  const T x1 = tb.xi[kx], y1 = tb.xi[ky], z1 = tb.xi[kz];
-  const T lx[2] = {T(1) - x1, x1}, ly[2] = {T(1) - y1, y1}, lz[2] = {T(1) - z1, z1};
+  const T y1 = tb.xi[ky], z1 = tb.xi[kz];
+  const T ly[2] = {T(1) - y1, y1}, lz[2] = {T(1) - z1, z1};
   const int64_t v0 = ix + (int64_t)vx * (iy + (int64_t)vy * iz);
-  T s = T(0);
+  T xc[2][2][2];
 #pragma unroll
   for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
     for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-      for (int dx = 0; dx < 2; ++dx)
-        s += lx[dx] * ly[dy] * lz[dz] * xv[v0 + dx + (int64_t)vx * (dy + (int64_t)vy * dz)];
-  u[g] += s;
+      for (int dx = 0; dx < 2; ++dx) xc[dz][dy][dx] = xv[v0 + dx + (int64_t)vx * (dy + (int64_t)vy * dz)];
+  T *ul = u + c * N3 + (int64_t)N * ky + (int64_t)N2 * kz;
+#pragma unroll
+  for (int kx = 0; kx < N; ++kx) {
+    const T x1 = tb.xi[kx];
+    const T lx[2] = {T(1) - x1, x1};
+    T s = T(0);
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) s += lx[dx] * ly[dy] * lz[dz] * xc[dz][dy][dx];
+    ul[kx] += s;
+  }
 }
 
 // out = r - A x for the 7-point (P0) levels
@@ -453,7 +467,7 @@ int q1_gather(int nx, int ny, int nz, const T *cs, T *rv, const T *dinv, T w, T 
 template <typename T>
 int q1_prolong_add(int p, int nx, int ny, int nz, const T *xv, T *u, hipStream_t s) {
   const int n = p + 1;
-  const dim3 g = grid_for((int64_t)nx * ny * nz * n * n * n);
+  const dim3 g = grid_for((int64_t)nx * ny * nz * n * n);
   switch (p) {
     case 1: hipLaunchKernelGGL((k_q1_prolong_add<2, T>), g, dim3(256), 0, s, nx, ny, nz, xv, u); break;
     case 2: hipLaunchKernelGGL((k_q1_prolong_add<3, T>), g, dim3(256), 0, s, nx, ny, nz, xv, u); break;
