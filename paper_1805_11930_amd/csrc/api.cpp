@@ -640,6 +640,31 @@ int dg_coarse_stencil(dg_problem *pr, int coarse_space, int level, int *dims, do
 // exported for solve.cpp
 namespace dgmg {
 namespace {
+// the preconditioner proper on rin -> zout in precision prec
+int precond_run(dg_problem *pr, const dg_solve_opts *o, int prec, const void *rin, void *zout, hipStream_t s) {
+  int rc;
+  if (o->precond == DG_PRECOND_MG) {
+    if ((rc = vcycle(pr, prec, rin, zout, &o->mg, s))) return rc;
+  } else {
+    // block smoother steps from zero: mg.smooth.n_sweeps of mg.smooth.sweep
+    SmoothArgs a;
+    if ((rc = smooth_args(pr, &o->mg.smooth, a))) return rc;
+    const int n = o->mg.smooth.n_sweeps > 1 ? o->mg.smooth.n_sweeps : 1;
+    if (a.sweep != DG_SWEEP_JACOBI) {
+      rc = sor_sweeps(pr, prec, rin, nullptr, zout, n, a.sweep, a, s);
+    } else if (n == 1) {
+      a.zero_guess = 1;
+      rc = launch_smooth(pr, prec, rin, rin, zout, a, nullptr, s);
+    } else {
+      void *alt;
+      if ((rc = alloc_tmp(pr, prec, 2, &alt))) return rc;
+      rc = sweeps(pr, prec, rin, nullptr, zout, alt, n, a, nullptr, s);
+    }
+    if (rc) return rc;
+  }
+  return DG_OK;
+}
+
 // z = M(r); with an FP32 preconditioner r is scaled by 1 / ||r||_2 before the
 // cast (host value rnorm, or rr = ||r||^2 in device memory when rr_dev is
 // given) and z scaled back after it.
@@ -660,26 +685,7 @@ int precond_core(dg_problem *pr, const dg_solve_opts *o, const double *r, double
     rin = r32;
     zout = z32;
   }
-  const int prec = mixed ? DG_FP32 : DG_FP64;
-  if (o->precond == DG_PRECOND_MG) {
-    if ((rc = vcycle(pr, prec, rin, zout, &o->mg, s))) return rc;
-  } else {
-    // block smoother steps from zero: mg.smooth.n_sweeps of mg.smooth.sweep
-    SmoothArgs a;
-    if ((rc = smooth_args(pr, &o->mg.smooth, a))) return rc;
-    const int n = o->mg.smooth.n_sweeps > 1 ? o->mg.smooth.n_sweeps : 1;
-    if (a.sweep != DG_SWEEP_JACOBI) {
-      rc = sor_sweeps(pr, prec, rin, nullptr, zout, n, a.sweep, a, s);
-    } else if (n == 1) {
-      a.zero_guess = 1;
-      rc = launch_smooth(pr, prec, rin, rin, zout, a, nullptr, s);
-    } else {
-      void *alt;
-      if ((rc = alloc_tmp(pr, prec, 2, &alt))) return rc;
-      rc = sweeps(pr, prec, rin, nullptr, zout, alt, n, a, nullptr, s);
-    }
-    if (rc) return rc;
-  }
+  if ((rc = precond_run(pr, o, mixed ? DG_FP32 : DG_FP64, rin, zout, s))) return rc;
   if (mixed) {
     rc = rr_dev ? cast_f2d_dev(pr->ndof, rr_dev, z32, z, s) : cast_f2d(pr->ndof, 1.0 / sc, z32, z, s);
     if (rc) return rc;
@@ -696,5 +702,13 @@ int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, doubl
 int precond_apply_dev(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, const double *rr_dev,
                       float *r32, float *z32, hipStream_t s) {
   return precond_core(pr, o, r, z, 0.0, rr_dev, r32, z32, s);
+}
+
+int precond_apply_fp32_dots(dg_problem *pr, const dg_solve_opts *o, const float *r32, float *z32, double *z,
+                            const double *rr_dev, int m, const double *b0, const double *b1, double *part,
+                            double *out, hipStream_t s) {
+  int rc = precond_run(pr, o, DG_FP32, r32, z32, s);
+  if (rc) return rc;
+  return cast_back_dots(pr->ndof, rr_dev, z32, z, m, b0, b1, part, out, s);
 }
 }  // namespace dgmg

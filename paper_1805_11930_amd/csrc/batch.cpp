@@ -40,8 +40,8 @@ struct dg_solve_state {
   double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *rold = nullptr;
   float *r32 = nullptr, *z32 = nullptr;
   double *part = nullptr, *dout = nullptr;
-  // device scalars: [0] pq, [2] (z, r), [3] (z, r_old), [4..5] rz by
-  // iteration parity, [6] rr, [7] breakdown flag ([1] unused)
+  // device scalars: [0] pq, [1] rr of the FP32 scaling in use, [2] (z, r),
+  // [3] (z, r_old), [4..5] rz by iteration parity, [6] rr, [7] breakdown flag
   double *dsc = nullptr;
   double *hdots = nullptr;  // pinned host: [0] setup dots, [1 + 2 par] rr and [2 + 2 par] flag by parity
   hipEvent_t ea0[2] = {nullptr, nullptr}, ea1[2] = {nullptr, nullptr};
@@ -113,8 +113,11 @@ int enqueue_iter(dg_solve_state *st) {
   // u += alpha p, r -= alpha q (flexible: the new residual goes to the other
   // buffer) and rr = (r, r) in the same pass
   double *r_out = st->flex ? st->rold : st->r;
+  // with the FP32 preconditioner the same pass writes r in FP32, scaled by
+  // the previous residual norm (its rr kept in dsc[1] for the cast back)
+  const bool f32 = st->o.precond_precision == DG_FP32 && st->o.precond != DG_PRECOND_NONE;
   if ((rc = cg_update_rr(n, rz_cur, st->dsc + 0, st->p, st->q, st->u, st->r, r_out, st->dsc + 7, st->part,
-                         st->dsc + 6, st->s)))
+                         st->dsc + 6, st->s, f32 ? st->r32 : nullptr, st->dsc + 6, st->dsc + 1)))
     return rc;
   if (st->flex) std::swap(st->r, st->rold);
   // rr and the breakdown flag are adjacent: one copy to the host
@@ -122,14 +125,22 @@ int enqueue_iter(dg_solve_state *st) {
   DG_HIP(hipEventRecord(st->err[par], st->s));
   // z = M(r), beta, p
   DG_HIP(hipEventRecord(st->ep0[par], st->s));
-  if ((rc = precond_apply_dev(st->pr, &st->o, st->r, st->z, st->dsc + 6, st->r32, st->z32, st->s))) return rc;
-  DG_HIP(hipEventRecord(st->ep1[par], st->s));
-  ds.m = st->flex ? 2 : 1;
-  ds.a[0] = st->z;
-  ds.b[0] = st->r;
-  ds.a[1] = st->z;
-  ds.b[1] = st->rold;
-  if ((rc = dots(ds, n, st->part, st->dsc + 2, st->s))) return rc;
+  if (f32) {
+    // z = M(r) and (z, r), (z, r_old) with the cast back
+    if ((rc = precond_apply_fp32_dots(st->pr, &st->o, st->r32, st->z32, st->z, st->dsc + 1, st->flex ? 2 : 1, st->r,
+                                      st->rold, st->part, st->dsc + 2, st->s)))
+      return rc;
+    DG_HIP(hipEventRecord(st->ep1[par], st->s));
+  } else {
+    if ((rc = precond_apply_dev(st->pr, &st->o, st->r, st->z, st->dsc + 6, st->r32, st->z32, st->s))) return rc;
+    DG_HIP(hipEventRecord(st->ep1[par], st->s));
+    ds.m = st->flex ? 2 : 1;
+    ds.a[0] = st->z;
+    ds.b[0] = st->r;
+    ds.a[1] = st->z;
+    ds.b[1] = st->rold;
+    if ((rc = dots(ds, n, st->part, st->dsc + 2, st->s))) return rc;
+  }
   if ((rc = beta_update(n, st->dsc + 2, st->dsc + 3, rz_cur, rz_next, st->flex, st->z, st->p, st->s))) return rc;
   st->pending = par;
   return DG_OK;
@@ -265,6 +276,9 @@ int start(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, hi
     // the device scalar of iteration 0, p = z
     e = hipMemsetAsync(st->dsc, 0, 8 * sizeof(double), st->s);
     if (e != hipSuccess) return fail(hip_fail(e, "hipMemsetAsync"));
+    // rr of the initial residual: the FP32 scaling of the first iteration
+    e = hipMemcpyAsync(st->dsc + 6, st->dout, sizeof(double), hipMemcpyDeviceToDevice, st->s);
+    if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpyAsync"));
     DotSet ds;
     ds.m = 1;
     ds.a[0] = st->r;

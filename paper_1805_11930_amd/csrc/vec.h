@@ -28,9 +28,16 @@ int cg_update(int64_t n, double a, const double *p, const double *q, double *x, 
 int cg_update_dev(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
                   const double *r_in, double *r_out, double *flag, hipStream_t s);
 // cg_update_dev and *rr = r_out . r_out (same sum as dots) in one pass over
-// the vectors; part: kDotBlocks doubles of scratch
+// the vectors; part: kDotBlocks doubles of scratch.  With r32: also
+// r32 = (1 / sqrt(*rr_old)) r_out in FP32 and *rr_keep = *rr_old (rr_old is
+// read before rr is written, so it may be the same slot)
 int cg_update_rr(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
-                 const double *r_in, double *r_out, double *flag, double *part, double *rr, hipStream_t s);
+                 const double *r_in, double *r_out, double *flag, double *part, double *rr, hipStream_t s,
+                 float *r32 = nullptr, const double *rr_old = nullptr, double *rr_keep = nullptr);
+// z = z32 scaled back by the factor of *rr (as cast_f2d_dev) and
+// out[j] = z . b_j for j < m <= 2 (same sums as dots), in one pass
+int cast_back_dots(int64_t n, const double *rr, const float *z32, double *z, int m, const double *b0,
+                   const double *b1, double *part, double *out, hipStream_t s);
 int beta_update(int64_t n, const double *zr, const double *zro, const double *rz_old, double *rz_new, bool flex,
                 const double *z, double *p, hipStream_t s);
 int cast_d2f_dev(int64_t n, const double *rr, const double *x, float *y, hipStream_t s);

@@ -119,12 +119,23 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_update_rr(int64_t n, const d
                                                               const double *__restrict__ p,
                                                               const double *__restrict__ q, double *__restrict__ x,
                                                               const double *r_in, double *r_out,
-                                                              double *__restrict__ flag, double *__restrict__ part) {
+                                                              double *__restrict__ flag, double *__restrict__ part,
+                                                              float *__restrict__ r32,
+                                                              const double *__restrict__ rr_old,
+                                                              double *__restrict__ rr_keep) {
   __shared__ double sh[kRedThreads / 64];
   const double d = *pq;
   double a = *rz / d;
   const bool bad = !(d > 0.0) || !isfinite(a);
   if (bad) a = 0.0;
+  // FP32 copy scaled by 1 / ||r|| of the previous iteration (the current
+  // norm is what this pass computes); the factor's rr is kept for the cast
+  // back of the preconditioned vector
+  double sc = 1.0;
+  if (r32) {
+    const double r2 = *rr_old;
+    sc = r2 > 0.0 ? 1.0 / sqrt(r2) : 1.0;
+  }
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kRedThreads;
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
@@ -132,8 +143,12 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_update_rr(int64_t n, const d
     const double ro = r_in[i] - a * q[i];
     r_out[i] = ro;
     acc += ro * ro;
+    if (r32) r32[i] = (float)(sc * ro);
   }
-  if (bad && blockIdx.x == 0 && threadIdx.x == 0) *flag = 1.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bad) *flag = 1.0;
+    if (r32) *rr_keep = *rr_old;
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
   if (lane == 0) sh[wv] = acc;
@@ -142,6 +157,45 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_update_rr(int64_t n, const d
     double s = 0.0;
     for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
     part[blockIdx.x] = s;
+  }
+}
+
+// z = (1 / (1 / sqrt(rr))) z32 (the inverse of the factor r32 was scaled
+// by, as k_cast_dscale) fused with the partial sums of z . b_j, j < m <= 2
+// (the order of k_dots_partial; k_dots_final adds them)
+__global__ __launch_bounds__(kRedThreads) void k_cast_back_dots(int64_t n, const double *__restrict__ rr,
+                                                                const float *__restrict__ z32,
+                                                                double *__restrict__ z, int m,
+                                                                const double *__restrict__ b0,
+                                                                const double *__restrict__ b1,
+                                                                double *__restrict__ part) {
+  __shared__ double sh[2][kRedThreads / 64];
+  const double r2 = *rr;
+  double sc = r2 > 0.0 ? 1.0 / sqrt(r2) : 1.0;
+  sc = 1.0 / sc;
+  double acc0 = 0.0, acc1 = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kRedThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
+    const double zi = (double)(sc * (double)z32[i]);
+    z[i] = zi;
+    acc0 += zi * b0[i];
+    if (m > 1) acc1 += zi * b1[i];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k = 32; k >= 1; k >>= 1) {
+    acc0 += __shfl_xor(acc0, k, 64);
+    acc1 += __shfl_xor(acc1, k, 64);
+  }
+  if (lane == 0) {
+    sh[0][wv] = acc0;
+    sh[1][wv] = acc1;
+  }
+  __syncthreads();
+  if (threadIdx.x < m) {
+    const int j = threadIdx.x;
+    double t = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) t += sh[j][w];
+    part[(size_t)j * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -186,9 +240,10 @@ int cg_update(int64_t n, double a, const double *p, const double *q, double *x, 
   return DG_OK;
 }
 int cg_update_rr(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
-                 const double *r_in, double *r_out, double *flag, double *part, double *rr, hipStream_t s) {
+                 const double *r_in, double *r_out, double *flag, double *part, double *rr, hipStream_t s,
+                 float *r32, const double *rr_old, double *rr_keep) {
   hipLaunchKernelGGL(k_cg_update_rr, dim3(kDotBlocks), dim3(kRedThreads), 0, s, n, rz, pq, p, q, x, r_in, r_out, flag,
-                     part);
+                     part, r32, rr_old, rr_keep);
   hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kRedThreads), 0, s, 1, kDotBlocks, part, rr);
   DG_HIP(hipGetLastError());
   return DG_OK;
@@ -202,6 +257,13 @@ int cg_update_dev(int64_t n, const double *rz, const double *pq, const double *p
 int beta_update(int64_t n, const double *zr, const double *zro, const double *rz_old, double *rz_new, bool flex,
                 const double *z, double *p, hipStream_t s) {
   hipLaunchKernelGGL(k_beta_update, grid1(n), dim3(256), 0, s, n, zr, zro, rz_old, rz_new, flex ? 1 : 0, z, p);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int cast_back_dots(int64_t n, const double *rr, const float *z32, double *z, int m, const double *b0,
+                   const double *b1, double *part, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_back_dots, dim3(kDotBlocks), dim3(kRedThreads), 0, s, n, rr, z32, z, m, b0, b1, part);
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kRedThreads), 0, s, m, kDotBlocks, part, out);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
