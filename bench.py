@@ -337,6 +337,21 @@ def main() -> int:
     v64 = torch.empty_like(u_rand)
     t_a64 = event_time(lambda: P.apply(u_rand, v64), 20)
     t_a32 = event_time(lambda: P.apply(u32, v32), 20)
+    # the same FP64 apply cycling through 8 input/output pairs (16 vectors,
+    # more than the 256 MB MALL holds at this size): every pass reads u from
+    # HBM instead of the MALL
+    pairs = [(u_rand * (1.0 + 0.01 * k), torch.empty_like(u_rand)) for k in range(8)]
+    cyc = [0]
+
+    def apply_cycled():
+        uu, vv = pairs[cyc[0] % len(pairs)]
+        cyc[0] += 1
+        P.apply(uu, vv)
+
+    for _ in range(8):
+        apply_cycled()
+    t_cold = event_time(apply_cycled, 24)
+    del pairs
     f32 = f.float() / f.norm()
     sm = smooth_opts(eps=1e-2, inner=inner, restart=12)
     out32 = torch.empty_like(f32)
@@ -424,6 +439,8 @@ def main() -> int:
         "rows": {
             "apply_fp64_gdofs": round(P.ndof / t_a64 / 1e9, 2),
             "apply_fp32_gdofs": round(P.ndof / t_a32 / 1e9, 2),
+            "apply_fp64_mall_cold": {"pairs": 8, "gdofs": round(P.ndof / t_cold / 1e9, 2),
+                                     "algorithmic_gbs": round(bpd * P.ndof / t_cold / 1e9, 1)},
             "smoother_sweep_fp32_ms": round(t_sm * 1e3, 3),
             "smoother_roofline": {"bound": "alu", "kernel": f"k_smooth<P={w.p},PCG,float>",
                                   "achieved": round(sm_tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
