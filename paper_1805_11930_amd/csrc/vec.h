@@ -22,13 +22,10 @@ struct DotSet {
 int dots(const DotSet &ds, int64_t n, double *part, double *out_dev, hipStream_t s);
 int axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
 int sub(int64_t n, const double *x, const double *y, double *z, hipStream_t s);
-int cg_update(int64_t n, double a, const double *p, const double *q, double *x, const double *r_in, double *r_out,
-              hipStream_t s);
 // outer-iteration kernels with device scalars (no host round trip)
-int cg_update_dev(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
-                  const double *r_in, double *r_out, double *flag, hipStream_t s);
-// cg_update_dev and *rr = r_out . r_out (same sum as dots) in one pass over
-// the vectors; part: kDotBlocks doubles of scratch.  With r32: also
+// x += a p, r_out = r_in - a q with a = *rz / *pq (a breakdown sets *flag =
+// 1 and leaves x, r unchanged) and *rr = r_out . r_out (same sum as dots) in
+// one pass over the vectors; part: kDotBlocks doubles of scratch.  With r32: also
 // r32 = (1 / sqrt(*rr_old)) r_out in FP32 and *rr_keep = *rr_old (rr_old is
 // read before rr is written, so it may be the same slot)
 int cg_update_rr(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,

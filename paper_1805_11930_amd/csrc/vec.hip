@@ -79,15 +79,6 @@ __global__ void k_sub(int64_t n, const double *__restrict__ x, const double *__r
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) z[i] = x[i] - y[i];
 }
-// x += a p ; r_out = r_in - a q   (r_out may be r_in)
-__global__ void k_cg_update(int64_t n, double a, const double *__restrict__ p, const double *__restrict__ q,
-                            double *__restrict__ x, const double *r_in, double *r_out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    x[i] += a * p[i];
-    r_out[i] = r_in[i] - a * q[i];
-  }
-}
 template <typename S, typename D>
 __global__ void k_cast_scale(int64_t n, double s, const S *__restrict__ x, D *__restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -96,24 +87,10 @@ __global__ void k_cast_scale(int64_t n, double s, const S *__restrict__ x, D *__
 
 // Outer-iteration kernels with their scalars in device memory, so that an
 // iteration is enqueued without waiting for the host.
-// x += a p ; r_out = r_in - a q with a = rz / pq; a breakdown (pq <= 0 or a
-// not finite) leaves x and r unchanged and sets *flag = 1.
-__global__ void k_cg_update_dev(int64_t n, const double *__restrict__ rz, const double *__restrict__ pq,
-                                const double *__restrict__ p, const double *__restrict__ q, double *__restrict__ x,
-                                const double *r_in, double *r_out, double *__restrict__ flag) {
-  const double d = *pq;
-  double a = *rz / d;
-  const bool bad = !(d > 0.0) || !isfinite(a);
-  if (bad) a = 0.0;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    x[i] += a * p[i];
-    r_out[i] = r_in[i] - a * q[i];
-  }
-  if (bad && i == 0) *flag = 1.0;
-}
-// k_cg_update_dev fused with the partial sums of r_out . r_out (grid-stride
-// over the fixed grid of k_dots_partial, same order; k_dots_final adds them)
+// x += a p ; r_out = r_in - a q with a = rz / pq (a breakdown, pq <= 0 or a
+// not finite, leaves x and r unchanged and sets *flag = 1), and the partial
+// sums of r_out . r_out (grid-stride over the fixed grid of k_dots_partial,
+// same order; k_dots_final adds them)
 __global__ __launch_bounds__(kRedThreads) void k_cg_update_rr(int64_t n, const double *__restrict__ rz,
                                                               const double *__restrict__ pq,
                                                               const double *__restrict__ p,
@@ -233,24 +210,12 @@ int sub(int64_t n, const double *x, const double *y, double *z, hipStream_t s) {
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
-int cg_update(int64_t n, double a, const double *p, const double *q, double *x, const double *r_in, double *r_out,
-              hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update, grid1(n), dim3(256), 0, s, n, a, p, q, x, r_in, r_out);
-  DG_HIP(hipGetLastError());
-  return DG_OK;
-}
 int cg_update_rr(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
                  const double *r_in, double *r_out, double *flag, double *part, double *rr, hipStream_t s,
                  float *r32, const double *rr_old, double *rr_keep) {
   hipLaunchKernelGGL(k_cg_update_rr, dim3(kDotBlocks), dim3(kRedThreads), 0, s, n, rz, pq, p, q, x, r_in, r_out, flag,
                      part, r32, rr_old, rr_keep);
   hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kRedThreads), 0, s, 1, kDotBlocks, part, rr);
-  DG_HIP(hipGetLastError());
-  return DG_OK;
-}
-int cg_update_dev(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
-                  const double *r_in, double *r_out, double *flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update_dev, grid1(n), dim3(256), 0, s, n, rz, pq, p, q, x, r_in, r_out, flag);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
