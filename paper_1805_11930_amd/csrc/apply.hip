@@ -23,6 +23,8 @@
 // mostly in that XCD's own L2.
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "line_ops.h"
 
 namespace dgmg {
@@ -485,35 +487,46 @@ __global__ __launch_bounds__(256) void k_rhs(Geo g, const double *__restrict__ f
   rhs[gid] = val;
 }
 
+// ev0 / ev1 (may be null): events recorded by the dispatch itself at the
+// start and end of the apply kernel (hipExtLaunchKernelGGL), so that their
+// difference is the kernel's own duration
 template <int P, typename T>
-static int launch_apply_t(const dg_problem *pr, const void *u, void *v, hipStream_t s, bool nb) {
+static int launch_apply_t(const dg_problem *pr, const void *u, void *v, hipStream_t s, bool nb, hipEvent_t ev0,
+                          hipEvent_t ev1) {
   constexpr int N = P + 1;
   const int G = (int)((pr->ncell + ApplyShape<N>::CPB - 1) / ApplyShape<N>::CPB);
-  if (nb && pr->geo.field == DG_FIELD_ROTATED_QUADRATIC) return launch_apply_tensor(pr, sizeof(T) == 8 ? DG_FP64 : DG_FP32, u, v, s);
+  const dim3 grid(G), block(kApplyThreads);
+  if (nb && pr->geo.field == DG_FIELD_ROTATED_QUADRATIC) {
+    if (ev0) DG_HIP(hipEventRecord(ev0, s));
+    const int rc = launch_apply_tensor(pr, sizeof(T) == 8 ? DG_FP64 : DG_FP32, u, v, s);
+    if (ev1) DG_HIP(hipEventRecord(ev1, s));
+    return rc;
+  }
   if (nb && pr->geo.field)
-    hipLaunchKernelGGL((k_apply<P, T, true, 0, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u,
-                       (T *)v, (const T *)nullptr, (T *)nullptr);
+    hipExtLaunchKernelGGL((k_apply<P, T, true, 0, true>), grid, block, 0, s, ev0, ev1, 0, pr->geo, (const T *)u,
+                          (T *)v, (const T *)nullptr, (T *)nullptr);
   else if (nb && pr->geo.has_b)
-    hipLaunchKernelGGL((k_apply<P, T, true>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u, (T *)v,
-                       (const T *)nullptr, (T *)nullptr);
+    hipExtLaunchKernelGGL((k_apply<P, T, true>), grid, block, 0, s, ev0, ev1, 0, pr->geo, (const T *)u, (T *)v,
+                          (const T *)nullptr, (T *)nullptr);
   else if (nb)
-    hipLaunchKernelGGL((k_apply<P, T, true, 0, false, false>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo,
-                       (const T *)u, (T *)v, (const T *)nullptr, (T *)nullptr);
+    hipExtLaunchKernelGGL((k_apply<P, T, true, 0, false, false>), grid, block, 0, s, ev0, ev1, 0, pr->geo,
+                          (const T *)u, (T *)v, (const T *)nullptr, (T *)nullptr);
   else
-    hipLaunchKernelGGL((k_apply<P, T, false>), dim3(G), dim3(kApplyThreads), 0, s, pr->geo, (const T *)u, (T *)v,
-                       (const T *)nullptr, (T *)nullptr);
+    hipExtLaunchKernelGGL((k_apply<P, T, false>), grid, block, 0, s, ev0, ev1, 0, pr->geo, (const T *)u, (T *)v,
+                          (const T *)nullptr, (T *)nullptr);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
 
 template <typename T>
-static int dispatch_apply(const dg_problem *pr, const void *u, void *v, hipStream_t s, bool nb) {
+static int dispatch_apply(const dg_problem *pr, const void *u, void *v, hipStream_t s, bool nb, hipEvent_t ev0 = nullptr,
+                          hipEvent_t ev1 = nullptr) {
   switch (pr->p) {
-    case 1: return launch_apply_t<1, T>(pr, u, v, s, nb);
-    case 2: return launch_apply_t<2, T>(pr, u, v, s, nb);
-    case 3: return launch_apply_t<3, T>(pr, u, v, s, nb);
-    case 4: return launch_apply_t<4, T>(pr, u, v, s, nb);
-    case 5: return launch_apply_t<5, T>(pr, u, v, s, nb);
+    case 1: return launch_apply_t<1, T>(pr, u, v, s, nb, ev0, ev1);
+    case 2: return launch_apply_t<2, T>(pr, u, v, s, nb, ev0, ev1);
+    case 3: return launch_apply_t<3, T>(pr, u, v, s, nb, ev0, ev1);
+    case 4: return launch_apply_t<4, T>(pr, u, v, s, nb, ev0, ev1);
+    case 5: return launch_apply_t<5, T>(pr, u, v, s, nb, ev0, ev1);
   }
   set_error("unsupported degree");
   return DG_EINVAL;
@@ -554,8 +567,10 @@ int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, cons
   return DG_EINVAL;
 }
 
-int launch_apply(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s) {
-  return prec == DG_FP64 ? dispatch_apply<double>(pr, u, v, s, true) : dispatch_apply<float>(pr, u, v, s, true);
+int launch_apply(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s, hipEvent_t ev0,
+                 hipEvent_t ev1) {
+  return prec == DG_FP64 ? dispatch_apply<double>(pr, u, v, s, true, ev0, ev1)
+                         : dispatch_apply<float>(pr, u, v, s, true, ev0, ev1);
 }
 
 int launch_block_apply(const dg_problem *pr, int prec, const void *x, void *y, hipStream_t s) {

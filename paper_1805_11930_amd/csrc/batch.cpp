@@ -102,9 +102,8 @@ int enqueue_iter(dg_solve_state *st) {
   double *rz_cur = st->dsc + 4 + par, *rz_next = st->dsc + 4 + (par ^ 1);
   int rc;
   // q = A p, pq
-  DG_HIP(hipEventRecord(st->ea0[par], st->s));
-  if ((rc = launch_apply(st->pr, DG_FP64, st->p, st->q, st->s))) return rc;
-  DG_HIP(hipEventRecord(st->ea1[par], st->s));
+  // the events are recorded by the apply's dispatch (its own start and end)
+  if ((rc = launch_apply(st->pr, DG_FP64, st->p, st->q, st->s, st->ea0[par], st->ea1[par]))) return rc;
   DotSet ds;
   ds.m = 1;
   ds.a[0] = st->p;

@@ -259,7 +259,9 @@ int hip_fail(hipError_t e, const char *what);
   } while (0)
 
 // kernel launchers (apply.hip / smooth.hip / vec.hip / coarse.hip)
-int launch_apply(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s);
+// ev0 / ev1 (optional): recorded by the kernel dispatch itself around the apply
+int launch_apply(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s, hipEvent_t ev0 = nullptr,
+                 hipEvent_t ev1 = nullptr);
 int launch_block_apply(const dg_problem *pr, int prec, const void *x, void *y, hipStream_t s);
 // outer operator of a full-tensor (rotated) coefficient field (apply_tensor.hip)
 int launch_apply_tensor(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s);

@@ -57,12 +57,10 @@ struct Ctx {
   int n_apply = 0, n_precond = 0;
 };
 
-// FP64 operator apply bracketed by HIP events on the solve's stream.
+// FP64 operator apply timed by HIP events that its dispatch records.
 int timed_apply(Ctx &c, const double *u, double *v) {
-  DG_HIP(hipEventRecord(c.ev0, c.s));
-  int rc = launch_apply(c.pr, DG_FP64, u, v, c.s);
+  int rc = launch_apply(c.pr, DG_FP64, u, v, c.s, c.ev0, c.ev1);
   if (rc) return rc;
-  DG_HIP(hipEventRecord(c.ev1, c.s));
   DG_HIP(hipEventSynchronize(c.ev1));
   float ms = 0.f;
   DG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
