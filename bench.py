@@ -158,6 +158,9 @@ def pe2000_leg(p: int = 3) -> dict:
             row[name] = {"time_to_solve_s": round(best.t_solve, 4), "iterations": best.iters,
                          "rel_residual": best.rel_residual,
                          "us_per_dof": round(best.t_solve / P.ndof * 1e6, 5)}
+            if name == "mixed":
+                # the FP64 applies inside the solve (dispatch-recorded events)
+                row["apply_fp64_gdofs"] = round(P.ndof * best.n_apply / max(best.t_apply, 1e-30) / 1e9, 2)
             log(f"[bench] Pe=2000 {tag} {name}: {best.t_solve * 1e3:.1f} ms, {best.iters} it, "
                 f"rel_res {best.rel_residual:.2e}")
         out[tag] = row
@@ -185,9 +188,7 @@ def diffusion_leg(p: int = 3) -> dict:
                                 b0=w.b0, B=w.B, kfield=w.kfield, cfield=w.cfield, nrot=w.nrot))
         f = P.rhs_from_functions(f=w.f, g=w.g, j=w.j)
         u = torch.zeros_like(f)
-        v = torch.empty_like(f)
-        t_a = event_time(lambda: P.apply(f, v), 20)
-        row = {"workload": w.name, "ndof": P.ndof, "apply_fp64_gdofs": round(P.ndof / t_a / 1e9, 2)}
+        row = {"workload": w.name, "ndof": P.ndof}
         for name, prec in (("mixed", DG_FP32), ("fp64", DG_FP64)):
             o = solve_opts(krylov=DG_KRYLOV_FCG, precond=DG_PRECOND_MG, precond_precision=prec, rtol=1e-8,
                            maxit=500)
@@ -199,6 +200,9 @@ def diffusion_leg(p: int = 3) -> dict:
             row[name] = {"time_to_solve_s": round(best.t_solve, 4), "iterations": best.iters,
                          "rel_residual": best.rel_residual,
                          "us_per_dof": round(best.t_solve / P.ndof * 1e6, 5)}
+            if name == "mixed":
+                # the FP64 applies inside the solve (dispatch-recorded events)
+                row["apply_fp64_gdofs"] = round(P.ndof * best.n_apply / max(best.t_apply, 1e-30) / 1e9, 2)
             log(f"[bench] {tag} p={p} {name}: {best.t_solve * 1e3:.1f} ms, {best.iters} it, "
                 f"rel_res {best.rel_residual:.2e}")
         out[tag] = row
