@@ -114,7 +114,7 @@ int solve_fgmres(Ctx &c, const double *f, double *u, dg_solve_result *res, DevBu
     if ((rc = wb.get(&z, c.n))) return rc;
   double *r, *tmp;
   if ((rc = wb.get(&r, c.n)) || (rc = wb.get(&tmp, c.n))) return rc;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 2);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(2 * kMaxBasis + 1);
   if ((rc = residual(c, f, u, r, tmp))) return rc;
   double beta = r0;
   int it = 0;
@@ -129,23 +129,20 @@ int solve_fgmres(Ctx &c, const double *f, double *u, dg_solve_result *res, DevBu
       if ((rc = timed_precond(c, V[j], Z[j], 1.0))) return rc;
       double *w = V[j + 1];
       if ((rc = timed_apply(c, Z[j], w))) return rc;
-      // classical Gram-Schmidt, applied twice
+      // classical Gram-Schmidt applied twice, in three passes over the basis:
+      // h1 = V^T w; w -= V h1 and h2 = V^T w; w -= V h2 and |w|^2.  The
+      // coefficients stay on the device; one host copy per step.
       VecList vl;
       for (int i = 0; i <= j; ++i) vl.v[i] = V[i];
-      std::vector<double> hc(j + 1, 0.0);
-      for (int pass = 0; pass < 2; ++pass) {
-        if ((rc = mdot(vl, j + 1, w, c.n, c.part, c.dout, c.s))) return rc;
-        DG_HIP(hipMemcpyAsync(h.data(), c.dout, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, c.s));
-        DG_HIP(hipStreamSynchronize(c.s));
-        Coefs cf;
-        for (int i = 0; i <= j; ++i) {
-          cf.c[i] = h[i];
-          hc[i] += h[i];
-        }
-        if ((rc = mupdate(vl, cf, j + 1, c.n, w, c.s))) return rc;
-      }
-      double hn2;
-      if ((rc = host_dot(c, w, w, &hn2))) return rc;
+      double *h1 = c.dout, *h2 = c.dout + kMaxBasis, *nw = c.dout + 2 * kMaxBasis;
+      if ((rc = gs_dot(vl, j + 1, w, c.n, c.part, h1, c.s))) return rc;
+      if ((rc = gs_update_dot(vl, j + 1, h1, w, c.n, c.part, h2, c.s))) return rc;
+      if ((rc = gs_update_norm(vl, j + 1, h2, w, c.n, c.part, nw, c.s))) return rc;
+      DG_HIP(hipMemcpyAsync(h.data(), c.dout, (2 * kMaxBasis + 1) * sizeof(double), hipMemcpyDeviceToHost, c.s));
+      DG_HIP(hipStreamSynchronize(c.s));
+      std::vector<double> hc(j + 1);
+      for (int i = 0; i <= j; ++i) hc[i] = h[i] + h[kMaxBasis + i];
+      const double hn2 = h[2 * kMaxBasis];
       const double hn = std::sqrt(hn2);
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc[i];
       for (int i = 0; i < j; ++i) {
@@ -236,7 +233,7 @@ extern "C" int dg_solve(dg_problem *pr, const double *f, double *u, const dg_sol
   DG_HIP(hipEventCreate(&evs.b));
   c.ev0 = evs.a;
   c.ev1 = evs.b;
-  if ((rc = wb.get(&c.part, (size_t)kMaxBasis * kDotBlocks)) || (rc = wb.get(&c.dout, kMaxBasis))) return rc;
+  if ((rc = wb.get(&c.part, (size_t)kMaxBasis * kDotBlocks)) || (rc = wb.get(&c.dout, 2 * kMaxBasis + 1))) return rc;
   if (o->precond_precision == DG_FP32 && o->precond != DG_PRECOND_NONE) {
     if ((rc = wb.get(&c.r32, c.n)) || (rc = wb.get(&c.z32, c.n))) return rc;
   }

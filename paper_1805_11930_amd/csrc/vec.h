@@ -88,9 +88,16 @@ struct VecList {
 struct Coefs {
   double c[kMaxBasis];
 };
-// out_dev[i] = V_i . w for i < m; part: kMaxBasis*kDotBlocks doubles
-int mdot(const VecList &vl, int m, const double *w, int64_t n, double *part, double *out_dev, hipStream_t s);
-int mupdate(const VecList &vl, const Coefs &h, int m, int64_t n, double *w, hipStream_t s);
+// Gram-Schmidt passes over the basis V_0..V_{m-1} (1 <= m <= kMaxBasis);
+// part: kMaxBasis*kDotBlocks doubles, h_dev and out_dev in device memory.
+// out_dev[i] = V_i . w
+int gs_dot(const VecList &vl, int m, const double *w, int64_t n, double *part, double *out_dev, hipStream_t s);
+// w -= sum_i h_dev[i] V_i, then out_dev[i] = V_i . w
+int gs_update_dot(const VecList &vl, int m, const double *h_dev, double *w, int64_t n, double *part,
+                  double *out_dev, hipStream_t s);
+// w -= sum_i h_dev[i] V_i, then out_dev[0] = w . w
+int gs_update_norm(const VecList &vl, int m, const double *h_dev, double *w, int64_t n, double *part,
+                   double *out_dev, hipStream_t s);
 int mcombine(const VecList &vl, const Coefs &y, int m, int64_t n, double *x, hipStream_t s);
 
 int iter_stats(int64_t n, const int *it, unsigned long long *out_dev, hipStream_t s);

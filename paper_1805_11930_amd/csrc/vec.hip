@@ -7,6 +7,8 @@
 // data give the same bits.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "dg_internal.h"
 #include "vec.h"
 
@@ -46,7 +48,8 @@ __global__ __launch_bounds__(kRedThreads) void k_dots_partial(DotSet ds, int64_t
 __global__ __launch_bounds__(kRedThreads) void k_dots_final(int m, int nblk, const double *__restrict__ part,
                                                              double *__restrict__ out) {
   __shared__ double sh[kRedThreads / 64];
-  for (int j = 0; j < m; ++j) {
+  // one block per sum when launched with m blocks (same order either way)
+  for (int j = blockIdx.x; j < m; j += gridDim.x) {
     double v = 0.0;
     for (int i = threadIdx.x; i < nblk; i += kRedThreads) v += part[(size_t)j * nblk + i];
     for (int mm = 32; mm >= 1; mm >>= 1) v += __shfl_xor(v, mm, 64);
@@ -63,7 +66,7 @@ __global__ __launch_bounds__(kRedThreads) void k_dots_final(int m, int nblk, con
 
 int dots(const DotSet &ds, int64_t n, double *part, double *out_dev, hipStream_t s) {
   hipLaunchKernelGGL(k_dots_partial, dim3(kDotBlocks), dim3(kRedThreads), 0, s, ds, n, part);
-  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kRedThreads), 0, s, ds.m, kDotBlocks, part, out_dev);
+  hipLaunchKernelGGL(k_dots_final, dim3(ds.m), dim3(kRedThreads), 0, s, ds.m, kDotBlocks, part, out_dev);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
@@ -228,7 +231,7 @@ int beta_update(int64_t n, const double *zr, const double *zro, const double *rz
 int cast_back_dots(int64_t n, const double *rr, const float *z32, double *z, int m, const double *b0,
                    const double *b1, double *part, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_cast_back_dots, dim3(kDotBlocks), dim3(kRedThreads), 0, s, n, rr, z32, z, m, b0, b1, part);
-  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kRedThreads), 0, s, m, kDotBlocks, part, out);
+  hipLaunchKernelGGL(k_dots_final, dim3(m), dim3(kRedThreads), 0, s, m, kDotBlocks, part, out);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
@@ -411,46 +414,87 @@ DG_INST(float)
 #undef DG_INST
 
 
-// ---- multi-vector kernels for Gram-Schmidt in FGMRES ------------------------
-// part[i*nblk + blk] = partial of V_i . w, i < m <= kMaxBasis
-__global__ __launch_bounds__(kRedThreads) void k_mdot_partial(VecList vl, int m, const double *__restrict__ w,
-                                                              int64_t n, double *__restrict__ part) {
-  __shared__ double sh[kMaxBasis][kRedThreads / 64];
-  double acc[kMaxBasis];
+// ---- Gram-Schmidt passes of the Arnoldi step in FGMRES --------------------
+// The basis size M is a compile-time constant so that the M loads of one
+// element are all in flight before the first is used.  MODE 0: part = V_i . w;
+// MODE 1: w -= sum_i h_i V_i, then part = V_i . w of the new w (first update
+// and second projection of classical Gram-Schmidt applied twice, one pass);
+// MODE 2: w -= sum_i h_i V_i, then part = w . w.  h is in device memory.
+template <int M, int MODE>
+__global__ __launch_bounds__(kRedThreads) void k_gs(VecList vl, const double *__restrict__ h, double *__restrict__ w,
+                                                    int64_t n, double *__restrict__ part) {
+  constexpr int NA = MODE == 2 ? 1 : M;
+  __shared__ double sh[NA][kRedThreads / 64];
+  double acc[NA];
 #pragma unroll
-  for (int j = 0; j < kMaxBasis; ++j) acc[j] = 0.0;
+  for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+  double hc[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) hc[j] = MODE == 0 ? 0.0 : h[j];
   const int64_t stride = (int64_t)gridDim.x * kRedThreads;
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
-    const double wi = w[i];
+    double v[M];
 #pragma unroll
-    for (int j = 0; j < kMaxBasis; ++j)
-      if (j < m) acc[j] += vl.v[j][i] * wi;
+    for (int j = 0; j < M; ++j) v[j] = vl.v[j][i];
+    double wi = w[i];
+    if (MODE != 0) {
+#pragma unroll
+      for (int j = 0; j < M; ++j) wi -= hc[j] * v[j];
+      w[i] = wi;
+    }
+    if (MODE == 2) {
+      acc[0] += wi * wi;
+    } else {
+#pragma unroll
+      for (int j = 0; j < M; ++j) acc[j] += v[j] * wi;
+    }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int j = 0; j < kMaxBasis; ++j) {
-    if (j < m) {
-      double v = acc[j];
-      for (int mm = 32; mm >= 1; mm >>= 1) v += __shfl_xor(v, mm, 64);
-      if (lane == 0) sh[j][wv] = v;
-    }
+  for (int j = 0; j < NA; ++j) {
+    double t = acc[j];
+    for (int mm = 32; mm >= 1; mm >>= 1) t += __shfl_xor(t, mm, 64);
+    if (lane == 0) sh[j][wv] = t;
   }
   __syncthreads();
-  if ((int)threadIdx.x < m) {
+  if ((int)threadIdx.x < NA) {
     const int j = threadIdx.x;
-    double s = 0.0;
-    for (int q = 0; q < kRedThreads / 64; ++q) s += sh[j][q];
-    part[(size_t)j * gridDim.x + blockIdx.x] = s;
+    double t = 0.0;
+    for (int q = 0; q < kRedThreads / 64; ++q) t += sh[j][q];
+    part[(size_t)j * gridDim.x + blockIdx.x] = t;
   }
 }
 
-// w -= sum_i h_i V_i
-__global__ void k_mupdate(VecList vl, Coefs h, int m, int64_t n, double *__restrict__ w) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = w[i];
-  for (int j = 0; j < m; ++j) s -= h.c[j] * vl.v[j][i];
-  w[i] = s;
+using GsKernel = void (*)(VecList, const double *, double *, int64_t, double *);
+template <int MODE, int... I>
+static GsKernel gs_pick(int m, std::integer_sequence<int, I...>) {
+  static const GsKernel tab[] = {&k_gs<I + 1, MODE>...};
+  return tab[m - 1];
+}
+template <int MODE>
+static int gs_pass(const VecList &vl, int m, const double *h_dev, double *w, int64_t n, double *part, double *out_dev,
+                   hipStream_t s) {
+  if (m < 1 || m > kMaxBasis) {
+    set_error("Gram-Schmidt pass: basis size out of range");
+    return DG_EINVAL;
+  }
+  const GsKernel k = gs_pick<MODE>(m, std::make_integer_sequence<int, kMaxBasis>{});
+  hipLaunchKernelGGL(k, dim3(kDotBlocks), dim3(kRedThreads), 0, s, vl, h_dev, w, n, part);
+  const int na = MODE == 2 ? 1 : m;
+  hipLaunchKernelGGL(k_dots_final, dim3(na), dim3(kRedThreads), 0, s, na, kDotBlocks, part, out_dev);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+int gs_dot(const VecList &vl, int m, const double *w, int64_t n, double *part, double *out_dev, hipStream_t s) {
+  return gs_pass<0>(vl, m, nullptr, const_cast<double *>(w), n, part, out_dev, s);
+}
+int gs_update_dot(const VecList &vl, int m, const double *h_dev, double *w, int64_t n, double *part,
+                  double *out_dev, hipStream_t s) {
+  return gs_pass<1>(vl, m, h_dev, w, n, part, out_dev, s);
+}
+int gs_update_norm(const VecList &vl, int m, const double *h_dev, double *w, int64_t n, double *part,
+                   double *out_dev, hipStream_t s) {
+  return gs_pass<2>(vl, m, h_dev, w, n, part, out_dev, s);
 }
 
 // x += sum_i y_i Z_i
@@ -462,17 +506,6 @@ __global__ void k_mcombine(VecList vl, Coefs y, int m, int64_t n, double *__rest
   x[i] = s;
 }
 
-int mdot(const VecList &vl, int m, const double *w, int64_t n, double *part, double *out_dev, hipStream_t s) {
-  hipLaunchKernelGGL(k_mdot_partial, dim3(kDotBlocks), dim3(kRedThreads), 0, s, vl, m, w, n, part);
-  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kRedThreads), 0, s, m, kDotBlocks, part, out_dev);
-  DG_HIP(hipGetLastError());
-  return DG_OK;
-}
-int mupdate(const VecList &vl, const Coefs &h, int m, int64_t n, double *w, hipStream_t s) {
-  hipLaunchKernelGGL(k_mupdate, grid1(n), dim3(256), 0, s, vl, h, m, n, w);
-  DG_HIP(hipGetLastError());
-  return DG_OK;
-}
 int mcombine(const VecList &vl, const Coefs &y, int m, int64_t n, double *x, hipStream_t s) {
   hipLaunchKernelGGL(k_mcombine, grid1(n), dim3(256), 0, s, vl, y, m, n, x);
   DG_HIP(hipGetLastError());
