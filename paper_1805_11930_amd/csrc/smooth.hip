@@ -23,8 +23,9 @@
 //   CG:    Hestenes-Stiefel PCG, x0 = 0, M = diag(D_T), stop when the
 //          recursive residual satisfies ||r||_2 <= eps ||d_T||_2 or after
 //          max_inner applications of D_T;
-//   GMRES: right-preconditioned restarted GMRES(restart), modified
-//          Gram-Schmidt, Givens rotations, stop when the Arnoldi residual
+//   GMRES: right-preconditioned restarted GMRES(restart), classical
+//          Gram-Schmidt applied twice (the projections of a pass are
+//          independent cell sums), Givens rotations, stop when the Arnoldi residual
 //          estimate <= eps ||d_T||_2 or after max_inner applications.
 // and, for b = 0, the exact solve with stored factors (fdm.hip):
 //   FDM:   x = (Tz (x) Ty (x) Tx) diag(1/(lx+ly+lz)) (Tz (x) Ty (x) Tx)^T d,
@@ -187,6 +188,47 @@ __device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1
   for (int i = 0; i < N; ++i) q[i] = on ? qx[i] + Qy[lpos<N>(0, i, a, b)] + Qz[lpos<N>(0, i, a, b)] : T(0);
 }
 
+// q = D_T p with the lane's three line operators held as N x N matrices in
+// registers, Mr[k][i * N + l] (axis k; the x-line, y-line and z-line of the
+// lane).  All lanes of the wavefront must call it.
+template <int P, typename T>
+__device__ inline void dt_apply_reg(const T (&Mr)[3][(P + 1) * (P + 1)], bool on, const T (&p)[P + 1],
+                                    T (&q)[P + 1], T *Ps, T *Qy, T *Qz, int a, int b) {
+  constexpr int N = P + 1;
+  T qx[N];
+  if (on) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T acc = T(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l) acc += Mr[0][i * N + l] * p[l];
+      qx[i] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) Ps[lpos<N>(0, i, a, b)] = p[i];
+  }
+  __syncthreads();
+  if (on) {
+#pragma unroll
+    for (int k = 1; k < 3; ++k) {
+      T yl[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) yl[i] = Ps[lpos<N>(k, i, a, b)];
+      T *Q = k == 1 ? Qy : Qz;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < N; ++l) acc += Mr[k][i * N + l] * yl[l];
+        Q[lpos<N>(k, i, a, b)] = acc;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) q[i] = on ? qx[i] + Qy[lpos<N>(0, i, a, b)] + Qz[lpos<N>(0, i, a, b)] : T(0);
+}
+
 // HASB: advection present (compile-time, so the b = 0 kernels carry no
 // advection code and keep only the per-cell matrices live in the loop).
 // Contraction of the lane's line with a matrix stored row-major in LDS:
@@ -228,7 +270,9 @@ __device__ inline void prec_apply(const T (&dinv)[N], const T (&tc)[N], const T 
 // uin and uout may be the same vector for a colour sweep: the cells written
 // are exactly the cells of that colour, each by its own lanes after they
 // read it, and the neighbours read all have the other colour.
-template <int P, int INNER, typename T, bool HASB, bool TRI>
+// RM: bound of the inner GMRES restart length, sizing the Krylov basis in
+// LDS and the rotation state in registers (12 or kGmresMax).
+template <int P, int INNER, typename T, bool HASB, bool TRI, int RM = kGmresMax>
 __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__restrict__ f, const T *uin, T *uout,
                                                            SmoothKArgs sa, int *__restrict__ iters,
                                                            const T *__restrict__ zh, const T *__restrict__ fdm) {
@@ -243,8 +287,8 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   __shared__ T Lm_all[INNER == DG_INNER_FDM ? S::CPW * 3 * N : 1];  // FDM eigenvalues
   // GMRES storage: Krylov basis (lane-private x-lines) and the rotated
   // Hessenberg columns of each cell.
-  __shared__ T Vs_all[INNER == DG_INNER_GMRES ? S::CPW * (kGmresMax + 1) * S::N3 : 1];
-  __shared__ T Hs_all[INNER == DG_INNER_GMRES ? S::CPW * kGmresMax * kGmresMax : 1];
+  __shared__ T Vs_all[INNER == DG_INNER_GMRES ? S::CPW * (RM + 1) * S::N3 : 1];
+  __shared__ T Hs_all[INNER == DG_INNER_GMRES ? S::CPW * RM * RM : 1];
 
   const int tid = threadIdx.x;
   const int cw = tid / L;
@@ -444,6 +488,34 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
     for (int i = 0; i < N; ++i) tc[i] = tl[i] = T(0);
   }
 
+  // With advection the operator of a line depends on its position.  Where
+  // registers allow, the lane's three line operators of D_T (zero
+  // neighbour traces) are built once as N x N matrices: column l is the
+  // operator applied to the unit vector e_l.
+  constexpr bool REGM = HASB && INNER != DG_INNER_FDM && (sizeof(T) == 4 ? N <= 5 : N <= 3);
+  T Mr[3][S::N2];
+  if constexpr (REGM) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        T e[N], col[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) e[i] = i == l ? T(1) : T(0);
+        line_apply<T, N>(tb, cl.f[k], cl.stan, cl.vol, k == 0 ? cl.cre : T(0), true, cl.lc[k], e, T(0), T(0), T(0),
+                         T(0), col);
+#pragma unroll
+        for (int i = 0; i < N; ++i) Mr[k][i * N + l] = on ? col[i] : T(0);
+      }
+    }
+  }
+  auto dtap = [&](const T(&pin)[N], T(&qout)[N]) {
+    if constexpr (REGM)
+      dt_apply_reg<P, T>(Mr, on, pin, qout, Ps, Qy, Qz, a, b);
+    else
+      dt_apply<P, T>(cl, tb, on, hasb, Ms, pin, qout, Ps, Qy, Qz, a, b);
+  };
+
   // ---- inner solve D_T x = d ------------------------------------------------
   T x[N];
 #pragma unroll
@@ -518,7 +590,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
     while (true) {
       const bool act = !conv && it < sa.max_inner;
       if (__ballot(act) == 0) break;
-      dt_apply<P, T>(cl, tb, on, hasb, Ms, p, q, Ps, Qy, Qz, a, b);
+      dtap(p, q);
       T pq = T(0);
 #pragma unroll
       for (int i = 0; i < N; ++i) pq += p[i] * q[i];
@@ -559,8 +631,8 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   } else {
     // restarted right-preconditioned GMRES
     const int R = sa.restart;
-    T *Vs = Vs_all + cw * (kGmresMax + 1) * S::N3;
-    T *Hs = Hs_all + cw * kGmresMax * kGmresMax;
+    T *Vs = Vs_all + cw * (RM + 1) * S::N3;
+    T *Hs = Hs_all + cw * RM * RM;
     const int my = lane * N;  // private slot of this lane's x-line in Vs
     const T dnorm = sqrt(dn2);
     const T target = epsT * dnorm;
@@ -571,9 +643,9 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
     T beta = dnorm;
 #pragma unroll 1
     while (__ballot(!done) != 0) {
-      T cs[kGmresMax], sn[kGmresMax], gv[kGmresMax + 1];
+      T cs[RM], sn[RM], gv[RM + 1];
 #pragma unroll
-      for (int j = 0; j < kGmresMax; ++j) {
+      for (int j = 0; j < RM; ++j) {
         cs[j] = T(0);
         sn[j] = T(0);
         gv[j + 1] = T(0);
@@ -600,25 +672,46 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
 #pragma unroll
           for (int i = 0; i < N; ++i) vj[i] = on ? Vs[j * S::N3 + my + i] * dinv[i] : T(0);
         }
-        dt_apply<P, T>(cl, tb, on, hasb, Ms, vj, w, Ps, Qy, Qz, a, b);
+        dtap(vj, w);
         if (cyc) ++it;
-        T hcol[kGmresMax + 1];
+        // classical Gram-Schmidt applied twice (equal to modified
+        // Gram-Schmidt in exact arithmetic, as stable in practice): the
+        // projections of one pass are independent cell sums, reduced four at
+        // a time so that their lane exchanges overlap
+        T hcol[RM + 1];
 #pragma unroll
-        for (int i = 0; i <= kGmresMax; ++i) hcol[i] = T(0);
+        for (int i = 0; i <= RM; ++i) hcol[i] = T(0);
 #pragma unroll
-        for (int i = 0; i < kGmresMax; ++i) {
-          if (i <= j) {  // modified Gram-Schmidt against V_0..V_j
-            T vi[N];
-            T h = T(0);
+        for (int pass = 0; pass < 2; ++pass) {
+          T hp[RM];
 #pragma unroll
-            for (int l = 0; l < N; ++l) {
-              vi[l] = on ? Vs[i * S::N3 + my + l] : T(0);
-              h += w[l] * vi[l];
+          for (int g0 = 0; g0 < RM; g0 += 4) {
+            T s4[4] = {T(0), T(0), T(0), T(0)};
+            if (g0 <= j) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int i = g0 + q;
+                if (i < RM && on && i <= j) {
+#pragma unroll
+                  for (int l = 0; l < N; ++l) s4[q] += w[l] * Vs[i * S::N3 + my + l];
+                }
+              }
+#pragma unroll
+              for (int q = 0; q < 4; ++q) s4[q] = cell_sum<L>(s4[q]);
             }
-            h = cell_sum<L>(h);
 #pragma unroll
-            for (int l = 0; l < N; ++l) w[l] -= h * vi[l];
-            hcol[i] = h;
+            for (int q = 0; q < 4; ++q)
+              if (g0 + q < RM) hp[g0 + q] = s4[q];
+          }
+#pragma unroll
+          for (int i = 0; i < RM; ++i) {
+            if (i <= j) {
+              if (on) {
+#pragma unroll
+                for (int l = 0; l < N; ++l) w[l] -= hp[i] * Vs[i * S::N3 + my + l];
+              }
+              hcol[i] += hp[i];
+            }
           }
         }
         T hn = T(0);
@@ -627,7 +720,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
         hn = sqrt(cell_sum<L>(hn));
         // earlier rotations, then the new one
 #pragma unroll
-        for (int i = 0; i < kGmresMax; ++i) {
+        for (int i = 0; i < RM; ++i) {
           if (i < j) {
             const T t0 = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
             hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
@@ -636,7 +729,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
         }
         T hj = T(0), gj = T(0);
 #pragma unroll
-        for (int i = 0; i < kGmresMax; ++i)
+        for (int i = 0; i < RM; ++i)
           if (i == j) {
             hj = hcol[i];
             gj = gv[i];
@@ -645,7 +738,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
         const T cj = inner_div(hj, rr), sj = inner_div(hn, rr);
         const T gnext = -sj * gj;
 #pragma unroll
-        for (int i = 0; i < kGmresMax; ++i)
+        for (int i = 0; i < RM; ++i)
           if (i == j) {
             cs[i] = cj;
             sn[i] = sj;
@@ -655,8 +748,8 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
           }
         if (cyc && lane == 0) {
 #pragma unroll
-          for (int i = 0; i < kGmresMax; ++i)
-            if (i <= j) Hs[i * kGmresMax + j] = hcol[i];
+          for (int i = 0; i < RM; ++i)
+            if (i <= j) Hs[i * RM + j] = hcol[i];
         }
         if (cyc) {
           kk = j + 1;
@@ -672,16 +765,16 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
       }
       __syncthreads();  // Hs written by lane 0 of each cell
       // back substitution H y = g and x += M^-1 V y (cells with kk > 0)
-      T y[kGmresMax];
+      T y[RM];
 #pragma unroll
-      for (int i = kGmresMax - 1; i >= 0; --i) {
+      for (int i = RM - 1; i >= 0; --i) {
         T s = T(0);
         if (i < kk) {
           s = gv[i];
 #pragma unroll
-          for (int l = 0; l < kGmresMax; ++l)
-            if (l > i && l < kk) s -= Hs[i * kGmresMax + l] * y[l];
-          s /= Hs[i * kGmresMax + i];
+          for (int l = 0; l < RM; ++l)
+            if (l > i && l < kk) s -= Hs[i * RM + l] * y[l];
+          s /= Hs[i * RM + i];
         }
         y[i] = s;
       }
@@ -692,7 +785,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
 #pragma unroll
           for (int l = 0; l < N; ++l) vy[l] = T(0);
 #pragma unroll
-          for (int i = 0; i < kGmresMax; ++i) {
+          for (int i = 0; i < RM; ++i) {
             if (i < kk) {
 #pragma unroll
               for (int l = 0; l < N; ++l) vy[l] += y[i] * Vs[i * S::N3 + my + l];
@@ -703,7 +796,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
           for (int l = 0; l < N; ++l) x[l] += mv[l];
         } else {
 #pragma unroll
-          for (int i = 0; i < kGmresMax; ++i) {
+          for (int i = 0; i < RM; ++i) {
             if (i < kk) {
 #pragma unroll
               for (int l = 0; l < N; ++l) x[l] += dinv[l] * y[i] * Vs[i * S::N3 + my + l];
@@ -717,7 +810,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
       // restart: r = d - D_T x (all lanes take part in the transposes)
       if (__ballot(!done) != 0) {
         T dx[N];
-        dt_apply<P, T>(cl, tb, on, hasb, Ms, x, dx, Ps, Qy, Qz, a, b);
+        dtap(x, dx);
         T rn = T(0);
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -767,9 +860,18 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
   ka.write_du = a.write_du;
   ka.defect = a.defect;
   const bool hb = pr->geo.has_b != 0;
-#define DG_SMOOTH_LAUNCH(INNER, HB, TRI)                                                                        \
-  hipLaunchKernelGGL((k_smooth<P, INNER, T, HB, TRI>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo,            \
+#define DG_SMOOTH_LAUNCH_RM(INNER, HB, TRI, RM)                                                                 \
+  hipLaunchKernelGGL((k_smooth<P, INNER, T, HB, TRI, RM>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo,        \
                      (const T *)f, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh, (const T *)fdm)
+  // inner GMRES with restart <= 12 (the default) takes the smaller build
+#define DG_SMOOTH_LAUNCH(INNER, HB, TRI) DG_SMOOTH_LAUNCH_RM(INNER, HB, TRI, kGmresMax)
+#define DG_SMOOTH_LAUNCH_GMRES(HB, TRI)                    \
+  do {                                                     \
+    if (a.restart <= 12)                                   \
+      DG_SMOOTH_LAUNCH_RM(DG_INNER_GMRES, HB, TRI, 12);    \
+    else                                                   \
+      DG_SMOOTH_LAUNCH_RM(DG_INNER_GMRES, HB, TRI, kGmresMax); \
+  } while (0)
   const void *fdm = pr->fdm[sizeof(T) == 8 ? DG_FP64 : DG_FP32];
   if (a.inner == DG_INNER_FDM) {
     if (hb || !fdm) {
@@ -788,16 +890,18 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
       DG_SMOOTH_LAUNCH(DG_INNER_CG, false, false);
   } else if (a.tridiag) {
     if (hb)
-      DG_SMOOTH_LAUNCH(DG_INNER_GMRES, true, true);
+      DG_SMOOTH_LAUNCH_GMRES(true, true);
     else
-      DG_SMOOTH_LAUNCH(DG_INNER_GMRES, false, true);
+      DG_SMOOTH_LAUNCH_GMRES(false, true);
   } else {
     if (hb)
-      DG_SMOOTH_LAUNCH(DG_INNER_GMRES, true, false);
+      DG_SMOOTH_LAUNCH_GMRES(true, false);
     else
-      DG_SMOOTH_LAUNCH(DG_INNER_GMRES, false, false);
+      DG_SMOOTH_LAUNCH_GMRES(false, false);
   }
 #undef DG_SMOOTH_LAUNCH
+#undef DG_SMOOTH_LAUNCH_RM
+#undef DG_SMOOTH_LAUNCH_GMRES
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
