@@ -492,7 +492,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   // registers allow, the lane's three line operators of D_T (zero
   // neighbour traces) are built once as N x N matrices: column l is the
   // operator applied to the unit vector e_l.
-  constexpr bool REGM = HASB && INNER != DG_INNER_FDM && (sizeof(T) == 4 ? N <= 5 : N <= 3);
+  constexpr bool REGM = HASB && INNER != DG_INNER_FDM && (sizeof(T) == 4 ? N <= 5 : N <= 4);
   T Mr[3][S::N2];
   if constexpr (REGM) {
 #pragma unroll
