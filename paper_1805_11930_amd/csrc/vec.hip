@@ -17,27 +17,46 @@ namespace dgmg {
 constexpr int kRedThreads = 256;
 
 // ---- deterministic dot products ------------------------------------------
-// out[j] = sum_i a_j[i] * b_j[i] for up to kMaxDots pairs in one pass.
+// out[j] = sum_i a_j[i] * b_j[i] for M <= kMaxDots pairs in one pass.  Each
+// thread loads U grid-stride elements before it adds them, in the order
+// i, i + stride, ... (the order of the fused partial sums below).
+template <int M>
 __global__ __launch_bounds__(kRedThreads) void k_dots_partial(DotSet ds, int64_t n, double *__restrict__ part) {
-  __shared__ double sh[kMaxDots][kRedThreads / 64];
-  double acc[kMaxDots];
+  constexpr int U = 4;
+  __shared__ double sh[M][kRedThreads / 64];
+  double acc[M];
 #pragma unroll
-  for (int j = 0; j < kMaxDots; ++j) acc[j] = 0.0;
+  for (int j = 0; j < M; ++j) acc[j] = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kRedThreads;
-  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
+  for (int64_t i0 = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i0 < n; i0 += U * stride) {
+    double av[U][M], bv[U][M];
 #pragma unroll
-    for (int j = 0; j < kMaxDots; ++j)
-      if (j < ds.m) acc[j] += ds.a[j][i] * ds.b[j][i];
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      const int64_t ic = i < n ? i : i0;  // in bounds; not added below
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        av[u][j] = ds.a[j][ic];
+        bv[u][j] = ds.b[j][ic];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i0 + u * stride < n) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) acc[j] += av[u][j] * bv[u][j];
+      }
+    }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int j = 0; j < kMaxDots; ++j) {
+  for (int j = 0; j < M; ++j) {
     double v = acc[j];
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
     if (lane == 0) sh[j][wv] = v;
   }
   __syncthreads();
-  if (threadIdx.x < kMaxDots) {
+  if (threadIdx.x < M) {
     const int j = threadIdx.x;
     double s = 0.0;
     for (int w = 0; w < kRedThreads / 64; ++w) s += sh[j][w];
@@ -65,7 +84,13 @@ __global__ __launch_bounds__(kRedThreads) void k_dots_final(int m, int nblk, con
 }
 
 int dots(const DotSet &ds, int64_t n, double *part, double *out_dev, hipStream_t s) {
-  hipLaunchKernelGGL(k_dots_partial, dim3(kDotBlocks), dim3(kRedThreads), 0, s, ds, n, part);
+  switch (ds.m) {
+    case 1: hipLaunchKernelGGL(k_dots_partial<1>, dim3(kDotBlocks), dim3(kRedThreads), 0, s, ds, n, part); break;
+    case 2: hipLaunchKernelGGL(k_dots_partial<2>, dim3(kDotBlocks), dim3(kRedThreads), 0, s, ds, n, part); break;
+    case 3: hipLaunchKernelGGL(k_dots_partial<3>, dim3(kDotBlocks), dim3(kRedThreads), 0, s, ds, n, part); break;
+    case 4: hipLaunchKernelGGL(k_dots_partial<4>, dim3(kDotBlocks), dim3(kRedThreads), 0, s, ds, n, part); break;
+    default: set_error("dots: 1..4 pairs"); return DG_EINVAL;
+  }
   hipLaunchKernelGGL(k_dots_final, dim3(ds.m), dim3(kRedThreads), 0, s, ds.m, kDotBlocks, part, out_dev);
   DG_HIP(hipGetLastError());
   return DG_OK;
