@@ -89,8 +89,8 @@ def test_block_pcg_replay(p):
     P.close()
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
-@pytest.mark.parametrize("restart", [4, 12])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("restart", [4, 12, 16])  # 16: the kernels built for restarts above 12
 def test_block_gmres_replay(p, restart):
     from paper_1805_11930_amd import DG_INNER_GMRES, smooth_opts
 
@@ -116,6 +116,14 @@ def test_block_gmres_replay(p, restart):
                        smooth_opts(eps=1e-13, inner=DG_INNER_GMRES, restart=restart, max_inner=20 * opr.nloc))
     dense = np.concatenate([np.linalg.solve(Db[T], D[T]) for T in range(opr.ncell)])
     assert rel(xt.cpu().numpy(), dense) <= 1e-9
+    # FP32 (register line matrices with advection): every block meets the
+    # tolerance, inner counts within one of the FP64 oracle's
+    x32, it32 = P.block_solve(torch.from_numpy(d).float().cuda(),
+                              smooth_opts(eps=1e-2, inner=DG_INNER_GMRES, restart=restart), iters=True)
+    x32 = x32.cpu().numpy().astype(np.float64).reshape(opr.ncell, -1)
+    for T in range(opr.ncell):
+        assert np.linalg.norm(D[T] - Db[T] @ x32[T]) <= 1.01e-2 * np.linalg.norm(D[T])
+    assert np.abs(it32.cpu().numpy() - np.array(its)).max() <= 1
     P.close()
 
 
