@@ -241,7 +241,8 @@ def main() -> int:
     ap.add_argument("--apply-only", type=int, default=0,
                     help="profiling aid: run this many FP64 applies and exit")
     ap.add_argument("--smooth-only", type=int, default=0,
-                    help="profiling aid: run this many FP32 block-Jacobi sweeps (inner PCG) and exit")
+                    help="profiling aid: run this many FP32 block-Jacobi sweeps (the workload's block "
+                         "solver: inner PCG, or inner GMRES with the Thomas preconditioner when b != 0) and exit")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="counter calibration: run this many 256 MiB device-to-device copies and exit")
     args = ap.parse_args()
@@ -278,18 +279,20 @@ def main() -> int:
         torch.cuda.synchronize()
         log(f"[bench] ran {args.apply_only} FP64 applies")
         return 0
+    conv = bool(w.b0 != (0.0, 0.0, 0.0) or np.any(np.asarray(w.B) != 0))
     if args.smooth_only:
         f32 = (u_rand / u_rand.norm()).float()
         u32 = torch.zeros_like(f32)
         o32 = torch.empty_like(f32)
-        sm = smooth_opts(eps=1e-2, inner=DG_INNER_CG)
+        # the workload's own block solver (as in its V-cycle)
+        sm = (smooth_opts(eps=1e-2, inner=DG_INNER_GMRES, restart=12, inner_precond=DG_IPREC_TRIDIAG) if conv
+              else smooth_opts(eps=1e-2, inner=DG_INNER_CG))
         for _ in range(args.smooth_only):
             P.block_smooth(f32, u32, sm, out=o32)
         torch.cuda.synchronize()
         log(f"[bench] ran {args.smooth_only} FP32 smoother sweeps")
         return 0
     f = P.rhs_from_functions(f=w.f, g=w.g, j=w.j)
-    conv = bool(w.b0 != (0.0, 0.0, 0.0) or np.any(np.asarray(w.B) != 0))
     inner = DG_INNER_GMRES if conv else DG_INNER_CG
     krylov = DG_KRYLOV_FGMRES if conv else DG_KRYLOV_FCG
     # convection-dominated blocks: the tridiagonal (Thomas) inner preconditioner (Sec. 3.2)
