@@ -3,8 +3,8 @@
 // the levels of the simple P0 aggregation cycle used as coarse solver.
 //
 // Reductions are deterministic: a fixed grid of partial sums followed by a
-// single-block final sum in a fixed order, so repeated calls on the same
-// data give the same bits.
+// final sum of each result in one block, in a fixed order, so repeated
+// calls on the same data give the same bits.
 #include <hip/hip_runtime.h>
 
 #include <utility>
