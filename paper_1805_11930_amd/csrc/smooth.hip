@@ -271,7 +271,8 @@ __device__ inline void prec_apply(const T (&dinv)[N], const T (&tc)[N], const T 
 // are exactly the cells of that colour, each by its own lanes after they
 // read it, and the neighbours read all have the other colour.
 // RM: bound of the inner GMRES restart length, sizing the Krylov basis in
-// LDS and the rotation state in registers (12 or kGmresMax).
+// LDS and the rotation state in registers (8, 12 or kGmresMax; at p = 3 in
+// FP32 the 8 build fits three wavefronts per SIMD, the 12 build two).
 template <int P, int INNER, typename T, bool HASB, bool TRI, int RM = kGmresMax>
 __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__restrict__ f, const T *uin, T *uout,
                                                            SmoothKArgs sa, int *__restrict__ iters,
@@ -863,11 +864,13 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
 #define DG_SMOOTH_LAUNCH_RM(INNER, HB, TRI, RM)                                                                 \
   hipLaunchKernelGGL((k_smooth<P, INNER, T, HB, TRI, RM>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo,        \
                      (const T *)f, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh, (const T *)fdm)
-  // inner GMRES with restart <= 12 (the default) takes the smaller build
+  // inner GMRES takes the smallest build that holds its restart length
 #define DG_SMOOTH_LAUNCH(INNER, HB, TRI) DG_SMOOTH_LAUNCH_RM(INNER, HB, TRI, kGmresMax)
 #define DG_SMOOTH_LAUNCH_GMRES(HB, TRI)                    \
   do {                                                     \
-    if (a.restart <= 12)                                   \
+    if (a.restart <= 8)                                    \
+      DG_SMOOTH_LAUNCH_RM(DG_INNER_GMRES, HB, TRI, 8);     \
+    else if (a.restart <= 12)                              \
       DG_SMOOTH_LAUNCH_RM(DG_INNER_GMRES, HB, TRI, 12);    \
     else                                                   \
       DG_SMOOTH_LAUNCH_RM(DG_INNER_GMRES, HB, TRI, kGmresMax); \
