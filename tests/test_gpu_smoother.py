@@ -90,7 +90,7 @@ def test_block_pcg_replay(p):
 
 
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
-@pytest.mark.parametrize("restart", [4, 12, 16])  # 16: the kernels built for restarts above 12
+@pytest.mark.parametrize("restart", [4, 8, 12, 16])  # kernels built for restarts up to 8, 12 and 16
 def test_block_gmres_replay(p, restart):
     from paper_1805_11930_amd import DG_INNER_GMRES, smooth_opts
 
