@@ -3,12 +3,16 @@
 A step is one pass of the whole hot path over the workload: one FP64
 flexible-CG solve to a relative residual of 1e-8, preconditioned by one
 FP32 hybrid-multigrid V-cycle per iteration (block-Jacobi smoother with
-inner PCG at eps = 1e-2, P0 coarse correction), i.e. operator applies,
-fused smoother sweeps, transfers, coarse cycle and outer vector work.
+inner PCG at eps = 1e-2, Q1 coarse space with a vertex-grid coarse
+cycle), i.e. operator applies, fused smoother sweeps, transfers, coarse
+cycle and outer vector work.  The convection workload (w4) takes
+FGMRES(30), inner GMRES(8) with the Thomas preconditioner and the P0
+coarse space.
 
 value  = DG operator-apply throughput (GDOF/s) of the FP64 applies that
-         run inside the timed solves, each bracketed by HIP events on the
-         solve's stream (dg_solve_result.t_apply / n_apply).
+         run inside the timed solves, each timed by the start and end
+         events that its dispatch records (dg_solve_result.t_apply /
+         n_apply).
 ms_per_step = mean wall time of one solve (time-to-solve, mixed).
 Also reported: FP64-preconditioned time-to-solve, FP32 apply throughput,
 smoother and V-cycle timings, the roofline of the apply kernel, and the
