@@ -1,25 +1,33 @@
 """Benchmark of the DG hot path on one MI355X.
 
-A step is one pass of the whole hot path over the workload: one FP64
-flexible-CG solve to a relative residual of 1e-8, preconditioned by one
-FP32 hybrid-multigrid V-cycle per iteration (block-Jacobi smoother with
-inner PCG at eps = 1e-2, Q1 coarse space with a vertex-grid coarse
-cycle), i.e. operator applies, fused smoother sweeps, transfers, coarse
-cycle and outer vector work.  The convection workload (w4) takes
-FGMRES(30), inner GMRES(8) with the Thomas preconditioner and the P0
-coarse space.
+A step is one pass of the whole hot path over the main workload (default:
+Poisson, 32^3 cells, p = 4): one FP64 flexible-CG solve to a relative
+residual of 1e-8, preconditioned by one FP32 hybrid-multigrid V-cycle per
+iteration (block-Jacobi smoother with inner PCG at eps = 1e-2, Q1 coarse
+space with a vertex-grid coarse cycle), i.e. operator applies, fused
+smoother sweeps, transfers, coarse cycle and outer vector work.
 
 value  = DG operator-apply throughput (GDOF/s) of the FP64 applies that
          run inside the timed solves, each timed by the start and end
          events that its dispatch records (dg_solve_result.t_apply /
          n_apply).
-ms_per_step = mean wall time of one solve (time-to-solve, mixed).
-Also reported: FP64-preconditioned time-to-solve, FP32 apply throughput,
-smoother and V-cycle timings, the roofline of the apply kernel, and the
-CPU oracle (explicitly assembled BSR matrix, scipy matvec) on a bounded
-sample of the same workload.
+ms_per_step = mean wall time of one mixed-precision solve (setup included).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload w2]
+Every other single-GPU configuration runs as its own leg with the same
+report (`workloads`): the 8^3 p = 2 Poisson problem (CG + one block-Jacobi
+sweep to 1e-10), the SPE10-like 60x220x85 p = 2 box and the 48^3 p = 3
+convection box (FGMRES(30), inner GMRES(8) with the Thomas preconditioner,
+P0 coarse space).  Per leg: FP64-preconditioned and mixed time-to-solve
+(both from dg_solve_result.t_solve, setup reported separately),
+iterations, true FP64 residuals, FP64 errors (against the exact solution
+where it is known, and mixed against the FP64-preconditioned answer), the
+inner iterations counted inside the solve, the in-solve FP64 apply rate
+with its HBM roofline, FP32 apply, smoother sweep and V-cycle times.
+Then the Sec. 4.2 diffusion tests, the Sec. 4.3 Pe = 2000 problem, the
+serving mix, and the CPU oracle (explicitly assembled BSR matrix, scipy
+matvec on 1 and on all host threads; its CG solve of the 8^3 problem).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload w2] [--legs w1,w3,w4]
 """
 from __future__ import annotations
 
@@ -65,13 +73,44 @@ def make_workload(name: str):
     return {"w1": inputs.w1, "w2": inputs.w2, "w3": inputs.w3, "w4": inputs.w4}[name]()
 
 
-def cpu_baseline(w, seconds: float = 12.0) -> dict:
-    """Oracle apply (explicit BSR matrix, scipy matvec) on a bounded sample
-    of the workload: the same p, coefficients and boundary types on an
-    8x8x8-cell sub-box."""
-    import numpy as np
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    from oracle import dg
+
+def _host_threads() -> int:
+    """Threads the CPU baseline may use: the cores this process may run on,
+    at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(w, seconds: float = 4.0) -> dict:
+    """The oracle on the host cores, on bounded samples of the workloads.
+
+    Apply: the oracle's explicitly assembled BSR matrix (scipy matvec) of the
+    workload's p, coefficients and boundary types on an 8x8x8-cell sub-box,
+    on one thread and on all host threads (row blocks of the same matrix,
+    one per thread; scipy releases the GIL in the matvec).  Solve: the
+    oracle's flexible CG with one block-Jacobi sweep (inner PCG, eps = 1e-2)
+    to 1e-10 on the 8^3, p = 2 Poisson problem, the same solve as the
+    workload's first configuration."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import scipy.sparse as sp
+
+    from oracle import dg, solvers
+    from paper_1805_11930_amd import inputs
 
     sub = (8, 8, 8)
     nc = 512
@@ -82,23 +121,52 @@ def cpu_baseline(w, seconds: float = 12.0) -> dict:
     A = dg.assemble(pr)
     t_asm = time.perf_counter() - t0
     u = np.random.default_rng(1).normal(size=pr.ndof)
-    v = A @ u
-    reps = 0
+
+    def rate(fn):
+        fn()
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            fn()
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                return pr.ndof * reps / el / 1e9, reps, el
+
+    g1, reps1, el1 = rate(lambda: A @ u)
+    nt = _host_threads()
+    nb = pr.nloc
+    Acsr = A.tocsr()
+    parts = [sp.bsr_matrix(Acsr[r[0] * nb:(r[-1] + 1) * nb], blocksize=(nb, nb))
+             for r in np.array_split(np.arange(pr.ncell), nt)]
+    with ThreadPoolExecutor(nt) as ex:
+        gN, repsN, elN = rate(lambda: np.concatenate(list(ex.map(lambda B: B @ u, parts))))
+    # time-to-solve of the 8^3, p = 2 Poisson problem
+    w1 = inputs.w1()
+    p1 = dg.Problem(cells=w1.cells, lengths=w1.lengths, p=w1.p, bc=w1.bc, sigma=w1.sigma, K=w1.K, c=w1.c)
+    A1 = dg.assemble(p1)
+    D1 = dg.block_diagonal(A1, p1.ncell)
+    f1 = dg.assemble_rhs(p1, f=w1.f)
+    M = lambda r: solvers.block_jacobi(A1, D1, r, np.zeros_like(r), omega=1.0, nsweeps=1, inner="cg",  # noqa: E731
+                                       eps=1e-2)
     t0 = time.perf_counter()
-    while True:
-        v = A @ u
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
+    _, it1, hist = solvers.cg(A1, f1, precond=M, rtol=1e-10, flexible=True)
+    t_solve = time.perf_counter() - t0
     return {
-        "value": pr.ndof * reps / el / 1e9,
+        "value": round(gN, 6),
         "unit": "GDOF/s",
-        "cores": 1,
+        "cores": nt,
         "kind": "oracle",
-        "sample": f"apply v=Au with the oracle's assembled BSR matrix (scipy matvec, single thread), "
-                  f"p={w.p}, 8x8x8 cells = {pr.ndof} DOF, {reps} applies in {el:.1f} s "
+        "sample": f"apply v=Au with the oracle's assembled BSR matrix (scipy matvec, row blocks on {nt} threads), "
+                  f"p={w.p}, 8x8x8 cells = {pr.ndof} DOF, {repsN} applies in {elN:.1f} s "
                   f"(assembly {t_asm:.1f} s not timed)",
+        "one_core_gdofs": round(g1, 6),
+        "one_core_sample": f"same matrix on 1 thread, {reps1} applies in {el1:.1f} s",
+        "nproc": os.cpu_count(),
+        "cpu_model": _cpu_model(),
+        "solve_poisson_8cube_p2": {"time_to_solve_s": round(t_solve, 3), "iterations": it1,
+                                   "rel_residual": hist[-1], "threads": 1,
+                                   "method": "flexible CG, one block-Jacobi sweep (inner PCG eps 1e-2), rtol 1e-10"},
     }
 
 
@@ -228,6 +296,213 @@ def event_time(fn, reps: int) -> float:
     return s.elapsed_time(e) * 1e-3 / reps
 
 
+def is_convective(w) -> bool:
+    import numpy as np
+
+    return bool(tuple(w.b0) != (0.0, 0.0, 0.0) or np.any(np.asarray(w.B) != 0))
+
+
+def leg_settings(w, coarse_opt: str = "auto"):
+    """Solver settings of a workload: (solve-option builder, smoother dict,
+    coarse-space name, description).  The 8^3 Poisson problem takes one
+    block-Jacobi sweep as the preconditioner of CG to 1e-10 (its stated
+    solve); the others the hybrid V-cycle to 1e-8: FCG and block-Jacobi with
+    inner PCG for diffusion, FGMRES(30) and inner GMRES(8) with the Thomas
+    preconditioner for convection (Sec. 3.2, 4.3)."""
+    from paper_1805_11930_amd import (DG_COARSE_P0, DG_COARSE_Q1, DG_INNER_CG, DG_INNER_GMRES, DG_IPREC_DIAG,
+                                      DG_IPREC_TRIDIAG, DG_KRYLOV_FCG, DG_KRYLOV_FGMRES, DG_PRECOND_BLOCK,
+                                      DG_PRECOND_MG, solve_opts)
+
+    conv = is_convective(w)
+    sm = (dict(eps=1e-2, inner=DG_INNER_GMRES, restart=8, inner_precond=DG_IPREC_TRIDIAG) if conv
+          else dict(eps=1e-2, inner=DG_INNER_CG, inner_precond=DG_IPREC_DIAG))
+    coarse_name = w.coarse if coarse_opt == "auto" else coarse_opt
+    if coarse_name == "auto":
+        coarse_name = "p0" if conv else "q1"
+    coarse = DG_COARSE_Q1 if coarse_name == "q1" else DG_COARSE_P0
+    krylov = DG_KRYLOV_FGMRES if conv else DG_KRYLOV_FCG
+    if w.name.startswith("poisson-8^3"):
+        def opts(prec, **kw):
+            return solve_opts(krylov=DG_KRYLOV_FCG, precond=DG_PRECOND_BLOCK, precond_precision=prec, rtol=1e-10,
+                              maxit=1000, smooth=dict(sm, n_sweeps=1), **kw)
+        desc = "flexible CG to 1e-10, one block-Jacobi sweep (inner PCG eps 1e-2) as preconditioner"
+        return opts, sm, "none", desc
+
+    def opts(prec, **kw):
+        return solve_opts(krylov=krylov, restart=30, precond=DG_PRECOND_MG, precond_precision=prec, rtol=1e-8,
+                          maxit=1000, smooth=sm, mg=dict(coarse_space=coarse), **kw)
+    desc = (("FGMRES(30)" if conv else "flexible CG") + " to 1e-8, hybrid V-cycle (block-Jacobi, " +
+            ("inner GMRES(8) with the Thomas preconditioner" if conv else "inner PCG") +
+            f" eps 1e-2, {coarse_name.upper()} coarse space)")
+    return opts, sm, coarse_name, desc
+
+
+def apply_kernel_name(w) -> str:
+    return f"k_apply<{w.p}, double, true, 0, false, {'true' if is_convective(w) else 'false'}>"
+
+
+def solve_leg(w, steps: int, warmup: int, coarse_opt: str = "auto", smoother_rows: bool = True) -> dict:
+    """One workload: FP64-preconditioned and mixed-precision solves (each
+    time-to-solve from dg_solve_result.t_solve, setup separately), the FP64
+    applies inside the mixed solves (dispatch-recorded events), per-result
+    FP64 errors (against the exact solution when known, and mixed against
+    the FP64-preconditioned answer), the inner iterations counted inside the
+    solve, and the smoother sweep and V-cycle of the same settings."""
+    import numpy as np
+    import torch
+
+    from paper_1805_11930_amd import DG_FP32, DG_FP64, Problem, ProblemSpec, mg_opts, smooth_opts
+
+    opts, smd, coarse_name, desc = leg_settings(w, coarse_opt)
+    t0 = time.perf_counter()
+    P = Problem(ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c,
+                            b0=w.b0, B=w.B))
+    f = P.rhs_from_functions(f=w.f, g=w.g, j=w.j)
+    exact = None
+    if w.exact is not None:
+        exact = torch.from_numpy(np.ascontiguousarray(w.exact(P.node_points()), dtype=np.float64)).cuda()
+    torch.cuda.synchronize()
+    t_problem = time.perf_counter() - t0
+    u = torch.zeros_like(f)
+
+    def run(o):
+        u.zero_()
+        _, r = P.solve(f, u, o)
+        return r
+
+    out = {"workload": w.name, "cells": list(w.cells), "p": w.p, "ndof": P.ndof, "solver": desc,
+           "problem_setup_s": round(t_problem, 3)}
+    res = {}
+    for name, prec in (("fp64", DG_FP64), ("mixed", DG_FP32)):
+        o = opts(prec)
+        for _ in range(warmup):
+            run(o)
+        torch.cuda.synchronize()
+        rs = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rs.append(run(o))
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        res[name] = (rs, wall)
+        if name == "fp64":
+            u64 = u.clone()
+    ts = {k: [r.t_solve for r in v[0]] for k, v in res.items()}
+    out["time_to_solve_s"] = {k: round(float(np.median(v)), 5) for k, v in ts.items()}
+    out["time_to_solve_min_s"] = {k: round(min(v), 5) for k, v in ts.items()}
+    out["wall_per_solve_s"] = {k: round(v[1], 5) for k, v in res.items()}
+    out["solve_setup_s"] = {k: round(float(np.median([r.t_setup for r in v[0]])), 5) for k, v in res.items()}
+    out["iterations"] = {k: v[0][-1].iters for k, v in res.items()}
+    out["rel_residual"] = {k: v[0][-1].rel_residual for k, v in res.items()}
+    out["status"] = {k: v[0][-1].status for k, v in res.items()}
+    mixed = res["mixed"][0]
+    t_apply = sum(r.t_apply for r in mixed)
+    n_apply = sum(r.n_apply for r in mixed)
+    apply_s = t_apply / max(n_apply, 1)
+    bpd = bytes_per_dof(w.p, 8)
+    out["apply_fp64_gdofs_in_solve"] = round(P.ndof / apply_s / 1e9, 3)
+    out["apply_launches_timed"] = n_apply
+    achieved = bpd * P.ndof / apply_s / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": apply_kernel_name(w), "achieved": round(achieved, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "bytes_per_dof": round(bpd, 3), "launch_us": round(apply_s * 1e6, 2)}
+    # per-result errors and in-solve inner counts (untimed runs)
+    err = {}
+    inner = {}
+    for name, prec in (("fp64", DG_FP64), ("mixed", DG_FP32)):
+        ref = exact if exact is not None else (u64 if name == "mixed" else None)
+        r = run(opts(prec, inner_stats=1, u_ref=ref.data_ptr() if ref is not None else None))
+        inner[name] = {"avg": round(r.inner_avg, 3), "max": r.inner_max, "blocks": r.inner_blocks}
+        if exact is not None:
+            err[f"{name}_vs_exact"] = r.error
+        elif name == "mixed":
+            err["mixed_vs_fp64"] = r.error
+    if exact is not None:
+        r = run(opts(DG_FP32, u_ref=u64.data_ptr()))
+        err["mixed_vs_fp64"] = r.error
+    out["error"] = err
+    out["inner_in_solve"] = inner
+    # standalone applies and the preconditioner pieces of the same settings
+    u_rand = torch.from_numpy(np.random.default_rng(3).normal(size=P.ndof)).cuda()
+    v64 = torch.empty_like(u_rand)
+    u32 = u_rand.float()
+    v32 = torch.empty_like(u32)
+    out["apply_fp64_gdofs"] = round(P.ndof / event_time(lambda: P.apply(u_rand, v64), 20) / 1e9, 2)
+    out["apply_fp32_gdofs"] = round(P.ndof / event_time(lambda: P.apply(u32, v32), 20) / 1e9, 2)
+    if smoother_rows:
+        f32 = f.float() / f.norm()
+        sm = smooth_opts(**smd)
+        out32 = torch.empty_like(f32)
+        t_sm = event_time(lambda: P.block_smooth(f32, u32, sm, out=out32), 5)
+        _, st = P.block_smooth(f32, u32, sm, out=out32, stats=True)
+        out["smoother_sweep_fp32_ms"] = round(t_sm * 1e3, 4)
+        out["smoother_inner_avg"] = round(st.inner_avg, 3)
+        out["smoother_inner_max"] = st.inner_max
+        if smd["inner"] == 0:
+            # algorithmic flops of the inner-PCG sweep: per cell the defect
+            # (three line operators on N^2 lines, N x N contractions, and the
+            # face terms: 6 N^4 + 20 N^3) and per inner iteration one D_T
+            # product (6 N^4) plus the dot products and updates (13 N^3)
+            nn = w.p + 1
+            fl = P.ncell * (6 * nn**4 + 20 * nn**3) + st.inner_total * (6 * nn**4 + 13 * nn**3)
+            out["smoother_roofline"] = {"bound": "alu", "kernel": f"k_smooth<{w.p}, 0, float, false, false, 16>",
+                                        "achieved": round(fl / t_sm / 1e12, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                                        "unit": "TFLOP/s", "frac": round(fl / t_sm / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4),
+                                        "flops_per_launch": int(fl)}
+        else:
+            out["smoother_kernel"] = f"k_smooth<{w.p}, 1, float, true, true, 8> (inner GMRES(8), Thomas)"
+        if coarse_name != "none":
+            from paper_1805_11930_amd import DG_COARSE_P0, DG_COARSE_Q1
+
+            mo = mg_opts(smooth=smd, coarse_space=DG_COARSE_Q1 if coarse_name == "q1" else DG_COARSE_P0)
+            out["vcycle_fp32_ms"] = round(event_time(lambda: P.mg_vcycle(f32, mo, out=out32), 5) * 1e3, 4)
+    log(f"[bench] {w.name}: FP64-prec {out['time_to_solve_s']['fp64'] * 1e3:.1f} ms ({out['iterations']['fp64']} it), "
+        f"mixed {out['time_to_solve_s']['mixed'] * 1e3:.1f} ms ({out['iterations']['mixed']} it), apply "
+        f"{out['apply_fp64_gdofs_in_solve']} GDOF/s (frac {out['roofline']['frac']}), errors {err}, inner {inner}")
+    P.close()
+    return out
+
+
+def fdm_leg(w, steps: int = 3) -> dict:
+    """Stored-factor (fast diagonalisation) exact block solve in the same
+    V-cycle and solves (b = 0)."""
+    import torch
+
+    from paper_1805_11930_amd import DG_FP32, DG_FP64, DG_INNER_FDM, Problem, ProblemSpec, smooth_opts, solve_opts
+
+    opts, _, coarse_name, _ = leg_settings(w)
+    P = Problem(ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c,
+                            b0=w.b0, B=w.B))
+    f = P.rhs_from_functions(f=w.f, g=w.g, j=w.j)
+    u = torch.zeros_like(f)
+    f32 = f.float() / f.norm()
+    u32 = torch.zeros_like(f32)
+    out32 = torch.empty_like(f32)
+    smf = smooth_opts(inner=DG_INNER_FDM)
+    P.block_smooth(f32, u32, smf, out=out32)
+    t_smf = event_time(lambda: P.block_smooth(f32, u32, smf, out=out32), 5)
+    res = {}
+    for name, prec in (("mixed", DG_FP32), ("fp64", DG_FP64)):
+        o = opts(prec)
+        o.mg.smooth.inner = DG_INNER_FDM
+        best = None
+        for _ in range(steps + 1):
+            u.zero_()
+            _, r = P.solve(f, u, o)
+            best = r if best is None or r.t_solve < best.t_solve else best
+        res[name] = best
+    P.close()
+    log(f"[bench] FDM smoother: sweep {t_smf * 1e3:.3f} ms, mixed solve {res['mixed'].t_solve * 1e3:.1f} ms "
+        f"({res['mixed'].iters} it), FP64 {res['fp64'].t_solve * 1e3:.1f} ms")
+    return {
+        "inner": "exact block solve by fast diagonalisation (stored per-cell factors)",
+        "smoother_sweep_fp32_ms": round(t_smf * 1e3, 3),
+        "time_to_solve_s": {k: round(v.t_solve, 4) for k, v in res.items()},
+        "iterations": {k: v.iters for k, v in res.items()},
+        "rel_residual": {k: v.rel_residual for k, v in res.items()},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,12 +511,17 @@ def main() -> int:
     ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w3", "w4"])
     ap.add_argument("--coarse", default="auto", choices=["auto", "p0", "q1"],
                     help="coarse space of the V-cycle (auto: the workload's own; Q1 for the diffusion boxes, P0 "
-                         "for the convection box and the layered SPE10-like field)")
+                         "for the convection box)")
+    ap.add_argument("--legs", default="w1,w3,w4",
+                    help="other single-GPU configurations to run as their own legs (comma list of w1..w4, "
+                         "or 'none')")
+    ap.add_argument("--leg-steps", type=int, default=3, help="timed solves per precision in each extra leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256, help="serving leg size (0 = skip)")
     ap.add_argument("--pe2000", type=int, default=1, help="run the Pe=2000 convection leg (0 = skip)")
     ap.add_argument("--diffusion", type=int, default=1,
                     help="run the Poisson / inhomogeneous diffusion leg on the paper's p=3 grid (0 = skip)")
+    ap.add_argument("--fdm", type=int, default=1, help="run the stored-factor smoother leg on the main workload")
     ap.add_argument("--apply-only", type=int, default=0,
                     help="profiling aid: run this many FP64 applies and exit")
     ap.add_argument("--smooth-only", type=int, default=0,
@@ -257,10 +537,7 @@ def main() -> int:
     import numpy as np
     import torch
 
-    from paper_1805_11930_amd import (DG_COARSE_P0, DG_COARSE_Q1, DG_FP32, DG_FP64, DG_INNER_CG, DG_INNER_FDM,
-                                      DG_INNER_GMRES, DG_IPREC_DIAG, DG_IPREC_TRIDIAG, DG_KRYLOV_FCG,
-                                      DG_KRYLOV_FGMRES, DG_PRECOND_MG, Problem, ProblemSpec, mg_opts, smooth_opts,
-                                      solve_opts)
+    from paper_1805_11930_amd import Problem, ProblemSpec, smooth_opts
 
     torch.cuda.set_device(0)
     if args.copy_only:
@@ -273,55 +550,38 @@ def main() -> int:
         return 0
     w = make_workload(args.workload)
     log(f"[bench] workload {w.name}: cells={w.cells} p={w.p} ndof={w.ndof}")
+    if args.apply_only or args.smooth_only:
+        P = Problem(ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c,
+                                b0=w.b0, B=w.B))
+        u_rand = torch.from_numpy(np.random.default_rng(3).normal(size=P.ndof)).cuda()
+        if args.apply_only:
+            v = torch.empty_like(u_rand)
+            for _ in range(args.apply_only):
+                P.apply(u_rand, v)
+            torch.cuda.synchronize()
+            log(f"[bench] ran {args.apply_only} FP64 applies")
+        else:
+            f32 = (u_rand / u_rand.norm()).float()
+            u32 = torch.zeros_like(f32)
+            o32 = torch.empty_like(f32)
+            _, smd, _, _ = leg_settings(w, args.coarse)  # the workload's own block solver
+            sm = smooth_opts(**smd)
+            for _ in range(args.smooth_only):
+                P.block_smooth(f32, u32, sm, out=o32)
+            torch.cuda.synchronize()
+            log(f"[bench] ran {args.smooth_only} FP32 smoother sweeps")
+        P.close()
+        return 0
+    # ---- the timed steps: mixed-precision solves of the main workload -----
+    opts, smd, coarse_name, desc = leg_settings(w, args.coarse)
     P = Problem(ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c,
                             b0=w.b0, B=w.B))
-    u_rand = torch.from_numpy(np.random.default_rng(3).normal(size=P.ndof)).cuda()
-    if args.apply_only:
-        v = torch.empty_like(u_rand)
-        for _ in range(args.apply_only):
-            P.apply(u_rand, v)
-        torch.cuda.synchronize()
-        log(f"[bench] ran {args.apply_only} FP64 applies")
-        return 0
-    conv = bool(w.b0 != (0.0, 0.0, 0.0) or np.any(np.asarray(w.B) != 0))
-    if args.smooth_only:
-        f32 = (u_rand / u_rand.norm()).float()
-        u32 = torch.zeros_like(f32)
-        o32 = torch.empty_like(f32)
-        # the workload's own block solver (as in its V-cycle)
-        sm = (smooth_opts(eps=1e-2, inner=DG_INNER_GMRES, restart=8, inner_precond=DG_IPREC_TRIDIAG) if conv
-              else smooth_opts(eps=1e-2, inner=DG_INNER_CG))
-        for _ in range(args.smooth_only):
-            P.block_smooth(f32, u32, sm, out=o32)
-        torch.cuda.synchronize()
-        log(f"[bench] ran {args.smooth_only} FP32 smoother sweeps")
-        return 0
     f = P.rhs_from_functions(f=w.f, g=w.g, j=w.j)
-    inner = DG_INNER_GMRES if conv else DG_INNER_CG
-    krylov = DG_KRYLOV_FGMRES if conv else DG_KRYLOV_FCG
-    # convection-dominated blocks: the tridiagonal (Thomas) inner preconditioner (Sec. 3.2)
-    iprec = DG_IPREC_TRIDIAG if conv else DG_IPREC_DIAG
-
-    coarse_name = w.coarse if args.coarse == "auto" else args.coarse
-    if coarse_name == "auto":
-        coarse_name = "p0" if conv else "q1"
-    coarse = DG_COARSE_Q1 if coarse_name == "q1" else DG_COARSE_P0
-
-    def opts(prec):
-        return solve_opts(krylov=krylov, restart=30, precond=DG_PRECOND_MG, precond_precision=prec, rtol=1e-8,
-                          maxit=1000, smooth=dict(eps=1e-2, inner=inner, restart=8 if conv else 12, inner_precond=iprec),
-                          mg=dict(coarse_space=coarse))
-
-    o_mixed, o_fp64 = opts(DG_FP32), opts(DG_FP64)
     u = torch.zeros_like(f)
-
-    def step(o):
-        u.zero_()
-        _, res = P.solve(f, u, o)
-        return res
-
+    o_mixed = opts(1)
     for i in range(args.warmup):
-        res = step(o_mixed)
+        u.zero_()
+        _, res = P.solve(f, u, o_mixed)
         log(f"[bench] warmup {i}: iters={res.iters} rel_res={res.rel_residual:.2e} t={res.t_solve:.3f}s")
     torch.cuda.synchronize()
     t_apply = 0.0
@@ -329,7 +589,8 @@ def main() -> int:
     iters = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        res = step(o_mixed)
+        u.zero_()
+        _, res = P.solve(f, u, o_mixed)
         t_apply += res.t_apply
         n_apply += res.n_apply
         iters.append(res.iters)
@@ -339,74 +600,13 @@ def main() -> int:
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     log(f"[bench] timed {args.steps} mixed solves: {ms_per_step:.1f} ms/step, iters={iters}")
+    P.close()
     apply_s = t_apply / max(n_apply, 1)
-    gdofs = P.ndof / apply_s / 1e9
+    gdofs = w.ndof / apply_s / 1e9
     bpd = bytes_per_dof(w.p, 8)
-    achieved = bpd * P.ndof / apply_s / 1e9
-    # ---- other rows of the hot path (outside the timed region) ----------
-    res64 = step(o_fp64)
-    log(f"[bench] FP64-preconditioned solve: iters={res64.iters} t={res64.t_solve:.3f}s")
-    res_m = step(o_mixed)
-    u32 = u_rand.float()
-    v32 = torch.empty_like(u32)
-    v64 = torch.empty_like(u_rand)
-    t_a64 = event_time(lambda: P.apply(u_rand, v64), 20)
-    t_a32 = event_time(lambda: P.apply(u32, v32), 20)
-    # the same FP64 apply cycling through 8 input/output pairs (16 vectors,
-    # more than the 256 MB MALL holds at this size): every pass reads u from
-    # HBM instead of the MALL
-    pairs = [(u_rand * (1.0 + 0.01 * k), torch.empty_like(u_rand)) for k in range(8)]
-    cyc = [0]
-
-    def apply_cycled():
-        uu, vv = pairs[cyc[0] % len(pairs)]
-        cyc[0] += 1
-        P.apply(uu, vv)
-
-    for _ in range(8):
-        apply_cycled()
-    t_cold = event_time(apply_cycled, 24)
-    del pairs
-    f32 = f.float() / f.norm()
-    sm = smooth_opts(eps=1e-2, inner=inner, restart=12)
-    out32 = torch.empty_like(f32)
-    t_sm = event_time(lambda: P.block_smooth(f32, u32, sm, out=out32), 5)
-    _, st = P.block_smooth(f32, u32, sm, out=out32, stats=True)
-    # algorithmic flops of the sweep: per cell the defect (three line
-    # operators of N^2 lines with N x N contractions and the face terms:
-    # 6 N^4 + 20 N^3) and per inner PCG iteration one D_T product (6 N^4)
-    # plus the dot products and updates (13 N^3)
-    nn = w.p + 1
-    sm_flops = P.ncell * (6 * nn**4 + 20 * nn**3) + st.inner_total * (6 * nn**4 + 13 * nn**3)
-    sm_tflops = sm_flops / t_sm / 1e12
-    mo = mg_opts(smooth=dict(eps=1e-2, inner=inner, restart=12), coarse_space=coarse)
-    t_vc = event_time(lambda: P.mg_vcycle(f32, mo, out=out32), 5)
-    # stored-factor exact block solve (b = 0 only): same V-cycle and solves
-    fdm = None
-    if not conv:
-        def opts_fdm(prec):
-            return solve_opts(krylov=krylov, restart=30, precond=DG_PRECOND_MG, precond_precision=prec, rtol=1e-8,
-                              maxit=1000, smooth=dict(inner=DG_INNER_FDM), mg=dict(coarse_space=coarse))
-        smf = smooth_opts(inner=DG_INNER_FDM)
-        P.block_smooth(f32, u32, smf, out=out32)
-        t_smf = event_time(lambda: P.block_smooth(f32, u32, smf, out=out32), 5)
-        fdm_res = {}
-        for name, prec in (("mixed", DG_FP32), ("fp64", DG_FP64)):
-            step(opts_fdm(prec))
-            best = None
-            for _ in range(3):
-                r_ = step(opts_fdm(prec))
-                best = r_ if best is None or r_.t_solve < best.t_solve else best
-            fdm_res[name] = best
-        fdm = {
-            "inner": "exact block solve by fast diagonalisation (stored per-cell factors)",
-            "smoother_sweep_fp32_ms": round(t_smf * 1e3, 3),
-            "time_to_solve_s": {k: round(v.t_solve, 4) for k, v in fdm_res.items()},
-            "iterations": {k: v.iters for k, v in fdm_res.items()},
-            "rel_residual": {k: v.rel_residual for k, v in fdm_res.items()},
-        }
-        log(f"[bench] FDM smoother: sweep {t_smf * 1e3:.3f} ms, mixed solve {fdm_res['mixed'].t_solve * 1e3:.1f} ms "
-            f"({fdm_res['mixed'].iters} it), FP64 {fdm_res['fp64'].t_solve * 1e3:.1f} ms")
+    achieved = bpd * w.ndof / apply_s / 1e9
+    # ---- the rest of the hot path, outside the timed region ---------------
+    main_leg = solve_leg(w, max(args.steps, 3), 1, args.coarse)
     traffic = None
     if os.path.exists(COUNTERS):
         with open(COUNTERS) as fh:
@@ -433,11 +633,11 @@ def main() -> int:
             "workload": w.name,
             "cells": list(w.cells),
             "p": w.p,
-            "ndof": P.ndof,
-            "step": "one FP64 flexible Krylov solve to 1e-8 preconditioned by an FP32 hybrid-multigrid V-cycle",
+            "ndof": w.ndof,
+            "step": "one FP64 Krylov solve preconditioned in FP32: " + desc,
             "coarse_space": coarse_name,
-            "block_solver": ("inner GMRES(8), Thomas-preconditioned" if conv else "inner PCG, diagonal") + ", eps 1e-2",
-            "value_from": "mean duration of the FP64 operator-apply kernel inside the timed solves (HIP events)",
+            "value_from": "mean duration of the FP64 operator-apply kernel inside the timed solves (HIP events "
+                          "recorded by its dispatch)",
         },
         "roofline": {
             "bound": "hbm",
@@ -446,30 +646,25 @@ def main() -> int:
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_apply<P=4,double>",
+            "kernel": apply_kernel_name(w),
             "bytes_per_dof": round(bpd, 3),
+            "launch_us": round(apply_s * 1e6, 2),
         },
-        "time_to_solve_s": {"mixed": round(ms_per_step / 1e3, 4), "fp64": round(res64.t_solve, 4)},
-        "iterations": {"mixed": iters, "fp64": res64.iters},
-        "rel_residual": {"mixed": res_m.rel_residual, "fp64": res64.rel_residual},
-        "rows": {
-            "apply_fp64_gdofs": round(P.ndof / t_a64 / 1e9, 2),
-            "apply_fp32_gdofs": round(P.ndof / t_a32 / 1e9, 2),
-            "apply_fp64_mall_cold": {"pairs": 8, "gdofs": round(P.ndof / t_cold / 1e9, 2),
-                                     "algorithmic_gbs": round(bpd * P.ndof / t_cold / 1e9, 1)},
-            "smoother_sweep_fp32_ms": round(t_sm * 1e3, 3),
-            "smoother_roofline": {"bound": "alu", "kernel": f"k_smooth<P={w.p},PCG,float>",
-                                  "achieved": round(sm_tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                                  "unit": "TFLOP/s", "frac": round(sm_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                                  "flops_per_launch": int(sm_flops)},
-            "smoother_inner_avg": round(st.inner_avg, 3),
-            "smoother_inner_max": st.inner_max,
-            "vcycle_fp32_ms": round(t_vc * 1e3, 3),
-            "precond_ms_per_iter_mixed": round(res_m.t_precond * 1e3 / max(res_m.n_precond, 1), 3),
-            "apply_launches_timed": n_apply,
-        },
-        "fdm_smoother": fdm,
+        "time_to_solve_s": main_leg["time_to_solve_s"],
+        "iterations": {"mixed_timed": iters, **main_leg["iterations"]},
+        "rel_residual": main_leg["rel_residual"],
+        "error": main_leg["error"],
+        "inner_in_solve": main_leg["inner_in_solve"],
+        "main": main_leg,
     }
+    if args.fdm and not is_convective(w):
+        line["fdm_smoother"] = fdm_leg(w)
+    legs = [] if args.legs in ("", "none", "0") else [x for x in args.legs.split(",") if x and x != args.workload]
+    line["workloads"] = {}
+    for name in legs:
+        wl = make_workload(name)
+        log(f"[bench] leg {name}: {wl.name}, {wl.ndof} DOF")
+        line["workloads"][name] = solve_leg(wl, args.leg_steps, 1)
     if args.diffusion:
         line["diffusion_sec42"] = diffusion_leg()
     if args.pe2000:
@@ -479,7 +674,6 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
         line["cpu_baseline"] = cpu_baseline(w)
-    P.close()
     print(json.dumps(line), flush=True)
     return 0
 

@@ -199,6 +199,18 @@ typedef struct {
   dg_mg_opts mg;            /* V-cycle options; DG_PRECOND_BLOCK applies
                                mg.smooth.n_sweeps smoother steps (kind
                                mg.smooth.sweep) from a zero guess           */
+  const double *u_ref;      /* DEVICE [ndof] reference solution (an exact
+                               solution, or the FP64-preconditioned answer
+                               that a mixed-precision solve is compared
+                               with), or NULL; the result's `error` is then
+                               ||u - u_ref||_2 / ||u_ref||_2 in FP64.  Read
+                               once at the end of the solve; must not
+                               overlap f or u.                              */
+  int inner_stats;          /* 1: count the inner iterations of every block
+                               solve the preconditioner performs (result
+                               inner_avg, inner_max, inner_blocks); costs
+                               one small reduction kernel per smoothing
+                               step.  0 (default): not counted.            */
 } dg_solve_opts;
 
 typedef struct {
@@ -206,14 +218,18 @@ typedef struct {
   int iters;                /* outer iterations                             */
   double rel_residual;      /* true FP64 ||f - A u||_2 / ||f - A u0||_2     */
   double t_setup, t_solve;  /* seconds                                      */
-  double inner_avg;         /* mean inner iterations per block solve        */
-  int inner_max;
+  double inner_avg;         /* mean inner iterations per block solve inside
+                               the preconditioner (opts->inner_stats; else 0) */
+  int inner_max;            /* largest inner iteration count (same)         */
   size_t footprint;         /* device bytes held by the problem + solve     */
   double t_apply;           /* seconds in FP64 operator-apply kernels (HIP
                                events on the solve's stream)                */
   int n_apply;              /* number of those applies                      */
   double t_precond;         /* seconds in the preconditioner (HIP events)   */
   int n_precond;            /* preconditioner applications                  */
+  double error;             /* ||u - u_ref||_2 / ||u_ref||_2 (FP64), or -1
+                               when opts->u_ref is NULL                     */
+  long long inner_blocks;   /* block solves counted (opts->inner_stats)     */
 } dg_solve_result;
 
 /* ---- problem lifetime ---------------------------------------------- */

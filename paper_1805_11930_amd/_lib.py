@@ -84,6 +84,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [
         ("krylov", ctypes.c_int), ("restart", ctypes.c_int), ("rtol", ctypes.c_double), ("maxit", ctypes.c_int),
         ("precond", ctypes.c_int), ("precond_precision", ctypes.c_int), ("mg", MgOpts),
+        ("u_ref", ctypes.c_void_p), ("inner_stats", ctypes.c_int),
     ]
 
 
@@ -93,6 +94,7 @@ class SolveResult(ctypes.Structure):
         ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double), ("inner_avg", ctypes.c_double),
         ("inner_max", ctypes.c_int), ("footprint", ctypes.c_size_t), ("t_apply", ctypes.c_double),
         ("n_apply", ctypes.c_int), ("t_precond", ctypes.c_double), ("n_precond", ctypes.c_int),
+        ("error", ctypes.c_double), ("inner_blocks", ctypes.c_longlong),
     ]
 
 

@@ -37,6 +37,13 @@ namespace {
 
 inline hipStream_t S(void *s) { return (hipStream_t)s; }
 
+// Scratch of the block smoother given by the caller (instead of the problem's own).
+struct ScratchParts {
+  void *alt = nullptr;                // Jacobi ping-pong vector (n_sweeps > 1)
+  int *iters = nullptr;               // [ncell] inner iterations per cell (stats)
+  unsigned long long *red = nullptr;  // [2] sum and max of iters (stats)
+};
+
 int check_vec(const void *p, const char *name) {
   if (!p) {
     set_error(std::string(name) + " is NULL");
@@ -95,6 +102,17 @@ int smooth_args(dg_problem *pr, const dg_smooth_opts *o, SmoothArgs &a) {
 
 size_t esize(int prec) { return prec == DG_FP64 ? sizeof(double) : sizeof(float); }
 
+// Per-cell iteration counts for a smoother launch: the caller's buffer, or
+// the problem's own while a solve counts its inner iterations.
+int *count_buf(dg_problem *pr, int *iters) { return iters ? iters : (pr->count_inner ? pr->iters_buf : nullptr); }
+
+// Adds the counts of one finished smoothing step (every cell solved once)
+// to the solve's running totals, when the solve counts them.
+int count_step(dg_problem *pr, int *iters, hipStream_t s) {
+  if (iters || !pr->count_inner) return DG_OK;
+  return iter_accum(pr->ncell, pr->iters_buf, pr->inner_acc, s);
+}
+
 // n block-Jacobi sweeps from `src` (NULL = zero) ending in `dst`, using
 // `alt` as the other ping-pong buffer.  dst != alt; src may equal alt but
 // not dst unless n == 0.
@@ -114,7 +132,8 @@ int sweeps(dg_problem *pr, int prec, const void *f, const void *src, void *dst, 
     SmoothArgs a = base;
     a.zero_guess = cur == nullptr ? 1 : 0;
     a.zh = (k == 1 && cur != nullptr) ? zh : nullptr;  // P0 correction enters the first sweep
-    int rc = launch_smooth(pr, prec, f, cur ? cur : f, out, a, iters, s);
+    int rc = launch_smooth(pr, prec, f, cur ? cur : f, out, a, count_buf(pr, iters), s);
+    if (!rc) rc = count_step(pr, iters, s);
     if (rc) return rc;
     cur = out;
   }
@@ -134,10 +153,10 @@ int sor_pass(dg_problem *pr, int prec, const void *f, void *u, bool backward, bo
     a.sor = 1;
     a.zh = nullptr;
     a.zero_guess = (zero && h == 0) ? 1 : 0;
-    int rc = launch_smooth(pr, prec, f, u, u, a, iters, s);
+    int rc = launch_smooth(pr, prec, f, u, u, a, count_buf(pr, iters), s);
     if (rc) return rc;
   }
-  return DG_OK;
+  return count_step(pr, iters, s);  // each cell was solved once by its colour
 }
 
 // Direction of the k-th of the n_dir single-direction sweeps of n steps of
@@ -397,6 +416,100 @@ int vcycle(dg_problem *pr, int prec, const void *r, void *z, const dg_mg_opts *o
   return vcycle_t<float>(pr, prec, (const float *)r, (float *)z, o, s);
 }
 
+// dg_block_smooth with its scratch (the Jacobi ping-pong vector, per-cell
+// iteration counts, reduction results) either from the problem (sp ==
+// NULL: allocated on first use) or from the caller's fixed buffers.
+int block_smooth_impl(dg_problem *pr, int precision, const void *f, const void *u_in, void *u_out,
+                      const dg_smooth_opts *opts, dg_smooth_stats *stats, hipStream_t s, const ScratchParts *sp) {
+  if (!pr) {
+    set_error("problem is NULL");
+    return DG_EINVAL;
+  }
+  int rc;
+  if ((rc = check_prec(precision)) || (rc = check_vec(f, "f")) || (rc = check_vec(u_out, "u_out"))) return rc;
+  if (!opts) {
+    set_error("smoother options are NULL");
+    return DG_EINVAL;
+  }
+  if (!opts->zero_guess && (rc = check_vec(u_in, "u_in"))) return rc;
+  if (opts->n_sweeps < 1) {
+    set_error("n_sweeps must be >= 1");
+    return DG_EINVAL;
+  }
+  SmoothArgs a;
+  if ((rc = smooth_args(pr, opts, a))) return rc;
+  if (a.sweep != DG_SWEEP_JACOBI) {
+    if (f == u_out) {
+      set_error("dg_block_smooth: u_out must differ from f");
+      return DG_EINVAL;
+    }
+    const bool zero = opts->zero_guess != 0;
+    if (!zero && u_in != u_out)
+      DG_HIP(hipMemcpyAsync(u_out, u_in, (size_t)pr->ndof * esize(precision), hipMemcpyDeviceToDevice, s));
+    int *iters = stats ? (sp ? sp->iters : pr->iters_buf) : nullptr;
+    unsigned long long tot = 0;
+    int mx = 0;
+    const int nd = sor_dirs(a.sweep, opts->n_sweeps);
+    for (int k = 0; k < nd; ++k) {
+      if ((rc = sor_pass(pr, precision, f, u_out, sor_backward(a.sweep, k), zero && k == 0, a, iters, s))) return rc;
+      if (stats) {
+        unsigned long long *dev = sp ? sp->red : (unsigned long long *)pr->red_buf;
+        if ((rc = iter_stats(pr->ncell, iters, dev, s))) return rc;
+        unsigned long long h[2];
+        DG_HIP(hipMemcpyAsync(h, dev, sizeof(h), hipMemcpyDeviceToHost, s));
+        DG_HIP(hipStreamSynchronize(s));
+        tot += h[0];
+        mx = (int)h[1] > mx ? (int)h[1] : mx;
+      }
+    }
+    if (stats) {
+      stats->blocks = (long long)pr->ncell * nd;
+      stats->inner_total = (long long)tot;
+      stats->inner_max = mx;
+      stats->inner_avg = stats->blocks ? (double)tot / stats->blocks : 0.0;
+    }
+    return DG_OK;
+  }
+  if (u_in == u_out || f == u_out) {
+    set_error("dg_block_smooth: u_out must differ from u_in and f");
+    return DG_EINVAL;
+  }
+  void *alt = nullptr;
+  if (opts->n_sweeps > 1) {
+    if (sp)
+      alt = sp->alt;
+    else if ((rc = alloc_tmp(pr, precision, 2, &alt)))
+      return rc;
+  }
+  int *iters = stats ? (sp ? sp->iters : pr->iters_buf) : nullptr;
+  unsigned long long tot = 0;
+  int mx = 0;
+  const void *cur = opts->zero_guess ? nullptr : u_in;
+  for (int k = 1; k <= opts->n_sweeps; ++k) {
+    void *out = ((opts->n_sweeps - k) % 2 == 0) ? u_out : alt;
+    SmoothArgs ak = a;
+    ak.zero_guess = cur == nullptr;
+    if ((rc = launch_smooth(pr, precision, f, cur ? cur : f, out, ak, iters, s))) return rc;
+    if (stats) {
+      unsigned long long *dev = sp ? sp->red : (unsigned long long *)pr->red_buf;
+      if ((rc = iter_stats(pr->ncell, iters, dev, s))) return rc;
+      unsigned long long h[2];
+      DG_HIP(hipMemcpyAsync(h, dev, sizeof(h), hipMemcpyDeviceToHost, s));
+      DG_HIP(hipStreamSynchronize(s));
+      tot += h[0];
+      mx = (int)h[1] > mx ? (int)h[1] : mx;
+    }
+    cur = out;
+  }
+  if (stats) {
+    stats->blocks = (long long)pr->ncell * opts->n_sweeps;
+    stats->inner_total = (long long)tot;
+    stats->inner_max = mx;
+    stats->inner_avg = stats->blocks ? (double)tot / stats->blocks : 0.0;
+  }
+  return DG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -436,6 +549,8 @@ void dg_default_solve_opts(dg_solve_opts *o) {
   o->precond = DG_PRECOND_MG;
   o->precond_precision = DG_FP32;
   dg_default_mg_opts(&o->mg);
+  o->u_ref = nullptr;
+  o->inner_stats = 0;
 }
 
 int dg_assemble_rhs(dg_problem *pr, const double *f_qp, const double *bnd_qp, double *rhs, void *stream) {
@@ -508,89 +623,7 @@ int dg_block_solve(dg_problem *pr, int precision, const void *d, void *x, const 
 
 int dg_block_smooth(dg_problem *pr, int precision, const void *f, const void *u_in, void *u_out,
                     const dg_smooth_opts *opts, dg_smooth_stats *stats, void *stream) {
-  if (!pr) {
-    set_error("problem is NULL");
-    return DG_EINVAL;
-  }
-  int rc;
-  if ((rc = check_prec(precision)) || (rc = check_vec(f, "f")) || (rc = check_vec(u_out, "u_out"))) return rc;
-  if (!opts) {
-    set_error("smoother options are NULL");
-    return DG_EINVAL;
-  }
-  if (!opts->zero_guess && (rc = check_vec(u_in, "u_in"))) return rc;
-  if (opts->n_sweeps < 1) {
-    set_error("n_sweeps must be >= 1");
-    return DG_EINVAL;
-  }
-  SmoothArgs a;
-  if ((rc = smooth_args(pr, opts, a))) return rc;
-  hipStream_t s = S(stream);
-  if (a.sweep != DG_SWEEP_JACOBI) {
-    if (f == u_out) {
-      set_error("dg_block_smooth: u_out must differ from f");
-      return DG_EINVAL;
-    }
-    const bool zero = opts->zero_guess != 0;
-    if (!zero && u_in != u_out)
-      DG_HIP(hipMemcpyAsync(u_out, u_in, (size_t)pr->ndof * esize(precision), hipMemcpyDeviceToDevice, s));
-    int *iters = stats ? pr->iters_buf : nullptr;
-    unsigned long long tot = 0;
-    int mx = 0;
-    const int nd = sor_dirs(a.sweep, opts->n_sweeps);
-    for (int k = 0; k < nd; ++k) {
-      if ((rc = sor_pass(pr, precision, f, u_out, sor_backward(a.sweep, k), zero && k == 0, a, iters, s))) return rc;
-      if (stats) {
-        unsigned long long *dev = (unsigned long long *)pr->red_buf;
-        if ((rc = iter_stats(pr->ncell, iters, dev, s))) return rc;
-        unsigned long long h[2];
-        DG_HIP(hipMemcpyAsync(h, dev, sizeof(h), hipMemcpyDeviceToHost, s));
-        DG_HIP(hipStreamSynchronize(s));
-        tot += h[0];
-        mx = (int)h[1] > mx ? (int)h[1] : mx;
-      }
-    }
-    if (stats) {
-      stats->blocks = (long long)pr->ncell * nd;
-      stats->inner_total = (long long)tot;
-      stats->inner_max = mx;
-      stats->inner_avg = stats->blocks ? (double)tot / stats->blocks : 0.0;
-    }
-    return DG_OK;
-  }
-  if (u_in == u_out || f == u_out) {
-    set_error("dg_block_smooth: u_out must differ from u_in and f");
-    return DG_EINVAL;
-  }
-  void *alt = nullptr;
-  if (opts->n_sweeps > 1 && (rc = alloc_tmp(pr, precision, 2, &alt))) return rc;
-  int *iters = stats ? pr->iters_buf : nullptr;
-  unsigned long long tot = 0;
-  int mx = 0;
-  const void *cur = opts->zero_guess ? nullptr : u_in;
-  for (int k = 1; k <= opts->n_sweeps; ++k) {
-    void *out = ((opts->n_sweeps - k) % 2 == 0) ? u_out : alt;
-    SmoothArgs ak = a;
-    ak.zero_guess = cur == nullptr;
-    if ((rc = launch_smooth(pr, precision, f, cur ? cur : f, out, ak, iters, s))) return rc;
-    if (stats) {
-      unsigned long long *dev = (unsigned long long *)pr->red_buf;
-      if ((rc = iter_stats(pr->ncell, iters, dev, s))) return rc;
-      unsigned long long h[2];
-      DG_HIP(hipMemcpyAsync(h, dev, sizeof(h), hipMemcpyDeviceToHost, s));
-      DG_HIP(hipStreamSynchronize(s));
-      tot += h[0];
-      mx = (int)h[1] > mx ? (int)h[1] : mx;
-    }
-    cur = out;
-  }
-  if (stats) {
-    stats->blocks = (long long)pr->ncell * opts->n_sweeps;
-    stats->inner_total = (long long)tot;
-    stats->inner_max = mx;
-    stats->inner_avg = stats->blocks ? (double)tot / stats->blocks : 0.0;
-  }
-  return DG_OK;
+  return block_smooth_impl(pr, precision, f, u_in, u_out, opts, stats, S(stream), nullptr);
 }
 
 int dg_mg_vcycle(dg_problem *pr, int precision, const void *r, void *z, const dg_mg_opts *opts, void *stream) {
@@ -639,6 +672,68 @@ int dg_coarse_stencil(dg_problem *pr, int coarse_space, int level, int *dims, do
 
 // exported for solve.cpp
 namespace dgmg {
+
+int check_solve_vectors(const double *f, const double *u, const dg_solve_opts *o) {
+  int rc;
+  if ((rc = check_vec(f, "f")) || (rc = check_vec(u, "u"))) return rc;
+  if (f == u) {
+    set_error("solve: f and u must differ");
+    return DG_EINVAL;
+  }
+  if (o->u_ref) {
+    if ((rc = check_vec(o->u_ref, "u_ref"))) return rc;
+    if (o->u_ref == f || o->u_ref == u) {
+      set_error("solve: u_ref must differ from f and u");
+      return DG_EINVAL;
+    }
+  }
+  if (o->inner_stats != 0 && o->inner_stats != 1) {
+    set_error("solve: inner_stats must be 0 or 1");
+    return DG_EINVAL;
+  }
+  return DG_OK;
+}
+
+int inner_count_begin(dg_problem *pr, const dg_solve_opts *o, hipStream_t s) {
+  pr->count_inner = 0;
+  if (!o->inner_stats) return DG_OK;
+  DG_HIP(hipMemsetAsync(pr->inner_acc, 0, 3 * sizeof(unsigned long long), s));
+  pr->count_inner = 1;
+  return DG_OK;
+}
+
+int inner_count_end(dg_problem *pr, const dg_solve_opts *o, dg_solve_result *res, hipStream_t s) {
+  pr->count_inner = 0;
+  if (!o->inner_stats) return DG_OK;
+  unsigned long long h[3];
+  DG_HIP(hipMemcpyAsync(h, pr->inner_acc, sizeof(h), hipMemcpyDeviceToHost, s));
+  DG_HIP(hipStreamSynchronize(s));
+  res->inner_blocks = (long long)h[2];
+  res->inner_max = (int)h[1];
+  res->inner_avg = h[2] ? (double)h[0] / (double)h[2] : 0.0;
+  return DG_OK;
+}
+
+int solution_error(int64_t n, const double *u, const double *u_ref, double *tmp, double *part, double *dout,
+                   hipStream_t s, double *err) {
+  *err = -1.0;
+  if (!u_ref) return DG_OK;
+  int rc = sub(n, u, u_ref, tmp, s);
+  if (rc) return rc;
+  DotSet ds;
+  ds.m = 2;
+  ds.a[0] = tmp;
+  ds.b[0] = tmp;
+  ds.a[1] = u_ref;
+  ds.b[1] = u_ref;
+  if ((rc = dots(ds, n, part, dout, s))) return rc;
+  double h[2];
+  DG_HIP(hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, s));
+  DG_HIP(hipStreamSynchronize(s));
+  *err = h[1] > 0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+  return DG_OK;
+}
+
 namespace {
 // the preconditioner proper on rin -> zout in precision prec
 int precond_run(dg_problem *pr, const dg_solve_opts *o, int prec, const void *rin, void *zout, hipStream_t s) {
@@ -654,7 +749,8 @@ int precond_run(dg_problem *pr, const dg_solve_opts *o, int prec, const void *ri
       rc = sor_sweeps(pr, prec, rin, nullptr, zout, n, a.sweep, a, s);
     } else if (n == 1) {
       a.zero_guess = 1;
-      rc = launch_smooth(pr, prec, rin, rin, zout, a, nullptr, s);
+      rc = launch_smooth(pr, prec, rin, rin, zout, a, count_buf(pr, nullptr), s);
+      if (!rc) rc = count_step(pr, nullptr, s);
     } else {
       void *alt;
       if ((rc = alloc_tmp(pr, prec, 2, &alt))) return rc;

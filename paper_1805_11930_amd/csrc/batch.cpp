@@ -52,12 +52,14 @@ struct dg_solve_state {
   double r0 = 0, rnorm = 0;
   int it = 0;
   bool done = false, finalized = false;
+  bool counting = false;  // this state counts its preconditioner's inner iterations
   double t_start = 0, t_iter0 = 0;
   double t_apply = 0, t_precond = 0;
   int n_apply = 0, n_precond = 0;
   dg_solve_result res;
 
   ~dg_solve_state() {
+    if (pr && counting) pr->count_inner = 0;
     for (int k = 0; k < 2; ++k)
       for (hipEvent_t e : {ea0[k], ea1[k], ep0[k], ep1[k], err[k]})
         if (e) (void)hipEventDestroy(e);
@@ -199,6 +201,12 @@ int finalize(dg_solve_state *st) {
   R.t_precond = st->t_precond;
   R.n_precond = st->n_precond;
   if (R.status == DG_OK && !(R.rel_residual <= st->o.rtol * 1.0000001)) R.status = DG_ENOCONV;
+  if (st->counting) {
+    st->counting = false;
+    if ((rc = inner_count_end(st->pr, &st->o, &R, st->s))) return rc;
+  }
+  if ((rc = solution_error(st->pr->ndof, st->u, st->o.u_ref, st->q, st->part, st->dout, st->s, &R.error)))
+    return rc;
   st->finalized = true;
   return DG_OK;
 }
@@ -211,6 +219,7 @@ int start(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, hi
     return DG_EINVAL;
   }
   int rc = validate_solve_opts(o);
+  if (!rc) rc = check_solve_vectors(f, u, o);
   if (rc) return rc;
   if (o->krylov == DG_KRYLOV_FGMRES) {
     set_error("resident solve states support CG and flexible CG");
@@ -225,6 +234,7 @@ int start(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, hi
   st->flex = o->krylov == DG_KRYLOV_FCG;
   std::memset(&st->res, 0, sizeof(st->res));
   st->res.status = DG_EAGAIN;
+  st->res.error = -1.0;
   const int64_t n = pr->ndof;
   auto fail = [&](int code) {
     delete st;
@@ -255,6 +265,8 @@ int start(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, hi
   }
   void *dummy;
   if (o->precond == DG_PRECOND_MG && (rc = alloc_tmp(pr, o->precond_precision, 0, &dummy))) return fail(rc);
+  if ((rc = inner_count_begin(pr, o, st->s))) return fail(rc);
+  st->counting = o->inner_stats != 0;
   // r = f - A u, r0 = ||r||
   if ((rc = launch_apply(pr, DG_FP64, u, st->q, st->s)) || (rc = sub(n, f, st->q, st->r, st->s)) ||
       (rc = enqueue_dots(st, 1, st->r, st->r)))

@@ -244,6 +244,12 @@ struct dg_problem {
   void *mg_tmp[2][4] = {{nullptr}};  // [precision][k]
   int *iters_buf = nullptr;          // [ncell]
   void *red_buf = nullptr;           // reduction scratch
+  // inner-iteration counting inside a solve (dg_solve_opts.inner_stats):
+  // while count_inner is set, every smoothing step writes its per-cell
+  // counts to iters_buf and adds them to inner_acc (device: total, max,
+  // blocks)
+  int count_inner = 0;
+  unsigned long long *inner_acc = nullptr;
   size_t held_bytes = 0;
 };
 

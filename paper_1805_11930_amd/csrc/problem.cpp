@@ -281,6 +281,7 @@ int alloc_small(dg_problem *pr) {
   int rc;
   if (!pr->iters_buf && (rc = dmalloc(pr, (void **)&pr->iters_buf, pr->ncell * sizeof(int)))) return rc;
   if (!pr->red_buf && (rc = dmalloc(pr, &pr->red_buf, 8 * 1024 * sizeof(double) + 64))) return rc;
+  if (!pr->inner_acc && (rc = dmalloc(pr, (void **)&pr->inner_acc, 4 * sizeof(unsigned long long)))) return rc;
   return DG_OK;
 }
 
@@ -312,6 +313,7 @@ void dg_problem_destroy(dg_problem *pr) {
     for (void *p : row) (void)hipFree(p);
   (void)hipFree(pr->iters_buf);
   (void)hipFree(pr->red_buf);
+  (void)hipFree(pr->inner_acc);
   delete pr;
 }
 

@@ -45,6 +45,15 @@ int validate_solve_opts(const dg_solve_opts *o) {
 
 namespace {
 
+// Timed phases: a pair of events around each FP64 apply (recorded by its
+// dispatch) and each preconditioner application.  They are read at the
+// host synchronisations the solver makes anyway (one per Arnoldi step), so
+// timing adds no wait of its own.
+struct TimedPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  int kind = 0;  // 0: apply, 1: preconditioner
+};
+
 struct Ctx {
   dg_problem *pr;
   const dg_solve_opts *o;
@@ -52,33 +61,79 @@ struct Ctx {
   double *part, *dout;
   float *r32 = nullptr, *z32 = nullptr;
   int64_t n;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<TimedPair> spare, pending;
+  int created = 0;
   double t_apply = 0.0, t_precond = 0.0;
   int n_apply = 0, n_precond = 0;
+  ~Ctx() {
+    for (auto *v : {&spare, &pending})
+      for (auto &tp : *v) {
+        (void)hipEventDestroy(tp.a);
+        (void)hipEventDestroy(tp.b);
+      }
+  }
 };
 
-// FP64 operator apply timed by HIP events that its dispatch records.
-int timed_apply(Ctx &c, const double *u, double *v) {
-  int rc = launch_apply(c.pr, DG_FP64, u, v, c.s, c.ev0, c.ev1);
-  if (rc) return rc;
-  DG_HIP(hipEventSynchronize(c.ev1));
-  float ms = 0.f;
-  DG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
-  c.t_apply += 1e-3 * ms;
-  ++c.n_apply;
+// Reads the pending phase times; `wait`: wait for them first (otherwise the
+// caller has just synchronised the stream).
+int harvest(Ctx &c, bool wait) {
+  for (auto &tp : c.pending) {
+    if (wait) DG_HIP(hipEventSynchronize(tp.b));
+    float ms = 0.f;
+    DG_HIP(hipEventElapsedTime(&ms, tp.a, tp.b));
+    if (tp.kind == 0) {
+      c.t_apply += 1e-3 * ms;
+      ++c.n_apply;
+    } else {
+      c.t_precond += 1e-3 * ms;
+      ++c.n_precond;
+    }
+    c.spare.push_back(tp);
+  }
+  c.pending.clear();
   return DG_OK;
 }
 
-int timed_precond(Ctx &c, const double *r, double *z, double rnorm) {
-  DG_HIP(hipEventRecord(c.ev0, c.s));
-  int rc = precond_apply(c.pr, c.o, r, z, rnorm, c.r32, c.z32, c.s);
+int take_pair(Ctx &c, int kind, TimedPair *out) {
+  if (c.spare.empty()) {
+    if (c.created >= 8) {
+      int rc = harvest(c, true);
+      if (rc) return rc;
+    } else {
+      TimedPair tp;
+      DG_HIP(hipEventCreate(&tp.a));
+      hipError_t e = hipEventCreate(&tp.b);
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(tp.a);
+        return hip_fail(e, "hipEventCreate");
+      }
+      ++c.created;
+      c.spare.push_back(tp);
+    }
+  }
+  *out = c.spare.back();
+  c.spare.pop_back();
+  out->kind = kind;
+  return DG_OK;
+}
+
+// FP64 operator apply timed by HIP events that its dispatch records.
+int timed_apply(Ctx &c, const double *u, double *v) {
+  TimedPair tp;
+  int rc = take_pair(c, 0, &tp);
   if (rc) return rc;
-  DG_HIP(hipEventRecord(c.ev1, c.s));
-  DG_HIP(hipEventSynchronize(c.ev1));
-  float ms = 0.f;
-  DG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
-  c.t_precond += 1e-3 * ms;
-  ++c.n_precond;
+  c.pending.push_back(tp);
+  return launch_apply(c.pr, DG_FP64, u, v, c.s, tp.a, tp.b);
+}
+
+int timed_precond(Ctx &c, const double *r, double *z, double rnorm) {
+  TimedPair tp;
+  int rc = take_pair(c, 1, &tp);
+  if (rc) return rc;
+  c.pending.push_back(tp);
+  DG_HIP(hipEventRecord(tp.a, c.s));
+  if ((rc = precond_apply(c.pr, c.o, r, z, rnorm, c.r32, c.z32, c.s))) return rc;
+  DG_HIP(hipEventRecord(tp.b, c.s));
   return DG_OK;
 }
 
@@ -87,7 +142,7 @@ int host_dots(Ctx &c, const DotSet &ds, double *out) {
   if (rc) return rc;
   DG_HIP(hipMemcpyAsync(out, c.dout, ds.m * sizeof(double), hipMemcpyDeviceToHost, c.s));
   DG_HIP(hipStreamSynchronize(c.s));
-  return DG_OK;
+  return harvest(c, false);
 }
 
 int host_dot(Ctx &c, const double *a, const double *b, double *out) {
@@ -140,6 +195,7 @@ int solve_fgmres(Ctx &c, const double *f, double *u, dg_solve_result *res, DevBu
       if ((rc = gs_update_norm(vl, j + 1, h2, w, c.n, c.part, nw, c.s))) return rc;
       DG_HIP(hipMemcpyAsync(h.data(), c.dout, (2 * kMaxBasis + 1) * sizeof(double), hipMemcpyDeviceToHost, c.s));
       DG_HIP(hipStreamSynchronize(c.s));
+      if ((rc = harvest(c, false))) return rc;
       std::vector<double> hc(j + 1);
       for (int i = 0; i <= j; ++i) hc[i] = h[i] + h[kMaxBasis + i];
       const double hn2 = h[2 * kMaxBasis];
@@ -209,10 +265,12 @@ extern "C" int dg_solve(dg_problem *pr, const double *f, double *u, const dg_sol
     return DG_EINVAL;
   }
   int rc = validate_solve_opts(o);
+  if (!rc) rc = check_solve_vectors(f, u, o);
   if (rc) return rc;
   dg_solve_result tmp;
   if (!res) res = &tmp;
   std::memset(res, 0, sizeof(*res));
+  res->error = -1.0;
   hipStream_t s = (hipStream_t)stream;
   if (o->krylov != DG_KRYLOV_FGMRES) return solve_cg_batched(pr, f, u, o, res, s);
   const double t0 = now_s();
@@ -222,17 +280,6 @@ extern "C" int dg_solve(dg_problem *pr, const double *f, double *u, const dg_sol
   c.o = o;
   c.s = s;
   c.n = pr->ndof;
-  struct Events {
-    hipEvent_t a = nullptr, b = nullptr;
-    ~Events() {
-      if (a) (void)hipEventDestroy(a);
-      if (b) (void)hipEventDestroy(b);
-    }
-  } evs;
-  DG_HIP(hipEventCreate(&evs.a));
-  DG_HIP(hipEventCreate(&evs.b));
-  c.ev0 = evs.a;
-  c.ev1 = evs.b;
   if ((rc = wb.get(&c.part, (size_t)kMaxBasis * kDotBlocks)) || (rc = wb.get(&c.dout, 2 * kMaxBasis + 1))) return rc;
   if (o->precond_precision == DG_FP32 && o->precond != DG_PRECOND_NONE) {
     if ((rc = wb.get(&c.r32, c.n)) || (rc = wb.get(&c.z32, c.n))) return rc;
@@ -243,6 +290,11 @@ extern "C" int dg_solve(dg_problem *pr, const double *f, double *u, const dg_sol
   if (o->precond == DG_PRECOND_MG && (rc = alloc_tmp(pr, o->precond_precision, 0, &dummy))) return rc;
   double *r, *t;
   if ((rc = wb.get(&r, c.n)) || (rc = wb.get(&t, c.n))) return rc;
+  if ((rc = inner_count_begin(pr, o, s))) return rc;
+  struct CountGuard {
+    dg_problem *pr;
+    ~CountGuard() { pr->count_inner = 0; }
+  } count_guard{pr};
   DG_HIP(hipStreamSynchronize(s));
   const double t1 = now_s();
   if ((rc = residual(c, f, u, r, t))) return rc;
@@ -264,10 +316,13 @@ extern "C" int dg_solve(dg_problem *pr, const double *f, double *u, const dg_sol
   double rr;
   if ((rc = host_dot(c, r, r, &rr))) return rc;
   const double t2 = now_s();
+  if ((rc = inner_count_end(pr, o, res, s))) return rc;
+  if ((rc = solution_error(c.n, u, o->u_ref, t, c.part, c.dout, s, &res->error))) return rc;
   res->rel_residual = r0 > 0 ? std::sqrt(rr) / r0 : 0.0;
   res->t_setup = t1 - t0;
   res->t_solve = t2 - t1;
   res->footprint = pr->held_bytes + wb.bytes;
+  if ((rc = harvest(c, true))) return rc;
   res->t_apply = c.t_apply;
   res->n_apply = c.n_apply;
   res->t_precond = c.t_precond;

@@ -47,6 +47,15 @@ inline double now_s() {
 }
 
 int validate_solve_opts(const dg_solve_opts *o);
+// f, u (and opts->u_ref) are 16-byte aligned, distinct device vectors
+int check_solve_vectors(const double *f, const double *u, const dg_solve_opts *o);
+// counting of the preconditioner's inner iterations (opts->inner_stats)
+int inner_count_begin(dg_problem *pr, const dg_solve_opts *o, hipStream_t s);
+int inner_count_end(dg_problem *pr, const dg_solve_opts *o, dg_solve_result *res, hipStream_t s);
+// *err = ||u - u_ref||_2 / ||u_ref||_2 (or -1 without u_ref); tmp: [n]
+// scratch, part / dout: dot scratch; synchronises s
+int solution_error(int64_t n, const double *u, const double *u_ref, double *tmp, double *part, double *dout,
+                   hipStream_t s, double *err);
 int validate_mg_opts(const dg_mg_opts *o);
 
 }  // namespace dgmg

@@ -101,5 +101,7 @@ int gs_update_norm(const VecList &vl, int m, const double *h_dev, double *w, int
 int mcombine(const VecList &vl, const Coefs &y, int m, int64_t n, double *x, hipStream_t s);
 
 int iter_stats(int64_t n, const int *it, unsigned long long *out_dev, hipStream_t s);
+// acc_dev[0] += sum it, acc_dev[1] = max(acc_dev[1], max it), acc_dev[2] += n
+int iter_accum(int64_t n, const int *it, unsigned long long *acc_dev, hipStream_t s);
 
 }  // namespace dgmg

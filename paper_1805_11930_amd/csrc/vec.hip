@@ -570,4 +570,48 @@ int iter_stats(int64_t n, const int *it, unsigned long long *out_dev, hipStream_
   return DG_OK;
 }
 
+// acc[0] += sum it, acc[1] = max(acc[1], max it), acc[2] += n: the counts of
+// one smoothing step added to a solve's running totals (integer atomics, so
+// the totals do not depend on the order of the blocks)
+__global__ __launch_bounds__(256) void k_iter_accum(int64_t n, const int *__restrict__ it,
+                                                    unsigned long long *__restrict__ acc) {
+  __shared__ unsigned long long ssum[4];
+  __shared__ unsigned long long smax[4];
+  unsigned long long s = 0, m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const unsigned long long v = (unsigned long long)it[i];
+    s += v;
+    m = v > m ? v : m;
+  }
+  for (int k = 32; k >= 1; k >>= 1) {
+    s += __shfl_xor(s, k, 64);
+    const unsigned long long o = __shfl_xor(m, k, 64);
+    m = o > m ? o : m;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    ssum[wv] = s;
+    smax[wv] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long ts = 0, tm = 0;
+    for (int w = 0; w < 4; ++w) {
+      ts += ssum[w];
+      tm = smax[w] > tm ? smax[w] : tm;
+    }
+    atomicAdd(&acc[0], ts);
+    atomicMax(&acc[1], tm);
+    if (blockIdx.x == 0) atomicAdd(&acc[2], (unsigned long long)n);
+  }
+}
+
+int iter_accum(int64_t n, const int *it, unsigned long long *acc_dev, hipStream_t s) {
+  const int64_t nb = (n + 255) / 256;
+  const int g = (int)(nb < 512 ? (nb > 0 ? nb : 1) : 512);
+  hipLaunchKernelGGL(k_iter_accum, dim3(g), dim3(256), 0, s, n, it, acc_dev);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
 }  // namespace dgmg

@@ -10,6 +10,11 @@ each on its own stream), retires finished solves (freeing their memory)
 and admits again.  A request whose footprint exceeds the
 whole budget is rejected (DG_ENOMEM).  All numerical work runs in the HIP
 library; this module only schedules.
+
+Freeing device memory (hipFree) waits for the whole device, so a retired
+request keeps its memory until the loop is idle (no active solve) or until
+an admission needs the bytes; only then are the retired states and
+problems destroyed, together.
 """
 from __future__ import annotations
 
@@ -86,14 +91,24 @@ class SolveServer:
         a.req.rel_residual = res.rel_residual
         if self.keep:
             a.req.solution = a.u.cpu().numpy()
-        self.lib.dg_solve_state_destroy(a.state)
-        a.prob.close()
+        self._dead.append(a)
+
+    def _flush(self) -> int:
+        """Destroys the retired states and problems; returns their bytes."""
+        freed = 0
+        for a in self._dead:
+            self.lib.dg_solve_state_destroy(a.state)
+            a.prob.close()
+            freed += a.nbytes
+        self._dead = []
+        return freed
 
     def run(self, requests: list[Request], log=None) -> dict:
         pending = sorted(requests, key=lambda r: r.arrival)
         queue: list[Request] = []
         active: list[_Active] = []
-        used = 0
+        self._dead = []
+        used = 0  # bytes of the active and of the retired, not yet freed requests
         steps = 0
         peak_active = 0
         t0 = time.perf_counter()
@@ -110,12 +125,15 @@ class SolveServer:
                     req.status = L.DG_ENOMEM
                     req.finished = now
                     continue
+                if used + need > self.budget and self._dead:
+                    used -= self._flush()
                 if used + need > self.budget:
                     break
                 queue.pop(0)
                 active.append(self._admit(req, time.perf_counter() - t0))
                 used += need
             if not active:
+                used -= self._flush()  # idle: nothing waits on the frees
                 if pending:
                     time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
                 continue
@@ -130,9 +148,9 @@ class SolveServer:
                     still.append(a)
                 else:
                     self._retire(a, now)
-                    used -= a.nbytes
             active = still
         makespan = time.perf_counter() - t0
+        used -= self._flush()
         done = [r for r in requests if r.status in (L.DG_OK, L.DG_ENOCONV)]
         lat = np.array([r.latency for r in done])
         return {
