@@ -293,6 +293,25 @@ int dg_block_solve(dg_problem *prob, int precision, const void *d, void *x,
 int dg_block_smooth(dg_problem *prob, int precision, const void *f, const void *u_in, void *u_out,
                     const dg_smooth_opts *opts, dg_smooth_stats *stats, void *stream);
 
+/* dg_block_smooth without device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same smoothing steps, kernels and results
+ * as dg_block_smooth, but its scratch -- the ping-pong vector of
+ * block-Jacobi with n_sweeps > 1, and with stats the per-cell inner
+ * iteration counts and their reduction -- lives in a fixed device array of
+ * 128 MiB (134217728 bytes) that each GPU the library runs on holds until
+ * the process ends.  Needs at most ndof * sizeof(element) + ncell * 4 +
+ * 768 bytes (rounded up to 256-byte parts); a call that needs more fails
+ * with DG_EINVAL, as does DG_INNER_FDM before its stored factors exist (a
+ * dg_block_smooth call with DG_INNER_FDM builds them) and a problem created
+ * on a device other than the current one.  The first call on a device
+ * looks up that device's copy of the array.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (different streams or
+ * threads) race and must be serialised by the caller.  No part of the
+ * array needs to start at zero: each call writes what it reads. */
+int dg_block_smooth_noalloc(dg_problem *prob, int precision, const void *f, const void *u_in, void *u_out,
+                            const dg_smooth_opts *opts, dg_smooth_stats *stats, void *stream);
+
 /* z ~= A^-1 r by one hybrid V-cycle from a zero initial guess
  * (alg hybrid_multigrid): presmooth, residual, restriction R = P^T
  * (Sec. 2.2.2), coarse correction with A_hat = P^T A P in the P0 or Q1

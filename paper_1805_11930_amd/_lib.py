@@ -35,7 +35,7 @@ EXPORTS = (
     "dg_node_points", "dg_boundary_points", "dg_assemble_rhs", "dg_apply", "dg_block_apply",
     "dg_block_diag", "dg_block_solve", "dg_block_smooth", "dg_mg_vcycle", "dg_solve", "dg_footprint",
     "dg_coarse_stencil", "dg_default_smooth_opts", "dg_default_mg_opts", "dg_default_solve_opts",
-    "dg_solve_start", "dg_batch_step", "dg_solve_poll", "dg_solve_state_destroy",
+    "dg_solve_start", "dg_batch_step", "dg_solve_poll", "dg_solve_state_destroy", "dg_block_smooth_noalloc",
 )
 
 
@@ -127,6 +127,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_block_solve.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.POINTER(SmoothOpts), vp, vp]
     lib.dg_block_smooth.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.POINTER(SmoothOpts),
                                     ctypes.POINTER(SmoothStats), vp]
+    lib.dg_block_smooth_noalloc.argtypes = lib.dg_block_smooth.argtypes
     lib.dg_mg_vcycle.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.POINTER(MgOpts), vp]
     lib.dg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveResult), vp]
     lib.dg_footprint.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(SolveOpts), ctypes.POINTER(ctypes.c_size_t)]

@@ -10,6 +10,9 @@
 #include "vec.h"
 
 namespace dgmg {
+// fixed device scratch of the allocation-free entry points (noalloc.hip)
+size_t scratch_capacity();
+int scratch_device_ptr(int device, void **out);
 int alloc_tmp(dg_problem *pr, int prec, int k, void **out);
 int alloc_small(dg_problem *pr);
 int ensure_hierarchy(dg_problem *pr, int kind);
@@ -37,7 +40,8 @@ namespace {
 
 inline hipStream_t S(void *s) { return (hipStream_t)s; }
 
-// Scratch of the block smoother given by the caller (instead of the problem's own).
+// Scratch of the block smoother given by the caller (instead of the problem's own):
+// the fixed device array of dg_block_smooth_noalloc.
 struct ScratchParts {
   void *alt = nullptr;                // Jacobi ping-pong vector (n_sweeps > 1)
   int *iters = nullptr;               // [ncell] inner iterations per cell (stats)
@@ -624,6 +628,53 @@ int dg_block_solve(dg_problem *pr, int precision, const void *d, void *x, const 
 int dg_block_smooth(dg_problem *pr, int precision, const void *f, const void *u_in, void *u_out,
                     const dg_smooth_opts *opts, dg_smooth_stats *stats, void *stream) {
   return block_smooth_impl(pr, precision, f, u_in, u_out, opts, stats, S(stream), nullptr);
+}
+
+int dg_block_smooth_noalloc(dg_problem *pr, int precision, const void *f, const void *u_in, void *u_out,
+                            const dg_smooth_opts *opts, dg_smooth_stats *stats, void *stream) {
+  if (!pr) {
+    set_error("problem is NULL");
+    return DG_EINVAL;
+  }
+  int rc;
+  if ((rc = check_prec(precision))) return rc;
+  if (!opts) {
+    set_error("smoother options are NULL");
+    return DG_EINVAL;
+  }
+  if (opts->inner == DG_INNER_FDM && !(pr->fdm[DG_FP64] && pr->fdm[DG_FP32])) {
+    set_error("dg_block_smooth_noalloc: the stored factors of DG_INNER_FDM do not exist yet (a call of "
+              "dg_block_smooth with DG_INNER_FDM builds them)");
+    return DG_EINVAL;
+  }
+  int dev = -1;
+  DG_HIP(hipGetDevice(&dev));
+  if (dev != pr->device) {
+    set_error("dg_block_smooth_noalloc: the problem's device is not the current device");
+    return DG_EINVAL;
+  }
+  // scratch layout: [ping-pong vector (Jacobi, n_sweeps > 1)][per-cell
+  // iteration counts][two reduction results]; every part is written before
+  // it is read within one call, so nothing has to start at zero
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const bool jac_alt = opts->sweep == DG_SWEEP_JACOBI && opts->n_sweeps > 1;
+  const size_t alt_bytes = jac_alt ? up((size_t)pr->ndof * esize(precision)) : 0;
+  const size_t cnt_bytes = stats ? up((size_t)pr->ncell * sizeof(int)) : 0;
+  const size_t red_bytes = stats ? 256 : 0;
+  const size_t need = alt_bytes + cnt_bytes + red_bytes;
+  const size_t cap = scratch_capacity();
+  if (need > cap) {
+    set_error("dg_block_smooth_noalloc: needs " + std::to_string(need) + " bytes of scratch, more than its fixed " +
+              std::to_string(cap) + " bytes");
+    return DG_EINVAL;
+  }
+  char *base = nullptr;
+  if (need > 0 && (rc = scratch_device_ptr(dev, (void **)&base))) return rc;
+  ScratchParts sp;
+  sp.alt = jac_alt ? base : nullptr;
+  sp.iters = stats ? (int *)(base + alt_bytes) : nullptr;
+  sp.red = stats ? (unsigned long long *)(base + alt_bytes + cnt_bytes) : nullptr;
+  return block_smooth_impl(pr, precision, f, u_in, u_out, opts, stats, S(stream), &sp);
 }
 
 int dg_mg_vcycle(dg_problem *pr, int precision, const void *r, void *z, const dg_mg_opts *opts, void *stream) {
