@@ -204,8 +204,9 @@ def pe2000_leg(p: int = 3) -> dict:
     Reported as time per unknown, the paper's unit for this test."""
     import torch
 
-    from paper_1805_11930_amd import (DG_FP32, DG_FP64, DG_INNER_GMRES, DG_IPREC_TRIDIAG, DG_KRYLOV_FGMRES,
-                                      DG_PRECOND_BLOCK, DG_SWEEP_SSOR, Problem, ProblemSpec, inputs, solve_opts)
+    from paper_1805_11930_amd import (DG_FP32, DG_FP64, DG_INNER_GMRES, DG_INNER_PMF, DG_IPREC_TRIDIAG,
+                                      DG_KRYLOV_FGMRES, DG_PRECOND_BLOCK, DG_SWEEP_SSOR, Problem, ProblemSpec, inputs,
+                                      solve_opts)
 
     out = {"preconditioner": "2 x block-SSOR in the 12-colour diagonal order, inner GMRES(8) eps=1e-2 with the "
                              "Thomas preconditioner",
@@ -235,6 +236,20 @@ def pe2000_leg(p: int = 3) -> dict:
                 row["apply_fp64_gdofs"] = round(P.ndof * best.n_apply / max(best.t_apply, 1e-30) / 1e9, 2)
             log(f"[bench] Pe=2000 {tag} {name}: {best.t_solve * 1e3:.1f} ms, {best.iters} it, "
                 f"rel_res {best.rel_residual:.2e}")
+            # partially matrix-free: the same SSOR steps with exact block
+            # solves by the stored inverses (the paper's PMF variant)
+            op = solve_opts(krylov=DG_KRYLOV_FGMRES, restart=30, precond=DG_PRECOND_BLOCK, precond_precision=prec,
+                            rtol=1e-8, maxit=300,
+                            smooth=dict(n_sweeps=2, sweep=DG_SWEEP_SSOR, omega=1.0, inner=DG_INNER_PMF, colours=12))
+            bp = None
+            for _ in range(3):
+                u.zero_()
+                _, r = P.solve(f, u, op)
+                bp = r if bp is None or r.t_solve < bp.t_solve else bp
+            row[name + "_pmf"] = {"time_to_solve_s": round(bp.t_solve, 4), "iterations": bp.iters,
+                                  "rel_residual": bp.rel_residual,
+                                  "us_per_dof": round(bp.t_solve / P.ndof * 1e6, 5)}
+            log(f"[bench] Pe=2000 {tag} {name} PMF: {bp.t_solve * 1e3:.1f} ms, {bp.iters} it")
         out[tag] = row
         P.close()
     return out
@@ -341,7 +356,61 @@ def apply_kernel_name(w) -> str:
     return f"k_apply<{w.p}, double, true, 0, false, {'true' if is_convective(w) else 'false'}>"
 
 
-def solve_leg(w, steps: int, warmup: int, coarse_opt: str = "auto", smoother_rows: bool = True) -> dict:
+def pmf_rows(P, w, f, opts, steps: int) -> dict:
+    """The partially matrix-free variant (Sec. 4.1): the same solves with
+    the block solves done by the stored inverses of the blocks D_T (built
+    on the device on first use; the build is timed as setup)."""
+    import torch
+
+    from paper_1805_11930_amd import DG_FP32, DG_FP64, DG_INNER_PMF, smooth_opts
+
+    f32 = f.float() / f.norm()
+    u32 = torch.zeros_like(f32)
+    out32 = torch.empty_like(f32)
+    smp = smooth_opts(inner=DG_INNER_PMF)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.block_smooth(f32, u32, smp, out=out32)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    t_sm = event_time(lambda: P.block_smooth(f32, u32, smp, out=out32), 5)
+    nn = (w.p + 1) ** 3
+    mat_bytes = P.ncell * nn * nn * 4
+    u = torch.zeros_like(f)
+    res = {}
+    for name, prec in (("fp64", DG_FP64), ("mixed", DG_FP32)):
+        o = opts(prec)
+        o.mg.smooth.inner = DG_INNER_PMF
+        o.mg.smooth.inner_precond = 0  # an exact block solve has no inner preconditioner
+        rs = []
+        for _ in range(steps + 1):
+            u.zero_()
+            _, r = P.solve(f, u, o)
+            rs.append(r)
+        res[name] = rs[1:]
+    import numpy as np
+
+    row = {
+        "inner": "stored inverse of every block D_T (partially matrix-free)",
+        "build_s": round(t_build, 4),
+        "stored_bytes_fp64_fp32": int(P.ncell * nn * nn * 12),
+        "smoother_sweep_fp32_ms": round(t_sm * 1e3, 4),
+        "smoother_sweep_roofline": {"bound": "hbm", "kernel": f"k_smooth<{w.p}, 3, float, ...> (stored inverse)",
+                                    "achieved": round(mat_bytes / t_sm / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(mat_bytes / t_sm / 1e9 / HBM_PEAK_GBS, 4),
+                                    "bytes_per_launch": int(mat_bytes)},
+        "time_to_solve_s": {k: round(float(np.median([r.t_solve for r in v])), 5) for k, v in res.items()},
+        "iterations": {k: v[-1].iters for k, v in res.items()},
+        "rel_residual": {k: v[-1].rel_residual for k, v in res.items()},
+    }
+    log(f"[bench] {w.name} PMF: build {t_build * 1e3:.1f} ms, sweep {t_sm * 1e3:.3f} ms, FP64-prec "
+        f"{row['time_to_solve_s']['fp64'] * 1e3:.1f} ms ({row['iterations']['fp64']} it), mixed "
+        f"{row['time_to_solve_s']['mixed'] * 1e3:.1f} ms ({row['iterations']['mixed']} it)")
+    return row
+
+
+def solve_leg(w, steps: int, warmup: int, coarse_opt: str = "auto", smoother_rows: bool = True,
+              pmf: bool = True) -> dict:
     """One workload: FP64-preconditioned and mixed-precision solves (each
     time-to-solve from dg_solve_result.t_solve, setup separately), the FP64
     applies inside the mixed solves (dispatch-recorded events), per-result
@@ -456,6 +525,8 @@ def solve_leg(w, steps: int, warmup: int, coarse_opt: str = "auto", smoother_row
 
             mo = mg_opts(smooth=smd, coarse_space=DG_COARSE_Q1 if coarse_name == "q1" else DG_COARSE_P0)
             out["vcycle_fp32_ms"] = round(event_time(lambda: P.mg_vcycle(f32, mo, out=out32), 5) * 1e3, 4)
+    if pmf and w.p <= 4:
+        out["pmf"] = pmf_rows(P, w, f, opts, steps)
     log(f"[bench] {w.name}: FP64-prec {out['time_to_solve_s']['fp64'] * 1e3:.1f} ms ({out['iterations']['fp64']} it), "
         f"mixed {out['time_to_solve_s']['mixed'] * 1e3:.1f} ms ({out['iterations']['mixed']} it), apply "
         f"{out['apply_fp64_gdofs_in_solve']} GDOF/s (frac {out['roofline']['frac']}), errors {err}, inner {inner}")

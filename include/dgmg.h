@@ -57,7 +57,7 @@ extern "C" {
 
 enum { DG_FP64 = 0, DG_FP32 = 1 };
 enum { DG_BC_DIRICHLET = 0, DG_BC_NEUMANN = 1 };
-enum { DG_INNER_CG = 0, DG_INNER_GMRES = 1, DG_INNER_FDM = 2 };
+enum { DG_INNER_CG = 0, DG_INNER_GMRES = 1, DG_INNER_FDM = 2, DG_INNER_PMF = 3 };
 enum { DG_KRYLOV_CG = 0, DG_KRYLOV_FCG = 1, DG_KRYLOV_FGMRES = 2 };
 enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK = 1, DG_PRECOND_MG = 2 };
 #define DG_PRECOND_BLOCK_JACOBI DG_PRECOND_BLOCK
@@ -131,7 +131,13 @@ typedef struct {
                        iterative block solves; DG_INNER_FDM (b = 0 only):
                        exact block solve with stored per-cell factors (fast
                        diagonalisation of the Kronecker-sum block, built on
-                       first use; eps, max_inner, restart are ignored)     */
+                       first use; eps, max_inner, restart are ignored);
+                       DG_INNER_PMF (any b, p <= 4): the partially
+                       matrix-free variant of Sec. 4.1 -- exact block solve
+                       with the stored inverse of every block D_T
+                       ((p+1)^6 numbers per cell, built on the device on
+                       first use in FP64, FP32 its rounding; eps,
+                       max_inner, restart, inner_precond are ignored)     */
   int restart;      /* inner GMRES restart length, 1..16 (<= 0: 12)        */
   int zero_guess;   /* 1: u_in is taken as zero and not read                */
   int sweep;        /* DG_SWEEP_* (default DG_SWEEP_JACOBI)                 */

@@ -21,7 +21,7 @@ DG_EINVAL, DG_ENOMEM, DG_EDEVICE, DG_EBREAKDOWN = -1, -2, -3, -4
 DG_MAX_P = 5
 DG_FP64, DG_FP32 = 0, 1
 DG_BC_DIRICHLET, DG_BC_NEUMANN = 0, 1
-DG_INNER_CG, DG_INNER_GMRES, DG_INNER_FDM = 0, 1, 2
+DG_INNER_CG, DG_INNER_GMRES, DG_INNER_FDM, DG_INNER_PMF = 0, 1, 2, 3
 DG_KRYLOV_CG, DG_KRYLOV_FCG, DG_KRYLOV_FGMRES = 0, 1, 2
 DG_PRECOND_NONE, DG_PRECOND_BLOCK, DG_PRECOND_MG = 0, 1, 2
 DG_PRECOND_BLOCK_JACOBI = DG_PRECOND_BLOCK

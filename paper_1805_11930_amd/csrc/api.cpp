@@ -74,18 +74,24 @@ int smooth_args(dg_problem *pr, const dg_smooth_opts *o, SmoothArgs &a) {
     return DG_EINVAL;
   }
   if (!(o->eps >= 0) || !std::isfinite(o->omega) ||
-      (o->inner != DG_INNER_CG && o->inner != DG_INNER_GMRES && o->inner != DG_INNER_FDM) ||
+      (o->inner != DG_INNER_CG && o->inner != DG_INNER_GMRES && o->inner != DG_INNER_FDM &&
+       o->inner != DG_INNER_PMF) ||
       o->sweep < DG_SWEEP_JACOBI || o->sweep > DG_SWEEP_SOR_BACKWARD ||
       (o->inner_precond != DG_IPREC_DIAG && o->inner_precond != DG_IPREC_TRIDIAG) ||
       (o->inner_precond == DG_IPREC_TRIDIAG && o->inner != DG_INNER_GMRES) || o->colours > 64) {
     set_error(
-        "invalid smoother options (eps >= 0, finite omega, inner CG, GMRES or FDM, sweep DG_SWEEP_*, "
+        "invalid smoother options (eps >= 0, finite omega, inner CG, GMRES, FDM or PMF, sweep DG_SWEEP_*, "
         "inner_precond DG_IPREC_DIAG, or DG_IPREC_TRIDIAG with inner GMRES, colours <= 64)");
     return DG_EINVAL;
   }
   if (o->inner == DG_INNER_FDM) {
     int rc = ensure_fdm(pr, DG_FP64);
     if (!rc) rc = ensure_fdm(pr, DG_FP32);
+    if (rc) return rc;
+  }
+  if (o->inner == DG_INNER_PMF) {
+    int rc = ensure_pmf(pr, DG_FP64);
+    if (!rc) rc = ensure_pmf(pr, DG_FP32);
     if (rc) return rc;
   }
   a.omega = o->omega;
@@ -642,9 +648,10 @@ int dg_block_smooth_noalloc(dg_problem *pr, int precision, const void *f, const 
     set_error("smoother options are NULL");
     return DG_EINVAL;
   }
-  if (opts->inner == DG_INNER_FDM && !(pr->fdm[DG_FP64] && pr->fdm[DG_FP32])) {
-    set_error("dg_block_smooth_noalloc: the stored factors of DG_INNER_FDM do not exist yet (a call of "
-              "dg_block_smooth with DG_INNER_FDM builds them)");
+  if ((opts->inner == DG_INNER_FDM && !(pr->fdm[DG_FP64] && pr->fdm[DG_FP32])) ||
+      (opts->inner == DG_INNER_PMF && !(pr->pmf[DG_FP64] && pr->pmf[DG_FP32]))) {
+    set_error("dg_block_smooth_noalloc: the stored factors of DG_INNER_FDM / DG_INNER_PMF do not exist yet (a "
+              "call of dg_block_smooth with that inner solve builds them)");
     return DG_EINVAL;
   }
   int dev = -1;

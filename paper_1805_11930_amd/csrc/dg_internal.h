@@ -238,6 +238,8 @@ struct dg_problem {
   dgmg::Hierarchy p0h, q1h;
   void *corner_buf[2] = {nullptr, nullptr};  // [ncell][8] Q1 corner sums per precision
   void *fdm[2] = {nullptr, nullptr};          // fast-diagonalisation factors per precision
+  void *pmf[2] = {nullptr, nullptr};          // stored block inverses per precision (DG_INNER_PMF)
+  int pmf_built = 0;                          // 0: not yet, 1: ready, < 0: failed with that status
   std::vector<dgmg::CoarseGraph> graphs;      // captured coarse solves
   hipStream_t capture_stream = nullptr;       // private stream used only for capturing
   // DG-sized temporaries for the V-cycle and smoother (allocated lazily)
@@ -295,5 +297,8 @@ int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin
                   const SmoothArgs &a, int *iters, hipStream_t s);
 // fast-diagonalisation factors of the cell blocks (b = 0), built on first use
 int ensure_fdm(dg_problem *pr, int prec);
+// stored inverses of the cell blocks D_T (any b, p <= 4), built on first use
+int ensure_pmf(dg_problem *pr, int prec);
+size_t pmf_bytes(const dg_problem *pr, int prec);
 
 }  // namespace dgmg

@@ -307,6 +307,7 @@ void dg_problem_destroy(dg_problem *pr) {
   }
   for (void *p : pr->corner_buf) (void)hipFree(p);
   for (void *p : pr->fdm) (void)hipFree(p);
+  for (void *p : pr->pmf) (void)hipFree(p);
   for (auto &cg : pr->graphs) (void)hipGraphExecDestroy(cg.exec);
   if (pr->capture_stream) (void)hipStreamDestroy(pr->capture_stream);
   for (auto &row : pr->mg_tmp)

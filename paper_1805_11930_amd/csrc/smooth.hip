@@ -29,7 +29,10 @@
 //          estimate <= eps ||d_T||_2 or after max_inner applications.
 // and, for b = 0, the exact solve with stored factors (fdm.hip):
 //   FDM:   x = (Tz (x) Ty (x) Tx) diag(1/(lx+ly+lz)) (Tz (x) Ty (x) Tx)^T d,
-//          the six contractions through the same LDS transposes.
+//          the six contractions through the same LDS transposes;
+// and, for any b, the partially matrix-free exact solve (pmf.hip):
+//   PMF:   x = D_T^-1 d with the stored inverse of the block, one dense
+//          product per cell streamed from memory.
 #include "line_ops.h"
 
 namespace dgmg {
@@ -362,7 +365,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
           Lm[k * N + (j - S::N2)] = val;
       }
     }
-  } else if (Ms && on) {
+  } else if (INNER != DG_INNER_PMF && Ms && on) {
 #pragma unroll
     for (int k = 0; k < 3; ++k)
       Ms[k * S::N2 + a * N + b] = line_matrix_entry<T, N>(tb, cl.f[k], cl.vol, k == 0 ? cl.cre : T(0), a, b);
@@ -449,7 +452,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     T dd = T(1);
-    if (INNER == DG_INNER_FDM) {
+    if (INNER == DG_INNER_FDM || INNER == DG_INNER_PMF) {
       // not used
     } else if (on && Ms) {
       // DOF (i, a, b): x-line (a, b), y-line (x=i, z=b), z-line (x=i, y=a)
@@ -493,7 +496,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   // registers allow, the lane's three line operators of D_T (zero
   // neighbour traces) are built once as N x N matrices: column l is the
   // operator applied to the unit vector e_l.
-  constexpr bool REGM = HASB && INNER != DG_INNER_FDM && (sizeof(T) == 4 ? N <= 5 : N <= 4);
+  constexpr bool REGM = HASB && INNER != DG_INNER_FDM && INNER != DG_INNER_PMF && (sizeof(T) == 4 ? N <= 5 : N <= 4);
   T Mr[3][S::N2];
   if constexpr (REGM) {
 #pragma unroll
@@ -572,6 +575,26 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
 #pragma unroll
       for (int i = 0; i < N; ++i) u1[i] = Ps[lpos<N>(0, i, a, b)];
       contract<T, N, false>(Tx, u1, x);
+    }
+    it = dn2 > T(0) ? 1 : 0;
+  } else if (INNER == DG_INNER_PMF) {
+    // x = D_T^-1 d with the stored inverse (pmf.hip), column by column: the
+    // cell's defect goes to LDS, and step J adds d_J times column J of the
+    // inverse, which the cell's lanes read as one contiguous run of (p+1)^3
+    // values (each lane the N entries of its x-line)
+    if (on) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) Ps[lpos<N>(0, i, a, b)] = d[i];
+    }
+    __syncthreads();
+    if (on) {
+      const T *col = fdm + (size_t)c * S::N3 * S::N3 + lpos<N>(0, 0, a, b);
+#pragma unroll 4
+      for (int J = 0; J < S::N3; ++J) {
+        const T dj = Ps[J];
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] += col[(size_t)J * S::N3 + i] * dj;
+      }
     }
     it = dn2 > T(0) ? 1 : 0;
   } else if (INNER == DG_INNER_CG) {
@@ -863,7 +886,7 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
   const bool hb = pr->geo.has_b != 0;
 #define DG_SMOOTH_LAUNCH_RM(INNER, HB, TRI, RM)                                                                 \
   hipLaunchKernelGGL((k_smooth<P, INNER, T, HB, TRI, RM>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo,        \
-                     (const T *)f, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh, (const T *)fdm)
+                     (const T *)f, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh, (const T *)factors)
   // inner GMRES takes the smallest build that holds its restart length
 #define DG_SMOOTH_LAUNCH(INNER, HB, TRI) DG_SMOOTH_LAUNCH_RM(INNER, HB, TRI, kGmresMax)
 #define DG_SMOOTH_LAUNCH_GMRES(HB, TRI)                    \
@@ -875,13 +898,24 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
     else                                                   \
       DG_SMOOTH_LAUNCH_RM(DG_INNER_GMRES, HB, TRI, kGmresMax); \
   } while (0)
-  const void *fdm = pr->fdm[sizeof(T) == 8 ? DG_FP64 : DG_FP32];
+  // stored per-cell factors of the exact block solves (FDM, PMF)
+  const int pi = sizeof(T) == 8 ? DG_FP64 : DG_FP32;
+  const void *factors = a.inner == DG_INNER_PMF ? pr->pmf[pi] : pr->fdm[pi];
   if (a.inner == DG_INNER_FDM) {
-    if (hb || !fdm) {
+    if (hb || !factors) {
       set_error("the fast-diagonalisation block solve needs b = 0 and its factors");
       return DG_EINVAL;
     }
     DG_SMOOTH_LAUNCH(DG_INNER_FDM, false, false);
+  } else if (a.inner == DG_INNER_PMF) {
+    if (!factors || a.tridiag) {
+      set_error("the stored-inverse block solve needs its factors (and no inner preconditioner)");
+      return DG_EINVAL;
+    }
+    if (hb)
+      DG_SMOOTH_LAUNCH(DG_INNER_PMF, true, false);
+    else
+      DG_SMOOTH_LAUNCH(DG_INNER_PMF, false, false);
   } else if (a.inner == DG_INNER_CG) {
     if (a.tridiag) {
       set_error("the tridiagonal inner preconditioner needs inner GMRES");

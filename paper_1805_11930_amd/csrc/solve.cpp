@@ -372,6 +372,8 @@ extern "C" int dg_footprint(const dg_problem_desc *d, const dg_solve_opts *o, si
     b += ndof * pe;
   if (o->precond != DG_PRECOND_NONE && o->mg.smooth.inner == DG_INNER_FDM)
     b += ncell * 3 * (int64_t)(d->p + 1) * (d->p + 2) * both;  // stored factors T_k, lambda_k
+  if (o->precond != DG_PRECOND_NONE && o->mg.smooth.inner == DG_INNER_PMF)
+    b += (size_t)ncell * nloc * nloc * both;  // stored block inverses, FP64 and FP32
   if (o->precond_precision == DG_FP32 && o->precond != DG_PRECOND_NONE) b += 2 * ndof * sizeof(float);
   int64_t nvec = 2;  // residual + temporary of dg_solve
   if (o->krylov == DG_KRYLOV_FGMRES) {
