@@ -317,13 +317,20 @@ def is_convective(w) -> bool:
     return bool(tuple(w.b0) != (0.0, 0.0, 0.0) or np.any(np.asarray(w.B) != 0))
 
 
-def leg_settings(w, coarse_opt: str = "auto"):
+# workloads whose coarse problem is solved by the aggregation AMG (two
+# cycles, two Jacobi sweeps per level): the SPE10-like field and the
+# convection box; the isotropic Poisson boxes keep the geometric cycle
+AMG_WORKLOADS = ("spe10-like", "convection-48")
+
+
+def leg_settings(w, coarse_opt: str = "auto", coarse_solver: str = "auto"):
     """Solver settings of a workload: (solve-option builder, smoother dict,
     coarse-space name, description).  The 8^3 Poisson problem takes one
     block-Jacobi sweep as the preconditioner of CG to 1e-10 (its stated
     solve); the others the hybrid V-cycle to 1e-8: FCG and block-Jacobi with
     inner PCG for diffusion, FGMRES(30) and inner GMRES(8) with the Thomas
-    preconditioner for convection (Sec. 3.2, 4.3)."""
+    preconditioner for convection (Sec. 3.2, 4.3); the coarse problem by the
+    geometric cycle or the aggregation AMG (AMG_WORKLOADS)."""
     from paper_1805_11930_amd import (DG_COARSE_P0, DG_COARSE_Q1, DG_INNER_CG, DG_INNER_GMRES, DG_IPREC_DIAG,
                                       DG_IPREC_TRIDIAG, DG_KRYLOV_FCG, DG_KRYLOV_FGMRES, DG_PRECOND_BLOCK,
                                       DG_PRECOND_MG, solve_opts)
@@ -343,12 +350,18 @@ def leg_settings(w, coarse_opt: str = "auto"):
         desc = "flexible CG to 1e-10, one block-Jacobi sweep (inner PCG eps 1e-2) as preconditioner"
         return opts, sm, "none", desc
 
+    amg = coarse_solver == "amg" or (coarse_solver == "auto" and w.name.startswith(AMG_WORKLOADS))
+    mg = dict(coarse_space=coarse)
+    if amg:
+        mg.update(coarse_solver=1, coarse_cycles=2, coarse_smooth=2)
+
     def opts(prec, **kw):
         return solve_opts(krylov=krylov, restart=30, precond=DG_PRECOND_MG, precond_precision=prec, rtol=1e-8,
-                          maxit=1000, smooth=sm, mg=dict(coarse_space=coarse), **kw)
+                          maxit=1000, smooth=sm, mg=mg, **kw)
     desc = (("FGMRES(30)" if conv else "flexible CG") + " to 1e-8, hybrid V-cycle (block-Jacobi, " +
             ("inner GMRES(8) with the Thomas preconditioner" if conv else "inner PCG") +
-            f" eps 1e-2, {coarse_name.upper()} coarse space)")
+            f" eps 1e-2, {coarse_name.upper()} coarse space, " +
+            ("aggregation AMG coarse solver, 2 cycles)" if amg else "geometric coarse cycle)"))
     return opts, sm, coarse_name, desc
 
 
@@ -523,7 +536,10 @@ def solve_leg(w, steps: int, warmup: int, coarse_opt: str = "auto", smoother_row
         if coarse_name != "none":
             from paper_1805_11930_amd import DG_COARSE_P0, DG_COARSE_Q1
 
-            mo = mg_opts(smooth=smd, coarse_space=DG_COARSE_Q1 if coarse_name == "q1" else DG_COARSE_P0)
+            o1 = opts(1)
+            mo = mg_opts(smooth=smd, coarse_space=DG_COARSE_Q1 if coarse_name == "q1" else DG_COARSE_P0,
+                         coarse_solver=o1.mg.coarse_solver, coarse_cycles=o1.mg.coarse_cycles,
+                         coarse_smooth=o1.mg.coarse_smooth)
             out["vcycle_fp32_ms"] = round(event_time(lambda: P.mg_vcycle(f32, mo, out=out32), 5) * 1e3, 4)
     if pmf and w.p <= 4:
         out["pmf"] = pmf_rows(P, w, f, opts, steps)

@@ -72,6 +72,7 @@ enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK = 1, DG_PRECOND_MG = 2 };
 enum { DG_SWEEP_JACOBI = 0, DG_SWEEP_SOR = 1, DG_SWEEP_SSOR = 2, DG_SWEEP_SOR_BACKWARD = 3 };
 enum { DG_IPREC_DIAG = 0, DG_IPREC_TRIDIAG = 1 };
 enum { DG_COARSE_P0 = 0, DG_COARSE_Q1 = 1, DG_COARSE_AUTO = 2 };
+enum { DG_COARSE_SOLVER_GEOMETRIC = 0, DG_COARSE_SOLVER_AMG = 1 };
 enum { DG_FIELD_NONE = 0, DG_FIELD_AXIS_QUADRATIC = 1, DG_FIELD_ROTATED_QUADRATIC = 2 };
 
 typedef struct dg_problem dg_problem;          /* opaque, library-owned */
@@ -192,6 +193,21 @@ typedef struct {
   int graph;                /* 1: replay the coarse solve from a HIP graph
                                (captured on first use per option set, kernel
                                nodes only); 0: launch its kernels directly */
+  int coarse_solver;        /* DG_COARSE_SOLVER_GEOMETRIC (default): the
+                               structured cycles above;
+                               DG_COARSE_SOLVER_AMG: smoothed-aggregation
+                               AMG on the coarse-space matrix (the paper
+                               solves the coarse problem by AMG, Sec. 2.2):
+                               strength max(|a_ij|, |a_ji|) >= theta
+                               sqrt(|a_ii a_jj|) (theta = 0.08, halved per
+                               level), greedy aggregation, prolongation
+                               smoothed once by damped Jacobi on the
+                               filtered matrix, R = P^T, Galerkin coarse
+                               matrices, CSR levels down to <= 1024 unknowns
+                               (dense inverse).  Set up on the host on first
+                               use; cycled on the device with the same
+                               damped Jacobi (coarse_smooth, coarse_omega,
+                               coarse_cycles) as the geometric solver.     */
 } dg_mg_opts;
 
 /* Outer solve options (Sec. 4.2: CG to 1e-8; Sec. 4.3: flexible GMRES). */
@@ -342,6 +358,16 @@ int dg_solve(dg_problem *prob, const double *f, double *u, const dg_solve_opts *
  * number of levels.  When out is not NULL it receives the FP64 stencil,
  * HOST [ns][vx*vy*vz].  Synchronous.  DG_EINVAL for a level out of range. */
 int dg_coarse_stencil(dg_problem *prob, int coarse_space, int level, int *dims, double *out);
+/* The aggregation-AMG hierarchy of the P0 or Q1 coarse space (built if
+ * needed): level 0 is the coarse-space matrix A_hat itself, level l >= 1
+ * the Galerkin product A_l = R_l A_(l-1) P_l.  which = 0: A_l; 1: P_l
+ * (rows: unknowns of level l-1, columns: of level l); 2: R_l = P_l^T
+ * (level >= 1 for 1 and 2).  dims (HOST int64[4]) receives (rows, cols,
+ * nnz, nlevels); when row_ptr is not NULL, HOST arrays row_ptr [rows+1],
+ * col [nnz] and val [nnz] receive the FP64 CSR matrix (sorted columns).
+ * Synchronous.  DG_EINVAL for a level or matrix out of range. */
+int dg_coarse_csr(dg_problem *prob, int coarse_space, int level, int which, int64_t *dims, int *row_ptr, int *col,
+                  double *val);
 
 /* ---- resident solves and continuous batching ---------------------- */
 /* Start an outer CG / flexible-CG solve of A u = f (options as dg_solve;

@@ -28,6 +28,7 @@ DG_PRECOND_BLOCK_JACOBI = DG_PRECOND_BLOCK
 DG_SWEEP_JACOBI, DG_SWEEP_SOR, DG_SWEEP_SSOR, DG_SWEEP_SOR_BACKWARD = 0, 1, 2, 3
 DG_IPREC_DIAG, DG_IPREC_TRIDIAG = 0, 1
 DG_COARSE_P0, DG_COARSE_Q1, DG_COARSE_AUTO = 0, 1, 2
+DG_COARSE_SOLVER_GEOMETRIC, DG_COARSE_SOLVER_AMG = 0, 1
 DG_FIELD_NONE, DG_FIELD_AXIS_QUADRATIC, DG_FIELD_ROTATED_QUADRATIC = 0, 1, 2
 
 EXPORTS = (
@@ -36,6 +37,7 @@ EXPORTS = (
     "dg_block_diag", "dg_block_solve", "dg_block_smooth", "dg_mg_vcycle", "dg_solve", "dg_footprint",
     "dg_coarse_stencil", "dg_default_smooth_opts", "dg_default_mg_opts", "dg_default_solve_opts",
     "dg_solve_start", "dg_batch_step", "dg_solve_poll", "dg_solve_state_destroy", "dg_block_smooth_noalloc",
+    "dg_coarse_csr",
 )
 
 
@@ -76,7 +78,7 @@ class MgOpts(ctypes.Structure):
     _fields_ = [
         ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int), ("smooth", SmoothOpts),
         ("coarse_space", ctypes.c_int), ("coarse_cycles", ctypes.c_int), ("coarse_smooth", ctypes.c_int),
-        ("coarse_omega", ctypes.c_double), ("graph", ctypes.c_int),
+        ("coarse_omega", ctypes.c_double), ("graph", ctypes.c_int), ("coarse_solver", ctypes.c_int),
     ]
 
 
@@ -132,6 +134,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveResult), vp]
     lib.dg_footprint.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(SolveOpts), ctypes.POINTER(ctypes.c_size_t)]
     lib.dg_coarse_stencil.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), vp]
+    lib.dg_coarse_csr.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), vp,
+                                  vp, vp]
     lib.dg_default_smooth_opts.argtypes = [ctypes.POINTER(SmoothOpts)]
     lib.dg_default_smooth_opts.restype = None
     lib.dg_default_mg_opts.argtypes = [ctypes.POINTER(MgOpts)]

@@ -16,6 +16,8 @@ int scratch_device_ptr(int device, void **out);
 int alloc_tmp(dg_problem *pr, int prec, int k, void **out);
 int alloc_small(dg_problem *pr);
 int ensure_hierarchy(dg_problem *pr, int kind);
+int ensure_amg(dg_problem *pr, int kind);
+int amg_level_csr(dg_problem *pr, int kind, int level, int which, int64_t *dims, int *rp, int *ci, double *v);
 
 int validate_mg_opts(const dg_mg_opts *o) {
   if (o->n_pre < 0 || o->n_post < 0 || o->n_pre > 64 || o->n_post > 64) {
@@ -28,6 +30,10 @@ int validate_mg_opts(const dg_mg_opts *o) {
   }
   if (o->coarse_cycles < 0 || o->coarse_cycles > 64 || o->coarse_smooth < 0 || o->coarse_smooth > 64) {
     set_error("coarse_cycles and coarse_smooth must be in 0..64");
+    return DG_EINVAL;
+  }
+  if (o->coarse_solver != DG_COARSE_SOLVER_GEOMETRIC && o->coarse_solver != DG_COARSE_SOLVER_AMG) {
+    set_error("coarse_solver must be DG_COARSE_SOLVER_GEOMETRIC or DG_COARSE_SOLVER_AMG");
     return DG_EINVAL;
   }
   return DG_OK;
@@ -216,6 +222,8 @@ struct LevelPtr<double> {
   static const double *A(const CoarseLevel &L) { return L.A64; }
   static const double *dinv(const CoarseLevel &L) { return L.dinv64; }
   static const double *inv(const Hierarchy &H) { return H.inv64; }
+  static const double *pv(const CoarseLevel &L) { return L.pv64; }
+  static const double *rv(const CoarseLevel &L) { return L.rv64; }
 };
 template <>
 struct LevelPtr<float> {
@@ -227,13 +235,25 @@ struct LevelPtr<float> {
   static const float *A(const CoarseLevel &L) { return L.A32; }
   static const float *dinv(const CoarseLevel &L) { return L.dinv32; }
   static const float *inv(const Hierarchy &H) { return H.inv32; }
+  static const float *pv(const CoarseLevel &L) { return L.pv32; }
+  static const float *rv(const CoarseLevel &L) { return L.rv32; }
 };
 
 template <typename T>
 int level_jacobi(const CoarseLevel &L, T w, const T *r, const T *xi, T *xo, hipStream_t s) {
   const T *A = LevelPtr<T>::A(L);
+  if (L.ns == 0) return csr_jacobi<T>(L.n, L.nnz, L.rp, L.ci, A, LevelPtr<T>::dinv(L), w, r, xi, xo, s);
   return L.ns == 27 ? jacobi27<T>(A, LevelPtr<T>::dinv(L), L.nx, L.ny, L.nz, w, r, xi, xo, s)
                     : coarse_jacobi<T>(A, L.nx, L.ny, L.nz, w, r, xi, xo, s);
+}
+
+// out = r - A_l x on a level of any kind
+template <typename T>
+int level_residual(const CoarseLevel &L, const T *r, const T *x, T *out, hipStream_t s) {
+  const T *A = LevelPtr<T>::A(L);
+  if (L.ns == 0) return csr_residual<T>(L.n, L.nnz, L.rp, L.ci, A, r, x, out, s);
+  return L.ns == 27 ? residual27<T>(A, L.nx, L.ny, L.nz, r, x, out, s)
+                    : residual7<T>(A, L.nx, L.ny, L.nz, r, x, out, s);
 }
 
 // x_l ~= A_l^-1 r_l: one V-cycle of the hierarchy from a zero guess; r_l is
@@ -259,8 +279,13 @@ int coarse_cycle(Hierarchy &H, size_t l, int nu, T w, hipStream_t s, T **result,
     std::swap(x, t);
   }
   CoarseLevel &C = H.levels[l + 1];
-  const bool fuse = L.ns == 27 && l + 2 < H.levels.size();  // the coarser level smooths
-  if (L.ns == 27) {
+  // the coarser level smooths: its first sweep is fused into the restriction
+  const bool fuse = L.ns == 27 && C.ns == 27 && l + 2 < H.levels.size();
+  if (C.ns == 0) {
+    // aggregation AMG level below: r_C = R (r - A x)
+    if ((rc = level_residual<T>(L, r, x, t, s))) return rc;
+    if ((rc = csr_spmv<T>(C.n, C.pnnz, C.rrp, C.rci, LP::rv(C), t, LP::r(C), false, s))) return rc;
+  } else if (L.ns == 27) {
     if ((rc = residual27<T>(A, L.nx, L.ny, L.nz, r, x, t, s))) return rc;
     if ((rc = restrict27<T>(L.nx, L.ny, L.nz, t, C.nx, C.ny, C.nz, LP::r(C), LP::dinv(C), w,
                             fuse ? LP::x(C) : nullptr, s)))
@@ -270,7 +295,9 @@ int coarse_cycle(Hierarchy &H, size_t l, int nu, T w, hipStream_t s, T **result,
   }
   T *xc = nullptr;
   if ((rc = coarse_cycle<T>(H, l + 1, nu, w, s, &xc, fuse))) return rc;
-  if (L.ns == 27)
+  if (C.ns == 0)
+    rc = csr_spmv<T>(L.n, C.pnnz, C.prp, C.pci, LP::pv(C), xc, x, true, s);  // x += P x_C
+  else if (L.ns == 27)
     rc = prolong27<T>(L.nx, L.ny, L.nz, C.nx, C.ny, C.nz, xc, x, s);
   else
     rc = coarse_prolong<T>(L.nx, L.ny, L.nz, C.nx, C.ny, xc, x, s);
@@ -300,11 +327,7 @@ int coarse_solve(Hierarchy &H, int cycles, int nu, T w, hipStream_t s, T **resul
   if ((rc = coarse_cycle<T>(H, 0, nu, w, s, &x, x_init))) return rc;
   if ((rc = copy_vec<T>(n, x, acc, s))) return rc;
   for (int c = 1; c < cycles; ++c) {
-    if (L.ns == 27)
-      rc = residual27<T>(LP::A(L), L.nx, L.ny, L.nz, rs, acc, LP::r(L), s);
-    else
-      rc = residual7<T>(LP::A(L), L.nx, L.ny, L.nz, rs, acc, LP::r(L), s);
-    if (rc) return rc;
+    if ((rc = level_residual<T>(L, rs, acc, LP::r(L), s))) return rc;
     if ((rc = coarse_cycle<T>(H, 0, nu, w, s, &x, false))) return rc;
     if ((rc = add_to<T>(n, x, acc, s))) return rc;
   }
@@ -322,8 +345,8 @@ int coarse_solve_graph(dg_problem *pr, Hierarchy &H, int prec, int cycles, int n
                        bool x_init) {
   CoarseGraph *hit = nullptr;
   for (auto &cg : pr->graphs)
-    if (cg.kind == H.kind && cg.prec == prec && cg.cycles == cycles && cg.nu == nu && cg.w == (double)w &&
-        cg.x_init == x_init) {
+    if (cg.kind == H.kind && cg.solver == H.solver && cg.prec == prec && cg.cycles == cycles && cg.nu == nu &&
+        cg.w == (double)w && cg.x_init == x_init) {
       hit = &cg;
       break;
     }
@@ -345,6 +368,7 @@ int coarse_solve_graph(dg_problem *pr, Hierarchy &H, int prec, int cycles, int n
     if (e2 != hipSuccess) return hip_fail(e2, "hipGraphInstantiate");
     CoarseGraph cg;
     cg.kind = H.kind;
+    cg.solver = H.solver;
     cg.prec = prec;
     cg.cycles = cycles;
     cg.nu = nu;
@@ -367,7 +391,9 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
   if (rc) return rc;
   const int kind = coarse_kind(o->coarse_space, pr->geo.has_b != 0);
   if ((rc = ensure_hierarchy(pr, kind))) return rc;
-  Hierarchy &H = kind == COARSE_Q1 ? pr->q1h : pr->p0h;
+  const bool amg = o->coarse_solver == DG_COARSE_SOLVER_AMG;
+  if (amg && (rc = ensure_amg(pr, kind))) return rc;
+  Hierarchy &H = kind == COARSE_Q1 ? (amg ? pr->q1amg : pr->q1h) : (amg ? pr->p0amg : pr->p0h);
   void *t0;
   if ((rc = alloc_tmp(pr, prec, 0, &t0))) return rc;
   // presmoothing ends in X so that postsmoothing ends in z without a copy
@@ -548,6 +574,7 @@ void dg_default_mg_opts(dg_mg_opts *o) {
   o->coarse_smooth = 0;
   o->coarse_omega = 2.0 / 3.0;
   o->graph = 1;
+  o->coarse_solver = DG_COARSE_SOLVER_GEOMETRIC;
 }
 
 void dg_default_solve_opts(dg_solve_opts *o) {
@@ -697,6 +724,24 @@ int dg_mg_vcycle(dg_problem *pr, int precision, const void *r, void *z, const dg
   }
   if ((rc = validate_mg_opts(opts))) return rc;
   return vcycle(pr, precision, r, z, opts, S(stream));
+}
+
+int dg_coarse_csr(dg_problem *pr, int coarse_space, int level, int which, int64_t *dims, int *row_ptr, int *col,
+                  double *val) {
+  if (!pr || !dims) {
+    set_error("dg_coarse_csr: problem or dims is NULL");
+    return DG_EINVAL;
+  }
+  if (coarse_space != DG_COARSE_P0 && coarse_space != DG_COARSE_Q1) {
+    set_error("coarse_space must be DG_COARSE_P0 or DG_COARSE_Q1");
+    return DG_EINVAL;
+  }
+  if (row_ptr && (!col || !val)) {
+    set_error("dg_coarse_csr: row_ptr given without col / val");
+    return DG_EINVAL;
+  }
+  return amg_level_csr(pr, coarse_space == DG_COARSE_Q1 ? COARSE_Q1 : COARSE_P0, level, which, dims, row_ptr, col,
+                       val);
 }
 
 int dg_coarse_stencil(dg_problem *pr, int coarse_space, int level, int *dims, double *out) {

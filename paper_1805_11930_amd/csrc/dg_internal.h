@@ -185,6 +185,17 @@ struct CoarseLevel {
   // repeated coarse cycles
   double *acc64 = nullptr, *rs64 = nullptr;
   float *acc32 = nullptr, *rs32 = nullptr;
+  // levels of the aggregation AMG (ns == 0): A in CSR (values in A64 /
+  // A32, nnz of them, sorted columns), and the transfers from the next
+  // finer level of nf unknowns: P (nf x n) and R = P^T (n x nf), CSR
+  int nnz = 0, nf = 0, pnnz = 0;  // entries of A and of P (= of R)
+  int *rp = nullptr, *ci = nullptr;
+  int *prp = nullptr, *pci = nullptr, *rrp = nullptr, *rci = nullptr;
+  double *pv64 = nullptr, *rv64 = nullptr;
+  float *pv32 = nullptr, *rv32 = nullptr;
+  // level 0 of an AMG hierarchy is the structured level 0 of the
+  // geometric hierarchy of the same coarse space (shared, not owned)
+  bool borrowed = false;
 };
 
 // 7-point stencil order: diag, -x, +x, -y, +y, -z, +z.
@@ -202,15 +213,18 @@ inline int coarse_kind(int option, bool has_b) {
 
 // A captured coarse solve (see coarse_solve_graph).
 struct CoarseGraph {
-  int kind, prec, cycles, nu;
+  int kind, solver, prec, cycles, nu;
   double w;
   bool x_init;
   hipGraphExec_t exec;
   void *result;  // device buffer that holds the coarse solution after a launch
 };
 
+enum CoarseSolver : int { SOLVER_GEOMETRIC = 0, SOLVER_AMG = 1 };
+
 struct Hierarchy {
   int kind = COARSE_P0;
+  int solver = SOLVER_GEOMETRIC;
   int built = 0;  // 0: not yet, 1: ready, < 0: failed with that status
   std::vector<CoarseLevel> levels;
   double *inv64 = nullptr;  // dense inverse of the coarsest matrix
@@ -236,6 +250,8 @@ struct dg_problem {
   double aniso = 1.0;
   // coarse hierarchies: P0 (built with the problem) and Q1 (on first use)
   dgmg::Hierarchy p0h, q1h;
+  // aggregation AMG coarse solvers on the same coarse spaces (on first use)
+  dgmg::Hierarchy p0amg, q1amg;
   void *corner_buf[2] = {nullptr, nullptr};  // [ncell][8] Q1 corner sums per precision
   void *fdm[2] = {nullptr, nullptr};          // fast-diagonalisation factors per precision
   void *pmf[2] = {nullptr, nullptr};          // stored block inverses per precision (DG_INNER_PMF)

@@ -297,10 +297,12 @@ void dg_problem_destroy(dg_problem *pr) {
   if (!pr) return;
   (void)hipFree(pr->dK);
   (void)hipFree(pr->dc);
-  for (Hierarchy *H : {&pr->p0h, &pr->q1h}) {
+  for (Hierarchy *H : {&pr->p0h, &pr->q1h, &pr->p0amg, &pr->q1amg}) {
     for (auto &L : H->levels) {
-      for (double *p : {L.A64, L.dinv64, L.r64, L.x64, L.t64, L.acc64, L.rs64}) (void)hipFree(p);
-      for (float *p : {L.A32, L.dinv32, L.r32, L.x32, L.t32, L.acc32, L.rs32}) (void)hipFree(p);
+      if (L.borrowed) continue;  // owned by the geometric hierarchy
+      for (double *p : {L.A64, L.dinv64, L.r64, L.x64, L.t64, L.acc64, L.rs64, L.pv64, L.rv64}) (void)hipFree(p);
+      for (float *p : {L.A32, L.dinv32, L.r32, L.x32, L.t32, L.acc32, L.rs32, L.pv32, L.rv32}) (void)hipFree(p);
+      for (int *p : {L.rp, L.ci, L.prp, L.pci, L.rrp, L.rci}) (void)hipFree(p);
     }
     (void)hipFree(H->inv64);
     (void)hipFree(H->inv32);

@@ -81,6 +81,17 @@ int add_to(int64_t n, const T *x, T *y, hipStream_t s);
 template <typename T>
 int copy_vec(int64_t n, const T *x, T *y, hipStream_t s);
 
+// CSR levels of the aggregation AMG (amg_kernels.hip)
+// (n rows, nnz entries: the mean row length picks the lanes per row)
+template <typename T>
+int csr_jacobi(int n, int nnz, const int *rp, const int *ci, const T *v, const T *dinv, T w, const T *r, const T *xi,
+               T *xo, hipStream_t s);
+template <typename T>
+int csr_residual(int n, int nnz, const int *rp, const int *ci, const T *v, const T *r, const T *x, T *out,
+                 hipStream_t s);
+template <typename T>
+int csr_spmv(int n, int nnz, const int *rp, const int *ci, const T *v, const T *x, T *y, bool add, hipStream_t s);
+
 constexpr int kMaxBasis = 32;
 struct VecList {
   const double *v[kMaxBasis];

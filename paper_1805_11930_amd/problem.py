@@ -7,6 +7,7 @@ Only argument marshalling happens here.
 from __future__ import annotations
 
 import ctypes
+import sys
 
 import numpy as np
 import torch
@@ -62,7 +63,11 @@ class Problem:
             self.lib.dg_problem_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # not while the interpreter shuts down (module globals may already
+        # be gone; the process is ending and the device memory goes with it)
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -171,6 +176,19 @@ class Problem:
         out = np.empty((ns, vx * vy * vz), dtype=np.float64)
         L._check(self.lib.dg_coarse_stencil(self.h, coarse_space, level, dims, out.ctypes.data))
         return (vx, vy, vz), out, nlev
+
+    def coarse_csr(self, coarse_space: int, level: int, which: int = 0):
+        """(row_ptr, col, val, shape, nlevels) of a level of the aggregation-AMG
+        hierarchy (which = 0: A_l, 1: P_l, 2: R_l), as numpy arrays."""
+        dims = (ctypes.c_int64 * 4)()
+        L._check(self.lib.dg_coarse_csr(self.h, coarse_space, level, which, dims, None, None, None))
+        rows, cols, nnz, nlev = (int(v) for v in dims)
+        rp = np.empty(rows + 1, dtype=np.int32)
+        ci = np.empty(max(nnz, 1), dtype=np.int32)
+        v = np.empty(max(nnz, 1), dtype=np.float64)
+        L._check(self.lib.dg_coarse_csr(self.h, coarse_space, level, which, dims, rp.ctypes.data, ci.ctypes.data,
+                                        v.ctypes.data))
+        return rp, ci[:nnz], v[:nnz], (rows, cols), nlev
 
     def mg_vcycle(self, r: torch.Tensor, opts: L.MgOpts | None = None, out: torch.Tensor | None = None):
         opts = opts or L.mg_opts()
