@@ -271,6 +271,8 @@ def diffusion_leg(p: int = 3) -> dict:
     cases = (("poisson", inputs.poisson_gauss(p)), ("inhomogeneous", inputs.inhomogeneous(p)),
              ("inhomogeneous_rotated", inputs.inhomogeneous(p, nrot=inputs.rotation(0.4, -0.7, 1.1))))
     for tag, w in cases:
+        if tag != "inhomogeneous_rotated":
+            out[tag + "_eps_sweep"] = eps_sweep(w)
         P = Problem(ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c,
                                 b0=w.b0, B=w.B, kfield=w.kfield, cfield=w.cfield, nrot=w.nrot))
         f = P.rhs_from_functions(f=w.f, g=w.g, j=w.j)
@@ -295,6 +297,42 @@ def diffusion_leg(p: int = 3) -> dict:
         out[tag] = row
         P.close()
     return out
+
+
+def eps_sweep(w) -> dict:
+    """Outer iterations and inner iterations against the inner tolerance eps
+    of the block solves (Sec. 4.2, the MF(eps) variants), and the exact
+    block solve by stored inverses (PMF), FP64 preconditioner as in the
+    paper: flexible CG to 1e-8, V-cycle with the Q1 coarse space."""
+    import torch
+
+    from paper_1805_11930_amd import (DG_FP64, DG_INNER_PMF, DG_KRYLOV_FCG, DG_PRECOND_MG, Problem, ProblemSpec,
+                                      solve_opts)
+
+    P = Problem(ProblemSpec(cells=w.cells, lengths=w.lengths, p=w.p, bc=w.bc, sigma=w.sigma, K=w.K, c=w.c,
+                            b0=w.b0, B=w.B, kfield=w.kfield, cfield=w.cfield, nrot=w.nrot))
+    f = P.rhs_from_functions(f=w.f, g=w.g, j=w.j)
+    u = torch.zeros_like(f)
+    rows = {}
+    for eps in (1e-12, 1e-8, 1e-4, 1e-2, "pmf"):
+        sm = dict(inner=DG_INNER_PMF) if eps == "pmf" else dict(eps=eps)
+        o = solve_opts(krylov=DG_KRYLOV_FCG, precond=DG_PRECOND_MG, precond_precision=DG_FP64, rtol=1e-8,
+                       maxit=500, smooth=sm)
+        u.zero_()
+        P.solve(f, u, o)
+        u.zero_()
+        _, r = P.solve(f, u, o)
+        o.inner_stats = 1
+        u.zero_()
+        _, rs = P.solve(f, u, o)
+        key = "pmf" if eps == "pmf" else f"{eps:.0e}"
+        rows[key] = {"iterations": r.iters, "time_to_solve_s": round(r.t_solve, 4),
+                     "us_per_dof": round(r.t_solve / P.ndof * 1e6, 5), "inner_avg": round(rs.inner_avg, 3),
+                     "inner_max": rs.inner_max}
+        log(f"[bench] {w.name} eps={key}: {r.iters} it, {r.t_solve * 1e3:.1f} ms, inner avg {rs.inner_avg:.2f} "
+            f"max {rs.inner_max}")
+    P.close()
+    return rows
 
 
 def event_time(fn, reps: int) -> float:
@@ -491,10 +529,17 @@ def solve_leg(w, steps: int, warmup: int, coarse_opt: str = "auto", smoother_row
     # per-result errors and in-solve inner counts (untimed runs)
     err = {}
     inner = {}
+    phases = {}
     for name, prec in (("fp64", DG_FP64), ("mixed", DG_FP32)):
         ref = exact if exact is not None else (u64 if name == "mixed" else None)
         r = run(opts(prec, inner_stats=1, u_ref=ref.data_ptr() if ref is not None else None))
         inner[name] = {"avg": round(r.inner_avg, 3), "max": r.inner_max, "blocks": r.inner_blocks}
+        # where the time of the solve goes (event-timed phases of that run)
+        phases[name] = {"solve_s": round(r.t_solve, 5), "apply_outer_s": round(r.t_apply, 5),
+                        "precond_s": round(r.t_precond, 5), "smoother_s": round(r.t_smoother, 5),
+                        "residual_restrict_s": round(r.t_restrict, 5), "coarse_s": round(r.t_coarse, 5),
+                        "prolong_s": round(r.t_prolong, 5),
+                        "rest_s": round(max(r.t_solve - r.t_apply - r.t_precond, 0.0), 5)}
         if exact is not None:
             err[f"{name}_vs_exact"] = r.error
         elif name == "mixed":
@@ -504,6 +549,7 @@ def solve_leg(w, steps: int, warmup: int, coarse_opt: str = "auto", smoother_row
         err["mixed_vs_fp64"] = r.error
     out["error"] = err
     out["inner_in_solve"] = inner
+    out["phases"] = phases
     # standalone applies and the preconditioner pieces of the same settings
     u_rand = torch.from_numpy(np.random.default_rng(3).normal(size=P.ndof)).cuda()
     v64 = torch.empty_like(u_rand)

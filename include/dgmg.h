@@ -228,11 +228,13 @@ typedef struct {
                                ||u - u_ref||_2 / ||u_ref||_2 in FP64.  Read
                                once at the end of the solve; must not
                                overlap f or u.                              */
-  int inner_stats;          /* 1: count the inner iterations of every block
-                               solve the preconditioner performs (result
-                               inner_avg, inner_max, inner_blocks); costs
+  int inner_stats;          /* 1: statistics of the preconditioner: count
+                               the inner iterations of every block solve
+                               (result inner_avg, inner_max, inner_blocks;
                                one small reduction kernel per smoothing
-                               step.  0 (default): not counted.            */
+                               step) and time its phases with HIP events
+                               (result t_smoother ... t_prolong).  0
+                               (default): neither.                         */
 } dg_solve_opts;
 
 typedef struct {
@@ -252,6 +254,11 @@ typedef struct {
   double error;             /* ||u - u_ref||_2 / ||u_ref||_2 (FP64), or -1
                                when opts->u_ref is NULL                     */
   long long inner_blocks;   /* block solves counted (opts->inner_stats)     */
+  /* seconds in the phases of the preconditioner (opts->inner_stats; else
+     0): block smoothing steps (with the P0 prolongation that is fused into
+     the first postsmoothing step), residual + restriction to the coarse
+     space, coarse solve, Q1 prolongation */
+  double t_smoother, t_restrict, t_coarse, t_prolong;
 } dg_solve_result;
 
 /* ---- problem lifetime ---------------------------------------------- */

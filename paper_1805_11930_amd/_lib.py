@@ -97,6 +97,8 @@ class SolveResult(ctypes.Structure):
         ("inner_max", ctypes.c_int), ("footprint", ctypes.c_size_t), ("t_apply", ctypes.c_double),
         ("n_apply", ctypes.c_int), ("t_precond", ctypes.c_double), ("n_precond", ctypes.c_int),
         ("error", ctypes.c_double), ("inner_blocks", ctypes.c_longlong),
+        ("t_smoother", ctypes.c_double), ("t_restrict", ctypes.c_double), ("t_coarse", ctypes.c_double),
+        ("t_prolong", ctypes.c_double),
     ]
 
 

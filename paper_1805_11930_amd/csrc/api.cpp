@@ -122,6 +122,38 @@ size_t esize(int prec) { return prec == DG_FP64 ? sizeof(double) : sizeof(float)
 // the problem's own while a solve counts its inner iterations.
 int *count_buf(dg_problem *pr, int *iters) { return iters ? iters : (pr->count_inner ? pr->iters_buf : nullptr); }
 
+// Phase timing of the preconditioner inside a solve that collects
+// statistics: phase_begin records the start event of a phase on s, and
+// phase_end its end event; both are no-ops otherwise.
+enum { PH_SMOOTH = 0, PH_RESTRICT = 1, PH_COARSE = 2, PH_PROLONG = 3 };
+
+int phase_event(dg_problem *pr, hipEvent_t *e) {
+  if (!pr->phase_spare.empty()) {
+    *e = pr->phase_spare.back();
+    pr->phase_spare.pop_back();
+    return DG_OK;
+  }
+  DG_HIP(hipEventCreate(e));
+  return DG_OK;
+}
+
+int phase_begin(dg_problem *pr, int phase, hipStream_t s) {
+  if (!pr->count_inner) return DG_OK;
+  dg_problem::PhaseMark m{phase, nullptr, nullptr};
+  int rc = phase_event(pr, &m.a);
+  if (!rc) rc = phase_event(pr, &m.b);
+  if (rc) return rc;
+  DG_HIP(hipEventRecord(m.a, s));
+  pr->phase_marks.push_back(m);
+  return DG_OK;
+}
+
+int phase_end(dg_problem *pr, hipStream_t s) {
+  if (!pr->count_inner || pr->phase_marks.empty()) return DG_OK;
+  DG_HIP(hipEventRecord(pr->phase_marks.back().b, s));
+  return DG_OK;
+}
+
 // Adds the counts of one finished smoothing step (every cell solved once)
 // to the solve's running totals, when the solve counts them.
 int count_step(dg_problem *pr, int *iters, hipStream_t s) {
@@ -403,11 +435,12 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
   const int sw_post = sw == DG_SWEEP_SOR ? DG_SWEEP_SOR_BACKWARD : (sw == DG_SWEEP_SOR_BACKWARD ? DG_SWEEP_SOR : sw);
   void *X = (!sor && o->n_post % 2 == 1) ? t0 : (void *)z;
   void *Y = (X == t0) ? (void *)z : t0;
+  if ((rc = phase_begin(pr, PH_SMOOTH, s))) return rc;
   if (sor)
     rc = sor_sweeps(pr, prec, r, nullptr, X, o->n_pre, sw, sa, s);
   else
     rc = sweeps(pr, prec, r, nullptr, X, Y, o->n_pre, sa, nullptr, s);
-  if (rc) return rc;
+  if (rc || (rc = phase_end(pr, s)) || (rc = phase_begin(pr, PH_RESTRICT, s))) return rc;
   // residual and restriction R = P^T
   using LP = LevelPtr<T>;
   CoarseLevel &L0 = H.levels[0];
@@ -429,22 +462,37 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
   }
   const int cycles = o->coarse_cycles > 1 ? o->coarse_cycles : 1;
   T *xh = nullptr;
+  if ((rc = phase_end(pr, s)) || (rc = phase_begin(pr, PH_COARSE, s))) return rc;
   if (o->graph)
     rc = coarse_solve_graph<T>(pr, H, prec, cycles, nu, w, s, &xh, x_init);
   else
     rc = coarse_solve<T>(H, cycles, nu, w, s, &xh, x_init);
-  if (rc) return rc;
+  if (rc || (rc = phase_end(pr, s))) return rc;
   if (kind == COARSE_Q1) {
     // prolongation P (nodal interpolation of the trilinear correction)
+    if ((rc = phase_begin(pr, PH_PROLONG, s))) return rc;
     if ((rc = q1_prolong_add<T>(pr->p, pr->geo.nx, pr->geo.ny, pr->geo.nz, xh, (T *)X, s))) return rc;
+    if ((rc = phase_end(pr, s))) return rc;
     if (o->n_post == 0) return DG_OK;  // X == z here
-    if (sor) return sor_sweeps(pr, prec, r, z, z, o->n_post, sw_post, sa, s);
-    return sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s);
+    if ((rc = phase_begin(pr, PH_SMOOTH, s))) return rc;
+    if (sor)
+      rc = sor_sweeps(pr, prec, r, z, z, o->n_post, sw_post, sa, s);
+    else
+      rc = sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s);
+    return rc ? rc : phase_end(pr, s);
   }
-  if (sor) return sor_sweeps(pr, prec, r, z, z, o->n_post, sw_post, sa, s, xh);
-  if (o->n_post == 0) return prolong_add_p0<T>(pr->ndof, pr->nloc, xh, (T *)X, s);  // X == z here
+  if (o->n_post == 0) {
+    if ((rc = phase_begin(pr, PH_PROLONG, s))) return rc;
+    rc = prolong_add_p0<T>(pr->ndof, pr->nloc, xh, (T *)X, s);  // X == z here
+    return rc ? rc : phase_end(pr, s);
+  }
   // prolongation P (injection) fused into the first postsmoothing sweep
-  return sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s, xh);
+  if ((rc = phase_begin(pr, PH_SMOOTH, s))) return rc;
+  if (sor)
+    rc = sor_sweeps(pr, prec, r, z, z, o->n_post, sw_post, sa, s, xh);
+  else
+    rc = sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s, xh);
+  return rc ? rc : phase_end(pr, s);
 }
 
 int vcycle(dg_problem *pr, int prec, const void *r, void *z, const dg_mg_opts *o, hipStream_t s) {
@@ -799,6 +847,11 @@ int check_solve_vectors(const double *f, const double *u, const dg_solve_opts *o
 
 int inner_count_begin(dg_problem *pr, const dg_solve_opts *o, hipStream_t s) {
   pr->count_inner = 0;
+  for (auto &m : pr->phase_marks) {
+    pr->phase_spare.push_back(m.a);
+    pr->phase_spare.push_back(m.b);
+  }
+  pr->phase_marks.clear();
   if (!o->inner_stats) return DG_OK;
   DG_HIP(hipMemsetAsync(pr->inner_acc, 0, 3 * sizeof(unsigned long long), s));
   pr->count_inner = 1;
@@ -814,6 +867,19 @@ int inner_count_end(dg_problem *pr, const dg_solve_opts *o, dg_solve_result *res
   res->inner_blocks = (long long)h[2];
   res->inner_max = (int)h[1];
   res->inner_avg = h[2] ? (double)h[0] / (double)h[2] : 0.0;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (auto &m : pr->phase_marks) {
+    float ms = 0.f;
+    DG_HIP(hipEventElapsedTime(&ms, m.a, m.b));
+    t[m.phase] += 1e-3 * ms;
+    pr->phase_spare.push_back(m.a);
+    pr->phase_spare.push_back(m.b);
+  }
+  pr->phase_marks.clear();
+  res->t_smoother = t[PH_SMOOTH];
+  res->t_restrict = t[PH_RESTRICT];
+  res->t_coarse = t[PH_COARSE];
+  res->t_prolong = t[PH_PROLONG];
   return DG_OK;
 }
 
@@ -847,6 +913,7 @@ int precond_run(dg_problem *pr, const dg_solve_opts *o, int prec, const void *ri
     // block smoother steps from zero: mg.smooth.n_sweeps of mg.smooth.sweep
     SmoothArgs a;
     if ((rc = smooth_args(pr, &o->mg.smooth, a))) return rc;
+    if ((rc = phase_begin(pr, PH_SMOOTH, s))) return rc;
     const int n = o->mg.smooth.n_sweeps > 1 ? o->mg.smooth.n_sweeps : 1;
     if (a.sweep != DG_SWEEP_JACOBI) {
       rc = sor_sweeps(pr, prec, rin, nullptr, zout, n, a.sweep, a, s);
@@ -859,7 +926,7 @@ int precond_run(dg_problem *pr, const dg_solve_opts *o, int prec, const void *ri
       if ((rc = alloc_tmp(pr, prec, 2, &alt))) return rc;
       rc = sweeps(pr, prec, rin, nullptr, zout, alt, n, a, nullptr, s);
     }
-    if (rc) return rc;
+    if (rc || (rc = phase_end(pr, s))) return rc;
   }
   return DG_OK;
 }

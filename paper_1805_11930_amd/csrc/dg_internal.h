@@ -268,6 +268,16 @@ struct dg_problem {
   // blocks)
   int count_inner = 0;
   unsigned long long *inner_acc = nullptr;
+  // per-phase timing of the preconditioner while count_inner is set:
+  // event pairs recorded on the solve's stream around each phase of every
+  // V-cycle (phase: 0 smoothing, 1 residual + restriction, 2 coarse solve,
+  // 3 prolongation), read when the solve ends; spare events are reused
+  struct PhaseMark {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<PhaseMark> phase_marks;
+  std::vector<hipEvent_t> phase_spare;
   size_t held_bytes = 0;
 };
 

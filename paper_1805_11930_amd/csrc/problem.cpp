@@ -317,6 +317,11 @@ void dg_problem_destroy(dg_problem *pr) {
   (void)hipFree(pr->iters_buf);
   (void)hipFree(pr->red_buf);
   (void)hipFree(pr->inner_acc);
+  for (auto &m : pr->phase_marks) {
+    (void)hipEventDestroy(m.a);
+    (void)hipEventDestroy(m.b);
+  }
+  for (hipEvent_t e : pr->phase_spare) (void)hipEventDestroy(e);
   delete pr;
 }
 

@@ -102,3 +102,23 @@ def test_solve_argument_checks():
     # a valid call still works afterwards
     assert lib.dg_solve(P.h, f.data_ptr(), u.data_ptr(), ctypes.byref(o), ctypes.byref(res), s) == L.DG_OK
     P.close()
+
+
+@pytest.mark.parametrize("krylov", [1, 2])
+def test_phase_times_in_solve(krylov):
+    from paper_1805_11930_amd import DG_COARSE_P0, DG_COARSE_Q1, solve_opts
+
+    w, P, f, _ = _w1_small()
+    for cs in (DG_COARSE_Q1, DG_COARSE_P0):
+        _, res = P.solve(f, opts=solve_opts(krylov=krylov, rtol=1e-10, inner_stats=1, mg=dict(coarse_space=cs)))
+        phases = (res.t_smoother, res.t_restrict, res.t_coarse, res.t_prolong)
+        assert all(t >= 0.0 for t in phases)
+        assert res.t_smoother > 0.0 and res.t_restrict > 0.0 and res.t_coarse > 0.0
+        if cs == DG_COARSE_Q1:
+            assert res.t_prolong > 0.0
+        # the phases lie inside the timed preconditioner applications (the
+        # first application of CG, on r_0, is not among those)
+        assert sum(phases) <= res.t_solve
+        _, res0 = P.solve(f, opts=solve_opts(krylov=krylov, rtol=1e-10, mg=dict(coarse_space=cs)))
+        assert (res0.t_smoother, res0.t_restrict, res0.t_coarse, res0.t_prolong) == (0.0, 0.0, 0.0, 0.0)
+    P.close()
