@@ -655,6 +655,10 @@ def main() -> int:
     ap.add_argument("--diffusion", type=int, default=1,
                     help="run the Poisson / inhomogeneous diffusion leg on the paper's p=3 grid (0 = skip)")
     ap.add_argument("--fdm", type=int, default=1, help="run the stored-factor smoother leg on the main workload")
+    ap.add_argument("--pmf", type=int, default=1,
+                    help="time the partially matrix-free variant (stored block inverses) in every leg")
+    ap.add_argument("--smooth-inner", default="own", choices=["own", "pmf"],
+                    help="--smooth-only: the workload's own block solver, or the stored block inverses")
     ap.add_argument("--apply-only", type=int, default=0,
                     help="profiling aid: run this many FP64 applies and exit")
     ap.add_argument("--smooth-only", type=int, default=0,
@@ -698,6 +702,8 @@ def main() -> int:
             u32 = torch.zeros_like(f32)
             o32 = torch.empty_like(f32)
             _, smd, _, _ = leg_settings(w, args.coarse)  # the workload's own block solver
+            if args.smooth_inner == "pmf":
+                smd = dict(inner=3)  # DG_INNER_PMF
             sm = smooth_opts(**smd)
             for _ in range(args.smooth_only):
                 P.block_smooth(f32, u32, sm, out=o32)
@@ -739,7 +745,7 @@ def main() -> int:
     bpd = bytes_per_dof(w.p, 8)
     achieved = bpd * w.ndof / apply_s / 1e9
     # ---- the rest of the hot path, outside the timed region ---------------
-    main_leg = solve_leg(w, max(args.steps, 3), 1, args.coarse)
+    main_leg = solve_leg(w, max(args.steps, 3), 1, args.coarse, pmf=bool(args.pmf))
     traffic = None
     if os.path.exists(COUNTERS):
         with open(COUNTERS) as fh:
@@ -797,7 +803,7 @@ def main() -> int:
     for name in legs:
         wl = make_workload(name)
         log(f"[bench] leg {name}: {wl.name}, {wl.ndof} DOF")
-        line["workloads"][name] = solve_leg(wl, args.leg_steps, 1)
+        line["workloads"][name] = solve_leg(wl, args.leg_steps, 1, pmf=bool(args.pmf))
     if args.diffusion:
         line["diffusion_sec42"] = diffusion_leg()
     if args.pe2000:
