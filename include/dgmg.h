@@ -74,6 +74,7 @@ enum { DG_IPREC_DIAG = 0, DG_IPREC_TRIDIAG = 1 };
 enum { DG_COARSE_P0 = 0, DG_COARSE_Q1 = 1, DG_COARSE_AUTO = 2 };
 enum { DG_COARSE_SOLVER_GEOMETRIC = 0, DG_COARSE_SOLVER_AMG = 1 };
 enum { DG_FIELD_NONE = 0, DG_FIELD_AXIS_QUADRATIC = 1, DG_FIELD_ROTATED_QUADRATIC = 2 };
+enum { DG_BASIS_GL = 0, DG_BASIS_GLL = 1 };
 
 typedef struct dg_problem dg_problem;          /* opaque, library-owned */
 typedef struct dg_solve_state dg_solve_state;  /* opaque, library-owned */
@@ -117,6 +118,29 @@ typedef struct {
   double kq[9];
   double cq[2];
   double nrot[9];          /* DG_FIELD_ROTATED_QUADRATIC: rows n_1, n_2, n_3 */
+  int basis;               /* nodes of the 1-D Lagrange basis (Sec. 2.1,
+                              basis paragraph):
+                              DG_BASIS_GL (0, default): the p+1 Gauss-Legendre
+                                points, collocated with the quadrature;
+                              DG_BASIS_GLL: the p+1 Gauss-Lobatto points (end
+                                points included), the paper's choice.
+                              Both span Q_p per cell with the same (p+1)-point
+                              Gauss quadrature, so the discrete solution as a
+                              function is the same; vectors hold the values at
+                              the basis nodes (dg_node_points).  With GLL the
+                              operator is S^T A S, S = V (x) V (x) V with
+                              V[q][j] = GLL polynomial j at Gauss point q
+                              (Stage 1 of Sec. 3.1 with a value matrix), and
+                              the block smoother solves S^T D_T S (its
+                              tridiagonal inner preconditioner takes the
+                              band of the whole block, which in this basis
+                              also couples consecutive x-lines).  GLL does
+                              not support the Q1 coarse space (AUTO selects
+                              P0), the fast-diagonalisation and
+                              stored-inverse block solves, or the serving
+                              entry point dg_solve_start (DG_EINVAL).  The
+                              problem holds 7 more DOF-sized vectors per
+                              precision (scratch and block entries).       */
 } dg_problem_desc;
 
 /* Block smoother options (alg block_jacobi, alg block_SOR, Sec. 2.2.1;
@@ -274,9 +298,14 @@ const char *dg_last_error(void);
 int64_t dg_ndof(const dg_problem *prob);
 int64_t dg_boundary_npoints(const dg_problem *prob);
 
-/* Physical coordinates, HOST output [ndof][3], of the DOF nodes, which are
- * also the volume quadrature points (Gauss nodes, collocated basis). */
+/* Physical coordinates, HOST output [ndof][3], of the DOF nodes: the
+ * Gauss points (DG_BASIS_GL) or the Gauss-Lobatto points (DG_BASIS_GLL) of
+ * each cell, in DOF order. */
 int dg_node_points(const dg_problem *prob, double *xyz);
+/* Physical coordinates, HOST output [ndof][3], of the volume quadrature
+ * points (the (p+1)^3 Gauss points of each cell, in DOF order) at which
+ * dg_assemble_rhs takes f.  Equal to dg_node_points for DG_BASIS_GL. */
+int dg_quadrature_points(const dg_problem *prob, double *xyz);
 /* Physical coordinates, HOST output [npts][3], of the boundary face
  * quadrature points: box faces 0..5 in order; on each box face, the faces
  * of the boundary cells with the first tangential cell index fastest

@@ -9,7 +9,8 @@ package does not load the library; constructing a Problem does, and fails
 loudly if it is missing.
 """
 from ._lib import (  # noqa: F401
-    DG_BC_DIRICHLET, DG_BC_NEUMANN, DG_COARSE_AUTO, DG_COARSE_P0, DG_COARSE_Q1, DG_COARSE_SOLVER_AMG, DG_COARSE_SOLVER_GEOMETRIC, DG_FIELD_AXIS_QUADRATIC,
+    DG_BASIS_GL, DG_BASIS_GLL, DG_BC_DIRICHLET, DG_BC_NEUMANN, DG_COARSE_AUTO, DG_COARSE_P0, DG_COARSE_Q1,
+    DG_COARSE_SOLVER_AMG, DG_COARSE_SOLVER_GEOMETRIC, DG_FIELD_AXIS_QUADRATIC,
     DG_FIELD_NONE, DG_FIELD_ROTATED_QUADRATIC, DG_FP32, DG_FP64, DG_INNER_CG, DG_INNER_FDM, DG_INNER_GMRES, DG_INNER_PMF,
     DG_IPREC_DIAG, DG_IPREC_TRIDIAG, DG_KRYLOV_CG, DG_KRYLOV_FCG, DG_KRYLOV_FGMRES, DG_PRECOND_BLOCK,
     DG_PRECOND_BLOCK_JACOBI, DG_PRECOND_MG, DG_PRECOND_NONE, DG_SWEEP_JACOBI, DG_SWEEP_SOR, DG_SWEEP_SOR_BACKWARD,

@@ -30,6 +30,7 @@ DG_IPREC_DIAG, DG_IPREC_TRIDIAG = 0, 1
 DG_COARSE_P0, DG_COARSE_Q1, DG_COARSE_AUTO = 0, 1, 2
 DG_COARSE_SOLVER_GEOMETRIC, DG_COARSE_SOLVER_AMG = 0, 1
 DG_FIELD_NONE, DG_FIELD_AXIS_QUADRATIC, DG_FIELD_ROTATED_QUADRATIC = 0, 1, 2
+DG_BASIS_GL, DG_BASIS_GLL = 0, 1
 
 EXPORTS = (
     "dg_problem_create", "dg_problem_destroy", "dg_last_error", "dg_ndof", "dg_boundary_npoints",
@@ -37,7 +38,7 @@ EXPORTS = (
     "dg_block_diag", "dg_block_solve", "dg_block_smooth", "dg_mg_vcycle", "dg_solve", "dg_footprint",
     "dg_coarse_stencil", "dg_default_smooth_opts", "dg_default_mg_opts", "dg_default_solve_opts",
     "dg_solve_start", "dg_batch_step", "dg_solve_poll", "dg_solve_state_destroy", "dg_block_smooth_noalloc",
-    "dg_coarse_csr",
+    "dg_coarse_csr", "dg_quadrature_points",
 )
 
 
@@ -56,7 +57,7 @@ class ProblemDesc(ctypes.Structure):
         ("c", ctypes.POINTER(ctypes.c_double)), ("c_scalar", ctypes.c_double),
         ("b0", ctypes.c_double * 3), ("B", ctypes.c_double * 9),
         ("field", ctypes.c_int), ("kq", ctypes.c_double * 9), ("cq", ctypes.c_double * 2),
-        ("nrot", ctypes.c_double * 9),
+        ("nrot", ctypes.c_double * 9), ("basis", ctypes.c_int),
     ]
 
 
@@ -123,6 +124,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dg_boundary_npoints.argtypes = [vp]
     lib.dg_boundary_npoints.restype = i64
     lib.dg_node_points.argtypes = [vp, dp]
+    lib.dg_quadrature_points.argtypes = [vp, dp]
     lib.dg_boundary_points.argtypes = [vp, dp]
     lib.dg_assemble_rhs.argtypes = [vp, vp, vp, vp, vp]
     lib.dg_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -212,6 +214,7 @@ class ProblemSpec:
     kfield: tuple | None = None
     cfield: tuple = (0.0, 0.0)
     nrot: tuple | None = None  # rows n_m of an orthonormal basis: K(x) = sum_m P_m(x_m) n_m n_m^T
+    basis: str = "gl"  # nodes of the 1-D basis: "gl" (Gauss-Legendre) or "gll" (Gauss-Lobatto)
     _keep: list = field(default_factory=list, repr=False)
 
     def desc(self) -> ProblemDesc:
@@ -257,6 +260,8 @@ class ProblemSpec:
             nr = np.eye(3) if self.nrot is None else np.asarray(self.nrot, dtype=np.float64)
             for i in range(9):
                 d.nrot[i] = float(nr.reshape(9)[i])
+        d.basis = {"gl": DG_BASIS_GL, "gll": DG_BASIS_GLL}[self.basis] if isinstance(self.basis, str) else int(
+            self.basis)
         return d
 
 

@@ -24,7 +24,7 @@ ARCH = os.environ.get("DGMG_OFFLOAD_ARCH", "gfx950")
 SOURCES = [
     "tables.cpp", "problem.cpp", "q1.cpp", "api.cpp", "solve.cpp", "batch.cpp", "amg.cpp",
     "apply.hip", "apply_tensor.hip", "smooth.hip", "vec.hip", "coarse.hip", "fdm.hip", "noalloc.hip", "pmf.hip",
-    "amg_kernels.hip",
+    "amg_kernels.hip", "basis.hip", "smooth_gll.hip",
 ]
 
 COMMON = [

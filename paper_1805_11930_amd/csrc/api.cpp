@@ -90,6 +90,10 @@ int smooth_args(dg_problem *pr, const dg_smooth_opts *o, SmoothArgs &a) {
         "inner_precond DG_IPREC_DIAG, or DG_IPREC_TRIDIAG with inner GMRES, colours <= 64)");
     return DG_EINVAL;
   }
+  if (pr->basis == DG_BASIS_GLL && o->inner != DG_INNER_CG && o->inner != DG_INNER_GMRES) {
+    set_error("the Gauss-Lobatto basis supports the inner CG and GMRES block solves");
+    return DG_EINVAL;
+  }
   if (o->inner == DG_INNER_FDM) {
     int rc = ensure_fdm(pr, DG_FP64);
     if (!rc) rc = ensure_fdm(pr, DG_FP32);
@@ -421,7 +425,11 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
   SmoothArgs sa;
   int rc = smooth_args(pr, &o->smooth, sa);
   if (rc) return rc;
-  const int kind = coarse_kind(o->coarse_space, pr->geo.has_b != 0);
+  const int kind = coarse_kind(o->coarse_space, pr->geo.has_b != 0, pr->basis == DG_BASIS_GLL);
+  if (kind == COARSE_Q1 && pr->basis == DG_BASIS_GLL) {
+    set_error("the Gauss-Lobatto basis supports the P0 coarse space only");
+    return DG_EINVAL;
+  }
   if ((rc = ensure_hierarchy(pr, kind))) return rc;
   const bool amg = o->coarse_solver == DG_COARSE_SOLVER_AMG;
   if (amg && (rc = ensure_amg(pr, kind))) return rc;

@@ -553,8 +553,8 @@ static int launch_res_t(const dg_problem *pr, const void *u, const void *r, void
   return DG_OK;
 }
 
-int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, const void *r, void *rh, hipStream_t s,
-                             int kind) {
+int launch_residual_restrict_gl(const dg_problem *pr, int prec, const void *u, const void *r, void *rh,
+                                hipStream_t s, int kind) {
   const bool d = prec == DG_FP64;
   switch (pr->p) {
     case 1: return d ? launch_res_t<1, double>(pr, u, r, rh, s, kind) : launch_res_t<1, float>(pr, u, r, rh, s, kind);
@@ -567,13 +567,43 @@ int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, cons
   return DG_EINVAL;
 }
 
-int launch_apply(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s, hipEvent_t ev0,
-                 hipEvent_t ev1) {
+int launch_apply_gl(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s, hipEvent_t ev0,
+                    hipEvent_t ev1) {
   return prec == DG_FP64 ? dispatch_apply<double>(pr, u, v, s, true, ev0, ev1)
                          : dispatch_apply<float>(pr, u, v, s, true, ev0, ev1);
 }
 
-int launch_block_apply(const dg_problem *pr, int prec, const void *x, void *y, hipStream_t s) {
+// v = A u with the coefficients at the cell centres: the operator of the
+// preconditioner when K and c are fields (equal to launch_apply_gl
+// otherwise)
+template <int P, typename T>
+static int launch_apply_cc_t(const dg_problem *pr, const void *u, void *v, hipStream_t s) {
+  constexpr int N = P + 1;
+  const dim3 grid((unsigned)((pr->ncell + ApplyShape<N>::CPB - 1) / ApplyShape<N>::CPB)), block(kApplyThreads);
+  if (pr->geo.has_b)
+    hipLaunchKernelGGL((k_apply<P, T, true>), grid, block, 0, s, pr->geo, (const T *)u, (T *)v, (const T *)nullptr,
+                       (T *)nullptr);
+  else
+    hipLaunchKernelGGL((k_apply<P, T, true, 0, false, false>), grid, block, 0, s, pr->geo, (const T *)u, (T *)v,
+                       (const T *)nullptr, (T *)nullptr);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int launch_apply_cc_gl(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s) {
+  const bool d = prec == DG_FP64;
+  switch (pr->p) {
+    case 1: return d ? launch_apply_cc_t<1, double>(pr, u, v, s) : launch_apply_cc_t<1, float>(pr, u, v, s);
+    case 2: return d ? launch_apply_cc_t<2, double>(pr, u, v, s) : launch_apply_cc_t<2, float>(pr, u, v, s);
+    case 3: return d ? launch_apply_cc_t<3, double>(pr, u, v, s) : launch_apply_cc_t<3, float>(pr, u, v, s);
+    case 4: return d ? launch_apply_cc_t<4, double>(pr, u, v, s) : launch_apply_cc_t<4, float>(pr, u, v, s);
+    case 5: return d ? launch_apply_cc_t<5, double>(pr, u, v, s) : launch_apply_cc_t<5, float>(pr, u, v, s);
+  }
+  set_error("unsupported degree");
+  return DG_EINVAL;
+}
+
+int launch_block_apply_gl(const dg_problem *pr, int prec, const void *x, void *y, hipStream_t s) {
   return prec == DG_FP64 ? dispatch_apply<double>(pr, x, y, s, false) : dispatch_apply<float>(pr, x, y, s, false);
 }
 
@@ -587,7 +617,7 @@ static int launch_diag_t(const dg_problem *pr, void *diag, hipStream_t s) {
   return DG_OK;
 }
 
-int launch_block_diag(const dg_problem *pr, int prec, void *diag, hipStream_t s) {
+int launch_block_diag_gl(const dg_problem *pr, int prec, void *diag, hipStream_t s) {
   switch (pr->p) {
     case 1: return prec == DG_FP64 ? launch_diag_t<1, double>(pr, diag, s) : launch_diag_t<1, float>(pr, diag, s);
     case 2: return prec == DG_FP64 ? launch_diag_t<2, double>(pr, diag, s) : launch_diag_t<2, float>(pr, diag, s);
@@ -608,7 +638,7 @@ static int launch_rhs_t(const dg_problem *pr, const double *fq, const double *bq
   return DG_OK;
 }
 
-int launch_rhs(const dg_problem *pr, const double *fq, const double *bq, double *rhs, hipStream_t s) {
+int launch_rhs_gl(const dg_problem *pr, const double *fq, const double *bq, double *rhs, hipStream_t s) {
   switch (pr->p) {
     case 1: return launch_rhs_t<1>(pr, fq, bq, rhs, s);
     case 2: return launch_rhs_t<2>(pr, fq, bq, rhs, s);

@@ -349,6 +349,12 @@ int dg_solve_start(dg_problem *prob, const double *f, double *u, const dg_solve_
     set_error("dg_solve_start: out is NULL");
     return DG_EINVAL;
   }
+  if (prob && prob->basis == DG_BASIS_GLL) {
+    // the basis changes use scratch owned by the problem, which the
+    // concurrent streams of several solves would share
+    set_error("dg_solve_start: the Gauss-Lobatto basis is not supported by the serving entry points");
+    return DG_EINVAL;
+  }
   return dgmg::start(prob, f, u, opts, nullptr, true, out);
 }
 

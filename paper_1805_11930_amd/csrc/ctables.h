@@ -136,5 +136,55 @@ struct Tabs {
   static constexpr Tab<N> t = make_tab<N>();
 };
 
+// The paper's basis: nodal at the N Gauss-Lobatto points on [0,1] (the end
+// points and the roots of P_(N-1)'), with the same N-point Gauss quadrature.
+// A function with GLL nodal values u' has the Gauss-point values u = V u'
+// along each axis, V[q][j] = lj(xq) for the GLL Lagrange polynomial lj at
+// the Gauss point xq; in 3-D u = (V x V x V) u' (Stage 1 of Sec. 3.1 with
+// the value matrix V).  Interior roots: Newton iteration on P_(N-1)' with
+// P_(N-1)'' from the Legendre equation, started from -cos(pi k / (N-1)).
+template <int N>
+struct GllTab {
+  double xi[N] = {};
+  double V[N][N] = {};  // V[q][j] = l_j^GLL(xi_q^GL)
+};
+
+template <int N>
+constexpr GllTab<N> make_gll_tab() {
+  GllTab<N> g;
+  constexpr Tab<N> t = make_tab<N>();
+  double x[N] = {};
+  x[0] = -1.0;
+  x[N - 1] = 1.0;
+  const int m = N - 1;  // roots of P_m'
+  for (int k = 1; k < N - 1; ++k) {
+    double z = -ccos(kPi * k / m);
+    for (int it = 0; it < 100; ++it) {
+      double pm = 0, dpm = 0;
+      legendre(m, z, pm, dpm);
+      const double d2 = (2.0 * z * dpm - m * (m + 1.0) * pm) / (1.0 - z * z);
+      const double dz = dpm / d2;
+      z -= dz;
+      if (cabs(dz) < 1e-17) break;
+    }
+    x[k] = z;
+  }
+  for (int i = 0; i < N; ++i) g.xi[i] = 0.5 * (x[i] + 1.0);
+  for (int i = 0; i < N / 2; ++i) {  // exact mirror symmetry
+    const double a = 0.5 * (g.xi[i] + (1.0 - g.xi[N - 1 - i]));
+    g.xi[i] = a;
+    g.xi[N - 1 - i] = 1.0 - a;
+  }
+  if (N % 2 == 1) g.xi[N / 2] = 0.5;
+  for (int q = 0; q < N; ++q)
+    for (int j = 0; j < N; ++j) {
+      double l = 1.0;
+      for (int r = 0; r < N; ++r)
+        if (r != j) l *= (t.xi[q] - g.xi[r]) / (g.xi[j] - g.xi[r]);
+      g.V[q][j] = l;
+    }
+  return g;
+}
+
 }  // namespace ct
 }  // namespace dgmg

@@ -28,6 +28,7 @@ struct Tables1D {
   double e0[kMaxN], e1[kMaxN], d0[kMaxN], d1[kMaxN];
 };
 void build_tables(int n, Tables1D &t);
+void gll_nodes(int n, double *xi);  // the n Gauss-Lobatto points on [0,1]
 
 // Kernel-side copy of the tables in the compute precision, built at compile
 // time from the constexpr tables (ctables.h); inside kernels every entry is
@@ -55,6 +56,22 @@ constexpr DevTab<T, N> make_ctab() {
     d.d0[i] = (T)t.d0[i];
     d.d1[i] = (T)t.d1[i];
   }
+  return d;
+}
+
+// Kernel-side GLL value matrix V[q][j] = l_j^GLL(xi_q^GL) (ctables.h) in
+// the compute precision, literals inside kernels.
+template <int N, typename T>
+struct GllDev {
+  T V[N][N] = {};
+};
+
+template <int N, typename T>
+constexpr GllDev<N, T> make_gll_dev() {
+  constexpr ct::GllTab<N> g = ct::make_gll_tab<N>();
+  GllDev<N, T> d;
+  for (int q = 0; q < N; ++q)
+    for (int j = 0; j < N; ++j) d.V[q][j] = (T)g.V[q][j];
   return d;
 }
 
@@ -204,10 +221,11 @@ constexpr int kDiag27 = 13;
 
 enum CoarseKind : int { COARSE_P0 = 0, COARSE_Q1 = 1 };
 
-// DG_COARSE_* option -> hierarchy (AUTO: Q1 without advection, else P0)
-inline int coarse_kind(int option, bool has_b) {
+// DG_COARSE_* option -> hierarchy (AUTO: Q1 without advection, else P0;
+// always P0 in the Gauss-Lobatto basis, which has no Q1 transfer)
+inline int coarse_kind(int option, bool has_b, bool gll = false) {
   if (option == DG_COARSE_Q1) return COARSE_Q1;
-  if (option == DG_COARSE_AUTO) return has_b ? COARSE_P0 : COARSE_Q1;
+  if (option == DG_COARSE_AUTO) return (has_b || gll) ? COARSE_P0 : COARSE_Q1;
   return COARSE_P0;
 }
 
@@ -278,6 +296,12 @@ struct dg_problem {
   };
   std::vector<PhaseMark> phase_marks;
   std::vector<hipEvent_t> phase_spare;
+  // DG_BASIS_GLL: three DOF-sized scratch vectors per precision for the
+  // basis changes, and the diagonal, band and band factors of the blocks
+  // S^T D_T S ([4][ndof] per precision; see basis.hip)
+  int basis = DG_BASIS_GL;
+  void *gll_tmp[2][3] = {{nullptr}};
+  void *gll_blk[2] = {nullptr, nullptr};
   size_t held_bytes = 0;
 };
 
@@ -293,18 +317,39 @@ int hip_fail(hipError_t e, const char *what);
   } while (0)
 
 // kernel launchers (apply.hip / smooth.hip / vec.hip / coarse.hip)
-// ev0 / ev1 (optional): recorded by the kernel dispatch itself around the apply
+// The operators of the problem's basis: for DG_BASIS_GLL the basis change
+// S (basis.hip) around the Gauss-point kernels (the *_gl launchers, which
+// always work in the Gauss-point basis).
+// ev0 / ev1 (optional): recorded around the apply (by the kernel dispatch
+// itself for the Gauss-point basis)
 int launch_apply(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s, hipEvent_t ev0 = nullptr,
                  hipEvent_t ev1 = nullptr);
 int launch_block_apply(const dg_problem *pr, int prec, const void *x, void *y, hipStream_t s);
-// outer operator of a full-tensor (rotated) coefficient field (apply_tensor.hip)
-int launch_apply_tensor(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s);
 // rh[c] = sum_{i in cell c} (r - A u)_i                  (P0 restriction)
 // rh[8 c + q] = sum_{i in cell c} phi_q(xi_i) (r - A u)_i  (Q1 corner sums)
 int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, const void *r, void *rh, hipStream_t s,
                              int kind = COARSE_P0);
 int launch_block_diag(const dg_problem *pr, int prec, void *diag, hipStream_t s);
 int launch_rhs(const dg_problem *pr, const double *f_qp, const double *bnd, double *rhs, hipStream_t s);
+int launch_apply_gl(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s, hipEvent_t ev0 = nullptr,
+                    hipEvent_t ev1 = nullptr);
+int launch_block_apply_gl(const dg_problem *pr, int prec, const void *x, void *y, hipStream_t s);
+// the apply with the coefficients at the cell centres (the preconditioner's
+// operator when K and c are fields)
+int launch_apply_cc_gl(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s);
+int launch_residual_restrict_gl(const dg_problem *pr, int prec, const void *u, const void *r, void *rh,
+                                hipStream_t s, int kind = COARSE_P0);
+int launch_block_diag_gl(const dg_problem *pr, int prec, void *diag, hipStream_t s);
+int launch_rhs_gl(const dg_problem *pr, const double *f_qp, const double *bnd, double *rhs, hipStream_t s);
+// outer operator of a full-tensor (rotated) coefficient field (apply_tensor.hip)
+int launch_apply_tensor(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s);
+// basis.hip: out = S (in + P zadd) (tr = false; zadd [ncell] or null) or
+// S^T in (tr = true), cell by cell; d = f - y elementwise (d may alias f or
+// y); the GLL scratch and block entries of a problem
+int launch_basis(const dg_problem *pr, int prec, const void *in, void *out, bool tr, hipStream_t s,
+                 const void *zadd = nullptr);
+int launch_diff(int64_t n, int prec, const void *f, const void *y, void *d, hipStream_t s);
+int gll_setup(dg_problem *pr);
 
 struct SmoothArgs {
   double omega, eps;
@@ -321,6 +366,9 @@ struct SmoothArgs {
 };
 int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin, void *uout,
                   const SmoothArgs &a, int *iters, hipStream_t s);
+// the same for the Gauss-Lobatto basis (smooth_gll.hip; called by launch_smooth)
+int launch_smooth_gll(const dg_problem *pr, int prec, const void *f, const void *uin, void *uout,
+                      const SmoothArgs &a, int *iters, hipStream_t s);
 // fast-diagonalisation factors of the cell blocks (b = 0), built on first use
 int ensure_fdm(dg_problem *pr, int prec);
 // stored inverses of the cell blocks D_T (any b, p <= 4), built on first use

@@ -310,6 +310,9 @@ void dg_problem_destroy(dg_problem *pr) {
   for (void *p : pr->corner_buf) (void)hipFree(p);
   for (void *p : pr->fdm) (void)hipFree(p);
   for (void *p : pr->pmf) (void)hipFree(p);
+  for (auto &row : pr->gll_tmp)
+    for (void *p : row) (void)hipFree(p);
+  for (void *p : pr->gll_blk) (void)hipFree(p);
   for (auto &cg : pr->graphs) (void)hipGraphExecDestroy(cg.exec);
   if (pr->capture_stream) (void)hipStreamDestroy(pr->capture_stream);
   for (auto &row : pr->mg_tmp)
@@ -371,6 +374,10 @@ int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
     }
   if (!std::isfinite(d->penalty_factor)) {
     set_error("penalty_factor must be finite");
+    return DG_EINVAL;
+  }
+  if (d->basis != DG_BASIS_GL && d->basis != DG_BASIS_GLL) {
+    set_error("basis must be DG_BASIS_GL or DG_BASIS_GLL");
     return DG_EINVAL;
   }
   if (d->field != DG_FIELD_NONE && d->field != DG_FIELD_AXIS_QUADRATIC && d->field != DG_FIELD_ROTATED_QUADRATIC) {
@@ -466,6 +473,7 @@ int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
   pr->nloc = n * n * n;
   pr->ncell = ncell;
   pr->ndof = ncell * pr->nloc;
+  pr->basis = d->basis;
   (void)hipGetDevice(&pr->device);
   build_tables(n, pr->tab);
   Geo &g = pr->geo;
@@ -518,6 +526,7 @@ int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
   pr->hc.swap(cc);
   if (!rc) rc = ensure_hierarchy(pr, COARSE_P0);
   if (!rc) rc = alloc_small(pr);
+  if (!rc && pr->basis == DG_BASIS_GLL) rc = gll_setup(pr);
   if (rc) {
     dg_problem_destroy(pr);
     return rc;
@@ -535,11 +544,8 @@ int64_t dg_boundary_npoints(const dg_problem *pr) {
   return 2 * n2 * ((int64_t)g.ny * g.nz + (int64_t)g.nx * g.nz + (int64_t)g.nx * g.ny);
 }
 
-int dg_node_points(const dg_problem *pr, double *xyz) {
-  if (!pr || !xyz) {
-    set_error("dg_node_points: NULL argument");
-    return DG_EINVAL;
-  }
+// the tensor points of the 1-D points xi in every cell, in DOF order
+static void cell_points(const dg_problem *pr, const double *xi, double *xyz) {
   const Geo &g = pr->geo;
   const int N = pr->n;
   int64_t o = 0;
@@ -548,12 +554,35 @@ int dg_node_points(const dg_problem *pr, double *xyz) {
     for (int k = 0; k < N; ++k)
       for (int j = 0; j < N; ++j)
         for (int i = 0; i < N; ++i) {
-          xyz[3 * o + 0] = (ix + pr->tab.xi[i]) * g.h[0];
-          xyz[3 * o + 1] = (iy + pr->tab.xi[j]) * g.h[1];
-          xyz[3 * o + 2] = (iz + pr->tab.xi[k]) * g.h[2];
+          xyz[3 * o + 0] = (ix + xi[i]) * g.h[0];
+          xyz[3 * o + 1] = (iy + xi[j]) * g.h[1];
+          xyz[3 * o + 2] = (iz + xi[k]) * g.h[2];
           ++o;
         }
   }
+}
+
+int dg_node_points(const dg_problem *pr, double *xyz) {
+  if (!pr || !xyz) {
+    set_error("dg_node_points: NULL argument");
+    return DG_EINVAL;
+  }
+  if (pr->basis == DG_BASIS_GLL) {
+    double xi[kMaxN];
+    gll_nodes(pr->n, xi);
+    cell_points(pr, xi, xyz);
+  } else {
+    cell_points(pr, pr->tab.xi, xyz);
+  }
+  return DG_OK;
+}
+
+int dg_quadrature_points(const dg_problem *pr, double *xyz) {
+  if (!pr || !xyz) {
+    set_error("dg_quadrature_points: NULL argument");
+    return DG_EINVAL;
+  }
+  cell_points(pr, pr->tab.xi, xyz);
   return DG_OK;
 }
 

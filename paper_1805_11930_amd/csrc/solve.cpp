@@ -360,12 +360,18 @@ extern "C" int dg_footprint(const dg_problem_desc *d, const dg_solve_opts *o, si
   bool has_b = false;
   for (int i = 0; i < 3; ++i) has_b = has_b || d->b0[i] != 0.0;
   for (int i = 0; i < 9; ++i) has_b = has_b || d->B[i] != 0.0;
-  const bool q1 = o->precond == DG_PRECOND_MG && coarse_kind(o->mg.coarse_space, has_b) == COARSE_Q1;
+  const bool q1 = o->precond == DG_PRECOND_MG &&
+                  coarse_kind(o->mg.coarse_space, has_b, d->basis == DG_BASIS_GLL) == COARSE_Q1;
   if (q1) {
     // Q1 hierarchy: vertex levels (27-point stencils), corner sums
     const int64_t nv = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
     b += ((nv + nv / 7 + 1) * (27 + 3) + 2 * nv) * both;
     b += 8 * ncell * both + 128 * 128 * both;
+  }
+  if (d->basis == DG_BASIS_GLL) {
+    // basis-change scratch (three vectors) and the stored block diagonal,
+    // band and band factors (four vectors), both precisions
+    b += 7 * ndof * both;
   }
   if (o->precond == DG_PRECOND_MG && o->mg.coarse_solver == DG_COARSE_SOLVER_AMG) {
     // AMG levels below the coarse space: P and R (about 10 entries per fine

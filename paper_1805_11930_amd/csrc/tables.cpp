@@ -1,5 +1,6 @@
-// Host copy of the 1-D Gauss-Legendre tables (see ctables.h for the
-// definitions; both come from the same constexpr functions).
+// Host copy of the 1-D Gauss-Legendre tables and of the Gauss-Lobatto
+// nodes (see ctables.h for the definitions; both come from the same
+// constexpr functions).
 #include "dg_internal.h"
 
 namespace dgmg {
@@ -18,6 +19,24 @@ static void copy_tab(Tables1D &t) {
       t.D[i][j] = c.D[i][j];
       t.S[i][j] = c.S[i][j];
     }
+  }
+}
+
+template <int N>
+static void copy_gll(double *xi) {
+  constexpr ct::GllTab<N> g = ct::make_gll_tab<N>();
+  for (int i = 0; i < N; ++i) xi[i] = g.xi[i];
+}
+
+// the n Gauss-Lobatto points on [0,1]
+void gll_nodes(int n, double *xi) {
+  switch (n) {
+    case 2: copy_gll<2>(xi); break;
+    case 3: copy_gll<3>(xi); break;
+    case 4: copy_gll<4>(xi); break;
+    case 5: copy_gll<5>(xi); break;
+    case 6: copy_gll<6>(xi); break;
+    default: break;
   }
 }
 

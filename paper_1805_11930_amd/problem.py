@@ -79,6 +79,11 @@ class Problem:
         L._check(self.lib.dg_node_points(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
 
+    def quadrature_points(self) -> np.ndarray:
+        out = np.zeros((self.ndof, 3))
+        L._check(self.lib.dg_quadrature_points(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
     def boundary_points(self) -> np.ndarray:
         n = int(self.lib.dg_boundary_npoints(self.h))
         out = np.zeros((n, 3))
@@ -100,7 +105,7 @@ class Problem:
         faces, j on Neumann faces)."""
         fq = None
         if f is not None:
-            fq = torch.from_numpy(np.ascontiguousarray(f(self.node_points()), dtype=np.float64)).cuda()
+            fq = torch.from_numpy(np.ascontiguousarray(f(self.quadrature_points()), dtype=np.float64)).cuda()
         bq = None
         if g is not None or j is not None:
             pts = self.boundary_points()
