@@ -13,6 +13,8 @@ iteration; the oracle assembles A', D_T' and l' from the GLL tables.
     oracle's steps on D_T' (equal per-cell counts, iterates <= 1e-9);
   * block-Jacobi and block-SOR / SSOR sweeps and the P0 V-cycle with the
     exact coarse solve match the oracle's algorithms on A' to 1e-9;
+  * coefficient fields (axis-aligned and rotated K(x), c(x)): apply and
+    right-hand side with the field, V-cycle with the cell-centre problem;
   * a solve in the GLL basis reaches the sparse direct solution, and S u'
     equals the Gauss-basis solution of the same problem.
 """
@@ -206,6 +208,37 @@ def test_vcycle_exact_coarse(p, with_b, npre, npost):
     assert rel(z.cpu().numpy(), ref) <= 1e-9
     z32 = P.mg_vcycle(_t(r, torch.float32), o)
     assert rel(z32.cpu().numpy().astype(np.float64), ref) <= 1e-3
+    P.close()
+
+
+@pytest.mark.parametrize("p,rotated", [(2, False), (3, True)])
+def test_field_apply_rhs_and_vcycle(p, rotated):
+    """Coefficient fields (Sec. 4.2): the outer operator with K(x), c(x) at
+    the quadrature points, the preconditioner with their cell-centre values,
+    in the GLL basis."""
+    from paper_1805_11930_amd import DG_COARSE_P0, DG_INNER_CG, mg_opts
+
+    print(f"GLL field p={p} rotated={rotated}", flush=True)
+    nrot = inputs.rotation(0.4, -0.7, 1.1) if rotated else None
+    w = inputs.inhomogeneous(p=p, cells=(4, 3, 5), kfield=((1.0, 0.5, 2.0), (0.4, -0.2, 0.3), (3.0, 1.0, 0.5)),
+                             nrot=nrot)
+    w.cfield = (0.3, 0.7)
+    opr = oracle_problem(w, basis="gll")
+    A = dg.assemble(opr)
+    P = _lib(w)
+    u = inputs.random_vector(opr.ndof, 12)
+    assert rel(P.apply(_t(u)).cpu().numpy(), A @ u) <= 1e-12
+    ref = dg.assemble_rhs(opr, f=w.f, g=w.g, j=w.j)
+    assert rel(P.rhs_from_functions(f=w.f, g=w.g, j=w.j).cpu().numpy(), ref) <= 1e-12
+    # the V-cycle works with the cell-centre problem
+    cc = dg.cell_centre_problem(opr)
+    Acc = dg.assemble(cc)
+    Dcc = dg.block_diagonal(Acc, cc.ncell)
+    r = inputs.random_vector(opr.ndof, 38)
+    cs = solvers.exact_coarse(solvers.p0_galerkin(Acc, cc))
+    zref = solvers.vcycle(Acc, Dcc, cc, r, cs, n_pre=1, n_post=1, omega=0.9, inner="cg", eps=1e-2)
+    z = P.mg_vcycle(_t(r), mg_opts(smooth=dict(omega=0.9, eps=1e-2, inner=DG_INNER_CG), coarse_space=DG_COARSE_P0))
+    assert rel(z.cpu().numpy(), zref) <= 1e-9
     P.close()
 
 
