@@ -56,9 +56,12 @@ __device__ inline int lpos(int k, int i, int a, int b) {
 }
 
 // Lane permutation of a 32-bit register within rows of 16 lanes (DPP).
+// Every lane of the permutations used here has a source lane, so the
+// bound-control bit changes nothing; with it set (and old = 0) the compiler
+// folds the permutation into the add that consumes it (v_add_f32_dpp).
 template <int CTRL>
 __device__ inline float dpp_perm(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ inline double dpp_perm(double v) {
@@ -139,30 +142,35 @@ struct CellLines {
   T stan, vol, cre;
 };
 
-// stan * (M u) with the cell's per-axis matrix M held in LDS (b = 0)
+// M u with one of the cell's per-axis matrices held in LDS (b = 0)
 template <typename T, int N>
-__device__ inline void mat_line(const T *M, T stan, const T (&u)[N], T (&v)[N]) {
+__device__ inline void mat_line(const T *M, const T (&u)[N], T (&v)[N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     T acc = T(0);
 #pragma unroll
     for (int l = 0; l < N; ++l) acc += M[i * N + l] * u[l];
-    v[i] = stan * acc;
+    v[i] = acc;
   }
 }
 
 // q = D_T p on the lane's x-line.  All lanes of the wavefront must call it.
-// Ms: the cell's three axis matrices (b = 0), or nullptr (generic path).
-template <int P, typename T>
+// MS (b = 0): Ms holds the cell's three axis matrices with their rows
+// divided by the node weights, Mt_k = W^-1 M_k: D_T is the Kronecker sum
+// Mx (x) Wy (x) Wz + Wx (x) My (x) Wz + Wx (x) Wy (x) Mz, so
+// D_T p = (Wx (x) Wy (x) Wz) (sum over k of Mt_k along axis k) p, and the
+// weights w3[i] = w_i w_a w_b of the lane's DOFs are applied once at the
+// end.  Otherwise the generic line operators (the stan weight inside).
+template <int P, typename T, bool MS>
 __device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1> &tb, bool on, bool hasb,
-                                const T *Ms, const T (&p)[P + 1], T (&q)[P + 1], T *Ps, T *Qy, T *Qz, int a,
-                                int b) {
+                                const T *Ms, const T (&w3)[P + 1], const T (&p)[P + 1], T (&q)[P + 1], T *Ps,
+                                T *Qy, T *Qz, int a, int b) {
   constexpr int N = P + 1;
   constexpr int N2 = N * N;
   T qx[N];
   if (on) {
-    if (Ms)
-      mat_line<T, N>(Ms, cl.stan, p, qx);
+    if constexpr (MS)
+      mat_line<T, N>(Ms, p, qx);
     else
       line_apply<T, N>(tb, cl.f[0], cl.stan, cl.vol, cl.cre, hasb, cl.lc[0], p, T(0), T(0), T(0), T(0), qx);
 #pragma unroll
@@ -173,16 +181,16 @@ __device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1
     T yl[N], yo[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) yl[i] = Ps[lpos<N>(1, i, a, b)];
-    if (Ms)
-      mat_line<T, N>(Ms + N2, cl.stan, yl, yo);
+    if constexpr (MS)
+      mat_line<T, N>(Ms + N2, yl, yo);
     else
       line_apply<T, N>(tb, cl.f[1], cl.stan, cl.vol, T(0), hasb, cl.lc[1], yl, T(0), T(0), T(0), T(0), yo);
 #pragma unroll
     for (int i = 0; i < N; ++i) Qy[lpos<N>(1, i, a, b)] = yo[i];
 #pragma unroll
     for (int i = 0; i < N; ++i) yl[i] = Ps[lpos<N>(2, i, a, b)];
-    if (Ms)
-      mat_line<T, N>(Ms + 2 * N2, cl.stan, yl, yo);
+    if constexpr (MS)
+      mat_line<T, N>(Ms + 2 * N2, yl, yo);
     else
       line_apply<T, N>(tb, cl.f[2], cl.stan, cl.vol, T(0), hasb, cl.lc[2], yl, T(0), T(0), T(0), T(0), yo);
 #pragma unroll
@@ -190,7 +198,10 @@ __device__ inline void dt_apply(const CellLines<P, T> &cl, const DevTab<T, P + 1
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < N; ++i) q[i] = on ? qx[i] + Qy[lpos<N>(0, i, a, b)] + Qz[lpos<N>(0, i, a, b)] : T(0);
+  for (int i = 0; i < N; ++i) {
+    const T sum = qx[i] + Qy[lpos<N>(0, i, a, b)] + Qz[lpos<N>(0, i, a, b)];
+    q[i] = on ? (MS ? w3[i] * sum : sum) : T(0);
+  }
 }
 
 // q = D_T p with the lane's three line operators held as N x N matrices in
@@ -452,10 +463,16 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
       }
     }
   } else if (INNER != DG_INNER_PMF && Ms && on) {
+    // row a of each axis matrix divided by w_a (see dt_apply)
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      Ms[k * S::N2 + a * N + b] = line_matrix_entry<T, N>(tb, cl.f[k], cl.vol, k == 0 ? cl.cre : T(0), a, b);
+      Ms[k * S::N2 + a * N + b] =
+          line_matrix_entry<T, N>(tb, cl.f[k], cl.vol, k == 0 ? cl.cre : T(0), a, b) / tb.w[a];
   }
+  // weights w_i w_a w_b of the lane's DOFs (the b = 0 form of dt_apply)
+  T w3[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) w3[i] = cl.stan * tb.w[i];
   __syncthreads();
 
   // ---- defect d = f - A u -------------------------------------------------
@@ -545,8 +562,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
       if (on) dd = fdm[base + lpos<N>(0, i, a, b)];
     } else if (on && Ms) {
       // DOF (i, a, b): x-line (a, b), y-line (x=i, z=b), z-line (x=i, y=a)
-      dd = tb.w[a] * tb.w[b] * Ms[i * N + i] + tb.w[i] * tb.w[b] * Ms[S::N2 + a * N + a] +
-           tb.w[i] * tb.w[a] * Ms[2 * S::N2 + b * N + b];
+      dd = w3[i] * (Ms[i * N + i] + Ms[S::N2 + a * N + a] + Ms[2 * S::N2 + b * N + b]);
     } else if (on) {
       // DOF (i, a, b) lies on the x-line (a, b), the y-line (x=i, z=b) and
       // the z-line (x=i, y=a)
@@ -621,7 +637,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
     if constexpr (REGM)
       dt_apply_reg<P, T>(Mr, on, pin, qout, Ps, Qy, Qz, a, b);
     else
-      dt_apply<P, T>(cl, tb, on, hasb, Ms, pin, qout, Ps, Qy, Qz, a, b);
+      dt_apply<P, T, !HASB>(cl, tb, on, hasb, Ms, w3, pin, qout, Ps, Qy, Qz, a, b);
   };
   auto dtap = [&](const T(&pin)[N], T(&qout)[N]) {
     if constexpr (GLL) {
