@@ -216,7 +216,9 @@ typedef struct {
   double coarse_omega;      /* Jacobi damping on the coarse levels (<= 0: 2/3) */
   int graph;                /* 1: replay the coarse solve from a HIP graph
                                (captured on first use per option set, kernel
-                               nodes only); 0: launch its kernels directly */
+                               nodes only); 0 (default): launch its kernels
+                               directly (measured as fast in steady state,
+                               and without the capture cost per problem)  */
   int coarse_solver;        /* DG_COARSE_SOLVER_GEOMETRIC (default): the
                                structured cycles above;
                                DG_COARSE_SOLVER_AMG: smoothed-aggregation
@@ -439,7 +441,7 @@ int dg_footprint(const dg_problem_desc *desc, const dg_solve_opts *opts, size_t 
 /* smoother: n_sweeps 1, omega 0.8, eps 1e-2 (the paper's choice),
  *   max_inner (p+1)^3, inner CG, restart 12;
  * V-cycle: n_pre = n_post = 1, coarse_space AUTO, coarse_cycles 1,
- *   coarse_smooth 0 (2 or 6 by anisotropy), coarse_omega 2/3, graph 1;
+ *   coarse_smooth 0 (2 or 6 by anisotropy), coarse_omega 2/3, graph 0;
  * solve: FCG, restart 30, rtol 1e-8, maxit 500, MG preconditioner in FP32. */
 void dg_default_smooth_opts(dg_smooth_opts *o);
 void dg_default_mg_opts(dg_mg_opts *o);

@@ -629,7 +629,7 @@ void dg_default_mg_opts(dg_mg_opts *o) {
   o->coarse_cycles = 1;
   o->coarse_smooth = 0;
   o->coarse_omega = 2.0 / 3.0;
-  o->graph = 1;
+  o->graph = 0;
   o->coarse_solver = DG_COARSE_SOLVER_GEOMETRIC;
 }
 

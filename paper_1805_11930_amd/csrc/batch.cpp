@@ -21,6 +21,8 @@
 // alone: nothing is shared between requests except the device.
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "dg_internal.h"
@@ -28,6 +30,74 @@
 #include "vec.h"
 
 using namespace dgmg;
+
+namespace {
+
+// Pinned host slots (8 doubles) and per-device streams reused by the solve
+// states of the process: pinned allocation and stream creation cost more
+// than the whole solve of a small request.  Held until the process ends.
+struct StatePool {
+  std::mutex m;
+  std::vector<double *> slots;
+  std::map<int, std::vector<hipStream_t>> streams;
+};
+StatePool &state_pool() {
+  static StatePool *p = new StatePool();  // never destroyed: states may outlive static destruction order
+  return *p;
+}
+
+constexpr int kSlotDoubles = 8, kSlotsPerBlock = 64;
+
+int take_slot(double **out) {
+  StatePool &P = state_pool();
+  std::lock_guard<std::mutex> g(P.m);
+  if (P.slots.empty()) {
+    double *blk = nullptr;
+    hipError_t e = hipHostMalloc((void **)&blk, sizeof(double) * kSlotDoubles * kSlotsPerBlock, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+    for (int k = kSlotsPerBlock - 1; k >= 0; --k) P.slots.push_back(blk + k * kSlotDoubles);
+  }
+  *out = P.slots.back();
+  P.slots.pop_back();
+  return DG_OK;
+}
+
+void give_slot(double *p) {
+  StatePool &P = state_pool();
+  std::lock_guard<std::mutex> g(P.m);
+  P.slots.push_back(p);
+}
+
+int take_stream(hipStream_t *out) {
+  int dev = 0;
+  DG_HIP(hipGetDevice(&dev));
+  StatePool &P = state_pool();
+  {
+    std::lock_guard<std::mutex> g(P.m);
+    auto &v = P.streams[dev];
+    if (!v.empty()) {
+      *out = v.back();
+      v.pop_back();
+      return DG_OK;
+    }
+  }
+  DG_HIP(hipStreamCreateWithFlags(out, hipStreamNonBlocking));
+  return DG_OK;
+}
+
+// s was taken on the current device and has no work in flight
+void give_stream(hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipStreamDestroy(s);
+    return;
+  }
+  StatePool &P = state_pool();
+  std::lock_guard<std::mutex> g(P.m);
+  P.streams[dev].push_back(s);
+}
+
+}  // namespace
 
 struct dg_solve_state {
   dg_problem *pr = nullptr;
@@ -60,11 +130,13 @@ struct dg_solve_state {
 
   ~dg_solve_state() {
     if (pr && counting) pr->count_inner = 0;
+    // nothing of this solve may still run when its slot and stream are reused
+    if (s) (void)hipStreamSynchronize(s);
     for (int k = 0; k < 2; ++k)
       for (hipEvent_t e : {ea0[k], ea1[k], ep0[k], ep1[k], err[k]})
         if (e) (void)hipEventDestroy(e);
-    if (hdots) (void)hipHostFree(hdots);
-    if (own_stream && s) (void)hipStreamDestroy(s);
+    if (hdots) give_slot(hdots);
+    if (own_stream && s) give_stream(s);
   }
 };
 
@@ -242,8 +314,7 @@ int start(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, hi
   };
   hipError_t e = hipSuccess;
   if (own_stream) {
-    e = hipStreamCreateWithFlags(&st->s, hipStreamNonBlocking);
-    if (e != hipSuccess) return fail(hip_fail(e, "hipStreamCreateWithFlags"));
+    if ((rc = take_stream(&st->s))) return fail(rc);
     st->own_stream = true;
   } else {
     st->s = s;
@@ -253,8 +324,16 @@ int start(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, hi
       e = hipEventCreate(ev);
       if (e != hipSuccess) return fail(hip_fail(e, "hipEventCreate"));
     }
-  e = hipHostMalloc((void **)&st->hdots, 8 * sizeof(double), hipHostMallocDefault);
-  if (e != hipSuccess) return fail(hip_fail(e, "hipHostMalloc"));
+  if ((rc = take_slot(&st->hdots))) return fail(rc);
+  {
+    // one block for the whole workspace
+    const bool f32 = o->precond_precision == DG_FP32 && o->precond != DG_PRECOND_NONE;
+    const size_t vec = DevBuf::round(n * sizeof(double));
+    const size_t total = (st->flex ? 5 : 4) * vec + DevBuf::round((size_t)kMaxDots * kDotBlocks * sizeof(double)) +
+                         DevBuf::round(kMaxDots * sizeof(double)) + DevBuf::round(8 * sizeof(double)) +
+                         (f32 ? 2 * DevBuf::round(n * sizeof(float)) : 0);
+    if ((rc = st->wb.reserve(total))) return fail(rc);
+  }
   if ((rc = st->wb.get(&st->r, n)) || (rc = st->wb.get(&st->p, n)) || (rc = st->wb.get(&st->q, n)) ||
       (rc = st->wb.get(&st->z, n)) || (rc = st->wb.get(&st->part, (size_t)kMaxDots * kDotBlocks)) ||
       (rc = st->wb.get(&st->dout, kMaxDots)) || (rc = st->wb.get(&st->dsc, 8)))

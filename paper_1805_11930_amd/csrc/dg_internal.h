@@ -302,6 +302,13 @@ struct dg_problem {
   int basis = DG_BASIS_GL;
   void *gll_tmp[2][3] = {{nullptr}};
   void *gll_blk[2] = {nullptr, nullptr};
+  // device memory of the problem (dmalloc): small buffers are carved from
+  // shared chunks, large ones get a block of their own; every block is
+  // freed by dg_problem_destroy (hipFree waits for the device, so the
+  // handful of blocks keeps teardown short)
+  std::vector<void *> blocks;
+  char *chunk_cur = nullptr;
+  size_t chunk_left = 0;
   size_t held_bytes = 0;
 };
 

@@ -195,11 +195,8 @@ int ensure_pmf(dg_problem *pr, int prec) {
     void *buf = nullptr;
     if ((rc = dmalloc(pr, &buf, pmf_bytes(pr, DG_FP32)))) return rc;
     const int64_t count = (int64_t)(pmf_bytes(pr, DG_FP32) / sizeof(float));
-    if ((rc = cast_d2f(count, 1.0, (const double *)pr->pmf[DG_FP64], (float *)buf, 0))) {
-      (void)hipFree(buf);
-      pr->held_bytes -= pmf_bytes(pr, DG_FP32);
-      return rc;
-    }
+    if ((rc = cast_d2f(count, 1.0, (const double *)pr->pmf[DG_FP64], (float *)buf, 0)))
+      return rc;  // buf stays with the problem's memory until it is destroyed
     pr->pmf[DG_FP32] = buf;
   }
   DG_HIP(hipStreamSynchronize(0));

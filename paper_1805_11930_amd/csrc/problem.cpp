@@ -18,11 +18,33 @@ int hip_fail(hipError_t e, const char *what) {
   return e == hipErrorOutOfMemory ? DG_ENOMEM : DG_EDEVICE;
 }
 
+// Device memory of a problem, released only by dg_problem_destroy.  Sizes
+// are rounded up to 256 bytes; requests up to kChunkBytes / 4 are carved
+// from shared chunks of kChunkBytes, larger ones get their own block.
+constexpr size_t kChunkBytes = size_t(4) << 20;
+
 int dmalloc(dg_problem *pr, void **p, size_t bytes) {
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    *p = nullptr;
-    return hip_fail(e, "hipMalloc");
+  *p = nullptr;
+  const size_t b = (bytes + 255) & ~size_t(255);
+  if (b > kChunkBytes / 4) {
+    hipError_t e = hipMalloc(p, b);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return hip_fail(e, "hipMalloc");
+    }
+    pr->blocks.push_back(*p);
+  } else {
+    if (pr->chunk_left < b) {
+      void *c = nullptr;
+      hipError_t e = hipMalloc(&c, kChunkBytes);
+      if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+      pr->blocks.push_back(c);
+      pr->chunk_cur = (char *)c;
+      pr->chunk_left = kChunkBytes;
+    }
+    *p = pr->chunk_cur;
+    pr->chunk_cur += b;
+    pr->chunk_left -= b;
   }
   pr->held_bytes += bytes;
   return DG_OK;
@@ -295,36 +317,15 @@ const char *dg_last_error(void) { return g_last_error.c_str(); }
 
 void dg_problem_destroy(dg_problem *pr) {
   if (!pr) return;
-  (void)hipFree(pr->dK);
-  (void)hipFree(pr->dc);
-  for (Hierarchy *H : {&pr->p0h, &pr->q1h, &pr->p0amg, &pr->q1amg}) {
-    for (auto &L : H->levels) {
-      if (L.borrowed) continue;  // owned by the geometric hierarchy
-      for (double *p : {L.A64, L.dinv64, L.r64, L.x64, L.t64, L.acc64, L.rs64, L.pv64, L.rv64}) (void)hipFree(p);
-      for (float *p : {L.A32, L.dinv32, L.r32, L.x32, L.t32, L.acc32, L.rs32, L.pv32, L.rv32}) (void)hipFree(p);
-      for (int *p : {L.rp, L.ci, L.prp, L.pci, L.rrp, L.rci}) (void)hipFree(p);
-    }
-    (void)hipFree(H->inv64);
-    (void)hipFree(H->inv32);
-  }
-  for (void *p : pr->corner_buf) (void)hipFree(p);
-  for (void *p : pr->fdm) (void)hipFree(p);
-  for (void *p : pr->pmf) (void)hipFree(p);
-  for (auto &row : pr->gll_tmp)
-    for (void *p : row) (void)hipFree(p);
-  for (void *p : pr->gll_blk) (void)hipFree(p);
   for (auto &cg : pr->graphs) (void)hipGraphExecDestroy(cg.exec);
   if (pr->capture_stream) (void)hipStreamDestroy(pr->capture_stream);
-  for (auto &row : pr->mg_tmp)
-    for (void *p : row) (void)hipFree(p);
-  (void)hipFree(pr->iters_buf);
-  (void)hipFree(pr->red_buf);
-  (void)hipFree(pr->inner_acc);
   for (auto &m : pr->phase_marks) {
     (void)hipEventDestroy(m.a);
     (void)hipEventDestroy(m.b);
   }
   for (hipEvent_t e : pr->phase_spare) (void)hipEventDestroy(e);
+  // every device buffer of the problem lives in one of its blocks (dmalloc)
+  for (void *p : pr->blocks) (void)hipFree(p);
   delete pr;
 }
 

@@ -20,22 +20,43 @@ int precond_apply_fp32_dots(dg_problem *pr, const dg_solve_opts *o, const float 
                             const double *rr_dev, int m, const double *b0, const double *b1, double *part,
                             double *out, hipStream_t s);
 
-// Device allocations owned by one solve; freed together.
+// Device allocations owned by one solve; freed together.  reserve() takes
+// one block for the buffers that follow (each rounded up to 256 bytes);
+// get() carves from it while it lasts, else allocates on its own.
 struct DevBuf {
   std::vector<void *> ptrs;
   size_t bytes = 0;
+  char *cur = nullptr;
+  size_t left = 0;
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
   ~DevBuf() {
     for (void *p : ptrs) (void)hipFree(p);
   }
-  template <typename T>
-  int get(T **out, size_t n) {
+  static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
+  int reserve(size_t total) {
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    hipError_t e = hipMalloc(&p, total);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc (solve workspace)");
     ptrs.push_back(p);
+    cur = (char *)p;
+    left = total;
+    return DG_OK;
+  }
+  template <typename T>
+  int get(T **out, size_t n) {
+    const size_t b = round(n * sizeof(T));
+    void *p = nullptr;
+    if (b <= left) {
+      p = cur;
+      cur += b;
+      left -= b;
+    } else {
+      hipError_t e = hipMalloc(&p, b);
+      if (e != hipSuccess) return hip_fail(e, "hipMalloc (solve workspace)");
+      ptrs.push_back(p);
+    }
     bytes += n * sizeof(T);
     *out = (T *)p;
     return DG_OK;
