@@ -266,7 +266,7 @@ struct dg_problem {
   // largest ratio over cells of max_k / min_k of K_kk / h_k^2 (the
   // anisotropy that point smoothers on the coarse levels have to overcome)
   double aniso = 1.0;
-  // coarse hierarchies: P0 (built with the problem) and Q1 (on first use)
+  // coarse hierarchies: P0 and Q1 (built on first use)
   dgmg::Hierarchy p0h, q1h;
   // aggregation AMG coarse solvers on the same coarse spaces (on first use)
   dgmg::Hierarchy p0amg, q1amg;

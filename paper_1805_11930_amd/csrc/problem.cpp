@@ -525,7 +525,6 @@ int dg_problem_create(const dg_problem_desc *d, dg_problem **out) {
   }
   pr->hK.swap(K);
   pr->hc.swap(cc);
-  if (!rc) rc = ensure_hierarchy(pr, COARSE_P0);
   if (!rc) rc = alloc_small(pr);
   if (!rc && pr->basis == DG_BASIS_GLL) rc = gll_setup(pr);
   if (rc) {

@@ -352,16 +352,18 @@ extern "C" int dg_footprint(const dg_problem_desc *d, const dg_solve_opts *o, si
     o = &def;
   }
   const size_t both = sizeof(double) + sizeof(float);
-  // P0 hierarchy (always built): levels ~8/7 of level 0, 7 stencil entries
-  // + 3 vectors per unknown, 2 more vectors on level 0, dense bottom
-  const int64_t nco = ncell + ncell / 7 + 1;
-  b += (nco * (7 + 3) + 2 * ncell) * both;
-  b += 128 * 128 * both;
   bool has_b = false;
   for (int i = 0; i < 3; ++i) has_b = has_b || d->b0[i] != 0.0;
   for (int i = 0; i < 9; ++i) has_b = has_b || d->B[i] != 0.0;
   const bool q1 = o->precond == DG_PRECOND_MG &&
                   coarse_kind(o->mg.coarse_space, has_b, d->basis == DG_BASIS_GLL) == COARSE_Q1;
+  if (o->precond == DG_PRECOND_MG && !q1) {
+    // P0 hierarchy: levels ~8/7 of level 0, 7 stencil entries + 3 vectors
+    // per unknown, 2 more vectors on level 0, dense bottom
+    const int64_t nco = ncell + ncell / 7 + 1;
+    b += (nco * (7 + 3) + 2 * ncell) * both;
+    b += 128 * 128 * both;
+  }
   if (q1) {
     // Q1 hierarchy: vertex levels (27-point stencils), corner sums
     const int64_t nv = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
