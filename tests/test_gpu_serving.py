@@ -6,7 +6,8 @@
     requested relative residual (checked against the oracle's matrix for
     the smallest request);
   * admission honours the HBM budget: a request larger than the budget is
-    rejected, the rest queue and complete;
+    rejected, the rest queue and complete (admission on a worker thread and
+    on the loop's thread);
   * FGMRES cannot be resident (DG_EINVAL).
 """
 import ctypes
@@ -79,7 +80,8 @@ def test_alone_vs_mixed_batch(prec):
         assert st["converged"] == 1
         alone.append(req)
     mixed = make_requests(MIX, None)
-    srv = SolveServer(_opts(prec), keep_solutions=True, max_active=8)
+    # admitted on the loop's thread: all six join the first step together
+    srv = SolveServer(_opts(prec), keep_solutions=True, max_active=8, prepare_ahead=0)
     st = srv.run(mixed)
     assert st["converged"] == len(MIX) and st["peak_active"] == len(MIX)
     for a, m in zip(alone, mixed):
@@ -108,7 +110,13 @@ def test_admission_budget_and_rejection():
     st = srv.run(reqs)
     assert st["rejected"] == 1 and reqs[3].status == L.DG_ENOMEM
     assert st["converged"] == 3
-    assert st["peak_active"] == 2
+    assert 1 <= st["peak_active"] <= 2  # never more than the two that fit
+    # the same with admission on the loop's thread: exactly two at a time
+    reqs = make_requests([(4, 2, 7201), (4, 2, 7202), (4, 2, 7203), (8, 4, 7204)], rate=None)
+    srv = SolveServer(_opts(1), keep_solutions=False, prepare_ahead=0)
+    srv.budget = 2 * small + 1
+    st = srv.run(reqs)
+    assert st["rejected"] == 1 and st["converged"] == 3 and st["peak_active"] == 2
 
 
 def test_fgmres_not_resident():
