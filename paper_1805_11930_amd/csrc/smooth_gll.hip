@@ -34,26 +34,36 @@ static int launch_smooth_gll_t(const dg_problem *pr, const void *d, const void *
   ka.defect = 0;  // d is the defect
   const bool hb = pr->geo.has_b != 0;
   const T *blk = (const T *)pr->gll_blk[sizeof(T) == 8 ? DG_FP64 : DG_FP32];
-#define DG_GLL_LAUNCH(INNER, HB, TRI)                                                                          \
-  hipLaunchKernelGGL((k_smooth<P, INNER, T, HB, TRI, kGmresMax, true>), dim3(G), dim3(kSmoothThreads), 0, s,   \
-                     pr->geo, (const T *)d, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh, blk)
+#define DG_GLL_LAUNCH_RM(INNER, HB, TRI, RM)                                                                \
+  hipLaunchKernelGGL((k_smooth<P, INNER, T, HB, TRI, RM, true>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo, \
+                     (const T *)d, (const T *)uin, (T *)uout, ka, iters, (const T *)a.zh, blk)
+  // inner GMRES: the restart-8 build (smaller Krylov basis in LDS and
+  // registers, more waves per SIMD) when the restart length allows
+#define DG_GLL_LAUNCH_GMRES(HB, TRI)                           \
+  do {                                                         \
+    if (a.restart <= 8)                                        \
+      DG_GLL_LAUNCH_RM(DG_INNER_GMRES, HB, TRI, 8);            \
+    else                                                       \
+      DG_GLL_LAUNCH_RM(DG_INNER_GMRES, HB, TRI, kGmresMax);    \
+  } while (0)
   if (a.inner == DG_INNER_CG) {
     if (hb)
-      DG_GLL_LAUNCH(DG_INNER_CG, true, false);
+      DG_GLL_LAUNCH_RM(DG_INNER_CG, true, false, kGmresMax);
     else
-      DG_GLL_LAUNCH(DG_INNER_CG, false, false);
+      DG_GLL_LAUNCH_RM(DG_INNER_CG, false, false, kGmresMax);
   } else if (a.tridiag) {
     if (hb)
-      DG_GLL_LAUNCH(DG_INNER_GMRES, true, true);
+      DG_GLL_LAUNCH_GMRES(true, true);
     else
-      DG_GLL_LAUNCH(DG_INNER_GMRES, false, true);
+      DG_GLL_LAUNCH_GMRES(false, true);
   } else {
     if (hb)
-      DG_GLL_LAUNCH(DG_INNER_GMRES, true, false);
+      DG_GLL_LAUNCH_GMRES(true, false);
     else
-      DG_GLL_LAUNCH(DG_INNER_GMRES, false, false);
+      DG_GLL_LAUNCH_GMRES(false, false);
   }
-#undef DG_GLL_LAUNCH
+#undef DG_GLL_LAUNCH_GMRES
+#undef DG_GLL_LAUNCH_RM
   DG_HIP(hipGetLastError());
   return DG_OK;
 }

@@ -328,33 +328,82 @@ __device__ inline void gll_change(bool on, const T (&u)[N], T (&v)[N], T *Ps, in
 // x-fastest DOF order (Gauss-Lobatto basis: unlike the Gauss-point basis,
 // the block couples the last DOF of an x-line to the first of the next, so
 // the band is one chain over the cell's (p+1)^3 DOFs).  Tf holds the cell's
-// Thomas factors in LDS: [0, N3) 1/m_k, [N3, 2 N3) sub_k, [2 N3, 3 N3) c_k;
-// the forward and back substitutions run in one lane (lead) through Tv.
-// All lanes of the wavefront must call it.
+// Thomas factors in LDS: [0, N3) 1/m_k, [N3, 2 N3) sub_k, [2 N3, 3 N3) c_k.
+// The substitutions y_k = (v_k - sub_k y_(k-1)) / m_k and
+// x_k = y_k - c_k x_(k+1) run along each lane's x-line as affine functions
+// of the value carried in from the neighbouring line (A + B * carry); one
+// lane then chains the (p+1)^2 line maps through LDS (Ab, carry), and every
+// lane finishes its line from its carry: (p+1)^2 + 2 (p+1) dependent steps
+// per substitution instead of (p+1)^3.  All lanes of the wavefront must call
+// it.
 template <typename T, int N>
-__device__ inline void tri_cell(bool on, bool lead, const T (&v)[N], T (&out)[N], T *Tv, const T *Tf, int a,
-                                int b) {
-  constexpr int N3 = N * N * N;
+__device__ inline void tri_cell(bool on, bool lead, const T (&v)[N], T (&out)[N], T *Ab, T *carry, const T *Tf,
+                                int a, int b) {
+  constexpr int N2 = N * N, N3 = N2 * N;
+  const int ln = a + N * b;
+  // forward: y_last = A + B * y_in on the lane's line
+  T A = T(0), B = T(1);
   if (on) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) Tv[lpos<N>(0, i, a, b)] = v[i];
+    for (int i = 0; i < N; ++i) {
+      const int k = i + N * ln;
+      const T m = Tf[k], sb = Tf[N3 + k];
+      A = (v[i] - sb * A) * m;
+      B = -sb * m * B;
+    }
+    Ab[2 * ln] = A;
+    Ab[2 * ln + 1] = B;
   }
   __syncthreads();
   if (lead) {
     T y = T(0);
-    for (int k = 0; k < N3; ++k) {
-      y = (Tv[k] - Tf[N3 + k] * y) * Tf[k];
-      Tv[k] = y;
-    }
-    T x = T(0);
-    for (int k = N3 - 1; k >= 0; --k) {
-      x = Tv[k] - Tf[2 * N3 + k] * x;
-      Tv[k] = x;
+    for (int l = 0; l < N2; ++l) {
+      carry[l] = y;
+      y = Ab[2 * l] + Ab[2 * l + 1] * y;
     }
   }
   __syncthreads();
+  T y[N];
+  {
+    T prev = on ? carry[ln] : T(0);
 #pragma unroll
-  for (int i = 0; i < N; ++i) out[i] = on ? Tv[lpos<N>(0, i, a, b)] : T(0);
+    for (int i = 0; i < N; ++i) {
+      const int k = i + N * ln;
+      y[i] = on ? (v[i] - Tf[N3 + k] * prev) * Tf[k] : T(0);
+      prev = y[i];
+    }
+  }
+  __syncthreads();  // the carries are read before they are rewritten
+  // backward: x_first = A + B * x_in on the lane's line
+  A = T(0);
+  B = T(1);
+  if (on) {
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+      const T c = Tf[2 * N3 + i + N * ln];
+      A = y[i] - c * A;
+      B = -c * B;
+    }
+    Ab[2 * ln] = A;
+    Ab[2 * ln + 1] = B;
+  }
+  __syncthreads();
+  if (lead) {
+    T x = T(0);
+    for (int l = N2 - 1; l >= 0; --l) {
+      carry[l] = x;
+      x = Ab[2 * l] + Ab[2 * l + 1] * x;
+    }
+  }
+  __syncthreads();
+  {
+    T next = on ? carry[ln] : T(0);
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+      out[i] = on ? y[i] - Tf[2 * N3 + i + N * ln] * next : T(0);
+      next = out[i];
+    }
+  }
 }
 
 // uin and uout may be the same vector for a colour sweep: the cells written
@@ -822,7 +871,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
 #pragma unroll
           for (int i = 0; i < N; ++i) vv[i] = on ? Vs[j * S::N3 + my + i] : T(0);
           if constexpr (TRIC)
-            tri_cell<T, N>(on, lead, vv, vj, Ps, Tf, a, b);
+            tri_cell<T, N>(on, lead, vv, vj, Qy, Qz, Tf, a, b);
           else
             prec_apply<T, N, TRI>(dinv, tc, tl, vv, vj);
         } else {
@@ -949,7 +998,7 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
             }
           }
         }
-        tri_cell<T, N>(on, lead, vy, mv, Ps, Tf, a, b);
+        tri_cell<T, N>(on, lead, vy, mv, Qy, Qz, Tf, a, b);
         if (on) {
 #pragma unroll
           for (int l = 0; l < N; ++l) x[l] += mv[l];

@@ -133,22 +133,22 @@ def test_block_pcg_replay(p, with_b):
     P.close()
 
 
-@pytest.mark.parametrize("p,tri", [(2, False), (3, True), (4, True)])
-def test_block_gmres_replay(p, tri):
+@pytest.mark.parametrize("p,tri,restart", [(2, False, 12), (3, True, 12), (4, True, 12), (3, True, 8), (2, False, 8)])
+def test_block_gmres_replay(p, tri, restart):
     from paper_1805_11930_amd import DG_INNER_GMRES, DG_IPREC_DIAG, DG_IPREC_TRIDIAG, smooth_opts
 
-    print(f"GLL block GMRES replay p={p} tridiag={tri}", flush=True)
+    print(f"GLL block GMRES replay p={p} tridiag={tri} restart={restart}", flush=True)
     w, opr, A, Db = _setup(p, True, seed=5)
     d = inputs.random_vector(opr.ndof, 33)
     D = d.reshape(opr.ncell, -1)
     prec = "tridiag" if tri else "diag"
     ref, its = [], []
     for T in range(opr.ncell):
-        x, it = solvers.block_gmres(Db[T], D[T], 1e-2, opr.nloc, 12, precond=prec)
+        x, it = solvers.block_gmres(Db[T], D[T], 1e-2, opr.nloc, min(restart, opr.nloc), precond=prec)
         ref.append(x)
         its.append(it)
     P = _lib(w)
-    o = smooth_opts(eps=1e-2, inner=DG_INNER_GMRES, restart=12,
+    o = smooth_opts(eps=1e-2, inner=DG_INNER_GMRES, restart=restart,
                     inner_precond=DG_IPREC_TRIDIAG if tri else DG_IPREC_DIAG)
     x, it_gpu = P.block_solve(_t(d), o, iters=True)
     assert list(it_gpu.cpu().numpy()) == its
