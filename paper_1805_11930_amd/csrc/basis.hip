@@ -11,7 +11,8 @@
 // V (S u'), the Gauss-point operator, and Stage 3 with V^T -- here as three
 // passes: k_basis (S), the collocated apply, k_basis (S^T).
 //
-// The block smoother takes S inside its inner iteration (smooth.hip).
+// The block smoother takes S inside its inner iteration (smooth_kernel.h,
+// smooth_gll.hip).
 //
 // Kernels:
 //   k_basis<P, T, TR>: out = S in (TR = false) or S^T in (TR = true), cell
