@@ -234,6 +234,15 @@ typedef struct {
                                use; cycled on the device with the same
                                damped Jacobi (coarse_smooth, coarse_omega,
                                coarse_cycles) as the geometric solver.     */
+  int fuse_small_levels;    /* 1 (default): the small levels of a Q1
+                               vertex-grid hierarchy and its dense bottom
+                               (at most 1024 unknowns on the first of them,
+                               192 KB of coefficients in the working
+                               precision) run as one single-workgroup
+                               kernel per cycle with their vectors in LDS;
+                               the same steps and arithmetic, bit for bit,
+                               as one kernel per step (0), which at these
+                               sizes is bound by launch latency            */
 } dg_mg_opts;
 
 /* Outer solve options (Sec. 4.2: CG to 1e-8; Sec. 4.3: flexible GMRES). */
@@ -441,7 +450,8 @@ int dg_footprint(const dg_problem_desc *desc, const dg_solve_opts *opts, size_t 
 /* smoother: n_sweeps 1, omega 0.8, eps 1e-2 (the paper's choice),
  *   max_inner (p+1)^3, inner CG, restart 12;
  * V-cycle: n_pre = n_post = 1, coarse_space AUTO, coarse_cycles 1,
- *   coarse_smooth 0 (2 or 6 by anisotropy), coarse_omega 2/3, graph 0;
+ *   coarse_smooth 0 (2 or 6 by anisotropy), coarse_omega 2/3, graph 0,
+ *   coarse_solver GEOMETRIC, fuse_small_levels 1;
  * solve: FCG, restart 30, rtol 1e-8, maxit 500, MG preconditioner in FP32. */
 void dg_default_smooth_opts(dg_smooth_opts *o);
 void dg_default_mg_opts(dg_mg_opts *o);

@@ -80,6 +80,7 @@ class MgOpts(ctypes.Structure):
         ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int), ("smooth", SmoothOpts),
         ("coarse_space", ctypes.c_int), ("coarse_cycles", ctypes.c_int), ("coarse_smooth", ctypes.c_int),
         ("coarse_omega", ctypes.c_double), ("graph", ctypes.c_int), ("coarse_solver", ctypes.c_int),
+        ("fuse_small_levels", ctypes.c_int),
     ]
 
 

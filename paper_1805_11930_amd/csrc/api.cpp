@@ -36,6 +36,10 @@ int validate_mg_opts(const dg_mg_opts *o) {
     set_error("coarse_solver must be DG_COARSE_SOLVER_GEOMETRIC or DG_COARSE_SOLVER_AMG");
     return DG_EINVAL;
   }
+  if (o->fuse_small_levels != 0 && o->fuse_small_levels != 1) {
+    set_error("fuse_small_levels must be 0 or 1");
+    return DG_EINVAL;
+  }
   return DG_OK;
 }
 }  // namespace dgmg
@@ -292,15 +296,61 @@ int level_residual(const CoarseLevel &L, const T *r, const T *x, T *out, hipStre
                     : residual7<T>(A, L.nx, L.ny, L.nz, r, x, out, s);
 }
 
+// Levels l .. end run as one single-workgroup kernel (k_coarse_tail) when
+// they are all 27-point vertex-grid levels, level l has at most
+// kTailMaxUnknowns unknowns, the dense bottom at most kTailBottomMax, all
+// of them together at most kTailLds, at least one level lies above the
+// bottom, and their coefficients (A and dinv above the bottom, the dense
+// inverse) take at most kTailCoefBytes: the workgroup pulls them through
+// one compute unit each cycle.
+bool tail_from(const Hierarchy &H, size_t l, size_t elem) {
+  const size_t nl = H.levels.size() - l;
+  if (nl < 2 || nl > (size_t)kTailLevels || H.levels[l].n > kTailMaxUnknowns || H.bottom_n > kTailBottomMax)
+    return false;
+  int64_t total = 0, coef = (int64_t)H.bottom_n * H.bottom_n;
+  for (size_t k = l; k < H.levels.size(); ++k) {
+    if (H.levels[k].ns != 27) return false;
+    total += H.levels[k].n;
+    if (k + 1 < H.levels.size()) coef += 28 * (int64_t)H.levels[k].n;
+  }
+  return total <= kTailLds && coef * (int64_t)elem <= kTailCoefBytes;
+}
+
+template <typename T>
+int run_tail(Hierarchy &H, size_t l, int nu, T w, hipStream_t s, T **result, bool x_init) {
+  using LP = LevelPtr<T>;
+  TailArgs<T> a;
+  a.nl = (int)(H.levels.size() - l);
+  for (int k = 0; k < a.nl; ++k) {
+    CoarseLevel &L = H.levels[l + k];
+    a.lv[k].A = LP::A(L);
+    a.lv[k].dinv = LP::dinv(L);
+    a.lv[k].r = LP::r(L);
+    a.lv[k].x = LP::x(L);
+    a.lv[k].t = LP::t(L);
+    a.lv[k].vx = L.nx;
+    a.lv[k].vy = L.ny;
+    a.lv[k].vz = L.nz;
+  }
+  a.inv = LP::inv(H);
+  a.bn = H.bottom_n;
+  a.nu = nu;
+  a.w = w;
+  a.x_init = x_init ? 1 : 0;
+  *result = LP::x(H.levels[l]);
+  return coarse_tail<T>(a, s);
+}
+
 // x_l ~= A_l^-1 r_l: one V-cycle of the hierarchy from a zero guess; r_l is
 // level l's r buffer, the result is left in one of level l's x / t buffers
 // and returned in *result.  x_init: level l's x buffer already holds the
 // first damped Jacobi sweep from zero, w D^-1 r_l (fused into the kernel
 // that produced r_l).
 template <typename T>
-int coarse_cycle(Hierarchy &H, size_t l, int nu, T w, hipStream_t s, T **result, bool x_init) {
+int coarse_cycle(Hierarchy &H, size_t l, int nu, T w, hipStream_t s, T **result, bool x_init, bool tail) {
   using LP = LevelPtr<T>;
   CoarseLevel &L = H.levels[l];
+  if (tail && tail_from(H, l, sizeof(T))) return run_tail<T>(H, l, nu, w, s, result, x_init);
   if (l + 1 == H.levels.size()) {
     *result = LP::x(L);
     return dense_mv<T>(H.bottom_n, LP::inv(H), LP::r(L), LP::x(L), s);
@@ -330,7 +380,7 @@ int coarse_cycle(Hierarchy &H, size_t l, int nu, T w, hipStream_t s, T **result,
     return rc;
   }
   T *xc = nullptr;
-  if ((rc = coarse_cycle<T>(H, l + 1, nu, w, s, &xc, fuse))) return rc;
+  if ((rc = coarse_cycle<T>(H, l + 1, nu, w, s, &xc, fuse, tail))) return rc;
   if (C.ns == 0)
     rc = csr_spmv<T>(L.n, C.pnnz, C.prp, C.pci, LP::pv(C), xc, x, true, s);  // x += P x_C
   else if (L.ns == 27)
@@ -351,20 +401,20 @@ int coarse_cycle(Hierarchy &H, size_t l, int nu, T w, hipStream_t s, T **result,
 // x_init as for coarse_cycle (first cycle only).  Kernels only: the
 // sequence can be captured into a HIP graph.
 template <typename T>
-int coarse_solve(Hierarchy &H, int cycles, int nu, T w, hipStream_t s, T **result, bool x_init) {
+int coarse_solve(Hierarchy &H, int cycles, int nu, T w, hipStream_t s, T **result, bool x_init, bool tail) {
   using LP = LevelPtr<T>;
   CoarseLevel &L = H.levels[0];
-  if (cycles <= 1 || H.levels.size() == 1) return coarse_cycle<T>(H, 0, nu, w, s, result, x_init);
+  if (cycles <= 1 || H.levels.size() == 1) return coarse_cycle<T>(H, 0, nu, w, s, result, x_init, tail);
   const int64_t n = L.n;
   T *acc = LP::acc(L), *rs = LP::rs(L);
   int rc;
   if ((rc = copy_vec<T>(n, LP::r(L), rs, s))) return rc;
   T *x = nullptr;
-  if ((rc = coarse_cycle<T>(H, 0, nu, w, s, &x, x_init))) return rc;
+  if ((rc = coarse_cycle<T>(H, 0, nu, w, s, &x, x_init, tail))) return rc;
   if ((rc = copy_vec<T>(n, x, acc, s))) return rc;
   for (int c = 1; c < cycles; ++c) {
     if ((rc = level_residual<T>(L, rs, acc, LP::r(L), s))) return rc;
-    if ((rc = coarse_cycle<T>(H, 0, nu, w, s, &x, false))) return rc;
+    if ((rc = coarse_cycle<T>(H, 0, nu, w, s, &x, false, tail))) return rc;
     if ((rc = add_to<T>(n, x, acc, s))) return rc;
   }
   // restore r_0 for callers that read it again
@@ -378,11 +428,11 @@ int coarse_solve(Hierarchy &H, int cycles, int nu, T w, hipStream_t s, T **resul
 // then launched on the caller's stream.  The graph holds kernel nodes only.
 template <typename T>
 int coarse_solve_graph(dg_problem *pr, Hierarchy &H, int prec, int cycles, int nu, T w, hipStream_t s, T **result,
-                       bool x_init) {
+                       bool x_init, bool tail) {
   CoarseGraph *hit = nullptr;
   for (auto &cg : pr->graphs)
     if (cg.kind == H.kind && cg.solver == H.solver && cg.prec == prec && cg.cycles == cycles && cg.nu == nu &&
-        cg.w == (double)w && cg.x_init == x_init) {
+        cg.w == (double)w && cg.x_init == x_init && cg.tail == tail) {
       hit = &cg;
       break;
     }
@@ -390,7 +440,7 @@ int coarse_solve_graph(dg_problem *pr, Hierarchy &H, int prec, int cycles, int n
     if (!pr->capture_stream) DG_HIP(hipStreamCreateWithFlags(&pr->capture_stream, hipStreamNonBlocking));
     DG_HIP(hipStreamBeginCapture(pr->capture_stream, hipStreamCaptureModeThreadLocal));
     T *res = nullptr;
-    int rc = coarse_solve<T>(H, cycles, nu, w, pr->capture_stream, &res, x_init);
+    int rc = coarse_solve<T>(H, cycles, nu, w, pr->capture_stream, &res, x_init, tail);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(pr->capture_stream, &graph);
     if (rc) {
@@ -410,6 +460,7 @@ int coarse_solve_graph(dg_problem *pr, Hierarchy &H, int prec, int cycles, int n
     cg.nu = nu;
     cg.w = (double)w;
     cg.x_init = x_init;
+    cg.tail = tail;
     cg.exec = exec;
     cg.result = res;
     pr->graphs.push_back(cg);
@@ -471,10 +522,11 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
   const int cycles = o->coarse_cycles > 1 ? o->coarse_cycles : 1;
   T *xh = nullptr;
   if ((rc = phase_end(pr, s)) || (rc = phase_begin(pr, PH_COARSE, s))) return rc;
+  const bool tail = o->fuse_small_levels != 0;
   if (o->graph)
-    rc = coarse_solve_graph<T>(pr, H, prec, cycles, nu, w, s, &xh, x_init);
+    rc = coarse_solve_graph<T>(pr, H, prec, cycles, nu, w, s, &xh, x_init, tail);
   else
-    rc = coarse_solve<T>(H, cycles, nu, w, s, &xh, x_init);
+    rc = coarse_solve<T>(H, cycles, nu, w, s, &xh, x_init, tail);
   if (rc || (rc = phase_end(pr, s))) return rc;
   if (kind == COARSE_Q1) {
     // prolongation P (nodal interpolation of the trilinear correction)
@@ -630,6 +682,7 @@ void dg_default_mg_opts(dg_mg_opts *o) {
   o->coarse_smooth = 0;
   o->coarse_omega = 2.0 / 3.0;
   o->graph = 0;
+  o->fuse_small_levels = 1;
   o->coarse_solver = DG_COARSE_SOLVER_GEOMETRIC;
 }
 

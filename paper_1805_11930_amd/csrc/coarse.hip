@@ -55,33 +55,57 @@ __device__ inline void grid_coords(int64_t i, int nx, int ny, int &ix, int &iy, 
 // vertices of a common cell, and Galerkin products keep that), so the
 // neighbour index is clamped into the grid instead of branching: all 54
 // loads are independent and issue at once.
-template <typename T>
-__device__ inline T stencil27(const T *__restrict__ A, int64_t n, const T *__restrict__ x, int64_t i, int ix, int iy,
+// The index type I is int in the single-workgroup cycle (x in LDS, every
+// index of the level below 2^31), int64_t in the one-kernel-per-step form.
+template <typename T, typename I>
+__device__ inline T stencil27(const T *__restrict__ A, int64_t n, const T *__restrict__ x, I i, int ix, int iy,
                               int iz, int vx, int vy, int vz) {
   const int ox[3] = {ix > 0 ? -1 : 0, 0, ix < vx - 1 ? 1 : 0};
   const int64_t oy[3] = {iy > 0 ? -(int64_t)vx : 0, 0, iy < vy - 1 ? (int64_t)vx : 0};
   const int64_t oz[3] = {iz > 0 ? -(int64_t)vx * vy : 0, 0, iz < vz - 1 ? (int64_t)vx * vy : 0};
   T s = T(0);
+  if constexpr (sizeof(I) == 4) {
+    // x in LDS: the 27 coefficients are all requested before the first
+    // product (in the large single-workgroup kernel the scheduler would
+    // otherwise issue them one at a time to save registers); the products
+    // are summed in the same order as below
+    T a[27];
 #pragma unroll
-  for (int dz = 0; dz < 3; ++dz)
+    for (int o = 0; o < 27; ++o) {
+      const T *Ao = A + o * n;
+      a[o] = Ao[i];
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
+    for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const int o = dx + 3 * dy + 9 * dz;
-        s += A[o * n + i] * x[i + ox[dx] + oy[dy] + oz[dz]];
-      }
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) s += a[dx + 3 * dy + 9 * dz] * x[i + ox[dx] + oy[dy] + oz[dz]];
+  } else {
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          const int o = dx + 3 * dy + 9 * dz;
+          s += A[o * n + i] * x[i + ox[dx] + oy[dy] + oz[dz]];
+        }
+  }
   return s;
 }
 
-// xo = xi + w Dinv (r - A xi); xi == null means xi = 0.  Dinv is the
-// inverse of half the l1 row norm (see CoarseLevel).
-template <typename T>
-__global__ void k_jacobi27(const T *__restrict__ A, const T *__restrict__ dinv, int vx, int vy, int vz, T w,
-                           const T *__restrict__ r, const T *__restrict__ xi, T *__restrict__ xo) {
+// Per-unknown bodies of the 27-point level operations, shared by the
+// one-thread-per-unknown kernels below and the single-workgroup cycle of
+// the small levels (k_coarse_tail), so that both give the same bits.
+
+// xo_i = xi_i + w Dinv_i (r_i - (A xi)_i); xi == null means xi = 0.  Dinv is
+// the inverse of half the l1 row norm (see CoarseLevel).
+template <typename T, typename I>
+__device__ inline void jacobi27_at(const T *__restrict__ A, const T *__restrict__ dinv, int vx, int vy, int vz, T w,
+                                   const T *__restrict__ r, const T *xi, T *xo, I i) {
   const int64_t n = (int64_t)vx * vy * vz;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
   const T wd = w * dinv[i];
   if (!xi) {
     xo[i] = wd * r[i];
@@ -92,28 +116,23 @@ __global__ void k_jacobi27(const T *__restrict__ A, const T *__restrict__ dinv, 
   xo[i] = xi[i] + wd * (r[i] - stencil27(A, n, xi, i, ix, iy, iz, vx, vy, vz));
 }
 
-// out = r - A x
-template <typename T>
-__global__ void k_residual27(const T *__restrict__ A, int vx, int vy, int vz, const T *__restrict__ r,
-                             const T *__restrict__ x, T *__restrict__ out) {
+// out_i = r_i - (A x)_i
+template <typename T, typename I>
+__device__ inline void residual27_at(const T *__restrict__ A, int vx, int vy, int vz, const T *__restrict__ r,
+                                     const T *x, T *out, I i) {
   const int64_t n = (int64_t)vx * vy * vz;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
   int ix, iy, iz;
   grid_coords(i, vx, vy, ix, iy, iz);
   out[i] = r[i] - stencil27(A, n, x, i, ix, iy, iz, vx, vy, vz);
 }
 
-// rc = P^T t: coarse J gathers the fine vertices within one fine step of
-// its own fine position, with their interpolation weights towards J.
-// When xz is not null, also xz = w dinv rc: the first damped Jacobi sweep
-// from zero on the coarse level.
+// rc_J = (P^T t)_J: coarse J gathers the fine vertices within one fine step
+// of its own fine position, with their interpolation weights towards J.
+// When xz is not null, also xz_J = w dinv_J rc_J: the first damped Jacobi
+// sweep from zero on the coarse level.
 template <typename T>
-__global__ void k_restrict27(int vx, int vy, int vz, const T *__restrict__ t, int cx, int cy, int cz,
-                             T *__restrict__ rc, const T *__restrict__ dinv, T w, T *__restrict__ xz) {
-  const int64_t nc = (int64_t)cx * cy * cz;
-  const int64_t J = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (J >= nc) return;
+__device__ inline void restrict27_at(int vx, int vy, int vz, const T *t, int cx, int cy, int cz, T *rc,
+                                     const T *__restrict__ dinv, T w, T *xz, int64_t J) {
   int jj[3];
   grid_coords(J, cx, cy, jj[0], jj[1], jj[2]);
   const int vf[3] = {vx, vy, vz}, vcs[3] = {cx, cy, cz};
@@ -129,10 +148,10 @@ __global__ void k_restrict27(int vx, int vy, int vz, const T *__restrict__ t, in
     for (int d = -1; d <= 1; ++d) {
       const int i = f + d;
       if (i < 0 || i >= vf[k]) continue;
-      const W1 w = interp1(i, vf[k], vcs[k]);
+      const W1 w1 = interp1(i, vf[k], vcs[k]);
       T wt = T(0);
-      if (w.j0 == jj[k]) wt = w.two ? T(0.5) : T(1);
-      else if (w.two && w.j0 + 1 == jj[k]) wt = T(0.5);
+      if (w1.j0 == jj[k]) wt = w1.two ? T(0.5) : T(1);
+      else if (w1.two && w1.j0 + 1 == jj[k]) wt = T(0.5);
       if (wt != T(0)) {
         fi[k][cnt[k]] = i;
         fw[k][cnt[k]] = wt;
@@ -149,13 +168,9 @@ __global__ void k_restrict27(int vx, int vy, int vz, const T *__restrict__ t, in
   if (xz) xz[J] = w * dinv[J] * s;
 }
 
-// x += P xc (trilinear interpolation from the coarser vertex level)
+// x_i += (P xc)_i (trilinear interpolation from the coarser vertex level)
 template <typename T>
-__global__ void k_prolong27(int vx, int vy, int vz, int cx, int cy, int cz, const T *__restrict__ xc,
-                            T *__restrict__ x) {
-  const int64_t n = (int64_t)vx * vy * vz;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__device__ inline void prolong27_at(int vx, int vy, int vz, int cx, int cy, int cz, const T *xc, T *x, int64_t i) {
   int ii[3];
   grid_coords(i, vx, vy, ii[0], ii[1], ii[2]);
   const int vf[3] = {vx, vy, vz}, vcs[3] = {cx, cy, cz};
@@ -177,6 +192,173 @@ __global__ void k_prolong27(int vx, int vy, int vz, int cx, int cy, int cz, cons
       for (int a = 0; a < cnt[0]; ++a)
         s += w[0][a] * w[1][b] * w[2][c] * xc[j[0][a] + (int64_t)cx * (j[1][b] + (int64_t)cy * j[2][c])];
   x[i] += s;
+}
+
+template <typename T>
+__global__ void k_jacobi27(const T *__restrict__ A, const T *__restrict__ dinv, int vx, int vy, int vz, T w,
+                           const T *__restrict__ r, const T *__restrict__ xi, T *__restrict__ xo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)vx * vy * vz) jacobi27_at<T>(A, dinv, vx, vy, vz, w, r, xi, xo, i);
+}
+
+template <typename T>
+__global__ void k_residual27(const T *__restrict__ A, int vx, int vy, int vz, const T *__restrict__ r,
+                             const T *__restrict__ x, T *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)vx * vy * vz) residual27_at<T>(A, vx, vy, vz, r, x, out, i);
+}
+
+template <typename T>
+__global__ void k_restrict27(int vx, int vy, int vz, const T *__restrict__ t, int cx, int cy, int cz,
+                             T *__restrict__ rc, const T *__restrict__ dinv, T w, T *__restrict__ xz) {
+  const int64_t J = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (J < (int64_t)cx * cy * cz) restrict27_at<T>(vx, vy, vz, t, cx, cy, cz, rc, dinv, w, xz, J);
+}
+
+template <typename T>
+__global__ void k_prolong27(int vx, int vy, int vz, int cx, int cy, int cz, const T *__restrict__ xc,
+                            T *__restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)vx * vy * vz) prolong27_at<T>(vx, vy, vz, cx, cy, cz, xc, x, i);
+}
+
+// One V-cycle of the small 27-point levels l_0 .. (from a zero guess, the
+// same steps and per-unknown arithmetic as the kernel-per-step cycle in
+// api.cpp: nu damped Jacobi sweeps before and after, residual, restriction
+// with the coarser level's first sweep fused, the dense inverse at the
+// bottom, prolongation) in one workgroup, with a barrier between steps:
+// at these sizes the kernel-per-step cycle is bound by launch latency.
+// The levels' vectors r, x, t live in LDS (level k at offset off[k] of each
+// of the three arrays); memory holds only the coefficients, r of level l_0
+// (read) and the result (written to level l_0's x buffer).
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_coarse_tail(TailArgs<T> a) {
+  __shared__ T sr[kTailLds], sx[kTailLds], st[kTailLds];
+  const int tid = threadIdx.x;
+  const int *off = a.off;
+  {
+    // one word of every 128-byte line of the levels' coefficients (A and
+    // dinv above the bottom, the dense inverse at it), all in flight
+    // together: the steps below then find them in this XCD's L2 instead of
+    // waiting for memory one step at a time.  Thread tid takes lines tid +
+    // kTailThreads j, j < kTailPrefetch, of the regions laid end to end.
+    constexpr int kLine = 128 / (int)sizeof(T);
+    const T *pf[kTailPrefetch];
+#pragma unroll
+    for (int j = 0; j < kTailPrefetch; ++j) pf[j] = a.inv;
+    int start = 0;
+    for (int q = 0; q < 2 * a.nl - 1; ++q) {
+      const int k = q >> 1;
+      const int n = off[k + 1] - off[k];
+      const T *base = k + 1 == a.nl ? a.inv : (q & 1) ? a.lv[k].dinv : a.lv[k].A;
+      const int cnt = k + 1 == a.nl ? a.bn * a.bn : (q & 1) ? n : 27 * n;
+      const int lines = (cnt + kLine - 1) / kLine;
+#pragma unroll
+      for (int j = 0; j < kTailPrefetch; ++j) {
+        const int g = tid + kTailThreads * j - start;
+        if (g >= 0 && g < lines) pf[j] = base + (size_t)g * kLine;
+      }
+      start += lines;
+    }
+    T v[kTailPrefetch];
+#pragma unroll
+    for (int j = 0; j < kTailPrefetch; ++j) v[j] = *pf[j];
+    const TailLevel<T> &L0 = a.lv[0];
+    const int n = off[1];
+    if (tid < n) {
+      sr[tid] = L0.r[tid];
+      if (a.x_init) sx[tid] = L0.x[tid];
+    }
+#pragma unroll
+    for (int j = 0; j < kTailPrefetch; ++j) asm volatile("" ::"v"(v[j]));
+    __syncthreads();
+  }
+  // bit l set: level l's current iterate is in t, else in x
+  unsigned in_t = 0;
+  bool fused = a.x_init != 0;  // the level's x holds its first sweep
+  for (int l = 0; l + 1 < a.nl; ++l) {
+    const TailLevel<T> &L = a.lv[l];
+    const int n = off[l + 1] - off[l];
+    const T *r = sr + off[l];
+    T *x = sx + off[l], *t = st + off[l];
+    if (!fused) {
+      if (tid < n)
+        jacobi27_at<T>(L.A, L.dinv, L.vx, L.vy, L.vz, a.w, r, nullptr, x, tid);
+      __syncthreads();
+    }
+    for (int k = 1; k < a.nu; ++k) {
+      if (tid < n) jacobi27_at<T>(L.A, L.dinv, L.vx, L.vy, L.vz, a.w, r, x, t, tid);
+      __syncthreads();
+      T *sw = x;
+      x = t;
+      t = sw;
+    }
+    if (tid < n) residual27_at<T>(L.A, L.vx, L.vy, L.vz, r, x, t, tid);
+    __syncthreads();
+    const TailLevel<T> &C = a.lv[l + 1];
+    fused = l + 2 < a.nl;  // the coarser level smooths (it is not the bottom)
+    const int nc = off[l + 2] - off[l + 1];
+    if (tid < nc)
+      restrict27_at<T>(L.vx, L.vy, L.vz, t, C.vx, C.vy, C.vz, sr + off[l + 1], C.dinv, a.w,
+                       fused ? sx + off[l + 1] : nullptr, tid);
+    __syncthreads();
+    if (x != sx + off[l]) in_t |= 1u << l;
+  }
+  {
+    // bottom: x = inv r.  Row wv + 16 k on wavefront wv: the lane-strided
+    // sums and shuffle reduction of k_dense_mv, row by row in the same
+    // order, with the rows of one wavefront interleaved so that their loads
+    // are in flight together.
+    constexpr int W = kTailThreads / 64, R = kTailBottomMax / W;
+    const T *br = sr + off[a.nl - 1];
+    T *bx = sx + off[a.nl - 1];
+    const int lane = tid & 63, wv = tid >> 6;
+    T s[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) s[k] = T(0);
+    for (int j = lane; j < a.bn; j += 64) {
+      const T rj = br[j];
+      T m[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int row = min(wv + W * k, a.bn - 1);
+        m[k] = a.inv[row * a.bn + j];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < R; ++k)
+        if (wv + W * k < a.bn) s[k] += m[k] * rj;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) s[k] += __shfl_xor(s[k], m, 64);
+      const int row = wv + W * k;
+      if (lane == 0 && row < a.bn) bx[row] = s[k];
+    }
+    __syncthreads();
+  }
+  for (int l = a.nl - 2; l >= 0; --l) {
+    const TailLevel<T> &L = a.lv[l];
+    const TailLevel<T> &C = a.lv[l + 1];
+    const int n = off[l + 1] - off[l];
+    const bool lt = (in_t >> l) & 1u;
+    const T *r = sr + off[l];
+    T *x = (lt ? st : sx) + off[l], *t = (lt ? sx : st) + off[l];
+    const T *xc = ((in_t >> (l + 1)) & 1u ? st : sx) + off[l + 1];
+    if (tid < n) prolong27_at<T>(L.vx, L.vy, L.vz, C.vx, C.vy, C.vz, xc, x, tid);
+    __syncthreads();
+    for (int k = 0; k < a.nu; ++k) {
+      if (tid < n) jacobi27_at<T>(L.A, L.dinv, L.vx, L.vy, L.vz, a.w, r, x, t, tid);
+      __syncthreads();
+      T *sw = x;
+      x = t;
+      t = sw;
+    }
+    in_t = (in_t & ~(1u << l)) | ((x != sx + off[l] ? 1u : 0u) << l);
+  }
+  const T *res = ((in_t & 1u) ? st : sx);
+  if (tid < off[1]) a.lv[0].x[tid] = res[tid];
 }
 
 // r_hat[v] = sum over the (up to eight) cells around vertex v of that
@@ -458,6 +640,25 @@ int prolong27(int vx, int vy, int vz, int cx, int cy, int cz, const T *xc, T *x,
   return DG_OK;
 }
 template <typename T>
+int coarse_tail(const TailArgs<T> &args, hipStream_t s) {
+  TailArgs<T> a = args;
+  int64_t total = 0;
+  a.off[0] = 0;
+  for (int k = 0; k < a.nl && k < kTailLevels; ++k) {
+    total += (int64_t)a.lv[k].vx * a.lv[k].vy * a.lv[k].vz;
+    a.off[k + 1] = (int)std::min<int64_t>(total, kTailLds);
+  }
+  if (a.nl < 2 || a.nl > kTailLevels || a.bn < 1 || a.bn > kTailBottomMax ||
+      (int64_t)a.lv[0].vx * a.lv[0].vy * a.lv[0].vz > kTailMaxUnknowns || total > kTailLds ||
+      (int64_t)a.lv[a.nl - 1].vx * a.lv[a.nl - 1].vy * a.lv[a.nl - 1].vz != a.bn) {
+    set_error("internal: coarse tail sizes");
+    return DG_EINVAL;
+  }
+  hipLaunchKernelGGL((k_coarse_tail<T>), dim3(1), dim3(kTailThreads), 0, s, a);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+template <typename T>
 int q1_gather(int nx, int ny, int nz, const T *cs, T *rv, const T *dinv, T w, T *xz, hipStream_t s) {
   hipLaunchKernelGGL((k_q1_gather<T>), grid_for((int64_t)(nx + 1) * (ny + 1) * (nz + 1)), dim3(256), 0, s, nx, ny,
                      nz, cs, rv, dinv, w, xz);
@@ -503,6 +704,7 @@ int copy_vec(int64_t n, const T *x, T *y, hipStream_t s) {
   template int residual27<T>(const T *, int, int, int, const T *, const T *, T *, hipStream_t);           \
   template int restrict27<T>(int, int, int, const T *, int, int, int, T *, const T *, T, T *, hipStream_t); \
   template int prolong27<T>(int, int, int, int, int, int, const T *, T *, hipStream_t);                   \
+  template int coarse_tail<T>(const TailArgs<T> &, hipStream_t);                                         \
   template int q1_gather<T>(int, int, int, const T *, T *, const T *, T, T *, hipStream_t);                \
   template int q1_prolong_add<T>(int, int, int, int, const T *, T *, hipStream_t);                        \
   template int residual7<T>(const T *, int, int, int, const T *, const T *, T *, hipStream_t);            \

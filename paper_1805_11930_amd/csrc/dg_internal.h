@@ -233,7 +233,7 @@ inline int coarse_kind(int option, bool has_b, bool gll = false) {
 struct CoarseGraph {
   int kind, solver, prec, cycles, nu;
   double w;
-  bool x_init;
+  bool x_init, tail;
   hipGraphExec_t exec;
   void *result;  // device buffer that holds the coarse solution after a launch
 };

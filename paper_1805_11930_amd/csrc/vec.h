@@ -70,6 +70,37 @@ int restrict27(int vx, int vy, int vz, const T *t, int cx, int cy, int cz, T *rc
                hipStream_t s);
 template <typename T>
 int prolong27(int vx, int vy, int vz, int cx, int cy, int cz, const T *xc, T *x, hipStream_t s);
+// One V-cycle of the small 27-point levels of a vertex-grid hierarchy in
+// a single workgroup (k_coarse_tail): levels lv[0 .. nl-1], lv[nl-1] the
+// bottom with the dense inverse inv (bn unknowns); reads lv[0].r, leaves
+// the result in lv[0].x and no other vector of the levels (they are kept
+// in LDS).  x_init: lv[0].x already holds the first damped sweep.
+constexpr int kTailLevels = 8;
+constexpr int kTailThreads = 1024;
+constexpr int64_t kTailMaxUnknowns = 1024;  // largest level the cycle takes
+constexpr int kTailBottomMax = 128;         // largest dense bottom it takes
+constexpr int kTailLds = 1536;              // unknowns of all its levels together
+constexpr int kTailPrefetch = 4;            // coefficient lines per thread pulled into L2
+// Largest coefficient volume the cycle takes.  Measured on the 729-unknown
+// level over a 125-unknown bottom: 144 KB (FP32) runs faster as one
+// workgroup than as 8 launches, 288 KB (FP64) slower.
+constexpr int64_t kTailCoefBytes = 192 * 1024;
+template <typename T>
+struct TailLevel {
+  const T *A = nullptr, *dinv = nullptr;
+  T *r = nullptr, *x = nullptr, *t = nullptr;
+  int vx = 0, vy = 0, vz = 0;
+};
+template <typename T>
+struct TailArgs {
+  TailLevel<T> lv[kTailLevels];
+  const T *inv = nullptr;
+  int nl = 0, bn = 0, nu = 1, x_init = 0;
+  T w = T(0);
+  int off[kTailLevels + 1] = {};  // level k's vectors at off[k] in LDS (set by coarse_tail)
+};
+template <typename T>
+int coarse_tail(const TailArgs<T> &a, hipStream_t s);
 template <typename T>
 int q1_gather(int nx, int ny, int nz, const T *cs, T *rv, const T *dinv, T w, T *xz, hipStream_t s);
 template <typename T>

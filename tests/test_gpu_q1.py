@@ -236,3 +236,52 @@ def test_coarse_graph_replays_equal_eager(space, prec, cycles):
             P.apply(rs[(k + 1) % 3], junk)  # eager work between replays
             P.mg_vcycle(rs[(k + 2) % 3], mg_opts(graph=0, **base), out=junk)
     P.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("cycles,nu", [(1, 1), (3, 2)])
+@pytest.mark.parametrize("cells", [(9, 7, 6), (9, 9, 9), (16, 14, 12)])
+def test_fused_small_levels_equal_kernel_per_step(prec, cycles, nu, cells):
+    """The single-workgroup cycle of the small vertex levels gives the same
+    bits as one kernel per step, whether it takes the whole hierarchy
+    (560 vertices on level 0 and the dense bottom; in FP32 also 1000, 216
+    and the bottom) or starts below level 0 (3315 vertices; 1000 in FP64,
+    whose coefficients exceed what the cycle takes), in eager launches and
+    in the replayed coarse graph."""
+    from paper_1805_11930_amd import DG_COARSE_Q1, mg_opts
+
+    print(f"fused small levels {prec} cycles={cycles} nu={nu} cells={cells}", flush=True)
+    w = inputs.random_case(1, cells=cells, seed=23)
+    P = _lib(w)
+    _, _, nlev = P.coarse_stencil(DG_COARSE_Q1, 0)
+    assert nlev >= 2
+    dt = torch.float64 if prec == "f64" else torch.float32
+    base = dict(coarse_space=DG_COARSE_Q1, coarse_cycles=cycles, coarse_smooth=nu)
+    rs = [torch.from_numpy(inputs.random_vector(P.ndof, 60 + k)).to(dt).cuda() for k in range(2)]
+    for r in rs:
+        ref = P.mg_vcycle(r, mg_opts(fuse_small_levels=0, **base)).clone()
+        for graph in (0, 1, 1):
+            z = P.mg_vcycle(r, mg_opts(fuse_small_levels=1, graph=graph, **base))
+            torch.cuda.synchronize()
+            assert torch.equal(z, ref), graph
+    P.close()
+
+
+def test_fused_small_levels_solve_identical():
+    """Outer FCG with the Q1 V-cycle: the same iterations and solution bits
+    with and without the single-workgroup small-level cycle."""
+    from paper_1805_11930_amd import DG_COARSE_Q1, DG_KRYLOV_FCG, DG_PRECOND_MG, solve_opts
+
+    w = inputs.random_case(2, cells=(12, 10, 8), seed=24)
+    P = _lib(w)
+    f = torch.from_numpy(inputs.random_vector(P.ndof, 70)).cuda()
+    out = []
+    for fuse in (0, 1):
+        o = solve_opts(krylov=DG_KRYLOV_FCG, precond=DG_PRECOND_MG, precond_precision=1, rtol=1e-8, maxit=200,
+                       mg=dict(coarse_space=DG_COARSE_Q1, fuse_small_levels=fuse))
+        u, res = P.solve(f, opts=o)
+        assert res.status == 0
+        out.append((u, res.iters))
+    assert out[0][1] == out[1][1]
+    assert torch.equal(out[0][0], out[1][0])
+    P.close()
