@@ -210,6 +210,10 @@ __device__ inline void residual_epilogue(const DevTab<T, N> &tb, bool active, in
 
 // NB: with neighbour couplings (A) or without (D_T).
 // RES = 0: write v = A u.
+// RES = 3 (T = double): write v = A u and rh[block] = the block's partial
+//   sum of u . v (per lane along its x-line, then over the wavefronts in
+//   order): the outer iteration's (p, A p) without a second pass over p
+//   and A p; dots_final adds the partials.
 // RES = 1: write rh[c] = sum over the DOFs of cell c of (r - A u): the
 //   residual followed by the P0 restriction R = P^T (Sec. 2.2.2), fused so
 //   that A u never goes to memory.
@@ -372,6 +376,28 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(Geo g, const T *__restr
       T *vb = v + (size_t)c * N3 + N * a + N2 * b;
 #pragma unroll
       for (int i = 0; i < N; ++i) vb[i] = qx[i];
+    }
+  } else if constexpr (RES == 3) {
+    static_assert(sizeof(T) == 8, "the fused dot is an FP64 reduction");
+    __shared__ double red[kApplyThreads / 64];
+    double d = 0.0;
+    if (active) {
+      T *vb = v + (size_t)c * N3 + N * a + N2 * b;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        vb[i] = qx[i];
+        d += own[line_pos<N>(0, i, a, b)] * qx[i];
+      }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) d += __shfl_xor(d, m, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = d;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kApplyThreads / 64; ++w) t += red[w];
+      rh[blk] = t;
     }
   } else {
     residual_epilogue<N, T, RES>(tb, active, c, cl, ln, a, b, qx, r, rh);
@@ -565,6 +591,51 @@ int launch_residual_restrict_gl(const dg_problem *pr, int prec, const void *u, c
   }
   set_error("unsupported degree");
   return DG_EINVAL;
+}
+
+// v = A u in FP64 with the partials of u . v (RES = 3); part holds
+// apply_blocks(pr) entries.  Not for the rotated-tensor field (its own
+// kernel): DG_EINVAL.
+template <int P>
+static int launch_apply_dot_t(const dg_problem *pr, const double *u, double *v, double *part, hipStream_t s,
+                              hipEvent_t ev0, hipEvent_t ev1) {
+  constexpr int N = P + 1;
+  const int G = (int)((pr->ncell + ApplyShape<N>::CPB - 1) / ApplyShape<N>::CPB);
+  const dim3 grid(G), block(kApplyThreads);
+  if (pr->geo.field == DG_FIELD_ROTATED_QUADRATIC) {
+    set_error("internal: no fused dot for the rotated-tensor apply");
+    return DG_EINVAL;
+  }
+  if (pr->geo.field)
+    hipExtLaunchKernelGGL((k_apply<P, double, true, 3, true>), grid, block, 0, s, ev0, ev1, 0, pr->geo, u, v,
+                          (const double *)nullptr, part);
+  else if (pr->geo.has_b)
+    hipExtLaunchKernelGGL((k_apply<P, double, true, 3>), grid, block, 0, s, ev0, ev1, 0, pr->geo, u, v,
+                          (const double *)nullptr, part);
+  else
+    hipExtLaunchKernelGGL((k_apply<P, double, true, 3, false, false>), grid, block, 0, s, ev0, ev1, 0, pr->geo, u,
+                          v, (const double *)nullptr, part);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int launch_apply_dot_gl(const dg_problem *pr, const double *u, double *v, double *part, hipStream_t s, hipEvent_t ev0,
+                        hipEvent_t ev1) {
+  switch (pr->p) {
+    case 1: return launch_apply_dot_t<1>(pr, u, v, part, s, ev0, ev1);
+    case 2: return launch_apply_dot_t<2>(pr, u, v, part, s, ev0, ev1);
+    case 3: return launch_apply_dot_t<3>(pr, u, v, part, s, ev0, ev1);
+    case 4: return launch_apply_dot_t<4>(pr, u, v, part, s, ev0, ev1);
+    case 5: return launch_apply_dot_t<5>(pr, u, v, part, s, ev0, ev1);
+  }
+  set_error("unsupported degree");
+  return DG_EINVAL;
+}
+
+int64_t apply_blocks(int p, int64_t ncell) {
+  const int n2 = (p + 1) * (p + 1);
+  const int64_t cpb = kApplyThreads / n2;
+  return (ncell + cpb - 1) / cpb;
 }
 
 int launch_apply_gl(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s, hipEvent_t ev0,

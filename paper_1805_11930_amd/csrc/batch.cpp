@@ -19,6 +19,7 @@
 // enqueues its next iteration; their kernels overlap on the device (one
 // stream per request).  Each request's arithmetic is exactly the same as
 // alone: nothing is shared between requests except the device.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -170,19 +171,31 @@ void finish(dg_solve_state *st, int status) {
 }
 
 // ---- one outer iteration ---------------------------------------------------
+// The apply computes (p, A p) itself (Gauss-point basis, not the
+// rotated-tensor field)
+bool fused_pq(const dg_problem *pr) {
+  return pr->basis == DG_BASIS_GL && pr->geo.field != DG_FIELD_ROTATED_QUADRATIC;
+}
+
 int enqueue_iter(dg_solve_state *st) {
   const int par = st->it & 1;
   const int64_t n = st->pr->ndof;
   double *rz_cur = st->dsc + 4 + par, *rz_next = st->dsc + 4 + (par ^ 1);
   int rc;
-  // q = A p, pq
+  // q = A p, pq (fused into the apply where it has the fused form)
   // the events are recorded by the apply's dispatch (its own start and end)
-  if ((rc = launch_apply(st->pr, DG_FP64, st->p, st->q, st->s, st->ea0[par], st->ea1[par]))) return rc;
   DotSet ds;
-  ds.m = 1;
-  ds.a[0] = st->p;
-  ds.b[0] = st->q;
-  if ((rc = dots(ds, n, st->part, st->dsc + 0, st->s))) return rc;
+  if (fused_pq(st->pr)) {
+    if ((rc = launch_apply_dot_gl(st->pr, st->p, st->q, st->part, st->s, st->ea0[par], st->ea1[par])) ||
+        (rc = dots_final((int)apply_blocks(st->pr->p, st->pr->ncell), st->part, st->dsc + 0, st->s)))
+      return rc;
+  } else {
+    if ((rc = launch_apply(st->pr, DG_FP64, st->p, st->q, st->s, st->ea0[par], st->ea1[par]))) return rc;
+    ds.m = 1;
+    ds.a[0] = st->p;
+    ds.b[0] = st->q;
+    if ((rc = dots(ds, n, st->part, st->dsc + 0, st->s))) return rc;
+  }
   // u += alpha p, r -= alpha q (flexible: the new residual goes to the other
   // buffer) and rr = (r, r) in the same pass
   double *r_out = st->flex ? st->rold : st->r;
@@ -325,17 +338,19 @@ int start(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, hi
       if (e != hipSuccess) return fail(hip_fail(e, "hipEventCreate"));
     }
   if ((rc = take_slot(&st->hdots))) return fail(rc);
+  // partial sums: the dots' fixed grid, or one per block of the fused apply
+  const size_t npart = std::max<size_t>((size_t)kMaxDots * kDotBlocks, (size_t)apply_blocks(pr->p, pr->ncell));
   {
     // one block for the whole workspace
     const bool f32 = o->precond_precision == DG_FP32 && o->precond != DG_PRECOND_NONE;
     const size_t vec = DevBuf::round(n * sizeof(double));
-    const size_t total = (st->flex ? 5 : 4) * vec + DevBuf::round((size_t)kMaxDots * kDotBlocks * sizeof(double)) +
+    const size_t total = (st->flex ? 5 : 4) * vec + DevBuf::round(npart * sizeof(double)) +
                          DevBuf::round(kMaxDots * sizeof(double)) + DevBuf::round(8 * sizeof(double)) +
                          (f32 ? 2 * DevBuf::round(n * sizeof(float)) : 0);
     if ((rc = st->wb.reserve(total))) return fail(rc);
   }
   if ((rc = st->wb.get(&st->r, n)) || (rc = st->wb.get(&st->p, n)) || (rc = st->wb.get(&st->q, n)) ||
-      (rc = st->wb.get(&st->z, n)) || (rc = st->wb.get(&st->part, (size_t)kMaxDots * kDotBlocks)) ||
+      (rc = st->wb.get(&st->z, n)) || (rc = st->wb.get(&st->part, npart)) ||
       (rc = st->wb.get(&st->dout, kMaxDots)) || (rc = st->wb.get(&st->dsc, 8)))
     return fail(rc);
   if (st->flex && (rc = st->wb.get(&st->rold, n))) return fail(rc);

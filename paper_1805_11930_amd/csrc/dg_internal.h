@@ -338,6 +338,11 @@ int launch_residual_restrict(const dg_problem *pr, int prec, const void *u, cons
                              int kind = COARSE_P0);
 int launch_block_diag(const dg_problem *pr, int prec, void *diag, hipStream_t s);
 int launch_rhs(const dg_problem *pr, const double *f_qp, const double *bnd, double *rhs, hipStream_t s);
+// v = A u (FP64, Gauss-point basis, not the rotated-tensor field) with the
+// per-block partials of u . v in part[apply_blocks(p, ncell)]
+int launch_apply_dot_gl(const dg_problem *pr, const double *u, double *v, double *part, hipStream_t s,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+int64_t apply_blocks(int p, int64_t ncell);
 int launch_apply_gl(const dg_problem *pr, int prec, const void *u, void *v, hipStream_t s, hipEvent_t ev0 = nullptr,
                     hipEvent_t ev1 = nullptr);
 int launch_block_apply_gl(const dg_problem *pr, int prec, const void *x, void *y, hipStream_t s);

@@ -11,6 +11,7 @@
 // keeps the preconditioned vectors Z.  Before the FP32 cast the residual
 // is scaled by 1/||r||_2 so that it is O(1) whatever the problem scale.
 #include <chrono>
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -398,7 +399,8 @@ extern "C" int dg_footprint(const dg_problem_desc *d, const dg_solve_opts *o, si
     nvec += o->krylov == DG_KRYLOV_FCG ? 5 : 4;
   }
   b += nvec * ndof * sizeof(double);
-  b += (kMaxBasis * kDotBlocks + kMaxBasis) * sizeof(double);
+  const int64_t npart = std::max<int64_t>((int64_t)kMaxBasis * kDotBlocks, apply_blocks(d->p, ncell));
+  b += (npart + kMaxBasis) * sizeof(double);
   *bytes = b;
   return DG_OK;
 }

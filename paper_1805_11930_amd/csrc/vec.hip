@@ -96,6 +96,13 @@ int dots(const DotSet &ds, int64_t n, double *part, double *out_dev, hipStream_t
   return DG_OK;
 }
 
+// out = the sum of part[0 .. nblk) in k_dots_final's order
+int dots_final(int nblk, const double *part, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kRedThreads), 0, s, 1, nblk, part, out);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
 // ---- BLAS-1 -----------------------------------------------------------------
 // y = a*x + b*y
 __global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, double b, double *__restrict__ y) {
