@@ -172,8 +172,11 @@ int count_step(dg_problem *pr, int *iters, hipStream_t s) {
 // n block-Jacobi sweeps from `src` (NULL = zero) ending in `dst`, using
 // `alt` as the other ping-pong buffer.  dst != alt; src may equal alt but
 // not dst unless n == 0.
+// cb: the last sweep also does the cast back of an FP32 preconditioner
+// (its FP32 result is then not written, so it must be the sweep into dst)
 int sweeps(dg_problem *pr, int prec, const void *f, const void *src, void *dst, void *alt, int n,
-           const SmoothArgs &base, int *iters, hipStream_t s, const void *zh = nullptr) {
+           const SmoothArgs &base, int *iters, hipStream_t s, const void *zh = nullptr,
+           const CastBackArgs *cb = nullptr) {
   if (n <= 0) {
     if (src == nullptr)
       DG_HIP(hipMemsetAsync(dst, 0, (size_t)pr->ndof * esize(prec), s));
@@ -188,12 +191,19 @@ int sweeps(dg_problem *pr, int prec, const void *f, const void *src, void *dst, 
     SmoothArgs a = base;
     a.zero_guess = cur == nullptr ? 1 : 0;
     a.zh = (k == 1 && cur != nullptr) ? zh : nullptr;  // P0 correction enters the first sweep
+    a.cb = k == n ? cb : nullptr;
     int rc = launch_smooth(pr, prec, f, cur ? cur : f, out, a, count_buf(pr, iters), s);
     if (!rc) rc = count_step(pr, iters, s);
     if (rc) return rc;
     cur = out;
   }
-  if (cur != dst) DG_HIP(hipMemcpyAsync(dst, cur, (size_t)pr->ndof * esize(prec), hipMemcpyDeviceToDevice, s));
+  if (cur != dst) {
+    if (cb) {
+      set_error("internal: the cast-back sweep must end in its output");
+      return DG_EINVAL;
+    }
+    DG_HIP(hipMemcpyAsync(dst, cur, (size_t)pr->ndof * esize(prec), hipMemcpyDeviceToDevice, s));
+  }
   return DG_OK;
 }
 
@@ -471,8 +481,12 @@ int coarse_solve_graph(dg_problem *pr, Hierarchy &H, int prec, int cycles, int n
   return DG_OK;
 }
 
+// cb (FP32 only, nullable): the last postsmoothing sweep also does the
+// cast back (see CastBackArgs); *fused tells whether it did.
 template <typename T>
-int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hipStream_t s) {
+int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hipStream_t s,
+             const CastBackArgs *cb = nullptr, bool *fused = nullptr) {
+  if (fused) *fused = false;
   SmoothArgs sa;
   int rc = smooth_args(pr, &o->smooth, sa);
   if (rc) return rc;
@@ -535,10 +549,12 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
     if ((rc = phase_end(pr, s))) return rc;
     if (o->n_post == 0) return DG_OK;  // X == z here
     if ((rc = phase_begin(pr, PH_SMOOTH, s))) return rc;
-    if (sor)
+    if (sor) {
       rc = sor_sweeps(pr, prec, r, z, z, o->n_post, sw_post, sa, s);
-    else
-      rc = sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s);
+    } else {
+      rc = sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s, nullptr, cb);
+      if (!rc && cb && fused) *fused = true;
+    }
     return rc ? rc : phase_end(pr, s);
   }
   if (o->n_post == 0) {
@@ -548,10 +564,12 @@ int vcycle_t(dg_problem *pr, int prec, const T *r, T *z, const dg_mg_opts *o, hi
   }
   // prolongation P (injection) fused into the first postsmoothing sweep
   if ((rc = phase_begin(pr, PH_SMOOTH, s))) return rc;
-  if (sor)
+  if (sor) {
     rc = sor_sweeps(pr, prec, r, z, z, o->n_post, sw_post, sa, s, xh);
-  else
-    rc = sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s, xh);
+  } else {
+    rc = sweeps(pr, prec, r, X, z, Y == z ? t0 : Y, o->n_post, sa, nullptr, s, xh, cb);
+    if (!rc && cb && fused) *fused = true;
+  }
   return rc ? rc : phase_end(pr, s);
 }
 
@@ -966,10 +984,19 @@ int solution_error(int64_t n, const double *u, const double *u_ref, double *tmp,
 
 namespace {
 // the preconditioner proper on rin -> zout in precision prec
-int precond_run(dg_problem *pr, const dg_solve_opts *o, int prec, const void *rin, void *zout, hipStream_t s) {
+// cb (FP32 Jacobi sweeps in the Gauss-point basis): the last sweep also
+// does the cast back; *fused tells whether it did.
+int precond_run(dg_problem *pr, const dg_solve_opts *o, int prec, const void *rin, void *zout, hipStream_t s,
+                const CastBackArgs *cb = nullptr, bool *fused = nullptr) {
   int rc;
+  if (fused) *fused = false;
+  if (pr->basis != DG_BASIS_GL || prec != DG_FP32) cb = nullptr;
   if (o->precond == DG_PRECOND_MG) {
-    if ((rc = vcycle(pr, prec, rin, zout, &o->mg, s))) return rc;
+    if (prec == DG_FP32)
+      rc = vcycle_t<float>(pr, prec, (const float *)rin, (float *)zout, &o->mg, s, cb, fused);
+    else
+      rc = vcycle(pr, prec, rin, zout, &o->mg, s);
+    if (rc) return rc;
   } else {
     // block smoother steps from zero: mg.smooth.n_sweeps of mg.smooth.sweep
     SmoothArgs a;
@@ -980,12 +1007,15 @@ int precond_run(dg_problem *pr, const dg_solve_opts *o, int prec, const void *ri
       rc = sor_sweeps(pr, prec, rin, nullptr, zout, n, a.sweep, a, s);
     } else if (n == 1) {
       a.zero_guess = 1;
+      a.cb = cb;
       rc = launch_smooth(pr, prec, rin, rin, zout, a, count_buf(pr, nullptr), s);
       if (!rc) rc = count_step(pr, nullptr, s);
+      if (!rc && cb && fused) *fused = true;
     } else {
       void *alt;
       if ((rc = alloc_tmp(pr, prec, 2, &alt))) return rc;
-      rc = sweeps(pr, prec, rin, nullptr, zout, alt, n, a, nullptr, s);
+      rc = sweeps(pr, prec, rin, nullptr, zout, alt, n, a, nullptr, s, nullptr, cb);
+      if (!rc && cb && fused) *fused = true;
     }
     if (rc || (rc = phase_end(pr, s))) return rc;
   }
@@ -1034,8 +1064,19 @@ int precond_apply_dev(dg_problem *pr, const dg_solve_opts *o, const double *r, d
 int precond_apply_fp32_dots(dg_problem *pr, const dg_solve_opts *o, const float *r32, float *z32, double *z,
                             const double *rr_dev, int m, const double *b0, const double *b1, double *part,
                             double *out, hipStream_t s) {
-  int rc = precond_run(pr, o, DG_FP32, r32, z32, s);
+  // the cast back and the dots in the last smoothing sweep where it is a
+  // Gauss-point Jacobi sweep, else in a pass of their own
+  CastBackArgs cb;
+  cb.rr = rr_dev;
+  cb.z = z;
+  cb.b0 = b0;
+  cb.b1 = b1;
+  cb.part = part;
+  cb.m = m;
+  bool fused = false;
+  int rc = precond_run(pr, o, DG_FP32, r32, z32, s, &cb, &fused);
   if (rc) return rc;
+  if (fused) return dots_final(m, (int)smooth_blocks(pr->p, pr->ncell), part, out, s);
   return cast_back_dots(pr->ndof, rr_dev, z32, z, m, b0, b1, part, out, s);
 }
 }  // namespace dgmg

@@ -187,7 +187,7 @@ int enqueue_iter(dg_solve_state *st) {
   DotSet ds;
   if (fused_pq(st->pr)) {
     if ((rc = launch_apply_dot_gl(st->pr, st->p, st->q, st->part, st->s, st->ea0[par], st->ea1[par])) ||
-        (rc = dots_final((int)apply_blocks(st->pr->p, st->pr->ncell), st->part, st->dsc + 0, st->s)))
+        (rc = dots_final(1, (int)apply_blocks(st->pr->p, st->pr->ncell), st->part, st->dsc + 0, st->s)))
       return rc;
   } else {
     if ((rc = launch_apply(st->pr, DG_FP64, st->p, st->q, st->s, st->ea0[par], st->ea1[par]))) return rc;
@@ -338,8 +338,10 @@ int start(dg_problem *pr, const double *f, double *u, const dg_solve_opts *o, hi
       if (e != hipSuccess) return fail(hip_fail(e, "hipEventCreate"));
     }
   if ((rc = take_slot(&st->hdots))) return fail(rc);
-  // partial sums: the dots' fixed grid, or one per block of the fused apply
-  const size_t npart = std::max<size_t>((size_t)kMaxDots * kDotBlocks, (size_t)apply_blocks(pr->p, pr->ncell));
+  // partial sums: the dots' fixed grid, one per block of the fused apply,
+  // or two per workgroup of the smoothing sweep with the cast back
+  const size_t npart = std::max<size_t>({(size_t)kMaxDots * kDotBlocks, (size_t)apply_blocks(pr->p, pr->ncell),
+                                          2 * (size_t)smooth_blocks(pr->p, pr->ncell)});
   {
     // one block for the whole workspace
     const bool f32 = o->precond_precision == DG_FP32 && o->precond != DG_PRECOND_NONE;

@@ -24,6 +24,14 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
   ka.zero_guess = a.zero_guess;
   ka.write_du = a.write_du;
   ka.defect = a.defect;
+  if (a.cb) {
+    if (sizeof(T) != 4 || a.colour >= 0 || a.write_du || !a.cb->rr || !a.cb->z || !a.cb->b0 || !a.cb->part ||
+        a.cb->m < 1 || a.cb->m > 2 || (a.cb->m == 2 && !a.cb->b1)) {
+      set_error("internal: the cast-back epilogue needs an FP32 Jacobi sweep and its buffers");
+      return DG_EINVAL;
+    }
+    ka.cb = *a.cb;
+  }
   const bool hb = pr->geo.has_b != 0;
 #define DG_SMOOTH_LAUNCH_RM(INNER, HB, TRI, RM)                                                                 \
   hipLaunchKernelGGL((k_smooth<P, INNER, T, HB, TRI, RM>), dim3(G), dim3(kSmoothThreads), 0, s, pr->geo,        \
@@ -82,6 +90,18 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
 #undef DG_SMOOTH_LAUNCH_GMRES
   DG_HIP(hipGetLastError());
   return DG_OK;
+}
+
+int64_t smooth_blocks(int p, int64_t ncell) {
+  int cpw = 1;
+  switch (p) {
+    case 1: cpw = SmoothShape<2>::CPW; break;
+    case 2: cpw = SmoothShape<3>::CPW; break;
+    case 3: cpw = SmoothShape<4>::CPW; break;
+    case 4: cpw = SmoothShape<5>::CPW; break;
+    case 5: cpw = SmoothShape<6>::CPW; break;
+  }
+  return (ncell + cpw - 1) / cpw;
 }
 
 int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin, void *uout, const SmoothArgs &a,

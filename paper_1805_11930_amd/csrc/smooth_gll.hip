@@ -74,6 +74,10 @@ int launch_smooth_gll(const dg_problem *pr, int prec, const void *f, const void 
     set_error("the Gauss-Lobatto basis supports the inner CG and GMRES block solves");
     return DG_EINVAL;
   }
+  if (a.cb) {
+    set_error("internal: no cast-back epilogue in the Gauss-Lobatto sweep");
+    return DG_EINVAL;
+  }
   if (a.inner == DG_INNER_CG && a.tridiag) {
     set_error("the tridiagonal inner preconditioner needs inner GMRES");
     return DG_EINVAL;

@@ -130,6 +130,7 @@ struct SmoothKArgs {
   // block-SOR form (alg block_SOR): the defect leaves out the cell's own
   // block and the new value is (1 - omega) u + omega x
   int sor;
+  CastBackArgs cb;  // cb.z != nullptr: the cast-back epilogue (T = float)
 };
 
 // Per-lane data of the three lines (x: y=a,z=b; y: x=a,z=b; z: x=a,y=b)
@@ -1052,15 +1053,44 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   }
 
   // ---- update ---------------------------------------------------------------
+  const bool cast_back = sizeof(T) == 4 && sa.cb.z != nullptr;
+  double acc0 = 0.0, acc1 = 0.0;
   if (on) {
     const T om = (T)sa.omega;
     const T keep = sa.sor ? T(1) - om : T(1);
+    double sc = 1.0;
+    if (cast_back) {
+      const double r2 = *sa.cb.rr;
+      sc = r2 > 0.0 ? 1.0 / sqrt(r2) : 1.0;
+      sc = 1.0 / sc;
+    }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const T val = sa.write_du ? x[i] : keep * ul[i] + om * x[i];
-      uout[base + lpos<N>(0, i, a, b)] = val;
+      const size_t idx = base + lpos<N>(0, i, a, b);
+      if (cast_back) {
+        const double zi = sc * (double)val;
+        sa.cb.z[idx] = zi;
+        acc0 += zi * sa.cb.b0[idx];
+        if (sa.cb.m > 1) acc1 += zi * sa.cb.b1[idx];
+      } else {
+        uout[idx] = val;
+      }
     }
     if (iters && lane == 0) iters[c] = it;
+  }
+  if (cast_back) {
+    // the workgroup is one wavefront: its partials by shuffles
+    static_assert(kSmoothThreads == 64, "one wavefront per workgroup");
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      acc0 += __shfl_xor(acc0, m, 64);
+      acc1 += __shfl_xor(acc1, m, 64);
+    }
+    if (tid == 0) {
+      sa.cb.part[blockIdx.x] = acc0;
+      if (sa.cb.m > 1) sa.cb.part[(size_t)gridDim.x + blockIdx.x] = acc1;
+    }
   }
 }
 

@@ -399,7 +399,8 @@ extern "C" int dg_footprint(const dg_problem_desc *d, const dg_solve_opts *o, si
     nvec += o->krylov == DG_KRYLOV_FCG ? 5 : 4;
   }
   b += nvec * ndof * sizeof(double);
-  const int64_t npart = std::max<int64_t>((int64_t)kMaxBasis * kDotBlocks, apply_blocks(d->p, ncell));
+  const int64_t npart = std::max<int64_t>(
+      {(int64_t)kMaxBasis * kDotBlocks, apply_blocks(d->p, ncell), 2 * smooth_blocks(d->p, ncell)});
   b += (npart + kMaxBasis) * sizeof(double);
   *bytes = b;
   return DG_OK;

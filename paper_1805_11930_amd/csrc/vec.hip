@@ -96,9 +96,40 @@ int dots(const DotSet &ds, int64_t n, double *part, double *out_dev, hipStream_t
   return DG_OK;
 }
 
-// out = the sum of part[0 .. nblk) in k_dots_final's order
-int dots_final(int nblk, const double *part, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kRedThreads), 0, s, 1, nblk, part, out);
+// Sum j of many partials (one block of 1024 threads per sum): thread t
+// adds part[j * nblk + t + 1024 k] over k in four interleaved
+// accumulators (k mod 4, their loads in flight together), combined in
+// order, then the wavefront and block sums in a fixed order.
+constexpr int kFinThreads = 1024;
+__global__ __launch_bounds__(kFinThreads) void k_sum_partials(int nblk, const double *__restrict__ part,
+                                                              double *__restrict__ out) {
+  __shared__ double sh[kFinThreads / 64];
+  const double *pj = part + (size_t)blockIdx.x * nblk;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i0 = threadIdx.x; i0 < nblk; i0 += 4 * kFinThreads) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * kFinThreads;
+      v[u] = i < nblk ? pj[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += v[u];
+  }
+  double t = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < kFinThreads / 64; ++w) r += sh[w];
+    out[blockIdx.x] = r;
+  }
+}
+
+// out[j] = the sum of part[j * nblk .. (j + 1) * nblk), j < m
+int dots_final(int m, int nblk, const double *part, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(m), dim3(kFinThreads), 0, s, nblk, part, out);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
