@@ -984,18 +984,18 @@ int solution_error(int64_t n, const double *u, const double *u_ref, double *tmp,
 
 namespace {
 // the preconditioner proper on rin -> zout in precision prec
-// cb (FP32 Jacobi sweeps in the Gauss-point basis): the last sweep also
-// does the cast back; *fused tells whether it did.
+// cb (Jacobi sweeps in the Gauss-point basis): the last sweep also takes
+// the dots (and, FP32, the cast back); *fused tells whether it did.
 int precond_run(dg_problem *pr, const dg_solve_opts *o, int prec, const void *rin, void *zout, hipStream_t s,
                 const CastBackArgs *cb = nullptr, bool *fused = nullptr) {
   int rc;
   if (fused) *fused = false;
-  if (pr->basis != DG_BASIS_GL || prec != DG_FP32) cb = nullptr;
+  if (pr->basis != DG_BASIS_GL || !smooth_takes_dots(prec, o->mg.smooth.inner)) cb = nullptr;
   if (o->precond == DG_PRECOND_MG) {
     if (prec == DG_FP32)
       rc = vcycle_t<float>(pr, prec, (const float *)rin, (float *)zout, &o->mg, s, cb, fused);
     else
-      rc = vcycle(pr, prec, rin, zout, &o->mg, s);
+      rc = vcycle_t<double>(pr, prec, (const double *)rin, (double *)zout, &o->mg, s, cb, fused);
     if (rc) return rc;
   } else {
     // block smoother steps from zero: mg.smooth.n_sweeps of mg.smooth.sweep
@@ -1022,11 +1022,10 @@ int precond_run(dg_problem *pr, const dg_solve_opts *o, int prec, const void *ri
   return DG_OK;
 }
 
-// z = M(r); with an FP32 preconditioner r is scaled by 1 / ||r||_2 before the
-// cast (host value rnorm, or rr = ||r||^2 in device memory when rr_dev is
-// given) and z scaled back after it.
-int precond_core(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, double rnorm,
-                 const double *rr_dev, float *r32, float *z32, hipStream_t s) {
+// z = M(r); with an FP32 preconditioner r is scaled by 1 / ||r||_2 (host
+// value rnorm) before the cast and z scaled back after it.
+int precond_core(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, double rnorm, float *r32,
+                 float *z32, hipStream_t s) {
   int rc;
   if (o->precond == DG_PRECOND_NONE) {
     DG_HIP(hipMemcpyAsync(z, r, (size_t)pr->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1037,14 +1036,14 @@ int precond_core(dg_problem *pr, const dg_solve_opts *o, const double *r, double
   const void *rin = r;
   void *zout = z;
   if (mixed) {
-    rc = rr_dev ? cast_d2f_dev(pr->ndof, rr_dev, r, r32, s) : cast_d2f(pr->ndof, sc, r, r32, s);
+    rc = cast_d2f(pr->ndof, sc, r, r32, s);
     if (rc) return rc;
     rin = r32;
     zout = z32;
   }
   if ((rc = precond_run(pr, o, mixed ? DG_FP32 : DG_FP64, rin, zout, s))) return rc;
   if (mixed) {
-    rc = rr_dev ? cast_f2d_dev(pr->ndof, rr_dev, z32, z, s) : cast_f2d(pr->ndof, 1.0 / sc, z32, z, s);
+    rc = cast_f2d(pr->ndof, 1.0 / sc, z32, z, s);
     if (rc) return rc;
   }
   return DG_OK;
@@ -1053,12 +1052,7 @@ int precond_core(dg_problem *pr, const dg_solve_opts *o, const double *r, double
 
 int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, double rnorm, float *r32,
                   float *z32, hipStream_t s) {
-  return precond_core(pr, o, r, z, rnorm, nullptr, r32, z32, s);
-}
-
-int precond_apply_dev(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, const double *rr_dev,
-                      float *r32, float *z32, hipStream_t s) {
-  return precond_core(pr, o, r, z, 0.0, rr_dev, r32, z32, s);
+  return precond_core(pr, o, r, z, rnorm, r32, z32, s);
 }
 
 int precond_apply_fp32_dots(dg_problem *pr, const dg_solve_opts *o, const float *r32, float *z32, double *z,
@@ -1078,5 +1072,31 @@ int precond_apply_fp32_dots(dg_problem *pr, const dg_solve_opts *o, const float 
   if (rc) return rc;
   if (fused) return dots_final(m, (int)smooth_blocks(pr->p, pr->ncell), part, out, s);
   return cast_back_dots(pr->ndof, rr_dev, z32, z, m, b0, b1, part, out, s);
+}
+
+int precond_apply_fp64_dots(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, int m,
+                            const double *b0, const double *b1, double *part, double *out, hipStream_t s) {
+  // the dots in the last smoothing sweep where it is a Gauss-point Jacobi
+  // sweep, else in a pass of their own
+  CastBackArgs cb;
+  cb.b0 = b0;
+  cb.b1 = b1;
+  cb.part = part;
+  cb.m = m;
+  bool fused = false;
+  int rc;
+  if (o->precond == DG_PRECOND_NONE) {
+    DG_HIP(hipMemcpyAsync(z, r, (size_t)pr->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else if ((rc = precond_run(pr, o, DG_FP64, r, z, s, &cb, &fused))) {
+    return rc;
+  }
+  if (fused) return dots_final(m, (int)smooth_blocks(pr->p, pr->ncell), part, out, s);
+  DotSet ds;
+  ds.m = m;
+  ds.a[0] = z;
+  ds.b[0] = b0;
+  ds.a[1] = z;
+  ds.b[1] = b1;
+  return dots(ds, pr->ndof, part, out, s);
 }
 }  // namespace dgmg

@@ -218,14 +218,11 @@ int enqueue_iter(dg_solve_state *st) {
       return rc;
     DG_HIP(hipEventRecord(st->ep1[par], st->s));
   } else {
-    if ((rc = precond_apply_dev(st->pr, &st->o, st->r, st->z, st->dsc + 6, st->r32, st->z32, st->s))) return rc;
+    // z = M(r) and (z, r), (z, r_old)
+    if ((rc = precond_apply_fp64_dots(st->pr, &st->o, st->r, st->z, st->flex ? 2 : 1, st->r, st->rold, st->part,
+                                      st->dsc + 2, st->s)))
+      return rc;
     DG_HIP(hipEventRecord(st->ep1[par], st->s));
-    ds.m = st->flex ? 2 : 1;
-    ds.a[0] = st->z;
-    ds.b[0] = st->r;
-    ds.a[1] = st->z;
-    ds.b[1] = st->rold;
-    if ((rc = dots(ds, n, st->part, st->dsc + 2, st->s))) return rc;
   }
   if ((rc = beta_update(n, st->dsc + 2, st->dsc + 3, rz_cur, rz_next, st->flex, st->z, st->p, st->s))) return rc;
   st->pending = par;

@@ -363,11 +363,11 @@ int launch_basis(const dg_problem *pr, int prec, const void *in, void *out, bool
 int launch_diff(int64_t n, int prec, const void *f, const void *y, void *d, hipStream_t s);
 int gll_setup(dg_problem *pr);
 
-// The last sweep of an FP32 preconditioner may also finish the outer
-// iteration's cast back: z = (1 / (1 / sqrt(rr))) u_new in FP64 (the
-// inverse of the factor r was scaled by) and, per workgroup, the partial
-// sums of z . b0 (and z . b1 when m = 2) in part[j * blocks + block]; the
-// FP32 result is then not written.
+// The last sweep of a preconditioner may also take the outer iteration's
+// dots: per workgroup, the partial sums of z . b0 (and z . b1 when m = 2)
+// in part[j * blocks + block].  FP32: z = (1 / (1 / sqrt(rr))) u_new in
+// FP64 (the inverse of the factor r was scaled by) is written to z and the
+// FP32 result is not; FP64: z is the sweep's own output (rr and z unused).
 struct CastBackArgs {
   const double *rr = nullptr;
   double *z = nullptr;
@@ -378,6 +378,9 @@ struct CastBackArgs {
 // workgroups of a Jacobi sweep of the Gauss-point smoother (the partials
 // of CastBackArgs per dot)
 int64_t smooth_blocks(int p, int64_t ncell);
+// whether the sweep of this precision and inner solver (DG_INNER_*) has
+// the epilogue (all but FP64 inner GMRES)
+bool smooth_takes_dots(int prec, int inner);
 
 struct SmoothArgs {
   double omega, eps;
@@ -391,7 +394,7 @@ struct SmoothArgs {
   int sor = 0;      // block-SOR update form (alg block_SOR)
   int sweep = 0;    // DG_SWEEP_* of the options (host-side dispatch)
   int tridiag = 0;  // inner preconditioner: tridiagonal part of D_T (Thomas)
-  const CastBackArgs *cb = nullptr;  // FP32 Jacobi sweep, Gauss-point basis only
+  const CastBackArgs *cb = nullptr;  // Jacobi sweep, Gauss-point basis only
 };
 int launch_smooth(const dg_problem *pr, int prec, const void *f, const void *uin, void *uout,
                   const SmoothArgs &a, int *iters, hipStream_t s);

@@ -25,9 +25,9 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
   ka.write_du = a.write_du;
   ka.defect = a.defect;
   if (a.cb) {
-    if (sizeof(T) != 4 || a.colour >= 0 || a.write_du || !a.cb->rr || !a.cb->z || !a.cb->b0 || !a.cb->part ||
-        a.cb->m < 1 || a.cb->m > 2 || (a.cb->m == 2 && !a.cb->b1)) {
-      set_error("internal: the cast-back epilogue needs an FP32 Jacobi sweep and its buffers");
+    if (!smooth_takes_dots(sizeof(T) == 8 ? DG_FP64 : DG_FP32, a.inner) || a.colour >= 0 || a.write_du || !a.cb->b0 || !a.cb->part || a.cb->m < 1 || a.cb->m > 2 ||
+        (a.cb->m == 2 && !a.cb->b1) || (sizeof(T) == 4 && (!a.cb->rr || !a.cb->z))) {
+      set_error("internal: the dots epilogue needs a Jacobi sweep and its buffers");
       return DG_EINVAL;
     }
     ka.cb = *a.cb;
@@ -91,6 +91,8 @@ static int launch_smooth_t(const dg_problem *pr, const void *f, const void *uin,
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
+
+bool smooth_takes_dots(int prec, int inner) { return prec == DG_FP32 || inner != DG_INNER_GMRES; }
 
 int64_t smooth_blocks(int p, int64_t ncell) {
   int cpw = 1;

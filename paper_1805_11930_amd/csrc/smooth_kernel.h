@@ -130,7 +130,7 @@ struct SmoothKArgs {
   // block-SOR form (alg block_SOR): the defect leaves out the cell's own
   // block and the new value is (1 - omega) u + omega x
   int sor;
-  CastBackArgs cb;  // cb.z != nullptr: the cast-back epilogue (T = float)
+  CastBackArgs cb;  // cb.part != nullptr: the dots (and, T = float, cast-back) epilogue
 };
 
 // Per-lane data of the three lines (x: y=a,z=b; y: x=a,z=b; z: x=a,y=b)
@@ -1053,7 +1053,11 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   }
 
   // ---- update ---------------------------------------------------------------
-  const bool cast_back = sizeof(T) == 4 && sa.cb.z != nullptr;
+  // (not built into the FP64 inner-GMRES sweeps, whose registers are
+  // already the tightest; see smooth_takes_dots)
+  constexpr bool kEpi = sizeof(T) == 4 || INNER != DG_INNER_GMRES;
+  const bool epi = kEpi && sa.cb.part != nullptr;
+  const bool cast_back = sizeof(T) == 4 && epi;
   double acc0 = 0.0, acc1 = 0.0;
   if (on) {
     const T om = (T)sa.omega;
@@ -1075,11 +1079,15 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
         if (sa.cb.m > 1) acc1 += zi * sa.cb.b1[idx];
       } else {
         uout[idx] = val;
+        if (epi) {
+          acc0 += (double)val * sa.cb.b0[idx];
+          if (sa.cb.m > 1) acc1 += (double)val * sa.cb.b1[idx];
+        }
       }
     }
     if (iters && lane == 0) iters[c] = it;
   }
-  if (cast_back) {
+  if (epi) {
     // the workgroup is one wavefront: its partials by shuffles
     static_assert(kSmoothThreads == 64, "one wavefront per workgroup");
 #pragma unroll

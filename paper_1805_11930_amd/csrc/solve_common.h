@@ -11,14 +11,15 @@ namespace dgmg {
 int alloc_tmp(dg_problem *pr, int prec, int k, void **out);
 int precond_apply(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, double rnorm, float *r32,
                   float *z32, hipStream_t s);
-// the same with rr = ||r||_2^2 read from device memory for the FP32 scaling
-int precond_apply_dev(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, const double *rr_dev,
-                      float *r32, float *z32, hipStream_t s);
 // FP32 preconditioner on an r32 the caller already scaled by 1 / sqrt(*rr_dev),
 // z scaled back, and out[j] = z . b_j (j < m <= 2) in the same pass
 int precond_apply_fp32_dots(dg_problem *pr, const dg_solve_opts *o, const float *r32, float *z32, double *z,
                             const double *rr_dev, int m, const double *b0, const double *b1, double *part,
                             double *out, hipStream_t s);
+// z = M(r) in FP64 and out[j] = z . b_j, j < m <= 2 (the dots in the last
+// smoothing sweep where it can take them)
+int precond_apply_fp64_dots(dg_problem *pr, const dg_solve_opts *o, const double *r, double *z, int m,
+                            const double *b0, const double *b1, double *part, double *out, hipStream_t s);
 
 // Device allocations owned by one solve; freed together.  reserve() takes
 // one block for the buffers that follow (each rounded up to 256 bytes);

@@ -34,14 +34,12 @@ int sub(int64_t n, const double *x, const double *y, double *z, hipStream_t s);
 int cg_update_rr(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
                  const double *r_in, double *r_out, double *flag, double *part, double *rr, hipStream_t s,
                  float *r32 = nullptr, const double *rr_old = nullptr, double *rr_keep = nullptr);
-// z = z32 scaled back by the factor of *rr (as cast_f2d_dev) and
+// z = z32 scaled back by the inverse of the factor 1 / sqrt(*rr) and
 // out[j] = z . b_j for j < m <= 2 (same sums as dots), in one pass
 int cast_back_dots(int64_t n, const double *rr, const float *z32, double *z, int m, const double *b0,
                    const double *b1, double *part, double *out, hipStream_t s);
 int beta_update(int64_t n, const double *zr, const double *zro, const double *rz_old, double *rz_new, bool flex,
                 const double *z, double *p, hipStream_t s);
-int cast_d2f_dev(int64_t n, const double *rr, const double *x, float *y, hipStream_t s);
-int cast_f2d_dev(int64_t n, const double *rr, const float *x, double *y, hipStream_t s);
 int cast_d2f(int64_t n, double sc, const double *x, float *y, hipStream_t s);
 int cast_f2d(int64_t n, double sc, const float *x, double *y, hipStream_t s);
 

@@ -203,8 +203,9 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_update_rr(int64_t n, const d
   }
 }
 
-// z = (1 / (1 / sqrt(rr))) z32 (the inverse of the factor r32 was scaled
-// by, as k_cast_dscale) fused with the partial sums of z . b_j, j < m <= 2
+// z = (1 / (1 / sqrt(rr))) z32 (the inverse of the rounded factor
+// 1 / sqrt(rr) that k_cg_update_rr scaled r32 by; 1 when rr is not
+// positive) fused with the partial sums of z . b_j, j < m <= 2
 // (the order of k_dots_partial; k_dots_final adds them)
 __global__ __launch_bounds__(kRedThreads) void k_cast_back_dots(int64_t n, const double *__restrict__ rr,
                                                                 const float *__restrict__ z32,
@@ -252,18 +253,6 @@ __global__ void k_beta_update(int64_t n, const double *__restrict__ zr, const do
   if (i < n) p[i] = 1.0 * z[i] + b * p[i];
   if (i == 0) *rz_new = *zr;
 }
-// y = s x with s = 1 / sqrt(rr) (INV = false) or 1 / (1 / sqrt(rr)) (the
-// inverse of the same rounded factor), rr read from device memory; s = 1
-// when rr is not positive
-template <typename S, typename D, bool INV>
-__global__ void k_cast_dscale(int64_t n, const double *__restrict__ rr, const S *__restrict__ x, D *__restrict__ y) {
-  const double r2 = *rr;
-  double s = r2 > 0.0 ? 1.0 / sqrt(r2) : 1.0;
-  if (INV) s = 1.0 / s;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (D)(s * (double)x[i]);
-}
-
 static inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 int axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
@@ -295,16 +284,6 @@ int cast_back_dots(int64_t n, const double *rr, const float *z32, double *z, int
                    const double *b1, double *part, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_cast_back_dots, dim3(kDotBlocks), dim3(kRedThreads), 0, s, n, rr, z32, z, m, b0, b1, part);
   hipLaunchKernelGGL(k_dots_final, dim3(m), dim3(kRedThreads), 0, s, m, kDotBlocks, part, out);
-  DG_HIP(hipGetLastError());
-  return DG_OK;
-}
-int cast_d2f_dev(int64_t n, const double *rr, const double *x, float *y, hipStream_t s) {
-  hipLaunchKernelGGL((k_cast_dscale<double, float, false>), grid1(n), dim3(256), 0, s, n, rr, x, y);
-  DG_HIP(hipGetLastError());
-  return DG_OK;
-}
-int cast_f2d_dev(int64_t n, const double *rr, const float *x, double *y, hipStream_t s) {
-  hipLaunchKernelGGL((k_cast_dscale<float, double, true>), grid1(n), dim3(256), 0, s, n, rr, x, y);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
