@@ -21,8 +21,8 @@ struct DotSet {
 // out_dev[j] = a_j . b_j ; part: device scratch of kMaxDots*kDotBlocks doubles
 int dots(const DotSet &ds, int64_t n, double *part, double *out_dev, hipStream_t s);
 // out_dev[j] = sum of part[j * nblk .. (j + 1) * nblk), j < m (partials
-// written by another kernel)
-int dots_final(int m, int nblk, const double *part, double *out_dev, hipStream_t s);
+// written by another kernel; large nblk: part is overwritten)
+int dots_final(int m, int nblk, double *part, double *out_dev, hipStream_t s);
 int axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
 int sub(int64_t n, const double *x, const double *y, double *z, hipStream_t s);
 // outer-iteration kernels with device scalars (no host round trip)

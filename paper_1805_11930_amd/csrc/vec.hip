@@ -127,8 +127,57 @@ __global__ __launch_bounds__(kFinThreads) void k_sum_partials(int nblk, const do
   }
 }
 
-// out[j] = the sum of part[j * nblk .. (j + 1) * nblk), j < m
-int dots_final(int m, int nblk, const double *part, double *out, hipStream_t s) {
+// Many partials: chunk c of sum j (kFinChunk entries, blockIdx = (c, j))
+// is added as in k_sum_partials and its sum stored over the chunk's first
+// entry (read only by this block, before the barrier); k_sum_chunks then
+// adds the chunk sums of each sum in order.
+constexpr int kFinChunk = 4 * kFinThreads;
+__global__ __launch_bounds__(kFinThreads) void k_sum_chunk(int nblk, double *__restrict__ part) {
+  __shared__ double sh[kFinThreads / 64];
+  double *pc = part + (size_t)blockIdx.y * nblk + (size_t)blockIdx.x * kFinChunk;
+  const int len = min(kFinChunk, nblk - (int)blockIdx.x * kFinChunk);
+  double v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = threadIdx.x + u * kFinThreads;
+    v[u] = i < len ? pc[i] : 0.0;
+  }
+  double t = (v[0] + v[1]) + (v[2] + v[3]);
+  for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < kFinThreads / 64; ++w) r += sh[w];
+    pc[0] = r;
+  }
+}
+__global__ __launch_bounds__(kRedThreads) void k_sum_chunks(int nblk, int nchunk, const double *__restrict__ part,
+                                                            double *__restrict__ out) {
+  __shared__ double sh[kRedThreads / 64];
+  const double *pj = part + (size_t)blockIdx.x * nblk;
+  double v = 0.0;
+  for (int c = threadIdx.x; c < nchunk; c += kRedThreads) v += pj[(size_t)c * kFinChunk];
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) r += sh[w];
+    out[blockIdx.x] = r;
+  }
+}
+
+// out[j] = the sum of part[j * nblk .. (j + 1) * nblk), j < m (part is
+// overwritten above 4 * kFinChunk entries per sum)
+int dots_final(int m, int nblk, double *part, double *out, hipStream_t s) {
+  if (nblk > 4 * kFinChunk) {
+    const int nchunk = (nblk + kFinChunk - 1) / kFinChunk;
+    hipLaunchKernelGGL(k_sum_chunk, dim3(nchunk, m), dim3(kFinThreads), 0, s, nblk, part);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(m), dim3(kRedThreads), 0, s, nblk, nchunk, part, out);
+    DG_HIP(hipGetLastError());
+    return DG_OK;
+  }
   hipLaunchKernelGGL(k_sum_partials, dim3(m), dim3(kFinThreads), 0, s, nblk, part, out);
   DG_HIP(hipGetLastError());
   return DG_OK;
