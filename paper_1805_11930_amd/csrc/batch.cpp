@@ -202,7 +202,8 @@ int enqueue_iter(dg_solve_state *st) {
   // with the FP32 preconditioner the same pass writes r in FP32, scaled by
   // the previous residual norm (its rr kept in dsc[1] for the cast back)
   const bool f32 = st->o.precond_precision == DG_FP32 && st->o.precond != DG_PRECOND_NONE;
-  if ((rc = cg_update_rr(n, rz_cur, st->dsc + 0, st->p, st->q, st->u, st->r, r_out, st->dsc + 7, st->part,
+  // (u += alpha p is left to the beta update, which reads p anyway)
+  if ((rc = cg_update_rr(n, rz_cur, st->dsc + 0, st->p, st->q, nullptr, st->r, r_out, st->dsc + 7, st->part,
                          st->dsc + 6, st->s, f32 ? st->r32 : nullptr, st->dsc + 6, st->dsc + 1)))
     return rc;
   if (st->flex) std::swap(st->r, st->rold);
@@ -224,7 +225,10 @@ int enqueue_iter(dg_solve_state *st) {
       return rc;
     DG_HIP(hipEventRecord(st->ep1[par], st->s));
   }
-  if ((rc = beta_update(n, st->dsc + 2, st->dsc + 3, rz_cur, rz_next, st->flex, st->z, st->p, st->s))) return rc;
+  // p = z + beta p, and u += alpha p of the old p
+  if ((rc = beta_update(n, st->dsc + 2, st->dsc + 3, rz_cur, rz_next, st->flex, st->z, st->p, st->s, st->u,
+                        st->dsc + 0)))
+    return rc;
   st->pending = par;
   return DG_OK;
 }

@@ -26,8 +26,9 @@ int dots_final(int m, int nblk, double *part, double *out_dev, hipStream_t s);
 int axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
 int sub(int64_t n, const double *x, const double *y, double *z, hipStream_t s);
 // outer-iteration kernels with device scalars (no host round trip)
-// x += a p, r_out = r_in - a q with a = *rz / *pq (a breakdown sets *flag =
-// 1 and leaves x, r unchanged) and *rr = r_out . r_out (same sum as dots) in
+// x += a p (not when x is nullptr), r_out = r_in - a q with a = *rz / *pq
+// (a breakdown sets *flag = 1 and leaves x, r unchanged) and
+// *rr = r_out . r_out (same sum as dots) in
 // one pass over the vectors; part: kDotBlocks doubles of scratch.  With r32: also
 // r32 = (1 / sqrt(*rr_old)) r_out in FP32 and *rr_keep = *rr_old (rr_old is
 // read before rr is written, so it may be the same slot)
@@ -38,8 +39,11 @@ int cg_update_rr(int64_t n, const double *rz, const double *pq, const double *p,
 // out[j] = z . b_j for j < m <= 2 (same sums as dots), in one pass
 int cast_back_dots(int64_t n, const double *rr, const float *z32, double *z, int m, const double *b0,
                    const double *b1, double *part, double *out, hipStream_t s);
+// p = z + beta p (see k_beta_update); with x and pq also x += a p of the
+// old p, a = rz_old / pq (0 on a breakdown), for a cg_update_rr called
+// with x == nullptr
 int beta_update(int64_t n, const double *zr, const double *zro, const double *rz_old, double *rz_new, bool flex,
-                const double *z, double *p, hipStream_t s);
+                const double *z, double *p, hipStream_t s, double *x = nullptr, const double *pq = nullptr);
 int cast_d2f(int64_t n, double sc, const double *x, float *y, hipStream_t s);
 int cast_f2d(int64_t n, double sc, const float *x, double *y, hipStream_t s);
 

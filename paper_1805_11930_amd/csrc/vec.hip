@@ -202,8 +202,15 @@ __global__ void k_cast_scale(int64_t n, double s, const S *__restrict__ x, D *__
 
 // Outer-iteration kernels with their scalars in device memory, so that an
 // iteration is enqueued without waiting for the host.
-// x += a p ; r_out = r_in - a q with a = rz / pq (a breakdown, pq <= 0 or a
-// not finite, leaves x and r unchanged and sets *flag = 1), and the partial
+// cg_alpha: a = rz / pq, or 0 on a breakdown (pq <= 0 or a not finite).
+__device__ inline double cg_alpha(double rz, double pq, bool *bad) {
+  double a = rz / pq;
+  *bad = !(pq > 0.0) || !isfinite(a);
+  return *bad ? 0.0 : a;
+}
+// x += a p (x == nullptr: left to k_beta_update, which reads p anyway) ;
+// r_out = r_in - a q with a = cg_alpha (a breakdown leaves x and r
+// unchanged and sets *flag = 1), and the partial
 // sums of r_out . r_out (grid-stride over the fixed grid of k_dots_partial,
 // same order; k_dots_final adds them)
 __global__ __launch_bounds__(kRedThreads) void k_cg_update_rr(int64_t n, const double *__restrict__ rz,
@@ -216,10 +223,8 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_update_rr(int64_t n, const d
                                                               const double *__restrict__ rr_old,
                                                               double *__restrict__ rr_keep) {
   __shared__ double sh[kRedThreads / 64];
-  const double d = *pq;
-  double a = *rz / d;
-  const bool bad = !(d > 0.0) || !isfinite(a);
-  if (bad) a = 0.0;
+  bool bad;
+  const double a = cg_alpha(*rz, *pq, &bad);
   // FP32 copy scaled by 1 / ||r|| of the previous iteration (the current
   // norm is what this pass computes); the factor's rr is kept for the cast
   // back of the preconditioned vector
@@ -231,7 +236,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_update_rr(int64_t n, const d
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kRedThreads;
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
-    x[i] += a * p[i];
+    if (x) x[i] += a * p[i];
     const double ro = r_in[i] - a * q[i];
     r_out[i] = ro;
     acc += ro * ro;
@@ -293,13 +298,23 @@ __global__ __launch_bounds__(kRedThreads) void k_cast_back_dots(int64_t n, const
 }
 
 // p = z + beta p with beta = (zr - zro) / rz_old (flexible CG) or
-// zr / rz_old; thread 0 stores rz_new = zr (rz_new is not rz_old)
+// zr / rz_old; thread 0 stores rz_new = zr (rz_new is not rz_old).  With
+// x: first x += a p of the old p, a = cg_alpha(rz_old, pq) (the update
+// k_cg_update_rr left out).
 __global__ void k_beta_update(int64_t n, const double *__restrict__ zr, const double *__restrict__ zro,
                               const double *__restrict__ rz_old, double *__restrict__ rz_new, int flex,
-                              const double *__restrict__ z, double *__restrict__ p) {
+                              const double *__restrict__ z, double *__restrict__ p, double *__restrict__ x,
+                              const double *__restrict__ pq) {
   const double b = flex ? (*zr - *zro) / *rz_old : *zr / *rz_old;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 1.0 * z[i] + b * p[i];
+  if (i < n) {
+    const double po = p[i];
+    if (x) {
+      bool bad;
+      x[i] += cg_alpha(*rz_old, *pq, &bad) * po;
+    }
+    p[i] = 1.0 * z[i] + b * po;
+  }
   if (i == 0) *rz_new = *zr;
 }
 static inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
@@ -324,8 +339,13 @@ int cg_update_rr(int64_t n, const double *rz, const double *pq, const double *p,
   return DG_OK;
 }
 int beta_update(int64_t n, const double *zr, const double *zro, const double *rz_old, double *rz_new, bool flex,
-                const double *z, double *p, hipStream_t s) {
-  hipLaunchKernelGGL(k_beta_update, grid1(n), dim3(256), 0, s, n, zr, zro, rz_old, rz_new, flex ? 1 : 0, z, p);
+                const double *z, double *p, hipStream_t s, double *x, const double *pq) {
+  if ((x == nullptr) != (pq == nullptr)) {
+    set_error("internal: beta_update takes x and pq together");
+    return DG_EINVAL;
+  }
+  hipLaunchKernelGGL(k_beta_update, grid1(n), dim3(256), 0, s, n, zr, zro, rz_old, rz_new, flex ? 1 : 0, z, p, x,
+                     pq);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
