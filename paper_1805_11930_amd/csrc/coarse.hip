@@ -129,41 +129,50 @@ __device__ inline void residual27_at(const T *__restrict__ A, int vx, int vy, in
 // rc_J = (P^T t)_J: coarse J gathers the fine vertices within one fine step
 // of its own fine position, with their interpolation weights towards J.
 // When xz is not null, also xz_J = w dinv_J rc_J: the first damped Jacobi
-// sweep from zero on the coarse level.
+// sweep from zero on the coarse level.  Branch-free: per axis the three
+// candidates f - 1, f, f + 1 (clamped into the grid, weight 0 where the
+// vertex is outside or does not interpolate from J), all 27 loads issued
+// at once; the nonzero terms are added in the same order as a loop over
+// the contributing vertices only, and a zero-weight term leaves the sum
+// unchanged.
 template <typename T>
 __device__ inline void restrict27_at(int vx, int vy, int vz, const T *t, int cx, int cy, int cz, T *rc,
                                      const T *__restrict__ dinv, T w, T *xz, int64_t J) {
   int jj[3];
   grid_coords(J, cx, cy, jj[0], jj[1], jj[2]);
   const int vf[3] = {vx, vy, vz}, vcs[3] = {cx, cy, cz};
-  // per axis: up to three fine indices and their weights towards jj
   int fi[3][3];
   T fw[3][3];
-  int cnt[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    cnt[k] = 0;
     const int f = min(2 * jj[k], vf[k] - 1);
 #pragma unroll
-    for (int d = -1; d <= 1; ++d) {
-      const int i = f + d;
-      if (i < 0 || i >= vf[k]) continue;
-      const W1 w1 = interp1(i, vf[k], vcs[k]);
+    for (int d = 0; d < 3; ++d) {
+      const int i = f + d - 1;
+      const bool in = i >= 0 && i < vf[k];
+      const int ic = in ? i : f;
+      const W1 w1 = interp1(ic, vf[k], vcs[k]);
       T wt = T(0);
       if (w1.j0 == jj[k]) wt = w1.two ? T(0.5) : T(1);
       else if (w1.two && w1.j0 + 1 == jj[k]) wt = T(0.5);
-      if (wt != T(0)) {
-        fi[k][cnt[k]] = i;
-        fw[k][cnt[k]] = wt;
-        ++cnt[k];
-      }
+      fi[k][d] = ic;
+      fw[k][d] = in ? wt : T(0);
     }
   }
+  T tv[27];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) tv[a + 3 * b + 9 * c] = t[fi[0][a] + (int64_t)vx * (fi[1][b] + (int64_t)vy * fi[2][c])];
   T s = T(0);
-  for (int c = 0; c < cnt[2]; ++c)
-    for (int b = 0; b < cnt[1]; ++b)
-      for (int a = 0; a < cnt[0]; ++a)
-        s += fw[0][a] * fw[1][b] * fw[2][c] * t[fi[0][a] + (int64_t)vx * (fi[1][b] + (int64_t)vy * fi[2][c])];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) s += fw[0][a] * fw[1][b] * fw[2][c] * tv[a + 3 * b + 9 * c];
   rc[J] = s;
   if (xz) xz[J] = w * dinv[J] * s;
 }
