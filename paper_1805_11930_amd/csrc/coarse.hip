@@ -177,7 +177,11 @@ __device__ inline void restrict27_at(int vx, int vy, int vz, const T *t, int cx,
   if (xz) xz[J] = w * dinv[J] * s;
 }
 
-// x_i += (P xc)_i (trilinear interpolation from the coarser vertex level)
+// x_i += (P xc)_i (trilinear interpolation from the coarser vertex level).
+// Branch-free: per axis the coarse vertices j0 and j0 + 1 (clamped into the
+// grid, weight 0 when the fine vertex sits on j0), all eight loads issued
+// at once, the terms added in the same order as a loop over the
+// contributing vertices only (a zero-weight term leaves the sum unchanged).
 template <typename T>
 __device__ inline void prolong27_at(int vx, int vy, int vz, int cx, int cy, int cz, const T *xc, T *x, int64_t i) {
   int ii[3];
@@ -185,21 +189,28 @@ __device__ inline void prolong27_at(int vx, int vy, int vz, int cx, int cy, int 
   const int vf[3] = {vx, vy, vz}, vcs[3] = {cx, cy, cz};
   int j[3][2];
   T w[3][2];
-  int cnt[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const W1 q = interp1(ii[k], vf[k], vcs[k]);
     j[k][0] = q.j0;
-    j[k][1] = q.j0 + 1;
+    j[k][1] = min(q.j0 + 1, vcs[k] - 1);
     w[k][0] = q.two ? T(0.5) : T(1);
-    w[k][1] = T(0.5);
-    cnt[k] = q.two ? 2 : 1;
+    w[k][1] = q.two ? T(0.5) : T(0);
   }
+  T v[8];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) v[a + 2 * b + 4 * c] = xc[j[0][a] + (int64_t)cx * (j[1][b] + (int64_t)cy * j[2][c])];
   T s = T(0);
-  for (int c = 0; c < cnt[2]; ++c)
-    for (int b = 0; b < cnt[1]; ++b)
-      for (int a = 0; a < cnt[0]; ++a)
-        s += w[0][a] * w[1][b] * w[2][c] * xc[j[0][a] + (int64_t)cx * (j[1][b] + (int64_t)cy * j[2][c])];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) s += w[0][a] * w[1][b] * w[2][c] * v[a + 2 * b + 4 * c];
   x[i] += s;
 }
 
@@ -383,25 +394,27 @@ __global__ void k_q1_gather(int nx, int ny, int nz, const T *__restrict__ cs, T 
   if (v >= n) return;
   int ix, iy, iz;
   grid_coords(v, vx, vy, ix, iy, iz);
-  T s = T(0);
+  // the (up to) eight cells around v, loaded at once (a cell outside the
+  // grid is replaced by a clamped one and its value by 0, which leaves the
+  // sum unchanged); the vertex is corner (1-sx, 1-sy, 1-sz) of cell s
+  T val[8];
+  bool in[8];
 #pragma unroll
-  for (int sz = 0; sz < 2; ++sz) {
-    const int cz = iz - 1 + sz;
-    if (cz < 0 || cz >= nz) continue;
+  for (int sz = 0; sz < 2; ++sz)
 #pragma unroll
-    for (int sy = 0; sy < 2; ++sy) {
-      const int cyy = iy - 1 + sy;
-      if (cyy < 0 || cyy >= ny) continue;
+    for (int sy = 0; sy < 2; ++sy)
 #pragma unroll
       for (int sx = 0; sx < 2; ++sx) {
-        const int cxx = ix - 1 + sx;
-        if (cxx < 0 || cxx >= nx) continue;
-        const int64_t c = cxx + (int64_t)nx * (cyy + (int64_t)ny * cz);
-        // the vertex is corner (1-sx, 1-sy, 1-sz) of that cell
-        s += cs[8 * c + (1 - sx) + 2 * (1 - sy) + 4 * (1 - sz)];
+        const int cz = iz - 1 + sz, cyy = iy - 1 + sy, cxx = ix - 1 + sx;
+        const int q = sx + 2 * sy + 4 * sz;
+        in[q] = cz >= 0 && cz < nz && cyy >= 0 && cyy < ny && cxx >= 0 && cxx < nx;
+        const int64_t c = min(max(cxx, 0), nx - 1) + (int64_t)nx * (min(max(cyy, 0), ny - 1) +
+                                                                    (int64_t)ny * min(max(cz, 0), nz - 1));
+        val[q] = cs[8 * c + (1 - sx) + 2 * (1 - sy) + 4 * (1 - sz)];
       }
-    }
-  }
+  T s = T(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s += in[q] ? val[q] : T(0);
   rv[v] = s;
   if (xz) xz[v] = w * dinv[v] * s;
 }
