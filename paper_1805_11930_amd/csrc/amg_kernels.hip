@@ -16,13 +16,32 @@ namespace {
 
 constexpr int kCsrThreads = 256;
 
-// sum over row i of v[k] * x[ci[k]] by the LPR lanes of the row's group
+// sum over row i of v[k] * x[ci[k]] by the LPR lanes of the row's group.
+// Four entries per lane and step: their column indices and values, then
+// the four gathers of x, are in flight together; the products are added
+// in entry order (as one entry per step would).
 template <int LPR, typename T>
 __device__ inline T row_dot(int i, int j, const int *__restrict__ rp, const int *__restrict__ ci,
                             const T *__restrict__ v, const T *__restrict__ x) {
+  constexpr int U = 4;
   T s = T(0);
   const int e = rp[i + 1];
-  for (int k = rp[i] + j; k < e; k += LPR) s += v[k] * x[ci[k]];
+  for (int k0 = rp[i] + j; k0 < e; k0 += U * LPR) {
+    int c[U];
+    T a[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * LPR;
+      const int kc = k < e ? k : k0;  // in the row; not added below
+      c[u] = ci[kc];
+      a[u] = v[kc];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u * LPR < e) s += a[u] * xv[u];
+  }
 #pragma unroll
   for (int m = LPR / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, LPR);
   return s;
