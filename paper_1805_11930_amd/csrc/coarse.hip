@@ -471,13 +471,22 @@ __global__ void k_residual7(const T *__restrict__ A, int nx, int ny, int nz, con
   if (i >= n) return;
   int ix, iy, iz;
   grid_coords(i, nx, ny, ix, iy, iz);
-  T s = A[i] * x[i];
-  if (ix > 0) s += A[n + i] * x[i - 1];
-  if (ix < nx - 1) s += A[2 * n + i] * x[i + 1];
-  if (iy > 0) s += A[3 * n + i] * x[i - nx];
-  if (iy < ny - 1) s += A[4 * n + i] * x[i + nx];
-  if (iz > 0) s += A[5 * n + i] * x[i - (int64_t)nx * ny];
-  if (iz < nz - 1) s += A[6 * n + i] * x[i + (int64_t)nx * ny];
+  // all 14 loads issued before the first product (a neighbour outside the
+  // grid reads the point itself and its term is not added)
+  const bool in[6] = {ix > 0, ix < nx - 1, iy > 0, iy < ny - 1, iz > 0, iz < nz - 1};
+  const int64_t off[6] = {-1, 1, -(int64_t)nx, (int64_t)nx, -(int64_t)nx * ny, (int64_t)nx * ny};
+  T a[7], v[7];
+  a[0] = A[i];
+  v[0] = x[i];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    a[k + 1] = A[(k + 1) * n + i];
+    v[k + 1] = x[in[k] ? i + off[k] : i];
+  }
+  T s = a[0] * v[0];
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    if (in[k]) s += a[k + 1] * v[k + 1];
   out[i] = r[i] - s;
 }
 

@@ -410,16 +410,26 @@ template int prolong_add_p0<float>(int64_t, int, const float *, float *, hipStre
 
 // ---- P0 aggregation levels (7-point stencils) ------------------------------
 // A[0][i] = diagonal, A[1..6][i] = couplings to -x,+x,-y,+y,-z,+z.
+// All 14 loads are issued before the first product (a neighbour outside
+// the grid reads the point itself and its term is not added), the terms
+// added in the order of the couplings.
 template <typename T>
 __device__ inline T stencil_apply(const T *__restrict__ A, int64_t n, const T *__restrict__ x, int i, int ix, int iy,
                                   int iz, int nx, int ny, int nz) {
-  T s = A[i] * x[i];
-  if (ix > 0) s += A[n + i] * x[i - 1];
-  if (ix < nx - 1) s += A[2 * n + i] * x[i + 1];
-  if (iy > 0) s += A[3 * n + i] * x[i - nx];
-  if (iy < ny - 1) s += A[4 * n + i] * x[i + nx];
-  if (iz > 0) s += A[5 * n + i] * x[i - nx * ny];
-  if (iz < nz - 1) s += A[6 * n + i] * x[i + nx * ny];
+  const bool in[6] = {ix > 0, ix < nx - 1, iy > 0, iy < ny - 1, iz > 0, iz < nz - 1};
+  const int off[6] = {-1, 1, -nx, nx, -nx * ny, nx * ny};
+  T a[7], v[7];
+  a[0] = A[i];
+  v[0] = x[i];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    a[k + 1] = A[(k + 1) * n + i];
+    v[k + 1] = x[in[k] ? i + off[k] : i];
+  }
+  T s = a[0] * v[0];
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    if (in[k]) s += a[k + 1] * v[k + 1];
   return s;
 }
 
@@ -448,14 +458,21 @@ __global__ void k_coarse_restrict(const T *__restrict__ A, int nx, int ny, int n
   if (j >= nc) return;
   const int jx = j % cnx, jy = (j / cnx) % cny, jz = j / (cnx * cny);
   const int n = nx * ny * nz;
+  // the eight children, unrolled with clamped coordinates so that their
+  // loads can be in flight together; a child outside the grid is not added
   T s = T(0);
+#pragma unroll
   for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
     for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
       for (int dx = 0; dx < 2; ++dx) {
         const int ix = 2 * jx + dx, iy = 2 * jy + dy, iz = 2 * jz + dz;
-        if (ix >= nx || iy >= ny || iz >= nz) continue;
-        const int i = ix + nx * (iy + ny * iz);
-        s += r[i] - stencil_apply(A, n, x, i, ix, iy, iz, nx, ny, nz);
+        const bool inside = ix < nx && iy < ny && iz < nz;
+        const int cx = inside ? ix : 2 * jx, cy = inside ? iy : 2 * jy, cz = inside ? iz : 2 * jz;
+        const int i = cx + nx * (cy + ny * cz);
+        const T t = r[i] - stencil_apply(A, n, x, i, cx, cy, cz, nx, ny, nz);
+        if (inside) s += t;
       }
   rc[j] = s;
 }
