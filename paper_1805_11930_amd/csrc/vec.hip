@@ -565,6 +565,9 @@ __global__ __launch_bounds__(kRedThreads) void k_gs(VecList vl, const double *__
 #pragma unroll
     for (int j = 0; j < M; ++j) v[j] = vl.v[j][i];
     double wi = w[i];
+    // all M + 1 loads before the first product (at large M the scheduler
+    // would otherwise trade them for registers and issue one at a time)
+    __builtin_amdgcn_sched_barrier(0);
     if (MODE != 0) {
 #pragma unroll
       for (int j = 0; j < M; ++j) wi -= hc[j] * v[j];
