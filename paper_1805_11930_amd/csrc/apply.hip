@@ -79,12 +79,20 @@ __device__ inline int stage_load(const Geo &g, const T *__restrict__ u, int c0, 
   const int64_t ndof = (int64_t)g.ncell * N3;
   const int64_t e_first = (int64_t)(c0 - St::H) * N3;
   const int64_t eb = e_first >= 0 ? (e_first / V) * V : -(((-e_first) + V - 1) / V) * V;
+  // every vector load is issued from an in-range, aligned address (all in
+  // flight together); the few vectors that reach outside [0, ndof) are
+  // then rebuilt element by element
+  const int64_t elast = (ndof / V) * V - V;  // last aligned full vector
 #pragma unroll
   for (int j = 0; j < St::NVEC; ++j) {
     const int64_t e = eb + (int64_t)(j * kApplyThreads + tid) * V;
-    if (e >= 0 && e + V <= ndof) {
-      pre[j] = *reinterpret_cast<const VT *>(u + e);
-    } else {
+    const int64_t ec = e < 0 ? 0 : (e > elast ? elast : e);
+    pre[j] = *reinterpret_cast<const VT *>(u + ec);
+  }
+#pragma unroll
+  for (int j = 0; j < St::NVEC; ++j) {
+    const int64_t e = eb + (int64_t)(j * kApplyThreads + tid) * V;
+    if (e < 0 || e + V > ndof) {
       T t[V];
 #pragma unroll
       for (int q = 0; q < V; ++q) t[q] = (e + q >= 0 && e + q < ndof) ? u[e + q] : T(0);
