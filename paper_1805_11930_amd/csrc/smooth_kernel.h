@@ -1053,8 +1053,10 @@ __global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__res
   }
 
   // ---- update ---------------------------------------------------------------
-  // (not built into the FP64 inner-GMRES sweeps, whose registers are
-  // already the tightest; see smooth_takes_dots)
+  // With sa.cb.part the outer iteration's dots (and, FP32, the cast back)
+  // follow the update: the CastBackArgs epilogue, not built into the FP64
+  // inner-GMRES sweeps, whose registers are already the tightest (see
+  // smooth_takes_dots).
   constexpr bool kEpi = sizeof(T) == 4 || INNER != DG_INNER_GMRES;
   const bool epi = kEpi && sa.cb.part != nullptr;
   const bool cast_back = sizeof(T) == 4 && epi;
