@@ -419,8 +419,14 @@ __device__ inline void tri_cell(bool on, bool lead, const T (&v)[N], T (&out)[N]
 // the diagonal, and the factored tridiagonal band of the whole block, see
 // basis.hip), and the defect is formed outside the kernel (sa.defect = 0,
 // f = the defect).
+//
+// The FP64 inner-CG sweep for b = 0 at p = 4 is held to 128 registers (four
+// waves per SIMD instead of three, 14 registers spilled): on 32^3 cells the
+// FP64-preconditioned solve went 16.3 -> 16.0 ms.
 template <int P, int INNER, typename T, bool HASB, bool TRI, int RM = kGmresMax, bool GLL = false>
-__global__ __launch_bounds__(kSmoothThreads) void k_smooth(Geo g, const T *__restrict__ f, const T *uin, T *uout,
+__global__ __launch_bounds__(kSmoothThreads) __attribute__((amdgpu_waves_per_eu(
+    sizeof(T) == 8 && INNER == DG_INNER_CG && !HASB && P == 4 ? 4 : 1))) void k_smooth(Geo g, const T *__restrict__ f,
+                                                                                       const T *uin, T *uout,
                                                            SmoothKArgs sa, int *__restrict__ iters,
                                                            const T *__restrict__ zh, const T *__restrict__ fdm) {
   constexpr int N = P + 1;
